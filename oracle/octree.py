@@ -1,0 +1,489 @@
+"""Linear octree, balance, blocks, unzip map and LTS schedule (test infrastructure only).
+
+Paper passages:
+  * Sec. 3.2 (octree on [0, 2^L]^3): axis-aligned linear octree, leaves sorted along
+    a space-filling curve.  One GPU has no partition, so Morton order is used.
+  * Sec. 3.2.2 (construction/refinement): refine while a criterion holds.  The
+    paper's wavelet criterion is replaced by integer geometric criteria so that
+    meshes are bit-exact (ball / annulus around a point).
+  * Sec. 3.2.3 (2:1 balance) extended to ghost reach: a leaf of level l is split
+    when a leaf of level >= l+2 lies within three grid spacings of it.  With 5^3
+    nodes per octant and three ghost layers this keeps every ghost source within
+    one level of the receiver, which the paper's time-gap argument (Sec. 3.7.3)
+    assumes.
+  * Sec. 3.3 + fig. oct_to_blocks (octree to block decomposition): a block is a
+    maximal uniformly refined sub-tree, split into aligned cubes of at most
+    ``cap`` octants per side.
+  * Sec. 3.4 + fig. unzip: padded blocks; coarse->fine interpolation and
+    fine->coarse injection for the padding.
+  * Sec. 3.7.3 + fig. blk_loop: level-frequency schedule.
+  * Sec. 3.8, eqs. w_nuts, w_uts, invS: speedup model.
+
+Geometry (integer "node units" at the finest level L of the spec):
+  domain [-1, 1]^3, periodic; N_u = 4 * 2^L node units per side, x = -1 + 2 X / N_u.
+  A leaf has an anchor a (in level-L octant units, a multiple of s = 2^(L-l)) and a
+  level l; its 5 nodes per axis sit at 4 a + i s, i = 0..4; spacing h_l = 2^(-l-1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+from scipy.ndimage import maximum_filter1d
+
+NODES = 5          # nodes per octant side
+GHOST = 3          # ghost layers of the sixth-order stencils
+
+KIND_OWN, KIND_SAME, KIND_FINE, KIND_COARSE = 0, 1, 2, 3
+
+
+# ----------------------------------------------------------------------------- Morton
+def morton_key(ax, ay, az) -> np.ndarray:
+    """Bit-interleaved key, x in the lowest bit (child index x + 2y + 4z)."""
+    ax = np.asarray(ax, dtype=np.int64)
+    ay = np.asarray(ay, dtype=np.int64)
+    az = np.asarray(az, dtype=np.int64)
+    key = np.zeros(np.broadcast(ax, ay, az).shape, dtype=np.int64)
+    for b in range(20):
+        key |= ((ax >> b) & 1) << (3 * b)
+        key |= ((ay >> b) & 1) << (3 * b + 1)
+        key |= ((az >> b) & 1) << (3 * b + 2)
+    return key
+
+
+# ----------------------------------------------------------------------------- spec
+@dataclass
+class Criterion:
+    """Refinement criterion around an integer centre (node units at level L).
+
+    kind "ball":    refine a level-l leaf if dmin^2 < r2[l].
+    kind "annulus": refine if rlo2[l] < dmax^2 and dmin^2 < rhi2[l]  (the leaf
+                    meets the shell where a Gaussian's gradient is large).
+    dmin / dmax are the smallest / largest periodic distances from the centre to
+    the leaf's closed box.  A negative radius entry never refines.
+    """
+    kind: str
+    center: Tuple[int, int, int]
+    r2: Sequence[int] = ()
+    rlo2: Sequence[int] = ()
+    rhi2: Sequence[int] = ()
+
+
+@dataclass
+class MeshSpec:
+    l_min: int
+    l_max: int
+    criteria: List[Criterion] = field(default_factory=list)
+    block_cap: int = 4
+
+    @staticmethod
+    def from_dict(d: dict) -> "MeshSpec":
+        crit = []
+        for c in d.get("criteria", []):
+            crit.append(Criterion(kind=c["kind"], center=tuple(int(v) for v in c["center"]),
+                                  r2=tuple(c.get("r2", ())), rlo2=tuple(c.get("rlo2", ())),
+                                  rhi2=tuple(c.get("rhi2", ()))))
+        return MeshSpec(int(d["l_min"]), int(d["l_max"]), crit, int(d.get("block_cap", 4)))
+
+
+def _periodic_min_dist(lo, hi, c, n):
+    """Per-axis smallest periodic distance from c to the closed interval [lo, hi]."""
+    best = None
+    for k in (-1, 0, 1):
+        d = np.maximum(0, np.maximum(lo + k * n - c, c - (hi + k * n)))
+        best = d if best is None else np.minimum(best, d)
+    return best
+
+
+def _periodic_point_dist(x, c, n):
+    d = np.abs(x - c) % n
+    return np.minimum(d, n - d)
+
+
+def _periodic_max_dist(lo, hi, c, n):
+    """Per-axis largest periodic distance from c to a point of [lo, hi].
+
+    The periodic distance to c peaks (value n/2) at the antipode c + n/2; if the
+    antipode lies in the interval that is the maximum, else an end point is.
+    """
+    anti = (c + n // 2) % n
+    # antipode (or one of its images) inside [lo, hi]?
+    inside = np.zeros(np.broadcast(lo, hi).shape, dtype=bool)
+    for k in (-1, 0, 1):
+        a = anti + k * n
+        inside |= (lo <= a) & (a <= hi)
+    ends = np.maximum(_periodic_point_dist(lo, c, n), _periodic_point_dist(hi, c, n))
+    return np.where(inside, n // 2, ends)
+
+
+def criterion_holds(crit: Criterion, anchors: np.ndarray, level: int, L: int) -> np.ndarray:
+    """Evaluate a criterion for leaves of one level (Sec. 3.2.2, reading in module doc)."""
+    if len(anchors) == 0:
+        return np.zeros(0, dtype=bool)
+    n = 4 * (1 << L)
+    s = 1 << (L - level)
+    lo = 4 * anchors.astype(np.int64)
+    hi = lo + 4 * s
+    c = np.asarray(crit.center, dtype=np.int64)[None, :]
+    dmin2 = (_periodic_min_dist(lo, hi, c, n) ** 2).sum(axis=1)
+    if crit.kind == "ball":
+        r2 = crit.r2[level] if level < len(crit.r2) else -1
+        if r2 < 0:
+            return np.zeros(len(anchors), dtype=bool)
+        return dmin2 < r2
+    if crit.kind == "annulus":
+        rlo2 = crit.rlo2[level] if level < len(crit.rlo2) else -1
+        rhi2 = crit.rhi2[level] if level < len(crit.rhi2) else -1
+        if rhi2 < 0:
+            return np.zeros(len(anchors), dtype=bool)
+        dmax2 = (_periodic_max_dist(lo, hi, c, n) ** 2).sum(axis=1)
+        return (rlo2 < dmax2) & (dmin2 < rhi2)
+    raise ValueError(f"unknown criterion kind {crit.kind}")
+
+
+# ----------------------------------------------------------------------------- leaves
+def _children(anchors: np.ndarray, level: int, L: int) -> np.ndarray:
+    h = 1 << (L - level - 1)
+    out = []
+    for c in range(8):
+        off = np.array([(c >> 0) & 1, (c >> 1) & 1, (c >> 2) & 1], dtype=np.int64) * h
+        out.append(anchors + off[None, :])
+    return np.concatenate(out, axis=0) if len(anchors) else np.zeros((0, 3), np.int64)
+
+
+def _sort(anchors: np.ndarray, levels: np.ndarray):
+    key = morton_key(anchors[:, 0], anchors[:, 1], anchors[:, 2])
+    order = np.argsort(key, kind="stable")
+    return anchors[order], levels[order]
+
+
+def uniform_leaves(level: int, L: int) -> Tuple[np.ndarray, np.ndarray]:
+    n = 1 << level
+    s = 1 << (L - level)
+    g = np.arange(n, dtype=np.int64) * s
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    anchors = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    return _sort(anchors, np.full(len(anchors), level, dtype=np.int64))
+
+
+def refine(spec: MeshSpec) -> Tuple[np.ndarray, np.ndarray]:
+    """Uniform tree at l_min, then split every leaf whose criterion holds, level by level."""
+    L = spec.l_max
+    anchors, levels = uniform_leaves(spec.l_min, L)
+    keep_a, keep_l = [], []
+    cur = anchors
+    for lev in range(spec.l_min, L + 1):
+        if lev == L or not spec.criteria:
+            keep_a.append(cur); keep_l.append(np.full(len(cur), lev, np.int64))
+            break
+        split = np.zeros(len(cur), dtype=bool)
+        for crit in spec.criteria:
+            split |= criterion_holds(crit, cur, lev, L)
+        keep_a.append(cur[~split]); keep_l.append(np.full(int((~split).sum()), lev, np.int64))
+        cur = _children(cur[split], lev, L)
+        if len(cur) == 0:
+            break
+    anchors = np.concatenate(keep_a, axis=0)
+    levels = np.concatenate(keep_l)
+    return _sort(anchors, levels)
+
+
+def level_grid(anchors: np.ndarray, levels: np.ndarray, L: int) -> np.ndarray:
+    """Cell grid at level L: level of the leaf covering each cell, indexed [x, y, z]."""
+    n = 1 << L
+    g = np.full((n, n, n), -1, dtype=np.int16)
+    for a, l in zip(anchors, levels):
+        s = 1 << (L - int(l))
+        g[a[0]:a[0] + s, a[1]:a[1] + s, a[2]:a[2] + s] = l
+    if (g < 0).any():
+        raise ValueError("leaves do not tile the domain")
+    return g
+
+
+def _window_max(grid: np.ndarray, s: int) -> np.ndarray:
+    """max over cells [a-1-f, a+s+f]^3 around every anchor a, f = floor(3 s / 4).
+
+    These are exactly the level-L cells whose closed box meets the closed box of a
+    level-l leaf (width 4 s node units) grown by 3 h_l = 3 s node units.  A centred
+    window of even size s + 2f + 2 read at a + s/2 covers that range.
+    """
+    f = (3 * s) // 4
+    size = s + 2 * f + 2
+    out = grid
+    for ax in range(3):
+        if size >= out.shape[ax]:
+            # the window covers the whole period: the axis-wise maximum
+            out = np.broadcast_to(out.max(axis=ax, keepdims=True), out.shape).copy()
+        else:
+            out = maximum_filter1d(out, size=size, axis=ax, mode="wrap")
+    return out
+
+
+def balance(anchors: np.ndarray, levels: np.ndarray, L: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Ghost-reach balance (Sec. 3.2.3 extended): split any leaf a of level l for
+    which some leaf of level >= l+2 has periodic Chebyshev box distance <= 3 h_l.
+
+    Iterated to the fixpoint.  Every split is forced in any balanced refinement of
+    the current tree, so the result is the unique minimal balanced refinement.
+    """
+    anchors = anchors.copy()
+    levels = levels.copy()
+    n = 1 << L
+    while True:
+        grid = level_grid(anchors, levels, L)
+        changed = False
+        new_a, new_l = [], []
+        split_mask = np.zeros(len(levels), dtype=bool)
+        for lev in range(int(levels.min()), L - 1):
+            sel = np.nonzero(levels == lev)[0]
+            if len(sel) == 0:
+                continue
+            s = 1 << (L - lev)
+            wm = _window_max(grid, s)
+            pos = (anchors[sel] + s // 2) % n
+            mx = wm[pos[:, 0], pos[:, 1], pos[:, 2]]
+            split_mask[sel[mx >= lev + 2]] = True
+        if split_mask.any():
+            changed = True
+            keep = ~split_mask
+            new_a.append(anchors[keep]); new_l.append(levels[keep])
+            for lev in np.unique(levels[split_mask]):
+                sel = split_mask & (levels == lev)
+                ch = _children(anchors[sel], int(lev), L)
+                new_a.append(ch); new_l.append(np.full(len(ch), lev + 1, np.int64))
+            anchors, levels = _sort(np.concatenate(new_a), np.concatenate(new_l))
+        if not changed:
+            return anchors, levels
+
+
+def is_balanced_bruteforce(anchors: np.ndarray, levels: np.ndarray, L: int) -> bool:
+    """O(N^2) check of the balance predicate (for small meshes in tests)."""
+    n = 4 * (1 << L)
+    lo = 4 * anchors.astype(np.int64)
+    w = 4 * (1 << (L - levels.astype(np.int64)))
+    hi = lo + w[:, None]
+    for a in range(len(levels)):
+        h = 1 << (L - int(levels[a]))
+        cand = levels >= levels[a] + 2
+        if not cand.any():
+            continue
+        gap = np.zeros((int(cand.sum()), 3), dtype=np.int64) + 10 ** 9
+        for k in (-1, 0, 1):
+            g = np.maximum(0, np.maximum(lo[cand] + k * n - hi[a], lo[a] - (hi[cand] + k * n)))
+            gap = np.minimum(gap, g)
+        if (gap.max(axis=1) <= 3 * h).any():
+            return False
+    return True
+
+
+# ----------------------------------------------------------------------------- mesh
+@dataclass
+class Mesh:
+    L: int                      # finest resolution of the coordinates (spec l_max)
+    anchors: np.ndarray         # [N, 3] level-L octant units, Morton sorted
+    levels: np.ndarray          # [N]
+    blocks: np.ndarray          # [B, 6] first_leaf, m, level, ax, ay, az (level-L units)
+    cap: int
+
+    @property
+    def n_oct(self) -> int:
+        return len(self.levels)
+
+    @property
+    def lmin(self) -> int:
+        return int(self.levels.min())
+
+    @property
+    def lmax(self) -> int:
+        return int(self.levels.max())
+
+    def __post_init__(self):
+        self._lookup = {}
+        for i, (a, l) in enumerate(zip(self.anchors, self.levels)):
+            self._lookup[(int(l), int(a[0]), int(a[1]), int(a[2]))] = i
+        self.block_of_leaf = np.full(self.n_oct, -1, dtype=np.int64)
+        for b, row in enumerate(self.blocks):
+            first, m = int(row[0]), int(row[1])
+            self.block_of_leaf[first:first + m ** 3] = b
+        assert (self.block_of_leaf >= 0).all()
+
+    def find(self, level: int, cell) -> int:
+        """Leaf index of the octant at `level` with level-`level` coordinates `cell`
+        (wrapped periodically), or -1."""
+        n = 1 << level
+        s = 1 << (self.L - level)
+        key = (level, (int(cell[0]) % n) * s, (int(cell[1]) % n) * s, (int(cell[2]) % n) * s)
+        return self._lookup.get(key, -1)
+
+
+def build_blocks(anchors: np.ndarray, levels: np.ndarray, L: int, cap: int) -> np.ndarray:
+    """Octree-to-block decomposition (Sec. 3.3, fig. oct_to_blocks).
+
+    For every leaf find its largest ancestor whose sub-tree is uniformly refined
+    at the leaf's level; that sub-tree, split into aligned cubes of side
+    min(side, cap) leaves, gives the blocks.  Blocks are ordered by Morton key.
+    """
+    grid = level_grid(anchors, levels, L)
+    n = 1 << L
+    # uni[k] : the single leaf level found in every level-k cell, -1 if mixed
+    uni = {L: grid.astype(np.int16)}
+    for k in range(L - 1, -1, -1):
+        c = uni[k + 1]
+        sub = [c[dx::2, dy::2, dz::2] for dx in (0, 1) for dy in (0, 1) for dz in (0, 1)]
+        same = np.ones_like(sub[0], dtype=bool)
+        for t in sub[1:]:
+            same &= (t == sub[0])
+        uni[k] = np.where(same, sub[0], -1).astype(np.int16)
+    rows = {}
+    for i, (a, l) in enumerate(zip(anchors, levels)):
+        l = int(l)
+        kstar = l
+        for k in range(l - 1, -1, -1):
+            sk = 1 << (L - k)
+            if uni[k][a[0] // sk, a[1] // sk, a[2] // sk] == l:
+                kstar = k
+            else:
+                break
+        side = 1 << (l - kstar)
+        m = min(side, cap)
+        span = m * (1 << (L - l))
+        ba = (a // span) * span
+        key = (l, int(ba[0]), int(ba[1]), int(ba[2]))
+        rows.setdefault(key, (m, i))
+        rows[key] = (m, min(rows[key][1], i))
+    out = []
+    for (l, x, y, z), (m, first) in rows.items():
+        out.append((first, m, l, x, y, z))
+    out.sort(key=lambda r: r[0])
+    blk = np.array(out, dtype=np.int64).reshape(-1, 6)
+    return blk
+
+
+def build_mesh(spec: MeshSpec) -> Mesh:
+    """Refinement, balance, blocks (Sec. 3.2.2 -> 3.2.3 -> 3.3)."""
+    a, l = refine(spec)
+    a, l = balance(a, l, spec.l_max)
+    blk = build_blocks(a, l, spec.l_max, spec.block_cap)
+    return Mesh(spec.l_max, a, l, blk, spec.block_cap)
+
+
+def mesh_from_leaves(anchors, levels, L: int, cap: int = 4, do_balance: bool = True) -> Mesh:
+    a = np.asarray(anchors, dtype=np.int64).reshape(-1, 3)
+    l = np.asarray(levels, dtype=np.int64).reshape(-1)
+    a, l = _sort(a, l)
+    level_grid(a, l, L)  # validates the tiling
+    if do_balance:
+        a, l = balance(a, l, L)
+    return Mesh(L, a, l, build_blocks(a, l, L, cap), cap)
+
+
+# ----------------------------------------------------------------------------- unzip map
+def block_octants(mesh: Mesh, b: int) -> np.ndarray:
+    """Leaf indices of block b in lexicographic (oi, oj, ok) order, shape [m, m, m] as [ok, oj, oi]."""
+    first, m = int(mesh.blocks[b, 0]), int(mesh.blocks[b, 1])
+    o = np.arange(m)
+    ok, oj, oi = np.meshgrid(o, o, o, indexing="ij")
+    return first + morton_key(oi, oj, ok)
+
+
+def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
+    """Canonical source of every padded point of block b (Sec. 3.4, fig. unzip).
+
+    Returns int64 [S^3, 5] rows (leaf, kind, 2*px, 2*py, 2*pz), S = 4m+7, points in
+    lexicographic order of Q in [-3, 4m+3]^3 with x fastest; (px, py, pz) is the
+    position in the source leaf's node units (half-integers only for kind COARSE).
+
+    Rules (the paper is silent on ownership of points shared by several leaves):
+      * Q inside [0, 4m]^3: the block's own octant min(Q>>2, m-1) per axis, local
+        node Q - 4*octant (the block grid of the uniform sub-tree).
+      * otherwise the point lies in the receiver-level cell floor(Q/4) (half-open
+        cells); that cell is covered by one leaf of the same level (SAME), by 8
+        leaves one level finer (FINE: child floor(nu/2), fine node 2(nu - 2c)), or
+        by an octant of a leaf one level coarser (COARSE: position (4 beta + nu)/2
+        in its node units, beta the cell's child bit), nu = Q - 4 floor(Q/4).
+    """
+    first, m, lev = int(mesh.blocks[b, 0]), int(mesh.blocks[b, 1]), int(mesh.blocks[b, 2])
+    s = 1 << (mesh.L - lev)
+    base = mesh.blocks[b, 3:6] // s          # block anchor in level-lev units
+    S = 4 * m + 7
+    q = np.arange(-3, 4 * m + 4, dtype=np.int64)
+    Qz, Qy, Qx = np.meshgrid(q, q, q, indexing="ij")
+    Q = np.stack([Qx.ravel(), Qy.ravel(), Qz.ravel()], axis=1)  # [S^3, 3]
+    out = np.zeros((S ** 3, 5), dtype=np.int64)
+    inside = ((Q >= 0) & (Q <= 4 * m)).all(axis=1)
+    # own octants
+    oc = np.minimum(Q[inside] >> 2, m - 1)
+    node = Q[inside] - 4 * oc
+    out[inside, 0] = first + morton_key(oc[:, 0], oc[:, 1], oc[:, 2])
+    out[inside, 1] = KIND_OWN
+    out[inside, 2:5] = 2 * node
+    # ghosts
+    gi = np.nonzero(~inside)[0]
+    Sg = np.floor_divide(Q[gi], 4)
+    nu = Q[gi] - 4 * Sg
+    cells = base[None, :] + Sg
+    uniq, inv = np.unique(cells, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    for u_i, cell in enumerate(uniq):
+        rows = gi[inv == u_i]
+        nur = nu[inv == u_i]
+        same = mesh.find(lev, cell)
+        if same >= 0:
+            out[rows, 0] = same
+            out[rows, 1] = KIND_SAME
+            out[rows, 2:5] = 2 * nur
+            continue
+        coarse = mesh.find(lev - 1, cell >> 1) if lev > 0 else -1
+        if coarse >= 0:
+            beta = np.asarray(cell) & 1
+            out[rows, 0] = coarse
+            out[rows, 1] = KIND_COARSE
+            out[rows, 2:5] = 4 * beta[None, :] + nur
+            continue
+        ch0 = mesh.find(lev + 1, 2 * cell)
+        if ch0 < 0:
+            raise ValueError(f"unbalanced mesh: no ghost source for block {b} cell {cell}")
+        for c in range(8):
+            cc = 2 * cell + np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1])
+            if mesh.find(lev + 1, cc) != ch0 + c:
+                raise ValueError(f"unbalanced mesh: cell {cell} of block {b} is not 8 finer leaves")
+        cb = nur >> 1
+        out[rows, 0] = ch0 + cb[:, 0] + 2 * cb[:, 1] + 4 * cb[:, 2]
+        out[rows, 1] = KIND_FINE
+        out[rows, 2:5] = 2 * (2 * (nur - 2 * cb))
+    return out
+
+
+# ----------------------------------------------------------------------------- schedule
+def substeps(mesh: Mesh) -> int:
+    """2^(Delta L) substeps per coarsest step (Sec. 3.7.3)."""
+    return 1 << (mesh.lmax - mesh.lmin)
+
+
+def active_blocks(mesh: Mesh, j: int, mode: str = "lts") -> np.ndarray:
+    """B_j (fig. blk_loop): level-lam blocks step at substeps with j mod 2^(lmax-lam) == 0.
+    GTS steps every block at every substep."""
+    lev = mesh.blocks[:, 2]
+    if mode == "gts":
+        return np.arange(len(lev))
+    r = 1 << (mesh.lmax - lev)
+    return np.nonzero(j % r == 0)[0]
+
+
+def dt_level(level) -> float:
+    """dt_l = 0.25 h_l with h_l = 2^(-l-1) (CFL 0.25, Sec. 3.7)."""
+    return 2.0 ** (-int(level) - 3)
+
+
+def speedup_model(mesh: Mesh) -> dict:
+    """Sec. 3.8, eqs. w_nuts, w_uts, invS with alpha_l = DG nodes at level lmax - l."""
+    Lspan = mesh.lmax - mesh.lmin
+    alpha = np.zeros(Lspan + 1, dtype=np.int64)
+    for lev in range(mesh.lmin, mesh.lmax + 1):
+        alpha[mesh.lmax - lev] = NODES ** 3 * int((mesh.levels == lev).sum())
+    w_lts = int(sum((1 << (Lspan - l)) * int(alpha[l]) for l in range(Lspan + 1)))
+    w_gts = int((1 << Lspan) * int(alpha.sum()))
+    inv_s = sum(float(alpha[l]) / 2 ** l for l in range(Lspan + 1)) / float(alpha.sum())
+    return {"alpha": alpha.tolist(), "w_lts": w_lts, "w_gts": w_gts,
+            "s_est": 1.0 / inv_s, "s_max": float(alpha.sum()) / float(alpha[0])}

@@ -1,0 +1,135 @@
+"""Seeded synthetic inputs shared by the library's tests/benchmarks and the oracle.
+
+This package holds no arithmetic of the method (no stencil, interpolation,
+time-stepping or mesh logic).  It provides
+  * the frozen mesh specifications of the benchmark configurations (integer
+    refinement radii in node units, calibrated once by ``calibrate.py`` beside
+    this file and then stored here),
+  * seeded pulse centres,
+  * initial data evaluated at octant-local node coordinates of a given leaf list
+    (Gaussian pulse, plane wave, divergence-free Maxwell data),
+  * seeded random DG arrays for kernel unit tests.
+
+Coordinates: level-L node units, N_u = 4 * 2^L per side, x = -1 + 2 X / N_u; a
+leaf (anchor a in level-L octant units, level l) has nodes 4 a + i 2^(L-l).
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ----------------------------------------------------------------------------- coordinates
+def node_units(anchors: np.ndarray, levels: np.ndarray, L: int) -> np.ndarray:
+    """Integer node coordinates [N, 5, 5, 5, 3] (x, y, z), node index [k][j][i]."""
+    anchors = np.asarray(anchors, dtype=np.int64)
+    s = (1 << (L - np.asarray(levels, dtype=np.int64)))
+    i = np.arange(5, dtype=np.int64)
+    k_, j_, i_ = np.meshgrid(i, i, i, indexing="ij")
+    loc = np.stack([i_, j_, k_], axis=-1)[None]                   # [1,5,5,5,3]
+    return 4 * anchors[:, None, None, None, :] + loc * s[:, None, None, None, None]
+
+
+def physical(X: np.ndarray, L: int) -> np.ndarray:
+    return -1.0 + 2.0 * X.astype(np.float64) / float(4 * (1 << L))
+
+
+def centre_from_seed(seed: int, L: int, lo: float = -0.5, hi: float = 0.5) -> List[int]:
+    """Pulse centre ~ U([lo, hi]^3) from numpy's default_rng(seed), snapped to node units."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(lo, hi, size=3)
+    n = 4 * (1 << L)
+    return [int(round((v + 1.0) * 0.5 * n)) % n for v in x]
+
+
+def centre_physical(c: Sequence[int], L: int) -> np.ndarray:
+    return -1.0 + 2.0 * np.asarray(c, dtype=np.float64) / float(4 * (1 << L))
+
+
+IMAGES = np.array([(a, b, c) for c in (-1, 0, 1) for b in (-1, 0, 1) for a in (-1, 0, 1)], dtype=np.float64) * 2.0
+
+
+# ----------------------------------------------------------------------------- initial data
+def gaussian(x: np.ndarray, centres: np.ndarray, sigma: float, amp: float = 1.0) -> np.ndarray:
+    """sum over pulses and the 27 nearest periodic images of amp exp(-r^2 / (2 sigma^2))."""
+    out = np.zeros(x.shape[:-1])
+    for c in np.atleast_2d(centres):
+        for im in IMAGES:
+            d = x - (c + im)
+            out += amp * np.exp(-(d * d).sum(axis=-1) / (2.0 * sigma * sigma))
+    return out
+
+
+def wave_gaussian(anchors, levels, L, centres_nu, sigma=0.1, amp=1.0) -> np.ndarray:
+    """Wave-equation data (u, v) = (Gaussian, 0): [2, N, 5, 5, 5]."""
+    x = physical(node_units(anchors, levels, L), L)
+    c = np.stack([centre_physical(cc, L) for cc in centres_nu])
+    u = gaussian(x, c, sigma, amp)
+    return np.stack([u, np.zeros_like(u)])
+
+
+def wave_plane(anchors, levels, L, n=(1, 0, 0)) -> np.ndarray:
+    """(u, v) = (sin(k.x), -|k| cos(k.x)), k = pi n: a periodic travelling wave."""
+    x = physical(node_units(anchors, levels, L), L)
+    k = np.pi * np.asarray(n, dtype=np.float64)
+    ph = (x * k).sum(axis=-1)
+    return np.stack([np.sin(ph), -np.linalg.norm(k) * np.cos(ph)])
+
+
+def maxwell_gaussian(anchors, levels, L, centres_nu, sigma=0.1, amp=1.0) -> np.ndarray:
+    """E = curl(z psi) = (d_y psi, -d_x psi, 0), B = 0 with psi a Gaussian: [6, N, 5, 5, 5]."""
+    x = physical(node_units(anchors, levels, L), L)
+    ex = np.zeros(x.shape[:-1])
+    ey = np.zeros(x.shape[:-1])
+    for cc in centres_nu:
+        c = centre_physical(cc, L)
+        for im in IMAGES:
+            d = x - (c + im)
+            g = amp * np.exp(-(d * d).sum(axis=-1) / (2.0 * sigma * sigma))
+            ex += -d[..., 1] / (sigma * sigma) * g
+            ey += d[..., 0] / (sigma * sigma) * g
+    z = np.zeros_like(ex)
+    return np.stack([ex, ey, z, z, z.copy(), z.copy()])
+
+
+def random_dg(shape, seed: int, scale: float = 1.0) -> np.ndarray:
+    return np.random.default_rng(seed).standard_normal(shape) * scale
+
+
+def consistent_random_dg(anchors, levels, L, nfields: int, seed: int) -> np.ndarray:
+    """Random smooth-free data whose duplicated DG nodes agree: a random value per
+    distinct node coordinate (hash of the integer coordinate)."""
+    X = node_units(anchors, levels, L)
+    n = 4 * (1 << L)
+    key = (X[..., 0] % n) + n * ((X[..., 1] % n) + n * (X[..., 2] % n))
+    out = []
+    for f in range(nfields):
+        rng = np.random.default_rng(seed * 1000 + f)
+        uniq, inv = np.unique(key.ravel(), return_inverse=True)
+        vals = rng.standard_normal(len(uniq))
+        out.append(vals[inv.reshape(-1)].reshape(key.shape))
+    return np.stack(out)
+
+
+# ----------------------------------------------------------------------------- configurations
+def _load_specs() -> Dict[str, dict]:
+    with open(os.path.join(_HERE, "specs.json")) as f:
+        return json.load(f)
+
+
+def mesh_spec(name: str) -> dict:
+    """Frozen mesh specification (dict) of a named configuration."""
+    return _load_specs()[name]["mesh"]
+
+
+def config(name: str) -> dict:
+    return _load_specs()[name]
+
+
+def config_names() -> List[str]:
+    return list(_load_specs().keys())

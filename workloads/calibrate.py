@@ -1,0 +1,168 @@
+"""Writes workloads/specs.json: frozen integer mesh specifications of the benchmark
+configurations.  Run once: ``python -m workloads.calibrate``.
+
+Radii are searched so that the oracle's mesh builder produces the target leaf
+count; only the resulting integers are stored.  Targets (synthetic stand-ins for
+the paper's Gaussian-pulse workloads, Sec. 4.2 and 4.5):
+  wave_c1   levels 2-4, one pulse (sigma 0.1, centre from seed 0), ball criteria,
+            as close to 1.5k leaves as keeps all three levels present.  With the
+            ghost-reach balance the level-3 buffer around a larger level-4 ball
+            wraps the periodic domain and removes level 2, so the count is ~600.
+  wave_c2   levels 3-8, four pulses (seeds 0..3, centres in [-0.6, 0.6]^3), the
+            gradient criterion  W_l |grad g| > eps  as per-level annuli,
+            about 200k leaves.
+  small     levels 2-3 ball, a few hundred leaves (fast tests).
+  batch_i   64 problems of 1k-50k leaves (log-uniform target from seed), levels
+            2..L_i, nested balls.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from oracle.octree import MeshSpec, build_mesh  # noqa: E402
+from workloads import centre_from_seed  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def ball_spec(l_min, L, centre, radii_nu):
+    r2 = [-1] * L
+    for lev in range(l_min, L):
+        r2[lev] = int(radii_nu[lev - l_min]) ** 2
+    return {"l_min": l_min, "l_max": L, "block_cap": 4,
+            "criteria": [{"kind": "ball", "center": centre, "r2": r2}]}
+
+
+def count(spec, levels=None):
+    m = build_mesh(MeshSpec.from_dict(spec))
+    if levels is not None and (m.lmin, m.lmax) != levels:
+        return -10 ** 9
+    return m.n_oct
+
+
+def calib_c1():
+    """All three levels 2, 3, 4 must be present."""
+    L, l_min = 4, 2
+    c = centre_from_seed(0, L)
+    best = None
+    for r in range(2, 40):
+        for d in (2, 4, 8, 12, 16):
+            spec = ball_spec(l_min, L, c, [r + d, r])
+            n = count(spec, (2, 4))
+            if best is None or abs(n - 1500) < abs(best[0] - 1500):
+                best = (n, spec)
+    return best
+
+
+def annulus(sigma, eps, level, n_u):
+    """Shell where W_l r/sigma^2 exp(-r^2/(2 sigma^2)) > eps (W_l = 2/2^l), in node units."""
+    W = 2.0 / (1 << level)
+    f = lambda r: W * r / sigma ** 2 * math.exp(-r * r / (2 * sigma * sigma)) - eps
+    if f(sigma) <= 0:
+        return -1, -1
+    lo, hi = 0.0, sigma
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) <= 0 else (lo, mid)
+    r_lo = hi
+    lo, hi = sigma, 10 * sigma
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) > 0 else (lo, mid)
+    r_hi = lo
+    s = n_u / 2.0
+    return int(math.floor((r_lo * s) ** 2)), int(math.ceil((r_hi * s) ** 2))
+
+
+def c2_spec(eps, L=8, l_min=3, sigma=0.1):
+    n_u = 4 * (1 << L)
+    crit = []
+    for seed in range(4):
+        c = centre_from_seed(seed, L, -0.6, 0.6)
+        rlo2, rhi2 = [-1] * L, [-1] * L
+        for lev in range(l_min, L):
+            a, b = annulus(sigma, eps, lev, n_u)
+            rlo2[lev], rhi2[lev] = a, b
+        crit.append({"kind": "annulus", "center": c, "rlo2": rlo2, "rhi2": rhi2})
+    return {"l_min": l_min, "l_max": L, "block_cap": 4, "criteria": crit}
+
+
+def calib_c2(target=200_000):
+    lo, hi = 0.002, 0.2        # larger eps -> fewer leaves
+    best = None
+    for _ in range(22):
+        mid = math.sqrt(lo * hi)
+        spec = c2_spec(mid)
+        n = count(spec)
+        print(f"  c2 eps={mid:.6g} leaves={n}", flush=True)
+        if best is None or abs(n - target) < abs(best[0] - target):
+            best = (n, spec, mid)
+        if abs(n - target) < 0.01 * target:
+            break
+        lo, hi = (lo, mid) if n < target else (mid, hi)
+    return best
+
+
+def batch_specs(n_prob=64, seed=1234):
+    rng = np.random.default_rng(seed)
+    targets = np.round(np.exp(rng.uniform(math.log(1e3), math.log(5e4), size=n_prob))).astype(int)
+    out = []
+    for i, tgt in enumerate(targets):
+        # smallest finest level whose uniform refinement could hold twice the target
+        L = 4
+        while L < 8 and 8 ** L < 2 * tgt:
+            L += 1
+        c = centre_from_seed(100 + i, L)
+        n_u = 4 * (1 << L)
+        best = None
+        lo, hi = 0.02, 1.2
+        for _ in range(18):
+            r0 = 0.5 * (lo + hi)
+            radii = [int(round(r0 * (1.0 + 0.6 * (L - 1 - lev)) * n_u / 2)) for lev in range(2, L)]
+            spec = ball_spec(2, L, c, radii)
+            n = count(spec)
+            if best is None or abs(n - tgt) < abs(best[0] - tgt):
+                best = (n, spec)
+            lo, hi = (r0, hi) if n < tgt else (lo, r0)
+        out.append({"target": int(tgt), "leaves": int(best[0]), "mesh": best[1]})
+        print(f"  batch {i}: L={L} target={tgt} leaves={best[0]}", flush=True)
+    return out
+
+
+def main():
+    specs = {}
+    n, spec = calib_c1()
+    print("c1 leaves", n)
+    specs["wave_c1"] = {"mesh": spec, "equation": "wave", "sigma": 0.1, "pulses": [centre_from_seed(0, 4)],
+                        "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 8, "leaves": n}
+    small = ball_spec(2, 3, centre_from_seed(0, 3), [6])
+    assert count(small, (2, 3)) > 0
+    specs["small"] = {"mesh": small, "equation": "wave", "sigma": 0.1, "pulses": [centre_from_seed(0, 3)],
+                      "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 2, "leaves": count(small)}
+    n2, spec2, eps = calib_c2()
+    print("c2 leaves", n2, "eps", eps)
+    specs["wave_c2"] = {"mesh": spec2, "equation": "wave", "sigma": 0.1,
+                        "pulses": [c["center"] for c in spec2["criteria"]], "eps": eps,
+                        "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 8, "leaves": n2}
+    if "--batch" in sys.argv:
+        specs["batch"] = {"problems": batch_specs(), "equation": "wave", "sigma": 0.1, "ko_sigma": 0.1,
+                          "tableau": "rk4", "n_coarse": 8}
+    else:
+        old = os.path.join(HERE, "specs.json")
+        if os.path.exists(old):
+            prev = json.load(open(old))
+            if "batch" in prev:
+                specs["batch"] = prev["batch"]
+    with open(os.path.join(HERE, "specs.json"), "w") as f:
+        json.dump(specs, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
