@@ -94,13 +94,15 @@ def _naive_balance(a, l, L):
         a = np.concatenate([a[keep], ch]); l = np.concatenate([l[keep], np.full(8, l[hit] + 1)])
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
-def test_balance_equals_naive_closure(seed):
-    a, l = _random_tree(seed)
-    ba, bl = ot.balance(a, l, 4)
-    na, nl = _naive_balance(a, l, 4)
+@pytest.mark.parametrize("seed,L,lmin,p", [(0, 4, 1, 0.35), (1, 4, 1, 0.35), (2, 4, 1, 0.35), (3, 4, 1, 0.35),
+                                            (4, 5, 2, 0.02), (5, 5, 2, 0.03), (6, 5, 2, 0.015)])
+def test_balance_equals_naive_closure(seed, L, lmin, p):
+    """Dense trees exercise plain 2:1 contact, sparse deep trees the 3 h reach."""
+    a, l = _random_tree(seed, L, lmin, p)
+    ba, bl = ot.balance(a, l, L)
+    na, nl = _naive_balance(a, l, L)
     assert np.array_equal(ba, na) and np.array_equal(bl, nl)
-    assert ot.is_balanced_bruteforce(ba, bl, 4)
+    assert ot.is_balanced_bruteforce(ba, bl, L)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
