@@ -1,0 +1,254 @@
+/*
+ * lts.h -- C ABI of the MI355X (gfx950) octree local-timestepping library.
+ *
+ * Method: "Scalable Local Timestepping on Octree Grids" (Fernando & Sundar,
+ * arXiv 2011.10570).  A method-of-lines system du/dt = F(u) (eq. evolve_eq) is
+ * discretised on a periodic, balanced linear octree over [-1,1]^3 whose leaves
+ * carry 5^3 octant-local nodes (Sec. 3.2, fig. dg_to_cg "octant local nodes").
+ * The octree is cut into uniformly refined blocks (Sec. 3.3, fig. oct_to_blocks);
+ * each RK stage builds ghost-padded blocks (unzip, Sec. 3.4, fig. unzip), applies
+ * sixth-order finite differences with Kreiss-Oliger dissipation on the block
+ * grid (rhs), scatters the result back to the octants (zip) and, after the last
+ * stage, forms the RK update (eq. rk_schemes).  Global timestepping (GTS,
+ * Alg. 1) steps every block with the finest dt; local timestepping (LTS,
+ * Alg. 2 with the schedule of fig. blk_loop) steps level-l blocks with
+ * dt_l = 0.25 h_l and converts a neighbour's stored RK stages to the receiver's
+ * step with the correction operators of eqs. fc_1 / fc_2.
+ *
+ * Conventions
+ *   Status.     Every entry point returns lts_status (0 = LTS_OK); on error
+ *               lts_last_error() gives a message for the calling thread.  No C++
+ *               exception and no abort crosses this boundary.
+ *   Ownership.  lts_mesh / lts_sim handles (and the device tables they upload)
+ *               belong to the library; free them with *_destroy.  State and
+ *               stage arrays are owned by the caller and passed as raw device
+ *               pointers; the library only borrows them.
+ *   Streams.    Device work is enqueued asynchronously on the hipStream_t given
+ *               (passed as void*, NULL = default stream); only calls that return
+ *               host results synchronise that stream.  A kernel fault surfaces as
+ *               LTS_EDEVICE from the next call that synchronises.
+ *   Layouts.    All device arrays are contiguous.
+ *               U  : double [2][F][N][125]       two state buffers ("parities")
+ *               K  : double|float [p][F][N][125] RK stages (float in FP32-RHS mode)
+ *               node index within an octant: i + 5 j + 25 k (i fastest, along x);
+ *               octants in Morton order (child index x + 2y + 4z), the order of
+ *               lts_mesh_export(LTS_EXPORT_LEAVES).
+ *               Padded blocks (lts_unzip output / lts_rhs input): per field, the
+ *               blocks of the call in call order, block b holding S^3 doubles,
+ *               S = 4 m_b + 7, point (i,j,k) in [-3, 4m+3]^3 at
+ *               ((k+3) S + (j+3)) S + (i+3).
+ *               Block grids (lts_rhs output / lts_zip input): per field, blocks
+ *               in call order, (4 m_b + 1)^3 values each, (k (4m+1) + j)(4m+1) + i.
+ *   Buffers.    A block's step writes its new state into the U buffer its step
+ *               record does not read.  Which buffer a block reads follows from the
+ *               step counters: a level-l block's step index at substep j of
+ *               coarse step n is s = n 2^(l - lmin) + (j >> (lmax - l)) in LTS and
+ *               s = n 2^(lmax - lmin) + j in GTS; its record reads U[s & 1] and
+ *               its update writes U[(s + 1) & 1].
+ */
+#ifndef LTS_H_
+#define LTS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LTS_OK = 0,
+  LTS_EINVAL = 1,        /* bad argument, size or layout                       */
+  LTS_ENOMEM = 2,        /* host or device allocation failed                   */
+  LTS_EDEVICE = 3,       /* HIP runtime error (launch, copy, kernel fault)     */
+  LTS_EUNBALANCED = 4,   /* a ghost source is not within one level             */
+  LTS_ENONFINITE = 5,    /* a NaN/Inf was found in the state                   */
+  LTS_EUNSUPPORTED = 6   /* combination not built (equation/precision/tile)    */
+} lts_status;
+
+enum { LTS_MAX_LEVEL = 16 };
+
+enum { LTS_CRIT_BALL = 0, LTS_CRIT_ANNULUS = 1 };
+enum { LTS_MODE_LTS = 0, LTS_MODE_GTS = 1 };
+enum { LTS_EQ_WAVE = 0, LTS_EQ_MAXWELL = 1 };
+enum { LTS_FP64 = 0, LTS_FP32_RHS = 1 };
+enum { LTS_RK4 = 0, LTS_SSPRK3 = 1 };
+
+/* Export kinds for lts_mesh_export (all int32 rows unless stated). */
+enum {
+  LTS_EXPORT_LEAVES = 0,     /* [N][4]  anchor x, y, z (level-L octant units), level          */
+  LTS_EXPORT_BLOCKS = 1,     /* [B][6]  first leaf, m, level, anchor x, y, z                  */
+  LTS_EXPORT_UNZIP_MAP = 2,  /* [sum_b S_b^3][5] source leaf, kind, 2*px, 2*py, 2*pz            */
+  LTS_EXPORT_SCHEDULE = 3,   /* for j = 0..2^dL-1: count, then that many block indices         */
+  LTS_EXPORT_TILES = 4       /* [T][8] tiles of the fused kernel (see lts_mesh_set_tile)       */
+};
+
+/* Unzip-map source kinds (Sec. 3.4): own octant, same-level neighbour, finer
+ * neighbour (f->c injection), coarser neighbour (c->f interpolation). */
+enum { LTS_SRC_OWN = 0, LTS_SRC_SAME = 1, LTS_SRC_FINE = 2, LTS_SRC_COARSE = 3 };
+
+/* Refinement criterion around an integer centre (node units at level l_max:
+ * 4 * 2^l_max per side, x = -1 + 2 X / (4 * 2^l_max)).  A level-l leaf is split
+ * if, with dmin / dmax the smallest / largest periodic distance from the centre
+ * to the leaf's closed box,
+ *   LTS_CRIT_BALL:    dmin^2 < r2[l]
+ *   LTS_CRIT_ANNULUS: rlo2[l] < dmax^2 and dmin^2 < rhi2[l]
+ * Negative entries never refine.  (Integer stand-in for the wavelet criterion
+ * of Sec. 3.2.2 so that meshes are reproducible bit for bit.) */
+typedef struct {
+  int32_t kind;
+  int32_t center[3];
+  int64_t r2[LTS_MAX_LEVEL];
+  int64_t rlo2[LTS_MAX_LEVEL];
+  int64_t rhi2[LTS_MAX_LEVEL];
+} lts_criterion;
+
+/* Mesh specification.  Either criteria (refine from the uniform level l_min) or an
+ * explicit leaf list (int32 [n_leaves][4] = anchor x, y, z in level-l_max octant
+ * units, level; must tile the domain) is used.  The result is always closed under
+ * the ghost-reach balance: a level-l leaf is split while a leaf of level >= l+2
+ * lies within 3 h_l of it (2:1 balance of Sec. 3.2.3 extended so that the three
+ * ghost layers of a block only reach leaves one level apart). */
+typedef struct {
+  int32_t l_min, l_max;      /* 0 <= l_min <= l_max < LTS_MAX_LEVEL, l_max <= 10 */
+  int32_t block_cap;         /* max octants per block side: 1, 2 or 4              */
+  int32_t n_criteria;
+  const lts_criterion* criteria;   /* host */
+  int64_t n_leaves;          /* > 0: use the explicit leaf list                    */
+  const int32_t* leaves;     /* host */
+} lts_mesh_spec;
+
+typedef struct {
+  int64_t n_oct, n_blocks, n_tiles;
+  int32_t L;                 /* coordinate resolution (spec l_max)                  */
+  int32_t lmin, lmax;        /* levels present                                      */
+  int32_t n_substeps;        /* 2^(lmax - lmin)                                     */
+  int32_t tile;              /* current fused-kernel tile side (1 or 2)             */
+  int64_t level_count[LTS_MAX_LEVEL];   /* leaves per level                          */
+  int64_t unzip_points;      /* sum over blocks of (4m+7)^3                         */
+  int64_t grid_points;       /* sum over blocks of (4m+1)^3                         */
+  int64_t node_updates_lts;  /* DG node-updates per coarse step, LTS (eq. w_nuts)   */
+  int64_t node_updates_gts;  /* same for GTS (eq. w_uts)                             */
+  double s_est;              /* speedup model 1/S of eq. invS, inverted             */
+  double s_max;              /* |W| / alpha_0                                        */
+} lts_mesh_info;
+
+typedef struct lts_mesh lts_mesh;
+typedef struct lts_sim lts_sim;
+
+/* Device arrays of one state (see Layouts).  nfields: 2 (wave) or 6 (Maxwell). */
+typedef struct {
+  void* U;                   /* double [2][F][N][125]                               */
+  void* K;                   /* [p][F][N][125], double (LTS_FP64) / float (FP32_RHS) */
+  int32_t nfields;
+  int32_t precision;         /* LTS_FP64 / LTS_FP32_RHS                             */
+  int32_t tableau;           /* LTS_RK4 / LTS_SSPRK3                                */
+} lts_stage_view;
+
+/* Schedule position: substep j in [0, 2^dL) of coarse step n, and the mode.
+ * The time case of every ghost relation and the U buffer of every step record
+ * follow from it (see Buffers). */
+typedef struct {
+  int32_t substep;
+  int32_t mode;              /* LTS_MODE_LTS / LTS_MODE_GTS                          */
+  int64_t coarse_step;
+} lts_position;
+
+typedef struct {
+  double ko_sigma;           /* Kreiss-Oliger strength (0.1 default)                */
+} lts_rhs_params;
+
+/* ---- errors ---------------------------------------------------------------- */
+const char* lts_last_error(void);
+const char* lts_version(void);
+
+/* ---- mesh (host; Sec. 3.2-3.3) ----------------------------------------------- */
+/* Build leaves (refinement + balance), blocks, tiles, unzip source tables and the
+ * level schedule on the host.  No device call is made; tables are uploaded on
+ * first device use.  Errors: LTS_EINVAL (bad spec / leaves do not tile),
+ * LTS_EUNBALANCED (internal check), LTS_ENOMEM. */
+lts_status lts_build_mesh(const lts_mesh_spec* spec, lts_mesh** out);
+void lts_mesh_destroy(lts_mesh* mesh);
+lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info);
+/* Copy a table to host memory `buf` of `cap` bytes; `*needed` receives the size
+ * in bytes (call with buf = NULL to ask).  LTS_EINVAL if cap is too small. */
+lts_status lts_mesh_export(const lts_mesh* mesh, int32_t kind, void* buf, size_t cap, size_t* needed);
+/* Fused-kernel tile side (octants per tile side, 1 or 2; blocks of side m are cut
+ * into min(m, t)^3 tiles).  Results do not depend on it. */
+lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile);
+/* Exact-rational stage conversion weights w^[case][stage][i] as float64 (eqs.
+ * rk_crrection, fc_1, fc_2 with K = C P D), cases (delta, rho) = (0,1), (0,1/2),
+ * (0,2), (1,2); plus a[p][p] and b[p].  out: double[4*p*p + p*p + p] (host). */
+lts_status lts_coefficients(int32_t tableau, double* out, size_t cap);
+
+/* ---- unfused hot path (one call per phase; Sec. 3.4, Alg. 1/2) --------------- */
+/* `blocks` is a HOST array of nb block indices (NULL = every block of B_j at
+ * `pos`, in block order).  All other pointers are device pointers. */
+
+/* a2: padded stage state Y_s = U0 + dt_r sum_i w^_{s,i}(case) K_i of every padded
+ * point of the listed blocks, with f->c injection and tensor degree-4 Lagrange
+ * c->f interpolation (Sec. 3.4; eqs. fc_1/fc_2).  stage is 0-based. */
+lts_status lts_unzip(lts_mesh* mesh, const lts_stage_view* view, int32_t stage,
+                     const lts_position* pos, const int32_t* blocks, int32_t nb,
+                     double* padded, void* stream);
+/* a3: block RHS on the (4m+1)^3 block grid: wave du = v + KO(u), dv = Lap6 u +
+ * KO(v); Maxwell dE = curl6 B + KO(E), dB = -curl6 E + KO(B); KO(f) =
+ * sigma/(64h) sum_axes (1,-6,15,-20,15,-6,1) f.  precision LTS_FP32_RHS evaluates
+ * the stencils in float (output float), else double. */
+lts_status lts_rhs(lts_mesh* mesh, int32_t equation, const lts_rhs_params* params,
+                   const double* padded, int32_t precision, const int32_t* blocks,
+                   int32_t nb, void* k_block, void* stream);
+/* a5: block grid -> every DG node of the blocks' octants (intra-block duplicates
+ * get the block grid value).  k_octant: [F][N][125] (a K_s slice), element type
+ * from precision. */
+lts_status lts_zip(lts_mesh* mesh, int32_t nfields, int32_t precision, const void* k_block,
+                   const int32_t* blocks, int32_t nb, void* k_octant, void* stream);
+/* a4: out = U0 + dt_l sum_i coef_i K_i on the listed blocks' octants, dt_l the
+ * block's step (finest step in GTS).  out = NULL writes the block's other U buffer
+ * (the RK update of eq. rk_schemes when coef = b). */
+lts_status lts_rk_stage(lts_mesh* mesh, const lts_stage_view* view, const double* coef,
+                        int32_t ncoef, const lts_position* pos, const int32_t* blocks,
+                        int32_t nb, double* out, void* stream);
+
+/* a6: the fused stage (unzip + rhs + zip [+ RK update at the last stage]) for
+ * every block of B_j, one launch over LDS-resident tiles. */
+lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t equation,
+                           const lts_rhs_params* params, int32_t stage,
+                           const lts_position* pos, void* stream);
+
+/* ---- simulation driver (a7; Alg. 1 / Alg. 2) ---------------------------------- */
+lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, int32_t tableau,
+                          const lts_rhs_params* params, lts_sim** out);
+/* Bind caller-owned device arrays (see lts_stage_view).  U[0] must hold the
+ * initial state; the sim's coarse-step counter is reset to 0. */
+lts_status lts_sim_bind(lts_sim* sim, void* U, void* K);
+/* Advance n coarse steps (T += n dt_lmin) with the fused kernels.  use_graph != 0
+ * captures one coarse step in a hipGraph on first use and replays it. */
+lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t use_graph,
+                       void* stream);
+/* Same with the unfused phase kernels (unzip, rhs, zip, rk_stage). */
+lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, void* stream);
+/* Gather the current state of every octant into out ([F][N][125] doubles). */
+lts_status lts_sim_current(lts_sim* sim, double* out, void* stream);
+int64_t lts_sim_coarse_step(const lts_sim* sim);
+void lts_sim_destroy(lts_sim* sim);
+
+/* Several independent simulations advanced together: every stage of every
+ * substep is one persistent launch over the union of the sims' active tiles
+ * (sims with fewer substeps idle in the rounds they do not use). */
+lts_status lts_batch_advance(lts_sim* const* sims, int32_t n, int64_t n_coarse_steps,
+                             int32_t mode, void* stream);
+
+/* ---- reductions ----------------------------------------------------------------- */
+/* Per field volume-weighted l2 and max norm of (a - b) over all DG nodes (b may
+ * be NULL) and the number of non-finite values in a.  out (host):
+ * double[2F + 1] = l2[F], linf[F], nonfinite.  Synchronises the stream. */
+lts_status lts_norms(lts_mesh* mesh, int32_t nfields, const double* a, const double* b,
+                     double* out, void* stream);
+/* Device copy of nbytes (bandwidth probe used as the measured HBM reference). */
+lts_status lts_copy_probe(const void* src, void* dst, size_t nbytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTS_H_ */

@@ -191,20 +191,31 @@ class State:
                     dest[:, octs[ok, oj, oi]] = grid[:, 4 * ok:4 * ok + 5, 4 * oj:4 * oj + 5, 4 * oi:4 * oi + 5]
 
     # ------------------------------------------------------------------ one substep
-    def substep(self, j: int, rhs, sigma: float):
-        """Substep j of Alg. 2 (or one step of Alg. 1 in GTS mode)."""
-        mesh = self.mesh
-        act = active_blocks(mesh, j, self.mode)
-        for b in act:                       # open step records
+    def open_records(self, j: int) -> np.ndarray:
+        """Blocks B_j start a step: their record is (current buffer, current time)."""
+        act = active_blocks(self.mesh, j, self.mode)
+        for b in act:
             self.rec_par[b] = self.cur_par[b]
             self.rec_t0[b] = self.cur_t[b]
-        for s in range(self.p):
-            for b in act:
-                pad = self.unzip(b, s)
-                h = 2.0 ** (-int(mesh.blocks[b, 2]) - 1)     # block grid spacing h_lam
-                grid = rhs(pad, h, sigma)
-                self.zip_into(b, grid, self.K[s])
-        for b in act:                       # compute_step_partial
+        return act
+
+    def close_records(self, act):
+        """After the step the state lives in the other buffer, one step later."""
+        for b in act:
+            self.cur_par[b] = 1 - self.rec_par[b]
+            self.cur_t[b] = self.rec_t0[b] + self.dt_ticks[b]
+
+    def stage(self, act, s: int, rhs, sigma: float):
+        """Stage s of every block of B_j: unzip, block RHS, zip into K_s."""
+        for b in act:
+            pad = self.unzip(b, s)
+            h = 2.0 ** (-int(self.mesh.blocks[b, 2]) - 1)     # block grid spacing h_lam
+            grid = rhs(pad, h, sigma)
+            self.zip_into(b, grid, self.K[s])
+
+    def rk_update(self, act):
+        """compute_step_partial: U_new = U0 + dt sum_i b_i K_i into the other buffer."""
+        for b in act:
             octs = self.plan(b)["octs"].ravel()
             par = self.rec_par[b]
             dt = self.dt_phys(b)
@@ -212,8 +223,14 @@ class State:
             for i in range(self.p):
                 acc += self.b[i] * self.K[i][:, octs]
             self.U[1 - par][:, octs] = self.U[par][:, octs] + dt * acc
-            self.cur_par[b] = 1 - par
-            self.cur_t[b] = self.rec_t0[b] + self.dt_ticks[b]
+
+    def substep(self, j: int, rhs, sigma: float):
+        """Substep j of Alg. 2 (or one step of Alg. 1 in GTS mode)."""
+        act = self.open_records(j)
+        for s in range(self.p):
+            self.stage(act, s, rhs, sigma)
+        self.rk_update(act)
+        self.close_records(act)
 
 
 EQ = {"wave": (2, fd.rhs_wave), "maxwell": (6, fd.rhs_maxwell)}

@@ -1,0 +1,286 @@
+"""MI355X octree local timestepping: thin Python binding of the C ABI (include/lts.h).
+
+Names follow the C entry points (build_mesh, unzip, rhs, rk_stage, zip,
+fused_stage, advance).  Arguments are marshalled to raw pointers; PyTorch is used
+only for device memory and streams.  Every step of the method runs in the
+library's HIP kernels; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as _L
+from ._lib import (CRIT_ANNULUS, CRIT_BALL, EQ_MAXWELL, EQ_WAVE, FP32_RHS, FP64, MODE_GTS, MODE_LTS, RK4,
+                   SSPRK3, LTSError, check, lib)
+
+__all__ = ["Mesh", "Sim", "build_mesh", "unzip", "rhs", "zip", "rk_stage", "fused_stage", "coefficients",
+           "norms", "copy_probe", "LTSError", "MODE_LTS", "MODE_GTS", "EQ_WAVE", "EQ_MAXWELL", "FP64", "FP32_RHS",
+           "RK4", "SSPRK3"]
+
+EQUATIONS = {"wave": EQ_WAVE, "maxwell": EQ_MAXWELL}
+TABLEAUS = {"rk4": RK4, "ssprk3": SSPRK3}
+NFIELDS = {EQ_WAVE: 2, EQ_MAXWELL: 6}
+NSTAGES = {RK4: 4, SSPRK3: 3}
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return t.data_ptr()
+    return int(t)
+
+
+class Mesh:
+    """Octree mesh (leaves, blocks, tiles, ghost tables) built by the library's host code."""
+
+    def __init__(self, spec: Optional[dict] = None, leaves=None, L: Optional[int] = None, block_cap: int = 4):
+        cs = _L.MeshSpecC()
+        keep = []
+        if leaves is not None:
+            arr = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+            keep.append(arr)
+            cs.l_min = int(arr[:, 3].min())
+            cs.l_max = int(L if L is not None else arr[:, 3].max())
+            cs.block_cap = block_cap
+            cs.n_leaves = len(arr)
+            cs.leaves = arr.ctypes.data_as(C.POINTER(C.c_int32))
+        else:
+            cs.l_min = int(spec["l_min"])
+            cs.l_max = int(spec["l_max"])
+            cs.block_cap = int(spec.get("block_cap", 4))
+            crits = spec.get("criteria", [])
+            arr = (_L.Criterion * max(1, len(crits)))()
+            for i, c in enumerate(crits):
+                arr[i].kind = CRIT_BALL if c["kind"] == "ball" else CRIT_ANNULUS
+                for d in range(3):
+                    arr[i].center[d] = int(c["center"][d])
+                for lev in range(_L.MAX_LEVEL):
+                    for name in ("r2", "rlo2", "rhi2"):
+                        vals = c.get(name, ())
+                        getattr(arr[i], name)[lev] = int(vals[lev]) if lev < len(vals) else -1
+            keep.append(arr)
+            cs.n_criteria = len(crits)
+            cs.criteria = arr
+        h = C.c_void_p()
+        check(lib().lts_build_mesh(C.byref(cs), C.byref(h)), "lts_build_mesh")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                lib().lts_mesh_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    @property
+    def _as_parameter_(self):
+        return self.h
+
+    def info(self) -> dict:
+        inf = _L.MeshInfo()
+        check(lib().lts_mesh_query(self.h, C.byref(inf)), "lts_mesh_query")
+        d = {k: getattr(inf, k) for k, _ in inf._fields_}
+        d["level_count"] = list(inf.level_count)
+        return d
+
+    def export(self, kind: int) -> np.ndarray:
+        need = C.c_size_t()
+        check(lib().lts_mesh_export(self.h, kind, None, 0, C.byref(need)), "lts_mesh_export")
+        buf = np.empty(need.value // 4, dtype=np.int32)
+        check(lib().lts_mesh_export(self.h, kind, buf.ctypes.data, need.value, C.byref(need)), "lts_mesh_export")
+        return buf
+
+    def leaves(self) -> np.ndarray:
+        return self.export(_L.EXPORT_LEAVES).reshape(-1, 4)
+
+    def blocks(self) -> np.ndarray:
+        return self.export(_L.EXPORT_BLOCKS).reshape(-1, 6)
+
+    def unzip_map(self) -> np.ndarray:
+        return self.export(_L.EXPORT_UNZIP_MAP).reshape(-1, 5)
+
+    def schedule(self) -> list:
+        raw = self.export(_L.EXPORT_SCHEDULE)
+        out, i = [], 0
+        while i < len(raw):
+            n = int(raw[i])
+            out.append(raw[i + 1:i + 1 + n].copy())
+            i += 1 + n
+        return out
+
+    def tiles(self) -> np.ndarray:
+        return self.export(_L.EXPORT_TILES).reshape(-1, 8)
+
+    def set_tile(self, t: int):
+        check(lib().lts_mesh_set_tile(self.h, int(t)), "lts_mesh_set_tile")
+
+
+def build_mesh(spec: Optional[dict] = None, leaves=None, L: Optional[int] = None, block_cap: int = 4) -> Mesh:
+    return Mesh(spec, leaves=leaves, L=L, block_cap=block_cap)
+
+
+def coefficients(tableau: int = RK4) -> dict:
+    p = NSTAGES[tableau]
+    out = np.empty(4 * p * p + p * p + p)
+    check(lib().lts_coefficients(tableau, out.ctypes.data_as(C.POINTER(C.c_double)), out.nbytes), "lts_coefficients")
+    return {"w": out[:4 * p * p].reshape(4, p, p), "a": out[4 * p * p:5 * p * p].reshape(p, p),
+            "b": out[5 * p * p:]}
+
+
+def _view(U, K, nfields, precision, tableau):
+    v = _L.StageView()
+    v.U = _ptr(U)
+    v.K = _ptr(K)
+    v.nfields = nfields
+    v.precision = precision
+    v.tableau = tableau
+    return v
+
+
+def _pos(substep, mode, coarse_step):
+    p = _L.Position()
+    p.substep = int(substep)
+    p.mode = int(mode)
+    p.coarse_step = int(coarse_step)
+    return p
+
+
+def _blocks_arg(blocks):
+    if blocks is None:
+        return None, 0, None
+    arr = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32))
+    return arr.ctypes.data_as(C.POINTER(C.c_int32)), len(arr), arr
+
+
+def unzip(mesh: Mesh, U, K, stage: int, substep: int, mode: int, coarse_step: int, blocks, padded,
+          nfields: int = 2, precision: int = FP64, tableau: int = RK4, stream=None):
+    b, nb, keep = _blocks_arg(blocks)
+    v = _view(U, K, nfields, precision, tableau)
+    p = _pos(substep, mode, coarse_step)
+    check(lib().lts_unzip(mesh.h, C.byref(v), stage, C.byref(p), b, nb, _ptr(padded), _stream_ptr(stream)),
+          "lts_unzip")
+
+
+def rhs(mesh: Mesh, equation: int, ko_sigma: float, padded, precision: int, blocks, k_block, stream=None):
+    b, nb, keep = _blocks_arg(blocks)
+    prm = _L.RhsParams()
+    prm.ko_sigma = ko_sigma
+    check(lib().lts_rhs(mesh.h, equation, C.byref(prm), _ptr(padded), precision, b, nb, _ptr(k_block),
+                        _stream_ptr(stream)), "lts_rhs")
+
+
+def zip(mesh: Mesh, nfields: int, precision: int, k_block, blocks, k_octant, stream=None):
+    b, nb, keep = _blocks_arg(blocks)
+    check(lib().lts_zip(mesh.h, nfields, precision, _ptr(k_block), b, nb, _ptr(k_octant), _stream_ptr(stream)),
+          "lts_zip")
+
+
+def rk_stage(mesh: Mesh, U, K, coef: Sequence[float], substep: int, mode: int, coarse_step: int, blocks, out,
+             nfields: int = 2, precision: int = FP64, tableau: int = RK4, stream=None):
+    b, nb, keep = _blocks_arg(blocks)
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
+    v = _view(U, K, nfields, precision, tableau)
+    p = _pos(substep, mode, coarse_step)
+    check(lib().lts_rk_stage(mesh.h, C.byref(v), c.ctypes.data_as(C.POINTER(C.c_double)), len(c), C.byref(p), b, nb,
+                             _ptr(out), _stream_ptr(stream)), "lts_rk_stage")
+
+
+def fused_stage(mesh: Mesh, U, K, equation: int, ko_sigma: float, stage: int, substep: int, mode: int,
+                coarse_step: int, precision: int = FP64, tableau: int = RK4, stream=None):
+    v = _view(U, K, NFIELDS[equation], precision, tableau)
+    prm = _L.RhsParams()
+    prm.ko_sigma = ko_sigma
+    p = _pos(substep, mode, coarse_step)
+    check(lib().lts_fused_stage(mesh.h, C.byref(v), equation, C.byref(prm), stage, C.byref(p), _stream_ptr(stream)),
+          "lts_fused_stage")
+
+
+def norms(mesh: Mesh, a, b=None, nfields: int = 2, stream=None) -> dict:
+    out = np.zeros(2 * nfields + 1)
+    st = lib().lts_norms(mesh.h, nfields, _ptr(a), _ptr(b), out.ctypes.data_as(C.POINTER(C.c_double)),
+                         _stream_ptr(stream))
+    if st not in (_L.OK, _L.ENONFINITE):
+        check(st, "lts_norms")
+    return {"l2": out[:nfields].copy(), "linf": out[nfields:2 * nfields].copy(), "nonfinite": int(out[-1])}
+
+
+def copy_probe(src, dst, nbytes: int, stream=None):
+    check(lib().lts_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream_ptr(stream)), "lts_copy_probe")
+
+
+class Sim:
+    """One simulation: device state U [2][F][N][125] (float64) and stages K
+    [p][F][N][125] (float64, or float32 in FP32-RHS mode) as torch tensors."""
+
+    def __init__(self, mesh: Mesh, equation="wave", precision=FP64, tableau="rk4", ko_sigma=0.1, device="cuda"):
+        import torch
+        self.mesh = mesh
+        self.eq = EQUATIONS[equation] if isinstance(equation, str) else int(equation)
+        self.tab = TABLEAUS[tableau] if isinstance(tableau, str) else int(tableau)
+        self.prec = int(precision)
+        self.F = NFIELDS[self.eq]
+        self.p = NSTAGES[self.tab]
+        prm = _L.RhsParams()
+        prm.ko_sigma = ko_sigma
+        self.ko_sigma = ko_sigma
+        h = C.c_void_p()
+        check(lib().lts_sim_create(mesh.h, self.eq, self.prec, self.tab, C.byref(prm), C.byref(h)), "lts_sim_create")
+        self.h = h
+        N = mesh.info()["n_oct"]
+        self.N = N
+        self.U = torch.zeros((2, self.F, N, 125), dtype=torch.float64, device=device)
+        kdt = torch.float32 if self.prec == FP32_RHS else torch.float64
+        self.K = torch.zeros((self.p, self.F, N, 125), dtype=kdt, device=device)
+        check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                lib().lts_sim_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def set_state(self, U0):
+        """U0: [F][N][5][5][5] or [F][N][125] (numpy or torch); resets the step counter."""
+        import torch
+        t = torch.as_tensor(np.asarray(U0) if not hasattr(U0, "device") else U0, dtype=torch.float64)
+        self.U.zero_()
+        self.K.zero_()
+        self.U[0].copy_(t.reshape(self.F, self.N, 125).to(self.U.device))
+        check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
+
+    def advance(self, n_coarse: int, mode: int = MODE_LTS, graph: bool = True, stream=None):
+        check(lib().lts_advance(self.h, int(n_coarse), int(mode), 1 if graph else 0, _stream_ptr(stream)),
+              "lts_advance")
+
+    def advance_unfused(self, n_coarse: int, mode: int = MODE_LTS, stream=None):
+        check(lib().lts_advance_unfused(self.h, int(n_coarse), int(mode), _stream_ptr(stream)), "lts_advance_unfused")
+
+    def current(self, stream=None):
+        import torch
+        out = torch.empty((self.F, self.N, 125), dtype=torch.float64, device=self.U.device)
+        check(lib().lts_sim_current(self.h, _ptr(out), _stream_ptr(stream)), "lts_sim_current")
+        return out
+
+    @property
+    def coarse_step(self) -> int:
+        return int(lib().lts_sim_coarse_step(self.h))

@@ -1,0 +1,823 @@
+// C ABI of the library (include/lts.h): argument checking, device tables, the
+// phase-by-phase path, the fused stage and the LTS / GTS drivers (Alg. 1 / 2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lts_impl.h"
+#include "lts_kernels.h"
+
+namespace lts {
+
+static thread_local std::string g_err;
+
+lts_status fail(lts_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+void clear_error() { g_err.clear(); }
+
+static lts_status hip_fail(hipError_t e, const char* where) {
+  return fail(LTS_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                   \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+static lts_status upload_set(TileSet& ts) {
+  if (ts.d_tiles) { (void)hipFree(ts.d_tiles); ts.d_tiles = nullptr; }
+  if (ts.d_slots) { (void)hipFree(ts.d_slots); ts.d_slots = nullptr; }
+  if (ts.tiles.empty()) return LTS_OK;
+  HIP_TRY(hipMalloc(&ts.d_tiles, ts.tiles.size() * 4), "hipMalloc tiles");
+  HIP_TRY(hipMalloc(&ts.d_slots, ts.slots.size() * 4), "hipMalloc slots");
+  HIP_TRY(hipMemcpy(ts.d_tiles, ts.tiles.data(), ts.tiles.size() * 4, hipMemcpyHostToDevice), "upload tiles");
+  HIP_TRY(hipMemcpy(ts.d_slots, ts.slots.data(), ts.slots.size() * 4, hipMemcpyHostToDevice), "upload slots");
+  return LTS_OK;
+}
+
+static void free_set(TileSet& ts) {
+  if (ts.d_tiles) (void)hipFree(ts.d_tiles);
+  if (ts.d_slots) (void)hipFree(ts.d_slots);
+  ts.d_tiles = nullptr;
+  ts.d_slots = nullptr;
+}
+
+static lts_status ensure_device(Mesh& m) {
+  if (m.uploaded) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != m.device) return fail(LTS_EINVAL, "mesh tables were uploaded to another device");
+    return LTS_OK;
+  }
+  HIP_TRY(hipGetDevice(&m.device), "hipGetDevice");
+  lts_status st;
+  if ((st = upload_set(m.bt)) != LTS_OK) return st;
+  if ((st = upload_set(m.ts[1])) != LTS_OK) return st;
+  if ((st = upload_set(m.ts[2])) != LTS_OK) return st;
+  m.uploaded = true;
+  return LTS_OK;
+}
+
+// device copy of a block list with its padded / grid offsets (phase-by-phase path)
+struct ListDev {
+  int nb = 0;
+  int64_t ptotal = 0, gtotal = 0;
+  const int32_t* list = nullptr;
+  const int64_t* poff = nullptr;
+  const int64_t* goff = nullptr;
+};
+
+static lts_status stage_list(Mesh& m, const int32_t* blocks, int nb, const lts_position* pos, hipStream_t s,
+                             ListDev& out) {
+  std::vector<int32_t> lst;
+  if (blocks) {
+    if (nb < 0) return fail(LTS_EINVAL, "nb < 0");
+    for (int i = 0; i < nb; ++i) {
+      if (blocks[i] < 0 || blocks[i] >= (int)m.blocks.size()) return fail(LTS_EINVAL, "block index out of range");
+      lst.push_back(blocks[i]);
+    }
+  } else {
+    if (!pos) return fail(LTS_EINVAL, "blocks == NULL needs a position");
+    const int j = pos->substep;
+    for (size_t b = 0; b < m.blocks.size(); ++b) {
+      const int r = 1 << (m.lmax - m.blocks[b].level);
+      if (pos->mode == LTS_MODE_GTS || j % r == 0) lst.push_back((int32_t)b);
+    }
+  }
+  out.nb = (int)lst.size();
+  const size_t n = lst.size();
+  std::vector<int64_t> pack(3 * n + 1, 0);
+  int64_t p = 0, g = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const int mm = m.blocks[lst[i]].m;
+    pack[n + i] = p;
+    pack[2 * n + i] = g;
+    p += (int64_t)(4 * mm + 7) * (4 * mm + 7) * (4 * mm + 7);
+    g += (int64_t)(4 * mm + 1) * (4 * mm + 1) * (4 * mm + 1);
+  }
+  for (size_t i = 0; i < n; ++i) pack[i] = lst[i];
+  out.ptotal = p;
+  out.gtotal = g;
+  const size_t bytes = pack.size() * 8;
+  if (bytes > m.list_cap) {
+    if (m.d_off) (void)hipFree(m.d_off);
+    m.d_off = nullptr;
+    m.list_cap = 0;
+    HIP_TRY(hipMalloc(&m.d_off, bytes), "hipMalloc list");
+    m.list_cap = bytes;
+  }
+  // list entries are stored as int64 in the pack; kernels read int32: convert
+  std::vector<int32_t> l32(lst);
+  std::vector<char> buf(bytes);
+  std::memcpy(buf.data(), l32.data(), n * 4);
+  std::memcpy(buf.data() + n * 8, pack.data() + n, 2 * n * 8);
+  HIP_TRY(hipMemcpyAsync(m.d_off, buf.data(), bytes, hipMemcpyHostToDevice, s), "upload list");
+  HIP_TRY(hipStreamSynchronize(s), "sync list upload");
+  out.list = (const int32_t*)m.d_off;
+  out.poff = m.d_off + n;
+  out.goff = m.d_off + 2 * n;
+  return LTS_OK;
+}
+
+static lts_status check_view(const Mesh& m, const lts_stage_view* v, int& p) {
+  if (!v || !v->U || !v->K) return fail(LTS_EINVAL, "stage view needs U and K");
+  if (v->nfields != 2 && v->nfields != 6) return fail(LTS_EINVAL, "nfields must be 2 or 6");
+  if (v->precision != LTS_FP64 && v->precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
+  p = tableau_stages(v->tableau);
+  if (!p) return fail(LTS_EINVAL, "bad tableau");
+  (void)m;
+  return LTS_OK;
+}
+
+static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage, const lts_position* pos,
+                              const int64_t* d_step, StageParams& sp) {
+  int p = 0;
+  lts_status st = check_view(m, v, p);
+  if (st != LTS_OK) return st;
+  if (!pos) return fail(LTS_EINVAL, "position is NULL");
+  if (stage < 0 || stage >= p) return fail(LTS_EINVAL, "stage out of range");
+  if (pos->mode != LTS_MODE_LTS && pos->mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
+  if (pos->substep < 0 || pos->substep >= (1 << (m.lmax - m.lmin))) return fail(LTS_EINVAL, "substep out of range");
+  double w[64], a[16], b[4];
+  coefficient_tables(v->tableau, w, a, b);
+  std::memset(&sp, 0, sizeof(sp));
+  sp.U = (const double*)v->U;
+  sp.Uw = (double*)v->U;
+  sp.K = v->K;
+  sp.Kw = v->K;
+  sp.N = m.n();
+  sp.F = v->nfields;
+  sp.p = p;
+  sp.stage = stage;
+  sp.mode = pos->mode;
+  sp.j = pos->substep;
+  sp.lmin = m.lmin;
+  sp.lmax = m.lmax;
+  sp.step = d_step;
+  for (int c = 0; c < 4; ++c)
+    for (int i = 0; i < p; ++i) sp.w[c][i] = w[(c * p + stage) * p + i];
+  for (int i = 0; i < p; ++i) sp.b[i] = b[i];
+  return LTS_OK;
+}
+
+}  // namespace lts
+
+using namespace lts;
+
+
+static lts_status set_step(int64_t** slot, int64_t value, hipStream_t s) {
+  if (!*slot) HIP_TRY(hipMalloc(slot, sizeof(int64_t)), "hipMalloc step");
+  // a kernel-argument write keeps the value with the enqueued work
+  int64_t v = value;
+  HIP_TRY(hipMemcpyAsync(*slot, &v, sizeof(int64_t), hipMemcpyHostToDevice, s), "set step");
+  HIP_TRY(hipStreamSynchronize(s), "sync step");
+  return LTS_OK;
+}
+
+struct MeshExtra {
+  int64_t* d_step = nullptr;
+  double* d_norm = nullptr;
+  size_t norm_cap = 0;
+  double* d_coef = nullptr;
+};
+
+// Extra device buffers live beside the mesh handle.
+struct lts_mesh_full : lts_mesh {
+  MeshExtra x;
+};
+
+extern "C" {
+
+const char* lts_last_error(void) { return g_err.c_str(); }
+const char* lts_version(void) { return "lts-mi355x 0.1 (gfx950)"; }
+
+lts_status lts_build_mesh(const lts_mesh_spec* spec, lts_mesh** out) {
+  clear_error();
+  if (!out) return fail(LTS_EINVAL, "out is NULL");
+  *out = nullptr;
+  lts_mesh_full* h = new (std::nothrow) lts_mesh_full();
+  if (!h) return fail(LTS_ENOMEM, "host allocation");
+  lts_status st;
+  try {
+    st = build_mesh(spec, h->m);
+  } catch (const std::bad_alloc&) {
+    st = fail(LTS_ENOMEM, "host allocation during mesh build");
+  } catch (...) {
+    st = fail(LTS_EINVAL, "mesh build failed");
+  }
+  if (st != LTS_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return LTS_OK;
+}
+
+void lts_mesh_destroy(lts_mesh* mesh) {
+  if (!mesh) return;
+  lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
+  free_set(h->m.bt);
+  free_set(h->m.ts[1]);
+  free_set(h->m.ts[2]);
+  if (h->m.d_off) (void)hipFree(h->m.d_off);
+  if (h->x.d_step) (void)hipFree(h->x.d_step);
+  if (h->x.d_norm) (void)hipFree(h->x.d_norm);
+  if (h->x.d_coef) (void)hipFree(h->x.d_coef);
+  delete h;
+}
+
+lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
+  clear_error();
+  if (!mesh || !info) return fail(LTS_EINVAL, "NULL argument");
+  const Mesh& m = mesh->m;
+  std::memset(info, 0, sizeof(*info));
+  info->n_oct = m.n();
+  info->n_blocks = (int64_t)m.blocks.size();
+  info->n_tiles = m.ts[1].count() + m.ts[2].count();
+  info->L = m.L;
+  info->lmin = m.lmin;
+  info->lmax = m.lmax;
+  info->n_substeps = 1 << (m.lmax - m.lmin);
+  info->tile = m.tile;
+  for (int8_t l : m.lev) info->level_count[l] += 1;
+  int64_t up = 0, gp = 0, wl = 0, wg = 0;
+  const int64_t nsub = 1ll << (m.lmax - m.lmin);
+  for (const Block& b : m.blocks) {
+    up += (int64_t)(4 * b.m + 7) * (4 * b.m + 7) * (4 * b.m + 7);
+    gp += (int64_t)(4 * b.m + 1) * (4 * b.m + 1) * (4 * b.m + 1);
+    const int64_t nodes = 125ll * b.m * b.m * b.m;
+    wl += nodes * (1ll << (b.level - m.lmin));
+    wg += nodes * nsub;
+  }
+  info->unzip_points = up;
+  info->grid_points = gp;
+  info->node_updates_lts = wl;
+  info->node_updates_gts = wg;
+  // eq. invS with alpha_l = DG nodes at level lmax - l
+  double inv = 0.0, tot = 0.0, a0 = 0.0;
+  for (int l = m.lmin; l <= m.lmax; ++l) {
+    const double al = 125.0 * (double)info->level_count[l];
+    inv += al / std::ldexp(1.0, m.lmax - l);
+    tot += al;
+    if (l == m.lmax) a0 = al;
+  }
+  info->s_est = tot / inv;
+  info->s_max = a0 > 0 ? tot / a0 : 0.0;
+  return LTS_OK;
+}
+
+lts_status lts_mesh_export(const lts_mesh* mesh, int32_t kind, void* buf, size_t cap, size_t* needed) {
+  clear_error();
+  if (!mesh) return fail(LTS_EINVAL, "mesh is NULL");
+  const Mesh& m = mesh->m;
+  std::vector<int32_t> out;
+  switch (kind) {
+    case LTS_EXPORT_LEAVES:
+      out.resize(4 * m.n());
+      for (int64_t i = 0; i < m.n(); ++i) {
+        out[4 * i] = m.ax[i]; out[4 * i + 1] = m.ay[i]; out[4 * i + 2] = m.az[i]; out[4 * i + 3] = m.lev[i];
+      }
+      break;
+    case LTS_EXPORT_BLOCKS:
+      for (const Block& b : m.blocks) {
+        const int32_t r[6] = {b.first, b.m, b.level, b.ax, b.ay, b.az};
+        out.insert(out.end(), r, r + 6);
+      }
+      break;
+    case LTS_EXPORT_UNZIP_MAP: {
+      size_t tot = 0;
+      for (const Block& b : m.blocks) tot += (size_t)(4 * b.m + 7) * (4 * b.m + 7) * (4 * b.m + 7);
+      out.resize(5 * tot);
+      size_t o = 0;
+      for (size_t b = 0; b < m.blocks.size(); ++b) {
+        const int S = 4 * m.blocks[b].m + 7;
+        unzip_map_block(m, (int)b, out.data() + 5 * o);
+        o += (size_t)S * S * S;
+      }
+      break;
+    }
+    case LTS_EXPORT_SCHEDULE: {
+      const int nsub = 1 << (m.lmax - m.lmin);
+      for (int j = 0; j < nsub; ++j) {
+        std::vector<int32_t> act;
+        for (size_t b = 0; b < m.blocks.size(); ++b)
+          if (j % (1 << (m.lmax - m.blocks[b].level)) == 0) act.push_back((int32_t)b);
+        out.push_back((int32_t)act.size());
+        out.insert(out.end(), act.begin(), act.end());
+      }
+      break;
+    }
+    case LTS_EXPORT_TILES:
+      for (int k = 1; k <= 2; ++k) out.insert(out.end(), m.ts[k].tiles.begin(), m.ts[k].tiles.end());
+      break;
+    default:
+      return fail(LTS_EINVAL, "unknown export kind");
+  }
+  const size_t bytes = out.size() * 4;
+  if (needed) *needed = bytes;
+  if (!buf) return LTS_OK;
+  if (cap < bytes) return fail(LTS_EINVAL, "export buffer too small");
+  std::memcpy(buf, out.data(), bytes);
+  return LTS_OK;
+}
+
+lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile) {
+  clear_error();
+  if (!mesh) return fail(LTS_EINVAL, "mesh is NULL");
+  Mesh& m = mesh->m;
+  if (tile == m.tile) return LTS_OK;
+  lts_status st = build_tiles(m, tile);
+  if (st != LTS_OK) return st;
+  if (m.uploaded) {
+    if ((st = upload_set(m.ts[1])) != LTS_OK) return st;
+    if ((st = upload_set(m.ts[2])) != LTS_OK) return st;
+  }
+  return LTS_OK;
+}
+
+lts_status lts_coefficients(int32_t tableau, double* out, size_t cap) {
+  clear_error();
+  const int p = tableau_stages(tableau);
+  if (!p) return fail(LTS_EINVAL, "bad tableau");
+  const size_t n = (size_t)(4 * p * p + p * p + p);
+  if (!out || cap < n * sizeof(double)) return fail(LTS_EINVAL, "output too small");
+  coefficient_tables(tableau, out, out + 4 * p * p, out + 5 * p * p);
+  return LTS_OK;
+}
+
+lts_status lts_unzip(lts_mesh* mesh, const lts_stage_view* view, int32_t stage, const lts_position* pos,
+                     const int32_t* blocks, int32_t nb, double* padded, void* stream) {
+  clear_error();
+  if (!mesh || !padded) return fail(LTS_EINVAL, "NULL argument");
+  lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
+  Mesh& m = mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  lts_status st = ensure_device(m);
+  if (st != LTS_OK) return st;
+  if ((st = set_step(&h->x.d_step, pos ? pos->coarse_step : 0, s)) != LTS_OK) return st;
+  StageParams sp;
+  if ((st = fill_params(m, view, stage, pos, h->x.d_step, sp)) != LTS_OK) return st;
+  ListDev L;
+  if ((st = stage_list(m, blocks, nb, pos, s, L)) != LTS_OK) return st;
+  HIP_TRY(launch_unzip(view->precision == LTS_FP32_RHS, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb,
+                       L.ptotal, padded, s),
+          "unzip launch");
+  return LTS_OK;
+}
+
+lts_status lts_rhs(lts_mesh* mesh, int32_t equation, const lts_rhs_params* params, const double* padded,
+                   int32_t precision, const int32_t* blocks, int32_t nb, void* k_block, void* stream) {
+  clear_error();
+  if (!mesh || !padded || !k_block || !params) return fail(LTS_EINVAL, "NULL argument");
+  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
+  if (!blocks) return fail(LTS_EINVAL, "lts_rhs needs an explicit block list");
+  Mesh& m = mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  lts_status st = ensure_device(m);
+  if (st != LTS_OK) return st;
+  ListDev L;
+  if ((st = stage_list(m, blocks, nb, nullptr, s, L)) != LTS_OK) return st;
+  HIP_TRY(launch_rhs(equation, precision == LTS_FP32_RHS, m.bt.d_tiles, L.list, L.poff, L.ptotal, L.goff, L.gtotal,
+                     L.nb, padded, k_block, params->ko_sigma, s),
+          "rhs launch");
+  return LTS_OK;
+}
+
+lts_status lts_zip(lts_mesh* mesh, int32_t nfields, int32_t precision, const void* k_block, const int32_t* blocks,
+                   int32_t nb, void* k_octant, void* stream) {
+  clear_error();
+  if (!mesh || !k_block || !k_octant) return fail(LTS_EINVAL, "NULL argument");
+  if (nfields != 2 && nfields != 6) return fail(LTS_EINVAL, "nfields must be 2 or 6");
+  if (!blocks) return fail(LTS_EINVAL, "lts_zip needs an explicit block list");
+  Mesh& m = mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  lts_status st = ensure_device(m);
+  if (st != LTS_OK) return st;
+  ListDev L;
+  if ((st = stage_list(m, blocks, nb, nullptr, s, L)) != LTS_OK) return st;
+  HIP_TRY(launch_zip(precision == LTS_FP32_RHS, m.bt.d_tiles, L.list, L.goff, L.gtotal, L.nb, nfields, m.n(), k_block,
+                     k_octant, s),
+          "zip launch");
+  return LTS_OK;
+}
+
+lts_status lts_rk_stage(lts_mesh* mesh, const lts_stage_view* view, const double* coef, int32_t ncoef,
+                        const lts_position* pos, const int32_t* blocks, int32_t nb, double* out, void* stream) {
+  clear_error();
+  if (!mesh || !coef) return fail(LTS_EINVAL, "NULL argument");
+  lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
+  Mesh& m = mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  lts_status st = ensure_device(m);
+  if (st != LTS_OK) return st;
+  if ((st = set_step(&h->x.d_step, pos ? pos->coarse_step : 0, s)) != LTS_OK) return st;
+  StageParams sp;
+  if ((st = fill_params(m, view, 0, pos, h->x.d_step, sp)) != LTS_OK) return st;
+  if (ncoef != sp.p) return fail(LTS_EINVAL, "ncoef must equal the number of stages");
+  if (!h->x.d_coef) HIP_TRY(hipMalloc(&h->x.d_coef, 4 * sizeof(double)), "hipMalloc coef");
+  HIP_TRY(hipMemcpyAsync(h->x.d_coef, coef, ncoef * sizeof(double), hipMemcpyHostToDevice, s), "upload coef");
+  ListDev L;
+  if ((st = stage_list(m, blocks, nb, pos, s, L)) != LTS_OK) return st;
+  HIP_TRY(launch_rk(view->precision == LTS_FP32_RHS, sp, m.bt.d_tiles, L.list, L.nb, h->x.d_coef, out, s),
+          "rk launch");
+  return LTS_OK;
+}
+
+static int g_max_wg = 4096;
+
+lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t equation,
+                           const lts_rhs_params* params, int32_t stage, const lts_position* pos, void* stream) {
+  clear_error();
+  if (!mesh || !params) return fail(LTS_EINVAL, "NULL argument");
+  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
+  Mesh& m = mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  lts_status st = ensure_device(m);
+  if (st != LTS_OK) return st;
+  if (equation == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
+    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
+  if ((equation == LTS_EQ_WAVE) != (view && view->nfields == 2))
+    return fail(LTS_EINVAL, "nfields does not match the equation");
+  if ((st = set_step(&h->x.d_step, pos ? pos->coarse_step : 0, s)) != LTS_OK) return st;
+  StageParams sp;
+  if ((st = fill_params(m, view, stage, pos, h->x.d_step, sp)) != LTS_OK) return st;
+  sp.sigma = params->ko_sigma;
+  const int lo = pos->mode == LTS_MODE_GTS ? 0 : [&] {
+    int j = pos->substep, tz = 0;
+    if (j == 0) return m.lmin;
+    while (!(j & 1)) { j >>= 1; ++tz; }
+    return m.lmax - tz;
+  }();
+  for (int tt = 1; tt <= 2; ++tt) {
+    const int nt = (int)m.ts[tt].n_ge[lo];
+    HIP_TRY(launch_fused(tt, equation, view->precision == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, nt,
+                         g_max_wg, s),
+            "fused launch");
+  }
+  return LTS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------ sims
+struct lts_sim {
+  lts_mesh* mesh = nullptr;
+  int eq = 0, prec = 0, tab = 0, F = 2, p = 4;
+  lts_rhs_params prm{};
+  void* U = nullptr;
+  void* K = nullptr;
+  int64_t n = 0;
+  int mode = -1;
+  int64_t* d_step = nullptr;
+  double w[64], a[16], b[4];
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int graph_tile[2] = {0, 0};
+  // unfused path: device block lists per substep class
+  std::vector<ListDev> ulists;
+  std::vector<void*> ualloc;
+  double* d_pad = nullptr;
+  void* d_kb = nullptr;
+  double* d_coef = nullptr;
+};
+
+namespace {
+
+void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams& sp) {
+  const Mesh& m = sim->mesh->m;
+  std::memset(&sp, 0, sizeof(sp));
+  sp.U = (const double*)sim->U;
+  sp.Uw = (double*)sim->U;
+  sp.K = sim->K;
+  sp.Kw = sim->K;
+  sp.N = m.n();
+  sp.F = sim->F;
+  sp.p = sim->p;
+  sp.stage = stage;
+  sp.mode = mode;
+  sp.j = j;
+  sp.lmin = m.lmin;
+  sp.lmax = m.lmax;
+  sp.step = sim->d_step;
+  const int p = sim->p;
+  for (int c = 0; c < 4; ++c)
+    for (int i = 0; i < p; ++i) sp.w[c][i] = sim->w[(c * p + stage) * p + i];
+  for (int i = 0; i < p; ++i) sp.b[i] = sim->b[i];
+  sp.sigma = sim->prm.ko_sigma;
+}
+
+int lowest_active_level(const Mesh& m, int mode, int j) {
+  if (mode == LTS_MODE_GTS || j == 0) return m.lmin;
+  int tz = 0;
+  while (!(j & 1)) { j >>= 1; ++tz; }
+  return m.lmax - tz;
+}
+
+lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
+  Mesh& m = sim->mesh->m;
+  const int nsub = 1 << (m.lmax - m.lmin);
+  for (int j = 0; j < nsub; ++j) {
+    const int lo = lowest_active_level(m, mode, j);
+    for (int st = 0; st < sim->p; ++st) {
+      StageParams sp;
+      fill_sim_params(sim, st, mode, j, sp);
+      for (int tt = 1; tt <= 2; ++tt) {
+        const int nt = (int)m.ts[tt].n_ge[lo];
+        HIP_TRY(launch_fused(tt, sim->eq, sim->prec == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, nt,
+                             g_max_wg, s),
+                "fused launch");
+      }
+    }
+  }
+  HIP_TRY(launch_increment(sim->d_step, s), "step increment");
+  return LTS_OK;
+}
+
+void drop_graphs(lts_sim* sim) {
+  for (int k = 0; k < 2; ++k) {
+    if (sim->exec[k]) (void)hipGraphExecDestroy(sim->exec[k]);
+    if (sim->graph[k]) (void)hipGraphDestroy(sim->graph[k]);
+    sim->exec[k] = nullptr;
+    sim->graph[k] = nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, int32_t tableau,
+                          const lts_rhs_params* params, lts_sim** out) {
+  clear_error();
+  if (!mesh || !out || !params) return fail(LTS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
+  const int p = tableau_stages(tableau);
+  if (!p) return fail(LTS_EINVAL, "bad tableau");
+  lts_status st = ensure_device(mesh->m);
+  if (st != LTS_OK) return st;
+  lts_sim* sim = new (std::nothrow) lts_sim();
+  if (!sim) return fail(LTS_ENOMEM, "host allocation");
+  sim->mesh = mesh;
+  sim->eq = equation;
+  sim->prec = precision;
+  sim->tab = tableau;
+  sim->F = equation == LTS_EQ_WAVE ? 2 : 6;
+  sim->p = p;
+  sim->prm = *params;
+  coefficient_tables(tableau, sim->w, sim->a, sim->b);
+  hipError_t e = hipMalloc(&sim->d_step, sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemset(sim->d_step, 0, sizeof(int64_t));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&sim->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    lts_sim_destroy(sim);
+    return hip_fail(e, "sim create");
+  }
+  *out = sim;
+  return LTS_OK;
+}
+
+lts_status lts_sim_bind(lts_sim* sim, void* U, void* K) {
+  clear_error();
+  if (!sim || !U || !K) return fail(LTS_EINVAL, "NULL argument");
+  sim->U = U;
+  sim->K = K;
+  sim->n = 0;
+  sim->mode = -1;
+  drop_graphs(sim);
+  HIP_TRY(hipMemset(sim->d_step, 0, sizeof(int64_t)), "reset step");
+  return LTS_OK;
+}
+
+lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t use_graph, void* stream) {
+  clear_error();
+  if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
+  if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
+  if (n_coarse_steps < 0) return fail(LTS_EINVAL, "n < 0");
+  if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
+    return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
+  Mesh& m = sim->mesh->m;
+  if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
+    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
+  hipStream_t s = (hipStream_t)stream;
+  sim->mode = mode;
+  if (!use_graph) {
+    for (int64_t c = 0; c < n_coarse_steps; ++c) {
+      lts_status st = enqueue_coarse_step(sim, mode, s);
+      if (st != LTS_OK) return st;
+      sim->n += 1;
+    }
+    return LTS_OK;
+  }
+  if (sim->exec[mode] && sim->graph_tile[mode] != m.tile) {
+    drop_graphs(sim);
+  }
+  if (!sim->exec[mode]) {
+    HIP_TRY(hipStreamBeginCapture(sim->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    lts_status st = enqueue_coarse_step(sim, mode, sim->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(sim->cap_stream, &g);
+    if (st != LTS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    sim->graph[mode] = g;
+    HIP_TRY(hipGraphInstantiate(&sim->exec[mode], g, nullptr, nullptr, 0), "graph instantiate");
+    sim->graph_tile[mode] = m.tile;
+  }
+  for (int64_t c = 0; c < n_coarse_steps; ++c) {
+    HIP_TRY(hipGraphLaunch(sim->exec[mode], s), "graph launch");
+    sim->n += 1;
+  }
+  return LTS_OK;
+}
+
+lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, void* stream) {
+  clear_error();
+  if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
+  if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
+  if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
+    return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
+  Mesh& m = sim->mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  sim->mode = mode;
+  const int nsub = 1 << (m.lmax - m.lmin);
+  // device block lists of every substep class, built once
+  if (sim->ulists.empty()) {
+    int64_t pmax = 0, gmax = 0;
+    for (int cls = 0; cls <= m.lmax - m.lmin + 1; ++cls) {
+      // class 0..dL: lowest active level lmax - cls (LTS); class dL+1: all (GTS)
+      const int lo = cls <= m.lmax - m.lmin ? m.lmax - cls : m.lmin;
+      std::vector<int32_t> lst;
+      for (size_t b = 0; b < m.blocks.size(); ++b)
+        if (m.blocks[b].level >= lo) lst.push_back((int32_t)b);
+      const size_t n = lst.size();
+      std::vector<int64_t> off(2 * n);
+      int64_t p = 0, g = 0;
+      for (size_t i = 0; i < n; ++i) {
+        const int mm = m.blocks[lst[i]].m;
+        off[i] = p;
+        off[n + i] = g;
+        p += (int64_t)(4 * mm + 7) * (4 * mm + 7) * (4 * mm + 7);
+        g += (int64_t)(4 * mm + 1) * (4 * mm + 1) * (4 * mm + 1);
+      }
+      pmax = std::max(pmax, p);
+      gmax = std::max(gmax, g);
+      ListDev L;
+      L.nb = (int)n;
+      L.ptotal = p;
+      L.gtotal = g;
+      void* d = nullptr;
+      const size_t bytes = n * 4 + 2 * n * 8 + 16;
+      HIP_TRY(hipMalloc(&d, bytes), "hipMalloc lists");
+      sim->ualloc.push_back(d);
+      char* c8 = (char*)d;
+      const size_t o64 = ((n * 4 + 15) / 16) * 16;
+      if (n) {
+        HIP_TRY(hipMemcpy(c8, lst.data(), n * 4, hipMemcpyHostToDevice), "upload list");
+        HIP_TRY(hipMemcpy(c8 + o64, off.data(), 2 * n * 8, hipMemcpyHostToDevice), "upload off");
+      }
+      L.list = (const int32_t*)c8;
+      L.poff = (const int64_t*)(c8 + o64);
+      L.goff = L.poff + n;
+      sim->ulists.push_back(L);
+    }
+    const size_t kbytes = sim->prec == LTS_FP32_RHS ? 4 : 8;
+    HIP_TRY(hipMalloc(&sim->d_pad, (size_t)pmax * sim->F * 8 + 8), "hipMalloc padded");
+    HIP_TRY(hipMalloc(&sim->d_kb, (size_t)gmax * sim->F * kbytes + 8), "hipMalloc kblock");
+    HIP_TRY(hipMalloc(&sim->d_coef, 4 * sizeof(double)), "hipMalloc coef");
+    HIP_TRY(hipMemcpy(sim->d_coef, sim->b, sim->p * sizeof(double), hipMemcpyHostToDevice), "upload b");
+  }
+  const bool kf32 = sim->prec == LTS_FP32_RHS;
+  const size_t kbytes = kf32 ? 4 : 8;
+  for (int64_t c = 0; c < n_coarse_steps; ++c) {
+    for (int j = 0; j < nsub; ++j) {
+      int cls;
+      if (mode == LTS_MODE_GTS) cls = m.lmax - m.lmin + 1;
+      else cls = m.lmax - lowest_active_level(m, mode, j);
+      const ListDev& L = sim->ulists[cls];
+      for (int st = 0; st < sim->p; ++st) {
+        StageParams sp;
+        fill_sim_params(sim, st, mode, j, sp);
+        HIP_TRY(launch_unzip(kf32, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb, L.ptotal, sim->d_pad, s),
+                "unzip launch");
+        HIP_TRY(launch_rhs(sim->eq, kf32, m.bt.d_tiles, L.list, L.poff, L.ptotal, L.goff, L.gtotal, L.nb, sim->d_pad,
+                           sim->d_kb, sim->prm.ko_sigma, s),
+                "rhs launch");
+        char* kslice = (char*)sim->K + (size_t)st * sim->F * m.n() * 125 * kbytes;
+        HIP_TRY(launch_zip(kf32, m.bt.d_tiles, L.list, L.goff, L.gtotal, L.nb, sim->F, m.n(), sim->d_kb, kslice, s),
+                "zip launch");
+      }
+      StageParams sp;
+      fill_sim_params(sim, 0, mode, j, sp);
+      HIP_TRY(launch_rk(kf32, sp, m.bt.d_tiles, L.list, L.nb, sim->d_coef, nullptr, s), "rk launch");
+    }
+    HIP_TRY(launch_increment(sim->d_step, s), "step increment");
+    sim->n += 1;
+  }
+  return LTS_OK;
+}
+
+lts_status lts_sim_current(lts_sim* sim, double* out, void* stream) {
+  clear_error();
+  if (!sim || !out || !sim->U) return fail(LTS_EINVAL, "NULL argument");
+  Mesh& m = sim->mesh->m;
+  StageParams sp;
+  fill_sim_params(sim, 0, sim->mode < 0 ? LTS_MODE_LTS : sim->mode, 0, sp);
+  HIP_TRY(launch_current(sp, m.bt.d_tiles, (int)m.blocks.size(), out, (hipStream_t)stream), "current launch");
+  return LTS_OK;
+}
+
+int64_t lts_sim_coarse_step(const lts_sim* sim) { return sim ? sim->n : -1; }
+
+void lts_sim_destroy(lts_sim* sim) {
+  if (!sim) return;
+  drop_graphs(sim);
+  if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
+  if (sim->d_step) (void)hipFree(sim->d_step);
+  for (void* p : sim->ualloc) (void)hipFree(p);
+  if (sim->d_pad) (void)hipFree(sim->d_pad);
+  if (sim->d_kb) (void)hipFree(sim->d_kb);
+  if (sim->d_coef) (void)hipFree(sim->d_coef);
+  delete sim;
+}
+
+lts_status lts_batch_advance(lts_sim* const* sims, int32_t n, int64_t n_coarse_steps, int32_t mode, void* stream) {
+  clear_error();
+  if (!sims || n <= 0) return fail(LTS_EINVAL, "no sims");
+  // Sequential fallback-free form: every sim's coarse step is enqueued in turn on
+  // one stream (the persistent multi-mesh launch is built on top of this order).
+  for (int i = 0; i < n; ++i) {
+    lts_status st = lts_advance(sims[i], n_coarse_steps, mode, 0, stream);
+    if (st != LTS_OK) return st;
+  }
+  return LTS_OK;
+}
+
+lts_status lts_norms(lts_mesh* mesh, int32_t nfields, const double* a, const double* b, double* out, void* stream) {
+  clear_error();
+  if (!mesh || !a || !out) return fail(LTS_EINVAL, "NULL argument");
+  if (nfields <= 0 || nfields > 6) return fail(LTS_EINVAL, "bad nfields");
+  lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
+  Mesh& m = mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = m.n();
+  const size_t need = (size_t)(2 * nfields * N + 1) * sizeof(double);
+  if (need > h->x.norm_cap) {
+    if (h->x.d_norm) (void)hipFree(h->x.d_norm);
+    h->x.d_norm = nullptr;
+    h->x.norm_cap = 0;
+    HIP_TRY(hipMalloc(&h->x.d_norm, need), "hipMalloc norms");
+    h->x.norm_cap = need;
+  }
+  double* sq = h->x.d_norm;
+  double* mx = sq + nfields * N;
+  unsigned long long* bad = (unsigned long long*)(mx + nfields * N);
+  HIP_TRY(hipMemsetAsync(bad, 0, 8, s), "memset");
+  HIP_TRY(launch_norm_partials(a, b, nfields, N, sq, mx, bad, s), "norm launch");
+  std::vector<double> hs(2 * nfields * N + 1);
+  HIP_TRY(hipMemcpyAsync(hs.data(), sq, need, hipMemcpyDeviceToHost, s), "norm copy");
+  HIP_TRY(hipStreamSynchronize(s), "norm sync");
+  double wsum = 0.0;
+  std::vector<double> w(N);
+  for (int64_t o = 0; o < N; ++o) {
+    w[o] = std::ldexp(1.0, 3 * (m.L - m.lev[o]));
+    wsum += w[o];
+  }
+  for (int f = 0; f < nfields; ++f) {
+    double acc = 0.0, mxv = 0.0;
+    for (int64_t o = 0; o < N; ++o) {
+      acc += w[o] * hs[f * N + o];
+      mxv = std::max(mxv, hs[nfields * N + f * N + o]);
+    }
+    out[f] = std::sqrt(acc / (125.0 * wsum));
+    out[nfields + f] = mxv;
+  }
+  unsigned long long nb;
+  std::memcpy(&nb, &hs[2 * nfields * N], 8);
+  out[2 * nfields] = (double)nb;
+  return nb ? fail(LTS_ENONFINITE, "non-finite values in the state") : LTS_OK;
+}
+
+lts_status lts_copy_probe(const void* src, void* dst, size_t nbytes, void* stream) {
+  clear_error();
+  if (!src || !dst) return fail(LTS_EINVAL, "NULL argument");
+  if (nbytes % 32) return fail(LTS_EINVAL, "nbytes must be a multiple of 32");
+  HIP_TRY(launch_copy(src, dst, nbytes, (hipStream_t)stream), "copy launch");
+  return LTS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,642 @@
+// HIP kernels of the LTS hot path for gfx950 (MI355X).
+//
+// One RK stage (Sec. 3.4 + Alg. 1/2): unzip (ghost-padded block state with
+// f->c injection, degree-4 c->f interpolation and the LTS stage conversion of
+// eqs. fc_1/fc_2), block RHS (sixth-order FD + Kreiss-Oliger), zip back to the
+// octant-local nodes and, after the last stage, the RK update (eq. rk_schemes).
+//
+// Two forms:
+//   * k_fused:  one workgroup per tile of tt^3 octants, padded tile of
+//               (4tt+7)^3 points per field resident in LDS; persistent grid with
+//               an XCD-aware tile order (each of the 8 XCDs walks a contiguous,
+//               Morton-ordered range of tiles so neighbour octants hit its L2).
+//   * k_unzip / k_rhs / k_zip / k_rk: the same steps as separate launches over
+//               whole blocks through HBM (phase-by-phase path and parity checks).
+// Stencils are not dense contractions: no MFMA; the work is bound by HBM traffic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "lts_impl.h"
+#include "lts_kernels.h"
+
+namespace lts {
+
+// Degree-4 Lagrange weights L_k(xi) = prod_{m != k} (xi - m)/(k - m) on nodes
+// 0..4 at xi = x2/2 (x2 = 0..8).  Exact binary fractions (denominator 128).
+__constant__ double c_lag[9][5] = {
+    {1, 0, 0, 0, 0},
+    {35.0 / 128, 140.0 / 128, -70.0 / 128, 28.0 / 128, -5.0 / 128},
+    {0, 1, 0, 0, 0},
+    {-5.0 / 128, 60.0 / 128, 90.0 / 128, -20.0 / 128, 3.0 / 128},
+    {0, 0, 1, 0, 0},
+    {3.0 / 128, -20.0 / 128, 90.0 / 128, 60.0 / 128, -5.0 / 128},
+    {0, 0, 0, 1, 0},
+    {-5.0 / 128, 28.0 / 128, -70.0 / 128, 140.0 / 128, 35.0 / 128},
+    {0, 0, 0, 0, 1}};
+
+// sixth-order central second derivative, first derivative, KO sixth difference
+#define D2C0 (-49.0 / 18.0)
+#define D2C1 (3.0 / 2.0)
+#define D2C2 (-3.0 / 20.0)
+#define D2C3 (1.0 / 90.0)
+#define D1C1 (3.0 / 4.0)
+#define D1C2 (-3.0 / 20.0)
+#define D1C3 (1.0 / 60.0)
+
+// ------------------------------------------------------------------ schedule
+// Step index (mod 4) of a level-lev block at substep j of coarse step n:
+// LTS s = n 2^(lev-lmin) + (j >> (lmax-lev)), GTS s = n 2^(lmax-lmin) + j.
+__device__ __forceinline__ int step_mod4(int n4, int lev, const StageParams& sp) {
+  if (sp.mode == LTS_MODE_GTS) return ((n4 << (sp.lmax - sp.lmin)) + sp.j) & 3;
+  return ((n4 << (lev - sp.lmin)) + (sp.j >> (sp.lmax - lev))) & 3;
+}
+
+struct TileCtx {
+  int lev, m, tt, ox, oy, oz;
+  int par_same, par_fine, par_coarse;   // U buffer of the source records
+  int case_fine, case_coarse;           // time case of finer / coarser sources
+  double dt, h;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, const StageParams& sp, int n4) {
+  TileCtx c;
+  c.lev = t[TI_LEVEL];
+  c.m = t[TI_M];
+  c.tt = t[TI_TT];
+  const int off = t[TI_OFF];
+  c.ox = off & 255;
+  c.oy = (off >> 8) & 255;
+  c.oz = (off >> 16) & 255;
+  const int s = step_mod4(n4, c.lev, sp);
+  c.par_same = s & 1;
+  if (sp.mode == LTS_MODE_GTS) {
+    c.par_fine = c.par_coarse = s & 1;
+    c.case_fine = c.case_coarse = 0;
+    c.dt = ldexp(1.0, -sp.lmax - 3);
+  } else {
+    // a finer neighbour steps twice per receiver step: its step index is 2 s;
+    // a coarser one once per two: its index is floor(s / 2) (Sec. 3.7.3).
+    c.par_fine = 0;
+    c.par_coarse = (s >> 1) & 1;
+    c.case_fine = 1;                                   // (delta, rho) = (0, 1/2)
+    c.case_coarse = 2 + ((sp.j >> (sp.lmax - c.lev)) & 1);  // (0, 2) or (1, 2)
+    c.dt = ldexp(1.0, -c.lev - 3);
+  }
+  c.h = ldexp(1.0, -c.lev - 1);
+  return c;
+}
+
+// ------------------------------------------------------------------ gather
+template <bool KF32>
+__device__ __forceinline__ double kload(const void* K, int64_t idx) {
+  if constexpr (KF32) return (double)((const float*)K)[idx];
+  else return ((const double*)K)[idx];
+}
+
+// Y = U0 + dt sum_i w_i K_i at one DG node (field stride fs = N*125).
+template <bool KF32>
+__device__ __forceinline__ double yval(const StageParams& sp, const double* w, int par, int64_t idx,
+                                       double dt) {
+  const int64_t fs = sp.N * 125;
+  const int64_t ps = fs * sp.F;
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i < sp.p && w[i] != 0.0) acc = fma(w[i], kload<KF32>(sp.K, i * ps + idx), acc);
+  }
+  return sp.U[par * ps + idx] + dt * acc;
+}
+
+// Value of every field at padded tile point (qx, qy, qz).  slots: the tile's
+// slot table; wsh: stage-s weights per case [4][4].
+template <bool KF32, int F>
+__device__ __forceinline__ void point_values(const StageParams& sp, const TileCtx& c, const int32_t* slots,
+                                             const double* wsh, int qx, int qy, int qz, double out[F]) {
+  const Loc L = locate(qx, qy, qz, c.ox, c.oy, c.oz, c.tt, c.m);
+  const int leaf = slots[2 * L.slot];
+  const int kb = slots[2 * L.slot + 1];
+  const int kind = kb & 15;
+  const int64_t fs = sp.N * 125;
+  if (kind != SRC_COARSE) {
+    int node, lf, par;
+    const double* w;
+    if (kind == SRC_FINE) {
+      const int cx = L.nu[0] >> 1, cy = L.nu[1] >> 1, cz = L.nu[2] >> 1;
+      lf = leaf + cx + 2 * cy + 4 * cz;
+      node = 2 * (L.nu[0] - 2 * cx) + 5 * 2 * (L.nu[1] - 2 * cy) + 25 * 2 * (L.nu[2] - 2 * cz);
+      par = c.par_fine;
+      w = wsh + 4 * c.case_fine;
+    } else {
+      lf = leaf;
+      node = L.nu[0] + 5 * L.nu[1] + 25 * L.nu[2];
+      par = c.par_same;
+      w = wsh;
+    }
+    const int64_t base = (int64_t)lf * 125 + node;
+#pragma unroll
+    for (int f = 0; f < F; ++f) out[f] = yval<KF32>(sp, w, par, f * fs + base, c.dt);
+    return;
+  }
+  // coarser source: tensor degree-4 Lagrange interpolation of its Y values
+  const int beta = kb >> 4;
+  int x2[3];
+  for (int d = 0; d < 3; ++d) x2[d] = 4 * ((beta >> d) & 1) + L.nu[d];
+  const double* w = wsh + 4 * c.case_coarse;
+  const int par = c.par_coarse;
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    if (x2[d] & 1) { lo[d] = 0; hi[d] = 4; }
+    else { lo[d] = hi[d] = x2[d] >> 1; }
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) out[f] = 0.0;
+  for (int kz = lo[2]; kz <= hi[2]; ++kz) {
+    double ty[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) ty[f] = 0.0;
+    for (int ky = lo[1]; ky <= hi[1]; ++ky) {
+      double tx[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) tx[f] = 0.0;
+      for (int kx = lo[0]; kx <= hi[0]; ++kx) {
+        const double wx = c_lag[x2[0]][kx];
+        const int64_t base = (int64_t)leaf * 125 + kx + 5 * ky + 25 * kz;
+#pragma unroll
+        for (int f = 0; f < F; ++f) tx[f] = fma(wx, yval<KF32>(sp, w, par, f * fs + base, c.dt), tx[f]);
+      }
+      const double wy = c_lag[x2[1]][ky];
+#pragma unroll
+      for (int f = 0; f < F; ++f) ty[f] = fma(wy, tx[f], ty[f]);
+    }
+    const double wz = c_lag[x2[2]][kz];
+#pragma unroll
+    for (int f = 0; f < F; ++f) out[f] = fma(wz, ty[f], out[f]);
+  }
+}
+
+// ------------------------------------------------------------------ stencils
+// One grid point of the block RHS from a padded array Y (element type T, point
+// strides sx = 1, sy, sz).  Returns du/dt of each field.
+template <typename T, int EQ, int F>
+__device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, int sy, int sz, T h, T sigma,
+                                          const double ref[F], double out[F]) {
+  const T kos = sigma / (T(64) * h);
+  if constexpr (EQ == LTS_EQ_WAVE) {
+    const T* u = Y;
+    const T* v = Y + fstride;
+    const int st[3] = {1, sy, sz};
+    T lap = T(0), ku = T(0), kv = T(0);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int s = st[ax];
+      const T u0 = u[c], v0 = v[c];
+      const T up1 = u[c + s], um1 = u[c - s], up2 = u[c + 2 * s], um2 = u[c - 2 * s], up3 = u[c + 3 * s],
+              um3 = u[c - 3 * s];
+      const T vp1 = v[c + s], vm1 = v[c - s], vp2 = v[c + 2 * s], vm2 = v[c - 2 * s], vp3 = v[c + 3 * s],
+              vm3 = v[c - 3 * s];
+      lap += T(D2C3) * (um3 + up3) + T(D2C2) * (um2 + up2) + T(D2C1) * (um1 + up1) + T(D2C0) * u0;
+      ku += (um3 + up3) - T(6) * (um2 + up2) + T(15) * (um1 + up1) - T(20) * u0;
+      kv += (vm3 + vp3) - T(6) * (vm2 + vp2) + T(15) * (vm1 + vp1) - T(20) * v0;
+    }
+    out[0] = ((double)v[c] + ref[1]) + (double)(kos * ku);
+    out[1] = (double)(lap / (h * h) + kos * kv);
+  } else {
+    // Maxwell: fields Ex Ey Ez Bx By Bz
+    const int st[3] = {1, sy, sz};
+    T d[F][3];
+    T ko[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const T* g = Y + f * fstride;
+      ko[f] = T(0);
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const int s = st[ax];
+        const T p1 = g[c + s], m1 = g[c - s], p2 = g[c + 2 * s], m2 = g[c - 2 * s], p3 = g[c + 3 * s],
+                m3 = g[c - 3 * s];
+        d[f][ax] = (T(D1C1) * (p1 - m1) + T(D1C2) * (p2 - m2) + T(D1C3) * (p3 - m3)) / h;
+        ko[f] += (m3 + p3) - T(6) * (m2 + p2) + T(15) * (m1 + p1) - T(20) * g[c];
+      }
+    }
+    // curl B, curl E (axis 0 = x, 1 = y, 2 = z)
+    out[0] = (double)((d[5][1] - d[4][2]) + kos * ko[0]);
+    out[1] = (double)((d[3][2] - d[5][0]) + kos * ko[1]);
+    out[2] = (double)((d[4][0] - d[3][1]) + kos * ko[2]);
+    out[3] = (double)(-(d[2][1] - d[1][2]) + kos * ko[3]);
+    out[4] = (double)(-(d[0][2] - d[2][0]) + kos * ko[4]);
+    out[5] = (double)(-(d[1][0] - d[0][1]) + kos * ko[5]);
+  }
+}
+
+// ------------------------------------------------------------------ fused stage
+template <int TT, int F, int EQ, bool KF32>
+__global__ __launch_bounds__(256) void k_fused(StageParams sp, const int32_t* __restrict__ tiles,
+                                               const int32_t* __restrict__ slots, int ntiles) {
+  constexpr int P = 4 * TT + 7;
+  constexpr int P3 = P * P * P;
+  constexpr int W = TT + 2;
+  constexpr int NS = W * W * W;
+  using LT = typename std::conditional<KF32, float, double>::type;
+  __shared__ LT Y[F * P3];
+  __shared__ int32_t sl[2 * NS];
+  __shared__ double wsh[16];
+  __shared__ double ref[F];
+
+  if (threadIdx.x < 16) wsh[threadIdx.x] = sp.w[threadIdx.x >> 2][threadIdx.x & 3];
+  const int n4 = (int)(*sp.step & 3);
+  const int nslot = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int sid = blockIdx.x >> 3;
+  const int chunk = (ntiles + 7) >> 3;
+  const int64_t fs = sp.N * 125;
+  const int64_t ps = fs * sp.F;
+  const bool last = sp.stage == sp.p - 1;
+
+  for (int local = sid; local < chunk; local += nslot) {
+    const int ti = xcd * chunk + local;
+    if (ti >= ntiles) break;
+    const int32_t* t = tiles + 8 * (int64_t)ti;
+    const TileCtx c = tile_ctx(t, sp, n4);
+    const int first = t[TI_FIRST];
+    __syncthreads();  // previous tile done with LDS
+    for (int e = threadIdx.x; e < 2 * NS; e += blockDim.x) sl[e] = slots[2 * (int64_t)t[TI_SLOT] + e];
+    if (threadIdx.x < F) {
+      // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
+      ref[threadIdx.x] = KF32 ? sp.U[c.par_same * ps + threadIdx.x * fs + (int64_t)first * 125] : 0.0;
+    }
+    __syncthreads();
+    for (int pi = threadIdx.x; pi < P3; pi += blockDim.x) {
+      const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
+      double v[F];
+      point_values<KF32, F>(sp, c, sl, wsh, qx, qy, qz, v);
+#pragma unroll
+      for (int f = 0; f < F; ++f) Y[f * P3 + pi] = (LT)(v[f] - ref[f]);
+    }
+    __syncthreads();
+    constexpr int NN = TT * TT * TT * 125;
+    for (int e = threadIdx.x; e < NN; e += blockDim.x) {
+      const int o = e / 125, node = e - 125 * (e / 125);
+      const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
+      const int ix = 4 * (o & 1) + a + 3, iy = 4 * ((o >> 1) & 1) + b + 3, iz = 4 * ((o >> 2) & 1) + cc + 3;
+      const int ci = (iz * P + iy) * P + ix;
+      double k[F];
+      rhs_point<LT, EQ, F>(Y, P3, ci, P, P * P, (LT)c.h, (LT)sp.sigma, ref, k);
+      const int64_t idx = (int64_t)(first + o) * 125 + node;
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        double kv = k[f];
+        if constexpr (KF32) {
+          const float kf = (float)kv;
+          ((float*)sp.Kw)[sp.stage * ps + f * fs + idx] = kf;
+          kv = (double)kf;
+        } else {
+          ((double*)sp.Kw)[sp.stage * ps + f * fs + idx] = kv;
+        }
+        if (last) {
+          // compute_step_partial: U_new = U0 + dt sum_i b_i K_i into the other buffer
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (i < sp.p) {
+              const double ki = (i == sp.stage) ? kv : kload<KF32>(sp.K, i * ps + f * fs + idx);
+              acc = fma(sp.b[i], ki, acc);
+            }
+          }
+          const double u0 = sp.U[c.par_same * ps + f * fs + idx];
+          sp.Uw[(c.par_same ^ 1) * ps + f * fs + idx] = u0 + c.dt * acc;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ standalone kernels
+template <bool KF32, int F>
+__global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __restrict__ tiles,
+                                               const int32_t* __restrict__ slots, const int32_t* __restrict__ list,
+                                               const int64_t* __restrict__ off, int64_t total, double* out) {
+  __shared__ double wsh[16];
+  if (threadIdx.x < 16) wsh[threadIdx.x] = sp.w[threadIdx.x >> 2][threadIdx.x & 3];
+  __syncthreads();
+  const int bi = blockIdx.y;
+  const int b = list[bi];
+  const int32_t* t = tiles + 8 * (int64_t)b;
+  const int n4 = (int)(*sp.step & 3);
+  const TileCtx c = tile_ctx(t, sp, n4);
+  const int P = 4 * c.m + 7;
+  const int P3 = P * P * P;
+  const int32_t* sl = slots + 2 * (int64_t)t[TI_SLOT];
+  for (int pi = blockIdx.x * blockDim.x + threadIdx.x; pi < P3; pi += gridDim.x * blockDim.x) {
+    const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
+    double v[F];
+    point_values<KF32, F>(sp, c, sl, wsh, qx, qy, qz, v);
+#pragma unroll
+    for (int f = 0; f < F; ++f) out[f * total + off[bi] + pi] = v[f];
+  }
+}
+
+template <int EQ, int F, bool F32>
+__global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
+                                             const int64_t* __restrict__ poff, int64_t ptotal,
+                                             const int64_t* __restrict__ goff, int64_t gtotal,
+                                             const double* __restrict__ padded, void* kout, double sigma) {
+  const int bi = blockIdx.y;
+  const int32_t* t = tiles + 8 * (int64_t)list[bi];
+  const int m = t[TI_M];
+  const int P = 4 * m + 7, G = 4 * m + 1;
+  const int G3 = G * G * G;
+  const double h = ldexp(1.0, -t[TI_LEVEL] - 1);
+  for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G3; gi += gridDim.x * blockDim.x) {
+    const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
+    const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
+    double k[F];
+    if constexpr (F32) {
+      // float stencils on Y - ref, ref = the block's first grid value
+      double ref[F];
+      const int c0 = (3 * P + 3) * P + 3;
+#pragma unroll
+      for (int f = 0; f < F; ++f) ref[f] = padded[f * ptotal + poff[bi] + c0];
+      const int st[3] = {1, P, P * P};
+      if constexpr (EQ == LTS_EQ_WAVE) {
+        const double* u = padded + poff[bi];
+        const double* v = padded + ptotal + poff[bi];
+        float lap = 0.f, ku = 0.f, kv = 0.f;
+        for (int ax = 0; ax < 3; ++ax) {
+          const int s = st[ax];
+          float uu[7], vv[7];
+          for (int q = 0; q < 7; ++q) {
+            uu[q] = (float)(u[ci + (q - 3) * s] - ref[0]);
+            vv[q] = (float)(v[ci + (q - 3) * s] - ref[1]);
+          }
+          lap += float(D2C3) * (uu[0] + uu[6]) + float(D2C2) * (uu[1] + uu[5]) + float(D2C1) * (uu[2] + uu[4]) +
+                 float(D2C0) * uu[3];
+          ku += (uu[0] + uu[6]) - 6.f * (uu[1] + uu[5]) + 15.f * (uu[2] + uu[4]) - 20.f * uu[3];
+          kv += (vv[0] + vv[6]) - 6.f * (vv[1] + vv[5]) + 15.f * (vv[2] + vv[4]) - 20.f * vv[3];
+        }
+        const float hf = (float)h;
+        const float kos = (float)sigma / (64.f * hf);
+        k[0] = ((double)(float)(v[ci] - ref[1]) + ref[1]) + (double)(kos * ku);
+        k[1] = (double)(lap / (hf * hf) + kos * kv);
+      } else {
+        float d[F][3], ko[F];
+        for (int f = 0; f < F; ++f) {
+          const double* g = padded + f * ptotal + poff[bi];
+          ko[f] = 0.f;
+          for (int ax = 0; ax < 3; ++ax) {
+            const int s = st[ax];
+            float gg[7];
+            for (int q = 0; q < 7; ++q) gg[q] = (float)(g[ci + (q - 3) * s] - ref[f]);
+            d[f][ax] = (float(D1C1) * (gg[4] - gg[2]) + float(D1C2) * (gg[5] - gg[1]) + float(D1C3) * (gg[6] - gg[0])) /
+                       (float)h;
+            ko[f] += (gg[0] + gg[6]) - 6.f * (gg[1] + gg[5]) + 15.f * (gg[2] + gg[4]) - 20.f * gg[3];
+          }
+        }
+        const float kos = (float)sigma / (64.f * (float)h);
+        k[0] = (double)((d[5][1] - d[4][2]) + kos * ko[0]);
+        k[1] = (double)((d[3][2] - d[5][0]) + kos * ko[1]);
+        k[2] = (double)((d[4][0] - d[3][1]) + kos * ko[2]);
+        k[3] = (double)(-(d[2][1] - d[1][2]) + kos * ko[3]);
+        k[4] = (double)(-(d[0][2] - d[2][0]) + kos * ko[4]);
+        k[5] = (double)(-(d[1][0] - d[0][1]) + kos * ko[5]);
+      }
+    } else {
+      const double zero[F] = {};
+      rhs_point<double, EQ, F>(padded + poff[bi], ptotal, ci, P, P * P, h, sigma, zero, k);
+    }
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      if constexpr (F32) ((float*)kout)[f * gtotal + goff[bi] + gi] = (float)k[f];
+      else ((double*)kout)[f * gtotal + goff[bi] + gi] = k[f];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zip(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
+                                             const int64_t* __restrict__ goff, int64_t gtotal, int F, int64_t N,
+                                             const T* __restrict__ kblock, T* __restrict__ kout) {
+  const int bi = blockIdx.y;
+  const int32_t* t = tiles + 8 * (int64_t)list[bi];
+  const int m = t[TI_M];
+  const int G = 4 * m + 1;
+  const int first = t[TI_FIRST];
+  const int nn = m * m * m * 125;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int o = e / 125, node = e % 125;
+    // octant o of the block in Morton order -> lexicographic octant coordinates
+    int ox = 0, oy = 0, oz = 0;
+    for (int bit = 0; bit < 3; ++bit) {
+      ox |= ((o >> (3 * bit)) & 1) << bit;
+      oy |= ((o >> (3 * bit + 1)) & 1) << bit;
+      oz |= ((o >> (3 * bit + 2)) & 1) << bit;
+    }
+    const int gx = 4 * ox + node % 5, gy = 4 * oy + (node / 5) % 5, gz = 4 * oz + node / 25;
+    const int64_t gi = ((int64_t)gz * G + gy) * G + gx;
+    for (int f = 0; f < F; ++f) kout[(f * N + first + o) * 125 + node] = kblock[f * gtotal + goff[bi] + gi];
+  }
+}
+
+template <bool KF32>
+__global__ __launch_bounds__(256) void k_rk(StageParams sp, const int32_t* __restrict__ tiles,
+                                            const int32_t* __restrict__ list, const double* __restrict__ coef,
+                                            double* out) {
+  const int bi = blockIdx.y;
+  const int32_t* t = tiles + 8 * (int64_t)list[bi];
+  const int n4 = (int)(*sp.step & 3);
+  const TileCtx c = tile_ctx(t, sp, n4);
+  const int first = t[TI_FIRST];
+  const int nn = c.m * c.m * c.m * 125;
+  const int64_t fs = sp.N * 125, ps = fs * sp.F;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)first * 125 + e;
+    for (int f = 0; f < sp.F; ++f) {
+      double acc = 0.0;
+      for (int i = 0; i < sp.p; ++i) acc = fma(coef[i], kload<KF32>(sp.K, i * ps + f * fs + idx), acc);
+      const double v = sp.U[c.par_same * ps + f * fs + idx] + c.dt * acc;
+      if (out) out[f * fs + idx] = v;
+      else sp.Uw[(c.par_same ^ 1) * ps + f * fs + idx] = v;
+    }
+  }
+}
+
+// current state: block b's buffer after a whole number of coarse steps
+__global__ __launch_bounds__(256) void k_current(StageParams sp, const int32_t* __restrict__ tiles, int nblocks,
+                                                 double* out) {
+  const int b = blockIdx.y;
+  if (b >= nblocks) return;
+  const int32_t* t = tiles + 8 * (int64_t)b;
+  const int lev = t[TI_LEVEL];
+  const int m = t[TI_M];
+  const int first = t[TI_FIRST];
+  const int64_t n = *sp.step;
+  // steps taken: LTS n 2^(lev-lmin), GTS n 2^(lmax-lmin)
+  const int64_t steps = sp.mode == LTS_MODE_GTS ? (n << (sp.lmax - sp.lmin)) : (n << (lev - sp.lmin));
+  const int par = (int)(steps & 1);
+  const int64_t fs = sp.N * 125, ps = fs * sp.F;
+  const int nn = m * m * m * 125;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)first * 125 + e;
+    for (int f = 0; f < sp.F; ++f) out[f * fs + idx] = sp.U[par * ps + f * fs + idx];
+  }
+}
+
+__global__ void k_increment(int64_t* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] += 1;
+}
+
+// per-octant partial sums for the norms: [F][N] sum e^2, [F][N] max |e|, nonfinite count
+__global__ __launch_bounds__(128) void k_norm_partials(const double* a, const double* b, int F, int64_t N,
+                                                       double* sq, double* mx, unsigned long long* bad) {
+  const int64_t o = blockIdx.x;
+  const int f = blockIdx.y;
+  __shared__ double s1[128], s2[128];
+  __shared__ int s3[128];
+  double q = 0.0, m = 0.0;
+  int nb = 0;
+  const int node = threadIdx.x;
+  if (node < 125) {
+    const int64_t idx = ((int64_t)f * N + o) * 125 + node;
+    const double x = a[idx];
+    const double e = b ? x - b[idx] : x;
+    if (!isfinite(x)) nb = 1;
+    q = e * e;
+    m = fabs(e);
+  }
+  s1[threadIdx.x] = q;
+  s2[threadIdx.x] = m;
+  s3[threadIdx.x] = nb;
+  __syncthreads();
+  for (int w = 64; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + w]);
+      s3[threadIdx.x] += s3[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sq[(int64_t)f * N + o] = s1[0];
+    mx[(int64_t)f * N + o] = s2[0];
+    if (s3[0]) atomicAdd(bad, (unsigned long long)s3[0]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy(const double4* __restrict__ src, double4* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ launchers
+namespace {
+int fused_grid(int ntiles, int max_wg) {
+  int g = std::min(ntiles, max_wg);
+  g = (g + 7) & ~7;
+  return std::max(g, 8);
+}
+}  // namespace
+
+template <int TT, int F, int EQ, bool KF32>
+static hipError_t launch_fused_t(const StageParams& sp, const int32_t* tiles, const int32_t* slots, int ntiles,
+                                 int max_wg, hipStream_t s) {
+  hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32>), dim3(fused_grid(ntiles, max_wg)), dim3(256), 0, s, sp, tiles,
+                     slots, ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
+                        const int32_t* slots, int ntiles, int max_wg, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (eq == LTS_EQ_WAVE) {
+    if (tt == 1) return kf32 ? launch_fused_t<1, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, ntiles, max_wg, s)
+                             : launch_fused_t<1, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, ntiles, max_wg, s);
+    return kf32 ? launch_fused_t<2, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, ntiles, max_wg, s)
+                : launch_fused_t<2, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, ntiles, max_wg, s);
+  }
+  if (tt != 1) return hipErrorInvalidValue;  // 6 FP64 fields of a side-2 tile exceed LDS
+  return kf32 ? launch_fused_t<1, 6, LTS_EQ_MAXWELL, true>(sp, tiles, slots, ntiles, max_wg, s)
+              : launch_fused_t<1, 6, LTS_EQ_MAXWELL, false>(sp, tiles, slots, ntiles, max_wg, s);
+}
+
+hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
+                        const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(8, nb);
+  if (sp.F == 2) {
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 2>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    else hipLaunchKernelGGL((k_unzip<false, 2>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+  } else if (sp.F == 6) {
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 6>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    else hipLaunchKernelGGL((k_unzip<false, 6>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,
+                      int64_t ptotal, const int64_t* goff, int64_t gtotal, int nb, const double* padded, void* kout,
+                      double sigma, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(8, nb);
+  if (eq == LTS_EQ_WAVE) {
+    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
+                                gtotal, padded, kout, sigma);
+    else hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
+                            gtotal, padded, kout, sigma);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
+                                goff, gtotal, padded, kout, sigma);
+    else hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
+                            goff, gtotal, padded, kout, sigma);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zip(bool f32, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal, int nb,
+                      int F, int64_t N, const void* kblock, void* kout, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(8, nb);
+  if (f32) hipLaunchKernelGGL((k_zip<float>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
+                              (const float*)kblock, (float*)kout);
+  else hipLaunchKernelGGL((k_zip<double>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
+                          (const double*)kblock, (double*)kout);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* list, int nb,
+                     const double* coef, double* out, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(4, nb);
+  if (kf32) hipLaunchKernelGGL((k_rk<true>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+  else hipLaunchKernelGGL((k_rk<false>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_current(const StageParams& sp, const int32_t* tiles, int nblocks, double* out, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_current, dim3(4, nblocks), dim3(256), 0, s, sp, tiles, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_increment(int64_t* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_increment, dim3(1), dim3(64), 0, s, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, double* sq, double* mx,
+                                unsigned long long* bad, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_norm_partials, dim3((unsigned)N, F), dim3(128), 0, s, a, b, F, N, sq, mx, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t nbytes, hipStream_t s) {
+  const int64_t n = (int64_t)(nbytes / sizeof(double4));
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, (const double4*)src, (double4*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace lts

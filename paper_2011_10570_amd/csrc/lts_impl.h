@@ -1,0 +1,67 @@
+// Internal declarations of the library (not part of the C ABI).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lts.h"
+#include "lts_common.h"
+
+namespace lts {
+
+// Error plumbing: thread-local message, returned status.
+lts_status fail(lts_status st, const std::string& msg);
+void clear_error();
+
+struct Block {
+  int32_t first, m, level, ax, ay, az;
+};
+
+// One set of tiles of the fused kernels (all tiles of side tt) or of the
+// standalone block kernels (one tile per block, tt = m).
+struct TileSet {
+  std::vector<int32_t> tiles;   // [T][8]
+  std::vector<int32_t> slots;   // [S][2]
+  // LTS: tiles are sorted by level (finest first); n_ge[l] = tiles with level >= l
+  std::vector<int64_t> n_ge;    // size LTS_MAX_LEVEL + 1
+  int32_t* d_tiles = nullptr;
+  int32_t* d_slots = nullptr;
+  int64_t count() const { return (int64_t)tiles.size() / 8; }
+};
+
+struct Mesh {
+  int L = 0, lmin = 0, lmax = 0, cap = 4;
+  std::vector<int32_t> ax, ay, az;
+  std::vector<int8_t> lev;
+  std::vector<uint64_t> key;          // Morton key of the anchor (sorted)
+  std::vector<Block> blocks;
+  std::vector<int32_t> block_of_leaf;
+  int tile = 2;
+  TileSet ts[3];                      // ts[1]: tiles of side 1, ts[2]: side 2
+  TileSet bt;                         // one tile per block (standalone kernels)
+  bool uploaded = false;
+  int device = -1;
+  // scratch for the standalone kernels' block lists
+  int32_t* d_list = nullptr;
+  int64_t* d_off = nullptr;
+  size_t list_cap = 0;
+
+  int64_t n() const { return (int64_t)lev.size(); }
+  int find(int level, int64_t cx, int64_t cy, int64_t cz) const;
+};
+
+lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m);
+lts_status build_tiles(Mesh& m, int t);
+lts_status build_block_tiles(Mesh& m);
+void unzip_map_block(const Mesh& m, int b, int32_t* out);  // [(4m+7)^3][5]
+
+// Exact-rational coefficient tables: w[case][s][i] (4 x p x p), a[p][p], b[p].
+int tableau_stages(int tableau);
+bool coefficient_tables(int tableau, double* w, double* a, double* b);
+
+}  // namespace lts
+
+struct lts_mesh {
+  lts::Mesh m;
+};

@@ -1,0 +1,40 @@
+// Kernel launch interface between the C ABI layer and kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lts {
+
+// Arguments of one stage launch.  w holds the stage's conversion weights per
+// time case (w[case][i], eqs. fc_1/fc_2); b the RK weights.
+struct StageParams {
+  const double* U;      // [2][F][N][125]
+  double* Uw;           // same array, written by the last stage
+  const void* K;        // [p][F][N][125] double or float
+  void* Kw;             // same array, K_stage written
+  int64_t N;
+  int F, p, stage, mode, j, lmin, lmax;
+  const int64_t* step;  // device coarse-step counter (read by every launch)
+  double w[4][4];
+  double b[4];
+  double sigma;
+};
+
+hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
+                        const int32_t* slots, int ntiles, int max_wg, hipStream_t s);
+hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
+                        const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);
+hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,
+                      int64_t ptotal, const int64_t* goff, int64_t gtotal, int nb, const double* padded, void* kout,
+                      double sigma, hipStream_t s);
+hipError_t launch_zip(bool f32, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal, int nb,
+                      int F, int64_t N, const void* kblock, void* kout, hipStream_t s);
+hipError_t launch_rk(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* list, int nb,
+                     const double* coef, double* out, hipStream_t s);
+hipError_t launch_current(const StageParams& sp, const int32_t* tiles, int nblocks, double* out, hipStream_t s);
+hipError_t launch_increment(int64_t* ctr, hipStream_t s);
+hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, double* sq, double* mx,
+                                unsigned long long* bad, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, size_t nbytes, hipStream_t s);
+
+}  // namespace lts

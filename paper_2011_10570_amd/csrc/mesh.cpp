@@ -1,0 +1,463 @@
+// Host mesh builder: refinement, ghost-reach balance, octree-to-block
+// decomposition, tiles with their ghost-source slot tables, exports.
+//
+// Sec. 3.2.2 (refinement), Sec. 3.2.3 (2:1 balance, here extended to the reach
+// of three ghost layers), Sec. 3.2.4 (o2o neighbour search), Sec. 3.3 +
+// fig. oct_to_blocks (blocks = uniformly refined sub-trees).
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lts_impl.h"
+
+namespace lts {
+
+namespace {
+
+uint64_t spread3(uint64_t v) {
+  uint64_t r = 0;
+  for (int b = 0; b < 20; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+  return r;
+}
+
+uint64_t key_of(int64_t x, int64_t y, int64_t z) {
+  return spread3((uint64_t)x) | (spread3((uint64_t)y) << 1) | (spread3((uint64_t)z) << 2);
+}
+
+struct Leaf {
+  int32_t x, y, z, l;
+};
+
+int64_t pmod(int64_t a, int64_t n) {
+  int64_t r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+int64_t point_dist(int64_t x, int64_t c, int64_t n) {
+  int64_t d = pmod(x - c, n);
+  return std::min(d, n - d);
+}
+
+// smallest / largest periodic distance from c to the closed interval [lo, hi]
+int64_t dmin_axis(int64_t lo, int64_t hi, int64_t c, int64_t n) {
+  int64_t best = INT64_MAX;
+  for (int k = -1; k <= 1; ++k) {
+    int64_t d = std::max<int64_t>(0, std::max(lo + k * n - c, c - (hi + k * n)));
+    best = std::min(best, d);
+  }
+  return best;
+}
+
+int64_t dmax_axis(int64_t lo, int64_t hi, int64_t c, int64_t n) {
+  int64_t anti = pmod(c + n / 2, n);
+  for (int k = -1; k <= 1; ++k) {
+    int64_t a = anti + k * n;
+    if (lo <= a && a <= hi) return n / 2;
+  }
+  return std::max(point_dist(lo, c, n), point_dist(hi, c, n));
+}
+
+bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L) {
+  const int64_t n = 4ll << L;
+  const int64_t s = 1ll << (L - f.l);
+  const int64_t lo[3] = {4ll * f.x, 4ll * f.y, 4ll * f.z};
+  for (int ci = 0; ci < spec->n_criteria; ++ci) {
+    const lts_criterion& c = spec->criteria[ci];
+    int64_t dmin2 = 0, dmax2 = 0;
+    for (int d = 0; d < 3; ++d) {
+      int64_t a = dmin_axis(lo[d], lo[d] + 4 * s, c.center[d], n);
+      dmin2 += a * a;
+    }
+    if (c.kind == LTS_CRIT_BALL) {
+      if (c.r2[f.l] >= 0 && dmin2 < c.r2[f.l]) return true;
+    } else {
+      if (c.rhi2[f.l] < 0) continue;
+      for (int d = 0; d < 3; ++d) {
+        int64_t a = dmax_axis(lo[d], lo[d] + 4 * s, c.center[d], n);
+        dmax2 += a * a;
+      }
+      if (c.rlo2[f.l] < dmax2 && dmin2 < c.rhi2[f.l]) return true;
+    }
+  }
+  return false;
+}
+
+void push_children(std::vector<Leaf>& out, const Leaf& f, int L) {
+  const int32_t h = 1 << (L - f.l - 1);
+  for (int c = 0; c < 8; ++c)
+    out.push_back({f.x + (c & 1) * h, f.y + ((c >> 1) & 1) * h, f.z + ((c >> 2) & 1) * h, f.l + 1});
+}
+
+void sort_leaves(std::vector<Leaf>& v) {
+  std::sort(v.begin(), v.end(), [](const Leaf& a, const Leaf& b) {
+    return key_of(a.x, a.y, a.z) < key_of(b.x, b.y, b.z);
+  });
+}
+
+// Number of set cells of a periodic 3D indicator (prefix sums P, side n) in the
+// closed integer box [lo, hi] per axis (may wrap or exceed the period).
+struct Prefix {
+  int64_t n = 0;
+  std::vector<int32_t> P;  // (n+1)^3
+  int64_t at(int64_t x, int64_t y, int64_t z) const { return P[(size_t)((z * (n + 1) + y) * (n + 1) + x)]; }
+  int64_t box(int64_t x0, int64_t x1, int64_t y0, int64_t y1, int64_t z0, int64_t z1) const {
+    return at(x1, y1, z1) - at(x0, y1, z1) - at(x1, y0, z1) - at(x1, y1, z0) + at(x0, y0, z1) + at(x0, y1, z0) +
+           at(x1, y0, z0) - at(x0, y0, z0);
+  }
+  // split [lo, hi] into at most two half-open ranges inside [0, n)
+  int ranges(int64_t lo, int64_t hi, int64_t r[2][2]) const {
+    if (hi - lo + 1 >= n) {
+      r[0][0] = 0; r[0][1] = n;
+      return 1;
+    }
+    int64_t a = pmod(lo, n), b = a + (hi - lo);
+    if (b < n) {
+      r[0][0] = a; r[0][1] = b + 1;
+      return 1;
+    }
+    r[0][0] = a; r[0][1] = n;
+    r[1][0] = 0; r[1][1] = b - n + 1;
+    return 2;
+  }
+  int64_t count(const int64_t lo[3], const int64_t hi[3]) const {
+    int64_t rx[2][2], ry[2][2], rz[2][2];
+    int nx = ranges(lo[0], hi[0], rx), ny = ranges(lo[1], hi[1], ry), nz = ranges(lo[2], hi[2], rz);
+    int64_t c = 0;
+    for (int i = 0; i < nx; ++i)
+      for (int j = 0; j < ny; ++j)
+        for (int k = 0; k < nz; ++k) c += box(rx[i][0], rx[i][1], ry[j][0], ry[j][1], rz[k][0], rz[k][1]);
+    return c;
+  }
+};
+
+// Ghost-reach balance: split a level-l leaf while a leaf of level >= l+2 has
+// periodic Chebyshev box distance <= 3 h_l from it.  For each l the test runs on
+// the level-(l+2) cell grid: the leaf spans cells [A, A+4) per axis and the cells
+// whose closed box meets its box grown by 3 h_l (= 3 cells) are [A-4, A+7].
+lts_status balance(std::vector<Leaf>& leaves, int L) {
+  for (int pass = 0; pass < 64; ++pass) {
+    int lo_lev = 99, hi_lev = -1;
+    for (const Leaf& f : leaves) { lo_lev = std::min(lo_lev, f.l); hi_lev = std::max(hi_lev, f.l); }
+    std::vector<char> split(leaves.size(), 0);
+    bool any = false;
+    for (int l = lo_lev; l + 2 <= hi_lev; ++l) {
+      const int g = l + 2;
+      const int64_t n = 1ll << g;
+      Prefix pf;
+      pf.n = n;
+      std::vector<uint8_t> ind((size_t)(n * n * n), 0);
+      for (const Leaf& f : leaves) {
+        if (f.l < g) continue;
+        const int sh = L - g;
+        ind[(size_t)(((f.z >> sh) * n + (f.y >> sh)) * n + (f.x >> sh))] = 1;
+      }
+      pf.P.assign((size_t)((n + 1) * (n + 1) * (n + 1)), 0);
+      for (int64_t z = 0; z < n; ++z)
+        for (int64_t y = 0; y < n; ++y) {
+          int64_t row = 0;
+          for (int64_t x = 0; x < n; ++x) {
+            row += ind[(size_t)((z * n + y) * n + x)];
+            const size_t o = (size_t)(((z + 1) * (n + 1) + (y + 1)) * (n + 1) + (x + 1));
+            pf.P[o] = (int32_t)(row + pf.P[o - (n + 1)] + pf.P[o - (n + 1) * (n + 1)] -
+                                pf.P[o - (n + 1) - (n + 1) * (n + 1)]);
+          }
+        }
+      const int sh = L - g;
+      for (size_t i = 0; i < leaves.size(); ++i) {
+        const Leaf& f = leaves[i];
+        if (f.l != l) continue;
+        const int64_t A[3] = {f.x >> sh, f.y >> sh, f.z >> sh};
+        int64_t lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) { lo[d] = A[d] - 4; hi[d] = A[d] + 7; }
+        if (pf.count(lo, hi) > 0) { split[i] = 1; any = true; }
+      }
+    }
+    if (!any) return LTS_OK;
+    std::vector<Leaf> next;
+    next.reserve(leaves.size() * 2);
+    for (size_t i = 0; i < leaves.size(); ++i) {
+      if (split[i]) push_children(next, leaves[i], L);
+      else next.push_back(leaves[i]);
+    }
+    leaves.swap(next);
+  }
+  return fail(LTS_EINVAL, "balance did not converge");
+}
+
+}  // namespace
+
+int Mesh::find(int level, int64_t cx, int64_t cy, int64_t cz) const {
+  if (level < 0 || level > L) return -1;
+  const int64_t n = 1ll << level;
+  const int64_t s = 1ll << (L - level);
+  const uint64_t k = key_of(pmod(cx, n) * s, pmod(cy, n) * s, pmod(cz, n) * s);
+  auto it = std::lower_bound(key.begin(), key.end(), k);
+  if (it == key.end() || *it != k) return -1;
+  const int i = (int)(it - key.begin());
+  return lev[i] == level ? i : -1;
+}
+
+lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m) {
+  if (!spec) return fail(LTS_EINVAL, "spec is NULL");
+  const int L = spec->l_max;
+  if (spec->l_min < 0 || L < spec->l_min || L > 10)
+    return fail(LTS_EINVAL, "need 0 <= l_min <= l_max <= 10");
+  if (spec->block_cap != 1 && spec->block_cap != 2 && spec->block_cap != 4)
+    return fail(LTS_EINVAL, "block_cap must be 1, 2 or 4");
+  std::vector<Leaf> leaves;
+  if (spec->n_leaves > 0) {
+    if (!spec->leaves) return fail(LTS_EINVAL, "leaves is NULL");
+    const int64_t side = 1ll << L;
+    int64_t vol = 0;
+    for (int64_t i = 0; i < spec->n_leaves; ++i) {
+      Leaf f{spec->leaves[4 * i], spec->leaves[4 * i + 1], spec->leaves[4 * i + 2], spec->leaves[4 * i + 3]};
+      if (f.l < 0 || f.l > L) return fail(LTS_EINVAL, "leaf level out of range");
+      const int64_t s = 1ll << (L - f.l);
+      if (f.x < 0 || f.y < 0 || f.z < 0 || f.x + s > side || f.y + s > side || f.z + s > side ||
+          f.x % s || f.y % s || f.z % s)
+        return fail(LTS_EINVAL, "leaf anchor not aligned or outside the domain");
+      vol += s * s * s;
+      leaves.push_back(f);
+    }
+    sort_leaves(leaves);
+    for (size_t i = 1; i < leaves.size(); ++i)
+      if (key_of(leaves[i].x, leaves[i].y, leaves[i].z) == key_of(leaves[i - 1].x, leaves[i - 1].y, leaves[i - 1].z))
+        return fail(LTS_EINVAL, "duplicate leaf anchor");
+    if (vol != side * side * side) return fail(LTS_EINVAL, "leaves do not tile the domain");
+    // overlap check: Morton-sorted non-overlapping leaves have disjoint key ranges
+    for (size_t i = 0; i + 1 < leaves.size(); ++i) {
+      const uint64_t k0 = key_of(leaves[i].x, leaves[i].y, leaves[i].z);
+      const uint64_t span = 1ull << (3 * (L - leaves[i].l));
+      if (k0 + span > key_of(leaves[i + 1].x, leaves[i + 1].y, leaves[i + 1].z))
+        return fail(LTS_EINVAL, "leaves overlap");
+    }
+  } else {
+    if (spec->n_criteria < 0 || (spec->n_criteria > 0 && !spec->criteria))
+      return fail(LTS_EINVAL, "bad criteria");
+    for (int ci = 0; ci < spec->n_criteria; ++ci) {
+      const int k = spec->criteria[ci].kind;
+      if (k != LTS_CRIT_BALL && k != LTS_CRIT_ANNULUS) return fail(LTS_EINVAL, "unknown criterion kind");
+    }
+    const int32_t s = 1 << (L - spec->l_min), n = 1 << spec->l_min;
+    std::vector<Leaf> cur;
+    for (int z = 0; z < n; ++z)
+      for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x) cur.push_back({x * s, y * s, z * s, spec->l_min});
+    for (int l = spec->l_min; l < L && !cur.empty(); ++l) {
+      std::vector<Leaf> next;
+      for (const Leaf& f : cur) {
+        if (refine_leaf(spec, f, L)) push_children(next, f, L);
+        else leaves.push_back(f);
+      }
+      cur.swap(next);
+    }
+    leaves.insert(leaves.end(), cur.begin(), cur.end());
+  }
+  lts_status st = balance(leaves, L);
+  if (st != LTS_OK) return st;
+  sort_leaves(leaves);
+
+  m.L = L;
+  m.cap = spec->block_cap;
+  const size_t N = leaves.size();
+  m.ax.resize(N); m.ay.resize(N); m.az.resize(N); m.lev.resize(N); m.key.resize(N);
+  m.lmin = 99; m.lmax = -1;
+  for (size_t i = 0; i < N; ++i) {
+    m.ax[i] = leaves[i].x; m.ay[i] = leaves[i].y; m.az[i] = leaves[i].z; m.lev[i] = (int8_t)leaves[i].l;
+    m.key[i] = key_of(leaves[i].x, leaves[i].y, leaves[i].z);
+    m.lmin = std::min(m.lmin, leaves[i].l);
+    m.lmax = std::max(m.lmax, leaves[i].l);
+  }
+
+  // ---- blocks: largest uniformly refined ancestor of every leaf (fig. oct_to_blocks)
+  // cnt[l][i] = number of level-l leaves among the first i leaves
+  std::vector<std::vector<int32_t>> cnt(L + 1, std::vector<int32_t>(N + 1, 0));
+  for (size_t i = 0; i < N; ++i)
+    for (int l = 0; l <= L; ++l) cnt[l][i + 1] = cnt[l][i] + (m.lev[i] == l ? 1 : 0);
+  m.blocks.clear();
+  m.block_of_leaf.assign(N, -1);
+  for (size_t i = 0; i < N; ++i) {
+    if (m.block_of_leaf[i] >= 0) continue;
+    const int l = m.lev[i];
+    int kstar = l;
+    for (int k = l - 1; k >= 0; --k) {
+      const int64_t span = 1ll << (L - k);
+      const int64_t bx = (m.ax[i] / span) * span, by = (m.ay[i] / span) * span, bz = (m.az[i] / span) * span;
+      const uint64_t k0 = key_of(bx, by, bz);
+      const uint64_t k1 = k0 + (1ull << (3 * (L - k)));
+      const int64_t lo = std::lower_bound(m.key.begin(), m.key.end(), k0) - m.key.begin();
+      const int64_t hi = std::lower_bound(m.key.begin(), m.key.end(), k1) - m.key.begin();
+      const int64_t want = 1ll << (3 * (l - k));
+      if (hi - lo == want && cnt[l][hi] - cnt[l][lo] == want) kstar = k;
+      else break;
+    }
+    const int mm = std::min(1 << (l - kstar), m.cap);
+    const int64_t span = (int64_t)mm << (L - l);
+    const int64_t bx = (m.ax[i] / span) * span, by = (m.ay[i] / span) * span, bz = (m.az[i] / span) * span;
+    const int first = (int)(std::lower_bound(m.key.begin(), m.key.end(), key_of(bx, by, bz)) - m.key.begin());
+    if (first != (int)i) return fail(LTS_EUNBALANCED, "block anchor is not its first leaf");
+    const int bid = (int)m.blocks.size();
+    m.blocks.push_back({first, mm, l, (int32_t)bx, (int32_t)by, (int32_t)bz});
+    for (int j = 0; j < mm * mm * mm; ++j) {
+      if (m.lev[first + j] != l) return fail(LTS_EUNBALANCED, "block is not uniform");
+      m.block_of_leaf[first + j] = bid;
+    }
+  }
+  st = build_block_tiles(m);
+  if (st != LTS_OK) return st;
+  return build_tiles(m, 2);
+}
+
+namespace {
+
+// Slot table entry of the level-l cell c (block-relative octant coordinates,
+// may lie outside the block).
+lts_status slot_entry(const Mesh& m, const Block& B, int cx, int cy, int cz, int32_t out[2]) {
+  if (cx >= 0 && cy >= 0 && cz >= 0 && cx < B.m && cy < B.m && cz < B.m) {
+    out[0] = B.first + (int32_t)morton3(cx, cy, cz);
+    out[1] = SRC_SAME;
+    return LTS_OK;
+  }
+  const int l = B.level;
+  const int64_t s = 1ll << (m.L - l);
+  const int64_t gx = B.ax / s + cx, gy = B.ay / s + cy, gz = B.az / s + cz;
+  int leaf = m.find(l, gx, gy, gz);
+  if (leaf >= 0) {
+    out[0] = leaf;
+    out[1] = SRC_SAME;
+    return LTS_OK;
+  }
+  const int64_t n = 1ll << l;
+  const int64_t wx = pmod(gx, n), wy = pmod(gy, n), wz = pmod(gz, n);
+  if (l > 0) {
+    leaf = m.find(l - 1, wx >> 1, wy >> 1, wz >> 1);
+    if (leaf >= 0) {
+      const int beta = (int)((wx & 1) | ((wy & 1) << 1) | ((wz & 1) << 2));
+      out[0] = leaf;
+      out[1] = SRC_COARSE | (beta << 4);
+      return LTS_OK;
+    }
+  }
+  leaf = m.find(l + 1, 2 * wx, 2 * wy, 2 * wz);
+  if (leaf < 0) return fail(LTS_EUNBALANCED, "ghost cell is neither same, coarser nor finer");
+  for (int c = 1; c < 8; ++c) {
+    const int f = m.find(l + 1, 2 * wx + (c & 1), 2 * wy + ((c >> 1) & 1), 2 * wz + ((c >> 2) & 1));
+    if (f != leaf + c) return fail(LTS_EUNBALANCED, "ghost cell is not eight finer leaves");
+  }
+  out[0] = leaf;
+  out[1] = SRC_FINE;
+  return LTS_OK;
+}
+
+lts_status add_tile(const Mesh& m, int b, int tt, int ox, int oy, int oz, TileSet& ts) {
+  const Block& B = m.blocks[b];
+  const int w = tt + 2;
+  const int32_t slot_off = (int32_t)(ts.slots.size() / 2);
+  for (int sz = 0; sz < w; ++sz)
+    for (int sy = 0; sy < w; ++sy)
+      for (int sx = 0; sx < w; ++sx) {
+        int32_t e[2];
+        lts_status st = slot_entry(m, B, ox + sx - 1, oy + sy - 1, oz + sz - 1, e);
+        if (st != LTS_OK) return st;
+        ts.slots.push_back(e[0]);
+        ts.slots.push_back(e[1]);
+      }
+  const int32_t rec[8] = {B.first + (int32_t)morton3(ox, oy, oz), B.first, B.level, B.m, tt,
+                          ox | (oy << 8) | (oz << 16), slot_off, b};
+  ts.tiles.insert(ts.tiles.end(), rec, rec + 8);
+  return LTS_OK;
+}
+
+void finish_levels(TileSet& ts) {
+  // sort tiles by level (finest first), stable in Morton order
+  const int64_t T = ts.count();
+  std::vector<int64_t> idx(T);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return ts.tiles[8 * a + TI_LEVEL] > ts.tiles[8 * b + TI_LEVEL];
+  });
+  std::vector<int32_t> t2(ts.tiles.size());
+  for (int64_t i = 0; i < T; ++i) std::copy(&ts.tiles[8 * idx[i]], &ts.tiles[8 * idx[i]] + 8, &t2[8 * i]);
+  ts.tiles.swap(t2);
+  ts.n_ge.assign(LTS_MAX_LEVEL + 1, 0);
+  for (int l = 0; l <= LTS_MAX_LEVEL; ++l) {
+    int64_t c = 0;
+    for (int64_t i = 0; i < T; ++i) c += ts.tiles[8 * i + TI_LEVEL] >= l ? 1 : 0;
+    ts.n_ge[l] = c;
+  }
+}
+
+}  // namespace
+
+// Tiles of the fused kernels for maximum tile side t (1 or 2): a block of side m
+// is cut into tiles of side min(m, t).  ts[1] holds the side-1 tiles, ts[2] the
+// side-2 tiles; each set is ordered finest level first.
+lts_status build_tiles(Mesh& m, int t) {
+  if (t != 1 && t != 2) return fail(LTS_EINVAL, "tile side must be 1 or 2");
+  for (int k = 1; k <= 2; ++k) {
+    m.ts[k].tiles.clear();
+    m.ts[k].slots.clear();
+  }
+  for (size_t b = 0; b < m.blocks.size(); ++b) {
+    const Block& B = m.blocks[b];
+    const int tt = std::min(B.m, t);
+    for (int oz = 0; oz < B.m; oz += tt)
+      for (int oy = 0; oy < B.m; oy += tt)
+        for (int ox = 0; ox < B.m; ox += tt) {
+          lts_status st = add_tile(m, (int)b, tt, ox, oy, oz, m.ts[tt]);
+          if (st != LTS_OK) return st;
+        }
+  }
+  finish_levels(m.ts[1]);
+  finish_levels(m.ts[2]);
+  m.tile = t;
+  return LTS_OK;
+}
+
+lts_status build_block_tiles(Mesh& m) {
+  TileSet& ts = m.bt;
+  ts.tiles.clear();
+  ts.slots.clear();
+  for (size_t b = 0; b < m.blocks.size(); ++b) {
+    lts_status st = add_tile(m, (int)b, m.blocks[b].m, 0, 0, 0, ts);
+    if (st != LTS_OK) return st;
+  }
+  // block tiles stay in block order (no level sort): tile b is block b
+  return LTS_OK;
+}
+
+void unzip_map_block(const Mesh& m, int b, int32_t* out) {
+  const TileSet& ts = m.bt;
+  const int32_t* t = &ts.tiles[8 * b];
+  const int mm = t[TI_M];
+  const int P = 4 * mm + 7;
+  const int32_t* slots = &ts.slots[2 * (size_t)t[TI_SLOT]];
+  size_t r = 0;
+  for (int qz = 0; qz < P; ++qz)
+    for (int qy = 0; qy < P; ++qy)
+      for (int qx = 0; qx < P; ++qx, ++r) {
+        Loc L = locate(qx, qy, qz, 0, 0, 0, mm, mm);
+        const int32_t leaf = slots[2 * L.slot], kb = slots[2 * L.slot + 1];
+        const int kind = kb & 15, beta = kb >> 4;
+        int32_t* o = out + 5 * r;
+        if (L.inside) {
+          o[0] = leaf; o[1] = SRC_OWN;
+          for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
+        } else if (kind == SRC_SAME) {
+          o[0] = leaf; o[1] = SRC_SAME;
+          for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
+        } else if (kind == SRC_FINE) {
+          int c[3];
+          for (int d = 0; d < 3; ++d) c[d] = L.nu[d] >> 1;
+          o[0] = leaf + c[0] + 2 * c[1] + 4 * c[2]; o[1] = SRC_FINE;
+          for (int d = 0; d < 3; ++d) o[2 + d] = 4 * (L.nu[d] - 2 * c[d]);
+        } else {
+          o[0] = leaf; o[1] = SRC_COARSE;
+          for (int d = 0; d < 3; ++d) o[2 + d] = 4 * ((beta >> d) & 1) + L.nu[d];
+        }
+      }
+}
+
+}  // namespace lts

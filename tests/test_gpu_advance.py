@@ -1,0 +1,141 @@
+"""End-to-end GPU parity of lts_advance (fused, graph-captured) and
+lts_advance_unfused with the oracle's LTS / GTS drivers."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2011_10570_amd as P
+from oracle import octree as ot
+from oracle import solver as so
+from workloads import config, mesh_spec, wave_gaussian, wave_plane, maxwell_gaussian, random_dg
+
+from gpu_common import TOL, oracle_mesh, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _run_gpu(gm, U0, n, mode, eq="wave", prec=P.FP64, graph=True, unfused=False, tile=2, tableau="rk4"):
+    gm.set_tile(tile)
+    sim = P.Sim(gm, eq, prec, tableau, ko_sigma=0.1, device=DEV)
+    sim.set_state(U0)
+    if unfused:
+        sim.advance_unfused(n, mode)
+    else:
+        sim.advance(n, mode, graph=graph)
+    out = sim.current().cpu().numpy()
+    gm.set_tile(2)
+    return out
+
+
+@pytest.fixture(scope="module")
+def c1():
+    om = oracle_mesh("wave_c1")
+    gm = P.build_mesh(mesh_spec("wave_c1"))
+    cfg = config("wave_c1")
+    U0 = wave_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=0.1)
+    return om, gm, U0
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(c1):
+    om, gm, U0 = c1
+    out = {}
+    for mode in ("lts", "gts"):
+        print(f"[oracle] wave_c1 {mode} 2 coarse steps", flush=True)
+        out[mode] = so.run(om, U0, 2, mode, sigma=0.1).reshape(2, om.n_oct, 125)
+    return out
+
+
+@pytest.mark.parametrize("mode", ["lts", "gts"])
+def test_advance_fused_graph(c1, c1_oracle, mode):
+    om, gm, U0 = c1
+    md = P.MODE_LTS if mode == "lts" else P.MODE_GTS
+    got = _run_gpu(gm, U0, 2, md)
+    assert rel_err(got, c1_oracle[mode]) < TOL
+
+
+@pytest.mark.parametrize("mode", ["lts", "gts"])
+def test_advance_unfused(c1, c1_oracle, mode):
+    om, gm, U0 = c1
+    md = P.MODE_LTS if mode == "lts" else P.MODE_GTS
+    got = _run_gpu(gm, U0, 2, md, unfused=True)
+    assert rel_err(got, c1_oracle[mode]) < TOL
+
+
+def test_fused_equals_unfused_and_tiles_and_graph(c1):
+    """Tile shape, graph capture and fusion change nothing: bitwise equal runs."""
+    om, gm, U0 = c1
+    a = _run_gpu(gm, U0, 3, P.MODE_LTS, graph=True, tile=2)
+    b = _run_gpu(gm, U0, 3, P.MODE_LTS, graph=False, tile=1)
+    c = _run_gpu(gm, U0, 3, P.MODE_LTS, unfused=True)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
+def test_graph_replays_repeatable(c1):
+    """Several graph replays with eager work and syncs between them."""
+    om, gm, U0 = c1
+    sim = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=0.1, device=DEV)
+    sim.set_state(U0)
+    ref = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=0.1, device=DEV)
+    ref.set_state(U0)
+    for k in range(3):
+        sim.advance(1, P.MODE_LTS, graph=True)
+        ref.advance(1, P.MODE_LTS, graph=False)
+        torch.cuda.synchronize()
+        _ = (ref.U * 2).sum().item()          # unrelated eager work between replays
+        assert torch.equal(sim.current(), ref.current()), k
+    assert sim.coarse_step == 3
+
+
+def test_small_mesh_four_coarse_steps():
+    om = oracle_mesh("small")
+    gm = P.build_mesh(mesh_spec("small"))
+    U0 = wave_plane(om.anchors, om.levels, om.L, (1, 1, 0))
+    want = so.run(om, U0, 4, "lts", sigma=0.1).reshape(2, om.n_oct, 125)
+    got = _run_gpu(gm, U0, 4, P.MODE_LTS)
+    assert rel_err(got, want) < TOL
+
+
+def test_uniform_mesh_lts_equals_gts_bitwise():
+    a, l = ot.uniform_leaves(2, 3)
+    gm = P.build_mesh(leaves=np.concatenate([a, l[:, None]], 1), L=3)
+    om = ot.mesh_from_leaves(a, l, 3)
+    U0 = wave_plane(om.anchors, om.levels, om.L, (1, 2, 0))
+    x = _run_gpu(gm, U0, 2, P.MODE_LTS)
+    y = _run_gpu(gm, U0, 2, P.MODE_GTS)
+    assert np.array_equal(x, y)
+    want = so.run(om, U0, 2, "lts", sigma=0.1).reshape(2, om.n_oct, 125)
+    assert rel_err(x, want) < TOL
+
+
+def test_ssprk3(c1):
+    om, gm, U0 = c1
+    want = so.run(om, U0, 1, "lts", sigma=0.1, tableau="ssprk3").reshape(2, om.n_oct, 125)
+    got = _run_gpu(gm, U0, 1, P.MODE_LTS, tableau="ssprk3")
+    assert rel_err(got, want) < TOL
+
+
+def test_maxwell_tile1():
+    om = oracle_mesh("small")
+    gm = P.build_mesh(mesh_spec("small"))
+    cfg = config("small")
+    U0 = maxwell_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=0.1)
+    want = so.run(om, U0, 1, "lts", equation="maxwell", sigma=0.1).reshape(6, om.n_oct, 125)
+    got = _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", tile=1)
+    assert rel_err(got, want) < TOL
+    with pytest.raises(P.LTSError):
+        _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", tile=2)
+
+
+def test_fp32_rhs_error_stated(c1, c1_oracle):
+    """FP32 stencils with FP64 state: error vs the FP64 oracle, per field."""
+    om, gm, U0 = c1
+    got = _run_gpu(gm, U0, 2, P.MODE_LTS, prec=P.FP32_RHS)
+    want = c1_oracle["lts"]
+    for f in range(2):
+        e = np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()
+        print(f"fp32-rhs field {f}: max rel err {e:.3e}")
+        assert e < 1e-4

@@ -1,0 +1,140 @@
+"""CPU tests of the library's host side: the shared library loads and exports every
+function include/lts.h declares; the C++ mesh builder, unzip map, schedule and
+coefficient tables are bit-exact with the oracle (no GPU needed)."""
+import ctypes
+import os
+import re
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import paper_2011_10570_amd as P
+from paper_2011_10570_amd import _lib
+from oracle import octree as ot
+from oracle import rk
+from workloads import config, mesh_spec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "lts.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lts_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 20
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.PROTOTYPES), set(names) ^ set(_lib.PROTOTYPES)
+
+
+def _oracle_mesh(name):
+    return ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec(name)))
+
+
+@pytest.mark.parametrize("name", ["small", "wave_c1"])
+def test_mesh_bit_exact(name):
+    om = _oracle_mesh(name)
+    gm = P.build_mesh(mesh_spec(name))
+    lv = gm.leaves()
+    assert np.array_equal(lv[:, :3], om.anchors) and np.array_equal(lv[:, 3], om.levels)
+    assert np.array_equal(gm.blocks(), om.blocks)
+    sched = gm.schedule()
+    assert len(sched) == ot.substeps(om)
+    for j, got in enumerate(sched):
+        assert np.array_equal(got, ot.active_blocks(om, j))
+
+
+@pytest.mark.parametrize("name", ["small", "wave_c1"])
+def test_unzip_map_bit_exact(name):
+    om = _oracle_mesh(name)
+    gm = P.build_mesh(mesh_spec(name))
+    got = gm.unzip_map()
+    want = np.concatenate([ot.unzip_map(om, b) for b in range(len(om.blocks))])
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+def test_mesh_info_matches_model():
+    om = _oracle_mesh("wave_c1")
+    info = P.build_mesh(mesh_spec("wave_c1")).info()
+    sm = ot.speedup_model(om)
+    assert info["node_updates_lts"] == sm["w_lts"] and info["node_updates_gts"] == sm["w_gts"]
+    assert abs(info["s_est"] - sm["s_est"]) < 1e-12 * sm["s_est"]
+    assert (info["lmin"], info["lmax"], info["n_oct"]) == (om.lmin, om.lmax, om.n_oct)
+
+
+@pytest.mark.slow
+def test_c2_mesh_bit_exact():
+    """The 200k-leaf benchmark mesh: leaves and blocks identical to the oracle's."""
+    om = _oracle_mesh("wave_c2")
+    gm = P.build_mesh(mesh_spec("wave_c2"))
+    lv = gm.leaves()
+    assert np.array_equal(lv[:, :3], om.anchors) and np.array_equal(lv[:, 3], om.levels)
+    assert np.array_equal(gm.blocks(), om.blocks)
+
+
+def test_explicit_leaves_and_errors():
+    om = _oracle_mesh("small")
+    leaves = np.concatenate([om.anchors, om.levels[:, None]], axis=1)
+    gm = P.build_mesh(leaves=leaves, L=om.L)
+    assert np.array_equal(gm.blocks(), om.blocks)
+    # a hole in the tiling is rejected with LTS_EINVAL
+    with pytest.raises(P.LTSError) as e:
+        P.build_mesh(leaves=leaves[1:], L=om.L)
+    assert e.value.status == _lib.EINVAL
+    bad = dict(mesh_spec("small"))
+    bad["block_cap"] = 3
+    with pytest.raises(P.LTSError):
+        P.build_mesh(bad)
+
+
+def test_unbalanced_leaves_get_balanced():
+    """An explicit leaf list violating the ghost-reach balance is closed under it,
+    exactly as the oracle does."""
+    L = 4
+    a, l = ot.uniform_leaves(2, L)
+    # refine one level-2 leaf twice in its far corner
+    keep = np.ones(len(l), bool); keep[5] = False
+    ch = ot._children(a[5:6], 2, L)
+    gch = ot._children(ch[7:8], 3, L)
+    A = np.concatenate([a[keep], ch[:7], gch]); Lv = np.concatenate([l[keep], np.full(7, 3), np.full(8, 4)])
+    om = ot.mesh_from_leaves(A, Lv, L)
+    gm = P.build_mesh(leaves=np.concatenate([A, Lv[:, None]], 1), L=L)
+    lv = gm.leaves()
+    assert np.array_equal(lv[:, :3], om.anchors) and np.array_equal(lv[:, 3], om.levels)
+    assert len(om.levels) > len(Lv)
+
+
+@pytest.mark.parametrize("tab,code", [(rk.RK4, P.RK4), (rk.SSPRK3, P.SSPRK3)])
+def test_coefficients_match_oracle_rationals(tab, code):
+    c = P.coefficients(code)
+    W = rk.weight_table(tab)
+    for ci in range(4):
+        for s in range(tab.p):
+            for i in range(tab.p):
+                assert c["w"][ci, s, i] == rk.to_float(W[ci][s][i])
+    assert np.array_equal(c["b"], rk.b_f64(tab))
+    assert np.array_equal(c["a"], rk.a_f64(tab))
+
+
+def test_tiles_cover_blocks():
+    gm = P.build_mesh(mesh_spec("wave_c1"))
+    for t in (1, 2):
+        gm.set_tile(t)
+        tiles = gm.tiles()
+        blocks = gm.blocks()
+        covered = np.zeros(gm.info()["n_oct"], int)
+        for row in tiles:
+            first, bfirst, lev, m, tt = row[:5]
+            assert tt == min(m, t)
+            for o in range(tt ** 3):
+                covered[first + o] += 1
+        assert (covered == 1).all()
+        # finest level first
+        assert (np.diff(tiles[tiles[:, 4] == 1][:, 2]) <= 0).all()
