@@ -1,0 +1,289 @@
+"""Benchmark of the octree LTS hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Workload (the metric's configuration): the 3D scalar wave equation on the
+periodic octree "wave_c2" -- levels 3-8, refined by a gradient criterion around
+four seeded Gaussian pulses, 201,216 octants of 5^3 nodes (25.2M nodes), RK4,
+sixth-order FD + Kreiss-Oliger, dt_l = 0.25 h_l.  A step is one coarsest step:
+2^5 = 32 substeps x 4 stages of the fused stage kernel over the active tiles
+(Alg. 2 with the schedule of fig. blk_loop), i.e. the whole hot path once.
+
+Reported (one JSON line):
+  value          raw LTS FP64 node-updates/s (a node-update = one DG node advanced
+                 one RK step at its own level's dt), inputs resident in HBM;
+  lts_vs_gts     GTS node-updates/s on the same mesh and final time, the measured
+                 LTS-over-GTS wall-time speedup and the speedup model of eq. invS;
+  fp32_rhs       the same LTS run with FP32 stencils (FP64 state/RK/time interp.);
+  accuracy       L2 / max error against the analytic solution at T = 8 dt_lmin
+                 for LTS, GTS and FP32-RHS, and FP32-RHS vs FP64;
+  roofline       fused stage kernel: algorithmic HBM bytes (224 B per FP64 LTS
+                 node-update) / measured kernel time, against 8 TB/s;
+  cpu_baseline   the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "wave_c2"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="fused tile side (0: autotuned)")
+    ap.add_argument("--only", default="", help="comma list of legs: lts,gts,fp32")
+    return ap.parse_args()
+
+
+# algorithmic passes over the DG arrays per stage (per field): read U0 and the
+# stages the stage state needs, write K_s; the last stage also writes U_new.
+def passes_rk4(stage: int) -> int:
+    return {0: 2, 1: 3, 2: 3, 3: 6}[stage]
+
+
+def analytic_error(sim_out, leaves, L, pulses, sigma, T):
+    """L2 (volume weighted) / max error of u against the periodic Gaussian spherical wave."""
+    import torch
+    dev = sim_out.device
+    lv = torch.as_tensor(leaves, dtype=torch.int64, device=dev)
+    s = torch.bitwise_left_shift(torch.ones_like(lv[:, 3]), L - lv[:, 3]).to(torch.float64)
+    i = torch.arange(5, dtype=torch.float64, device=dev)
+    k_, j_, i_ = torch.meshgrid(i, i, i, indexing="ij")
+    loc = torch.stack([i_, j_, k_], -1).reshape(125, 3)
+    X = 4.0 * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]
+    x = -1.0 + 2.0 * X / float(4 * (1 << L))
+    u = torch.zeros(x.shape[:2], dtype=torch.float64, device=dev)
+
+    def phi(xi):
+        return xi * torch.exp(-xi * xi / (2 * sigma * sigma))
+
+    def dphi(xi):
+        return torch.exp(-xi * xi / (2 * sigma * sigma)) * (1 - xi * xi / sigma ** 2)
+
+    for cc in pulses:
+        c = -1.0 + 2.0 * torch.tensor(cc, dtype=torch.float64, device=dev) / float(4 * (1 << L))
+        for a in (-1, 0, 1):
+            for b in (-1, 0, 1):
+                for d in (-1, 0, 1):
+                    dd = x - (c + 2.0 * torch.tensor([a, b, d], dtype=torch.float64, device=dev))
+                    r = torch.sqrt((dd * dd).sum(-1))
+                    small = r < 1e-4
+                    rs = torch.where(small, torch.ones_like(r), r)
+                    val = (phi(rs + T) + phi(rs - T)) / (2 * rs)
+                    u += torch.where(small, dphi(torch.full_like(r, T)), val)
+    e = sim_out[0] - u
+    w = (2.0 ** (L - lv[:, 3].to(torch.float64))) ** 3
+    l2 = torch.sqrt((w * (e * e).sum(1)).sum() / (125.0 * w.sum())).item()
+    return {"l2": l2, "linf": e.abs().max().item(), "l2_u": torch.sqrt((w * (u * u).sum(1)).sum() / (125.0 * w.sum())).item()}
+
+
+def time_leg(P, gm, U0, mode, prec, steps, warmup, torch):
+    """Warmup + timed coarse steps; HIP events on the launch stream bracket the
+    timed region, torch.cuda.synchronize() on both sides."""
+    sim = P.Sim(gm, "wave", prec, "rk4", ko_sigma=0.1, device="cuda:0")
+    sim.set_state(U0)
+    stream = torch.cuda.current_stream()
+    sim.advance(warmup, mode, graph=True, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.advance(steps, mode, graph=True, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = e0.elapsed_time(e1) / 1e3
+    del sim
+    return wall, ev
+
+
+def cpu_baseline(spec, cfg, target_s=15.0):
+    """The oracle (FP64 NumPy, single process) on a bounded sample of the workload:
+    stage-by-stage RK steps (unzip, rhs, zip, update) of the first blocks of B_0 of
+    the first coarse step, until ~target_s of CPU time."""
+    from oracle import fd
+    from oracle import octree as ot
+    from oracle import solver as so
+    from workloads import wave_gaussian_torch
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    om = ot.build_mesh(ot.MeshSpec.from_dict(spec))
+    st = so.State(om, 2, "rk4", "lts")
+    act = st.open_records(0)
+    leaves = np.concatenate([om.anchors, om.levels[:, None]], axis=1)
+    U0 = wave_gaussian_torch(leaves, om.L, cfg["pulses"], sigma=cfg["sigma"], device="cpu").numpy()
+    st.U[0] = U0.reshape(st.U[0].shape)
+    done_nodes = 0
+    nblk = 0
+    t0 = time.process_time()
+    w0 = time.perf_counter()
+    batch = 16
+    while time.process_time() - t0 < target_s and nblk < len(act):
+        blk = act[nblk:nblk + batch]
+        for s in range(4):
+            st.stage(blk, s, fd.rhs_wave, cfg["ko_sigma"])
+        st.rk_update(blk)
+        done_nodes += int((125 * om.blocks[blk, 1] ** 3).sum())
+        nblk += len(blk)
+    cpu = time.process_time() - t0
+    wall = time.perf_counter() - w0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    return {"value": done_nodes / wall, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nblk} blocks of B_0 (first coarse step) of {WORKLOAD}, one full RK4 step each "
+                      f"(4 x unzip+rhs+zip, update): {done_nodes} node-updates in {wall:.1f} s wall "
+                      f"({cpu:.1f} s CPU), single thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
+              "of the path is a design, not built here.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2011_10570_amd as P
+    from workloads import config, mesh_spec, wave_gaussian_torch
+
+    torch.cuda.set_device(0)
+    cfg = config(WORKLOAD)
+    spec = mesh_spec(WORKLOAD)
+    gm = P.build_mesh(spec)
+    if args.tile:
+        gm.set_tile(args.tile)
+    info = gm.info()
+    leaves = gm.leaves()
+    U0 = wave_gaussian_torch(leaves, info["L"], cfg["pulses"], sigma=cfg["sigma"], device="cuda:0")
+    legs = set(args.only.split(",")) if args.only else {"lts", "gts", "fp32"}
+
+    w_lts = info["node_updates_lts"]       # DG node-updates per coarse step (eq. w_nuts)
+    w_gts = info["node_updates_gts"]       # (eq. w_uts)
+    res = {}
+    for leg in ("lts", "gts", "fp32"):
+        if leg not in legs:
+            continue
+        mode = P.MODE_GTS if leg == "gts" else P.MODE_LTS
+        prec = P.FP32_RHS if leg == "fp32" else P.FP64
+        wall, ev = time_leg(P, gm, U0, mode, prec, args.steps, args.warmup, torch)
+        nu = (w_gts if leg == "gts" else w_lts) * args.steps
+        res[leg] = {"wall_s": wall, "event_s": ev, "node_updates": nu, "rate": nu / wall,
+                    "ms_per_step": 1e3 * wall / args.steps}
+        print(f"[bench] {leg}: {res[leg]['rate']:.4e} node-updates/s, {res[leg]['ms_per_step']:.3f} ms/step",
+              file=sys.stderr, flush=True)
+
+    # accuracy at the configuration's final time T = n_coarse dt_lmin
+    acc = {}
+    if not args.no_accuracy:
+        nco = cfg["n_coarse"]
+        T = nco * 2.0 ** (-info["lmin"] - 3)
+        outs = {}
+        for leg in ("lts", "gts", "fp32"):
+            if leg not in legs:
+                continue
+            mode = P.MODE_GTS if leg == "gts" else P.MODE_LTS
+            prec = P.FP32_RHS if leg == "fp32" else P.FP64
+            sim = P.Sim(gm, "wave", prec, "rk4", ko_sigma=0.1, device="cuda:0")
+            sim.set_state(U0)
+            sim.advance(nco, mode, graph=True)
+            outs[leg] = sim.current()
+            acc[leg] = analytic_error(outs[leg], leaves, info["L"], cfg["pulses"], cfg["sigma"], T)
+            del sim
+        if "lts" in outs and "gts" in outs:
+            d = (outs["lts"] - outs["gts"])[0].abs().max().item()
+            acc["lts_minus_gts_linf"] = d
+        if "lts" in outs and "fp32" in outs:
+            for f in range(2):
+                den = outs["lts"][f].abs().max().item()
+                acc[f"fp32_vs_fp64_rel_linf_field{f}"] = (outs["fp32"][f] - outs["lts"][f]).abs().max().item() / den
+        acc["T"] = T
+
+    # roofline of the fused stage kernel (the whole timed region is fused launches
+    # plus one 1-thread counter increment per coarse step)
+    lts = res.get("lts")
+    roof = None
+    if lts:
+        nsub = info["n_substeps"]
+        # executed nodes per launch class: sum over the step's launches of nodes * passes
+        tiles = gm.tiles()
+        lev = tiles[:, 2]
+        nodes_t = 125 * tiles[:, 4].astype(np.int64) ** 3
+        alg = 0
+        launches = 0
+        for j in range(nsub):
+            lo = info["lmin"] if j == 0 else info["lmax"] - ((j & -j).bit_length() - 1)
+            nodes = int(nodes_t[lev >= lo].sum())
+            for s in range(4):
+                alg += nodes * passes_rk4(s) * 8 * 2
+                launches += int((tiles[lev >= lo, 4] == 1).any()) + int((tiles[lev >= lo, 4] == 2).any())
+        assert alg == 224 * w_lts
+        t_kernel = lts["event_s"] / args.steps
+        achieved = alg / t_kernel / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_fused (FP64 wave, tile sides 1 and 2)",
+                "algorithmic_bytes_per_launch": round(alg / launches), "launches_per_step": launches,
+                "avg_launch_us": round(1e6 * t_kernel / launches, 2)}
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(spec, cfg)
+
+    value = lts["rate"] if lts else None
+    out = {
+        "metric": "node-updates/s (LTS vs GTS, FP64 vs FP32-RHS) at fixed L2 error; p99 latency",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": lts["ms_per_step"] if lts else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}: 3D scalar wave (u, v), periodic [-1,1]^3 octree, levels "
+                               f"{info['lmin']}-{info['lmax']}, 4 seeded Gaussian pulses (sigma 0.1), "
+                               f"{info['n_oct']} octants x 125 nodes, RK4, 6th-order FD + KO, LTS, "
+                               f"dt_l = 0.25 h_l; step = one coarsest step ({info['n_substeps']} substeps)",
+                   "n_octants": info["n_oct"], "nodes": 125 * info["n_oct"],
+                   "node_updates_per_step_lts": w_lts, "node_updates_per_step_gts": w_gts,
+                   "tile": info["tile"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if "gts" in res and lts:
+        out["lts_vs_gts"] = {"gts_rate": res["gts"]["rate"], "gts_ms_per_step": res["gts"]["ms_per_step"],
+                             "measured_speedup": res["gts"]["wall_s"] / lts["wall_s"],
+                             "model_speedup_eq_invS": info["s_est"], "model_s_max": info["s_max"],
+                             "effective_gts_equivalent_rate": w_gts * args.steps / lts["wall_s"]}
+    if "fp32" in res and lts:
+        out["fp32_rhs"] = {"rate": res["fp32"]["rate"], "speedup_over_fp64": lts["wall_s"] / res["fp32"]["wall_s"]}
+    if acc:
+        out["accuracy"] = acc
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -216,6 +216,12 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
                            const lts_rhs_params* params, int32_t stage,
                            const lts_position* pos, void* stream);
 
+/* Launch shape of the fused stage kernels (process-wide; used by every later
+ * fused launch and graph capture): threads per workgroup (256, 512 or 1024) and
+ * the cap on the persistent grid in workgroups.  Results do not depend on it. */
+lts_status lts_set_launch(int32_t threads, int32_t max_workgroups);
+lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups);
+
 /* ---- simulation driver (a7; Alg. 1 / Alg. 2) ---------------------------------- */
 lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, int32_t tableau,
                           const lts_rhs_params* params, lts_sim** out);

@@ -394,14 +394,19 @@ def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
     lexicographic order of Q in [-3, 4m+3]^3 with x fastest; (px, py, pz) is the
     position in the source leaf's node units (half-integers only for kind COARSE).
 
-    Rules (the paper is silent on ownership of points shared by several leaves):
-      * Q inside [0, 4m]^3: the block's own octant min(Q>>2, m-1) per axis, local
-        node Q - 4*octant (the block grid of the uniform sub-tree).
-      * otherwise the point lies in the receiver-level cell floor(Q/4) (half-open
-        cells); that cell is covered by one leaf of the same level (SAME), by 8
-        leaves one level finer (FINE: child floor(nu/2), fine node 2(nu - 2c)), or
-        by an octant of a leaf one level coarser (COARSE: position (4 beta + nu)/2
-        in its node units, beta the cell's child bit), nu = Q - 4 floor(Q/4).
+    Ownership rule (the paper is silent on points shared by several leaves), per
+    axis on the receiver-level grid (node spacing h_lam, 4 per octant):
+      cell = -1 if Q < 0;  min(Q >> 2, m-1) if 0 <= Q <= 4m;  m if Q > 4m,
+      nu = Q - 4 cell in [0, 4],
+    i.e. the block's closed box is cut along its own octant grid (its upper faces
+    belong to its last octants) and outside it the cells are half-open.  The
+    receiver-level cell (cx, cy, cz) is then
+      * one of the block's octants (OWN): node nu;
+      * one same-level leaf (SAME): node nu;
+      * 8 leaves one level finer (FINE): child c = min(nu >> 1, 1) per axis, fine
+        node 2 (nu - 2c)  (injection of the coincident fine node);
+      * one octant (child bits beta) of a leaf one level coarser (COARSE): position
+        (4 beta + nu) / 2 in its node units (interpolated when odd).
     """
     first, m, lev = int(mesh.blocks[b, 0]), int(mesh.blocks[b, 1]), int(mesh.blocks[b, 2])
     s = 1 << (mesh.L - lev)
@@ -410,45 +415,43 @@ def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
     q = np.arange(-3, 4 * m + 4, dtype=np.int64)
     Qz, Qy, Qx = np.meshgrid(q, q, q, indexing="ij")
     Q = np.stack([Qx.ravel(), Qy.ravel(), Qz.ravel()], axis=1)  # [S^3, 3]
+    cell = np.where(Q < 0, -1, np.where(Q <= 4 * m, np.minimum(Q >> 2, m - 1), m))
+    nu = Q - 4 * cell
     out = np.zeros((S ** 3, 5), dtype=np.int64)
-    inside = ((Q >= 0) & (Q <= 4 * m)).all(axis=1)
-    # own octants
-    oc = np.minimum(Q[inside] >> 2, m - 1)
-    node = Q[inside] - 4 * oc
+    inside = ((cell >= 0) & (cell <= m - 1)).all(axis=1)
+    oc = cell[inside]
     out[inside, 0] = first + morton_key(oc[:, 0], oc[:, 1], oc[:, 2])
     out[inside, 1] = KIND_OWN
-    out[inside, 2:5] = 2 * node
-    # ghosts
+    out[inside, 2:5] = 2 * nu[inside]
     gi = np.nonzero(~inside)[0]
-    Sg = np.floor_divide(Q[gi], 4)
-    nu = Q[gi] - 4 * Sg
-    cells = base[None, :] + Sg
+    cells = base[None, :] + cell[gi]
+    nug = nu[gi]
     uniq, inv = np.unique(cells, axis=0, return_inverse=True)
     inv = inv.reshape(-1)
-    for u_i, cell in enumerate(uniq):
+    for u_i, c in enumerate(uniq):
         rows = gi[inv == u_i]
-        nur = nu[inv == u_i]
-        same = mesh.find(lev, cell)
+        nur = nug[inv == u_i]
+        same = mesh.find(lev, c)
         if same >= 0:
             out[rows, 0] = same
             out[rows, 1] = KIND_SAME
             out[rows, 2:5] = 2 * nur
             continue
-        coarse = mesh.find(lev - 1, cell >> 1) if lev > 0 else -1
+        coarse = mesh.find(lev - 1, c >> 1) if lev > 0 else -1
         if coarse >= 0:
-            beta = np.asarray(cell) & 1
+            beta = np.asarray(c) & 1
             out[rows, 0] = coarse
             out[rows, 1] = KIND_COARSE
             out[rows, 2:5] = 4 * beta[None, :] + nur
             continue
-        ch0 = mesh.find(lev + 1, 2 * cell)
+        ch0 = mesh.find(lev + 1, 2 * c)
         if ch0 < 0:
-            raise ValueError(f"unbalanced mesh: no ghost source for block {b} cell {cell}")
-        for c in range(8):
-            cc = 2 * cell + np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1])
-            if mesh.find(lev + 1, cc) != ch0 + c:
-                raise ValueError(f"unbalanced mesh: cell {cell} of block {b} is not 8 finer leaves")
-        cb = nur >> 1
+            raise ValueError(f"unbalanced mesh: no ghost source for block {b} cell {c}")
+        for k in range(8):
+            cc = 2 * c + np.array([k & 1, (k >> 1) & 1, (k >> 2) & 1])
+            if mesh.find(lev + 1, cc) != ch0 + k:
+                raise ValueError(f"unbalanced mesh: cell {c} of block {b} is not 8 finer leaves")
+        cb = np.minimum(nur >> 1, 1)
         out[rows, 0] = ch0 + cb[:, 0] + 2 * cb[:, 1] + 4 * cb[:, 2]
         out[rows, 1] = KIND_FINE
         out[rows, 2:5] = 2 * (2 * (nur - 2 * cb))

@@ -127,6 +127,14 @@ static lts_status stage_list(Mesh& m, const int32_t* blocks, int nb, const lts_p
   return LTS_OK;
 }
 
+static void set_kmask(StageParams& sp) {
+  for (int c = 0; c < 4; ++c) {
+    sp.kmask[c] = 0;
+    for (int i = 0; i < sp.p; ++i)
+      if (sp.w[c][i] != 0.0) sp.kmask[c] |= 1 << i;
+  }
+}
+
 static lts_status check_view(const Mesh& m, const lts_stage_view* v, int& p) {
   if (!v || !v->U || !v->K) return fail(LTS_EINVAL, "stage view needs U and K");
   if (v->nfields != 2 && v->nfields != 6) return fail(LTS_EINVAL, "nfields must be 2 or 6");
@@ -146,6 +154,8 @@ static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage,
   if (stage < 0 || stage >= p) return fail(LTS_EINVAL, "stage out of range");
   if (pos->mode != LTS_MODE_LTS && pos->mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
   if (pos->substep < 0 || pos->substep >= (1 << (m.lmax - m.lmin))) return fail(LTS_EINVAL, "substep out of range");
+  if ((int64_t)p * v->nfields * m.n() * 125 >= (1ll << 31))
+    return fail(LTS_EUNSUPPORTED, "stage arrays exceed 2^31 elements (32-bit offsets in the kernels)");
   double w[64], a[16], b[4];
   coefficient_tables(v->tableau, w, a, b);
   std::memset(&sp, 0, sizeof(sp));
@@ -165,6 +175,7 @@ static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage,
   for (int c = 0; c < 4; ++c)
     for (int i = 0; i < p; ++i) sp.w[c][i] = w[(c * p + stage) * p + i];
   for (int i = 0; i < p; ++i) sp.b[i] = b[i];
+  set_kmask(sp);
   return LTS_OK;
 }
 
@@ -432,7 +443,22 @@ lts_status lts_rk_stage(lts_mesh* mesh, const lts_stage_view* view, const double
   return LTS_OK;
 }
 
-static int g_max_wg = 4096;
+static LaunchShape g_shape;  // defaults: 256 threads, grid cap 4096
+
+lts_status lts_set_launch(int32_t threads, int32_t max_workgroups) {
+  clear_error();
+  if (threads != 256 && threads != 512 && threads != 1024) return fail(LTS_EINVAL, "threads must be 256, 512 or 1024");
+  if (max_workgroups < 8) return fail(LTS_EINVAL, "max_workgroups must be >= 8");
+  g_shape.threads = threads;
+  g_shape.max_wg = max_workgroups;
+  return LTS_OK;
+}
+
+lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups) {
+  if (threads) *threads = g_shape.threads;
+  if (max_workgroups) *max_workgroups = g_shape.max_wg;
+  return LTS_OK;
+}
 
 lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t equation,
                            const lts_rhs_params* params, int32_t stage, const lts_position* pos, void* stream) {
@@ -459,9 +485,10 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
     return m.lmax - tz;
   }();
   for (int tt = 1; tt <= 2; ++tt) {
-    const int nt = (int)m.ts[tt].n_ge[lo];
-    HIP_TRY(launch_fused(tt, equation, view->precision == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, nt,
-                         g_max_wg, s),
+    XcdRanges xr;
+    for (int x = 0; x < 9; ++x) xr.b[x] = m.ts[tt].xcd[lo][x];
+    HIP_TRY(launch_fused(tt, equation, view->precision == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, xr,
+                         g_shape, s),
             "fused launch");
   }
   return LTS_OK;
@@ -515,6 +542,7 @@ void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams
     for (int i = 0; i < p; ++i) sp.w[c][i] = sim->w[(c * p + stage) * p + i];
   for (int i = 0; i < p; ++i) sp.b[i] = sim->b[i];
   sp.sigma = sim->prm.ko_sigma;
+  set_kmask(sp);
 }
 
 int lowest_active_level(const Mesh& m, int mode, int j) {
@@ -533,9 +561,10 @@ lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
       StageParams sp;
       fill_sim_params(sim, st, mode, j, sp);
       for (int tt = 1; tt <= 2; ++tt) {
-        const int nt = (int)m.ts[tt].n_ge[lo];
-        HIP_TRY(launch_fused(tt, sim->eq, sim->prec == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, nt,
-                             g_max_wg, s),
+        XcdRanges xr;
+        for (int x = 0; x < 9; ++x) xr.b[x] = m.ts[tt].xcd[lo][x];
+        HIP_TRY(launch_fused(tt, sim->eq, sim->prec == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, xr,
+                             g_shape, s),
                 "fused launch");
       }
     }
@@ -566,6 +595,8 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
   if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
   const int p = tableau_stages(tableau);
   if (!p) return fail(LTS_EINVAL, "bad tableau");
+  if ((int64_t)p * (equation == LTS_EQ_WAVE ? 2 : 6) * mesh->m.n() * 125 >= (1ll << 31))
+    return fail(LTS_EUNSUPPORTED, "stage arrays exceed 2^31 elements (32-bit offsets in the kernels)");
   lts_status st = ensure_device(mesh->m);
   if (st != LTS_OK) return st;
   lts_sim* sim = new (std::nothrow) lts_sim();

@@ -95,18 +95,48 @@ __device__ __forceinline__ double kload(const void* K, int64_t idx) {
   else return ((const double*)K)[idx];
 }
 
-// Y = U0 + dt sum_i w_i K_i at one DG node (field stride fs = N*125).
+// Y = U0 + dt sum_i w_i K_i at one DG node (field stride fs = N*125); only the
+// stages with a non-zero weight (bit mask km, uniform per case) are read.
 template <bool KF32>
-__device__ __forceinline__ double yval(const StageParams& sp, const double* w, int par, int64_t idx,
+__device__ __forceinline__ double yval(const StageParams& sp, const double* w, int km, int par, int64_t idx,
                                        double dt) {
   const int64_t fs = sp.N * 125;
   const int64_t ps = fs * sp.F;
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    if (i < sp.p && w[i] != 0.0) acc = fma(w[i], kload<KF32>(sp.K, i * ps + idx), acc);
+    if ((km >> i) & 1) acc = fma(w[i], kload<KF32>(sp.K, i * ps + idx), acc);
   }
   return sp.U[par * ps + idx] + dt * acc;
+}
+
+// The same value split in a load step and a combine step, so that a thread can
+// keep the loads of several nodes in flight before using any of them.
+template <bool KF32, int F>
+struct YLoad {
+  double u[F];
+  double k[F][4];
+};
+
+template <bool KF32, int F>
+__device__ __forceinline__ void yload(const StageParams& sp, int km, int par, int64_t base, YLoad<KF32, F>& r) {
+  const int64_t fs = sp.N * 125;
+  const int64_t ps = fs * sp.F;
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    r.u[f] = sp.U[par * ps + f * fs + base];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.k[f][i] = ((km >> i) & 1) ? kload<KF32>(sp.K, i * ps + f * fs + base) : 0.0;
+  }
+}
+
+template <bool KF32, int F>
+__device__ __forceinline__ double ycombine(const YLoad<KF32, F>& r, int f, const double* w, int km, double dt) {
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if ((km >> i) & 1) acc = fma(w[i], r.k[f][i], acc);
+  return r.u[f] + dt * acc;
 }
 
 // Value of every field at padded tile point (qx, qy, qz).  slots: the tile's
@@ -120,30 +150,33 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
   const int kind = kb & 15;
   const int64_t fs = sp.N * 125;
   if (kind != SRC_COARSE) {
-    int node, lf, par;
+    int node, lf, par, km;
     const double* w;
     if (kind == SRC_FINE) {
-      const int cx = L.nu[0] >> 1, cy = L.nu[1] >> 1, cz = L.nu[2] >> 1;
+      const int cx = min(L.nu[0] >> 1, 1), cy = min(L.nu[1] >> 1, 1), cz = min(L.nu[2] >> 1, 1);
       lf = leaf + cx + 2 * cy + 4 * cz;
       node = 2 * (L.nu[0] - 2 * cx) + 5 * 2 * (L.nu[1] - 2 * cy) + 25 * 2 * (L.nu[2] - 2 * cz);
       par = c.par_fine;
       w = wsh + 4 * c.case_fine;
+      km = sp.kmask[c.case_fine];
     } else {
       lf = leaf;
       node = L.nu[0] + 5 * L.nu[1] + 25 * L.nu[2];
       par = c.par_same;
       w = wsh;
+      km = sp.kmask[0];
     }
     const int64_t base = (int64_t)lf * 125 + node;
 #pragma unroll
-    for (int f = 0; f < F; ++f) out[f] = yval<KF32>(sp, w, par, f * fs + base, c.dt);
+    for (int f = 0; f < F; ++f) out[f] = yval<KF32>(sp, w, km, par, f * fs + base, c.dt);
     return;
   }
   // coarser source: tensor degree-4 Lagrange interpolation of its Y values
-  const int beta = kb >> 4;
+  const int beta = (kb >> 4) & 7;
   int x2[3];
   for (int d = 0; d < 3; ++d) x2[d] = 4 * ((beta >> d) & 1) + L.nu[d];
   const double* w = wsh + 4 * c.case_coarse;
+  const int km = sp.kmask[c.case_coarse];
   const int par = c.par_coarse;
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
@@ -164,7 +197,7 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
         const double wx = c_lag[x2[0]][kx];
         const int64_t base = (int64_t)leaf * 125 + kx + 5 * ky + 25 * kz;
 #pragma unroll
-        for (int f = 0; f < F; ++f) tx[f] = fma(wx, yval<KF32>(sp, w, par, f * fs + base, c.dt), tx[f]);
+        for (int f = 0; f < F; ++f) tx[f] = fma(wx, yval<KF32>(sp, w, km, par, f * fs + base, c.dt), tx[f]);
       }
       const double wy = c_lag[x2[1]][ky];
 #pragma unroll
@@ -231,81 +264,263 @@ __device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, in
 }
 
 // ------------------------------------------------------------------ fused stage
-template <int TT, int F, int EQ, bool KF32>
-__global__ __launch_bounds__(256) void k_fused(StageParams sp, const int32_t* __restrict__ tiles,
-                                               const int32_t* __restrict__ slots, int ntiles) {
+// Per tile:
+//   (0) the slot table and per-axis location tables (slot position and node
+//       offset of every padded coordinate, from the location rule) go to LDS;
+//   (1) every padded point whose slot is a same-level leaf (the tile's own
+//       octants included) or 8 finer leaves reads its stage value Y = U0 +
+//       dt sum w_i K_i directly; addresses are uniform base pointers plus 32-bit
+//       element offsets, and UB points per thread are loaded before use;
+//   (2) the distinct coarser source leaves are staged in LDS (NCB at a time) and
+//       the points of coarser slots interpolated from there;
+//   (3) the stencils run on the LDS tile; K_s (and the RK update at the last
+//       stage) are written to the tile's contiguous octants.
+template <int TT, int F, int EQ, bool KF32, int NT>
+__global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __restrict__ tiles,
+                                              const int32_t* __restrict__ slots, XcdRanges xr) {
   constexpr int P = 4 * TT + 7;
   constexpr int P3 = P * P * P;
   constexpr int W = TT + 2;
   constexpr int NS = W * W * W;
+  constexpr int NCB = 2;                     // coarser leaves prolongated per batch
+  constexpr int UB = 2;                      // points per thread loaded together
   using LT = typename std::conditional<KF32, float, double>::type;
+  using KT = typename std::conditional<KF32, float, double>::type;
   __shared__ LT Y[F * P3];
-  __shared__ int32_t sl[2 * NS];
+  __shared__ int32_t sl[2 * (2 * NS + 27)];  // slot table + work lists
+  __shared__ int8_t axs[3][P], axn[3][P];    // per-axis slot position / node offset
   __shared__ double wsh[16];
+  __shared__ double lag[45];
   __shared__ double ref[F];
+  __shared__ double Yc[NCB * F * 125];       // stage values of coarser source leaves
+  __shared__ double T1[NCB * F * 225];       // ... interpolated along x: [x2 0..8][ky][kz]
+  __shared__ double T2[NCB * F * 405];       // ... and along y: [x2][y2 0..8][kz]
 
   if (threadIdx.x < 16) wsh[threadIdx.x] = sp.w[threadIdx.x >> 2][threadIdx.x & 3];
+  if (threadIdx.x < 45) lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
   const int n4 = (int)(*sp.step & 3);
+  // workgroups are dealt to the 8 XCDs round robin: XCD x walks its own
+  // contiguous (Morton-ordered, cost-balanced) range of tiles
   const int nslot = gridDim.x >> 3;
   const int xcd = blockIdx.x & 7;
   const int sid = blockIdx.x >> 3;
-  const int chunk = (ntiles + 7) >> 3;
-  const int64_t fs = sp.N * 125;
-  const int64_t ps = fs * sp.F;
+  const int fsz = (int)(sp.N * 125);          // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
+  const KT* __restrict__ Kr = (const KT*)sp.K;
+  KT* __restrict__ Kw = (KT*)sp.Kw + (int64_t)sp.stage * F * fsz;
+  const int km0 = sp.kmask[0];
 
-  for (int local = sid; local < chunk; local += nslot) {
-    const int ti = xcd * chunk + local;
-    if (ti >= ntiles) break;
+  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot) {
     const int32_t* t = tiles + 8 * (int64_t)ti;
     const TileCtx c = tile_ctx(t, sp, n4);
     const int first = t[TI_FIRST];
+    const int counts = t[TI_COUNTS];
+    const int ncl = (counts >> 24) & 255;
+    const int nent = NS + (counts & 255) + ((counts >> 8) & 255) + ((counts >> 16) & 255) + ncl;
+    const double* __restrict__ Us = sp.U + (int64_t)c.par_same * F * fsz;
+    const double* __restrict__ Uf = sp.U + (int64_t)c.par_fine * F * fsz;
+    const double* __restrict__ Uc = sp.U + (int64_t)c.par_coarse * F * fsz;
+    const int kmf = sp.kmask[c.case_fine], kmc = sp.kmask[c.case_coarse];
+    const double* wf = wsh + 4 * c.case_fine;
+    const double* wc = wsh + 4 * c.case_coarse;
     __syncthreads();  // previous tile done with LDS
-    for (int e = threadIdx.x; e < 2 * NS; e += blockDim.x) sl[e] = slots[2 * (int64_t)t[TI_SLOT] + e];
+    for (int e = threadIdx.x; e < 2 * nent; e += NT) sl[e] = slots[2 * (int64_t)t[TI_SLOT] + e];
+    if (threadIdx.x < 3 * P) {
+      const int d = threadIdx.x / P, q = threadIdx.x - P * d;
+      const int o = d == 0 ? c.ox : (d == 1 ? c.oy : c.oz);
+      const int Q = 4 * o + q - 3;
+      const int cell = cell_of(Q, c.m);
+      axs[d][q] = (int8_t)(cell - o + 1);
+      axn[d][q] = (int8_t)(Q - 4 * cell);
+    }
     if (threadIdx.x < F) {
       // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
-      ref[threadIdx.x] = KF32 ? sp.U[c.par_same * ps + threadIdx.x * fs + (int64_t)first * 125] : 0.0;
+      ref[threadIdx.x] = KF32 ? Us[threadIdx.x * fsz + first * 125] : 0.0;
     }
     __syncthreads();
-    for (int pi = threadIdx.x; pi < P3; pi += blockDim.x) {
-      const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
-      double v[F];
-      point_values<KF32, F>(sp, c, sl, wsh, qx, qy, qz, v);
+    const int32_t* lst_cleaf = sl + 2 * (nent - ncl);
+
+    // (1) same-level and finer sources
+    for (int p0 = threadIdx.x; p0 < P3; p0 += UB * NT) {
+      int pidx[UB], kind[UB], leaf[UB], nuv[UB][3];
 #pragma unroll
-      for (int f = 0; f < F; ++f) Y[f * P3 + pi] = (LT)(v[f] - ref[f]);
+      for (int u = 0; u < UB; ++u) {
+        const int pi = p0 + u * NT;
+        kind[u] = SRC_COARSE;
+        pidx[u] = pi;
+        if (pi >= P3) continue;
+        const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
+        const int si = axs[0][qx] + W * (axs[1][qy] + W * axs[2][qz]);
+        nuv[u][0] = axn[0][qx];
+        nuv[u][1] = axn[1][qy];
+        nuv[u][2] = axn[2][qz];
+        kind[u] = sl[2 * si + 1] & 15;
+        leaf[u] = sl[2 * si];
+      }
+      double uu[UB][F], kk[UB][F][4];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (kind[u] != SRC_SAME) continue;
+        const int off = leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2];
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          uu[u][f] = Us[f * fsz + off];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if ((km0 >> i) & 1) kk[u][f][i] = (double)Kr[(i * F + f) * fsz + off];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (kind[u] == SRC_FINE) {
+          const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
+          const int off = (leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
+                          10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz);
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if ((kmf >> i) & 1) acc = fma(wf[i], (double)Kr[(i * F + f) * fsz + off], acc);
+            Y[f * P3 + pidx[u]] = (LT)(Uf[f * fsz + off] + c.dt * acc - ref[f]);
+          }
+        } else if (kind[u] == SRC_SAME) {
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if ((km0 >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
+            Y[f * P3 + pidx[u]] = (LT)(uu[u][f] + c.dt * acc - ref[f]);
+          }
+        }
+      }
+    }
+    // (2) coarser sources: stage the distinct leaves (NCB at a time), prolongate
+    // each separably on its half-node grid (x, then y; the same sums, in the
+    // same order, as the direct tensor interpolation), finish along z per point
+    for (int b0 = 0; b0 < ncl; b0 += NCB) {
+      const int nb = min(NCB, ncl - b0);
+      if (b0 > 0) __syncthreads();   // previous batch's points done
+      for (int e = threadIdx.x; e < nb * F * 125; e += NT) {
+        const int k = e / (F * 125), rem = e - k * (F * 125);
+        const int f = rem / 125, n = rem - 125 * f;
+        const int off = lst_cleaf[2 * (b0 + k)] * 125 + n;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if ((kmc >> i) & 1) acc = fma(wc[i], (double)Kr[(i * F + f) * fsz + off], acc);
+        Yc[e] = Uc[f * fsz + off] + c.dt * acc;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < nb * F * 225; e += NT) {
+        const int kf = e / 225, r = e - 225 * kf;        // kf = leaf * F + field
+        const int x2 = r / 25, yz = r - 25 * x2;          // yz = ky + 5 kz
+        const double* yc = Yc + kf * 125 + 5 * yz;
+        double tx;
+        if (x2 & 1) {
+          tx = 0.0;
+#pragma unroll
+          for (int kx = 0; kx < 5; ++kx) tx = fma(lag[5 * x2 + kx], yc[kx], tx);
+        } else {
+          tx = fma(1.0, yc[x2 >> 1], 0.0);
+        }
+        T1[e] = tx;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < nb * F * 405; e += NT) {
+        const int kf = e / 405, r = e - 405 * kf;
+        const int x2 = r / 45, r2 = r - 45 * x2;
+        const int y2 = r2 / 5, kz = r2 - 5 * y2;
+        const double* t1 = T1 + kf * 225 + 25 * x2 + 5 * kz;   // [ky] stride 1
+        double ty;
+        if (y2 & 1) {
+          ty = 0.0;
+#pragma unroll
+          for (int ky = 0; ky < 5; ++ky) ty = fma(lag[5 * y2 + ky], t1[ky], ty);
+        } else {
+          ty = fma(1.0, t1[y2 >> 1], 0.0);
+        }
+        T2[e] = ty;
+      }
+      __syncthreads();
+      for (int pi = threadIdx.x; pi < P3; pi += NT) {
+        const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
+        const int si = axs[0][qx] + W * (axs[1][qy] + W * axs[2][qz]);
+        const int kb = sl[2 * si + 1];
+        if ((kb & 15) != SRC_COARSE) continue;
+        const int cidx = kb >> 8;
+        if (cidx < b0 || cidx >= b0 + nb) continue;
+        const int beta = (kb >> 4) & 7;
+        const int x2 = 4 * (beta & 1) + axn[0][qx], y2 = 4 * ((beta >> 1) & 1) + axn[1][qy],
+                  z2 = 4 * ((beta >> 2) & 1) + axn[2][qz];
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          const double* t2 = T2 + ((cidx - b0) * F + f) * 405 + 45 * x2 + 5 * y2;   // [kz]
+          double v;
+          if (z2 & 1) {
+            v = 0.0;
+#pragma unroll
+            for (int kz = 0; kz < 5; ++kz) v = fma(lag[5 * z2 + kz], t2[kz], v);
+          } else {
+            v = fma(1.0, t2[z2 >> 1], 0.0);
+          }
+          Y[f * P3 + pi] = (LT)(v - ref[f]);
+        }
+      }
     }
     __syncthreads();
-    constexpr int NN = TT * TT * TT * 125;
-    for (int e = threadIdx.x; e < NN; e += blockDim.x) {
-      const int o = e / 125, node = e - 125 * (e / 125);
-      const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
-      const int ix = 4 * (o & 1) + a + 3, iy = 4 * ((o >> 1) & 1) + b + 3, iz = 4 * ((o >> 2) & 1) + cc + 3;
-      const int ci = (iz * P + iy) * P + ix;
+    // (3a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
+    // (the coarse prolongation buffer is free by now)
+    constexpr int G = 4 * TT + 1;
+    constexpr int G3 = G * G * G;
+    static_assert(NCB * F * 405 >= F * G3, "grid result buffer");
+    double* R = T2;
+    for (int gi = threadIdx.x; gi < G3; gi += NT) {
+      const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
+      const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
       double k[F];
       rhs_point<LT, EQ, F>(Y, P3, ci, P, P * P, (LT)c.h, (LT)sp.sigma, ref, k);
-      const int64_t idx = (int64_t)(first + o) * 125 + node;
+#pragma unroll
+      for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
+    }
+    __syncthreads();
+    // (3b) zip: every DG node of the tile's (contiguous) octants takes its grid
+    // value; node e of the tile is element first*125 + e of every field array;
+    // the last stage also forms the RK update
+    constexpr int NN = TT * TT * TT * 125;
+    for (int e = threadIdx.x; e < NN; e += NT) {
+      const int off = first * 125 + e;
+      double u0[F], kprev[F][4];
+      if (last) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          u0[f] = Us[f * fsz + off];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) kprev[f][i] = (i < sp.stage) ? (double)Kr[(i * F + f) * fsz + off] : 0.0;
+        }
+      }
+      const int o = e / 125, node = e - 125 * (e / 125);
+      const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
+      const int gi = ((4 * ((o >> 2) & 1) + cc) * G + (4 * ((o >> 1) & 1) + b)) * G + (4 * (o & 1) + a);
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        double kv = k[f];
+        double kv = R[f * G3 + gi];
         if constexpr (KF32) {
           const float kf = (float)kv;
-          ((float*)sp.Kw)[sp.stage * ps + f * fs + idx] = kf;
+          Kw[f * fsz + off] = kf;
           kv = (double)kf;
         } else {
-          ((double*)sp.Kw)[sp.stage * ps + f * fs + idx] = kv;
+          Kw[f * fsz + off] = kv;
         }
         if (last) {
           // compute_step_partial: U_new = U0 + dt sum_i b_i K_i into the other buffer
           double acc = 0.0;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            if (i < sp.p) {
-              const double ki = (i == sp.stage) ? kv : kload<KF32>(sp.K, i * ps + f * fs + idx);
-              acc = fma(sp.b[i], ki, acc);
-            }
+            if (i < sp.p) acc = fma(sp.b[i], (i == sp.stage) ? kv : kprev[f][i], acc);
           }
-          const double u0 = sp.U[c.par_same * ps + f * fs + idx];
-          sp.Uw[(c.par_same ^ 1) * ps + f * fs + idx] = u0 + c.dt * acc;
+          sp.Uw[(int64_t)(c.par_same ^ 1) * F * fsz + f * fsz + off] = u0[f] + c.dt * acc;
         }
       }
     }
@@ -537,26 +752,38 @@ int fused_grid(int ntiles, int max_wg) {
 }
 }  // namespace
 
-template <int TT, int F, int EQ, bool KF32>
-static hipError_t launch_fused_t(const StageParams& sp, const int32_t* tiles, const int32_t* slots, int ntiles,
-                                 int max_wg, hipStream_t s) {
-  hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32>), dim3(fused_grid(ntiles, max_wg)), dim3(256), 0, s, sp, tiles,
-                     slots, ntiles);
+template <int TT, int F, int EQ, bool KF32, int NT>
+static hipError_t launch_fused_nt(const StageParams& sp, const int32_t* tiles, const int32_t* slots,
+                                  const XcdRanges& xr, int max_wg, hipStream_t s) {
+  const int ntiles = xr.b[8];
+  hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32, NT>), dim3(fused_grid(ntiles, max_wg)), dim3(NT), 0, s, sp, tiles,
+                     slots, xr);
   return hipGetLastError();
 }
 
+template <int TT, int F, int EQ, bool KF32>
+static hipError_t launch_fused_t(const StageParams& sp, const int32_t* tiles, const int32_t* slots,
+                                 const XcdRanges& xr, const LaunchShape& ls, hipStream_t s) {
+  switch (ls.threads) {
+    case 256: return launch_fused_nt<TT, F, EQ, KF32, 256>(sp, tiles, slots, xr, ls.max_wg, s);
+    case 512: return launch_fused_nt<TT, F, EQ, KF32, 512>(sp, tiles, slots, xr, ls.max_wg, s);
+    case 1024: return launch_fused_nt<TT, F, EQ, KF32, 1024>(sp, tiles, slots, xr, ls.max_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
-                        const int32_t* slots, int ntiles, int max_wg, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+                        const int32_t* slots, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s) {
+  if (xr.b[8] <= 0) return hipSuccess;
   if (eq == LTS_EQ_WAVE) {
-    if (tt == 1) return kf32 ? launch_fused_t<1, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, ntiles, max_wg, s)
-                             : launch_fused_t<1, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, ntiles, max_wg, s);
-    return kf32 ? launch_fused_t<2, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, ntiles, max_wg, s)
-                : launch_fused_t<2, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, ntiles, max_wg, s);
+    if (tt == 1) return kf32 ? launch_fused_t<1, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, xr, ls, s)
+                             : launch_fused_t<1, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, xr, ls, s);
+    return kf32 ? launch_fused_t<2, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, xr, ls, s)
+                : launch_fused_t<2, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, xr, ls, s);
   }
   if (tt != 1) return hipErrorInvalidValue;  // 6 FP64 fields of a side-2 tile exceed LDS
-  return kf32 ? launch_fused_t<1, 6, LTS_EQ_MAXWELL, true>(sp, tiles, slots, ntiles, max_wg, s)
-              : launch_fused_t<1, 6, LTS_EQ_MAXWELL, false>(sp, tiles, slots, ntiles, max_wg, s);
+  return kf32 ? launch_fused_t<1, 6, LTS_EQ_MAXWELL, true>(sp, tiles, slots, xr, ls, s)
+              : launch_fused_t<1, 6, LTS_EQ_MAXWELL, false>(sp, tiles, slots, xr, ls, s);
 }
 
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,

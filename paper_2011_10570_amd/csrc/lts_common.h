@@ -3,16 +3,15 @@
 // Point location inside a tile's padded region (Sec. 3.4, fig. unzip).  A tile is
 // a cube of tt^3 octants at offset o (octants) inside a block of m^3 octants at
 // level l.  Padded tile point q in [0, 4tt+7)^3 has block-relative node
-// coordinate Q = 4 o + q - 3 in [-3, 4m+3].
-//   * Q inside [0, 4m]^3: the block's own octant min(Q>>2, m-1), node Q - 4 oct
-//     (the block grid of a uniformly refined sub-tree).
-//   * otherwise: the receiver-level cell floor(Q/4) (half-open cells) and the node
-//     offset nu = Q - 4 floor(Q/4) in [0, 3] inside it.
-// The cell is looked up in the tile's slot table of (tt+2)^3 entries (cells
-// o-1 .. o+tt per axis).  A slot holds one same-level leaf, 8 leaves one level
-// finer (first child; child c = nu>>1, fine node 2(nu - 2c)), or one octant
-// (child bits beta) of a leaf one level coarser (position (4 beta + nu)/2 in its
-// node units; interpolated when odd).
+// coordinate Q = 4 o + q - 3 in [-3, 4m+3].  Per axis the receiver-level cell is
+//   -1 if Q < 0,   min(Q >> 2, m-1) if 0 <= Q <= 4m,   m if Q > 4m,
+// and nu = Q - 4 cell in [0, 4]: the block's closed box is cut along its own
+// octant grid, outside it cells are half-open.  The cell is looked up in the
+// tile's slot table of (tt+2)^3 entries (cells o-1 .. o+tt per axis).  A slot
+// holds one same-level leaf (node nu), 8 leaves one level finer (child
+// c = min(nu>>1, 1), fine node 2(nu - 2c)), or one octant (child bits beta) of a
+// leaf one level coarser (position (4 beta + nu)/2 in its node units,
+// interpolated when odd).
 #pragma once
 #include <stdint.h>
 
@@ -27,9 +26,11 @@ namespace lts {
 
 enum { SRC_OWN = 0, SRC_SAME = 1, SRC_FINE = 2, SRC_COARSE = 3 };
 
-// tile record: int32[8]
-enum { TI_FIRST = 0, TI_BLOCK_FIRST = 1, TI_LEVEL = 2, TI_M = 3, TI_TT = 4, TI_OFF = 5, TI_SLOT = 6, TI_BLOCK = 7 };
-// slot record: int32[2] = leaf, kind | beta << 4
+// tile record: int32[8]; TI_COUNTS packs the lengths of the tile's work lists:
+// same-level slots | finer slots << 8 | coarser slots << 16 | coarser leaves << 24
+enum { TI_FIRST = 0, TI_COUNTS = 1, TI_LEVEL = 2, TI_M = 3, TI_TT = 4, TI_OFF = 5, TI_SLOT = 6, TI_BLOCK = 7 };
+// slot record: int32[2] = leaf, kind | beta << 4 | cidx << 8 (cidx: index of a
+// coarser source leaf in the tile's list of distinct coarser leaves)
 
 LTS_HD uint32_t part1by2(uint32_t v) {
   uint32_t r = 0;
@@ -41,40 +42,42 @@ LTS_HD uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
 }
 
-// Result of locating one padded point: slot index, node offset inside the slot
-// cell (0..4) and whether it is a block-interior point.
+// Result of locating one padded point: slot index and node offset inside the
+// slot's cell (0..4).
 struct Loc {
   int slot;
   int nu[3];
-  bool inside;
 };
+
+LTS_HD int cell_of(int Q, int m) {
+  if (Q < 0) return -1;
+  if (Q > 4 * m) return m;
+  const int c = Q >> 2;
+  return c < m - 1 ? c : m - 1;
+}
 
 LTS_HD Loc locate(int qx, int qy, int qz, int ox, int oy, int oz, int tt, int m) {
   const int q[3] = {qx, qy, qz};
   const int o[3] = {ox, oy, oz};
-  int Q[3];
-  bool inside = true;
-  for (int d = 0; d < 3; ++d) {
-    Q[d] = 4 * o[d] + q[d] - 3;
-    inside = inside && Q[d] >= 0 && Q[d] <= 4 * m;
-  }
   Loc r;
-  r.inside = inside;
   int s[3];
   for (int d = 0; d < 3; ++d) {
-    int cell;
-    if (inside) {
-      cell = Q[d] >> 2;
-      if (cell > m - 1) cell = m - 1;
-    } else {
-      cell = Q[d] >> 2;  // arithmetic shift: floor for negative Q
-    }
-    r.nu[d] = Q[d] - 4 * cell;
+    const int Q = 4 * o[d] + q[d] - 3;
+    const int cell = cell_of(Q, m);
+    r.nu[d] = Q - 4 * cell;
     s[d] = cell - o[d] + 1;
   }
   const int w = tt + 2;
   r.slot = s[0] + w * (s[1] + w * s[2]);
   return r;
+}
+
+// Nodes of slot position s (0 .. tt+1 along one axis) that the location rule
+// assigns to that slot inside the padded region: nu in [lo, hi].
+LTS_HD void owned_range(int s, int o, int tt, int m, int& lo, int& hi) {
+  const int cell = o + s - 1;
+  lo = (s == 0 || cell >= m) ? 1 : 0;
+  hi = (s >= 1 && s <= tt && cell == m - 1) ? 4 : 3;
 }
 
 }  // namespace lts

@@ -25,6 +25,9 @@ struct TileSet {
   std::vector<int32_t> slots;   // [S][2]
   // LTS: tiles are sorted by level (finest first); n_ge[l] = tiles with level >= l
   std::vector<int64_t> n_ge;    // size LTS_MAX_LEVEL + 1
+  // per lowest active level l: the prefix [0, n_ge[l]) cut into 8 contiguous
+  // ranges of equal estimated cost (one per XCD): xcd[l][0..8]
+  std::vector<std::vector<int32_t>> xcd;
   int32_t* d_tiles = nullptr;
   int32_t* d_slots = nullptr;
   int64_t count() const { return (int64_t)tiles.size() / 8; }

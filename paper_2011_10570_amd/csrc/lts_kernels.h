@@ -18,10 +18,24 @@ struct StageParams {
   double w[4][4];
   double b[4];
   double sigma;
+  int kmask[4];         // per case: bit i set if w[case][i] != 0 (uniform branches)
+};
+
+// Launch shape of the fused kernel: threads per workgroup (256, 512, 1024) and the
+// cap on the persistent grid (workgroups, rounded to a multiple of 8 XCDs).
+struct LaunchShape {
+  int threads = 256;
+  int max_wg = 4096;
+};
+
+// Tiles of one launch cut into 8 contiguous ranges, one per XCD: XCD x walks
+// tiles [b[x], b[x+1]); b[8] is the launch's tile count.
+struct XcdRanges {
+  int b[9];
 };
 
 hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
-                        const int32_t* slots, int ntiles, int max_wg, hipStream_t s);
+                        const int32_t* slots, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s);
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
                         const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);
 hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,

@@ -351,20 +351,52 @@ lts_status slot_entry(const Mesh& m, const Block& B, int cx, int cy, int cz, int
   return LTS_OK;
 }
 
+// A tile's slot table: (tt+2)^3 entries (leaf, kind | beta << 4 | cidx << 8) in slot
+// order, followed by work lists (one int pair each): the same-level slots, the
+// finer slots, the coarser slots, then the distinct coarser source leaves (cidx
+// numbers them in order of first appearance).
 lts_status add_tile(const Mesh& m, int b, int tt, int ox, int oy, int oz, TileSet& ts) {
   const Block& B = m.blocks[b];
   const int w = tt + 2;
-  const int32_t slot_off = (int32_t)(ts.slots.size() / 2);
+  const int ns = w * w * w;
+  std::vector<int32_t> tab(2 * ns);
+  std::vector<int32_t> same, fine, coarse, cleaves;
   for (int sz = 0; sz < w; ++sz)
     for (int sy = 0; sy < w; ++sy)
       for (int sx = 0; sx < w; ++sx) {
         int32_t e[2];
         lts_status st = slot_entry(m, B, ox + sx - 1, oy + sy - 1, oz + sz - 1, e);
         if (st != LTS_OK) return st;
-        ts.slots.push_back(e[0]);
-        ts.slots.push_back(e[1]);
+        const int si = sx + w * (sy + w * sz);
+        const int kind = e[1] & 15;
+        if (kind == SRC_COARSE) {
+          int cidx = -1;
+          for (size_t k = 0; k < cleaves.size(); ++k)
+            if (cleaves[k] == e[0]) cidx = (int)k;
+          if (cidx < 0) {
+            cidx = (int)cleaves.size();
+            cleaves.push_back(e[0]);
+          }
+          e[1] |= cidx << 8;
+          coarse.push_back(si);
+        } else if (kind == SRC_FINE) {
+          fine.push_back(si);
+        } else {
+          same.push_back(si);
+        }
+        tab[2 * si] = e[0];
+        tab[2 * si + 1] = e[1];
       }
-  const int32_t rec[8] = {B.first + (int32_t)morton3(ox, oy, oz), B.first, B.level, B.m, tt,
+  const int32_t slot_off = (int32_t)(ts.slots.size() / 2);
+  ts.slots.insert(ts.slots.end(), tab.begin(), tab.end());
+  for (const auto* lst : {&same, &fine, &coarse, &cleaves})
+    for (int32_t v : *lst) {
+      ts.slots.push_back(v);
+      ts.slots.push_back(0);
+    }
+  const int32_t counts = (int32_t)same.size() | ((int32_t)fine.size() << 8) | ((int32_t)coarse.size() << 16) |
+                         ((int32_t)cleaves.size() << 24);
+  const int32_t rec[8] = {B.first + (int32_t)morton3(ox, oy, oz), counts, B.level, B.m, tt,
                           ox | (oy << 8) | (oz << 16), slot_off, b};
   ts.tiles.insert(ts.tiles.end(), rec, rec + 8);
   return LTS_OK;
@@ -386,6 +418,28 @@ void finish_levels(TileSet& ts) {
     int64_t c = 0;
     for (int64_t i = 0; i < T; ++i) c += ts.tiles[8 * i + TI_LEVEL] >= l ? 1 : 0;
     ts.n_ge[l] = c;
+  }
+  // Weighted partition of every launch prefix over the 8 XCDs (the paper's
+  // weighted SFC partitioning, Sec. 3.7.4, applied to the chip's dies): cost of a
+  // tile = direct points + coarser slots + coarser leaves to prolongate.
+  std::vector<double> pre(T + 1, 0.0);
+  for (int64_t i = 0; i < T; ++i) {
+    const int cnt = ts.tiles[8 * i + TI_COUNTS];
+    const int ncs = (cnt >> 16) & 255, ncl = (cnt >> 24) & 255, nf = (cnt >> 8) & 255;
+    pre[i + 1] = pre[i] + 8.0 + 1.0 * ncs + 3.0 * ncl + 0.5 * nf;
+  }
+  ts.xcd.assign(LTS_MAX_LEVEL + 1, std::vector<int32_t>(9, 0));
+  for (int l = 0; l <= LTS_MAX_LEVEL; ++l) {
+    const int64_t n = ts.n_ge[l];
+    std::vector<int32_t>& b = ts.xcd[l];
+    b[0] = 0;
+    for (int x = 1; x < 8; ++x) {
+      const double target = pre[n] * x / 8.0;
+      int64_t k = std::lower_bound(pre.begin(), pre.begin() + n + 1, target) - pre.begin();
+      if (k < b[x - 1]) k = b[x - 1];
+      b[x] = (int32_t)std::min<int64_t>(k, n);
+    }
+    b[8] = (int32_t)n;
   }
 }
 
@@ -440,9 +494,11 @@ void unzip_map_block(const Mesh& m, int b, int32_t* out) {
       for (int qx = 0; qx < P; ++qx, ++r) {
         Loc L = locate(qx, qy, qz, 0, 0, 0, mm, mm);
         const int32_t leaf = slots[2 * L.slot], kb = slots[2 * L.slot + 1];
-        const int kind = kb & 15, beta = kb >> 4;
+        const int kind = kb & 15, beta = (kb >> 4) & 7;
+        const int sx = L.slot % (mm + 2), sy = (L.slot / (mm + 2)) % (mm + 2), sz = L.slot / ((mm + 2) * (mm + 2));
+        const bool inside = sx >= 1 && sx <= mm && sy >= 1 && sy <= mm && sz >= 1 && sz <= mm;
         int32_t* o = out + 5 * r;
-        if (L.inside) {
+        if (inside) {
           o[0] = leaf; o[1] = SRC_OWN;
           for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
         } else if (kind == SRC_SAME) {
@@ -450,7 +506,7 @@ void unzip_map_block(const Mesh& m, int b, int32_t* out) {
           for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
         } else if (kind == SRC_FINE) {
           int c[3];
-          for (int d = 0; d < 3; ++d) c[d] = L.nu[d] >> 1;
+          for (int d = 0; d < 3; ++d) c[d] = L.nu[d] >> 1 < 1 ? L.nu[d] >> 1 : 1;
           o[0] = leaf + c[0] + 2 * c[1] + 4 * c[2]; o[1] = SRC_FINE;
           for (int d = 0; d < 3; ++d) o[2 + d] = 4 * (L.nu[d] - 2 * c[d]);
         } else {

@@ -131,7 +131,7 @@ def test_tiles_cover_blocks():
         blocks = gm.blocks()
         covered = np.zeros(gm.info()["n_oct"], int)
         for row in tiles:
-            first, bfirst, lev, m, tt = row[:5]
+            first, counts, lev, m, tt = row[:5]
             assert tt == min(m, t)
             for o in range(tt ** 3):
                 covered[first + o] += 1

@@ -133,3 +133,24 @@ def config(name: str) -> dict:
 
 def config_names() -> List[str]:
     return list(_load_specs().keys())
+
+
+def wave_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1.0, device="cuda"):
+    """Same data as wave_gaussian, evaluated with torch on `device` (large meshes).
+    leaves: int [N, 4] (anchor x, y, z, level).  Returns [2, N, 125] float64."""
+    import torch
+    lv = torch.as_tensor(np.asarray(leaves), dtype=torch.int64, device=device)
+    s = torch.bitwise_left_shift(torch.ones_like(lv[:, 3]), L - lv[:, 3]).to(torch.float64)
+    i = torch.arange(5, dtype=torch.float64, device=device)
+    k_, j_, i_ = torch.meshgrid(i, i, i, indexing="ij")
+    loc = torch.stack([i_, j_, k_], -1).reshape(125, 3)
+    X = 4.0 * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]       # [N,125,3]
+    x = -1.0 + 2.0 * X / float(4 * (1 << L))
+    u = torch.zeros(x.shape[:2], dtype=torch.float64, device=device)
+    ims = torch.as_tensor(IMAGES, device=device)
+    for cc in centres_nu:
+        c = torch.as_tensor(centre_physical(cc, L), device=device)
+        for im in ims:
+            d = x - (c + im)
+            u += amp * torch.exp(-(d * d).sum(-1) / (2.0 * sigma * sigma))
+    return torch.stack([u, torch.zeros_like(u)])
