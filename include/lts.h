@@ -131,10 +131,12 @@ typedef struct {
   int64_t node_updates_gts;  /* same for GTS (eq. w_uts)                             */
   double s_est;              /* speedup model 1/S of eq. invS, inverted             */
   double s_max;              /* |W| / alpha_0                                        */
+  int64_t table_bytes;       /* device memory of the mesh's tables (all tile sides) */
 } lts_mesh_info;
 
 typedef struct lts_mesh lts_mesh;
 typedef struct lts_sim lts_sim;
+typedef struct lts_batch lts_batch;
 
 /* Device arrays of one state (see Layouts).  nfields: 2 (wave) or 6 (Maxwell). */
 typedef struct {
@@ -217,7 +219,7 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
                            const lts_position* pos, void* stream);
 
 /* Launch shape of the fused stage kernels (process-wide; used by every later
- * fused launch and graph capture): threads per workgroup (256, 512 or 1024) and
+ * fused launch and graph capture): threads per workgroup (256 or 512) and
  * the cap on the persistent grid in workgroups.  Results do not depend on it. */
 lts_status lts_set_launch(int32_t threads, int32_t max_workgroups);
 lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups);
@@ -239,9 +241,46 @@ lts_status lts_sim_current(lts_sim* sim, double* out, void* stream);
 int64_t lts_sim_coarse_step(const lts_sim* sim);
 void lts_sim_destroy(lts_sim* sim);
 
-/* Several independent simulations advanced together: every stage of every
- * substep is one persistent launch over the union of the sims' active tiles
- * (sims with fewer substeps idle in the rounds they do not use). */
+/* ---- batches: several simulations per launch (continuous batching) ---------------
+ * A batch advances up to `capacity` (<= 256) independent simulations of one
+ * equation, precision, tableau and mode together, by rounds.  In round r a sim
+ * that joined at round r0 runs its own substep j = (r - r0) mod 2^(lmax-lmin)
+ * (Alg. 2 schedule, fig. blk_loop, of its own mesh) of coarse step
+ * n0 + (r - r0) div 2^(lmax-lmin); every stage of a round is one persistent launch
+ * per tile side over the union of the active tiles of all attached sims (the
+ * sims' meshes, level ranges and sizes may differ).  Each sim's arithmetic is the
+ * one lts_advance performs: its results are bitwise those of running it alone.
+ * A batch is used from one host thread and one stream. */
+typedef struct {
+  int64_t round;             /* next round to run                                   */
+  int64_t rounds_to_drain;   /* rounds until every attached sim is done             */
+  int32_t attached, capacity;
+} lts_batch_info;
+
+lts_status lts_batch_create(int32_t equation, int32_t precision, int32_t tableau, int32_t mode,
+                            int32_t capacity, lts_batch** out);
+/* Attach a bound sim for n coarse steps (n 2^(lmax-lmin) rounds) starting at the
+ * next round.  While attached, the sim is driven only by the batch (lts_advance,
+ * lts_sim_bind and lts_mesh_set_tile of its mesh return LTS_EINVAL).  When its
+ * rounds are done it is released by itself and its coarse-step counter advanced.
+ * n = 0 attaches nothing.  LTS_EINVAL: batch full, mismatched equation /
+ * precision / tableau / device, or a mode that differs from the sim's history. */
+lts_status lts_batch_attach(lts_batch* batch, lts_sim* sim, int64_t n_coarse_steps);
+/* Release an attached sim early, at one of its coarse-step boundaries (else
+ * LTS_EINVAL); its counter advances by the coarse steps it completed. */
+lts_status lts_batch_detach(lts_batch* batch, lts_sim* sim, void* stream);
+/* Enqueue n rounds on `stream` (asynchronous; a table upload after attach or
+ * release goes through pinned memory and waits only for the previous upload). */
+lts_status lts_batch_run(lts_batch* batch, int64_t n_rounds, void* stream);
+lts_status lts_batch_query(const lts_batch* batch, lts_batch_info* info);
+/* Rounds the sim still takes part in (0 when it is not attached). */
+int64_t lts_sim_rounds_left(const lts_sim* sim);
+/* Waits for the batch's enqueued work, releases sims still attached (their
+ * counters are not advanced) and frees the batch. */
+void lts_batch_destroy(lts_batch* batch);
+
+/* All of sims[0..n) (n <= 256) advanced n_coarse_steps coarse steps in one batch
+ * (create, attach, run until drained, destroy). */
 lts_status lts_batch_advance(lts_sim* const* sims, int32_t n, int64_t n_coarse_steps,
                              int32_t mode, void* stream);
 

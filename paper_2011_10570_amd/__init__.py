@@ -18,7 +18,7 @@ from ._lib import (CRIT_ANNULUS, CRIT_BALL, EQ_MAXWELL, EQ_WAVE, FP32_RHS, FP64,
 
 __all__ = ["Mesh", "Sim", "build_mesh", "unzip", "rhs", "zip", "rk_stage", "fused_stage", "coefficients",
            "norms", "copy_probe", "LTSError", "MODE_LTS", "MODE_GTS", "EQ_WAVE", "EQ_MAXWELL", "FP64", "FP32_RHS",
-           "RK4", "SSPRK3"]
+           "RK4", "SSPRK3", "Batch", "batch_advance", "set_launch", "get_launch"]
 
 EQUATIONS = {"wave": EQ_WAVE, "maxwell": EQ_MAXWELL}
 TABLEAUS = {"rk4": RK4, "ssprk3": SSPRK3}
@@ -221,6 +221,17 @@ def norms(mesh: Mesh, a, b=None, nfields: int = 2, stream=None) -> dict:
     return {"l2": out[:nfields].copy(), "linf": out[nfields:2 * nfields].copy(), "nonfinite": int(out[-1])}
 
 
+def set_launch(threads: int, max_workgroups: int):
+    """Launch shape of every later fused launch (threads 256 or 512; persistent-grid cap)."""
+    check(lib().lts_set_launch(int(threads), int(max_workgroups)), "lts_set_launch")
+
+
+def get_launch() -> tuple:
+    t, w = C.c_int32(), C.c_int32()
+    check(lib().lts_get_launch(C.byref(t), C.byref(w)), "lts_get_launch")
+    return t.value, w.value
+
+
 def copy_probe(src, dst, nbytes: int, stream=None):
     check(lib().lts_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream_ptr(stream)), "lts_copy_probe")
 
@@ -284,3 +295,65 @@ class Sim:
     @property
     def coarse_step(self) -> int:
         return int(lib().lts_sim_coarse_step(self.h))
+
+    @property
+    def rounds_left(self) -> int:
+        """Rounds this sim still takes part in while attached to a Batch (else 0)."""
+        return int(lib().lts_sim_rounds_left(self.h))
+
+
+class Batch:
+    """Continuous batching of independent sims (one equation, precision, tableau
+    and mode): round r runs every attached sim's own substep; each stage of a
+    round is one launch per tile side over the union of their active tiles."""
+
+    def __init__(self, equation="wave", precision=FP64, tableau="rk4", mode: int = MODE_LTS, capacity: int = 64):
+        self.eq = EQUATIONS[equation] if isinstance(equation, str) else int(equation)
+        self.tab = TABLEAUS[tableau] if isinstance(tableau, str) else int(tableau)
+        h = C.c_void_p()
+        check(lib().lts_batch_create(self.eq, int(precision), self.tab, int(mode), int(capacity), C.byref(h)),
+              "lts_batch_create")
+        self.h = h
+        self._attached = {}   # id(sim) -> sim (keeps attached sims alive)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                lib().lts_batch_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def attach(self, sim: "Sim", n_coarse: int):
+        check(lib().lts_batch_attach(self.h, sim.h, int(n_coarse)), "lts_batch_attach")
+        if sim.rounds_left > 0:
+            self._attached[id(sim)] = sim
+
+    def detach(self, sim: "Sim", stream=None):
+        check(lib().lts_batch_detach(self.h, sim.h, _stream_ptr(stream)), "lts_batch_detach")
+        self._attached.pop(id(sim), None)
+
+    def run(self, n_rounds: int, stream=None) -> list:
+        """Enqueue n rounds; returns the sims that finished in them."""
+        check(lib().lts_batch_run(self.h, int(n_rounds), _stream_ptr(stream)), "lts_batch_run")
+        done = [s for s in self._attached.values() if s.rounds_left == 0]
+        for s in done:
+            del self._attached[id(s)]
+        return done
+
+    def info(self) -> dict:
+        i = _L.BatchInfo()
+        check(lib().lts_batch_query(self.h, C.byref(i)), "lts_batch_query")
+        return {"round": i.round, "rounds_to_drain": i.rounds_to_drain, "attached": i.attached,
+                "capacity": i.capacity}
+
+    def drain(self, stream=None) -> list:
+        return self.run(self.info()["rounds_to_drain"], stream)
+
+
+def batch_advance(sims: Sequence["Sim"], n_coarse: int, mode: int = MODE_LTS, stream=None):
+    """Advance every sim n_coarse coarse steps in one batch."""
+    arr = (C.c_void_p * len(sims))(*[s.h.value for s in sims])
+    check(lib().lts_batch_advance(arr, len(sims), int(n_coarse), int(mode), _stream_ptr(stream)),
+          "lts_batch_advance")

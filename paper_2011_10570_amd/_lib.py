@@ -40,7 +40,7 @@ class MeshInfo(C.Structure):
                 ("lmin", C.c_int32), ("lmax", C.c_int32), ("n_substeps", C.c_int32), ("tile", C.c_int32),
                 ("level_count", C.c_int64 * MAX_LEVEL), ("unzip_points", C.c_int64), ("grid_points", C.c_int64),
                 ("node_updates_lts", C.c_int64), ("node_updates_gts", C.c_int64), ("s_est", C.c_double),
-                ("s_max", C.c_double)]
+                ("s_max", C.c_double), ("table_bytes", C.c_int64)]
 
 
 class StageView(C.Structure):
@@ -54,6 +54,11 @@ class Position(C.Structure):
 
 class RhsParams(C.Structure):
     _fields_ = [("ko_sigma", C.c_double)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("round", C.c_int64), ("rounds_to_drain", C.c_int64), ("attached", C.c_int32),
+                ("capacity", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -85,6 +90,13 @@ PROTOTYPES = {
     "lts_sim_current": (C.c_int, [_P, _P, _P]),
     "lts_sim_coarse_step": (C.c_int64, [_P]),
     "lts_sim_destroy": (None, [_P]),
+    "lts_batch_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "lts_batch_attach": (C.c_int, [_P, _P, C.c_int64]),
+    "lts_batch_detach": (C.c_int, [_P, _P, _P]),
+    "lts_batch_run": (C.c_int, [_P, C.c_int64, _P]),
+    "lts_batch_query": (C.c_int, [_P, C.POINTER(BatchInfo)]),
+    "lts_sim_rounds_left": (C.c_int64, [_P]),
+    "lts_batch_destroy": (None, [_P]),
     "lts_batch_advance": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int64, C.c_int32, _P]),
     "lts_norms": (C.c_int, [_P, C.c_int32, _P, _P, _DP, _P]),
     "lts_copy_probe": (C.c_int, [_P, _P, C.c_size_t, _P]),

@@ -154,8 +154,8 @@ static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage,
   if (stage < 0 || stage >= p) return fail(LTS_EINVAL, "stage out of range");
   if (pos->mode != LTS_MODE_LTS && pos->mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
   if (pos->substep < 0 || pos->substep >= (1 << (m.lmax - m.lmin))) return fail(LTS_EINVAL, "substep out of range");
-  if ((int64_t)p * v->nfields * m.n() * 125 >= (1ll << 31))
-    return fail(LTS_EUNSUPPORTED, "stage arrays exceed 2^31 elements (32-bit offsets in the kernels)");
+  if ((int64_t)p * v->nfields * m.n() * 125 >= (1ll << 31) || m.n() * 125 * 8 >= (1ll << 32))
+    return fail(LTS_EUNSUPPORTED, "arrays too large for the kernels' 32-bit offsets");
   double w[64], a[16], b[4];
   coefficient_tables(v->tableau, w, a, b);
   std::memset(&sp, 0, sizeof(sp));
@@ -186,10 +186,8 @@ using namespace lts;
 
 static lts_status set_step(int64_t** slot, int64_t value, hipStream_t s) {
   if (!*slot) HIP_TRY(hipMalloc(slot, sizeof(int64_t)), "hipMalloc step");
-  // a kernel-argument write keeps the value with the enqueued work
-  int64_t v = value;
-  HIP_TRY(hipMemcpyAsync(*slot, &v, sizeof(int64_t), hipMemcpyHostToDevice, s), "set step");
-  HIP_TRY(hipStreamSynchronize(s), "sync step");
+  // a kernel-argument write keeps the value with the enqueued work (no sync)
+  HIP_TRY(launch_set_i64(*slot, value, s), "set step");
   return LTS_OK;
 }
 
@@ -270,6 +268,10 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   }
   info->unzip_points = up;
   info->grid_points = gp;
+  // device tables: tile records and slot tables of the block tiles (phase
+  // kernels) and of the fused tiles
+  info->table_bytes = 4 * (int64_t)(m.bt.tiles.size() + m.bt.slots.size() + m.ts[1].tiles.size() +
+                                    m.ts[1].slots.size() + m.ts[2].tiles.size() + m.ts[2].slots.size());
   info->node_updates_lts = wl;
   info->node_updates_gts = wg;
   // eq. invS with alpha_l = DG nodes at level lmax - l
@@ -345,8 +347,10 @@ lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile) {
   if (!mesh) return fail(LTS_EINVAL, "mesh is NULL");
   Mesh& m = mesh->m;
   if (tile == m.tile) return LTS_OK;
+  if (m.attached > 0) return fail(LTS_EINVAL, "a sim of this mesh is attached to a batch");
   lts_status st = build_tiles(m, tile);
   if (st != LTS_OK) return st;
+  m.tables_gen += 1;   // device tile tables move: captured graphs must be redone
   if (m.uploaded) {
     if ((st = upload_set(m.ts[1])) != LTS_OK) return st;
     if ((st = upload_set(m.ts[2])) != LTS_OK) return st;
@@ -444,11 +448,13 @@ lts_status lts_rk_stage(lts_mesh* mesh, const lts_stage_view* view, const double
 }
 
 static LaunchShape g_shape;  // defaults: 256 threads, grid cap 4096
+static int64_t g_shape_gen = 0;  // bumped by every change (captured graphs bake the shape in)
 
 lts_status lts_set_launch(int32_t threads, int32_t max_workgroups) {
   clear_error();
-  if (threads != 256 && threads != 512 && threads != 1024) return fail(LTS_EINVAL, "threads must be 256, 512 or 1024");
+  if (threads != 256 && threads != 512) return fail(LTS_EINVAL, "threads must be 256 or 512");
   if (max_workgroups < 8) return fail(LTS_EINVAL, "max_workgroups must be >= 8");
+  if (g_shape.threads != threads || g_shape.max_wg != max_workgroups) ++g_shape_gen;
   g_shape.threads = threads;
   g_shape.max_wg = max_workgroups;
   return LTS_OK;
@@ -510,16 +516,23 @@ struct lts_sim {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
-  int graph_tile[2] = {0, 0};
+  int64_t graph_tables[2] = {0, 0};  // mesh table generation of each captured graph
+  int64_t graph_gen[2] = {0, 0};   // launch-shape generation of each captured graph
   // unfused path: device block lists per substep class
   std::vector<ListDev> ulists;
   std::vector<void*> ualloc;
   double* d_pad = nullptr;
   void* d_kb = nullptr;
   double* d_coef = nullptr;
+  // continuous batching: the batch the sim is attached to, its round range
+  lts_batch* batch = nullptr;
+  int slot = -1;
+  int64_t r0 = 0, rounds = 0;
 };
 
 namespace {
+
+void release_slot(lts_batch* b, lts_sim* sim);
 
 void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams& sp) {
   const Mesh& m = sim->mesh->m;
@@ -595,8 +608,9 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
   if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
   const int p = tableau_stages(tableau);
   if (!p) return fail(LTS_EINVAL, "bad tableau");
-  if ((int64_t)p * (equation == LTS_EQ_WAVE ? 2 : 6) * mesh->m.n() * 125 >= (1ll << 31))
-    return fail(LTS_EUNSUPPORTED, "stage arrays exceed 2^31 elements (32-bit offsets in the kernels)");
+  if ((int64_t)p * (equation == LTS_EQ_WAVE ? 2 : 6) * mesh->m.n() * 125 >= (1ll << 31) ||
+      mesh->m.n() * 125 * 8 >= (1ll << 32))
+    return fail(LTS_EUNSUPPORTED, "arrays too large for the kernels' 32-bit offsets");
   lts_status st = ensure_device(mesh->m);
   if (st != LTS_OK) return st;
   lts_sim* sim = new (std::nothrow) lts_sim();
@@ -623,6 +637,7 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
 lts_status lts_sim_bind(lts_sim* sim, void* U, void* K) {
   clear_error();
   if (!sim || !U || !K) return fail(LTS_EINVAL, "NULL argument");
+  if (sim->batch) return fail(LTS_EINVAL, "sim is attached to a batch");
   sim->U = U;
   sim->K = K;
   sim->n = 0;
@@ -635,6 +650,7 @@ lts_status lts_sim_bind(lts_sim* sim, void* U, void* K) {
 lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t use_graph, void* stream) {
   clear_error();
   if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
+  if (sim->batch) return fail(LTS_EINVAL, "sim is attached to a batch");
   if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
   if (n_coarse_steps < 0) return fail(LTS_EINVAL, "n < 0");
   if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
@@ -652,7 +668,7 @@ lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32
     }
     return LTS_OK;
   }
-  if (sim->exec[mode] && sim->graph_tile[mode] != m.tile) {
+  if (sim->exec[mode] && (sim->graph_tables[mode] != m.tables_gen || sim->graph_gen[mode] != g_shape_gen)) {
     drop_graphs(sim);
   }
   if (!sim->exec[mode]) {
@@ -667,7 +683,8 @@ lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32
     if (e != hipSuccess) return hip_fail(e, "end capture");
     sim->graph[mode] = g;
     HIP_TRY(hipGraphInstantiate(&sim->exec[mode], g, nullptr, nullptr, 0), "graph instantiate");
-    sim->graph_tile[mode] = m.tile;
+    sim->graph_tables[mode] = m.tables_gen;
+    sim->graph_gen[mode] = g_shape_gen;
   }
   for (int64_t c = 0; c < n_coarse_steps; ++c) {
     HIP_TRY(hipGraphLaunch(sim->exec[mode], s), "graph launch");
@@ -679,6 +696,7 @@ lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32
 lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, void* stream) {
   clear_error();
   if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
+  if (sim->batch) return fail(LTS_EINVAL, "sim is attached to a batch");
   if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
   if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
     return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
@@ -776,6 +794,7 @@ int64_t lts_sim_coarse_step(const lts_sim* sim) { return sim ? sim->n : -1; }
 
 void lts_sim_destroy(lts_sim* sim) {
   if (!sim) return;
+  if (sim->batch) release_slot(sim->batch, sim);
   drop_graphs(sim);
   if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
   if (sim->d_step) (void)hipFree(sim->d_step);
@@ -789,12 +808,27 @@ void lts_sim_destroy(lts_sim* sim) {
 lts_status lts_batch_advance(lts_sim* const* sims, int32_t n, int64_t n_coarse_steps, int32_t mode, void* stream) {
   clear_error();
   if (!sims || n <= 0) return fail(LTS_EINVAL, "no sims");
-  // Sequential fallback-free form: every sim's coarse step is enqueued in turn on
-  // one stream (the persistent multi-mesh launch is built on top of this order).
-  for (int i = 0; i < n; ++i) {
-    lts_status st = lts_advance(sims[i], n_coarse_steps, mode, 0, stream);
-    if (st != LTS_OK) return st;
+  if (n > kMaxBatch) return fail(LTS_EINVAL, "more sims than a batch holds");
+  if (n_coarse_steps < 0) return fail(LTS_EINVAL, "n < 0");
+  for (int i = 0; i < n; ++i)
+    if (!sims[i]) return fail(LTS_EINVAL, "NULL sim");
+  lts_batch* b = nullptr;
+  lts_status st = lts_batch_create(sims[0]->eq, sims[0]->prec, sims[0]->tab, mode, n, &b);
+  if (st != LTS_OK) return st;
+  for (int i = 0; i < n && st == LTS_OK; ++i) st = lts_batch_attach(b, sims[i], n_coarse_steps);
+  if (st == LTS_OK) {
+    lts_batch_info info;
+    lts_batch_query(b, &info);
+    st = lts_batch_run(b, info.rounds_to_drain, stream);
   }
+  if (st != LTS_OK) {
+    std::string msg = g_err;
+    for (int i = 0; i < n; ++i)
+      if (sims[i]->batch == b) release_slot(b, sims[i]);
+    lts_batch_destroy(b);
+    return fail(st, msg);
+  }
+  lts_batch_destroy(b);
   return LTS_OK;
 }
 
@@ -849,6 +883,256 @@ lts_status lts_copy_probe(const void* src, void* dst, size_t nbytes, void* strea
   if (nbytes % 32) return fail(LTS_EINVAL, "nbytes must be a multiple of 32");
   HIP_TRY(launch_copy(src, dst, nbytes, (hipStream_t)stream), "copy launch");
   return LTS_OK;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------- batches
+// Continuous batching: a table of up to `cap` simulations (one equation,
+// precision, tableau and mode) advanced by rounds.  Round r runs, for every
+// attached simulation, its substep (r - r0) mod 2^(lmax-lmin); each stage of a
+// round is one persistent launch per tile side over the union of the active
+// tiles.  Simulations join and leave at round boundaries.
+struct lts_batch {
+  int eq = 0, prec = 0, tab = 0, mode = 0, F = 2, p = 4, cap = 0;
+  int device = -1;
+  double w[64], a[16], b[4];
+  std::vector<lts_sim*> sims;   // per slot; nullptr = free
+  std::vector<BatchSim> desc;   // host copy of the device table
+  BatchSim* d_desc = nullptr;
+  BatchSim* h_stage = nullptr;  // pinned staging buffer of table uploads
+  hipEvent_t staged = nullptr;  // the last upload has read h_stage
+  hipEvent_t done = nullptr;    // end of the last enqueued round
+  bool staged_rec = false, done_rec = false;
+  bool dirty = true;
+  int nused = 0;                // table entries [0, nused) are passed to the kernels
+  int64_t round = 0;            // next round to run
+};
+
+namespace {
+
+void release_slot(lts_batch* b, lts_sim* sim) {
+  const int k = sim->slot;
+  if (k >= 0 && k < (int)b->sims.size() && b->sims[k] == sim) {
+    b->sims[k] = nullptr;
+    b->desc[k].rounds = 0;
+    b->dirty = true;
+    sim->mesh->m.attached -= 1;
+  }
+  sim->batch = nullptr;
+  sim->slot = -1;
+  int n = (int)b->sims.size();
+  while (n > 0 && !b->sims[n - 1]) --n;
+  b->nused = n;
+}
+
+int64_t rounds_left(const lts_batch* b, const lts_sim* sim) { return sim->r0 + sim->rounds - b->round; }
+
+// stage parameters shared by the batch (arrays and position come from the table)
+void fill_batch_params(const lts_batch* b, int stage, StageParams& sp) {
+  std::memset(&sp, 0, sizeof(sp));
+  sp.F = b->F;
+  sp.p = b->p;
+  sp.stage = stage;
+  sp.mode = b->mode;
+  for (int c = 0; c < 4; ++c)
+    for (int i = 0; i < b->p; ++i) sp.w[c][i] = b->w[(c * b->p + stage) * b->p + i];
+  for (int i = 0; i < b->p; ++i) sp.b[i] = b->b[i];
+  set_kmask(sp);
+}
+
+lts_status upload_table(lts_batch* b, hipStream_t s) {
+  if (!b->dirty) return LTS_OK;
+  if (b->nused > 0) {
+    if (b->staged_rec) HIP_TRY(hipEventSynchronize(b->staged), "staging wait");
+    std::memcpy(b->h_stage, b->desc.data(), b->nused * sizeof(BatchSim));
+    HIP_TRY(hipMemcpyAsync(b->d_desc, b->h_stage, b->nused * sizeof(BatchSim), hipMemcpyHostToDevice, s),
+            "table upload");
+    HIP_TRY(hipEventRecord(b->staged, s), "event record");
+    b->staged_rec = true;
+  }
+  b->dirty = false;
+  return LTS_OK;
+}
+
+// the sim's coarse-step counter after `done` rounds of its batch run
+lts_status finish_rounds(lts_batch* b, lts_sim* sim, int64_t done, hipStream_t s) {
+  const int nsub = 1 << (sim->mesh->m.lmax - sim->mesh->m.lmin);
+  sim->n = b->desc[sim->slot].n0 + done / nsub;
+  HIP_TRY(launch_set_i64(sim->d_step, sim->n, s), "set step");
+  release_slot(b, sim);
+  return LTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lts_status lts_batch_create(int32_t equation, int32_t precision, int32_t tableau, int32_t mode, int32_t capacity,
+                            lts_batch** out) {
+  clear_error();
+  if (!out) return fail(LTS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
+  if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
+  const int p = tableau_stages(tableau);
+  if (!p) return fail(LTS_EINVAL, "bad tableau");
+  if (capacity < 1 || capacity > kMaxBatch) return fail(LTS_EINVAL, "capacity must be in [1, 256]");
+  lts_batch* b = new (std::nothrow) lts_batch();
+  if (!b) return fail(LTS_ENOMEM, "host allocation");
+  b->eq = equation;
+  b->prec = precision;
+  b->tab = tableau;
+  b->mode = mode;
+  b->F = equation == LTS_EQ_WAVE ? 2 : 6;
+  b->p = p;
+  b->cap = capacity;
+  coefficient_tables(tableau, b->w, b->a, b->b);
+  b->sims.assign(capacity, nullptr);
+  b->desc.assign(capacity, BatchSim{});
+  hipError_t e = hipGetDevice(&b->device);
+  if (e == hipSuccess) e = hipMalloc(&b->d_desc, capacity * sizeof(BatchSim));
+  if (e == hipSuccess) e = hipHostMalloc(&b->h_stage, capacity * sizeof(BatchSim), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    lts_batch_destroy(b);
+    return hip_fail(e, "batch create");
+  }
+  *out = b;
+  return LTS_OK;
+}
+
+lts_status lts_batch_attach(lts_batch* b, lts_sim* sim, int64_t n_coarse_steps) {
+  clear_error();
+  if (!b || !sim) return fail(LTS_EINVAL, "NULL argument");
+  if (!sim->U) return fail(LTS_EINVAL, "sim not bound");
+  if (sim->batch) return fail(LTS_EINVAL, "sim is already attached to a batch");
+  if (n_coarse_steps < 0) return fail(LTS_EINVAL, "n < 0");
+  if (sim->eq != b->eq || sim->prec != b->prec || sim->tab != b->tab)
+    return fail(LTS_EINVAL, "equation, precision and tableau must match the batch's");
+  if (sim->mode >= 0 && sim->mode != b->mode && sim->n > 0)
+    return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
+  Mesh& m = sim->mesh->m;
+  if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
+    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
+  if (m.device != b->device) return fail(LTS_EINVAL, "sim and batch are on different devices");
+  int k = 0;
+  while (k < b->cap && b->sims[k]) ++k;
+  if (k == b->cap) return fail(LTS_EINVAL, "batch is full");
+  const int dl = m.lmax - m.lmin;
+  BatchSim d;
+  std::memset(&d, 0, sizeof(d));
+  d.U = (double*)sim->U;
+  d.K = sim->K;
+  for (int t = 0; t < 2; ++t) {
+    d.tiles[t] = m.ts[t + 1].d_tiles;
+    d.slots[t] = m.ts[t + 1].d_slots;
+    for (int l = 0; l <= LTS_MAX_LEVEL; ++l) d.n_ge[t][l] = (int32_t)m.ts[t + 1].n_ge[l];
+  }
+  d.N = m.n();
+  d.r0 = b->round;
+  d.rounds = n_coarse_steps << dl;
+  d.n0 = sim->n;
+  d.sigma = sim->prm.ko_sigma;
+  d.lmin = m.lmin;
+  d.lmax = m.lmax;
+  sim->mode = b->mode;
+  if (d.rounds == 0) return LTS_OK;   // nothing to do: not attached
+  b->desc[k] = d;
+  b->sims[k] = sim;
+  b->nused = std::max(b->nused, k + 1);
+  b->dirty = true;
+  sim->batch = b;
+  sim->slot = k;
+  sim->r0 = d.r0;
+  sim->rounds = d.rounds;
+  m.attached += 1;
+  return LTS_OK;
+}
+
+lts_status lts_batch_detach(lts_batch* b, lts_sim* sim, void* stream) {
+  clear_error();
+  if (!b || !sim) return fail(LTS_EINVAL, "NULL argument");
+  if (sim->batch != b) return fail(LTS_EINVAL, "sim is not attached to this batch");
+  const int64_t done = b->round - sim->r0;
+  const int nsub = 1 << (sim->mesh->m.lmax - sim->mesh->m.lmin);
+  if (done % nsub) return fail(LTS_EINVAL, "sim is inside a coarse step (detach at a coarse-step boundary)");
+  return finish_rounds(b, sim, done, (hipStream_t)stream);
+}
+
+lts_status lts_batch_run(lts_batch* b, int64_t n_rounds, void* stream) {
+  clear_error();
+  if (!b) return fail(LTS_EINVAL, "batch is NULL");
+  if (n_rounds < 0) return fail(LTS_EINVAL, "n < 0");
+  hipStream_t s = (hipStream_t)stream;
+  const bool kf32 = b->prec == LTS_FP32_RHS;
+  for (int64_t k = 0; k < n_rounds; ++k) {
+    lts_status st = upload_table(b, s);
+    if (st != LTS_OK) return st;
+    const int64_t r = b->round;
+    int64_t total[2] = {0, 0};
+    for (int i = 0; i < b->nused; ++i) {
+      const lts_sim* sim = b->sims[i];
+      if (!sim) continue;
+      const BatchSim& d = b->desc[i];
+      const int64_t rr = r - d.r0;
+      if (rr < 0 || rr >= d.rounds) continue;
+      const int j = (int)(rr & ((1 << (d.lmax - d.lmin)) - 1));
+      const int lo = lowest_active_level(sim->mesh->m, b->mode, j);
+      total[0] += d.n_ge[0][lo];
+      total[1] += d.n_ge[1][lo];
+    }
+    for (int stg = 0; stg < b->p; ++stg) {
+      StageParams sp;
+      fill_batch_params(b, stg, sp);
+      for (int tt = 1; tt <= 2; ++tt)
+        HIP_TRY(launch_fused_batch(tt, b->eq, kf32, sp, b->d_desc, b->nused, r, total[tt - 1], g_shape, s),
+                "batch launch");
+    }
+    b->round += 1;
+    for (int i = 0; i < b->nused; ++i) {
+      lts_sim* sim = b->sims[i];
+      if (sim && rounds_left(b, sim) == 0 && (st = finish_rounds(b, sim, sim->rounds, s)) != LTS_OK) return st;
+    }
+  }
+  HIP_TRY(hipEventRecord(b->done, s), "event record");
+  b->done_rec = true;
+  return LTS_OK;
+}
+
+lts_status lts_batch_query(const lts_batch* b, lts_batch_info* info) {
+  clear_error();
+  if (!b || !info) return fail(LTS_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->round = b->round;
+  info->capacity = b->cap;
+  for (int i = 0; i < b->nused; ++i) {
+    const lts_sim* sim = b->sims[i];
+    if (!sim) continue;
+    info->attached += 1;
+    info->rounds_to_drain = std::max(info->rounds_to_drain, rounds_left(b, sim));
+  }
+  return LTS_OK;
+}
+
+int64_t lts_sim_rounds_left(const lts_sim* sim) {
+  if (!sim || !sim->batch) return 0;
+  return rounds_left(sim->batch, sim);
+}
+
+void lts_batch_destroy(lts_batch* b) {
+  if (!b) return;
+  if (b->done_rec) (void)hipEventSynchronize(b->done);
+  if (b->staged_rec) (void)hipEventSynchronize(b->staged);
+  for (int i = 0; i < (int)b->sims.size(); ++i)
+    if (b->sims[i]) release_slot(b, b->sims[i]);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  if (b->done) (void)hipEventDestroy(b->done);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
+  delete b;
 }
 
 }  // extern "C"

@@ -48,9 +48,9 @@ __constant__ double c_lag[9][5] = {
 // ------------------------------------------------------------------ schedule
 // Step index (mod 4) of a level-lev block at substep j of coarse step n:
 // LTS s = n 2^(lev-lmin) + (j >> (lmax-lev)), GTS s = n 2^(lmax-lmin) + j.
-__device__ __forceinline__ int step_mod4(int n4, int lev, const StageParams& sp) {
-  if (sp.mode == LTS_MODE_GTS) return ((n4 << (sp.lmax - sp.lmin)) + sp.j) & 3;
-  return ((n4 << (lev - sp.lmin)) + (sp.j >> (sp.lmax - lev))) & 3;
+__device__ __forceinline__ int step_mod4(int n4, int lev, int mode, int j, int lmin, int lmax) {
+  if (mode == LTS_MODE_GTS) return ((n4 << (lmax - lmin)) + j) & 3;
+  return ((n4 << (lev - lmin)) + (j >> (lmax - lev))) & 3;
 }
 
 struct TileCtx {
@@ -60,7 +60,7 @@ struct TileCtx {
   double dt, h;
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, const StageParams& sp, int n4) {
+__device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, int mode, int j, int lmin, int lmax, int n4) {
   TileCtx c;
   c.lev = t[TI_LEVEL];
   c.m = t[TI_M];
@@ -69,26 +69,42 @@ __device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, const StageParams&
   c.ox = off & 255;
   c.oy = (off >> 8) & 255;
   c.oz = (off >> 16) & 255;
-  const int s = step_mod4(n4, c.lev, sp);
+  const int s = step_mod4(n4, c.lev, mode, j, lmin, lmax);
   c.par_same = s & 1;
-  if (sp.mode == LTS_MODE_GTS) {
+  if (mode == LTS_MODE_GTS) {
     c.par_fine = c.par_coarse = s & 1;
     c.case_fine = c.case_coarse = 0;
-    c.dt = ldexp(1.0, -sp.lmax - 3);
+    c.dt = ldexp(1.0, -lmax - 3);
   } else {
     // a finer neighbour steps twice per receiver step: its step index is 2 s;
     // a coarser one once per two: its index is floor(s / 2) (Sec. 3.7.3).
     c.par_fine = 0;
     c.par_coarse = (s >> 1) & 1;
     c.case_fine = 1;                                   // (delta, rho) = (0, 1/2)
-    c.case_coarse = 2 + ((sp.j >> (sp.lmax - c.lev)) & 1);  // (0, 2) or (1, 2)
+    c.case_coarse = 2 + ((j >> (lmax - c.lev)) & 1);  // (0, 2) or (1, 2)
     c.dt = ldexp(1.0, -c.lev - 3);
   }
   c.h = ldexp(1.0, -c.lev - 1);
   return c;
 }
 
+__device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, const StageParams& sp, int n4) {
+  return tile_ctx(t, sp.mode, sp.j, sp.lmin, sp.lmax, n4);
+}
+
 // ------------------------------------------------------------------ gather
+// Element `idx` of a field array given by a uniform base pointer, addressed with a
+// 32-bit byte offset (lets the compiler use scalar-base + 32-bit-offset loads;
+// the host limits arrays to < 2^32 bytes per field).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t idx) {
+  return *(const T*)((const char*)base + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t idx, T v) {
+  *(T*)((char*)base + idx * (uint32_t)sizeof(T)) = v;
+}
+
 template <bool KF32>
 __device__ __forceinline__ double kload(const void* K, int64_t idx) {
   if constexpr (KF32) return (double)((const float*)K)[idx];
@@ -264,62 +280,90 @@ __device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, in
 }
 
 // ------------------------------------------------------------------ fused stage
-// Per tile:
+// LDS of one workgroup of the fused stage kernels.
+template <int TT, int F, bool KF32>
+struct FusedLds {
+  static constexpr int P = 4 * TT + 7;
+  static constexpr int P3 = P * P * P;
+  static constexpr int W = TT + 2;
+  static constexpr int NS = W * W * W;
+  static constexpr int NCB = 2;                        // coarser leaves prolongated per batch
+  using LT = typename std::conditional<KF32, float, double>::type;
+  LT Y[F * P3];
+  int32_t sl[2 * (2 * NS + 27)];  // slot table + work lists
+  uint8_t axl[3][P];              // per axis: slot position | node offset << 3
+  double wsh[16];
+  double lag[45];
+  double ref[F];
+  double Yc[NCB * F * 125];       // stage values of coarser source leaves
+  double T1[NCB * F * 225];       // ... interpolated along x: [x2 0..8][ky][kz]
+  double T2[NCB * F * 405];       // ... and along y: [x2][y2 0..8][kz]
+};
+
+// The arrays and schedule position of the simulation a tile belongs to.
+struct SimView {
+  const double* U;
+  double* Uw;
+  const void* K;
+  void* Kw;
+  int64_t N;
+  int lmin, lmax, j;
+  double sigma;
+};
+
+// One tile of the fused stage (Sec. 3.4, eqs. fc_1/fc_2, eq. rk_schemes):
 //   (0) the slot table and per-axis location tables (slot position and node
 //       offset of every padded coordinate, from the location rule) go to LDS;
 //   (1) every padded point whose slot is a same-level leaf (the tile's own
 //       octants included) or 8 finer leaves reads its stage value Y = U0 +
-//       dt sum w_i K_i directly; addresses are uniform base pointers plus 32-bit
-//       element offsets, and UB points per thread are loaded before use;
-//   (2) the distinct coarser source leaves are staged in LDS (NCB at a time) and
-//       the points of coarser slots interpolated from there;
-//   (3) the stencils run on the LDS tile; K_s (and the RK update at the last
-//       stage) are written to the tile's contiguous octants.
-template <int TT, int F, int EQ, bool KF32, int NT>
-__global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __restrict__ tiles,
-                                              const int32_t* __restrict__ slots, XcdRanges xr) {
+//       dt sum w_i K_i directly (uniform base pointers, 32-bit offsets, UB points
+//       per thread loaded before use);
+//   (2) the distinct coarser source leaves are staged in LDS (NCB at a time),
+//       prolongated separably, and the points of coarser slots finished along z;
+//   (3) the stencils run once per tile grid point; K_s (and the RK update at the
+//       last stage) are written to every DG node of the tile's contiguous octants.
+// sp holds the stage (weights, masks), v the tile's simulation.
+template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const StageParams& sp, const SimView& v,
+                                           int n4, const int32_t* __restrict__ tile,
+                                           const int32_t* __restrict__ slots) {
   constexpr int P = 4 * TT + 7;
   constexpr int P3 = P * P * P;
   constexpr int W = TT + 2;
   constexpr int NS = W * W * W;
-  constexpr int NCB = 2;                     // coarser leaves prolongated per batch
+  constexpr int NCB = FusedLds<TT, F, KF32>::NCB;
   constexpr int UB = 2;                      // points per thread loaded together
   using LT = typename std::conditional<KF32, float, double>::type;
   using KT = typename std::conditional<KF32, float, double>::type;
-  __shared__ LT Y[F * P3];
-  __shared__ int32_t sl[2 * (2 * NS + 27)];  // slot table + work lists
-  __shared__ int8_t axs[3][P], axn[3][P];    // per-axis slot position / node offset
-  __shared__ double wsh[16];
-  __shared__ double lag[45];
-  __shared__ double ref[F];
-  __shared__ double Yc[NCB * F * 125];       // stage values of coarser source leaves
-  __shared__ double T1[NCB * F * 225];       // ... interpolated along x: [x2 0..8][ky][kz]
-  __shared__ double T2[NCB * F * 405];       // ... and along y: [x2][y2 0..8][kz]
-
-  if (threadIdx.x < 16) wsh[threadIdx.x] = sp.w[threadIdx.x >> 2][threadIdx.x & 3];
-  if (threadIdx.x < 45) lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
-  const int n4 = (int)(*sp.step & 3);
-  // workgroups are dealt to the 8 XCDs round robin: XCD x walks its own
-  // contiguous (Morton-ordered, cost-balanced) range of tiles
-  const int nslot = gridDim.x >> 3;
-  const int xcd = blockIdx.x & 7;
-  const int sid = blockIdx.x >> 3;
-  const int fsz = (int)(sp.N * 125);          // elements per field (< 2^31)
+  auto& Y = L.Y;
+  auto& sl = L.sl;
+  auto& axl = L.axl;
+  auto& wsh = L.wsh;
+  auto& lag = L.lag;
+  auto& ref = L.ref;
+  auto& Yc = L.Yc;
+  auto& T1 = L.T1;
+  auto& T2 = L.T2;
+  const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
-  const KT* __restrict__ Kr = (const KT*)sp.K;
-  KT* __restrict__ Kw = (KT*)sp.Kw + (int64_t)sp.stage * F * fsz;
-  const int km0 = sp.kmask[0];
-
-  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot) {
-    const int32_t* t = tiles + 8 * (int64_t)ti;
-    const TileCtx c = tile_ctx(t, sp, n4);
+  const KT* __restrict__ Kr = (const KT*)v.K;
+  KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
+  // KS: stages read by same-level sources (the tableau row's non-zero pattern),
+  // a compile-time mask so the hot gather has no branches around its loads
+    // the tile record is uniform: keep it in scalar registers
+    int32_t trec[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) trec[k] = __builtin_amdgcn_readfirstlane(tile[k]);
+    const int32_t* t = trec;
+    const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, n4);
     const int first = t[TI_FIRST];
     const int counts = t[TI_COUNTS];
     const int ncl = (counts >> 24) & 255;
     const int nent = NS + (counts & 255) + ((counts >> 8) & 255) + ((counts >> 16) & 255) + ncl;
-    const double* __restrict__ Us = sp.U + (int64_t)c.par_same * F * fsz;
-    const double* __restrict__ Uf = sp.U + (int64_t)c.par_fine * F * fsz;
-    const double* __restrict__ Uc = sp.U + (int64_t)c.par_coarse * F * fsz;
+    const double* __restrict__ Us = v.U + (int64_t)c.par_same * F * fsz;
+    const double* __restrict__ Uf = v.U + (int64_t)c.par_fine * F * fsz;
+    const double* __restrict__ Uc = v.U + (int64_t)c.par_coarse * F * fsz;
+    double* __restrict__ Uw1 = v.Uw + (int64_t)(c.par_same ^ 1) * F * fsz;
     const int kmf = sp.kmask[c.case_fine], kmc = sp.kmask[c.case_coarse];
     const double* wf = wsh + 4 * c.case_fine;
     const double* wc = wsh + 4 * c.case_coarse;
@@ -330,8 +374,7 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
       const int o = d == 0 ? c.ox : (d == 1 ? c.oy : c.oz);
       const int Q = 4 * o + q - 3;
       const int cell = cell_of(Q, c.m);
-      axs[d][q] = (int8_t)(cell - o + 1);
-      axn[d][q] = (int8_t)(Q - 4 * cell);
+      axl[d][q] = (uint8_t)((cell - o + 1) | ((Q - 4 * cell) << 3));
     }
     if (threadIdx.x < F) {
       // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
@@ -350,10 +393,11 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
         pidx[u] = pi;
         if (pi >= P3) continue;
         const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
-        const int si = axs[0][qx] + W * (axs[1][qy] + W * axs[2][qz]);
-        nuv[u][0] = axn[0][qx];
-        nuv[u][1] = axn[1][qy];
-        nuv[u][2] = axn[2][qz];
+        const int ax = axl[0][qx], ay = axl[1][qy], az = axl[2][qz];
+        const int si = (ax & 7) + W * ((ay & 7) + W * (az & 7));
+        nuv[u][0] = ax >> 3;
+        nuv[u][1] = ay >> 3;
+        nuv[u][2] = az >> 3;
         kind[u] = sl[2 * si + 1] & 15;
         leaf[u] = sl[2 * si];
       }
@@ -361,28 +405,28 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         if (kind[u] != SRC_SAME) continue;
-        const int off = leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2];
+        const uint32_t off = (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]);
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          uu[u][f] = Us[f * fsz + off];
+          uu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if ((km0 >> i) & 1) kk[u][f][i] = (double)Kr[(i * F + f) * fsz + off];
+            if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
         }
       }
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         if (kind[u] == SRC_FINE) {
           const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
-          const int off = (leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
-                          10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz);
+          const uint32_t off = (uint32_t)((leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
+                                          10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz));
 #pragma unroll
           for (int f = 0; f < F; ++f) {
             double acc = 0.0;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-              if ((kmf >> i) & 1) acc = fma(wf[i], (double)Kr[(i * F + f) * fsz + off], acc);
-            Y[f * P3 + pidx[u]] = (LT)(Uf[f * fsz + off] + c.dt * acc - ref[f]);
+              if ((kmf >> i) & 1) acc = fma(wf[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
+            Y[f * P3 + pidx[u]] = (LT)(ld32(Uf + (uint32_t)(f * fsz), off) + c.dt * acc - ref[f]);
           }
         } else if (kind[u] == SRC_SAME) {
 #pragma unroll
@@ -390,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
             double acc = 0.0;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-              if ((km0 >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
+              if ((KS >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
             Y[f * P3 + pidx[u]] = (LT)(uu[u][f] + c.dt * acc - ref[f]);
           }
         }
@@ -405,12 +449,12 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
       for (int e = threadIdx.x; e < nb * F * 125; e += NT) {
         const int k = e / (F * 125), rem = e - k * (F * 125);
         const int f = rem / 125, n = rem - 125 * f;
-        const int off = lst_cleaf[2 * (b0 + k)] * 125 + n;
+        const uint32_t off = (uint32_t)(lst_cleaf[2 * (b0 + k)] * 125 + n);
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if ((kmc >> i) & 1) acc = fma(wc[i], (double)Kr[(i * F + f) * fsz + off], acc);
-        Yc[e] = Uc[f * fsz + off] + c.dt * acc;
+          if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
+        Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
       }
       __syncthreads();
       for (int e = threadIdx.x; e < nb * F * 225; e += NT) {
@@ -446,14 +490,15 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
       __syncthreads();
       for (int pi = threadIdx.x; pi < P3; pi += NT) {
         const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
-        const int si = axs[0][qx] + W * (axs[1][qy] + W * axs[2][qz]);
+        const int ax = axl[0][qx], ay = axl[1][qy], az = axl[2][qz];
+        const int si = (ax & 7) + W * ((ay & 7) + W * (az & 7));
         const int kb = sl[2 * si + 1];
         if ((kb & 15) != SRC_COARSE) continue;
         const int cidx = kb >> 8;
         if (cidx < b0 || cidx >= b0 + nb) continue;
         const int beta = (kb >> 4) & 7;
-        const int x2 = 4 * (beta & 1) + axn[0][qx], y2 = 4 * ((beta >> 1) & 1) + axn[1][qy],
-                  z2 = 4 * ((beta >> 2) & 1) + axn[2][qz];
+        const int x2 = 4 * (beta & 1) + (ax >> 3), y2 = 4 * ((beta >> 1) & 1) + (ay >> 3),
+                  z2 = 4 * ((beta >> 2) & 1) + (az >> 3);
 #pragma unroll
         for (int f = 0; f < F; ++f) {
           const double* t2 = T2 + ((cidx - b0) * F + f) * 405 + 45 * x2 + 5 * y2;   // [kz]
@@ -480,7 +525,7 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
       const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
       const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
       double k[F];
-      rhs_point<LT, EQ, F>(Y, P3, ci, P, P * P, (LT)c.h, (LT)sp.sigma, ref, k);
+      rhs_point<LT, EQ, F>(Y, P3, ci, P, P * P, (LT)c.h, (LT)v.sigma, ref, k);
 #pragma unroll
       for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
     }
@@ -490,14 +535,15 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
     // the last stage also forms the RK update
     constexpr int NN = TT * TT * TT * 125;
     for (int e = threadIdx.x; e < NN; e += NT) {
-      const int off = first * 125 + e;
+      const uint32_t off = (uint32_t)(first * 125 + e);
       double u0[F], kprev[F][4];
       if (last) {
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          u0[f] = Us[f * fsz + off];
+          u0[f] = ld32(Us + (uint32_t)(f * fsz), off);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) kprev[f][i] = (i < sp.stage) ? (double)Kr[(i * F + f) * fsz + off] : 0.0;
+          for (int i = 0; i < 4; ++i)
+            kprev[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
         }
       }
       const int o = e / 125, node = e - 125 * (e / 125);
@@ -508,10 +554,10 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
         double kv = R[f * G3 + gi];
         if constexpr (KF32) {
           const float kf = (float)kv;
-          Kw[f * fsz + off] = kf;
+          st32(Kw + (uint32_t)(f * fsz), off, kf);
           kv = (double)kf;
         } else {
-          Kw[f * fsz + off] = kv;
+          st32(Kw + (uint32_t)(f * fsz), off, kv);
         }
         if (last) {
           // compute_step_partial: U_new = U0 + dt sum_i b_i K_i into the other buffer
@@ -520,10 +566,83 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
           for (int i = 0; i < 4; ++i) {
             if (i < sp.p) acc = fma(sp.b[i], (i == sp.stage) ? kv : kprev[f][i], acc);
           }
-          sp.Uw[(int64_t)(c.par_same ^ 1) * F * fsz + f * fsz + off] = u0[f] + c.dt * acc;
+          st32(Uw1 + (uint32_t)(f * fsz), off, u0[f] + c.dt * acc);
         }
       }
     }
+}
+
+template <int TT, int F, bool KF32>
+__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const StageParams& sp) {
+  if (threadIdx.x < 16) L.wsh[threadIdx.x] = sp.w[threadIdx.x >> 2][threadIdx.x & 3];
+  if (threadIdx.x < 45) L.lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
+}
+
+// One mesh: workgroups are dealt to the 8 XCDs round robin; XCD x walks its own
+// contiguous (Morton-ordered, cost-balanced) range of tiles.
+template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+__global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __restrict__ tiles,
+                                              const int32_t* __restrict__ slots, XcdRanges xr) {
+  __shared__ FusedLds<TT, F, KF32> L;
+  fused_init(L, sp);
+  const int n4 = (int)(*sp.step & 3);
+  const int nslot = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int sid = blockIdx.x >> 3;
+  const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
+  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot)
+    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots);
+}
+
+// Several independent meshes advanced together (continuous batching): in round r
+// every simulation of the table is at its own substep (BatchSim); one launch per
+// stage covers the union of the active tiles of side TT of all of them, in table
+// order.  Union tile t belongs to the simulation whose cumulative-count range
+// holds it; the union is cut into 8 contiguous ranges, one per XCD.  The
+// arithmetic of every tile is that of the one-mesh kernel.
+template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+__global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims,
+                                                    int64_t r) {
+  __shared__ FusedLds<TT, F, KF32> L;
+  __shared__ int cum[kMaxBatch + 1];
+  fused_init(L, sp0);
+  for (int s = threadIdx.x; s < nsims; s += NT) {
+    const BatchSim& b = sims[s];
+    const int64_t rr = r - b.r0;
+    int cnt = 0;
+    if (rr >= 0 && rr < b.rounds) {
+      const int j = (int)(rr & ((1 << (b.lmax - b.lmin)) - 1));
+      const int lo = (sp0.mode == LTS_MODE_GTS || j == 0) ? b.lmin : b.lmax - __builtin_ctz(j);
+      cnt = b.n_ge[TT - 1][lo];
+    }
+    cum[s + 1] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cum[0] = 0;
+    for (int s = 0; s < nsims; ++s) cum[s + 1] += cum[s];
+  }
+  __syncthreads();
+  const int total = cum[nsims];
+  const int nslot = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int sid = blockIdx.x >> 3;
+  const int lo = (int)((int64_t)total * xcd / 8), hi = (int)((int64_t)total * (xcd + 1) / 8);
+  for (int ti = lo + sid; ti < hi; ti += nslot) {
+    int a = 0, z = nsims - 1;   // the simulation s with cum[s] <= ti < cum[s+1]
+    while (a < z) {
+      const int mid = (a + z + 1) >> 1;
+      if (cum[mid] <= ti) a = mid;
+      else z = mid - 1;
+    }
+    const int s = __builtin_amdgcn_readfirstlane(a);
+    const BatchSim& b = sims[s];
+    const int64_t rr = r - b.r0;
+    const int dl = b.lmax - b.lmin;
+    const SimView v{b.U, b.U, b.K, b.K, b.N, b.lmin, b.lmax, (int)(rr & ((1 << dl) - 1)), b.sigma};
+    const int n4 = (int)((b.n0 + (rr >> dl)) & 3);
+    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
+                                        b.slots[TT - 1]);
   }
 }
 
@@ -752,38 +871,92 @@ int fused_grid(int ntiles, int max_wg) {
 }
 }  // namespace
 
-template <int TT, int F, int EQ, bool KF32, int NT>
-static hipError_t launch_fused_nt(const StageParams& sp, const int32_t* tiles, const int32_t* slots,
-                                  const XcdRanges& xr, int max_wg, hipStream_t s) {
-  const int ntiles = xr.b[8];
-  hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32, NT>), dim3(fused_grid(ntiles, max_wg)), dim3(NT), 0, s, sp, tiles,
-                     slots, xr);
+namespace {
+struct OneArgs {
+  const int32_t* tiles;
+  const int32_t* slots;
+  XcdRanges xr;
+};
+struct BatchArgs {
+  const BatchSim* sims;
+  int nsims;
+  int64_t r, total;
+};
+}  // namespace
+
+// Launch of one template combination; the argument pack selects the kernel.
+template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+static hipError_t go(const StageParams& sp, const OneArgs& a, int max_wg, hipStream_t s) {
+  hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32, NT, KS>), dim3(fused_grid(a.xr.b[8], max_wg)), dim3(NT), 0, s, sp,
+                     a.tiles, a.slots, a.xr);
+  return hipGetLastError();
+}
+template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+static hipError_t go(const StageParams& sp, const BatchArgs& a, int max_wg, hipStream_t s) {
+  const int grid = fused_grid((int)std::min<int64_t>(a.total, 1 << 30), max_wg);
+  hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims, a.r);
   return hipGetLastError();
 }
 
-template <int TT, int F, int EQ, bool KF32>
-static hipError_t launch_fused_t(const StageParams& sp, const int32_t* tiles, const int32_t* slots,
-                                 const XcdRanges& xr, const LaunchShape& ls, hipStream_t s) {
-  switch (ls.threads) {
-    case 256: return launch_fused_nt<TT, F, EQ, KF32, 256>(sp, tiles, slots, xr, ls.max_wg, s);
-    case 512: return launch_fused_nt<TT, F, EQ, KF32, 512>(sp, tiles, slots, xr, ls.max_wg, s);
-    case 1024: return launch_fused_nt<TT, F, EQ, KF32, 1024>(sp, tiles, slots, xr, ls.max_wg, s);
+// The same-level stage mask and the workgroup size are template arguments: the
+// masks that occur for the built tableaus are RK4: none, {0}, {1}, {2} and
+// SSP-RK3: none, {0}, {0,1}.
+template <int TT, int F, int EQ, bool KF32, int NT, typename A>
+static hipError_t dispatch_ks(const StageParams& sp, const A& a, int max_wg, hipStream_t s) {
+  switch (sp.kmask[0]) {
+    case 0: return go<TT, F, EQ, KF32, NT, 0>(sp, a, max_wg, s);
+    case 1: return go<TT, F, EQ, KF32, NT, 1>(sp, a, max_wg, s);
+    case 2: return go<TT, F, EQ, KF32, NT, 2>(sp, a, max_wg, s);
+    case 3: return go<TT, F, EQ, KF32, NT, 3>(sp, a, max_wg, s);
+    case 4: return go<TT, F, EQ, KF32, NT, 4>(sp, a, max_wg, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int TT, int F, int EQ, bool KF32, typename A>
+static hipError_t dispatch_nt(const StageParams& sp, const A& a, const LaunchShape& ls, hipStream_t s) {
+  switch (ls.threads) {
+    case 256: return dispatch_ks<TT, F, EQ, KF32, 256>(sp, a, ls.max_wg, s);
+    case 512: return dispatch_ks<TT, F, EQ, KF32, 512>(sp, a, ls.max_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename A>
+static hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& sp, const A& a, const LaunchShape& ls,
+                                 hipStream_t s) {
+  if (eq == LTS_EQ_WAVE) {
+    if (tt == 1) return kf32 ? dispatch_nt<1, 2, LTS_EQ_WAVE, true>(sp, a, ls, s)
+                             : dispatch_nt<1, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);
+    if (tt == 2) return kf32 ? dispatch_nt<2, 2, LTS_EQ_WAVE, true>(sp, a, ls, s)
+                             : dispatch_nt<2, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);
+    return hipErrorInvalidValue;
+  }
+  if (tt != 1) return hipErrorInvalidValue;  // 6 FP64 fields of a side-2 tile exceed LDS
+  return kf32 ? dispatch_nt<1, 6, LTS_EQ_MAXWELL, true>(sp, a, ls, s)
+              : dispatch_nt<1, 6, LTS_EQ_MAXWELL, false>(sp, a, ls, s);
 }
 
 hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
                         const int32_t* slots, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s) {
   if (xr.b[8] <= 0) return hipSuccess;
-  if (eq == LTS_EQ_WAVE) {
-    if (tt == 1) return kf32 ? launch_fused_t<1, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, xr, ls, s)
-                             : launch_fused_t<1, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, xr, ls, s);
-    return kf32 ? launch_fused_t<2, 2, LTS_EQ_WAVE, true>(sp, tiles, slots, xr, ls, s)
-                : launch_fused_t<2, 2, LTS_EQ_WAVE, false>(sp, tiles, slots, xr, ls, s);
-  }
-  if (tt != 1) return hipErrorInvalidValue;  // 6 FP64 fields of a side-2 tile exceed LDS
-  return kf32 ? launch_fused_t<1, 6, LTS_EQ_MAXWELL, true>(sp, tiles, slots, xr, ls, s)
-              : launch_fused_t<1, 6, LTS_EQ_MAXWELL, false>(sp, tiles, slots, xr, ls, s);
+  return dispatch_fused(tt, eq, kf32, sp, OneArgs{tiles, slots, xr}, ls, s);
+}
+
+hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
+                              int64_t r, int64_t total, const LaunchShape& ls, hipStream_t s) {
+  if (total <= 0 || nsims <= 0) return hipSuccess;
+  if (nsims > kMaxBatch) return hipErrorInvalidValue;
+  return dispatch_fused(tt, eq, kf32, sp0, BatchArgs{sims, nsims, r, total}, ls, s);
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, ptr, value);
+  return hipGetLastError();
 }
 
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,

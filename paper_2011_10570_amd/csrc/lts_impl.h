@@ -45,6 +45,8 @@ struct Mesh {
   TileSet bt;                         // one tile per block (standalone kernels)
   bool uploaded = false;
   int device = -1;
+  int attached = 0;                   // sims of this mesh attached to batches
+  int64_t tables_gen = 0;             // bumped whenever the tile tables are rebuilt
   // scratch for the standalone kernels' block lists
   int32_t* d_list = nullptr;
   int64_t* d_off = nullptr;

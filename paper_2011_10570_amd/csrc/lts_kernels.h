@@ -21,7 +21,7 @@ struct StageParams {
   int kmask[4];         // per case: bit i set if w[case][i] != 0 (uniform branches)
 };
 
-// Launch shape of the fused kernel: threads per workgroup (256, 512, 1024) and the
+// Launch shape of the fused kernel: threads per workgroup (256 or 512) and the
 // cap on the persistent grid (workgroups, rounded to a multiple of 8 XCDs).
 struct LaunchShape {
   int threads = 256;
@@ -34,8 +34,29 @@ struct XcdRanges {
   int b[9];
 };
 
+// One simulation of a batched launch (continuous batching).  It joined at round
+// r0 from coarse step n0 and takes part in `rounds` rounds; round r is its
+// substep (r - r0) mod 2^(lmax-lmin) of coarse step n0 + (r - r0) div 2^(lmax-lmin).
+constexpr int kMaxBatch = 256;
+struct BatchSim {
+  double* U;                     // [2][F][N][125]
+  void* K;                       // [p][F][N][125]
+  const int32_t* tiles[2];       // tile records of side 1 and 2 (finest level first)
+  const int32_t* slots[2];
+  int64_t N;
+  int64_t r0, rounds, n0;
+  double sigma;
+  int32_t lmin, lmax;
+  int32_t n_ge[2][LTS_MAX_LEVEL + 1];  // tiles of side t+1 with level >= l
+};
+
 hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
                         const int32_t* slots, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s);
+// One stage of round r for the simulations sims[0..nsims) (device table); the
+// union of their active side-tt tiles is `total` (host-computed, sizes the grid).
+hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
+                              int64_t r, int64_t total, const LaunchShape& ls, hipStream_t s);
+hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s);
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
                         const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);
 hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,

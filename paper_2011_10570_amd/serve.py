@@ -1,0 +1,247 @@
+"""Serving loop: independent LTS simulations arriving over time, admitted by their
+device-memory footprint and advanced by continuous batching.
+
+Each request is one problem (mesh specification, equation, initial pulse, T as a
+number of coarse steps).  A request's mesh is built on the host (thread pool, the
+C++ builder releases the GIL) when it arrives; it is admitted, first come first
+served, once its footprint fits the device-memory budget:
+
+    footprint = N * 125 * F * (2 * 8 + p * sizeof(K)) + device tables
+
+(two U buffers in float64, p stage arrays).  Admitted sims are attached to the
+batch of their equation (wave or Maxwell: one fused kernel each) at the next
+round boundary; each round advances every attached sim by one of its own
+substeps; sims leave when they reach T and their memory returns to the budget.
+Time-to-T of a request = completion - arrival (host clock, taken when the round
+that finished it has completed on the device).
+
+    python -m paper_2011_10570_amd.serve [--requests N] [--budget-gib G]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import concurrent.futures as cf
+import json
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import FP32_RHS, FP64, MODE_LTS, NFIELDS, NSTAGES, EQUATIONS, TABLEAUS, Batch, Mesh, Sim
+
+
+@dataclass
+class Request:
+    rid: int
+    equation: str
+    mesh_spec: dict
+    centre: list
+    n_coarse: int
+    arrival: float = 0.0          # seconds after the start
+    sigma: float = 0.1
+    # filled by the server
+    mesh: Optional[Mesh] = None
+    sim: Optional[Sim] = None
+    footprint: int = 0
+    node_updates: int = 0
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    state: Optional[object] = None  # final state [F][N][125] when kept
+
+    @property
+    def time_to_t(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint_bytes(info: dict, equation: str, precision: int, tableau: str = "rk4") -> int:
+    F = NFIELDS[EQUATIONS[equation]]
+    p = NSTAGES[TABLEAUS[tableau]]
+    kb = 4 if precision == FP32_RHS else 8
+    return int(info["n_oct"]) * 125 * F * (2 * 8 + p * kb) + int(info["table_bytes"])
+
+
+def initial_state(mesh: Mesh, equation: str, centre, sigma: float, device):
+    """Gaussian pulse data of the request on `device`: [F][N][125]."""
+    from workloads import maxwell_gaussian_torch, wave_gaussian_torch
+    gen = wave_gaussian_torch if equation == "wave" else maxwell_gaussian_torch
+    return gen(mesh.leaves(), mesh.info()["L"], [centre], sigma=sigma, device=device)
+
+
+class Server:
+    def __init__(self, budget_bytes: int, precision: int = FP64, tableau: str = "rk4", mode: int = MODE_LTS,
+                 capacity: int = 64, tick_rounds: int = 4, keep_state: bool = False, device: str = "cuda",
+                 builders: int = 4, ko_sigma: float = 0.1):
+        self.budget = int(budget_bytes)
+        self.prec = precision
+        self.tab = tableau
+        self.mode = mode
+        self.tick_rounds = max(1, int(tick_rounds))
+        self.keep_state = keep_state
+        self.device = device
+        self.ko_sigma = ko_sigma
+        self.batches = {eq: Batch(eq, precision, tableau, mode, capacity) for eq in ("wave", "maxwell")}
+        self.capacity = capacity
+        self.pool = cf.ThreadPoolExecutor(max_workers=builders)
+
+    def _prepare(self, req: Request):
+        m = Mesh(req.mesh_spec)
+        m.set_tile(2 if req.equation == "wave" else 1)
+        return m
+
+    def _admit(self, req: Request, now: float):
+        req.sim = Sim(req.mesh, req.equation, self.prec, self.tab, ko_sigma=self.ko_sigma, device=self.device)
+        req.sim.set_state(initial_state(req.mesh, req.equation, req.centre, req.sigma, self.device))
+        self.batches[req.equation].attach(req.sim, req.n_coarse)
+        req.admitted = now
+
+    def run(self, requests: List[Request]) -> dict:
+        import torch
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending = collections.deque(reqs)
+        building = collections.deque()     # (req, future) in arrival order
+        resident: List[Request] = []
+        used = 0
+        peak = 0
+        nb_att = {eq: 0 for eq in self.batches}
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        while pending or building or resident:
+            now = clock()
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                building.append((r, self.pool.submit(self._prepare, r)))
+            # first come, first served: the head of the queue blocks later requests
+            while building and building[0][1].done():
+                r, fut = building[0]
+                if r.mesh is None:
+                    r.mesh = fut.result()
+                    info = r.mesh.info()
+                    r.footprint = footprint_bytes(info, r.equation, self.prec, self.tab)
+                    if r.footprint > self.budget:
+                        raise ValueError(f"request {r.rid} needs {r.footprint} B, more than the budget")
+                    r.node_updates = int(info["node_updates_lts" if self.mode == MODE_LTS
+                                              else "node_updates_gts"]) * r.n_coarse
+                if used + r.footprint > self.budget or nb_att[r.equation] >= self.capacity:
+                    break
+                building.popleft()
+                self._admit(r, clock())
+                nb_att[r.equation] += 1
+                used += r.footprint
+                peak = max(peak, used)
+                resident.append(r)
+            if not resident:
+                wait = (pending[0].arrival - clock()) if pending else 0.0
+                time.sleep(min(max(wait, 0.0), 0.01) if pending else 0.001)
+                continue
+            k = min(self.tick_rounds, min(r.sim.rounds_left for r in resident))
+            done = []
+            for eq, b in self.batches.items():
+                if nb_att[eq]:
+                    done += b.run(k)
+            torch.cuda.current_stream().synchronize()
+            now = clock()
+            fin = {id(s) for s in done}
+            keep = []
+            for r in resident:
+                if id(r.sim) in fin:
+                    r.finished = now
+                    if self.keep_state:
+                        r.state = r.sim.current()
+                    used -= r.footprint
+                    nb_att[r.equation] -= 1
+                    r.sim = None
+                    r.mesh = None
+                else:
+                    keep.append(r)
+            resident = keep
+        wall = clock()
+        tt = np.array([r.time_to_t for r in reqs])
+        total = sum(r.node_updates for r in reqs)
+        return {"requests": len(reqs), "wall_s": wall, "node_updates": total,
+                "node_updates_per_s": total / wall if wall > 0 else float("nan"),
+                "p50_time_to_t_s": float(np.percentile(tt, 50)), "p99_time_to_t_s": float(np.percentile(tt, 99)),
+                "mean_queue_s": float(np.mean([r.admitted - r.arrival for r in reqs])),
+                "peak_resident_bytes": peak, "budget_bytes": self.budget,
+                "wave": sum(r.equation == "wave" for r in reqs), "maxwell": sum(r.equation == "maxwell" for r in reqs)}
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+
+def requests_from_config(n: Optional[int] = None, rate: Optional[float] = None) -> List[Request]:
+    """The stored serving workload; arrival gaps (unit-rate exponential draws)
+    divided by `rate` requests/s (None: everything arrives at t = 0)."""
+    from workloads import config
+    cfg = config("serve")
+    out = []
+    t = 0.0
+    for i, q in enumerate(cfg["requests"][:n]):
+        if rate:
+            t += q["gap"] / rate
+        out.append(Request(i, q["equation"], q["mesh"], q["centre"], cfg["n_coarse"], arrival=t, sigma=cfg["sigma"]))
+    return out
+
+
+def batch_throughput(problems: list, n_coarse: int = 1, precision: int = FP64, device: str = "cuda",
+                     mode: int = MODE_LTS) -> dict:
+    """Wave problems advanced together in one batch from a Gaussian pulse: raw
+    node-updates per second over the wall time until all reach T (setup excluded)."""
+    import torch
+    from workloads import wave_gaussian_torch
+    sims = []
+    work = 0
+    for p in problems:
+        m = Mesh(p["mesh"])
+        s = Sim(m, "wave", precision, "rk4", ko_sigma=0.1, device=device)
+        c = p["mesh"]["criteria"][0]["center"]
+        s.set_state(wave_gaussian_torch(m.leaves(), m.info()["L"], [c], sigma=0.1, device=device))
+        info = m.info()
+        work += info["node_updates_lts" if mode == MODE_LTS else "node_updates_gts"] * n_coarse
+        sims.append(s)
+    b = Batch("wave", precision, "rk4", mode, capacity=max(1, len(sims)))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for s in sims:
+        b.attach(s, n_coarse)
+    b.drain()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    return {"problems": len(sims), "node_updates": work, "wall_s": wall, "node_updates_per_s": work / wall}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--requests", type=int, default=None, help="first N stored requests (default all)")
+    ap.add_argument("--budget-gib", type=float, default=None, help="device memory budget (default half free)")
+    ap.add_argument("--capacity", type=float, default=None,
+                    help="node-updates/s used to set the arrival rate (default: measured on the batch workload)")
+    ap.add_argument("--tick-rounds", type=int, default=4)
+    args = ap.parse_args(argv)
+    import torch
+    from workloads import config
+    torch.cuda.init()
+    budget = int(args.budget_gib * 2 ** 30) if args.budget_gib else int(torch.cuda.mem_get_info()[0] * 0.5)
+    cap = args.capacity
+    if cap is None:
+        cap = batch_throughput(config("batch")["problems"], 1)["node_updates_per_s"]
+    cfg = config("serve")
+    reqs = requests_from_config(args.requests)
+    # mean work per request from the stored leaf counts (work ~ leaves, per coarse step)
+    srv = Server(budget, tick_rounds=args.tick_rounds)
+    # arrival rate rho * capacity / mean work; work known after the meshes are built
+    work = []
+    for r in reqs:
+        m = Mesh(r.mesh_spec)
+        work.append(m.info()["node_updates_lts"] * r.n_coarse)
+    rate = cfg["rho"] * cap / float(np.mean(work))
+    reqs = requests_from_config(args.requests, rate)
+    stats = srv.run(reqs)
+    srv.close()
+    stats.update({"rho": cfg["rho"], "capacity_node_updates_per_s": cap, "arrival_rate_per_s": rate})
+    print(json.dumps(stats))
+
+
+if __name__ == "__main__":
+    main()

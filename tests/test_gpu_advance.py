@@ -139,3 +139,25 @@ def test_fp32_rhs_error_stated(c1, c1_oracle):
         e = np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()
         print(f"fp32-rhs field {f}: max rel err {e:.3e}")
         assert e < 1e-4
+
+
+def test_graph_recaptured_after_table_and_shape_changes(c1):
+    """A captured coarse step bakes in device table addresses and the launch
+    shape: rebuilding the tile tables (set_tile away and back) or changing the
+    launch shape between replays must not replay a stale graph."""
+    om, gm, U0 = c1
+    gm.set_tile(2)
+    sim = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=0.1, device=DEV)
+    sim.set_state(U0)
+    sim.advance(1, P.MODE_LTS, graph=True)
+    gm.set_tile(1)
+    gm.set_tile(2)
+    sim.advance(1, P.MODE_LTS, graph=True)
+    old = P.get_launch()
+    try:
+        P.set_launch(512, 1024)
+        sim.advance(1, P.MODE_LTS, graph=True)
+    finally:
+        P.set_launch(*old)
+    want = _run_gpu(gm, U0, 3, P.MODE_LTS, graph=False)
+    assert np.array_equal(sim.current().cpu().numpy(), want)

@@ -138,3 +138,18 @@ def test_tiles_cover_blocks():
         assert (covered == 1).all()
         # finest level first
         assert (np.diff(tiles[tiles[:, 4] == 1][:, 2]) <= 0).all()
+
+
+def test_batch_arguments_checked_before_device_use():
+    """lts_batch_create rejects bad arguments with LTS_EINVAL without a device."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    for args in ((7, P.FP64, P.RK4, P.MODE_LTS, 4), (P.EQ_WAVE, 9, P.RK4, P.MODE_LTS, 4),
+                 (P.EQ_WAVE, P.FP64, 9, P.MODE_LTS, 4), (P.EQ_WAVE, P.FP64, P.RK4, 5, 4),
+                 (P.EQ_WAVE, P.FP64, P.RK4, P.MODE_LTS, 0), (P.EQ_WAVE, P.FP64, P.RK4, P.MODE_LTS, 257)):
+        assert L.lts_batch_create(*args, ctypes.byref(h)) == _lib.EINVAL
+        assert not h.value
+    assert L.lts_batch_attach(None, None, 1) == _lib.EINVAL
+    assert L.lts_batch_run(None, 1, None) == _lib.EINVAL
+    assert L.lts_sim_rounds_left(None) == 0
+    L.lts_batch_destroy(None)

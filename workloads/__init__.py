@@ -135,9 +135,8 @@ def config_names() -> List[str]:
     return list(_load_specs().keys())
 
 
-def wave_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1.0, device="cuda"):
-    """Same data as wave_gaussian, evaluated with torch on `device` (large meshes).
-    leaves: int [N, 4] (anchor x, y, z, level).  Returns [2, N, 125] float64."""
+def _nodes_torch(leaves: np.ndarray, L: int, device):
+    """Physical coordinates [N, 125, 3] of every DG node (torch, float64)."""
     import torch
     lv = torch.as_tensor(np.asarray(leaves), dtype=torch.int64, device=device)
     s = torch.bitwise_left_shift(torch.ones_like(lv[:, 3]), L - lv[:, 3]).to(torch.float64)
@@ -145,7 +144,14 @@ def wave_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1
     k_, j_, i_ = torch.meshgrid(i, i, i, indexing="ij")
     loc = torch.stack([i_, j_, k_], -1).reshape(125, 3)
     X = 4.0 * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]       # [N,125,3]
-    x = -1.0 + 2.0 * X / float(4 * (1 << L))
+    return -1.0 + 2.0 * X / float(4 * (1 << L))
+
+
+def wave_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1.0, device="cuda"):
+    """Same data as wave_gaussian, evaluated with torch on `device` (large meshes).
+    leaves: int [N, 4] (anchor x, y, z, level).  Returns [2, N, 125] float64."""
+    import torch
+    x = _nodes_torch(leaves, L, device)
     u = torch.zeros(x.shape[:2], dtype=torch.float64, device=device)
     ims = torch.as_tensor(IMAGES, device=device)
     for cc in centres_nu:
@@ -154,3 +160,21 @@ def wave_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1
             d = x - (c + im)
             u += amp * torch.exp(-(d * d).sum(-1) / (2.0 * sigma * sigma))
     return torch.stack([u, torch.zeros_like(u)])
+
+
+def maxwell_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1.0, device="cuda"):
+    """Same data as maxwell_gaussian with torch: [6, N, 125] float64."""
+    import torch
+    x = _nodes_torch(leaves, L, device)
+    ex = torch.zeros(x.shape[:2], dtype=torch.float64, device=device)
+    ey = torch.zeros_like(ex)
+    ims = torch.as_tensor(IMAGES, device=device)
+    for cc in centres_nu:
+        c = torch.as_tensor(centre_physical(cc, L), device=device)
+        for im in ims:
+            d = x - (c + im)
+            g = amp * torch.exp(-(d * d).sum(-1) / (2.0 * sigma * sigma))
+            ex += -d[..., 1] / (sigma * sigma) * g
+            ey += d[..., 0] / (sigma * sigma) * g
+    z = torch.zeros_like(ex)
+    return torch.stack([ex, ey, z, z.clone(), z.clone(), z.clone()])

@@ -14,6 +14,14 @@ the paper's Gaussian-pulse workloads, Sec. 4.2 and 4.5):
   small     levels 2-3 ball, a few hundred leaves (fast tests).
   batch_i   64 problems of 1k-50k leaves (log-uniform target from seed), levels
             2..L_i, nested balls.
+  serve     32 requests for the serving loop: leaf targets log-uniform in
+            [2k, 200k], wave or Maxwell with probability 1/2, nested balls;
+            unit-rate exponential inter-arrival gaps and a load factor
+            rho ~ U(0.5, 0.9) (the loop scales gaps by the measured capacity).
+
+Usage: ``python -m workloads.calibrate [--base] [--batch] [--serve]`` recomputes
+the named groups (all of them when the file does not exist yet) and keeps the
+others as stored.
 """
 from __future__ import annotations
 
@@ -110,6 +118,43 @@ def calib_c2(target=200_000):
     return best
 
 
+def ball_problem(tgt, centre_seed, iters=18):
+    """Nested-ball mesh (levels 2..L) whose leaf count is closest to tgt."""
+    L = 4
+    while L < 8 and 8 ** L < 2 * tgt:
+        L += 1
+    c = centre_from_seed(centre_seed, L)
+    n_u = 4 * (1 << L)
+    best = None
+    lo, hi = 0.02, 1.2
+    for _ in range(iters):
+        r0 = 0.5 * (lo + hi)
+        radii = [int(round(r0 * (1.0 + 0.6 * (L - 1 - lev)) * n_u / 2)) for lev in range(2, L)]
+        spec = ball_spec(2, L, c, radii)
+        n = count(spec)
+        if best is None or abs(n - tgt) < abs(best[0] - tgt):
+            best = (n, spec)
+        if abs(n - tgt) < 0.02 * tgt:
+            break
+        lo, hi = (r0, hi) if n < tgt else (lo, r0)
+    return best, c
+
+
+def serve_specs(n_req=32, seed=4321):
+    rng = np.random.default_rng(seed)
+    targets = np.round(np.exp(rng.uniform(math.log(2e3), math.log(2e5), size=n_req))).astype(int)
+    eqs = np.where(rng.uniform(size=n_req) < 0.5, "wave", "maxwell")
+    gaps = rng.exponential(1.0, size=n_req)
+    rho = float(rng.uniform(0.5, 0.9))
+    out = []
+    for i, tgt in enumerate(targets):
+        (n, spec), c = ball_problem(int(tgt), 500 + i, iters=14)
+        out.append({"target": int(tgt), "leaves": int(n), "mesh": spec, "equation": str(eqs[i]),
+                    "centre": c, "gap": float(gaps[i])})
+        print(f"  serve {i}: {eqs[i]} target={tgt} leaves={n}", flush=True)
+    return {"requests": out, "rho": rho, "sigma": 0.1, "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 8}
+
+
 def batch_specs(n_prob=64, seed=1234):
     rng = np.random.default_rng(seed)
     targets = np.round(np.exp(rng.uniform(math.log(1e3), math.log(5e4), size=n_prob))).astype(int)
@@ -137,30 +182,28 @@ def batch_specs(n_prob=64, seed=1234):
 
 
 def main():
-    specs = {}
-    n, spec = calib_c1()
-    print("c1 leaves", n)
-    specs["wave_c1"] = {"mesh": spec, "equation": "wave", "sigma": 0.1, "pulses": [centre_from_seed(0, 4)],
-                        "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 8, "leaves": n}
-    small = ball_spec(2, 3, centre_from_seed(0, 3), [6])
-    assert count(small, (2, 3)) > 0
-    specs["small"] = {"mesh": small, "equation": "wave", "sigma": 0.1, "pulses": [centre_from_seed(0, 3)],
-                      "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 2, "leaves": count(small)}
-    n2, spec2, eps = calib_c2()
-    print("c2 leaves", n2, "eps", eps)
-    specs["wave_c2"] = {"mesh": spec2, "equation": "wave", "sigma": 0.1,
-                        "pulses": [c["center"] for c in spec2["criteria"]], "eps": eps,
-                        "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 8, "leaves": n2}
-    if "--batch" in sys.argv:
+    path = os.path.join(HERE, "specs.json")
+    specs = json.load(open(path)) if os.path.exists(path) else {}
+    if "--base" in sys.argv or "wave_c2" not in specs:
+        n, spec = calib_c1()
+        print("c1 leaves", n)
+        specs["wave_c1"] = {"mesh": spec, "equation": "wave", "sigma": 0.1, "pulses": [centre_from_seed(0, 4)],
+                            "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 8, "leaves": n}
+        small = ball_spec(2, 3, centre_from_seed(0, 3), [6])
+        assert count(small, (2, 3)) > 0
+        specs["small"] = {"mesh": small, "equation": "wave", "sigma": 0.1, "pulses": [centre_from_seed(0, 3)],
+                          "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 2, "leaves": count(small)}
+        n2, spec2, eps = calib_c2()
+        print("c2 leaves", n2, "eps", eps)
+        specs["wave_c2"] = {"mesh": spec2, "equation": "wave", "sigma": 0.1,
+                            "pulses": [c["center"] for c in spec2["criteria"]], "eps": eps,
+                            "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": 8, "leaves": n2}
+    if "--batch" in sys.argv or "batch" not in specs:
         specs["batch"] = {"problems": batch_specs(), "equation": "wave", "sigma": 0.1, "ko_sigma": 0.1,
                           "tableau": "rk4", "n_coarse": 8}
-    else:
-        old = os.path.join(HERE, "specs.json")
-        if os.path.exists(old):
-            prev = json.load(open(old))
-            if "batch" in prev:
-                specs["batch"] = prev["batch"]
-    with open(os.path.join(HERE, "specs.json"), "w") as f:
+    if "--serve" in sys.argv or "serve" not in specs:
+        specs["serve"] = serve_specs()
+    with open(path, "w") as f:
         json.dump(specs, f, indent=1)
 
 
