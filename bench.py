@@ -19,7 +19,15 @@ Reported (one JSON line):
                  for LTS, GTS and FP32-RHS, and FP32-RHS vs FP64;
   roofline       fused stage kernel: algorithmic HBM bytes (224 B per FP64 LTS
                  node-update) / measured kernel time, against 8 TB/s;
-  cpu_baseline   the FP64 oracle on a bounded sample of the same workload.
+  cpu_baseline   the FP64 oracle on a bounded sample of the same workload;
+  batch          64 independent wave problems (1k-50k leaves, levels 2..4-8)
+                 advanced to T together by continuous batching: raw
+                 node-updates/s until all reach T (--no-batch skips it);
+  serve          with --serve: the Poisson-arrival wave/Maxwell serving loop
+                 (throughput, p50/p99 time-to-T).
+
+    python bench.py --copy-probe-mib N   only times the device copy probe (the
+                                         known-size kernel that scales counters)
 """
 from __future__ import annotations
 
@@ -46,9 +54,48 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--tile", type=int, default=0, help="fused tile side (0: autotuned)")
+    ap.add_argument("--tile", type=int, default=0, help="fused tile side (0: the mesh default, 2)")
+    ap.add_argument("--tune", action="store_true", help="autotune tile side and launch shape first")
     ap.add_argument("--only", default="", help="comma list of legs: lts,gts,fp32")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
+    ap.add_argument("--serve", action="store_true", help="also run the serving loop")
+    ap.add_argument("--copy-probe-mib", type=int, default=0, help="only time a copy of this many MiB")
     return ap.parse_args()
+
+
+def copy_probe_gbs(P, torch, mib: int = 2048, reps: int = 5) -> float:
+    """Device-to-device copy through the library's copy kernel: (read + write) GB/s."""
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    P.copy_probe(a, b, n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.copy_probe(a, b, n)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+
+def stored_traffic():
+    """HBM traffic per fused launch from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_fused_wave_c2_counters.md")
+    src = os.path.join(ROOT, "paper_2011_10570_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernels_hip_sha256:\s*([0-9a-f]{64})", txt)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
+        return None
+    return float(t.group(1))
 
 
 # algorithmic passes over the DG arrays per stage (per field): read U0 and the
@@ -166,6 +213,10 @@ def main():
     from workloads import config, mesh_spec, wave_gaussian_torch
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        print(json.dumps({"copy_probe_mib": args.copy_probe_mib,
+                          "gbs": copy_probe_gbs(P, torch, args.copy_probe_mib)}))
+        return
     cfg = config(WORKLOAD)
     spec = mesh_spec(WORKLOAD)
     gm = P.build_mesh(spec)
@@ -175,6 +226,12 @@ def main():
     leaves = gm.leaves()
     U0 = wave_gaussian_torch(leaves, info["L"], cfg["pulses"], sigma=cfg["sigma"], device="cuda:0")
     legs = set(args.only.split(",")) if args.only else {"lts", "gts", "fp32"}
+    tuned = None
+    if args.tune:
+        from paper_2011_10570_amd import tune
+        tuned = tune.tune(gm, U0, reps=1)
+        print(f"[bench] tuned: {tuned['best']} {tuned['ms']:.2f} ms", file=sys.stderr, flush=True)
+        info = gm.info()
 
     w_lts = info["node_updates_lts"]       # DG node-updates per coarse step (eq. w_nuts)
     w_gts = info["node_updates_gts"]       # (eq. w_uts)
@@ -238,11 +295,27 @@ def main():
         assert alg == 224 * w_lts
         t_kernel = lts["event_s"] / args.steps
         achieved = alg / t_kernel / 1e9
+        cp = copy_probe_gbs(P, torch)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(),
                 "kernel": "k_fused (FP64 wave, tile sides 1 and 2)",
                 "algorithmic_bytes_per_launch": round(alg / launches), "launches_per_step": launches,
-                "avg_launch_us": round(1e6 * t_kernel / launches, 2)}
+                "avg_launch_us": round(1e6 * t_kernel / launches, 2),
+                "copy_probe_gbs": round(cp, 1), "frac_of_copy": round(achieved / cp, 4)}
+
+    batch = None
+    if not args.no_batch:
+        from paper_2011_10570_amd import serve
+        print("[bench] batch: 64 problems to T...", file=sys.stderr, flush=True)
+        bc = config("batch")
+        batch = serve.batch_throughput(bc["problems"], bc["n_coarse"])
+        print(f"[bench] batch: {batch['node_updates_per_s']:.4e} node-updates/s", file=sys.stderr, flush=True)
+    served = None
+    if args.serve:
+        from paper_2011_10570_amd import serve
+        print("[bench] serving loop...", file=sys.stderr, flush=True)
+        cap = batch["node_updates_per_s"] if batch else None
+        served = serve.run_config(capacity=cap, verbose=True)
 
     cpu = None
     if not args.no_cpu:
@@ -282,6 +355,12 @@ def main():
         out["fp32_rhs"] = {"rate": res["fp32"]["rate"], "speedup_over_fp64": lts["wall_s"] / res["fp32"]["wall_s"]}
     if acc:
         out["accuracy"] = acc
+    if batch:
+        out["batch"] = batch
+    if served:
+        out["serve"] = served
+    if tuned:
+        out["tuned"] = {"best": tuned["best"], "ms": tuned["ms"]}
     print(json.dumps(out))
 
 

@@ -270,8 +270,12 @@ lts_status lts_batch_attach(lts_batch* batch, lts_sim* sim, int64_t n_coarse_ste
  * LTS_EINVAL); its counter advances by the coarse steps it completed. */
 lts_status lts_batch_detach(lts_batch* batch, lts_sim* sim, void* stream);
 /* Enqueue n rounds on `stream` (asynchronous; a table upload after attach or
- * release goes through pinned memory and waits only for the previous upload). */
-lts_status lts_batch_run(lts_batch* batch, int64_t n_rounds, void* stream);
+ * early release goes through pinned memory and waits only for the previous
+ * upload).  use_graph != 0 captures one round (p stages x 2 tile sides + the
+ * device round counter) as a hipGraph and replays it; the capture is redone when
+ * a sim joins or leaves early or the launch shape changes (sims that reach T
+ * keep it valid: they are inactive in later rounds). */
+lts_status lts_batch_run(lts_batch* batch, int64_t n_rounds, int32_t use_graph, void* stream);
 lts_status lts_batch_query(const lts_batch* batch, lts_batch_info* info);
 /* Rounds the sim still takes part in (0 when it is not attached). */
 int64_t lts_sim_rounds_left(const lts_sim* sim);
@@ -280,7 +284,7 @@ int64_t lts_sim_rounds_left(const lts_sim* sim);
 void lts_batch_destroy(lts_batch* batch);
 
 /* All of sims[0..n) (n <= 256) advanced n_coarse_steps coarse steps in one batch
- * (create, attach, run until drained, destroy). */
+ * (create, attach, run graph-captured rounds until drained, destroy). */
 lts_status lts_batch_advance(lts_sim* const* sims, int32_t n, int64_t n_coarse_steps,
                              int32_t mode, void* stream);
 

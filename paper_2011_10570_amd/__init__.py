@@ -334,9 +334,10 @@ class Batch:
         check(lib().lts_batch_detach(self.h, sim.h, _stream_ptr(stream)), "lts_batch_detach")
         self._attached.pop(id(sim), None)
 
-    def run(self, n_rounds: int, stream=None) -> list:
-        """Enqueue n rounds; returns the sims that finished in them."""
-        check(lib().lts_batch_run(self.h, int(n_rounds), _stream_ptr(stream)), "lts_batch_run")
+    def run(self, n_rounds: int, graph: bool = True, stream=None) -> list:
+        """Enqueue n rounds (graph-captured rounds by default); returns the sims
+        that finished in them."""
+        check(lib().lts_batch_run(self.h, int(n_rounds), 1 if graph else 0, _stream_ptr(stream)), "lts_batch_run")
         done = [s for s in self._attached.values() if s.rounds_left == 0]
         for s in done:
             del self._attached[id(s)]
@@ -348,8 +349,8 @@ class Batch:
         return {"round": i.round, "rounds_to_drain": i.rounds_to_drain, "attached": i.attached,
                 "capacity": i.capacity}
 
-    def drain(self, stream=None) -> list:
-        return self.run(self.info()["rounds_to_drain"], stream)
+    def drain(self, graph: bool = True, stream=None) -> list:
+        return self.run(self.info()["rounds_to_drain"], graph, stream)
 
 
 def batch_advance(sims: Sequence["Sim"], n_coarse: int, mode: int = MODE_LTS, stream=None):

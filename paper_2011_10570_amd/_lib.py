@@ -93,7 +93,7 @@ PROTOTYPES = {
     "lts_batch_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
     "lts_batch_attach": (C.c_int, [_P, _P, C.c_int64]),
     "lts_batch_detach": (C.c_int, [_P, _P, _P]),
-    "lts_batch_run": (C.c_int, [_P, C.c_int64, _P]),
+    "lts_batch_run": (C.c_int, [_P, C.c_int64, C.c_int32, _P]),
     "lts_batch_query": (C.c_int, [_P, C.POINTER(BatchInfo)]),
     "lts_sim_rounds_left": (C.c_int64, [_P]),
     "lts_batch_destroy": (None, [_P]),

@@ -532,7 +532,7 @@ struct lts_sim {
 
 namespace {
 
-void release_slot(lts_batch* b, lts_sim* sim);
+void release_slot(lts_batch* b, lts_sim* sim, bool upload);
 
 void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams& sp) {
   const Mesh& m = sim->mesh->m;
@@ -794,7 +794,7 @@ int64_t lts_sim_coarse_step(const lts_sim* sim) { return sim ? sim->n : -1; }
 
 void lts_sim_destroy(lts_sim* sim) {
   if (!sim) return;
-  if (sim->batch) release_slot(sim->batch, sim);
+  if (sim->batch) release_slot(sim->batch, sim, true);
   drop_graphs(sim);
   if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
   if (sim->d_step) (void)hipFree(sim->d_step);
@@ -819,12 +819,12 @@ lts_status lts_batch_advance(lts_sim* const* sims, int32_t n, int64_t n_coarse_s
   if (st == LTS_OK) {
     lts_batch_info info;
     lts_batch_query(b, &info);
-    st = lts_batch_run(b, info.rounds_to_drain, stream);
+    st = lts_batch_run(b, info.rounds_to_drain, 1, stream);
   }
   if (st != LTS_OK) {
     std::string msg = g_err;
     for (int i = 0; i < n; ++i)
-      if (sims[i]->batch == b) release_slot(b, sims[i]);
+      if (sims[i]->batch == b) release_slot(b, sims[i], true);
     lts_batch_destroy(b);
     return fail(st, msg);
   }
@@ -907,23 +907,34 @@ struct lts_batch {
   bool dirty = true;
   int nused = 0;                // table entries [0, nused) are passed to the kernels
   int64_t round = 0;            // next round to run
+  int64_t* d_round = nullptr;   // device copy of `round`, read by the kernels
+  // one round captured as a graph (valid while the table and the shape stay)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t graph_gen = -1;
 };
 
 namespace {
 
-void release_slot(lts_batch* b, lts_sim* sim) {
+// Free the sim's slot.  A sim released before the end of its rounds must also
+// leave the device table (upload = true); one that has used up its rounds is
+// already inactive there, so the table (and a captured round) stays valid.
+void release_slot(lts_batch* b, lts_sim* sim, bool upload) {
   const int k = sim->slot;
   if (k >= 0 && k < (int)b->sims.size() && b->sims[k] == sim) {
     b->sims[k] = nullptr;
     b->desc[k].rounds = 0;
-    b->dirty = true;
+    if (upload) b->dirty = true;
     sim->mesh->m.attached -= 1;
   }
   sim->batch = nullptr;
   sim->slot = -1;
-  int n = (int)b->sims.size();
-  while (n > 0 && !b->sims[n - 1]) --n;
-  b->nused = n;
+  if (b->dirty) {   // the table is uploaded again: it can shrink
+    int n = (int)b->sims.size();
+    while (n > 0 && !b->sims[n - 1]) --n;
+    b->nused = n;
+  }
 }
 
 int64_t rounds_left(const lts_batch* b, const lts_sim* sim) { return sim->r0 + sim->rounds - b->round; }
@@ -941,8 +952,16 @@ void fill_batch_params(const lts_batch* b, int stage, StageParams& sp) {
   set_kmask(sp);
 }
 
+void drop_batch_graph(lts_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
 lts_status upload_table(lts_batch* b, hipStream_t s) {
   if (!b->dirty) return LTS_OK;
+  drop_batch_graph(b);
   if (b->nused > 0) {
     if (b->staged_rec) HIP_TRY(hipEventSynchronize(b->staged), "staging wait");
     std::memcpy(b->h_stage, b->desc.data(), b->nused * sizeof(BatchSim));
@@ -960,7 +979,41 @@ lts_status finish_rounds(lts_batch* b, lts_sim* sim, int64_t done, hipStream_t s
   const int nsub = 1 << (sim->mesh->m.lmax - sim->mesh->m.lmin);
   sim->n = b->desc[sim->slot].n0 + done / nsub;
   HIP_TRY(launch_set_i64(sim->d_step, sim->n, s), "set step");
-  release_slot(b, sim);
+  release_slot(b, sim, done != sim->rounds);
+  return LTS_OK;
+}
+
+// Active side-1 / side-2 tiles of round r (exact), or of any round (every
+// attached sim at its lowest level: the bound a captured round is sized for).
+void round_totals(const lts_batch* b, int64_t r, bool any_round, int64_t total[2]) {
+  total[0] = total[1] = 0;
+  for (int i = 0; i < b->nused; ++i) {
+    const lts_sim* sim = b->sims[i];
+    if (!sim) continue;
+    const BatchSim& d = b->desc[i];
+    int lo = d.lmin;
+    if (!any_round) {
+      const int64_t rr = r - d.r0;
+      if (rr < 0 || rr >= d.rounds) continue;
+      const int j = (int)(rr & ((1 << (d.lmax - d.lmin)) - 1));
+      lo = lowest_active_level(sim->mesh->m, b->mode, j);
+    }
+    total[0] += d.n_ge[0][lo];
+    total[1] += d.n_ge[1][lo];
+  }
+}
+
+// The launches of one round: p stages x 2 tile sides, then the round counter.
+lts_status enqueue_round(lts_batch* b, const int64_t total[2], hipStream_t s) {
+  const bool kf32 = b->prec == LTS_FP32_RHS;
+  for (int stg = 0; stg < b->p; ++stg) {
+    StageParams sp;
+    fill_batch_params(b, stg, sp);
+    for (int tt = 1; tt <= 2; ++tt)
+      HIP_TRY(launch_fused_batch(tt, b->eq, kf32, sp, b->d_desc, b->nused, b->d_round, total[tt - 1], g_shape, s),
+              "batch launch");
+  }
+  HIP_TRY(launch_increment(b->d_round, s), "round increment");
   return LTS_OK;
 }
 
@@ -996,6 +1049,9 @@ lts_status lts_batch_create(int32_t equation, int32_t precision, int32_t tableau
   if (e == hipSuccess) e = hipHostMalloc(&b->h_stage, capacity * sizeof(BatchSim), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&b->d_round, sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemset(b->d_round, 0, sizeof(int64_t));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     lts_batch_destroy(b);
     return hip_fail(e, "batch create");
@@ -1062,34 +1118,37 @@ lts_status lts_batch_detach(lts_batch* b, lts_sim* sim, void* stream) {
   return finish_rounds(b, sim, done, (hipStream_t)stream);
 }
 
-lts_status lts_batch_run(lts_batch* b, int64_t n_rounds, void* stream) {
+lts_status lts_batch_run(lts_batch* b, int64_t n_rounds, int32_t use_graph, void* stream) {
   clear_error();
   if (!b) return fail(LTS_EINVAL, "batch is NULL");
   if (n_rounds < 0) return fail(LTS_EINVAL, "n < 0");
   hipStream_t s = (hipStream_t)stream;
-  const bool kf32 = b->prec == LTS_FP32_RHS;
+  lts_status st;
   for (int64_t k = 0; k < n_rounds; ++k) {
-    lts_status st = upload_table(b, s);
-    if (st != LTS_OK) return st;
-    const int64_t r = b->round;
-    int64_t total[2] = {0, 0};
-    for (int i = 0; i < b->nused; ++i) {
-      const lts_sim* sim = b->sims[i];
-      if (!sim) continue;
-      const BatchSim& d = b->desc[i];
-      const int64_t rr = r - d.r0;
-      if (rr < 0 || rr >= d.rounds) continue;
-      const int j = (int)(rr & ((1 << (d.lmax - d.lmin)) - 1));
-      const int lo = lowest_active_level(sim->mesh->m, b->mode, j);
-      total[0] += d.n_ge[0][lo];
-      total[1] += d.n_ge[1][lo];
-    }
-    for (int stg = 0; stg < b->p; ++stg) {
-      StageParams sp;
-      fill_batch_params(b, stg, sp);
-      for (int tt = 1; tt <= 2; ++tt)
-        HIP_TRY(launch_fused_batch(tt, b->eq, kf32, sp, b->d_desc, b->nused, r, total[tt - 1], g_shape, s),
-                "batch launch");
+    if ((st = upload_table(b, s)) != LTS_OK) return st;
+    if (use_graph) {
+      if (b->exec && b->graph_gen != g_shape_gen) drop_batch_graph(b);
+      if (!b->exec) {
+        int64_t total[2];
+        round_totals(b, 0, true, total);
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        st = enqueue_round(b, total, b->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (st != LTS_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
+        b->graph_gen = g_shape_gen;
+      }
+      HIP_TRY(hipGraphLaunch(b->exec, s), "graph launch");
+    } else {
+      int64_t total[2];
+      round_totals(b, b->round, false, total);
+      if ((st = enqueue_round(b, total, s)) != LTS_OK) return st;
     }
     b->round += 1;
     for (int i = 0; i < b->nused; ++i) {
@@ -1127,7 +1186,10 @@ void lts_batch_destroy(lts_batch* b) {
   if (b->done_rec) (void)hipEventSynchronize(b->done);
   if (b->staged_rec) (void)hipEventSynchronize(b->staged);
   for (int i = 0; i < (int)b->sims.size(); ++i)
-    if (b->sims[i]) release_slot(b, b->sims[i]);
+    if (b->sims[i]) release_slot(b, b->sims[i], true);
+  drop_batch_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->d_round) (void)hipFree(b->d_round);
   if (b->staged) (void)hipEventDestroy(b->staged);
   if (b->done) (void)hipEventDestroy(b->done);
   if (b->d_desc) (void)hipFree(b->d_desc);

@@ -602,10 +602,11 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
 // arithmetic of every tile is that of the one-mesh kernel.
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
 __global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims,
-                                                    int64_t r) {
+                                                    const int64_t* __restrict__ round) {
   __shared__ FusedLds<TT, F, KF32> L;
   __shared__ int cum[kMaxBatch + 1];
   fused_init(L, sp0);
+  const int64_t r = *round;
   for (int s = threadIdx.x; s < nsims; s += NT) {
     const BatchSim& b = sims[s];
     const int64_t rr = r - b.r0;
@@ -880,7 +881,8 @@ struct OneArgs {
 struct BatchArgs {
   const BatchSim* sims;
   int nsims;
-  int64_t r, total;
+  const int64_t* round;
+  int64_t total;
 };
 }  // namespace
 
@@ -894,7 +896,8 @@ static hipError_t go(const StageParams& sp, const OneArgs& a, int max_wg, hipStr
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
 static hipError_t go(const StageParams& sp, const BatchArgs& a, int max_wg, hipStream_t s) {
   const int grid = fused_grid((int)std::min<int64_t>(a.total, 1 << 30), max_wg);
-  hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims, a.r);
+  hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims,
+                     a.round);
   return hipGetLastError();
 }
 
@@ -944,10 +947,10 @@ hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const 
 }
 
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
-                              int64_t r, int64_t total, const LaunchShape& ls, hipStream_t s) {
+                              const int64_t* round, int64_t total, const LaunchShape& ls, hipStream_t s) {
   if (total <= 0 || nsims <= 0) return hipSuccess;
   if (nsims > kMaxBatch) return hipErrorInvalidValue;
-  return dispatch_fused(tt, eq, kf32, sp0, BatchArgs{sims, nsims, r, total}, ls, s);
+  return dispatch_fused(tt, eq, kf32, sp0, BatchArgs{sims, nsims, round, total}, ls, s);
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) {

@@ -52,10 +52,11 @@ struct BatchSim {
 
 hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
                         const int32_t* slots, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s);
-// One stage of round r for the simulations sims[0..nsims) (device table); the
-// union of their active side-tt tiles is `total` (host-computed, sizes the grid).
+// One stage of the round *round (device counter) for the simulations
+// sims[0..nsims) (device table); `total` bounds the union of their active side-tt
+// tiles and sizes the grid (host-computed; any larger value is correct too).
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
-                              int64_t r, int64_t total, const LaunchShape& ls, hipStream_t s);
+                              const int64_t* round, int64_t total, const LaunchShape& ls, hipStream_t s);
 hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s);
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
                         const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);

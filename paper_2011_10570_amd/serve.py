@@ -72,7 +72,8 @@ def initial_state(mesh: Mesh, equation: str, centre, sigma: float, device):
 class Server:
     def __init__(self, budget_bytes: int, precision: int = FP64, tableau: str = "rk4", mode: int = MODE_LTS,
                  capacity: int = 64, tick_rounds: int = 4, keep_state: bool = False, device: str = "cuda",
-                 builders: int = 4, ko_sigma: float = 0.1):
+                 builders: int = 4, ko_sigma: float = 0.1, verbose: bool = False):
+        self.verbose = verbose
         self.budget = int(budget_bytes)
         self.prec = precision
         self.tab = tableau
@@ -147,6 +148,9 @@ class Server:
             for r in resident:
                 if id(r.sim) in fin:
                     r.finished = now
+                    if self.verbose:
+                        print(f"[serve] request {r.rid} ({r.equation}, {r.node_updates} node-updates) done: "
+                              f"queued {r.admitted - r.arrival:.3f} s, time-to-T {r.time_to_t:.3f} s", flush=True)
                     if self.keep_state:
                         r.state = r.sim.current()
                     used -= r.footprint
@@ -211,6 +215,30 @@ def batch_throughput(problems: list, n_coarse: int = 1, precision: int = FP64, d
     return {"problems": len(sims), "node_updates": work, "wall_s": wall, "node_updates_per_s": work / wall}
 
 
+def run_config(capacity: Optional[float] = None, n: Optional[int] = None, budget: Optional[int] = None,
+               tick_rounds: int = 4, verbose: bool = False) -> dict:
+    """The stored serving workload end to end.  Arrival rate = rho * capacity /
+    mean work per request, capacity in node-updates/s (default: measured on the
+    batched-problems workload)."""
+    import torch
+    from workloads import config
+    if budget is None:
+        budget = int(torch.cuda.mem_get_info()[0] * 0.5)
+    if capacity is None:
+        capacity = batch_throughput(config("batch")["problems"], 1)["node_updates_per_s"]
+    cfg = config("serve")
+    work = [Mesh(r.mesh_spec).info()["node_updates_lts"] * r.n_coarse for r in requests_from_config(n)]
+    rate = cfg["rho"] * capacity / float(np.mean(work))
+    reqs = requests_from_config(n, rate)
+    srv = Server(budget, tick_rounds=tick_rounds, verbose=verbose)
+    try:
+        stats = srv.run(reqs)
+    finally:
+        srv.close()
+    stats.update({"rho": cfg["rho"], "capacity_node_updates_per_s": capacity, "arrival_rate_per_s": rate})
+    return stats
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--requests", type=int, default=None, help="first N stored requests (default all)")
@@ -219,27 +247,8 @@ def main(argv=None):
                     help="node-updates/s used to set the arrival rate (default: measured on the batch workload)")
     ap.add_argument("--tick-rounds", type=int, default=4)
     args = ap.parse_args(argv)
-    import torch
-    from workloads import config
-    torch.cuda.init()
-    budget = int(args.budget_gib * 2 ** 30) if args.budget_gib else int(torch.cuda.mem_get_info()[0] * 0.5)
-    cap = args.capacity
-    if cap is None:
-        cap = batch_throughput(config("batch")["problems"], 1)["node_updates_per_s"]
-    cfg = config("serve")
-    reqs = requests_from_config(args.requests)
-    # mean work per request from the stored leaf counts (work ~ leaves, per coarse step)
-    srv = Server(budget, tick_rounds=args.tick_rounds)
-    # arrival rate rho * capacity / mean work; work known after the meshes are built
-    work = []
-    for r in reqs:
-        m = Mesh(r.mesh_spec)
-        work.append(m.info()["node_updates_lts"] * r.n_coarse)
-    rate = cfg["rho"] * cap / float(np.mean(work))
-    reqs = requests_from_config(args.requests, rate)
-    stats = srv.run(reqs)
-    srv.close()
-    stats.update({"rho": cfg["rho"], "capacity_node_updates_per_s": cap, "arrival_rate_per_s": rate})
+    budget = int(args.budget_gib * 2 ** 30) if args.budget_gib else None
+    stats = run_config(args.capacity, args.requests, budget, args.tick_rounds, verbose=True)
     print(json.dumps(stats))
 
 

@@ -102,25 +102,26 @@ def test_many_sims_one_mesh():
         assert torch.equal(s.current(), w)
 
 
-def test_join_and_leave(meshes):
+@pytest.mark.parametrize("graph", [True, False])
+def test_join_and_leave(meshes, graph):
     """A joins at round 0, B at round 5 (inside A's second coarse step); A leaves
     at a coarse-step boundary and later joins again; every state equals the alone
-    run of the same number of coarse steps."""
+    run of the same number of coarse steps (graph-captured rounds or not)."""
     (ga, ta, Ua), (gb, tb, Ub) = meshes[1], meshes[4]
     a = _sim(ga, ta, Ua)
     b = _sim(gb, tb, Ub)
     nsub_a = 1 << (ga.info()["lmax"] - ga.info()["lmin"])
     B = P.Batch("wave", P.FP64, "rk4", P.MODE_LTS, capacity=4)
     B.attach(a, 3)
-    B.run(5)
+    B.run(5, graph)
     B.attach(b, 2)
     assert B.info()["attached"] == 2
-    B.run(2 * nsub_a - 5)            # a is now at a coarse-step boundary (2 done)
+    B.run(2 * nsub_a - 5, graph)     # a is now at a coarse-step boundary (2 done)
     B.detach(a)
     assert a.coarse_step == 2 and a.rounds_left == 0
     assert torch.equal(a.current(), _alone(ga, ta, Ua, 2, P.MODE_LTS))
     B.attach(a, 1)                     # continues from coarse step 2
-    done = B.drain()
+    done = B.drain(graph)
     assert set(map(id, done)) == {id(a), id(b)}
     assert B.info()["attached"] == 0
     assert a.coarse_step == 3 and b.coarse_step == 2

@@ -150,6 +150,6 @@ def test_batch_arguments_checked_before_device_use():
         assert L.lts_batch_create(*args, ctypes.byref(h)) == _lib.EINVAL
         assert not h.value
     assert L.lts_batch_attach(None, None, 1) == _lib.EINVAL
-    assert L.lts_batch_run(None, 1, None) == _lib.EINVAL
+    assert L.lts_batch_run(None, 1, 1, None) == _lib.EINVAL
     assert L.lts_sim_rounds_left(None) == 0
     L.lts_batch_destroy(None)
