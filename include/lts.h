@@ -123,7 +123,7 @@ typedef struct {
   int32_t L;                 /* coordinate resolution (spec l_max)                  */
   int32_t lmin, lmax;        /* levels present                                      */
   int32_t n_substeps;        /* 2^(lmax - lmin)                                     */
-  int32_t tile;              /* current fused-kernel tile side (1 or 2)             */
+  int32_t tile;              /* current fused-kernel tile side (1, 2 or 4)          */
   int64_t level_count[LTS_MAX_LEVEL];   /* leaves per level                          */
   int64_t unzip_points;      /* sum over blocks of (4m+7)^3                         */
   int64_t grid_points;       /* sum over blocks of (4m+1)^3                         */
@@ -175,8 +175,14 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info);
 /* Copy a table to host memory `buf` of `cap` bytes; `*needed` receives the size
  * in bytes (call with buf = NULL to ask).  LTS_EINVAL if cap is too small. */
 lts_status lts_mesh_export(const lts_mesh* mesh, int32_t kind, void* buf, size_t cap, size_t* needed);
-/* Fused-kernel tile side (octants per tile side, 1 or 2; blocks of side m are cut
- * into min(m, t)^3 tiles).  Results do not depend on it. */
+/* Fused-kernel tile side t (1, 2 or 4): a block of side m is cut into tiles of
+ * side min(m, t).  Tiles of side 1 and 2 sit whole in LDS; side-4 tiles (whole
+ * 4^3-octant blocks, wave equation only) are streamed plane by plane after a
+ * pre-pass that prolongates their coarser ghosts.  FP64 results do not depend on
+ * t (bitwise); in FP32-RHS mode the FP32 stencils run on Y minus one FP64
+ * reference value per tile, so results differ between tile sides at FP32
+ * rounding.  Maxwell needs t = 1; batches (lts_batch_*) need t = 1 or 2.
+ * LTS_EINVAL for other t or while a sim of the mesh is attached to a batch. */
 lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile);
 /* Exact-rational stage conversion weights w^[case][stage][i] as float64 (eqs.
  * rk_crrection, fc_1, fc_2 with K = C P D), cases (delta, rho) = (0,1), (0,1/2),
@@ -219,10 +225,12 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
                            const lts_position* pos, void* stream);
 
 /* Launch shape of the fused stage kernels (process-wide; used by every later
- * fused launch and graph capture): threads per workgroup (256 or 512) and
- * the cap on the persistent grid in workgroups.  Results do not depend on it. */
-lts_status lts_set_launch(int32_t threads, int32_t max_workgroups);
-lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups);
+ * fused launch and graph capture): threads per workgroup of the LDS tile kernels
+ * (256 or 512, default 512) and of the streaming kernel of side-4 tiles (256 or
+ * 512, default 256), and the cap on the persistent grid in workgroups (default
+ * 4096).  Results do not depend on it.  LTS_EINVAL for other values. */
+lts_status lts_set_launch(int32_t threads, int32_t max_workgroups, int32_t stream_threads);
+lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups, int32_t* stream_threads);
 
 /* ---- simulation driver (a7; Alg. 1 / Alg. 2) ---------------------------------- */
 lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, int32_t tableau,

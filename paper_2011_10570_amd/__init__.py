@@ -221,15 +221,17 @@ def norms(mesh: Mesh, a, b=None, nfields: int = 2, stream=None) -> dict:
     return {"l2": out[:nfields].copy(), "linf": out[nfields:2 * nfields].copy(), "nonfinite": int(out[-1])}
 
 
-def set_launch(threads: int, max_workgroups: int):
-    """Launch shape of every later fused launch (threads 256 or 512; persistent-grid cap)."""
-    check(lib().lts_set_launch(int(threads), int(max_workgroups)), "lts_set_launch")
+def set_launch(threads: int, max_workgroups: int, stream_threads: int = 256):
+    """Launch shape of every later fused launch: threads of the LDS tile kernels and
+    of the streaming kernel (256 or 512 each), persistent-grid cap."""
+    check(lib().lts_set_launch(int(threads), int(max_workgroups), int(stream_threads)), "lts_set_launch")
 
 
 def get_launch() -> tuple:
-    t, w = C.c_int32(), C.c_int32()
-    check(lib().lts_get_launch(C.byref(t), C.byref(w)), "lts_get_launch")
-    return t.value, w.value
+    """(threads, max_workgroups, stream_threads)"""
+    t, w, st = C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib().lts_get_launch(C.byref(t), C.byref(w), C.byref(st)), "lts_get_launch")
+    return t.value, w.value, st.value
 
 
 def copy_probe(src, dst, nbytes: int, stream=None):

@@ -20,7 +20,11 @@ ARCH = os.environ.get("LTS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["mesh.cpp", "coeffs.cpp", "api.cpp", "kernels.hip"]
 
-COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
+# -ffp-contract=on: a multiply-add is fused only inside one expression, so the
+# rounding of a stencil or combine does not depend on how the compiler lays out
+# the surrounding code (loops unrolled or not, kernel shape); every kernel that
+# evaluates the same expression gets bitwise the same result.
+COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-ffp-contract=on",
           f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

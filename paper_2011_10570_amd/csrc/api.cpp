@@ -32,22 +32,28 @@ static lts_status hip_fail(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(e_, where); \
   } while (0)
 
-static lts_status upload_set(TileSet& ts) {
-  if (ts.d_tiles) { (void)hipFree(ts.d_tiles); ts.d_tiles = nullptr; }
-  if (ts.d_slots) { (void)hipFree(ts.d_slots); ts.d_slots = nullptr; }
-  if (ts.tiles.empty()) return LTS_OK;
-  HIP_TRY(hipMalloc(&ts.d_tiles, ts.tiles.size() * 4), "hipMalloc tiles");
-  HIP_TRY(hipMalloc(&ts.d_slots, ts.slots.size() * 4), "hipMalloc slots");
-  HIP_TRY(hipMemcpy(ts.d_tiles, ts.tiles.data(), ts.tiles.size() * 4, hipMemcpyHostToDevice), "upload tiles");
-  HIP_TRY(hipMemcpy(ts.d_slots, ts.slots.data(), ts.slots.size() * 4, hipMemcpyHostToDevice), "upload slots");
+static void free_set(TileSet& ts) {
+  for (int32_t** p : {&ts.d_tiles, &ts.d_slots, &ts.d_pairs, &ts.d_cbase}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+}
+
+static lts_status upload_vec(const std::vector<int32_t>& v, int32_t** d, const char* what) {
+  if (v.empty()) return LTS_OK;
+  HIP_TRY(hipMalloc(d, v.size() * 4), what);
+  HIP_TRY(hipMemcpy(*d, v.data(), v.size() * 4, hipMemcpyHostToDevice), what);
   return LTS_OK;
 }
 
-static void free_set(TileSet& ts) {
-  if (ts.d_tiles) (void)hipFree(ts.d_tiles);
-  if (ts.d_slots) (void)hipFree(ts.d_slots);
-  ts.d_tiles = nullptr;
-  ts.d_slots = nullptr;
+static lts_status upload_set(TileSet& ts) {
+  free_set(ts);
+  if (ts.tiles.empty()) return LTS_OK;
+  lts_status st;
+  if ((st = upload_vec(ts.tiles, &ts.d_tiles, "upload tiles")) != LTS_OK) return st;
+  if ((st = upload_vec(ts.slots, &ts.d_slots, "upload slots")) != LTS_OK) return st;
+  if ((st = upload_vec(ts.pairs, &ts.d_pairs, "upload pairs")) != LTS_OK) return st;
+  return upload_vec(ts.cbase, &ts.d_cbase, "upload cbase");
 }
 
 static lts_status ensure_device(Mesh& m) {
@@ -60,8 +66,8 @@ static lts_status ensure_device(Mesh& m) {
   HIP_TRY(hipGetDevice(&m.device), "hipGetDevice");
   lts_status st;
   if ((st = upload_set(m.bt)) != LTS_OK) return st;
-  if ((st = upload_set(m.ts[1])) != LTS_OK) return st;
-  if ((st = upload_set(m.ts[2])) != LTS_OK) return st;
+  for (int k : {1, 2, 4})
+    if ((st = upload_set(m.ts[k])) != LTS_OK) return st;
   m.uploaded = true;
   return LTS_OK;
 }
@@ -196,7 +202,86 @@ struct MeshExtra {
   double* d_norm = nullptr;
   size_t norm_cap = 0;
   double* d_coef = nullptr;
+  double* d_cscr = nullptr;   // coarser-ghost scratch of lts_fused_stage (side-4 tiles)
+  size_t cscr_cap = 0;
 };
+
+// Scratch of the coarser-ghost pre-pass of side-4 tiles: F x 729 doubles per
+// (tile, coarser leaf) pair.  Grown outside graph capture only.
+static lts_status ensure_cscr(const Mesh& m, int F, double** p, size_t* cap) {
+  const size_t need = (m.ts[4].pairs.size() / 2) * (size_t)F * 729 * sizeof(double);
+  if (need <= *cap) return LTS_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  HIP_TRY(hipMalloc(p, need), "hipMalloc ghost scratch");
+  *cap = need;
+  return LTS_OK;
+}
+
+// Side streams and events that let the launches of one stage (one per tile side)
+// run concurrently: they read the same inputs and write disjoint octants.
+struct Fork {
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // fork, join side 0, join side 1
+  bool ok() const { return side[0] && side[1] && ev[0] && ev[1] && ev[2]; }
+};
+
+static hipError_t fork_create(Fork& f) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&f.side[k], hipStreamNonBlocking);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&f.ev[k], hipEventDisableTiming);
+  return e;
+}
+
+static void fork_destroy(Fork& f) {
+  for (auto& x : f.side)
+    if (x) (void)hipStreamDestroy(x);
+  for (auto& x : f.ev)
+    if (x) (void)hipEventDestroy(x);
+  f = Fork{};
+}
+
+// Every fused launch of one stage for the tiles of levels >= lo: streamed side-4
+// tiles (with their coarser-ghost pre-pass), side-2 and side-1 tiles.  With a
+// fork, the side-2 and side-1 launches go to side streams that wait for the
+// work before them on s, and s waits for both before the stage ends (also under
+// graph capture, where the waits become graph edges).
+static lts_status launch_stage(const Mesh& m, int eq, bool kf32, const StageParams& sp, int lo, double* cscr,
+                               const LaunchShape& ls, hipStream_t s, const Fork* fk = nullptr) {
+  int groups = 0;
+  for (int tt : {4, 2, 1}) groups += m.ts[tt].count() > 0 && m.ts[tt].n_ge[lo] > 0;
+  const bool fork = fk && fk->ok() && groups > 1;
+  if (fork) HIP_TRY(hipEventRecord(fk->ev[0], s), "fork record");
+  int k = 0;
+  bool joined[2] = {false, false};
+  for (int tt : {4, 2, 1}) {
+    const TileSet& ts = m.ts[tt];
+    if (ts.count() == 0 || ts.n_ge[lo] == 0) continue;
+    XcdRanges xr;
+    for (int x = 0; x < 9; ++x) xr.b[x] = ts.xcd[lo][x];
+    hipStream_t q = s;
+    if (fork && k > 0) {
+      q = fk->side[k - 1];
+      HIP_TRY(hipStreamWaitEvent(q, fk->ev[0], 0), "fork wait");
+    }
+    if (tt == 4) {
+      HIP_TRY(launch_stream(eq, kf32, sp, ts.d_tiles, ts.d_slots, ts.d_pairs, ts.pair_ge[lo], ts.d_cbase, cscr, xr, ls,
+                            q),
+              "stream launch");
+    } else {
+      HIP_TRY(launch_fused(tt, eq, kf32, sp, ts.d_tiles, ts.d_slots, xr, ls, q), "fused launch");
+    }
+    if (fork && k > 0) {
+      HIP_TRY(hipEventRecord(fk->ev[k], q), "join record");
+      joined[k - 1] = true;
+    }
+    ++k;
+  }
+  for (int j = 0; j < 2; ++j)
+    if (joined[j]) HIP_TRY(hipStreamWaitEvent(s, fk->ev[j + 1], 0), "join wait");
+  return LTS_OK;
+}
 
 // Extra device buffers live beside the mesh handle.
 struct lts_mesh_full : lts_mesh {
@@ -234,8 +319,8 @@ void lts_mesh_destroy(lts_mesh* mesh) {
   if (!mesh) return;
   lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
   free_set(h->m.bt);
-  free_set(h->m.ts[1]);
-  free_set(h->m.ts[2]);
+  for (int k : {1, 2, 4}) free_set(h->m.ts[k]);
+  if (h->x.d_cscr) (void)hipFree(h->x.d_cscr);
   if (h->m.d_off) (void)hipFree(h->m.d_off);
   if (h->x.d_step) (void)hipFree(h->x.d_step);
   if (h->x.d_norm) (void)hipFree(h->x.d_norm);
@@ -250,7 +335,7 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   std::memset(info, 0, sizeof(*info));
   info->n_oct = m.n();
   info->n_blocks = (int64_t)m.blocks.size();
-  info->n_tiles = m.ts[1].count() + m.ts[2].count();
+  info->n_tiles = m.ts[1].count() + m.ts[2].count() + m.ts[4].count();
   info->L = m.L;
   info->lmin = m.lmin;
   info->lmax = m.lmax;
@@ -270,8 +355,10 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   info->grid_points = gp;
   // device tables: tile records and slot tables of the block tiles (phase
   // kernels) and of the fused tiles
-  info->table_bytes = 4 * (int64_t)(m.bt.tiles.size() + m.bt.slots.size() + m.ts[1].tiles.size() +
-                                    m.ts[1].slots.size() + m.ts[2].tiles.size() + m.ts[2].slots.size());
+  int64_t tb = (int64_t)(m.bt.tiles.size() + m.bt.slots.size());
+  for (int k : {1, 2, 4})
+    tb += (int64_t)(m.ts[k].tiles.size() + m.ts[k].slots.size() + m.ts[k].pairs.size() + m.ts[k].cbase.size());
+  info->table_bytes = 4 * tb;
   info->node_updates_lts = wl;
   info->node_updates_gts = wg;
   // eq. invS with alpha_l = DG nodes at level lmax - l
@@ -329,7 +416,7 @@ lts_status lts_mesh_export(const lts_mesh* mesh, int32_t kind, void* buf, size_t
       break;
     }
     case LTS_EXPORT_TILES:
-      for (int k = 1; k <= 2; ++k) out.insert(out.end(), m.ts[k].tiles.begin(), m.ts[k].tiles.end());
+      for (int k : {1, 2, 4}) out.insert(out.end(), m.ts[k].tiles.begin(), m.ts[k].tiles.end());
       break;
     default:
       return fail(LTS_EINVAL, "unknown export kind");
@@ -352,8 +439,8 @@ lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile) {
   if (st != LTS_OK) return st;
   m.tables_gen += 1;   // device tile tables move: captured graphs must be redone
   if (m.uploaded) {
-    if ((st = upload_set(m.ts[1])) != LTS_OK) return st;
-    if ((st = upload_set(m.ts[2])) != LTS_OK) return st;
+    for (int k : {1, 2, 4})
+      if ((st = upload_set(m.ts[k])) != LTS_OK) return st;
   }
   return LTS_OK;
 }
@@ -447,22 +534,26 @@ lts_status lts_rk_stage(lts_mesh* mesh, const lts_stage_view* view, const double
   return LTS_OK;
 }
 
-static LaunchShape g_shape;  // defaults: 256 threads, grid cap 4096
+static LaunchShape g_shape;  // defaults: tile kernels 512 threads, streaming kernel 256, grid cap 4096
 static int64_t g_shape_gen = 0;  // bumped by every change (captured graphs bake the shape in)
 
-lts_status lts_set_launch(int32_t threads, int32_t max_workgroups) {
+lts_status lts_set_launch(int32_t threads, int32_t max_workgroups, int32_t stream_threads) {
   clear_error();
   if (threads != 256 && threads != 512) return fail(LTS_EINVAL, "threads must be 256 or 512");
+  if (stream_threads != 256 && stream_threads != 512) return fail(LTS_EINVAL, "stream_threads must be 256 or 512");
   if (max_workgroups < 8) return fail(LTS_EINVAL, "max_workgroups must be >= 8");
-  if (g_shape.threads != threads || g_shape.max_wg != max_workgroups) ++g_shape_gen;
+  if (g_shape.threads != threads || g_shape.max_wg != max_workgroups || g_shape.stream_threads != stream_threads)
+    ++g_shape_gen;
   g_shape.threads = threads;
   g_shape.max_wg = max_workgroups;
+  g_shape.stream_threads = stream_threads;
   return LTS_OK;
 }
 
-lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups) {
+lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups, int32_t* stream_threads) {
   if (threads) *threads = g_shape.threads;
   if (max_workgroups) *max_workgroups = g_shape.max_wg;
+  if (stream_threads) *stream_threads = g_shape.stream_threads;
   return LTS_OK;
 }
 
@@ -476,7 +567,7 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
   hipStream_t s = (hipStream_t)stream;
   lts_status st = ensure_device(m);
   if (st != LTS_OK) return st;
-  if (equation == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
+  if (equation == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
     return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
   if ((equation == LTS_EQ_WAVE) != (view && view->nfields == 2))
     return fail(LTS_EINVAL, "nfields does not match the equation");
@@ -490,14 +581,8 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
     while (!(j & 1)) { j >>= 1; ++tz; }
     return m.lmax - tz;
   }();
-  for (int tt = 1; tt <= 2; ++tt) {
-    XcdRanges xr;
-    for (int x = 0; x < 9; ++x) xr.b[x] = m.ts[tt].xcd[lo][x];
-    HIP_TRY(launch_fused(tt, equation, view->precision == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, xr,
-                         g_shape, s),
-            "fused launch");
-  }
-  return LTS_OK;
+  if ((st = ensure_cscr(m, sp.F, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
+  return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, h->x.d_cscr, g_shape, s);
 }
 
 }  // extern "C"
@@ -524,6 +609,9 @@ struct lts_sim {
   double* d_pad = nullptr;
   void* d_kb = nullptr;
   double* d_coef = nullptr;
+  double* d_cscr = nullptr;     // coarser-ghost scratch (side-4 tiles)
+  size_t cscr_cap = 0;
+  Fork fork;                     // concurrent launches of one stage
   // continuous batching: the batch the sim is attached to, its round range
   lts_batch* batch = nullptr;
   int slot = -1;
@@ -573,13 +661,8 @@ lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
     for (int st = 0; st < sim->p; ++st) {
       StageParams sp;
       fill_sim_params(sim, st, mode, j, sp);
-      for (int tt = 1; tt <= 2; ++tt) {
-        XcdRanges xr;
-        for (int x = 0; x < 9; ++x) xr.b[x] = m.ts[tt].xcd[lo][x];
-        HIP_TRY(launch_fused(tt, sim->eq, sim->prec == LTS_FP32_RHS, sp, m.ts[tt].d_tiles, m.ts[tt].d_slots, xr,
-                             g_shape, s),
-                "fused launch");
-      }
+      lts_status r = launch_stage(m, sim->eq, sim->prec == LTS_FP32_RHS, sp, lo, sim->d_cscr, g_shape, s, &sim->fork);
+      if (r != LTS_OK) return r;
     }
   }
   HIP_TRY(launch_increment(sim->d_step, s), "step increment");
@@ -626,6 +709,7 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
   hipError_t e = hipMalloc(&sim->d_step, sizeof(int64_t));
   if (e == hipSuccess) e = hipMemset(sim->d_step, 0, sizeof(int64_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&sim->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = fork_create(sim->fork);
   if (e != hipSuccess) {
     lts_sim_destroy(sim);
     return hip_fail(e, "sim create");
@@ -656,9 +740,11 @@ lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32
   if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
     return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
   Mesh& m = sim->mesh->m;
-  if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
+  if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
     return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
   hipStream_t s = (hipStream_t)stream;
+  lts_status sc = ensure_cscr(m, sim->F, &sim->d_cscr, &sim->cscr_cap);
+  if (sc != LTS_OK) return sc;
   sim->mode = mode;
   if (!use_graph) {
     for (int64_t c = 0; c < n_coarse_steps; ++c) {
@@ -797,11 +883,13 @@ void lts_sim_destroy(lts_sim* sim) {
   if (sim->batch) release_slot(sim->batch, sim, true);
   drop_graphs(sim);
   if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
+  fork_destroy(sim->fork);
   if (sim->d_step) (void)hipFree(sim->d_step);
   for (void* p : sim->ualloc) (void)hipFree(p);
   if (sim->d_pad) (void)hipFree(sim->d_pad);
   if (sim->d_kb) (void)hipFree(sim->d_kb);
   if (sim->d_coef) (void)hipFree(sim->d_coef);
+  if (sim->d_cscr) (void)hipFree(sim->d_cscr);
   delete sim;
 }
 
@@ -1073,6 +1161,8 @@ lts_status lts_batch_attach(lts_batch* b, lts_sim* sim, int64_t n_coarse_steps) 
   Mesh& m = sim->mesh->m;
   if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
     return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
+  if (m.ts[4].count() > 0)
+    return fail(LTS_EUNSUPPORTED, "batched launches use tile sides 1 and 2 (lts_mesh_set_tile)");
   if (m.device != b->device) return fail(LTS_EINVAL, "sim and batch are on different devices");
   int k = 0;
   while (k < b->cap && b->sims[k]) ++k;

@@ -53,6 +53,25 @@ __device__ __forceinline__ int step_mod4(int n4, int lev, int mode, int j, int l
   return ((n4 << (lev - lmin)) + (j >> (lmax - lev))) & 3;
 }
 
+// Kernel-argument arrays indexed without a dynamic index (a per-lane or computed
+// index into a by-value argument makes the compiler copy the whole argument to
+// scratch memory): stage weight e = 4 case + i, and the stage mask of a case.
+__device__ __forceinline__ double stage_weight(const StageParams& sp, int e) {
+  double w = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (e == k) w = sp.w[k >> 2][k & 3];
+  return w;
+}
+
+__device__ __forceinline__ int stage_mask(const StageParams& sp, int cs) {
+  int m = sp.kmask[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k)
+    if (cs == k) m = sp.kmask[k];
+  return m;
+}
+
 struct TileCtx {
   int lev, m, tt, ox, oy, oz;
   int par_same, par_fine, par_coarse;   // U buffer of the source records
@@ -119,7 +138,7 @@ __device__ __forceinline__ double yval(const StageParams& sp, const double* w, i
   const int64_t fs = sp.N * 125;
   const int64_t ps = fs * sp.F;
   double acc = 0.0;
-#pragma unroll
+  #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if ((km >> i) & 1) acc = fma(w[i], kload<KF32>(sp.K, i * ps + idx), acc);
   }
@@ -138,10 +157,10 @@ template <bool KF32, int F>
 __device__ __forceinline__ void yload(const StageParams& sp, int km, int par, int64_t base, YLoad<KF32, F>& r) {
   const int64_t fs = sp.N * 125;
   const int64_t ps = fs * sp.F;
-#pragma unroll
+  #pragma unroll
   for (int f = 0; f < F; ++f) {
     r.u[f] = sp.U[par * ps + f * fs + base];
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < 4; ++i) r.k[f][i] = ((km >> i) & 1) ? kload<KF32>(sp.K, i * ps + f * fs + base) : 0.0;
   }
 }
@@ -149,7 +168,7 @@ __device__ __forceinline__ void yload(const StageParams& sp, int km, int par, in
 template <bool KF32, int F>
 __device__ __forceinline__ double ycombine(const YLoad<KF32, F>& r, int f, const double* w, int km, double dt) {
   double acc = 0.0;
-#pragma unroll
+  #pragma unroll
   for (int i = 0; i < 4; ++i)
     if ((km >> i) & 1) acc = fma(w[i], r.k[f][i], acc);
   return r.u[f] + dt * acc;
@@ -174,7 +193,7 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
       node = 2 * (L.nu[0] - 2 * cx) + 5 * 2 * (L.nu[1] - 2 * cy) + 25 * 2 * (L.nu[2] - 2 * cz);
       par = c.par_fine;
       w = wsh + 4 * c.case_fine;
-      km = sp.kmask[c.case_fine];
+      km = stage_mask(sp, c.case_fine);
     } else {
       lf = leaf;
       node = L.nu[0] + 5 * L.nu[1] + 25 * L.nu[2];
@@ -183,7 +202,7 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
       km = sp.kmask[0];
     }
     const int64_t base = (int64_t)lf * 125 + node;
-#pragma unroll
+    #pragma unroll
     for (int f = 0; f < F; ++f) out[f] = yval<KF32>(sp, w, km, par, f * fs + base, c.dt);
     return;
   }
@@ -192,81 +211,83 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
   int x2[3];
   for (int d = 0; d < 3; ++d) x2[d] = 4 * ((beta >> d) & 1) + L.nu[d];
   const double* w = wsh + 4 * c.case_coarse;
-  const int km = sp.kmask[c.case_coarse];
+  const int km = stage_mask(sp, c.case_coarse);
   const int par = c.par_coarse;
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
     if (x2[d] & 1) { lo[d] = 0; hi[d] = 4; }
     else { lo[d] = hi[d] = x2[d] >> 1; }
   }
-#pragma unroll
+  #pragma unroll
   for (int f = 0; f < F; ++f) out[f] = 0.0;
   for (int kz = lo[2]; kz <= hi[2]; ++kz) {
     double ty[F];
-#pragma unroll
+    #pragma unroll
     for (int f = 0; f < F; ++f) ty[f] = 0.0;
     for (int ky = lo[1]; ky <= hi[1]; ++ky) {
       double tx[F];
-#pragma unroll
+      #pragma unroll
       for (int f = 0; f < F; ++f) tx[f] = 0.0;
       for (int kx = lo[0]; kx <= hi[0]; ++kx) {
         const double wx = c_lag[x2[0]][kx];
         const int64_t base = (int64_t)leaf * 125 + kx + 5 * ky + 25 * kz;
-#pragma unroll
+        #pragma unroll
         for (int f = 0; f < F; ++f) tx[f] = fma(wx, yval<KF32>(sp, w, km, par, f * fs + base, c.dt), tx[f]);
       }
       const double wy = c_lag[x2[1]][ky];
-#pragma unroll
+      #pragma unroll
       for (int f = 0; f < F; ++f) ty[f] = fma(wy, tx[f], ty[f]);
     }
     const double wz = c_lag[x2[2]][kz];
-#pragma unroll
+    #pragma unroll
     for (int f = 0; f < F; ++f) out[f] = fma(wz, ty[f], out[f]);
   }
 }
 
 // ------------------------------------------------------------------ stencils
-// One grid point of the block RHS from a padded array Y (element type T, point
-// strides sx = 1, sy, sz).  Returns du/dt of each field.
-template <typename T, int EQ, int F>
-__device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, int sy, int sz, T h, T sigma,
-                                          const double ref[F], double out[F]) {
+// One grid point of the block RHS.  at(f, axis, k) is field f at offset k (-3..3)
+// from the point along axis (0 = x, 1 = y, 2 = z); k = 0 is the point itself.
+// Returns du/dt of each field.  Every caller goes through this one body, so the
+// floating-point operations and their order do not depend on the data layout.
+template <typename T, int EQ, int F, bool SEQ = false, typename At>
+__device__ __forceinline__ void rhs_at(const At& at, T h, T sigma, const double ref[F], double out[F]) {
   const T kos = sigma / (T(64) * h);
   if constexpr (EQ == LTS_EQ_WAVE) {
-    const T* u = Y;
-    const T* v = Y + fstride;
-    const int st[3] = {1, sy, sz};
     T lap = T(0), ku = T(0), kv = T(0);
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const int s = st[ax];
-      const T u0 = u[c], v0 = v[c];
-      const T up1 = u[c + s], um1 = u[c - s], up2 = u[c + 2 * s], um2 = u[c - 2 * s], up3 = u[c + 3 * s],
-              um3 = u[c - 3 * s];
-      const T vp1 = v[c + s], vm1 = v[c - s], vp2 = v[c + 2 * s], vm2 = v[c - 2 * s], vp3 = v[c + 3 * s],
-              vm3 = v[c - 3 * s];
+    auto axis = [&](int ax) {
+      const T u0 = at(0, ax, 0), v0 = at(1, ax, 0);
+      const T up1 = at(0, ax, 1), um1 = at(0, ax, -1), up2 = at(0, ax, 2), um2 = at(0, ax, -2), up3 = at(0, ax, 3),
+              um3 = at(0, ax, -3);
+      const T vp1 = at(1, ax, 1), vm1 = at(1, ax, -1), vp2 = at(1, ax, 2), vm2 = at(1, ax, -2), vp3 = at(1, ax, 3),
+              vm3 = at(1, ax, -3);
       lap += T(D2C3) * (um3 + up3) + T(D2C2) * (um2 + up2) + T(D2C1) * (um1 + up1) + T(D2C0) * u0;
       ku += (um3 + up3) - T(6) * (um2 + up2) + T(15) * (um1 + up1) - T(20) * u0;
       kv += (vm3 + vp3) - T(6) * (vm2 + vp2) + T(15) * (vm1 + vp1) - T(20) * v0;
+    };
+    // SEQ: one axis at a time (fewer live registers); same operations, same order
+    if constexpr (SEQ) {
+#pragma unroll 1
+      for (int ax = 0; ax < 3; ++ax) axis(ax);
+    } else {
+      axis(0);
+      axis(1);
+      axis(2);
     }
-    out[0] = ((double)v[c] + ref[1]) + (double)(kos * ku);
+    out[0] = ((double)at(1, 0, 0) + ref[1]) + (double)(kos * ku);
     out[1] = (double)(lap / (h * h) + kos * kv);
   } else {
     // Maxwell: fields Ex Ey Ez Bx By Bz
-    const int st[3] = {1, sy, sz};
     T d[F][3];
     T ko[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      const T* g = Y + f * fstride;
       ko[f] = T(0);
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        const int s = st[ax];
-        const T p1 = g[c + s], m1 = g[c - s], p2 = g[c + 2 * s], m2 = g[c - 2 * s], p3 = g[c + 3 * s],
-                m3 = g[c - 3 * s];
+        const T p1 = at(f, ax, 1), m1 = at(f, ax, -1), p2 = at(f, ax, 2), m2 = at(f, ax, -2), p3 = at(f, ax, 3),
+                m3 = at(f, ax, -3);
         d[f][ax] = (T(D1C1) * (p1 - m1) + T(D1C2) * (p2 - m2) + T(D1C3) * (p3 - m3)) / h;
-        ko[f] += (m3 + p3) - T(6) * (m2 + p2) + T(15) * (m1 + p1) - T(20) * g[c];
+        ko[f] += (m3 + p3) - T(6) * (m2 + p2) + T(15) * (m1 + p1) - T(20) * at(f, ax, 0);
       }
     }
     // curl B, curl E (axis 0 = x, 1 = y, 2 = z)
@@ -277,6 +298,24 @@ __device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, in
     out[4] = (double)(-(d[0][2] - d[2][0]) + kos * ko[4]);
     out[5] = (double)(-(d[1][0] - d[0][1]) + kos * ko[5]);
   }
+}
+
+// Accessor of a padded array with point strides (1, sy, sz) and field stride fs.
+template <typename T>
+struct StridedAt {
+  const T* Y;
+  int64_t fs;
+  int c, sy, sz;
+  __device__ __forceinline__ T operator()(int f, int ax, int k) const {
+    const int s = ax == 0 ? 1 : (ax == 1 ? sy : sz);
+    return Y[f * fs + c + k * s];
+  }
+};
+
+template <typename T, int EQ, int F>
+__device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, int sy, int sz, T h, T sigma,
+                                          const double ref[F], double out[F]) {
+  rhs_at<T, EQ, F>(StridedAt<T>{Y, fstride, c, sy, sz}, h, sigma, ref, out);
 }
 
 // ------------------------------------------------------------------ fused stage
@@ -352,7 +391,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   // a compile-time mask so the hot gather has no branches around its loads
     // the tile record is uniform: keep it in scalar registers
     int32_t trec[8];
-#pragma unroll
+    #pragma unroll
     for (int k = 0; k < 8; ++k) trec[k] = __builtin_amdgcn_readfirstlane(tile[k]);
     const int32_t* t = trec;
     const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, n4);
@@ -364,7 +403,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     const double* __restrict__ Uf = v.U + (int64_t)c.par_fine * F * fsz;
     const double* __restrict__ Uc = v.U + (int64_t)c.par_coarse * F * fsz;
     double* __restrict__ Uw1 = v.Uw + (int64_t)(c.par_same ^ 1) * F * fsz;
-    const int kmf = sp.kmask[c.case_fine], kmc = sp.kmask[c.case_coarse];
+    const int kmf = stage_mask(sp, c.case_fine), kmc = stage_mask(sp, c.case_coarse);
     const double* wf = wsh + 4 * c.case_fine;
     const double* wc = wsh + 4 * c.case_coarse;
     __syncthreads();  // previous tile done with LDS
@@ -386,7 +425,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     // (1) same-level and finer sources
     for (int p0 = threadIdx.x; p0 < P3; p0 += UB * NT) {
       int pidx[UB], kind[UB], leaf[UB], nuv[UB][3];
-#pragma unroll
+      #pragma unroll
       for (int u = 0; u < UB; ++u) {
         const int pi = p0 + u * NT;
         kind[u] = SRC_COARSE;
@@ -402,37 +441,37 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         leaf[u] = sl[2 * si];
       }
       double uu[UB][F], kk[UB][F][4];
-#pragma unroll
+      #pragma unroll
       for (int u = 0; u < UB; ++u) {
         if (kind[u] != SRC_SAME) continue;
         const uint32_t off = (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]);
-#pragma unroll
+        #pragma unroll
         for (int f = 0; f < F; ++f) {
           uu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
-#pragma unroll
+          #pragma unroll
           for (int i = 0; i < 4; ++i)
             if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
         }
       }
-#pragma unroll
+      #pragma unroll
       for (int u = 0; u < UB; ++u) {
         if (kind[u] == SRC_FINE) {
           const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
           const uint32_t off = (uint32_t)((leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
                                           10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz));
-#pragma unroll
+          #pragma unroll
           for (int f = 0; f < F; ++f) {
             double acc = 0.0;
-#pragma unroll
+            #pragma unroll
             for (int i = 0; i < 4; ++i)
               if ((kmf >> i) & 1) acc = fma(wf[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
             Y[f * P3 + pidx[u]] = (LT)(ld32(Uf + (uint32_t)(f * fsz), off) + c.dt * acc - ref[f]);
           }
         } else if (kind[u] == SRC_SAME) {
-#pragma unroll
+          #pragma unroll
           for (int f = 0; f < F; ++f) {
             double acc = 0.0;
-#pragma unroll
+            #pragma unroll
             for (int i = 0; i < 4; ++i)
               if ((KS >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
             Y[f * P3 + pidx[u]] = (LT)(uu[u][f] + c.dt * acc - ref[f]);
@@ -451,7 +490,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         const int f = rem / 125, n = rem - 125 * f;
         const uint32_t off = (uint32_t)(lst_cleaf[2 * (b0 + k)] * 125 + n);
         double acc = 0.0;
-#pragma unroll
+        #pragma unroll
         for (int i = 0; i < 4; ++i)
           if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
         Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
@@ -464,7 +503,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         double tx;
         if (x2 & 1) {
           tx = 0.0;
-#pragma unroll
+          #pragma unroll
           for (int kx = 0; kx < 5; ++kx) tx = fma(lag[5 * x2 + kx], yc[kx], tx);
         } else {
           tx = fma(1.0, yc[x2 >> 1], 0.0);
@@ -480,7 +519,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         double ty;
         if (y2 & 1) {
           ty = 0.0;
-#pragma unroll
+          #pragma unroll
           for (int ky = 0; ky < 5; ++ky) ty = fma(lag[5 * y2 + ky], t1[ky], ty);
         } else {
           ty = fma(1.0, t1[y2 >> 1], 0.0);
@@ -499,13 +538,13 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         const int beta = (kb >> 4) & 7;
         const int x2 = 4 * (beta & 1) + (ax >> 3), y2 = 4 * ((beta >> 1) & 1) + (ay >> 3),
                   z2 = 4 * ((beta >> 2) & 1) + (az >> 3);
-#pragma unroll
+        #pragma unroll
         for (int f = 0; f < F; ++f) {
           const double* t2 = T2 + ((cidx - b0) * F + f) * 405 + 45 * x2 + 5 * y2;   // [kz]
           double v;
           if (z2 & 1) {
             v = 0.0;
-#pragma unroll
+            #pragma unroll
             for (int kz = 0; kz < 5; ++kz) v = fma(lag[5 * z2 + kz], t2[kz], v);
           } else {
             v = fma(1.0, t2[z2 >> 1], 0.0);
@@ -526,7 +565,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
       double k[F];
       rhs_point<LT, EQ, F>(Y, P3, ci, P, P * P, (LT)c.h, (LT)v.sigma, ref, k);
-#pragma unroll
+      #pragma unroll
       for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
     }
     __syncthreads();
@@ -538,10 +577,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       const uint32_t off = (uint32_t)(first * 125 + e);
       double u0[F], kprev[F][4];
       if (last) {
-#pragma unroll
+        #pragma unroll
         for (int f = 0; f < F; ++f) {
           u0[f] = ld32(Us + (uint32_t)(f * fsz), off);
-#pragma unroll
+          #pragma unroll
           for (int i = 0; i < 4; ++i)
             kprev[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
         }
@@ -549,7 +588,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       const int o = e / 125, node = e - 125 * (e / 125);
       const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
       const int gi = ((4 * ((o >> 2) & 1) + cc) * G + (4 * ((o >> 1) & 1) + b)) * G + (4 * (o & 1) + a);
-#pragma unroll
+      #pragma unroll
       for (int f = 0; f < F; ++f) {
         double kv = R[f * G3 + gi];
         if constexpr (KF32) {
@@ -562,7 +601,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         if (last) {
           // compute_step_partial: U_new = U0 + dt sum_i b_i K_i into the other buffer
           double acc = 0.0;
-#pragma unroll
+          #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (i < sp.p) acc = fma(sp.b[i], (i == sp.stage) ? kv : kprev[f][i], acc);
           }
@@ -574,7 +613,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
 
 template <int TT, int F, bool KF32>
 __device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const StageParams& sp) {
-  if (threadIdx.x < 16) L.wsh[threadIdx.x] = sp.w[threadIdx.x >> 2][threadIdx.x & 3];
+  if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
   if (threadIdx.x < 45) L.lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
 }
 
@@ -647,13 +686,441 @@ __global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const Batch
   }
 }
 
+// ------------------------------------------------------------------ streamed blocks
+// Whole 4^3-octant blocks (side-4 tiles) are streamed along z: the padded block
+// (23^3 points per field) never sits in LDS at once.  A ring of 8 padded planes
+// holds the 7 planes one output plane of the 17^3 block grid needs plus the plane
+// being loaded, so the loads of padded plane z+7 are in flight while the stencils
+// of output plane z run.  Gathered points per DG node drop from 3.4 (side-2
+// tiles) to 1.5.
+
+// Coarser ghosts of side-4 tiles, before the streamed stage: pair q = (tile,
+// cidx) gets the stage state of the tile's cidx-th distinct coarser source leaf
+// prolongated to its 9^3 half-node grid, scr[q][f][z2][y2][x2].  The sums and
+// their order are those of the fused kernel's separable prolongation, so a ghost
+// has the same value whichever kernel computes it.
+template <bool KF32, int F>
+__global__ __launch_bounds__(256) void k_coarse_pre(StageParams sp, const int32_t* __restrict__ tiles,
+                                                    const int32_t* __restrict__ slots,
+                                                    const int32_t* __restrict__ pairs, double* __restrict__ scr) {
+  using KT = typename std::conditional<KF32, float, double>::type;
+  __shared__ double wsh[16];
+  __shared__ double lag[45];
+  __shared__ double Yc[F * 125];
+  __shared__ double T1[F * 225];
+  __shared__ double T2[F * 405];
+  if (threadIdx.x < 16) wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
+  if (threadIdx.x < 45) lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
+  const int q = blockIdx.x;
+  const int ti = __builtin_amdgcn_readfirstlane(pairs[2 * q]);
+  const int k = __builtin_amdgcn_readfirstlane(pairs[2 * q + 1]);
+  int32_t trec[8];
+  #pragma unroll
+  for (int e = 0; e < 8; ++e) trec[e] = __builtin_amdgcn_readfirstlane(tiles[8 * (int64_t)ti + e]);
+  const int32_t* t = trec;
+  const TileCtx c = tile_ctx(t, sp, (int)(*sp.step & 3));
+  const int counts = t[TI_COUNTS];
+  const int ncl = (counts >> 24) & 255;
+  const int ns = (c.tt + 2) * (c.tt + 2) * (c.tt + 2);
+  const int nent = ns + (counts & 255) + ((counts >> 8) & 255) + ((counts >> 16) & 255) + ncl;
+  const int leaf = __builtin_amdgcn_readfirstlane(slots[2 * ((int64_t)t[TI_SLOT] + nent - ncl + k)]);
+  const int fsz = (int)(sp.N * 125);
+  const double* __restrict__ Uc = sp.U + (int64_t)c.par_coarse * F * fsz;
+  const KT* __restrict__ Kr = (const KT*)sp.K;
+  const int kmc = stage_mask(sp, c.case_coarse);
+  __syncthreads();
+  const double* wc = wsh + 4 * c.case_coarse;
+  for (int e = threadIdx.x; e < F * 125; e += 256) {
+    const int f = e / 125, n = e - 125 * f;
+    const uint32_t off = (uint32_t)(leaf * 125 + n);
+    double acc = 0.0;
+    #pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
+    Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < F * 225; e += 256) {
+    const int kf = e / 225, r = e - 225 * kf;
+    const int x2 = r / 25, yz = r - 25 * x2;
+    const double* yc = Yc + kf * 125 + 5 * yz;
+    double tx;
+    if (x2 & 1) {
+      tx = 0.0;
+      #pragma unroll
+      for (int kx = 0; kx < 5; ++kx) tx = fma(lag[5 * x2 + kx], yc[kx], tx);
+    } else {
+      tx = fma(1.0, yc[x2 >> 1], 0.0);
+    }
+    T1[e] = tx;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < F * 405; e += 256) {
+    const int kf = e / 405, r = e - 405 * kf;
+    const int x2 = r / 45, r2 = r - 45 * x2;
+    const int y2 = r2 / 5, kz = r2 - 5 * y2;
+    const double* t1 = T1 + kf * 225 + 25 * x2 + 5 * kz;
+    double ty;
+    if (y2 & 1) {
+      ty = 0.0;
+      #pragma unroll
+      for (int ky = 0; ky < 5; ++ky) ty = fma(lag[5 * y2 + ky], t1[ky], ty);
+    } else {
+      ty = fma(1.0, t1[y2 >> 1], 0.0);
+    }
+    T2[e] = ty;
+  }
+  __syncthreads();
+  double* out = scr + (int64_t)q * F * 729;
+  for (int e = threadIdx.x; e < F * 729; e += 256) {
+    const int f = e / 729, r = e - 729 * f;
+    const int z2 = r / 81, y2 = (r / 9) % 9, x2 = r % 9;
+    const double* t2 = T2 + f * 405 + 45 * x2 + 5 * y2;
+    double v;
+    if (z2 & 1) {
+      v = 0.0;
+      #pragma unroll
+      for (int kz = 0; kz < 5; ++kz) v = fma(lag[5 * z2 + kz], t2[kz], v);
+    } else {
+      v = fma(1.0, t2[z2 >> 1], 0.0);
+    }
+    out[e] = v;
+  }
+}
+
+template <int F, bool KF32>
+struct StreamLds {
+  static constexpr int P = 23, PL = P * P, G = 17, GL = G * G, RING = 8, NS = 216;
+  using LT = typename std::conditional<KF32, float, double>::type;
+  LT Y[F * RING * PL];       // ring of padded planes: [f][slot][y][x]
+  double R[2][F * GL];       // stencil results of an output plane (double buffered)
+  int32_t sl[2 * NS];        // slot table
+  uint8_t axl[2][P];         // x / y: slot position | node offset << 3
+  double wsh[16];
+  double ref[F];
+};
+
+// Accessor of the ring: x, y inside a plane, z across the ring slots zb[0..6].
+template <typename T>
+struct RingAt {
+  const T* Y;
+  int fs, cxy;
+  const int* zb;
+  __device__ __forceinline__ T operator()(int f, int ax, int k) const {
+    if (ax == 2) return Y[f * fs + zb[3 + k] + cxy];
+    return Y[f * fs + zb[3] + cxy + k * (ax == 0 ? 1 : 23)];
+  }
+};
+
+// Raw loads of one padded plane (per thread: KP points), issued one step before
+// they are combined into stage values, so that their latency spans a whole step.
+template <int KP, int F>
+struct PlaneLoads {
+  int kind[KP];
+  double uu[KP][F];
+  double kk[KP][F][3];   // a stage state reads K_i, i < p - 1 <= 3
+};
+
+// Last stage: U0 and the earlier stages at the DG nodes of one output plane
+// (per thread: KN nodes), loaded one step before the RK update uses them.
+template <int KN, int F>
+struct NodeLoads {
+  double u0[KN][F];
+  double kp[KN][F][3];
+};
+
+// Per-block constants of the streaming kernel.
+template <bool KF32>
+struct StreamCtx {
+  using KT = typename std::conditional<KF32, float, double>::type;
+  const double* Us;      // U buffer of the block's step (same-level sources, U0)
+  const double* Uf;      // U buffer of finer sources
+  double* Uw1;           // the other U buffer (RK update)
+  const KT* Kr;          // stages
+  KT* Kw;                // K_s
+  const double* cs;      // prolongated coarser ghosts of this block
+  const double* wf;      // weights of finer sources (LDS)
+  double dt, h, sigma;
+  int fsz, first, kmf;
+};
+
+// loads of padded plane pz into Q.  Every path writes every field of Q (values
+// are selected, not the fields), so Q stays in registers across the step.
+template <int F, bool KF32, int NT, int KS, int KP>
+__device__ __forceinline__ void stream_issue(const StreamLds<F, KF32>& L, const StreamCtx<KF32>& x, int pz,
+                                             PlaneLoads<KP, F>& Q) {
+  constexpr int P = StreamLds<F, KF32>::P, PL = StreamLds<F, KF32>::PL;
+  if (pz >= P) return;
+  const int Qz = pz - 3;
+  const int cz = cell_of(Qz, 4);
+  const int nuz = Qz - 4 * cz, szz = cz + 1;
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int p = threadIdx.x + u * NT;
+    const bool on = p < PL;
+    const int pp = on ? p : 0;
+    const int qy = pp / P, qx = pp - P * qy;
+    const int ax = L.axl[0][qx], ay = L.axl[1][qy];
+    const int si = (ax & 7) + 6 * ((ay & 7) + 6 * szz);
+    const int kb = L.sl[2 * si + 1];
+    const int leaf = L.sl[2 * si];
+    const int nux = ax >> 3, nuy = ay >> 3;
+    const int kind = kb & 15;
+    const bool fine = kind == SRC_FINE, coarse = kind == SRC_COARSE;
+    // node of the source leaf (finer: the coincident node of child c)
+    const int cx = fine ? min(nux >> 1, 1) : 0, cy = fine ? min(nuy >> 1, 1) : 0, czz = fine ? min(nuz >> 1, 1) : 0;
+    const int sc = fine ? 2 : 1;
+    const uint32_t off = (uint32_t)((leaf + cx + 2 * cy + 4 * czz) * 125 + sc * (nux - 2 * cx) +
+                                    5 * sc * (nuy - 2 * cy) + 25 * sc * (nuz - 2 * czz));
+    // coarser: the prolongated ghost in scr
+    const int beta = (kb >> 4) & 7, cidx = kb >> 8;
+    const int x2 = 4 * (beta & 1) + nux, y2 = 4 * ((beta >> 1) & 1) + nuy, z2 = 4 * ((beta >> 2) & 1) + nuz;
+    const int km = (!on || coarse) ? 0 : (fine ? x.kmf : KS);
+    Q.kind[u] = on ? kind : -1;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double uv = 0.0;
+      if (on) {
+        if (coarse) uv = x.cs[((int64_t)cidx * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
+        else uv = ld32((fine ? x.Uf : x.Us) + (uint32_t)(f * x.fsz), off);
+      }
+      Q.uu[u][f] = uv;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        Q.kk[u][f][i] = ((km >> i) & 1) ? (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off) : 0.0;
+    }
+  }
+}
+
+// stage values of plane pz (loads in Q) into its ring slot: Y = U + dt sum w K
+// (same-level: case (0,1) weights, finer: case (0,1/2)), coarser ghosts as they are
+template <int F, bool KF32, int NT, int KS, int KP>
+__device__ __forceinline__ void stream_store(StreamLds<F, KF32>& L, const StreamCtx<KF32>& x, int pz,
+                                             const PlaneLoads<KP, F>& Q) {
+  using LS = StreamLds<F, KF32>;
+  constexpr int P = LS::P, PL = LS::PL;
+  using LT = typename LS::LT;
+  if (pz >= P) return;
+  LT* Yp = L.Y + (pz & 7) * PL;
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int kind = Q.kind[u];
+    if (kind < 0) continue;
+    const int p = threadIdx.x + u * NT;
+    const bool fine = kind == SRC_FINE;
+    const int km = fine ? x.kmf : KS;
+    const double* w = fine ? x.wf : L.wsh;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double y;
+      if (kind == SRC_COARSE) {
+        y = Q.uu[u][f] - L.ref[f];
+      } else {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          if ((km >> i) & 1) acc = fma(w[i], Q.kk[u][f][i], acc);
+        y = Q.uu[u][f] + x.dt * acc - L.ref[f];
+      }
+      Yp[f * 8 * PL + p] = (LT)y;
+    }
+  }
+}
+
+// stencils of output plane gz from the ring into R
+template <int F, int EQ, bool KF32, int NT>
+__device__ __forceinline__ void stream_stencil(const StreamLds<F, KF32>& L, const StreamCtx<KF32>& x, int gz,
+                                               double* R) {
+  using LS = StreamLds<F, KF32>;
+  constexpr int P = LS::P, PL = LS::PL, G = LS::G, GL = LS::GL;
+  using LT = typename LS::LT;
+  if (gz < 0 || gz >= G) return;
+  int zb[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) zb[k] = ((gz + k) & 7) * PL;
+  for (int gp = threadIdx.x; gp < GL; gp += NT) {
+    const int gy = gp / G, gx = gp - G * gy;
+    double kv[F];
+    rhs_at<LT, EQ, F, true>(RingAt<LT>{L.Y, 8 * PL, (gy + 3) * P + (gx + 3), zb}, (LT)x.h, (LT)x.sigma, L.ref, kv);
+#pragma unroll
+    for (int f = 0; f < F; ++f) R[f * GL + gp] = kv[f];
+  }
+}
+
+// DG node e (0 .. 400 nl) of output plane gz: its element offset and its point
+// of the block grid plane.  The plane's node layers: octant layer oz1, node layer
+// c1, and where octant layers meet (gz = 4, 8, 12) also layer oz1-1, node 4.
+__device__ __forceinline__ void plane_node(int first, int gz, int e, uint32_t& off, int& gp) {
+  const int oz1 = min(gz >> 2, 3), c1 = gz - 4 * oz1;
+  const int layer = e / 400, r = e - 400 * layer;
+  const int qo = r / 25, n = r - 25 * qo;
+  const int ox = qo & 3, oy = qo >> 2;
+  const int oz = layer ? oz1 - 1 : oz1, cz = layer ? 4 : c1;
+  off = (uint32_t)((first + (int)morton3(ox, oy, oz)) * 125 + cz * 25 + n);
+  const int b = n / 5, a = n - 5 * b;
+  gp = (4 * oy + b) * 17 + (4 * ox + a);
+}
+
+__device__ __forceinline__ int plane_nodes(int gz) { return ((gz & 3) == 0 && gz > 0 && gz < 16) ? 800 : 400; }
+
+// last stage: the RK-update operands of output plane gz into N
+template <int F, bool KF32, int NT, int KN>
+__device__ __forceinline__ void stream_issue_rk(const StageParams& sp, const StreamCtx<KF32>& x, int gz,
+                                                NodeLoads<KN, F>& N) {
+  if (gz < 0 || gz >= 17) return;
+  const int nn = plane_nodes(gz);
+#pragma unroll
+  for (int u = 0; u < KN; ++u) {
+    const int e = threadIdx.x + u * NT;
+    uint32_t off = 0;
+    int gp = 0;
+    if (e < nn) plane_node(x.first, gz, e, off, gp);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      N.u0[u][f] = e < nn ? ld32(x.Us + (uint32_t)(f * x.fsz), off) : 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        N.kp[u][f][i] = (e < nn && i < sp.stage) ? (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off) : 0.0;
+    }
+  }
+}
+
+// zip (+ RK update at the last stage, operands in N) of output plane gz from R
+template <int F, bool KF32, int NT, bool LAST, int KN>
+__device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCtx<KF32>& x, int gz, const double* R,
+                                           const NodeLoads<KN, F>& N) {
+  constexpr int GL = StreamLds<F, KF32>::GL;
+  if (gz < 0 || gz >= 17) return;
+  const int nn = plane_nodes(gz);
+  double bs = sp.b[0];   // b_s without a dynamic index into the kernel arguments
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (i == sp.stage) bs = sp.b[i];
+  constexpr int KZ = (800 + NT - 1) / NT;
+#pragma unroll
+  for (int u = 0; u < KZ; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e >= nn) continue;
+    uint32_t off;
+    int gp;
+    plane_node(x.first, gz, e, off, gp);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double kv = R[f * GL + gp];
+      if constexpr (KF32) {
+        const float kf = (float)kv;
+        st32(x.Kw + (uint32_t)(f * x.fsz), off, kf);
+        kv = (double)kf;
+      } else {
+        st32(x.Kw + (uint32_t)(f * x.fsz), off, kv);
+      }
+      if constexpr (LAST) {
+        // U0 + dt (b_0 K_0 + ... + b_s K_s), s = p - 1, accumulated in stage order
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          if (i < sp.stage) acc = fma(sp.b[i], N.kp[u][f][i], acc);
+        acc = fma(bs, kv, acc);
+        st32(x.Uw1 + (uint32_t)(f * x.fsz), off, N.u0[u][f] + x.dt * acc);
+      }
+    }
+  }
+}
+
+// One streamed block, a software pipeline over the 23 padded planes.  Step `it`
+// (0..24): issue the loads of padded plane it+1 (stage values of same-level /
+// finer sources, prolongated coarser ghosts from scr) and, at the last stage,
+// of the RK operands of output plane it-7; zip (and RK-update) output plane it-8
+// from the LDS result of the previous step; run the stencils of output plane
+// it-7 from the ring; combine the loads of plane it (issued in the previous
+// step) into its ring slot; barrier.
+template <int F, int EQ, bool KF32, int NT, int KS, bool LAST>
+__device__ __forceinline__ void stream_tile(StreamLds<F, KF32>& L, const StageParams& sp, const SimView& v, int n4,
+                                            const int32_t* __restrict__ tile, const int32_t* __restrict__ slots,
+                                            const double* __restrict__ cs) {
+  using LS = StreamLds<F, KF32>;
+  constexpr int P = LS::P, PL = LS::PL, NS = LS::NS;
+  constexpr int KP = (PL + NT - 1) / NT;          // padded points per thread and plane
+  using KT = typename std::conditional<KF32, float, double>::type;
+  int32_t trec[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) trec[e] = __builtin_amdgcn_readfirstlane(tile[e]);
+  const int32_t* t = trec;
+  const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, n4);
+  StreamCtx<KF32> x;
+  x.fsz = (int)(v.N * 125);
+  x.first = t[TI_FIRST];
+  x.Us = v.U + (int64_t)c.par_same * F * x.fsz;
+  x.Uf = v.U + (int64_t)c.par_fine * F * x.fsz;
+  x.Uw1 = v.Uw + (int64_t)(c.par_same ^ 1) * F * x.fsz;
+  x.Kr = (const KT*)v.K;
+  x.Kw = (KT*)v.Kw + (int64_t)sp.stage * F * x.fsz;
+  x.cs = cs;
+  x.kmf = stage_mask(sp, c.case_fine);
+  x.wf = L.wsh + 4 * c.case_fine;
+  x.dt = c.dt;
+  x.h = c.h;
+  x.sigma = v.sigma;
+  __syncthreads();  // previous block done with LDS
+  for (int e = threadIdx.x; e < 2 * NS; e += NT) L.sl[e] = slots[2 * (int64_t)t[TI_SLOT] + e];
+  if (threadIdx.x < 2 * P) {
+    const int q = threadIdx.x % P;
+    const int Q = q - 3;
+    const int cell = cell_of(Q, 4);
+    L.axl[threadIdx.x / P][q] = (uint8_t)((cell + 1) | ((Q - 4 * cell) << 3));
+  }
+  if (threadIdx.x < F) L.ref[threadIdx.x] = KF32 ? x.Us[threadIdx.x * x.fsz + x.first * 125] : 0.0;
+  __syncthreads();
+  // Two sets of plane loads alternate: step `it` issues plane it+1 into one set
+  // while the other, issued in step it-1, is consumed.  At the last stage the
+  // RK operands of output plane it-8 are issued at the start of step it and used
+  // by its zip after the stencils.
+  constexpr int KN = (800 + NT - 1) / NT;
+  PlaneLoads<KP, F> A, B;
+  NodeLoads<LAST ? KN : 1, F> N;
+  stream_issue<F, KF32, NT, KS>(L, x, 0, A);
+  for (int it = 0; it <= P + 1; it += 2) {
+    if constexpr (LAST) stream_issue_rk<F, KF32, NT>(sp, x, it - 8, N);
+    stream_issue<F, KF32, NT, KS>(L, x, it + 1, B);
+    stream_stencil<F, EQ, KF32, NT>(L, x, it - 7, L.R[it & 1]);
+    stream_zip<F, KF32, NT, LAST>(sp, x, it - 8, L.R[(it + 1) & 1], N);
+    stream_store<F, KF32, NT, KS>(L, x, it, A);
+    __syncthreads();
+    if (it + 1 > P + 1) break;
+    if constexpr (LAST) stream_issue_rk<F, KF32, NT>(sp, x, it - 7, N);
+    stream_issue<F, KF32, NT, KS>(L, x, it + 2, A);
+    stream_stencil<F, EQ, KF32, NT>(L, x, it - 6, L.R[(it + 1) & 1]);
+    stream_zip<F, KF32, NT, LAST>(sp, x, it - 7, L.R[it & 1], N);
+    stream_store<F, KF32, NT, KS>(L, x, it + 1, B);
+    __syncthreads();
+  }
+}
+
+template <int F, int EQ, bool KF32, int NT, int KS, bool LAST>
+__global__ __launch_bounds__(NT) void k_stream(StageParams sp, const int32_t* __restrict__ tiles,
+                                               const int32_t* __restrict__ slots, const int32_t* __restrict__ cbase,
+                                               const double* __restrict__ scr, XcdRanges xr) {
+  __shared__ StreamLds<F, KF32> L;
+  if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
+  const int n4 = (int)(*sp.step & 3);
+  const int nslot = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int sid = blockIdx.x >> 3;
+  const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
+  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot) {
+    const int cb = __builtin_amdgcn_readfirstlane(cbase[ti]);
+    stream_tile<F, EQ, KF32, NT, KS, LAST>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots,
+                                           scr + (int64_t)cb * F * 729);
+  }
+}
+
 // ------------------------------------------------------------------ standalone kernels
 template <bool KF32, int F>
 __global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __restrict__ tiles,
                                                const int32_t* __restrict__ slots, const int32_t* __restrict__ list,
                                                const int64_t* __restrict__ off, int64_t total, double* out) {
   __shared__ double wsh[16];
-  if (threadIdx.x < 16) wsh[threadIdx.x] = sp.w[threadIdx.x >> 2][threadIdx.x & 3];
+  if (threadIdx.x < 16) wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
   __syncthreads();
   const int bi = blockIdx.y;
   const int b = list[bi];
@@ -667,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __
     const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
     double v[F];
     point_values<KF32, F>(sp, c, sl, wsh, qx, qy, qz, v);
-#pragma unroll
+    #pragma unroll
     for (int f = 0; f < F; ++f) out[f * total + off[bi] + pi] = v[f];
   }
 }
@@ -691,7 +1158,7 @@ __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, 
       // float stencils on Y - ref, ref = the block's first grid value
       double ref[F];
       const int c0 = (3 * P + 3) * P + 3;
-#pragma unroll
+      #pragma unroll
       for (int f = 0; f < F; ++f) ref[f] = padded[f * ptotal + poff[bi] + c0];
       const int st[3] = {1, P, P * P};
       if constexpr (EQ == LTS_EQ_WAVE) {
@@ -740,7 +1207,7 @@ __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, 
       const double zero[F] = {};
       rhs_point<double, EQ, F>(padded + poff[bi], ptotal, ci, P, P * P, h, sigma, zero, k);
     }
-#pragma unroll
+    #pragma unroll
     for (int f = 0; f < F; ++f) {
       if constexpr (F32) ((float*)kout)[f * gtotal + goff[bi] + gi] = (float)k[f];
       else ((double*)kout)[f * gtotal + goff[bi] + gi] = k[f];
@@ -951,6 +1418,56 @@ hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0,
   if (total <= 0 || nsims <= 0) return hipSuccess;
   if (nsims > kMaxBatch) return hipErrorInvalidValue;
   return dispatch_fused(tt, eq, kf32, sp0, BatchArgs{sims, nsims, round, total}, ls, s);
+}
+
+// Streamed side-4 tiles (wave equation): coarser-ghost pre-pass, then the
+// streaming kernel over the launch's tiles.
+template <bool KF32, int NT, int KS>
+static hipError_t go_stream(const StageParams& sp, const int32_t* tiles, const int32_t* slots, const int32_t* cbase,
+                            const double* scr, const XcdRanges& xr, int max_wg, hipStream_t s) {
+  const dim3 grid(fused_grid(xr.b[8], max_wg));
+  if (sp.stage == sp.p - 1)
+    hipLaunchKernelGGL((k_stream<2, LTS_EQ_WAVE, KF32, NT, KS, true>), grid, dim3(NT), 0, s, sp, tiles, slots, cbase,
+                       scr, xr);
+  else
+    hipLaunchKernelGGL((k_stream<2, LTS_EQ_WAVE, KF32, NT, KS, false>), grid, dim3(NT), 0, s, sp, tiles, slots, cbase,
+                       scr, xr);
+  return hipGetLastError();
+}
+
+template <bool KF32, int NT>
+static hipError_t stream_ks(const StageParams& sp, const int32_t* tiles, const int32_t* slots, const int32_t* cbase,
+                            const double* scr, const XcdRanges& xr, int max_wg, hipStream_t s) {
+  switch (sp.kmask[0]) {
+    case 0: return go_stream<KF32, NT, 0>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
+    case 1: return go_stream<KF32, NT, 1>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
+    case 2: return go_stream<KF32, NT, 2>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
+    case 3: return go_stream<KF32, NT, 3>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
+    case 4: return go_stream<KF32, NT, 4>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_stream(int eq, bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
+                         const int32_t* pairs, int64_t npairs, const int32_t* cbase, double* scr, const XcdRanges& xr,
+                         const LaunchShape& ls, hipStream_t s) {
+  if (xr.b[8] <= 0) return hipSuccess;
+  if (eq != LTS_EQ_WAVE) return hipErrorInvalidValue;   // 6 fields do not fit the plane ring
+  if (npairs > 0) {
+    if (kf32) hipLaunchKernelGGL((k_coarse_pre<true, 2>), dim3((unsigned)npairs), dim3(256), 0, s, sp, tiles, slots,
+                                 pairs, scr);
+    else hipLaunchKernelGGL((k_coarse_pre<false, 2>), dim3((unsigned)npairs), dim3(256), 0, s, sp, tiles, slots,
+                            pairs, scr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  switch (ls.stream_threads) {
+    case 256: return kf32 ? stream_ks<true, 256>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s)
+                          : stream_ks<false, 256>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s);
+    case 512: return kf32 ? stream_ks<true, 512>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s)
+                          : stream_ks<false, 512>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) {

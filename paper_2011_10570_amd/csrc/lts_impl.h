@@ -28,8 +28,16 @@ struct TileSet {
   // per lowest active level l: the prefix [0, n_ge[l]) cut into 8 contiguous
   // ranges of equal estimated cost (one per XCD): xcd[l][0..8]
   std::vector<std::vector<int32_t>> xcd;
+  // side-4 tiles only (streamed whole blocks): the (tile, distinct coarser leaf)
+  // pairs whose prolongation a pre-pass writes to scratch, in tile order;
+  // cbase[t] = first pair of tile t; pair_ge[l] = pairs of tiles with level >= l
+  std::vector<int32_t> pairs;   // [Q][2] = tile, cidx
+  std::vector<int32_t> cbase;
+  std::vector<int64_t> pair_ge;
   int32_t* d_tiles = nullptr;
   int32_t* d_slots = nullptr;
+  int32_t* d_pairs = nullptr;
+  int32_t* d_cbase = nullptr;
   int64_t count() const { return (int64_t)tiles.size() / 8; }
 };
 
@@ -41,7 +49,7 @@ struct Mesh {
   std::vector<Block> blocks;
   std::vector<int32_t> block_of_leaf;
   int tile = 2;
-  TileSet ts[3];                      // ts[1]: tiles of side 1, ts[2]: side 2
+  TileSet ts[5];                      // ts[t]: tiles of side t (1, 2, 4)
   TileSet bt;                         // one tile per block (standalone kernels)
   bool uploaded = false;
   int device = -1;

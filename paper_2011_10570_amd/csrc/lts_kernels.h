@@ -21,11 +21,13 @@ struct StageParams {
   int kmask[4];         // per case: bit i set if w[case][i] != 0 (uniform branches)
 };
 
-// Launch shape of the fused kernel: threads per workgroup (256 or 512) and the
-// cap on the persistent grid (workgroups, rounded to a multiple of 8 XCDs).
+// Launch shape of the fused kernels: threads per workgroup of the tile kernels
+// and of the streaming kernel (256 or 512 each) and the cap on the persistent
+// grid (workgroups, rounded to a multiple of 8 XCDs).
 struct LaunchShape {
-  int threads = 256;
+  int threads = 512;
   int max_wg = 4096;
+  int stream_threads = 256;
 };
 
 // Tiles of one launch cut into 8 contiguous ranges, one per XCD: XCD x walks
@@ -57,6 +59,12 @@ hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const 
 // tiles and sizes the grid (host-computed; any larger value is correct too).
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
                               const int64_t* round, int64_t total, const LaunchShape& ls, hipStream_t s);
+// Streamed whole 4^3 blocks (side-4 tiles, wave equation): the coarser-ghost
+// pre-pass over pairs[0..npairs) into scr, then the streaming kernel over the
+// launch's tiles (XCD ranges as for launch_fused).
+hipError_t launch_stream(int eq, bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
+                         const int32_t* pairs, int64_t npairs, const int32_t* cbase, double* scr, const XcdRanges& xr,
+                         const LaunchShape& ls, hipStream_t s);
 hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s);
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
                         const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);

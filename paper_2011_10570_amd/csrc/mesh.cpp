@@ -445,14 +445,37 @@ void finish_levels(TileSet& ts) {
 
 }  // namespace
 
-// Tiles of the fused kernels for maximum tile side t (1 or 2): a block of side m
-// is cut into tiles of side min(m, t).  ts[1] holds the side-1 tiles, ts[2] the
-// side-2 tiles; each set is ordered finest level first.
+// Side-4 tiles: the coarser-leaf prolongation pairs of each tile (tile order).
+void build_pairs(TileSet& ts) {
+  const int64_t T = ts.count();
+  ts.pairs.clear();
+  ts.cbase.assign(T, 0);
+  for (int64_t i = 0; i < T; ++i) {
+    ts.cbase[i] = (int32_t)(ts.pairs.size() / 2);
+    const int ncl = (ts.tiles[8 * i + TI_COUNTS] >> 24) & 255;
+    for (int k = 0; k < ncl; ++k) {
+      ts.pairs.push_back((int32_t)i);
+      ts.pairs.push_back(k);
+    }
+  }
+  ts.pair_ge.assign(LTS_MAX_LEVEL + 1, 0);
+  for (int l = 0; l <= LTS_MAX_LEVEL; ++l) {
+    const int64_t n = ts.n_ge[l];   // tiles [0, n) have level >= l
+    ts.pair_ge[l] = n < T ? ts.cbase[n] : (int64_t)(ts.pairs.size() / 2);
+  }
+}
+
+// Tiles of the fused kernels for maximum tile side t (1, 2 or 4): a block of side
+// m is cut into tiles of side min(m, t).  ts[k] holds the side-k tiles, each set
+// ordered finest level first.  Side-4 tiles (whole 4^3 blocks) are streamed plane
+// by plane; their coarser ghosts come from a prolongation pre-pass.
 lts_status build_tiles(Mesh& m, int t) {
-  if (t != 1 && t != 2) return fail(LTS_EINVAL, "tile side must be 1 or 2");
-  for (int k = 1; k <= 2; ++k) {
+  if (t != 1 && t != 2 && t != 4) return fail(LTS_EINVAL, "tile side must be 1, 2 or 4");
+  for (int k = 1; k <= 4; ++k) {
     m.ts[k].tiles.clear();
     m.ts[k].slots.clear();
+    m.ts[k].pairs.clear();
+    m.ts[k].cbase.clear();
   }
   for (size_t b = 0; b < m.blocks.size(); ++b) {
     const Block& B = m.blocks[b];
@@ -464,8 +487,8 @@ lts_status build_tiles(Mesh& m, int t) {
           if (st != LTS_OK) return st;
         }
   }
-  finish_levels(m.ts[1]);
-  finish_levels(m.ts[2]);
+  for (int k : {1, 2, 4}) finish_levels(m.ts[k]);
+  build_pairs(m.ts[4]);
   m.tile = t;
   return LTS_OK;
 }

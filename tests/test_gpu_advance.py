@@ -70,8 +70,23 @@ def test_fused_equals_unfused_and_tiles_and_graph(c1):
     a = _run_gpu(gm, U0, 3, P.MODE_LTS, graph=True, tile=2)
     b = _run_gpu(gm, U0, 3, P.MODE_LTS, graph=False, tile=1)
     c = _run_gpu(gm, U0, 3, P.MODE_LTS, unfused=True)
+    d = _run_gpu(gm, U0, 3, P.MODE_LTS, graph=True, tile=4)
     assert np.array_equal(a, b)
     assert np.array_equal(a, c)
+    assert np.array_equal(a, d)
+
+
+@pytest.mark.parametrize("mode", [P.MODE_LTS, P.MODE_GTS])
+def test_streamed_blocks_equal_tiles(mode):
+    """A mesh with several 4^3 blocks next to coarser and finer leaves: streamed
+    whole blocks (tile side 4) give bitwise the side-2 tile result."""
+    p = config("batch")["problems"][6]
+    gm = P.build_mesh(p["mesh"])
+    lv = gm.leaves()
+    U0 = wave_gaussian(lv[:, :3], lv[:, 3], gm.info()["L"], [p["mesh"]["criteria"][0]["center"]], sigma=0.1)
+    a = _run_gpu(gm, U0, 2, mode, tile=2)
+    b = _run_gpu(gm, U0, 2, mode, tile=4)
+    assert np.array_equal(a, b)
 
 
 def test_graph_replays_repeatable(c1):
@@ -126,19 +141,21 @@ def test_maxwell_tile1():
     want = so.run(om, U0, 1, "lts", equation="maxwell", sigma=0.1).reshape(6, om.n_oct, 125)
     got = _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", tile=1)
     assert rel_err(got, want) < TOL
-    with pytest.raises(P.LTSError):
-        _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", tile=2)
+    for tile in (2, 4):
+        with pytest.raises(P.LTSError):
+            _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", tile=tile)
 
 
 def test_fp32_rhs_error_stated(c1, c1_oracle):
     """FP32 stencils with FP64 state: error vs the FP64 oracle, per field."""
     om, gm, U0 = c1
-    got = _run_gpu(gm, U0, 2, P.MODE_LTS, prec=P.FP32_RHS)
     want = c1_oracle["lts"]
-    for f in range(2):
-        e = np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()
-        print(f"fp32-rhs field {f}: max rel err {e:.3e}")
-        assert e < 1e-4
+    for tile in (2, 4):
+        got = _run_gpu(gm, U0, 2, P.MODE_LTS, prec=P.FP32_RHS, tile=tile)
+        for f in range(2):
+            e = np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()
+            print(f"fp32-rhs tile {tile} field {f}: max rel err {e:.3e}")
+            assert e < 1e-4
 
 
 def test_graph_recaptured_after_table_and_shape_changes(c1):

@@ -170,3 +170,9 @@ def test_batch_misuse(meshes):
     assert a.coarse_step == 2
     gm.set_tile(3 - t)
     gm.set_tile(t)
+    # streamed 4^3 blocks are not batched
+    g4, t4, U4 = meshes[1]
+    d = _sim(g4, 4, U4)
+    with pytest.raises(P.LTSError):
+        B.attach(d, 1)
+    g4.set_tile(t4)

@@ -110,7 +110,7 @@ def test_rk_update(meshes, mode, n, j):
     assert rel_err(U.cpu().numpy().reshape(2, 2, -1), st.U.reshape(2, 2, -1)) < TOL
 
 
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 4])
 @pytest.mark.parametrize("mode,n,j", [("lts", 0, 0), ("lts", 0, 1), ("lts", 1, 2), ("lts", 3, 3), ("gts", 1, 1)])
 @pytest.mark.parametrize("stage", [0, 1, 3])
 def test_fused_stage(meshes, tile, mode, n, j, stage):

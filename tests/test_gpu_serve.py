@@ -74,12 +74,12 @@ def test_autotuner_applies_fastest_and_keeps_results():
     U0 = wave_gaussian_torch(m.leaves(), m.info()["L"], [[36, 25, 17]], device=DEV)
     old = P.get_launch()
     try:
-        res = tune.tune(m, U0, tiles=(1, 2), threads=(256, 512), max_workgroups=(512, 4096), reps=1,
-                        device=DEV, use_cache=False)
-        assert len(res["table"]) == 8
+        res = tune.tune(m, U0, tiles=(1, 2, 4), threads=(256, 512), max_workgroups=(512, 4096),
+                        stream_threads=(256, 512), reps=1, device=DEV, use_cache=False)
+        assert len(res["table"]) == 4 + 4 + 8
         best = res["best"]
         assert res["ms"] == min(ms for _, ms in res["table"])
-        assert m.info()["tile"] == best[0] and P.get_launch() == (best[1], best[2])
+        assert m.info()["tile"] == best[0] and P.get_launch() == (best[1], best[2], best[3])
         res2 = tune.tune(m, U0, device=DEV)          # cached: applies without timing
         assert res2["table"] is None or res2["best"] is not None
     finally:

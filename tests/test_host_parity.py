@@ -125,7 +125,7 @@ def test_coefficients_match_oracle_rationals(tab, code):
 
 def test_tiles_cover_blocks():
     gm = P.build_mesh(mesh_spec("wave_c1"))
-    for t in (1, 2):
+    for t in (1, 2, 4):
         gm.set_tile(t)
         tiles = gm.tiles()
         blocks = gm.blocks()
@@ -136,8 +136,12 @@ def test_tiles_cover_blocks():
             for o in range(tt ** 3):
                 covered[first + o] += 1
         assert (covered == 1).all()
-        # finest level first
-        assert (np.diff(tiles[tiles[:, 4] == 1][:, 2]) <= 0).all()
+        # finest level first within each tile side
+        for tt in (1, 2, 4):
+            assert (np.diff(tiles[tiles[:, 4] == tt][:, 2]) <= 0).all()
+    assert (gm.tiles()[:, 4] == 4).sum() == (gm.blocks()[:, 1] == 4).sum() > 0
+    with pytest.raises(P.LTSError):
+        gm.set_tile(3)
 
 
 def test_batch_arguments_checked_before_device_use():
