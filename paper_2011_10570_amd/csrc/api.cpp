@@ -33,7 +33,7 @@ static lts_status hip_fail(hipError_t e, const char* where) {
   } while (0)
 
 static void free_set(TileSet& ts) {
-  for (int32_t** p : {&ts.d_tiles, &ts.d_slots, &ts.d_pairs, &ts.d_cbase}) {
+  for (int32_t** p : {&ts.d_tiles, &ts.d_slots}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
@@ -51,9 +51,17 @@ static lts_status upload_set(TileSet& ts) {
   if (ts.tiles.empty()) return LTS_OK;
   lts_status st;
   if ((st = upload_vec(ts.tiles, &ts.d_tiles, "upload tiles")) != LTS_OK) return st;
-  if ((st = upload_vec(ts.slots, &ts.d_slots, "upload slots")) != LTS_OK) return st;
-  if ((st = upload_vec(ts.pairs, &ts.d_pairs, "upload pairs")) != LTS_OK) return st;
-  return upload_vec(ts.cbase, &ts.d_cbase, "upload cbase");
+  return upload_vec(ts.slots, &ts.d_slots, "upload slots");
+}
+
+// tile sets of the fused kernels and the ghost table (rebuilt together)
+static lts_status upload_fused_sets(Mesh& m) {
+  lts_status st;
+  for (int k : {1, 2, 4})
+    if ((st = upload_set(m.ts[k])) != LTS_OK) return st;
+  if (m.d_ghosts) (void)hipFree(m.d_ghosts);
+  m.d_ghosts = nullptr;
+  return upload_vec(m.ghosts, &m.d_ghosts, "upload ghost table");
 }
 
 static lts_status ensure_device(Mesh& m) {
@@ -66,8 +74,7 @@ static lts_status ensure_device(Mesh& m) {
   HIP_TRY(hipGetDevice(&m.device), "hipGetDevice");
   lts_status st;
   if ((st = upload_set(m.bt)) != LTS_OK) return st;
-  for (int k : {1, 2, 4})
-    if ((st = upload_set(m.ts[k])) != LTS_OK) return st;
+  if ((st = upload_fused_sets(m)) != LTS_OK) return st;
   m.uploaded = true;
   return LTS_OK;
 }
@@ -206,10 +213,10 @@ struct MeshExtra {
   size_t cscr_cap = 0;
 };
 
-// Scratch of the coarser-ghost pre-pass of side-4 tiles: F x 729 doubles per
-// (tile, coarser leaf) pair.  Grown outside graph capture only.
+// Ghost-table scratch: F x 729 doubles per entry.  Grown outside graph capture
+// only.
 static lts_status ensure_cscr(const Mesh& m, int F, double** p, size_t* cap) {
-  const size_t need = (m.ts[4].pairs.size() / 2) * (size_t)F * 729 * sizeof(double);
+  const size_t need = (m.ghosts.size() / 2) * (size_t)F * 729 * sizeof(double);
   if (need <= *cap) return LTS_OK;
   if (*p) (void)hipFree(*p);
   *p = nullptr;
@@ -242,13 +249,14 @@ static void fork_destroy(Fork& f) {
   f = Fork{};
 }
 
-// Every fused launch of one stage for the tiles of levels >= lo: streamed side-4
-// tiles (with their coarser-ghost pre-pass), side-2 and side-1 tiles.  With a
-// fork, the side-2 and side-1 launches go to side streams that wait for the
-// work before them on s, and s waits for both before the stage ends (also under
-// graph capture, where the waits become graph edges).
+// Every fused launch of one stage for the tiles of levels >= lo: the ghost-table
+// pre-pass for receivers of levels >= lo, then streamed side-4 tiles, side-2 and
+// side-1 tiles.  With a fork, the side-2 and side-1 launches go to side streams
+// that wait for the work before them on s, and s waits for both before the stage
+// ends (also under graph capture, where the waits become graph edges).
 static lts_status launch_stage(const Mesh& m, int eq, bool kf32, const StageParams& sp, int lo, double* cscr,
                                const LaunchShape& ls, hipStream_t s, const Fork* fk = nullptr) {
+  HIP_TRY(launch_ghost_pre(sp.F, kf32, sp, m.d_ghosts, m.ghost_ge[lo], cscr, s), "ghost pre-pass");
   int groups = 0;
   for (int tt : {4, 2, 1}) groups += m.ts[tt].count() > 0 && m.ts[tt].n_ge[lo] > 0;
   const bool fork = fk && fk->ok() && groups > 1;
@@ -266,11 +274,9 @@ static lts_status launch_stage(const Mesh& m, int eq, bool kf32, const StagePara
       HIP_TRY(hipStreamWaitEvent(q, fk->ev[0], 0), "fork wait");
     }
     if (tt == 4) {
-      HIP_TRY(launch_stream(eq, kf32, sp, ts.d_tiles, ts.d_slots, ts.d_pairs, ts.pair_ge[lo], ts.d_cbase, cscr, xr, ls,
-                            q),
-              "stream launch");
+      HIP_TRY(launch_stream(eq, kf32, sp, ts.d_tiles, ts.d_slots, cscr, xr, ls, q), "stream launch");
     } else {
-      HIP_TRY(launch_fused(tt, eq, kf32, sp, ts.d_tiles, ts.d_slots, xr, ls, q), "fused launch");
+      HIP_TRY(launch_fused(tt, eq, kf32, sp, ts.d_tiles, ts.d_slots, cscr, xr, ls, q), "fused launch");
     }
     if (fork && k > 0) {
       HIP_TRY(hipEventRecord(fk->ev[k], q), "join record");
@@ -320,6 +326,7 @@ void lts_mesh_destroy(lts_mesh* mesh) {
   lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
   free_set(h->m.bt);
   for (int k : {1, 2, 4}) free_set(h->m.ts[k]);
+  if (h->m.d_ghosts) (void)hipFree(h->m.d_ghosts);
   if (h->x.d_cscr) (void)hipFree(h->x.d_cscr);
   if (h->m.d_off) (void)hipFree(h->m.d_off);
   if (h->x.d_step) (void)hipFree(h->x.d_step);
@@ -356,8 +363,8 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   // device tables: tile records and slot tables of the block tiles (phase
   // kernels) and of the fused tiles
   int64_t tb = (int64_t)(m.bt.tiles.size() + m.bt.slots.size());
-  for (int k : {1, 2, 4})
-    tb += (int64_t)(m.ts[k].tiles.size() + m.ts[k].slots.size() + m.ts[k].pairs.size() + m.ts[k].cbase.size());
+  for (int k : {1, 2, 4}) tb += (int64_t)(m.ts[k].tiles.size() + m.ts[k].slots.size());
+  tb += (int64_t)m.ghosts.size();
   info->table_bytes = 4 * tb;
   info->node_updates_lts = wl;
   info->node_updates_gts = wg;
@@ -438,10 +445,7 @@ lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile) {
   lts_status st = build_tiles(m, tile);
   if (st != LTS_OK) return st;
   m.tables_gen += 1;   // device tile tables move: captured graphs must be redone
-  if (m.uploaded) {
-    for (int k : {1, 2, 4})
-      if ((st = upload_set(m.ts[k])) != LTS_OK) return st;
-  }
+  if (m.uploaded && (st = upload_fused_sets(m)) != LTS_OK) return st;
   return LTS_OK;
 }
 

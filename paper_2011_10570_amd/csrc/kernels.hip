@@ -320,13 +320,13 @@ __device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, in
 
 // ------------------------------------------------------------------ fused stage
 // LDS of one workgroup of the fused stage kernels.
-template <int TT, int F, bool KF32>
+template <int TT, int F, bool KF32, bool CPRE>
 struct FusedLds {
   static constexpr int P = 4 * TT + 7;
   static constexpr int P3 = P * P * P;
   static constexpr int W = TT + 2;
   static constexpr int NS = W * W * W;
-  static constexpr int NCB = 2;                        // coarser leaves prolongated per batch
+  static constexpr int NCB = 4;                        // coarser leaves prolongated per batch
   using LT = typename std::conditional<KF32, float, double>::type;
   LT Y[F * P3];
   int32_t sl[2 * (2 * NS + 27)];  // slot table + work lists
@@ -334,9 +334,12 @@ struct FusedLds {
   double wsh[16];
   double lag[45];
   double ref[F];
-  double Yc[NCB * F * 125];       // stage values of coarser source leaves
-  double T1[NCB * F * 225];       // ... interpolated along x: [x2 0..8][ky][kz]
-  double T2[NCB * F * 405];       // ... and along y: [x2][y2 0..8][kz]
+  static constexpr int G3 = (4 * TT + 1) * (4 * TT + 1) * (4 * TT + 1);
+  // in-kernel prolongation (CPRE = false): stage values of coarser source leaves
+  // and their interpolation along x, [x2 0..8][ky][kz]; T1 also holds the stencil
+  // results.  With the ghost pre-pass (CPRE) only the results.
+  double Yc[CPRE ? 1 : NCB * F * 125];
+  double T1[CPRE ? F * G3 : NCB * F * 225];
 };
 
 // The arrays and schedule position of the simulation a tile belongs to.
@@ -362,15 +365,15 @@ struct SimView {
 //   (3) the stencils run once per tile grid point; K_s (and the RK update at the
 //       last stage) are written to every DG node of the tile's contiguous octants.
 // sp holds the stage (weights, masks), v the tile's simulation.
-template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const StageParams& sp, const SimView& v,
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, bool CPRE>
+__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, CPRE>& L, const StageParams& sp, const SimView& v,
                                            int n4, const int32_t* __restrict__ tile,
-                                           const int32_t* __restrict__ slots) {
+                                           const int32_t* __restrict__ slots, const double* __restrict__ cs) {
   constexpr int P = 4 * TT + 7;
   constexpr int P3 = P * P * P;
   constexpr int W = TT + 2;
   constexpr int NS = W * W * W;
-  constexpr int NCB = FusedLds<TT, F, KF32>::NCB;
+  constexpr int NCB = FusedLds<TT, F, KF32, CPRE>::NCB;
   constexpr int UB = 2;                      // points per thread loaded together
   using LT = typename std::conditional<KF32, float, double>::type;
   using KT = typename std::conditional<KF32, float, double>::type;
@@ -382,7 +385,6 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   auto& ref = L.ref;
   auto& Yc = L.Yc;
   auto& T1 = L.T1;
-  auto& T2 = L.T2;
   const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
   const KT* __restrict__ Kr = (const KT*)v.K;
@@ -421,14 +423,21 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     }
     __syncthreads();
     const int32_t* lst_cleaf = sl + 2 * (nent - ncl);
+    const int ncs = (counts >> 16) & 255;
+    const int32_t* lst_cslot = sl + 2 * (NS + (counts & 255) + ((counts >> 8) & 255));
 
-    // (1) same-level and finer sources
+    // prefetching the last stage's RK operands pays for the FP64 wave equation
+    // (6 fields would spill; FP32 tiles would lose a resident workgroup per CU)
+    constexpr bool PF = F <= 2 && !KF32;
+
+    // (1) same-level and finer sources (and, with the ghost pre-pass, the
+    // prolongated coarser ghosts)
     for (int p0 = threadIdx.x; p0 < P3; p0 += UB * NT) {
-      int pidx[UB], kind[UB], leaf[UB], nuv[UB][3];
+      int pidx[UB], kind[UB], leaf[UB], kbv[UB], nuv[UB][3];
       #pragma unroll
       for (int u = 0; u < UB; ++u) {
         const int pi = p0 + u * NT;
-        kind[u] = SRC_COARSE;
+        kind[u] = -1;
         pidx[u] = pi;
         if (pi >= P3) continue;
         const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
@@ -437,20 +446,29 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         nuv[u][0] = ax >> 3;
         nuv[u][1] = ay >> 3;
         nuv[u][2] = az >> 3;
-        kind[u] = sl[2 * si + 1] & 15;
+        kbv[u] = sl[2 * si + 1];
+        kind[u] = kbv[u] & 15;
         leaf[u] = sl[2 * si];
       }
       double uu[UB][F], kk[UB][F][4];
       #pragma unroll
       for (int u = 0; u < UB; ++u) {
-        if (kind[u] != SRC_SAME) continue;
-        const uint32_t off = (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]);
-        #pragma unroll
-        for (int f = 0; f < F; ++f) {
-          uu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
+        if (kind[u] == SRC_SAME) {
+          const uint32_t off = (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]);
           #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
+          for (int f = 0; f < F; ++f) {
+            uu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
+            #pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
+          }
+        } else if (CPRE && kind[u] == SRC_COARSE) {
+          // ghost-table entry (in the slot's first int), octant beta of the leaf
+          const int beta = (kbv[u] >> 4) & 7;
+          const int x2 = 4 * (beta & 1) + nuv[u][0], y2 = 4 * ((beta >> 1) & 1) + nuv[u][1],
+                    z2 = 4 * ((beta >> 2) & 1) + nuv[u][2];
+          #pragma unroll
+          for (int f = 0; f < F; ++f) uu[u][f] = cs[((int64_t)leaf[u] * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
         }
       }
       #pragma unroll
@@ -476,13 +494,19 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
               if ((KS >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
             Y[f * P3 + pidx[u]] = (LT)(uu[u][f] + c.dt * acc - ref[f]);
           }
+        } else if (CPRE && kind[u] == SRC_COARSE) {
+          #pragma unroll
+          for (int f = 0; f < F; ++f) Y[f * P3 + pidx[u]] = (LT)(uu[u][f] - ref[f]);
         }
       }
     }
     // (2) coarser sources: stage the distinct leaves (NCB at a time), prolongate
-    // each separably on its half-node grid (x, then y; the same sums, in the
-    // same order, as the direct tensor interpolation), finish along z per point
-    for (int b0 = 0; b0 < ncl; b0 += NCB) {
+    // each along x on its half-node grid, then finish y and z per point.  The
+    // sums and their order are those of the separable prolongation x, y, z (and
+    // of the direct tensor form with x innermost).  Only the points of the tile's
+    // coarser slots are visited: slot position s and node offset nu per axis,
+    // nu within the range the location rule gives that slot.
+    for (int b0 = 0; b0 < (CPRE ? 0 : ncl); b0 += NCB) {
       const int nb = min(NCB, ncl - b0);
       if (b0 > 0) __syncthreads();   // previous batch's points done
       for (int e = threadIdx.x; e < nb * F * 125; e += NT) {
@@ -490,7 +514,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         const int f = rem / 125, n = rem - 125 * f;
         const uint32_t off = (uint32_t)(lst_cleaf[2 * (b0 + k)] * 125 + n);
         double acc = 0.0;
-        #pragma unroll
+#pragma unroll
         for (int i = 0; i < 4; ++i)
           if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
         Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
@@ -503,7 +527,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         double tx;
         if (x2 & 1) {
           tx = 0.0;
-          #pragma unroll
+#pragma unroll
           for (int kx = 0; kx < 5; ++kx) tx = fma(lag[5 * x2 + kx], yc[kx], tx);
         } else {
           tx = fma(1.0, yc[x2 >> 1], 0.0);
@@ -511,60 +535,88 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         T1[e] = tx;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < nb * F * 405; e += NT) {
-        const int kf = e / 405, r = e - 405 * kf;
-        const int x2 = r / 45, r2 = r - 45 * x2;
-        const int y2 = r2 / 5, kz = r2 - 5 * y2;
-        const double* t1 = T1 + kf * 225 + 25 * x2 + 5 * kz;   // [ky] stride 1
-        double ty;
-        if (y2 & 1) {
-          ty = 0.0;
-          #pragma unroll
-          for (int ky = 0; ky < 5; ++ky) ty = fma(lag[5 * y2 + ky], t1[ky], ty);
-        } else {
-          ty = fma(1.0, t1[y2 >> 1], 0.0);
-        }
-        T2[e] = ty;
-      }
-      __syncthreads();
-      for (int pi = threadIdx.x; pi < P3; pi += NT) {
-        const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
-        const int ax = axl[0][qx], ay = axl[1][qy], az = axl[2][qz];
-        const int si = (ax & 7) + W * ((ay & 7) + W * (az & 7));
+      for (int e = threadIdx.x; e < ncs * 125; e += NT) {
+        const int k = e / 125, r = e - 125 * k;
+        const int si = lst_cslot[2 * k];
         const int kb = sl[2 * si + 1];
-        if ((kb & 15) != SRC_COARSE) continue;
         const int cidx = kb >> 8;
         if (cidx < b0 || cidx >= b0 + nb) continue;
+        const int s3[3] = {si % W, (si / W) % W, si / (W * W)};
+        const int o3[3] = {c.ox, c.oy, c.oz};
+        const int nu3[3] = {r % 5, (r / 5) % 5, r / 25};
+        bool own = true;
+        int q3[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          int lo, hi;
+          owned_range(s3[d], o3[d], TT, c.m, lo, hi);
+          own = own && nu3[d] >= lo && nu3[d] <= hi;
+          q3[d] = 4 * (s3[d] - 1) + nu3[d] + 3;
+        }
+        if (!own) continue;
+        const int pi = (q3[2] * P + q3[1]) * P + q3[0];
         const int beta = (kb >> 4) & 7;
-        const int x2 = 4 * (beta & 1) + (ax >> 3), y2 = 4 * ((beta >> 1) & 1) + (ay >> 3),
-                  z2 = 4 * ((beta >> 2) & 1) + (az >> 3);
-        #pragma unroll
+        const int x2 = 4 * (beta & 1) + nu3[0], y2 = 4 * ((beta >> 1) & 1) + nu3[1],
+                  z2 = 4 * ((beta >> 2) & 1) + nu3[2];
+#pragma unroll
         for (int f = 0; f < F; ++f) {
-          const double* t2 = T2 + ((cidx - b0) * F + f) * 405 + 45 * x2 + 5 * y2;   // [kz]
+          const double* t1 = T1 + ((cidx - b0) * F + f) * 225 + 25 * x2;   // [ky + 5 kz]
+          // along y at each kz, then along z
+          auto ty = [&](int kz) {
+            const double* col = t1 + 5 * kz;
+            double v;
+            if (y2 & 1) {
+              v = 0.0;
+#pragma unroll
+              for (int ky = 0; ky < 5; ++ky) v = fma(lag[5 * y2 + ky], col[ky], v);
+            } else {
+              v = fma(1.0, col[y2 >> 1], 0.0);
+            }
+            return v;
+          };
           double v;
           if (z2 & 1) {
             v = 0.0;
-            #pragma unroll
-            for (int kz = 0; kz < 5; ++kz) v = fma(lag[5 * z2 + kz], t2[kz], v);
+#pragma unroll
+            for (int kz = 0; kz < 5; ++kz) v = fma(lag[5 * z2 + kz], ty(kz), v);
           } else {
-            v = fma(1.0, t2[z2 >> 1], 0.0);
+            v = fma(1.0, ty(z2 >> 1), 0.0);
           }
           Y[f * P3 + pi] = (LT)(v - ref[f]);
         }
       }
     }
     __syncthreads();
+    // last stage: U0 and the earlier stages at this thread's zip nodes, issued
+    // before the stencils so that their latency overlaps them
+    constexpr int NN = TT * TT * TT * 125;
+    constexpr int KZ = (NN + NT - 1) / NT;
+    double zu[KZ][F], zk[KZ][F][3];
+#pragma unroll
+    for (int u = 0; u < KZ; ++u) {
+      const int e = threadIdx.x + u * NT;
+      const bool on = PF && last && e < NN;
+      const uint32_t off = (uint32_t)(first * 125 + (e < NN ? e : 0));
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        zu[u][f] = on ? ld32(Us + (uint32_t)(f * fsz), off) : 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          zk[u][f][i] = (on && i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
+      }
+    }
     // (3a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
     // (the coarse prolongation buffer is free by now)
     constexpr int G = 4 * TT + 1;
     constexpr int G3 = G * G * G;
-    static_assert(NCB * F * 405 >= F * G3, "grid result buffer");
-    double* R = T2;
+    static_assert(NCB * F * 225 >= F * G3, "grid result buffer");
+    double* R = T1;
     for (int gi = threadIdx.x; gi < G3; gi += NT) {
       const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
       const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
       double k[F];
-      rhs_point<LT, EQ, F>(Y, P3, ci, P, P * P, (LT)c.h, (LT)v.sigma, ref, k);
+      // one axis at a time: fewer live registers (same operations, same order)
+      rhs_at<LT, EQ, F, true>(StridedAt<LT>{Y, P3, ci, P, P * P}, (LT)c.h, (LT)v.sigma, ref, k);
       #pragma unroll
       for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
     }
@@ -572,23 +624,28 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     // (3b) zip: every DG node of the tile's (contiguous) octants takes its grid
     // value; node e of the tile is element first*125 + e of every field array;
     // the last stage also forms the RK update
-    constexpr int NN = TT * TT * TT * 125;
-    for (int e = threadIdx.x; e < NN; e += NT) {
+    double bs = sp.b[0];   // b_s without a dynamic index into the kernel arguments
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+      if (i == sp.stage) bs = sp.b[i];
+#pragma unroll
+    for (int u = 0; u < KZ; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (e >= NN) continue;
       const uint32_t off = (uint32_t)(first * 125 + e);
-      double u0[F], kprev[F][4];
-      if (last) {
-        #pragma unroll
+      if (!PF && last) {
+#pragma unroll
         for (int f = 0; f < F; ++f) {
-          u0[f] = ld32(Us + (uint32_t)(f * fsz), off);
-          #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            kprev[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
+          zu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+            zk[u][f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
         }
       }
       const int o = e / 125, node = e - 125 * (e / 125);
       const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
       const int gi = ((4 * ((o >> 2) & 1) + cc) * G + (4 * ((o >> 1) & 1) + b)) * G + (4 * (o & 1) + a);
-      #pragma unroll
+#pragma unroll
       for (int f = 0; f < F; ++f) {
         double kv = R[f * G3 + gi];
         if constexpr (KF32) {
@@ -599,30 +656,43 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
           st32(Kw + (uint32_t)(f * fsz), off, kv);
         }
         if (last) {
-          // compute_step_partial: U_new = U0 + dt sum_i b_i K_i into the other buffer
+          // compute_step_partial: U_new = U0 + dt (b_0 K_0 + ... + b_s K_s),
+          // s = p - 1, accumulated in stage order, into the other buffer
           double acc = 0.0;
-          #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (i < sp.p) acc = fma(sp.b[i], (i == sp.stage) ? kv : kprev[f][i], acc);
-          }
-          st32(Uw1 + (uint32_t)(f * fsz), off, u0[f] + c.dt * acc);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+            if (i < sp.stage) acc = fma(sp.b[i], zk[u][f][i], acc);
+          acc = fma(bs, kv, acc);
+          st32(Uw1 + (uint32_t)(f * fsz), off, zu[u][f] + c.dt * acc);
         }
       }
     }
 }
 
-template <int TT, int F, bool KF32>
-__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const StageParams& sp) {
+template <int TT, int F, bool KF32, bool CPRE>
+__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32, CPRE>& L, const StageParams& sp) {
   if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
   if (threadIdx.x < 45) L.lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
 }
 
+// Waves per SIMD that the LDS of one workgroup allows: the register budget the
+// compiler is asked to keep so that registers do not cost occupancy.  Capped at
+// 6 (80 registers), and left free for 6 fields, where a tighter budget spills.
+template <int TT, int F, bool KF32, bool CPRE, int NT>
+constexpr int fused_waves_per_eu() {
+  const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32, CPRE>);
+  const int w = wg * (NT / 64) / 4;
+  return (F > 2 || w < 1) ? 1 : (w > 6 ? 6 : w);
+}
+
 // One mesh: workgroups are dealt to the 8 XCDs round robin; XCD x walks its own
-// contiguous (Morton-ordered, cost-balanced) range of tiles.
+// contiguous (Morton-ordered, cost-balanced) range of tiles.  Coarser ghosts come
+// prolongated from the ghost-table pre-pass (scr).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __restrict__ tiles,
-                                              const int32_t* __restrict__ slots, XcdRanges xr) {
-  __shared__ FusedLds<TT, F, KF32> L;
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, true, NT>())))
+void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* __restrict__ slots,
+             const double* __restrict__ scr, XcdRanges xr) {
+  __shared__ FusedLds<TT, F, KF32, true> L;
   fused_init(L, sp);
   const int n4 = (int)(*sp.step & 3);
   const int nslot = gridDim.x >> 3;
@@ -630,7 +700,7 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
   const int sid = blockIdx.x >> 3;
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
   for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot)
-    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots);
+    fused_tile<TT, F, EQ, KF32, NT, KS, true>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots, scr);
 }
 
 // Several independent meshes advanced together (continuous batching): in round r
@@ -638,11 +708,12 @@ __global__ __launch_bounds__(NT) void k_fused(StageParams sp, const int32_t* __r
 // stage covers the union of the active tiles of side TT of all of them, in table
 // order.  Union tile t belongs to the simulation whose cumulative-count range
 // holds it; the union is cut into 8 contiguous ranges, one per XCD.  The
-// arithmetic of every tile is that of the one-mesh kernel.
+// arithmetic of every tile is that of the one-mesh kernel (coarser ghosts are
+// prolongated in the kernel, with the pre-pass's sums in the pre-pass's order).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
 __global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims,
                                                     const int64_t* __restrict__ round) {
-  __shared__ FusedLds<TT, F, KF32> L;
+  __shared__ FusedLds<TT, F, KF32, false> L;
   __shared__ int cum[kMaxBatch + 1];
   fused_init(L, sp0);
   const int64_t r = *round;
@@ -681,8 +752,8 @@ __global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const Batch
     const int dl = b.lmax - b.lmin;
     const SimView v{b.U, b.U, b.K, b.K, b.N, b.lmin, b.lmax, (int)(rr & ((1 << dl) - 1)), b.sigma};
     const int n4 = (int)((b.n0 + (rr >> dl)) & 3);
-    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
-                                        b.slots[TT - 1]);
+    fused_tile<TT, F, EQ, KF32, NT, KS, false>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
+                                               b.slots[TT - 1], nullptr);
   }
 }
 
@@ -694,15 +765,16 @@ __global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const Batch
 // of output plane z run.  Gathered points per DG node drop from 3.4 (side-2
 // tiles) to 1.5.
 
-// Coarser ghosts of side-4 tiles, before the streamed stage: pair q = (tile,
-// cidx) gets the stage state of the tile's cidx-th distinct coarser source leaf
-// prolongated to its 9^3 half-node grid, scr[q][f][z2][y2][x2].  The sums and
-// their order are those of the fused kernel's separable prolongation, so a ghost
-// has the same value whichever kernel computes it.
+// Ghost-table pre-pass, before the fused launches of a stage: entry g (a leaf
+// that is a coarser source of receivers one level finer) gets its stage state
+// for those receivers (time case, buffer and dt of the receiver level, eqs.
+// fc_1/fc_2) prolongated to its 9^3 half-node grid, scr[g][f][z2][y2][x2].  The
+// prolongation is separable, x, then y, then z, each a degree-4 Lagrange sum in
+// node order (the in-kernel prolongation of the batched kernel adds the same
+// terms in the same order, so a ghost has one value whichever kernel forms it).
 template <bool KF32, int F>
-__global__ __launch_bounds__(256) void k_coarse_pre(StageParams sp, const int32_t* __restrict__ tiles,
-                                                    const int32_t* __restrict__ slots,
-                                                    const int32_t* __restrict__ pairs, double* __restrict__ scr) {
+__global__ __launch_bounds__(256) void k_ghost_pre(StageParams sp, const int32_t* __restrict__ ghosts,
+                                                   double* __restrict__ scr) {
   using KT = typename std::conditional<KF32, float, double>::type;
   __shared__ double wsh[16];
   __shared__ double lag[45];
@@ -711,19 +783,12 @@ __global__ __launch_bounds__(256) void k_coarse_pre(StageParams sp, const int32_
   __shared__ double T2[F * 405];
   if (threadIdx.x < 16) wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
   if (threadIdx.x < 45) lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
-  const int q = blockIdx.x;
-  const int ti = __builtin_amdgcn_readfirstlane(pairs[2 * q]);
-  const int k = __builtin_amdgcn_readfirstlane(pairs[2 * q + 1]);
-  int32_t trec[8];
-  #pragma unroll
-  for (int e = 0; e < 8; ++e) trec[e] = __builtin_amdgcn_readfirstlane(tiles[8 * (int64_t)ti + e]);
-  const int32_t* t = trec;
-  const TileCtx c = tile_ctx(t, sp, (int)(*sp.step & 3));
-  const int counts = t[TI_COUNTS];
-  const int ncl = (counts >> 24) & 255;
-  const int ns = (c.tt + 2) * (c.tt + 2) * (c.tt + 2);
-  const int nent = ns + (counts & 255) + ((counts >> 8) & 255) + ((counts >> 16) & 255) + ncl;
-  const int leaf = __builtin_amdgcn_readfirstlane(slots[2 * ((int64_t)t[TI_SLOT] + nent - ncl + k)]);
+  const int g = blockIdx.x;
+  const int leaf = __builtin_amdgcn_readfirstlane(ghosts[2 * g]);
+  // a receiver tile of the entry's receiver level (only its level matters here)
+  int32_t trec[8] = {0, 0, 0, 1, 1, 0, 0, 0};
+  trec[TI_LEVEL] = __builtin_amdgcn_readfirstlane(ghosts[2 * g + 1]);
+  const TileCtx c = tile_ctx(trec, sp, (int)(*sp.step & 3));
   const int fsz = (int)(sp.N * 125);
   const double* __restrict__ Uc = sp.U + (int64_t)c.par_coarse * F * fsz;
   const KT* __restrict__ Kr = (const KT*)sp.K;
@@ -771,7 +836,7 @@ __global__ __launch_bounds__(256) void k_coarse_pre(StageParams sp, const int32_
     T2[e] = ty;
   }
   __syncthreads();
-  double* out = scr + (int64_t)q * F * 729;
+  double* out = scr + (int64_t)g * F * 729;
   for (int e = threadIdx.x; e < F * 729; e += 256) {
     const int f = e / 729, r = e - 729 * f;
     const int z2 = r / 81, y2 = (r / 9) % 9, x2 = r % 9;
@@ -838,7 +903,7 @@ struct StreamCtx {
   double* Uw1;           // the other U buffer (RK update)
   const KT* Kr;          // stages
   KT* Kw;                // K_s
-  const double* cs;      // prolongated coarser ghosts of this block
+  const double* cs;      // ghost table (prolongated coarser ghosts)
   const double* wf;      // weights of finer sources (LDS)
   double dt, h, sigma;
   int fsz, first, kmf;
@@ -873,7 +938,7 @@ __device__ __forceinline__ void stream_issue(const StreamLds<F, KF32>& L, const 
     const uint32_t off = (uint32_t)((leaf + cx + 2 * cy + 4 * czz) * 125 + sc * (nux - 2 * cx) +
                                     5 * sc * (nuy - 2 * cy) + 25 * sc * (nuz - 2 * czz));
     // coarser: the prolongated ghost in scr
-    const int beta = (kb >> 4) & 7, cidx = kb >> 8;
+    const int beta = (kb >> 4) & 7;   // coarser: leaf = the ghost-table entry
     const int x2 = 4 * (beta & 1) + nux, y2 = 4 * ((beta >> 1) & 1) + nuy, z2 = 4 * ((beta >> 2) & 1) + nuz;
     const int km = (!on || coarse) ? 0 : (fine ? x.kmf : KS);
     Q.kind[u] = on ? kind : -1;
@@ -881,7 +946,7 @@ __device__ __forceinline__ void stream_issue(const StreamLds<F, KF32>& L, const 
     for (int f = 0; f < F; ++f) {
       double uv = 0.0;
       if (on) {
-        if (coarse) uv = x.cs[((int64_t)cidx * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
+        if (coarse) uv = x.cs[((int64_t)leaf * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
         else uv = ld32((fine ? x.Uf : x.Us) + (uint32_t)(f * x.fsz), off);
       }
       Q.uu[u][f] = uv;
@@ -1098,8 +1163,8 @@ __device__ __forceinline__ void stream_tile(StreamLds<F, KF32>& L, const StagePa
 
 template <int F, int EQ, bool KF32, int NT, int KS, bool LAST>
 __global__ __launch_bounds__(NT) void k_stream(StageParams sp, const int32_t* __restrict__ tiles,
-                                               const int32_t* __restrict__ slots, const int32_t* __restrict__ cbase,
-                                               const double* __restrict__ scr, XcdRanges xr) {
+                                               const int32_t* __restrict__ slots, const double* __restrict__ scr,
+                                               XcdRanges xr) {
   __shared__ StreamLds<F, KF32> L;
   if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
   const int n4 = (int)(*sp.step & 3);
@@ -1107,11 +1172,8 @@ __global__ __launch_bounds__(NT) void k_stream(StageParams sp, const int32_t* __
   const int xcd = blockIdx.x & 7;
   const int sid = blockIdx.x >> 3;
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
-  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot) {
-    const int cb = __builtin_amdgcn_readfirstlane(cbase[ti]);
-    stream_tile<F, EQ, KF32, NT, KS, LAST>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots,
-                                           scr + (int64_t)cb * F * 729);
-  }
+  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot)
+    stream_tile<F, EQ, KF32, NT, KS, LAST>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots, scr);
 }
 
 // ------------------------------------------------------------------ standalone kernels
@@ -1343,6 +1405,7 @@ namespace {
 struct OneArgs {
   const int32_t* tiles;
   const int32_t* slots;
+  const double* scr;
   XcdRanges xr;
 };
 struct BatchArgs {
@@ -1357,7 +1420,7 @@ struct BatchArgs {
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
 static hipError_t go(const StageParams& sp, const OneArgs& a, int max_wg, hipStream_t s) {
   hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32, NT, KS>), dim3(fused_grid(a.xr.b[8], max_wg)), dim3(NT), 0, s, sp,
-                     a.tiles, a.slots, a.xr);
+                     a.tiles, a.slots, a.scr, a.xr);
   return hipGetLastError();
 }
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
@@ -1408,9 +1471,26 @@ static hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& s
 }
 
 hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
-                        const int32_t* slots, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s) {
+                        const int32_t* slots, const double* scr, const XcdRanges& xr, const LaunchShape& ls,
+                        hipStream_t s) {
   if (xr.b[8] <= 0) return hipSuccess;
-  return dispatch_fused(tt, eq, kf32, sp, OneArgs{tiles, slots, xr}, ls, s);
+  return dispatch_fused(tt, eq, kf32, sp, OneArgs{tiles, slots, scr, xr}, ls, s);
+}
+
+hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32_t* ghosts, int64_t n, double* scr,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)n);
+  if (F == 2) {
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 2>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    else hipLaunchKernelGGL((k_ghost_pre<false, 2>), grid, dim3(256), 0, s, sp, ghosts, scr);
+  } else if (F == 6) {
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    else hipLaunchKernelGGL((k_ghost_pre<false, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
@@ -1420,52 +1500,41 @@ hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0,
   return dispatch_fused(tt, eq, kf32, sp0, BatchArgs{sims, nsims, round, total}, ls, s);
 }
 
-// Streamed side-4 tiles (wave equation): coarser-ghost pre-pass, then the
-// streaming kernel over the launch's tiles.
+// Streamed side-4 tiles (wave equation), after the ghost pre-pass.
 template <bool KF32, int NT, int KS>
-static hipError_t go_stream(const StageParams& sp, const int32_t* tiles, const int32_t* slots, const int32_t* cbase,
-                            const double* scr, const XcdRanges& xr, int max_wg, hipStream_t s) {
+static hipError_t go_stream(const StageParams& sp, const int32_t* tiles, const int32_t* slots, const double* scr,
+                            const XcdRanges& xr, int max_wg, hipStream_t s) {
   const dim3 grid(fused_grid(xr.b[8], max_wg));
   if (sp.stage == sp.p - 1)
-    hipLaunchKernelGGL((k_stream<2, LTS_EQ_WAVE, KF32, NT, KS, true>), grid, dim3(NT), 0, s, sp, tiles, slots, cbase,
-                       scr, xr);
+    hipLaunchKernelGGL((k_stream<2, LTS_EQ_WAVE, KF32, NT, KS, true>), grid, dim3(NT), 0, s, sp, tiles, slots, scr, xr);
   else
-    hipLaunchKernelGGL((k_stream<2, LTS_EQ_WAVE, KF32, NT, KS, false>), grid, dim3(NT), 0, s, sp, tiles, slots, cbase,
-                       scr, xr);
+    hipLaunchKernelGGL((k_stream<2, LTS_EQ_WAVE, KF32, NT, KS, false>), grid, dim3(NT), 0, s, sp, tiles, slots, scr,
+                       xr);
   return hipGetLastError();
 }
 
 template <bool KF32, int NT>
-static hipError_t stream_ks(const StageParams& sp, const int32_t* tiles, const int32_t* slots, const int32_t* cbase,
-                            const double* scr, const XcdRanges& xr, int max_wg, hipStream_t s) {
+static hipError_t stream_ks(const StageParams& sp, const int32_t* tiles, const int32_t* slots, const double* scr,
+                            const XcdRanges& xr, int max_wg, hipStream_t s) {
   switch (sp.kmask[0]) {
-    case 0: return go_stream<KF32, NT, 0>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
-    case 1: return go_stream<KF32, NT, 1>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
-    case 2: return go_stream<KF32, NT, 2>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
-    case 3: return go_stream<KF32, NT, 3>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
-    case 4: return go_stream<KF32, NT, 4>(sp, tiles, slots, cbase, scr, xr, max_wg, s);
+    case 0: return go_stream<KF32, NT, 0>(sp, tiles, slots, scr, xr, max_wg, s);
+    case 1: return go_stream<KF32, NT, 1>(sp, tiles, slots, scr, xr, max_wg, s);
+    case 2: return go_stream<KF32, NT, 2>(sp, tiles, slots, scr, xr, max_wg, s);
+    case 3: return go_stream<KF32, NT, 3>(sp, tiles, slots, scr, xr, max_wg, s);
+    case 4: return go_stream<KF32, NT, 4>(sp, tiles, slots, scr, xr, max_wg, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_stream(int eq, bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
-                         const int32_t* pairs, int64_t npairs, const int32_t* cbase, double* scr, const XcdRanges& xr,
-                         const LaunchShape& ls, hipStream_t s) {
+                         const double* scr, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s) {
   if (xr.b[8] <= 0) return hipSuccess;
   if (eq != LTS_EQ_WAVE) return hipErrorInvalidValue;   // 6 fields do not fit the plane ring
-  if (npairs > 0) {
-    if (kf32) hipLaunchKernelGGL((k_coarse_pre<true, 2>), dim3((unsigned)npairs), dim3(256), 0, s, sp, tiles, slots,
-                                 pairs, scr);
-    else hipLaunchKernelGGL((k_coarse_pre<false, 2>), dim3((unsigned)npairs), dim3(256), 0, s, sp, tiles, slots,
-                            pairs, scr);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   switch (ls.stream_threads) {
-    case 256: return kf32 ? stream_ks<true, 256>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s)
-                          : stream_ks<false, 256>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s);
-    case 512: return kf32 ? stream_ks<true, 512>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s)
-                          : stream_ks<false, 512>(sp, tiles, slots, cbase, scr, xr, ls.max_wg, s);
+    case 256: return kf32 ? stream_ks<true, 256>(sp, tiles, slots, scr, xr, ls.max_wg, s)
+                          : stream_ks<false, 256>(sp, tiles, slots, scr, xr, ls.max_wg, s);
+    case 512: return kf32 ? stream_ks<true, 512>(sp, tiles, slots, scr, xr, ls.max_wg, s)
+                          : stream_ks<false, 512>(sp, tiles, slots, scr, xr, ls.max_wg, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -30,7 +30,9 @@ enum { SRC_OWN = 0, SRC_SAME = 1, SRC_FINE = 2, SRC_COARSE = 3 };
 // same-level slots | finer slots << 8 | coarser slots << 16 | coarser leaves << 24
 enum { TI_FIRST = 0, TI_COUNTS = 1, TI_LEVEL = 2, TI_M = 3, TI_TT = 4, TI_OFF = 5, TI_SLOT = 6, TI_BLOCK = 7 };
 // slot record: int32[2] = leaf, kind | beta << 4 | cidx << 8 (cidx: index of a
-// coarser source leaf in the tile's list of distinct coarser leaves)
+// coarser source leaf in the tile's list of distinct coarser leaves).  In the
+// tile sets of the fused kernels a coarser slot's first int is the coarser
+// leaf's ghost-table entry instead (the tile's list keeps (leaf, entry) pairs).
 
 LTS_HD uint32_t part1by2(uint32_t v) {
   uint32_t r = 0;

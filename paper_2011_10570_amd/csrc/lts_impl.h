@@ -28,16 +28,8 @@ struct TileSet {
   // per lowest active level l: the prefix [0, n_ge[l]) cut into 8 contiguous
   // ranges of equal estimated cost (one per XCD): xcd[l][0..8]
   std::vector<std::vector<int32_t>> xcd;
-  // side-4 tiles only (streamed whole blocks): the (tile, distinct coarser leaf)
-  // pairs whose prolongation a pre-pass writes to scratch, in tile order;
-  // cbase[t] = first pair of tile t; pair_ge[l] = pairs of tiles with level >= l
-  std::vector<int32_t> pairs;   // [Q][2] = tile, cidx
-  std::vector<int32_t> cbase;
-  std::vector<int64_t> pair_ge;
   int32_t* d_tiles = nullptr;
   int32_t* d_slots = nullptr;
-  int32_t* d_pairs = nullptr;
-  int32_t* d_cbase = nullptr;
   int64_t count() const { return (int64_t)tiles.size() / 8; }
 };
 
@@ -50,6 +42,14 @@ struct Mesh {
   std::vector<int32_t> block_of_leaf;
   int tile = 2;
   TileSet ts[5];                      // ts[t]: tiles of side t (1, 2, 4)
+  // Ghost table: every leaf that is a coarser source of some fused tile, with the
+  // level of its receivers (its own level + 1), ordered by receiver level
+  // (finest first); ghost_ge[l] = entries with receiver level >= l.  The
+  // prolongation pre-pass writes entry g's stage state on its 9^3 half-node grid
+  // to scratch g; a tile's list of distinct coarser leaves holds (leaf, g).
+  std::vector<int32_t> ghosts;        // [E][2] = leaf, receiver level
+  std::vector<int64_t> ghost_ge;
+  int32_t* d_ghosts = nullptr;
   TileSet bt;                         // one tile per block (standalone kernels)
   bool uploaded = false;
   int device = -1;

@@ -52,19 +52,24 @@ struct BatchSim {
   int32_t n_ge[2][LTS_MAX_LEVEL + 1];  // tiles of side t+1 with level >= l
 };
 
+// One stage over tiles of side tt (1 or 2) in LDS; coarser ghosts are read from
+// the ghost table scr, which launch_ghost_pre has filled for this stage.
 hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const int32_t* tiles,
-                        const int32_t* slots, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s);
+                        const int32_t* slots, const double* scr, const XcdRanges& xr, const LaunchShape& ls,
+                        hipStream_t s);
+// Ghost-table pre-pass of one stage: entries [0, n) (leaf, receiver level) of
+// ghosts, prolongated to scr[g][F][729].
+hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32_t* ghosts, int64_t n, double* scr,
+                            hipStream_t s);
 // One stage of the round *round (device counter) for the simulations
 // sims[0..nsims) (device table); `total` bounds the union of their active side-tt
 // tiles and sizes the grid (host-computed; any larger value is correct too).
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
                               const int64_t* round, int64_t total, const LaunchShape& ls, hipStream_t s);
-// Streamed whole 4^3 blocks (side-4 tiles, wave equation): the coarser-ghost
-// pre-pass over pairs[0..npairs) into scr, then the streaming kernel over the
-// launch's tiles (XCD ranges as for launch_fused).
+// Streamed whole 4^3 blocks (side-4 tiles, wave equation) over the launch's
+// tiles (XCD ranges as for launch_fused), ghosts from the ghost table scr.
 hipError_t launch_stream(int eq, bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
-                         const int32_t* pairs, int64_t npairs, const int32_t* cbase, double* scr, const XcdRanges& xr,
-                         const LaunchShape& ls, hipStream_t s);
+                         const double* scr, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s);
 hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s);
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
                         const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);

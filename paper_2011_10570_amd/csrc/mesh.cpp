@@ -445,37 +445,73 @@ void finish_levels(TileSet& ts) {
 
 }  // namespace
 
-// Side-4 tiles: the coarser-leaf prolongation pairs of each tile (tile order).
-void build_pairs(TileSet& ts) {
-  const int64_t T = ts.count();
-  ts.pairs.clear();
-  ts.cbase.assign(T, 0);
-  for (int64_t i = 0; i < T; ++i) {
-    ts.cbase[i] = (int32_t)(ts.pairs.size() / 2);
-    const int ncl = (ts.tiles[8 * i + TI_COUNTS] >> 24) & 255;
-    for (int k = 0; k < ncl; ++k) {
-      ts.pairs.push_back((int32_t)i);
-      ts.pairs.push_back(k);
+// The ghost table (see Mesh::ghosts) of the current tile sets; the second int of
+// every entry of a tile's list of distinct coarser leaves becomes the leaf's
+// ghost-table index.
+static void build_ghosts(Mesh& m) {
+  std::vector<int32_t> gid(m.n(), -1);
+  std::vector<int32_t> leaves;
+  for (int k : {1, 2, 4}) {
+    TileSet& ts = m.ts[k];
+    for (int64_t i = 0; i < ts.count(); ++i) {
+      const int32_t* t = &ts.tiles[8 * i];
+      const int cnt = t[TI_COUNTS], tt = t[TI_TT];
+      const int ns = (tt + 2) * (tt + 2) * (tt + 2);
+      const int ncl = (cnt >> 24) & 255;
+      const int nent = ns + (cnt & 255) + ((cnt >> 8) & 255) + ((cnt >> 16) & 255) + ncl;
+      for (int c = 0; c < ncl; ++c) {
+        const int32_t leaf = ts.slots[2 * ((int64_t)t[TI_SLOT] + nent - ncl + c)];
+        if (gid[leaf] < 0) {
+          gid[leaf] = 0;
+          leaves.push_back(leaf);
+        }
+      }
     }
   }
-  ts.pair_ge.assign(LTS_MAX_LEVEL + 1, 0);
+  // receiver level = coarser leaf level + 1; finest receivers first, then leaf order
+  std::stable_sort(leaves.begin(), leaves.end(), [&](int32_t a, int32_t b) { return m.lev[a] > m.lev[b]; });
+  m.ghosts.clear();
+  for (size_t g = 0; g < leaves.size(); ++g) {
+    gid[leaves[g]] = (int32_t)g;
+    m.ghosts.push_back(leaves[g]);
+    m.ghosts.push_back(m.lev[leaves[g]] + 1);
+  }
+  m.ghost_ge.assign(LTS_MAX_LEVEL + 1, 0);
   for (int l = 0; l <= LTS_MAX_LEVEL; ++l) {
-    const int64_t n = ts.n_ge[l];   // tiles [0, n) have level >= l
-    ts.pair_ge[l] = n < T ? ts.cbase[n] : (int64_t)(ts.pairs.size() / 2);
+    int64_t c = 0;
+    for (size_t g = 0; g < leaves.size(); ++g) c += m.ghosts[2 * g + 1] >= l ? 1 : 0;
+    m.ghost_ge[l] = c;
+  }
+  for (int k : {1, 2, 4}) {
+    TileSet& ts = m.ts[k];
+    for (int64_t i = 0; i < ts.count(); ++i) {
+      const int32_t* t = &ts.tiles[8 * i];
+      const int cnt = t[TI_COUNTS], tt = t[TI_TT];
+      const int ns = (tt + 2) * (tt + 2) * (tt + 2);
+      const int ncl = (cnt >> 24) & 255;
+      const int nent = ns + (cnt & 255) + ((cnt >> 8) & 255) + ((cnt >> 16) & 255) + ncl;
+      for (int c = 0; c < ncl; ++c) {
+        const int64_t e = 2 * ((int64_t)t[TI_SLOT] + nent - ncl + c);
+        ts.slots[e + 1] = gid[ts.slots[e]];
+      }
+      // in the slot table itself a coarser slot names its ghost-table entry
+      for (int q = 0; q < ns; ++q) {
+        const int64_t e = 2 * ((int64_t)t[TI_SLOT] + q);
+        if ((ts.slots[e + 1] & 15) == SRC_COARSE) ts.slots[e] = gid[ts.slots[e]];
+      }
+    }
   }
 }
 
 // Tiles of the fused kernels for maximum tile side t (1, 2 or 4): a block of side
 // m is cut into tiles of side min(m, t).  ts[k] holds the side-k tiles, each set
 // ordered finest level first.  Side-4 tiles (whole 4^3 blocks) are streamed plane
-// by plane; their coarser ghosts come from a prolongation pre-pass.
+// by plane.  Coarser ghosts of every side come from the ghost-table pre-pass.
 lts_status build_tiles(Mesh& m, int t) {
   if (t != 1 && t != 2 && t != 4) return fail(LTS_EINVAL, "tile side must be 1, 2 or 4");
   for (int k = 1; k <= 4; ++k) {
     m.ts[k].tiles.clear();
     m.ts[k].slots.clear();
-    m.ts[k].pairs.clear();
-    m.ts[k].cbase.clear();
   }
   for (size_t b = 0; b < m.blocks.size(); ++b) {
     const Block& B = m.blocks[b];
@@ -488,7 +524,7 @@ lts_status build_tiles(Mesh& m, int t) {
         }
   }
   for (int k : {1, 2, 4}) finish_levels(m.ts[k]);
-  build_pairs(m.ts[4]);
+  build_ghosts(m);
   m.tile = t;
   return LTS_OK;
 }
