@@ -226,66 +226,20 @@ static lts_status ensure_cscr(const Mesh& m, int F, double** p, size_t* cap) {
   return LTS_OK;
 }
 
-// Side streams and events that let the launches of one stage (one per tile side)
-// run concurrently: they read the same inputs and write disjoint octants.
-struct Fork {
-  hipStream_t side[2] = {nullptr, nullptr};
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // fork, join side 0, join side 1
-  bool ok() const { return side[0] && side[1] && ev[0] && ev[1] && ev[2]; }
-};
-
-static hipError_t fork_create(Fork& f) {
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&f.side[k], hipStreamNonBlocking);
-  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&f.ev[k], hipEventDisableTiming);
-  return e;
-}
-
-static void fork_destroy(Fork& f) {
-  for (auto& x : f.side)
-    if (x) (void)hipStreamDestroy(x);
-  for (auto& x : f.ev)
-    if (x) (void)hipEventDestroy(x);
-  f = Fork{};
-}
-
 // Every fused launch of one stage for the tiles of levels >= lo: the ghost-table
 // pre-pass for receivers of levels >= lo, then streamed side-4 tiles, side-2 and
-// side-1 tiles.  With a fork, the side-2 and side-1 launches go to side streams
-// that wait for the work before them on s, and s waits for both before the stage
-// ends (also under graph capture, where the waits become graph edges).
+// side-1 tiles, in stream order.
 static lts_status launch_stage(const Mesh& m, int eq, bool kf32, const StageParams& sp, int lo, double* cscr,
-                               const LaunchShape& ls, hipStream_t s, const Fork* fk = nullptr) {
+                               const LaunchShape& ls, hipStream_t s) {
   HIP_TRY(launch_ghost_pre(sp.F, kf32, sp, m.d_ghosts, m.ghost_ge[lo], cscr, s), "ghost pre-pass");
-  int groups = 0;
-  for (int tt : {4, 2, 1}) groups += m.ts[tt].count() > 0 && m.ts[tt].n_ge[lo] > 0;
-  const bool fork = fk && fk->ok() && groups > 1;
-  if (fork) HIP_TRY(hipEventRecord(fk->ev[0], s), "fork record");
-  int k = 0;
-  bool joined[2] = {false, false};
   for (int tt : {4, 2, 1}) {
     const TileSet& ts = m.ts[tt];
     if (ts.count() == 0 || ts.n_ge[lo] == 0) continue;
     XcdRanges xr;
     for (int x = 0; x < 9; ++x) xr.b[x] = ts.xcd[lo][x];
-    hipStream_t q = s;
-    if (fork && k > 0) {
-      q = fk->side[k - 1];
-      HIP_TRY(hipStreamWaitEvent(q, fk->ev[0], 0), "fork wait");
-    }
-    if (tt == 4) {
-      HIP_TRY(launch_stream(eq, kf32, sp, ts.d_tiles, ts.d_slots, cscr, xr, ls, q), "stream launch");
-    } else {
-      HIP_TRY(launch_fused(tt, eq, kf32, sp, ts.d_tiles, ts.d_slots, cscr, xr, ls, q), "fused launch");
-    }
-    if (fork && k > 0) {
-      HIP_TRY(hipEventRecord(fk->ev[k], q), "join record");
-      joined[k - 1] = true;
-    }
-    ++k;
+    if (tt == 4) HIP_TRY(launch_stream(eq, kf32, sp, ts.d_tiles, ts.d_slots, cscr, xr, ls, s), "stream launch");
+    else HIP_TRY(launch_fused(tt, eq, kf32, sp, ts.d_tiles, ts.d_slots, cscr, xr, ls, s), "fused launch");
   }
-  for (int j = 0; j < 2; ++j)
-    if (joined[j]) HIP_TRY(hipStreamWaitEvent(s, fk->ev[j + 1], 0), "join wait");
   return LTS_OK;
 }
 
@@ -615,7 +569,6 @@ struct lts_sim {
   double* d_coef = nullptr;
   double* d_cscr = nullptr;     // coarser-ghost scratch (side-4 tiles)
   size_t cscr_cap = 0;
-  Fork fork;                     // concurrent launches of one stage
   // continuous batching: the batch the sim is attached to, its round range
   lts_batch* batch = nullptr;
   int slot = -1;
@@ -665,7 +618,7 @@ lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
     for (int st = 0; st < sim->p; ++st) {
       StageParams sp;
       fill_sim_params(sim, st, mode, j, sp);
-      lts_status r = launch_stage(m, sim->eq, sim->prec == LTS_FP32_RHS, sp, lo, sim->d_cscr, g_shape, s, &sim->fork);
+      lts_status r = launch_stage(m, sim->eq, sim->prec == LTS_FP32_RHS, sp, lo, sim->d_cscr, g_shape, s);
       if (r != LTS_OK) return r;
     }
   }
@@ -713,7 +666,6 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
   hipError_t e = hipMalloc(&sim->d_step, sizeof(int64_t));
   if (e == hipSuccess) e = hipMemset(sim->d_step, 0, sizeof(int64_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&sim->cap_stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = fork_create(sim->fork);
   if (e != hipSuccess) {
     lts_sim_destroy(sim);
     return hip_fail(e, "sim create");
@@ -887,7 +839,6 @@ void lts_sim_destroy(lts_sim* sim) {
   if (sim->batch) release_slot(sim->batch, sim, true);
   drop_graphs(sim);
   if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
-  fork_destroy(sim->fork);
   if (sim->d_step) (void)hipFree(sim->d_step);
   for (void* p : sim->ualloc) (void)hipFree(p);
   if (sim->d_pad) (void)hipFree(sim->d_pad);
@@ -1005,6 +956,9 @@ struct lts_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t graph_gen = -1;
+  // ghost tables of the attached sims (sim in slot k at entry desc[k].gbase)
+  double* d_gscr = nullptr;
+  size_t gscr_cap = 0;
 };
 
 namespace {
@@ -1054,6 +1008,20 @@ void drop_batch_graph(lts_batch* b) {
 lts_status upload_table(lts_batch* b, hipStream_t s) {
   if (!b->dirty) return LTS_OK;
   drop_batch_graph(b);
+  // ghost-table regions, in slot order
+  int64_t ge = 0;
+  for (int i = 0; i < b->nused; ++i) {
+    b->desc[i].gbase = ge;
+    if (b->sims[i]) ge += (int64_t)(b->sims[i]->mesh->m.ghosts.size() / 2);
+  }
+  const size_t need = (size_t)ge * b->F * 729 * sizeof(double);
+  if (need > b->gscr_cap) {
+    if (b->d_gscr) (void)hipFree(b->d_gscr);   // waits for the work that used it
+    b->d_gscr = nullptr;
+    b->gscr_cap = 0;
+    HIP_TRY(hipMalloc(&b->d_gscr, need), "hipMalloc batch ghost scratch");
+    b->gscr_cap = need;
+  }
   if (b->nused > 0) {
     if (b->staged_rec) HIP_TRY(hipEventSynchronize(b->staged), "staging wait");
     std::memcpy(b->h_stage, b->desc.data(), b->nused * sizeof(BatchSim));
@@ -1077,8 +1045,8 @@ lts_status finish_rounds(lts_batch* b, lts_sim* sim, int64_t done, hipStream_t s
 
 // Active side-1 / side-2 tiles of round r (exact), or of any round (every
 // attached sim at its lowest level: the bound a captured round is sized for).
-void round_totals(const lts_batch* b, int64_t r, bool any_round, int64_t total[2]) {
-  total[0] = total[1] = 0;
+void round_totals(const lts_batch* b, int64_t r, bool any_round, int64_t total[3]) {
+  total[0] = total[1] = total[2] = 0;
   for (int i = 0; i < b->nused; ++i) {
     const lts_sim* sim = b->sims[i];
     if (!sim) continue;
@@ -1092,17 +1060,23 @@ void round_totals(const lts_batch* b, int64_t r, bool any_round, int64_t total[2
     }
     total[0] += d.n_ge[0][lo];
     total[1] += d.n_ge[1][lo];
+    total[2] += d.ghost_ge[lo];
   }
 }
 
-// The launches of one round: p stages x 2 tile sides, then the round counter.
-lts_status enqueue_round(lts_batch* b, const int64_t total[2], hipStream_t s) {
+// The launches of one round: per stage the ghost pre-pass and the two tile
+// sides, then the round counter.
+lts_status enqueue_round(lts_batch* b, const int64_t total[3], hipStream_t s) {
   const bool kf32 = b->prec == LTS_FP32_RHS;
   for (int stg = 0; stg < b->p; ++stg) {
     StageParams sp;
     fill_batch_params(b, stg, sp);
+    HIP_TRY(launch_ghost_pre_batch(b->F, kf32, sp, b->d_desc, b->nused, b->d_round, total[2], b->d_gscr,
+                                   g_shape.max_wg, s),
+            "batch ghost pre-pass");
     for (int tt = 1; tt <= 2; ++tt)
-      HIP_TRY(launch_fused_batch(tt, b->eq, kf32, sp, b->d_desc, b->nused, b->d_round, total[tt - 1], g_shape, s),
+      HIP_TRY(launch_fused_batch(tt, b->eq, kf32, sp, b->d_desc, b->nused, b->d_round, total[tt - 1], b->d_gscr,
+                                 g_shape, s),
               "batch launch");
   }
   HIP_TRY(launch_increment(b->d_round, s), "round increment");
@@ -1181,6 +1155,8 @@ lts_status lts_batch_attach(lts_batch* b, lts_sim* sim, int64_t n_coarse_steps) 
     d.slots[t] = m.ts[t + 1].d_slots;
     for (int l = 0; l <= LTS_MAX_LEVEL; ++l) d.n_ge[t][l] = (int32_t)m.ts[t + 1].n_ge[l];
   }
+  d.ghosts = m.d_ghosts;
+  for (int l = 0; l <= LTS_MAX_LEVEL; ++l) d.ghost_ge[l] = (int32_t)m.ghost_ge[l];
   d.N = m.n();
   d.r0 = b->round;
   d.rounds = n_coarse_steps << dl;
@@ -1223,7 +1199,7 @@ lts_status lts_batch_run(lts_batch* b, int64_t n_rounds, int32_t use_graph, void
     if (use_graph) {
       if (b->exec && b->graph_gen != g_shape_gen) drop_batch_graph(b);
       if (!b->exec) {
-        int64_t total[2];
+        int64_t total[3];
         round_totals(b, 0, true, total);
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
         st = enqueue_round(b, total, b->cap_stream);
@@ -1240,7 +1216,7 @@ lts_status lts_batch_run(lts_batch* b, int64_t n_rounds, int32_t use_graph, void
       }
       HIP_TRY(hipGraphLaunch(b->exec, s), "graph launch");
     } else {
-      int64_t total[2];
+      int64_t total[3];
       round_totals(b, b->round, false, total);
       if ((st = enqueue_round(b, total, s)) != LTS_OK) return st;
     }
@@ -1282,6 +1258,7 @@ void lts_batch_destroy(lts_batch* b) {
   for (int i = 0; i < (int)b->sims.size(); ++i)
     if (b->sims[i]) release_slot(b, b->sims[i], true);
   drop_batch_graph(b);
+  if (b->d_gscr) (void)hipFree(b->d_gscr);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_round) (void)hipFree(b->d_round);
   if (b->staged) (void)hipEventDestroy(b->staged);

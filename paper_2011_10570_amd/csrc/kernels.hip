@@ -708,12 +708,13 @@ void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* _
 // stage covers the union of the active tiles of side TT of all of them, in table
 // order.  Union tile t belongs to the simulation whose cumulative-count range
 // holds it; the union is cut into 8 contiguous ranges, one per XCD.  The
-// arithmetic of every tile is that of the one-mesh kernel (coarser ghosts are
-// prolongated in the kernel, with the pre-pass's sums in the pre-pass's order).
+// arithmetic of every tile is that of the one-mesh kernel; coarser ghosts come
+// from the batch's ghost pre-pass (scr, simulation s at entry gbase_s).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims,
-                                                    const int64_t* __restrict__ round) {
-  __shared__ FusedLds<TT, F, KF32, false> L;
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, true, NT>())))
+void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims, const int64_t* __restrict__ round,
+                   const double* __restrict__ scr) {
+  __shared__ FusedLds<TT, F, KF32, true> L;
   __shared__ int cum[kMaxBatch + 1];
   fused_init(L, sp0);
   const int64_t r = *round;
@@ -752,8 +753,8 @@ __global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const Batch
     const int dl = b.lmax - b.lmin;
     const SimView v{b.U, b.U, b.K, b.K, b.N, b.lmin, b.lmax, (int)(rr & ((1 << dl) - 1)), b.sigma};
     const int n4 = (int)((b.n0 + (rr >> dl)) & 3);
-    fused_tile<TT, F, EQ, KF32, NT, KS, false>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
-                                               b.slots[TT - 1], nullptr);
+    fused_tile<TT, F, EQ, KF32, NT, KS, true>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
+                                              b.slots[TT - 1], scr + (int64_t)b.gbase * F * 729);
   }
 }
 
@@ -772,84 +773,157 @@ __global__ __launch_bounds__(NT) void k_fused_batch(StageParams sp0, const Batch
 // prolongation is separable, x, then y, then z, each a degree-4 Lagrange sum in
 // node order (the in-kernel prolongation of the batched kernel adds the same
 // terms in the same order, so a ghost has one value whichever kernel forms it).
+template <int F>
+struct GhostLds {
+  double wsh[16];
+  double lag[45];
+  double Yc[F * 125];
+  double T1[F * 225];
+  double T2[F * 405];
+};
+
+// One ghost-table entry of simulation v: leaf (coarser source), receivers of
+// level rlev; the 9^3 grid of each field to out[f][729].
 template <bool KF32, int F>
-__global__ __launch_bounds__(256) void k_ghost_pre(StageParams sp, const int32_t* __restrict__ ghosts,
-                                                   double* __restrict__ scr) {
+__device__ __forceinline__ void ghost_entry(GhostLds<F>& L, const StageParams& sp, const SimView& v, int n4,
+                                            int leaf, int rlev, double* __restrict__ out) {
   using KT = typename std::conditional<KF32, float, double>::type;
-  __shared__ double wsh[16];
-  __shared__ double lag[45];
-  __shared__ double Yc[F * 125];
-  __shared__ double T1[F * 225];
-  __shared__ double T2[F * 405];
-  if (threadIdx.x < 16) wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
-  if (threadIdx.x < 45) lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
-  const int g = blockIdx.x;
-  const int leaf = __builtin_amdgcn_readfirstlane(ghosts[2 * g]);
   // a receiver tile of the entry's receiver level (only its level matters here)
   int32_t trec[8] = {0, 0, 0, 1, 1, 0, 0, 0};
-  trec[TI_LEVEL] = __builtin_amdgcn_readfirstlane(ghosts[2 * g + 1]);
-  const TileCtx c = tile_ctx(trec, sp, (int)(*sp.step & 3));
-  const int fsz = (int)(sp.N * 125);
-  const double* __restrict__ Uc = sp.U + (int64_t)c.par_coarse * F * fsz;
-  const KT* __restrict__ Kr = (const KT*)sp.K;
+  trec[TI_LEVEL] = rlev;
+  const TileCtx c = tile_ctx(trec, sp.mode, v.j, v.lmin, v.lmax, n4);
+  const int fsz = (int)(v.N * 125);
+  const double* __restrict__ Uc = v.U + (int64_t)c.par_coarse * F * fsz;
+  const KT* __restrict__ Kr = (const KT*)v.K;
   const int kmc = stage_mask(sp, c.case_coarse);
-  __syncthreads();
-  const double* wc = wsh + 4 * c.case_coarse;
-  for (int e = threadIdx.x; e < F * 125; e += 256) {
+  const double* wc = L.wsh + 4 * c.case_coarse;
+  __syncthreads();   // weights loaded; previous entry done with Yc / T1 / T2
+  for (int e = threadIdx.x; e < F * 125; e += blockDim.x) {
     const int f = e / 125, n = e - 125 * f;
     const uint32_t off = (uint32_t)(leaf * 125 + n);
     double acc = 0.0;
     #pragma unroll
     for (int i = 0; i < 4; ++i)
       if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
-    Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
+    L.Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < F * 225; e += 256) {
+  for (int e = threadIdx.x; e < F * 225; e += blockDim.x) {
     const int kf = e / 225, r = e - 225 * kf;
     const int x2 = r / 25, yz = r - 25 * x2;
-    const double* yc = Yc + kf * 125 + 5 * yz;
+    const double* yc = L.Yc + kf * 125 + 5 * yz;
     double tx;
     if (x2 & 1) {
       tx = 0.0;
       #pragma unroll
-      for (int kx = 0; kx < 5; ++kx) tx = fma(lag[5 * x2 + kx], yc[kx], tx);
+      for (int kx = 0; kx < 5; ++kx) tx = fma(L.lag[5 * x2 + kx], yc[kx], tx);
     } else {
       tx = fma(1.0, yc[x2 >> 1], 0.0);
     }
-    T1[e] = tx;
+    L.T1[e] = tx;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < F * 405; e += 256) {
+  for (int e = threadIdx.x; e < F * 405; e += blockDim.x) {
     const int kf = e / 405, r = e - 405 * kf;
     const int x2 = r / 45, r2 = r - 45 * x2;
     const int y2 = r2 / 5, kz = r2 - 5 * y2;
-    const double* t1 = T1 + kf * 225 + 25 * x2 + 5 * kz;
+    const double* t1 = L.T1 + kf * 225 + 25 * x2 + 5 * kz;
     double ty;
     if (y2 & 1) {
       ty = 0.0;
       #pragma unroll
-      for (int ky = 0; ky < 5; ++ky) ty = fma(lag[5 * y2 + ky], t1[ky], ty);
+      for (int ky = 0; ky < 5; ++ky) ty = fma(L.lag[5 * y2 + ky], t1[ky], ty);
     } else {
       ty = fma(1.0, t1[y2 >> 1], 0.0);
     }
-    T2[e] = ty;
+    L.T2[e] = ty;
   }
   __syncthreads();
-  double* out = scr + (int64_t)g * F * 729;
-  for (int e = threadIdx.x; e < F * 729; e += 256) {
+  for (int e = threadIdx.x; e < F * 729; e += blockDim.x) {
     const int f = e / 729, r = e - 729 * f;
     const int z2 = r / 81, y2 = (r / 9) % 9, x2 = r % 9;
-    const double* t2 = T2 + f * 405 + 45 * x2 + 5 * y2;
-    double v;
+    const double* t2 = L.T2 + f * 405 + 45 * x2 + 5 * y2;
+    double v2;
     if (z2 & 1) {
-      v = 0.0;
+      v2 = 0.0;
       #pragma unroll
-      for (int kz = 0; kz < 5; ++kz) v = fma(lag[5 * z2 + kz], t2[kz], v);
+      for (int kz = 0; kz < 5; ++kz) v2 = fma(L.lag[5 * z2 + kz], t2[kz], v2);
     } else {
-      v = fma(1.0, t2[z2 >> 1], 0.0);
+      v2 = fma(1.0, t2[z2 >> 1], 0.0);
     }
-    out[e] = v;
+    out[e] = v2;
+  }
+}
+
+template <int F>
+__device__ __forceinline__ void ghost_init(GhostLds<F>& L, const StageParams& sp) {
+  if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
+  if (threadIdx.x < 45) L.lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
+}
+
+// Ghost-table pre-pass, before the fused launches of a stage: entry g (a leaf
+// that is a coarser source of receivers one level finer) gets its stage state
+// for those receivers (time case, buffer and dt of the receiver level, eqs.
+// fc_1/fc_2) prolongated to its 9^3 half-node grid, scr[g][f][z2][y2][x2].  The
+// prolongation is separable, x, then y, then z, each a degree-4 Lagrange sum in
+// node order.
+template <bool KF32, int F>
+__global__ __launch_bounds__(256) void k_ghost_pre(StageParams sp, const int32_t* __restrict__ ghosts,
+                                                   double* __restrict__ scr) {
+  __shared__ GhostLds<F> L;
+  ghost_init(L, sp);
+  const int g = blockIdx.x;
+  const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
+  ghost_entry<KF32, F>(L, sp, v, (int)(*sp.step & 3), __builtin_amdgcn_readfirstlane(ghosts[2 * g]),
+                       __builtin_amdgcn_readfirstlane(ghosts[2 * g + 1]), scr + (int64_t)g * F * 729);
+}
+
+// The same for every simulation of a batch in round *round: the union of their
+// active entries (receivers of levels >= each one's lowest active level), in
+// table order; simulation s writes its entries at gbase_s.  Persistent grid.
+template <bool KF32, int F>
+__global__ __launch_bounds__(256) void k_ghost_pre_batch(StageParams sp0, const BatchSim* __restrict__ sims,
+                                                         int nsims, const int64_t* __restrict__ round,
+                                                         double* __restrict__ scr) {
+  __shared__ GhostLds<F> L;
+  __shared__ int cum[kMaxBatch + 1];
+  ghost_init(L, sp0);
+  const int64_t r = *round;
+  for (int s = threadIdx.x; s < nsims; s += blockDim.x) {
+    const BatchSim& b = sims[s];
+    const int64_t rr = r - b.r0;
+    int cnt = 0;
+    if (rr >= 0 && rr < b.rounds) {
+      const int j = (int)(rr & ((1 << (b.lmax - b.lmin)) - 1));
+      const int lo = (sp0.mode == LTS_MODE_GTS || j == 0) ? b.lmin : b.lmax - __builtin_ctz(j);
+      cnt = b.ghost_ge[lo];
+    }
+    cum[s + 1] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cum[0] = 0;
+    for (int s = 0; s < nsims; ++s) cum[s + 1] += cum[s];
+  }
+  __syncthreads();
+  const int total = cum[nsims];
+  for (int q = blockIdx.x; q < total; q += gridDim.x) {
+    int a = 0, z = nsims - 1;   // the simulation s with cum[s] <= q < cum[s+1]
+    while (a < z) {
+      const int mid = (a + z + 1) >> 1;
+      if (cum[mid] <= q) a = mid;
+      else z = mid - 1;
+    }
+    const int s = __builtin_amdgcn_readfirstlane(a);
+    const BatchSim& b = sims[s];
+    const int64_t rr = r - b.r0;
+    const int dl = b.lmax - b.lmin;
+    const SimView v{b.U, b.U, b.K, b.K, b.N, b.lmin, b.lmax, (int)(rr & ((1 << dl) - 1)), b.sigma};
+    const int n4 = (int)((b.n0 + (rr >> dl)) & 3);
+    const int g = q - cum[s];
+    ghost_entry<KF32, F>(L, sp0, v, n4, __builtin_amdgcn_readfirstlane(b.ghosts[2 * g]),
+                         __builtin_amdgcn_readfirstlane(b.ghosts[2 * g + 1]),
+                         scr + ((int64_t)b.gbase + g) * F * 729);
   }
 }
 
@@ -1413,6 +1487,7 @@ struct BatchArgs {
   int nsims;
   const int64_t* round;
   int64_t total;
+  const double* scr;
 };
 }  // namespace
 
@@ -1427,7 +1502,7 @@ template <int TT, int F, int EQ, bool KF32, int NT, int KS>
 static hipError_t go(const StageParams& sp, const BatchArgs& a, int max_wg, hipStream_t s) {
   const int grid = fused_grid((int)std::min<int64_t>(a.total, 1 << 30), max_wg);
   hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims,
-                     a.round);
+                     a.round, a.scr);
   return hipGetLastError();
 }
 
@@ -1494,10 +1569,28 @@ hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32
 }
 
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
-                              const int64_t* round, int64_t total, const LaunchShape& ls, hipStream_t s) {
+                              const int64_t* round, int64_t total, const double* scr, const LaunchShape& ls,
+                              hipStream_t s) {
   if (total <= 0 || nsims <= 0) return hipSuccess;
   if (nsims > kMaxBatch) return hipErrorInvalidValue;
-  return dispatch_fused(tt, eq, kf32, sp0, BatchArgs{sims, nsims, round, total}, ls, s);
+  return dispatch_fused(tt, eq, kf32, sp0, BatchArgs{sims, nsims, round, total, scr}, ls, s);
+}
+
+hipError_t launch_ghost_pre_batch(int F, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
+                                  const int64_t* round, int64_t total, double* scr, int max_wg, hipStream_t s) {
+  if (total <= 0 || nsims <= 0) return hipSuccess;
+  if (nsims > kMaxBatch) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, max_wg)));
+  if (F == 2) {
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre_batch<true, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
+    else hipLaunchKernelGGL((k_ghost_pre_batch<false, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
+  } else if (F == 6) {
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre_batch<true, 6>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
+    else hipLaunchKernelGGL((k_ghost_pre_batch<false, 6>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // Streamed side-4 tiles (wave equation), after the ghost pre-pass.

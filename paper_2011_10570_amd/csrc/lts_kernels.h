@@ -45,11 +45,14 @@ struct BatchSim {
   void* K;                       // [p][F][N][125]
   const int32_t* tiles[2];       // tile records of side 1 and 2 (finest level first)
   const int32_t* slots[2];
+  const int32_t* ghosts;         // ghost table [E][2] (leaf, receiver level)
   int64_t N;
   int64_t r0, rounds, n0;
+  int64_t gbase;                 // first entry of this simulation in the batch's ghost scratch
   double sigma;
   int32_t lmin, lmax;
   int32_t n_ge[2][LTS_MAX_LEVEL + 1];  // tiles of side t+1 with level >= l
+  int32_t ghost_ge[LTS_MAX_LEVEL + 1]; // ghost entries with receiver level >= l
 };
 
 // One stage over tiles of side tt (1 or 2) in LDS; coarser ghosts are read from
@@ -65,7 +68,12 @@ hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32
 // sims[0..nsims) (device table); `total` bounds the union of their active side-tt
 // tiles and sizes the grid (host-computed; any larger value is correct too).
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
-                              const int64_t* round, int64_t total, const LaunchShape& ls, hipStream_t s);
+                              const int64_t* round, int64_t total, const double* scr, const LaunchShape& ls,
+                              hipStream_t s);
+// The batch's ghost pre-pass of one stage: the union (at most `total` entries)
+// of the active ghost entries of every simulation, into scr at each gbase.
+hipError_t launch_ghost_pre_batch(int F, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
+                                  const int64_t* round, int64_t total, double* scr, int max_wg, hipStream_t s);
 // Streamed whole 4^3 blocks (side-4 tiles, wave equation) over the launch's
 // tiles (XCD ranges as for launch_fused), ghosts from the ghost table scr.
 hipError_t launch_stream(int eq, bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
