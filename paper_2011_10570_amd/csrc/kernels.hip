@@ -319,27 +319,79 @@ __device__ __forceinline__ void rhs_point(const T* Y, int64_t fstride, int c, in
 }
 
 // ------------------------------------------------------------------ fused stage
+// The block RHS reads only along the axes (centred first and second differences
+// and Kreiss-Oliger terms, no mixed derivatives), so of the (4tt+7)^3 padded
+// points of a tile it uses those with at most one coordinate in the 3-point halo.
+// They are kept plane by plane: core plane z = 3 + gz (gz < G) as a P x P square
+// at gz P^2 (its four 3 x 3 corners unused), then the six halo planes (z = h for
+// h < 3, z = G + h for h >= 3) as G x G squares of the core x and y.
+template <int TT>
+struct Cross {
+  static constexpr int P = 4 * TT + 7;     // padded points per axis
+  static constexpr int G = 4 * TT + 1;     // grid points per axis
+  static constexpr int PP = P * P, GG = G * G;
+  static constexpr int HB = G * PP;        // element of the first halo plane
+  static constexpr int LS = HB + 6 * GG;   // elements per field
+  static constexpr int NA = P * GG;        // core planes, y in the core: whole x rows
+  static constexpr int NB = 6 * GG;        // core planes, y in the halo: x in the core
+  static constexpr int NC = NA + NB + 6 * GG;
+  // used point i (x rows, then y-halo rows, then halo planes) -> padded
+  // coordinates and element
+  __device__ static __forceinline__ void point(int i, int& qx, int& qy, int& qz, int& li) {
+    if (i < NA) {
+      qx = i % P;
+      const int r = i / P;
+      qy = 3 + r % G;
+      qz = 3 + r / G;
+    } else if (i < NA + NB) {
+      const int j = i - NA, r = j / G, h = r % 6;
+      qx = 3 + j % G;
+      qy = h < 3 ? h : G + h;
+      qz = 3 + r / 6;
+    } else {
+      const int j = i - NA - NB, r = j / G, h = r / G;
+      qx = 3 + j % G;
+      qy = 3 + r % G;
+      qz = h < 3 ? h : G + h;
+    }
+    li = (qz >= 3 && qz < 3 + G) ? ((qz - 3) * P + qy) * P + qx : HB + ((qz < 3 ? qz : qz - G) * G + qy - 3) * G + qx - 3;
+  }
+};
+
+// Accessor of the plane-wise padded tile at grid point (gx, gy, gz): c is its
+// element in the core planes, hb the element of (gx, gy) in the first halo plane.
+template <typename T, int TT>
+struct CrossAt {
+  const T* Y;
+  int c, hb, gz;
+  __device__ __forceinline__ T operator()(int f, int ax, int k) const {
+    using X = Cross<TT>;
+    int e;
+    if (ax == 0) {
+      e = c + k;
+    } else if (ax == 1) {
+      e = c + k * X::P;
+    } else {
+      const int z = gz + k;
+      e = (z >= 0 && z < X::G) ? c + k * X::PP : hb + (z < 0 ? z + 3 : z - X::G + 3) * X::GG;
+    }
+    return Y[f * X::LS + e];
+  }
+};
+
 // LDS of one workgroup of the fused stage kernels.
-template <int TT, int F, bool KF32, bool CPRE>
+template <int TT, int F, bool KF32>
 struct FusedLds {
-  static constexpr int P = 4 * TT + 7;
-  static constexpr int P3 = P * P * P;
   static constexpr int W = TT + 2;
   static constexpr int NS = W * W * W;
-  static constexpr int NCB = 4;                        // coarser leaves prolongated per batch
-  using LT = typename std::conditional<KF32, float, double>::type;
-  LT Y[F * P3];
-  int32_t sl[2 * (2 * NS + 27)];  // slot table + work lists
-  uint8_t axl[3][P];              // per axis: slot position | node offset << 3
-  double wsh[16];
-  double lag[45];
-  double ref[F];
   static constexpr int G3 = (4 * TT + 1) * (4 * TT + 1) * (4 * TT + 1);
-  // in-kernel prolongation (CPRE = false): stage values of coarser source leaves
-  // and their interpolation along x, [x2 0..8][ky][kz]; T1 also holds the stencil
-  // results.  With the ghost pre-pass (CPRE) only the results.
-  double Yc[CPRE ? 1 : NCB * F * 125];
-  double T1[CPRE ? F * G3 : NCB * F * 225];
+  using LT = typename std::conditional<KF32, float, double>::type;
+  double R[F * G3];               // stencil results
+  double wsh[16];                 // stage weights of the 4 time cases
+  double ref[F];
+  LT Y[F * Cross<TT>::LS];        // stage values of the used padded points
+  int32_t sl[2 * NS];             // slot records
+  uint8_t axl[3][4 * TT + 7];     // per axis: slot position | node offset << 3
 };
 
 // The arrays and schedule position of the simulation a tile belongs to.
@@ -354,26 +406,25 @@ struct SimView {
 };
 
 // One tile of the fused stage (Sec. 3.4, eqs. fc_1/fc_2, eq. rk_schemes):
-//   (0) the slot table and per-axis location tables (slot position and node
+//   (0) the slot records and per-axis location tables (slot position and node
 //       offset of every padded coordinate, from the location rule) go to LDS;
-//   (1) every padded point whose slot is a same-level leaf (the tile's own
-//       octants included) or 8 finer leaves reads its stage value Y = U0 +
-//       dt sum w_i K_i directly (uniform base pointers, 32-bit offsets, UB points
-//       per thread loaded before use);
-//   (2) the distinct coarser source leaves are staged in LDS (NCB at a time),
-//       prolongated separably, and the points of coarser slots finished along z;
-//   (3) the stencils run once per tile grid point; K_s (and the RK update at the
+//   (1) every used padded point takes its stage value: a same-level leaf (the
+//       tile's own octants included) or 8 finer leaves give Y = U0 + dt sum w_i
+//       K_i, read directly (uniform base pointers, 32-bit offsets, UB points per
+//       thread loaded before use); a coarser leaf gives its prolongated value
+//       from the ghost table cs;
+//   (2) the stencils run once per tile grid point; K_s (and the RK update at the
 //       last stage) are written to every DG node of the tile's contiguous octants.
 // sp holds the stage (weights, masks), v the tile's simulation.
-template <int TT, int F, int EQ, bool KF32, int NT, int KS, bool CPRE>
-__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, CPRE>& L, const StageParams& sp, const SimView& v,
+template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const StageParams& sp, const SimView& v,
                                            int n4, const int32_t* __restrict__ tile,
                                            const int32_t* __restrict__ slots, const double* __restrict__ cs) {
-  constexpr int P = 4 * TT + 7;
-  constexpr int P3 = P * P * P;
+  using X = Cross<TT>;
+  constexpr int P = X::P;
+  constexpr int LS = X::LS;
   constexpr int W = TT + 2;
   constexpr int NS = W * W * W;
-  constexpr int NCB = FusedLds<TT, F, KF32, CPRE>::NCB;
   constexpr int UB = 2;                      // points per thread loaded together
   using LT = typename std::conditional<KF32, float, double>::type;
   using KT = typename std::conditional<KF32, float, double>::type;
@@ -381,318 +432,220 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, CPRE>& L, const
   auto& sl = L.sl;
   auto& axl = L.axl;
   auto& wsh = L.wsh;
-  auto& lag = L.lag;
   auto& ref = L.ref;
-  auto& Yc = L.Yc;
-  auto& T1 = L.T1;
+  auto& R = L.R;
   const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
   const KT* __restrict__ Kr = (const KT*)v.K;
   KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
   // KS: stages read by same-level sources (the tableau row's non-zero pattern),
   // a compile-time mask so the hot gather has no branches around its loads
-    // the tile record is uniform: keep it in scalar registers
-    int32_t trec[8];
-    #pragma unroll
-    for (int k = 0; k < 8; ++k) trec[k] = __builtin_amdgcn_readfirstlane(tile[k]);
-    const int32_t* t = trec;
-    const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, n4);
-    const int first = t[TI_FIRST];
-    const int counts = t[TI_COUNTS];
-    const int ncl = (counts >> 24) & 255;
-    const int nent = NS + (counts & 255) + ((counts >> 8) & 255) + ((counts >> 16) & 255) + ncl;
-    const double* __restrict__ Us = v.U + (int64_t)c.par_same * F * fsz;
-    const double* __restrict__ Uf = v.U + (int64_t)c.par_fine * F * fsz;
-    const double* __restrict__ Uc = v.U + (int64_t)c.par_coarse * F * fsz;
-    double* __restrict__ Uw1 = v.Uw + (int64_t)(c.par_same ^ 1) * F * fsz;
-    const int kmf = stage_mask(sp, c.case_fine), kmc = stage_mask(sp, c.case_coarse);
-    const double* wf = wsh + 4 * c.case_fine;
-    const double* wc = wsh + 4 * c.case_coarse;
-    __syncthreads();  // previous tile done with LDS
-    for (int e = threadIdx.x; e < 2 * nent; e += NT) sl[e] = slots[2 * (int64_t)t[TI_SLOT] + e];
-    if (threadIdx.x < 3 * P) {
-      const int d = threadIdx.x / P, q = threadIdx.x - P * d;
-      const int o = d == 0 ? c.ox : (d == 1 ? c.oy : c.oz);
-      const int Q = 4 * o + q - 3;
-      const int cell = cell_of(Q, c.m);
-      axl[d][q] = (uint8_t)((cell - o + 1) | ((Q - 4 * cell) << 3));
-    }
-    if (threadIdx.x < F) {
-      // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
-      ref[threadIdx.x] = KF32 ? Us[threadIdx.x * fsz + first * 125] : 0.0;
-    }
-    __syncthreads();
-    const int32_t* lst_cleaf = sl + 2 * (nent - ncl);
-    const int ncs = (counts >> 16) & 255;
-    const int32_t* lst_cslot = sl + 2 * (NS + (counts & 255) + ((counts >> 8) & 255));
+  // the tile record is uniform: keep it in scalar registers
+  int32_t trec[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) trec[k] = __builtin_amdgcn_readfirstlane(tile[k]);
+  const int32_t* t = trec;
+  const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, n4);
+  const int first = t[TI_FIRST];
+  const double* __restrict__ Us = v.U + (int64_t)c.par_same * F * fsz;
+  const double* __restrict__ Uf = v.U + (int64_t)c.par_fine * F * fsz;
+  double* __restrict__ Uw1 = v.Uw + (int64_t)(c.par_same ^ 1) * F * fsz;
+  const int kmf = stage_mask(sp, c.case_fine);
+  const double* wf = wsh + 4 * c.case_fine;
+  __syncthreads();  // previous tile done with LDS
+  for (int e = threadIdx.x; e < 2 * NS; e += NT) sl[e] = slots[2 * (int64_t)t[TI_SLOT] + e];
+  if (threadIdx.x < 3 * P) {
+    const int d = threadIdx.x / P, q = threadIdx.x - P * d;
+    const int o = d == 0 ? c.ox : (d == 1 ? c.oy : c.oz);
+    const int Q = 4 * o + q - 3;
+    const int cell = cell_of(Q, c.m);
+    axl[d][q] = (uint8_t)((cell - o + 1) | ((Q - 4 * cell) << 3));
+  }
+  if (threadIdx.x < F) {
+    // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
+    ref[threadIdx.x] = KF32 ? Us[threadIdx.x * fsz + first * 125] : 0.0;
+  }
+  __syncthreads();
 
-    // prefetching the last stage's RK operands pays for the FP64 wave equation
-    // (6 fields would spill; FP32 tiles would lose a resident workgroup per CU)
-    constexpr bool PF = F <= 2 && !KF32;
+  // PF: issue the last stage's RK operands before the stencils.  Off: holding
+  // them costs the registers that 3 resident side-2 workgroups per CU leave.
+  constexpr bool PF = false;
 
-    // (1) same-level and finer sources (and, with the ghost pre-pass, the
-    // prolongated coarser ghosts)
-    for (int p0 = threadIdx.x; p0 < P3; p0 += UB * NT) {
-      int pidx[UB], kind[UB], leaf[UB], kbv[UB], nuv[UB][3];
-      #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        const int pi = p0 + u * NT;
-        kind[u] = -1;
-        pidx[u] = pi;
-        if (pi >= P3) continue;
-        const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
-        const int ax = axl[0][qx], ay = axl[1][qy], az = axl[2][qz];
-        const int si = (ax & 7) + W * ((ay & 7) + W * (az & 7));
-        nuv[u][0] = ax >> 3;
-        nuv[u][1] = ay >> 3;
-        nuv[u][2] = az >> 3;
-        kbv[u] = sl[2 * si + 1];
-        kind[u] = kbv[u] & 15;
-        leaf[u] = sl[2 * si];
-      }
-      double uu[UB][F], kk[UB][F][4];
-      #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        if (kind[u] == SRC_SAME) {
-          const uint32_t off = (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]);
-          #pragma unroll
-          for (int f = 0; f < F; ++f) {
-            uu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
-            #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
-          }
-        } else if (CPRE && kind[u] == SRC_COARSE) {
-          // ghost-table entry (in the slot's first int), octant beta of the leaf
-          const int beta = (kbv[u] >> 4) & 7;
-          const int x2 = 4 * (beta & 1) + nuv[u][0], y2 = 4 * ((beta >> 1) & 1) + nuv[u][1],
-                    z2 = 4 * ((beta >> 2) & 1) + nuv[u][2];
-          #pragma unroll
-          for (int f = 0; f < F; ++f) uu[u][f] = cs[((int64_t)leaf[u] * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
-        }
-      }
-      #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        if (kind[u] == SRC_FINE) {
-          const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
-          const uint32_t off = (uint32_t)((leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
-                                          10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz));
-          #pragma unroll
-          for (int f = 0; f < F; ++f) {
-            double acc = 0.0;
-            #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if ((kmf >> i) & 1) acc = fma(wf[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
-            Y[f * P3 + pidx[u]] = (LT)(ld32(Uf + (uint32_t)(f * fsz), off) + c.dt * acc - ref[f]);
-          }
-        } else if (kind[u] == SRC_SAME) {
-          #pragma unroll
-          for (int f = 0; f < F; ++f) {
-            double acc = 0.0;
-            #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if ((KS >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
-            Y[f * P3 + pidx[u]] = (LT)(uu[u][f] + c.dt * acc - ref[f]);
-          }
-        } else if (CPRE && kind[u] == SRC_COARSE) {
-          #pragma unroll
-          for (int f = 0; f < F; ++f) Y[f * P3 + pidx[u]] = (LT)(uu[u][f] - ref[f]);
-        }
-      }
+  // (1) stage values of the used padded points
+  for (int p0 = threadIdx.x; p0 < X::NC; p0 += UB * NT) {
+    int li[UB], kind[UB], leaf[UB], kbv[UB], nuv[UB][3];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int pi = p0 + u * NT;
+      kind[u] = -1;
+      li[u] = 0;
+      if (pi >= X::NC) continue;
+      int qx, qy, qz;
+      X::point(pi, qx, qy, qz, li[u]);
+      const int ax = axl[0][qx], ay = axl[1][qy], az = axl[2][qz];
+      const int si = (ax & 7) + W * ((ay & 7) + W * (az & 7));
+      nuv[u][0] = ax >> 3;
+      nuv[u][1] = ay >> 3;
+      nuv[u][2] = az >> 3;
+      kbv[u] = sl[2 * si + 1];
+      kind[u] = kbv[u] & 15;
+      leaf[u] = sl[2 * si];
     }
-    // (2) coarser sources: stage the distinct leaves (NCB at a time), prolongate
-    // each along x on its half-node grid, then finish y and z per point.  The
-    // sums and their order are those of the separable prolongation x, y, z (and
-    // of the direct tensor form with x innermost).  Only the points of the tile's
-    // coarser slots are visited: slot position s and node offset nu per axis,
-    // nu within the range the location rule gives that slot.
-    for (int b0 = 0; b0 < (CPRE ? 0 : ncl); b0 += NCB) {
-      const int nb = min(NCB, ncl - b0);
-      if (b0 > 0) __syncthreads();   // previous batch's points done
-      for (int e = threadIdx.x; e < nb * F * 125; e += NT) {
-        const int k = e / (F * 125), rem = e - k * (F * 125);
-        const int f = rem / 125, n = rem - 125 * f;
-        const uint32_t off = (uint32_t)(lst_cleaf[2 * (b0 + k)] * 125 + n);
-        double acc = 0.0;
+    double uu[UB][F], kk[UB][F][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
-        Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < nb * F * 225; e += NT) {
-        const int kf = e / 225, r = e - 225 * kf;        // kf = leaf * F + field
-        const int x2 = r / 25, yz = r - 25 * x2;          // yz = ky + 5 kz
-        const double* yc = Yc + kf * 125 + 5 * yz;
-        double tx;
-        if (x2 & 1) {
-          tx = 0.0;
-#pragma unroll
-          for (int kx = 0; kx < 5; ++kx) tx = fma(lag[5 * x2 + kx], yc[kx], tx);
-        } else {
-          tx = fma(1.0, yc[x2 >> 1], 0.0);
-        }
-        T1[e] = tx;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < ncs * 125; e += NT) {
-        const int k = e / 125, r = e - 125 * k;
-        const int si = lst_cslot[2 * k];
-        const int kb = sl[2 * si + 1];
-        const int cidx = kb >> 8;
-        if (cidx < b0 || cidx >= b0 + nb) continue;
-        const int s3[3] = {si % W, (si / W) % W, si / (W * W)};
-        const int o3[3] = {c.ox, c.oy, c.oz};
-        const int nu3[3] = {r % 5, (r / 5) % 5, r / 25};
-        bool own = true;
-        int q3[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          int lo, hi;
-          owned_range(s3[d], o3[d], TT, c.m, lo, hi);
-          own = own && nu3[d] >= lo && nu3[d] <= hi;
-          q3[d] = 4 * (s3[d] - 1) + nu3[d] + 3;
-        }
-        if (!own) continue;
-        const int pi = (q3[2] * P + q3[1]) * P + q3[0];
-        const int beta = (kb >> 4) & 7;
-        const int x2 = 4 * (beta & 1) + nu3[0], y2 = 4 * ((beta >> 1) & 1) + nu3[1],
-                  z2 = 4 * ((beta >> 2) & 1) + nu3[2];
+    for (int u = 0; u < UB; ++u) {
+      if (kind[u] == SRC_SAME) {
+        const uint32_t off = (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]);
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          const double* t1 = T1 + ((cidx - b0) * F + f) * 225 + 25 * x2;   // [ky + 5 kz]
-          // along y at each kz, then along z
-          auto ty = [&](int kz) {
-            const double* col = t1 + 5 * kz;
-            double v;
-            if (y2 & 1) {
-              v = 0.0;
+          uu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
 #pragma unroll
-              for (int ky = 0; ky < 5; ++ky) v = fma(lag[5 * y2 + ky], col[ky], v);
-            } else {
-              v = fma(1.0, col[y2 >> 1], 0.0);
-            }
-            return v;
-          };
-          double v;
-          if (z2 & 1) {
-            v = 0.0;
-#pragma unroll
-            for (int kz = 0; kz < 5; ++kz) v = fma(lag[5 * z2 + kz], ty(kz), v);
-          } else {
-            v = fma(1.0, ty(z2 >> 1), 0.0);
-          }
-          Y[f * P3 + pi] = (LT)(v - ref[f]);
+          for (int i = 0; i < 4; ++i)
+            if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
         }
+      } else if (kind[u] == SRC_COARSE) {
+        // ghost-table entry (in the slot's first int), octant beta of the leaf
+        const int beta = (kbv[u] >> 4) & 7;
+        const int x2 = 4 * (beta & 1) + nuv[u][0], y2 = 4 * ((beta >> 1) & 1) + nuv[u][1],
+                  z2 = 4 * ((beta >> 2) & 1) + nuv[u][2];
+#pragma unroll
+        for (int f = 0; f < F; ++f) uu[u][f] = cs[((int64_t)leaf[u] * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
       }
     }
-    __syncthreads();
-    // last stage: U0 and the earlier stages at this thread's zip nodes, issued
-    // before the stencils so that their latency overlaps them
-    constexpr int NN = TT * TT * TT * 125;
-    constexpr int KZ = (NN + NT - 1) / NT;
-    double zu[KZ][F], zk[KZ][F][3];
 #pragma unroll
-    for (int u = 0; u < KZ; ++u) {
-      const int e = threadIdx.x + u * NT;
-      const bool on = PF && last && e < NN;
-      const uint32_t off = (uint32_t)(first * 125 + (e < NN ? e : 0));
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        zu[u][f] = on ? ld32(Us + (uint32_t)(f * fsz), off) : 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-          zk[u][f][i] = (on && i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
-      }
-    }
-    // (3a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
-    // (the coarse prolongation buffer is free by now)
-    constexpr int G = 4 * TT + 1;
-    constexpr int G3 = G * G * G;
-    static_assert(NCB * F * 225 >= F * G3, "grid result buffer");
-    double* R = T1;
-    for (int gi = threadIdx.x; gi < G3; gi += NT) {
-      const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
-      const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
-      double k[F];
-      // one axis at a time: fewer live registers (same operations, same order)
-      rhs_at<LT, EQ, F, true>(StridedAt<LT>{Y, P3, ci, P, P * P}, (LT)c.h, (LT)v.sigma, ref, k);
-      #pragma unroll
-      for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
-    }
-    __syncthreads();
-    // (3b) zip: every DG node of the tile's (contiguous) octants takes its grid
-    // value; node e of the tile is element first*125 + e of every field array;
-    // the last stage also forms the RK update
-    double bs = sp.b[0];   // b_s without a dynamic index into the kernel arguments
-#pragma unroll
-    for (int i = 1; i < 4; ++i)
-      if (i == sp.stage) bs = sp.b[i];
-#pragma unroll
-    for (int u = 0; u < KZ; ++u) {
-      const int e = threadIdx.x + u * NT;
-      if (e >= NN) continue;
-      const uint32_t off = (uint32_t)(first * 125 + e);
-      if (!PF && last) {
+    for (int u = 0; u < UB; ++u) {
+      if (kind[u] == SRC_FINE) {
+        const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
+        const uint32_t off = (uint32_t)((leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
+                                        10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz));
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          zu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
-#pragma unroll
-          for (int i = 0; i < 3; ++i)
-            zk[u][f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
-        }
-      }
-      const int o = e / 125, node = e - 125 * (e / 125);
-      const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
-      const int gi = ((4 * ((o >> 2) & 1) + cc) * G + (4 * ((o >> 1) & 1) + b)) * G + (4 * (o & 1) + a);
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        double kv = R[f * G3 + gi];
-        if constexpr (KF32) {
-          const float kf = (float)kv;
-          st32(Kw + (uint32_t)(f * fsz), off, kf);
-          kv = (double)kf;
-        } else {
-          st32(Kw + (uint32_t)(f * fsz), off, kv);
-        }
-        if (last) {
-          // compute_step_partial: U_new = U0 + dt (b_0 K_0 + ... + b_s K_s),
-          // s = p - 1, accumulated in stage order, into the other buffer
           double acc = 0.0;
 #pragma unroll
-          for (int i = 0; i < 3; ++i)
-            if (i < sp.stage) acc = fma(sp.b[i], zk[u][f][i], acc);
-          acc = fma(bs, kv, acc);
-          st32(Uw1 + (uint32_t)(f * fsz), off, zu[u][f] + c.dt * acc);
+          for (int i = 0; i < 4; ++i)
+            if ((kmf >> i) & 1) acc = fma(wf[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
+          Y[f * LS + li[u]] = (LT)(ld32(Uf + (uint32_t)(f * fsz), off) + c.dt * acc - ref[f]);
         }
+      } else if (kind[u] == SRC_SAME) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if ((KS >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
+          Y[f * LS + li[u]] = (LT)(uu[u][f] + c.dt * acc - ref[f]);
+        }
+      } else if (kind[u] == SRC_COARSE) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) Y[f * LS + li[u]] = (LT)(uu[u][f] - ref[f]);
       }
     }
+  }
+  __syncthreads();
+  // last stage: U0 and the earlier stages at this thread's zip nodes, issued
+  // before the stencils so that their latency overlaps them
+  constexpr int NN = TT * TT * TT * 125;
+  constexpr int KZ = (NN + NT - 1) / NT;
+  double zu[KZ][F], zk[KZ][F][3];
+#pragma unroll
+  for (int u = 0; u < KZ; ++u) {
+    const int e = threadIdx.x + u * NT;
+    const bool on = PF && last && e < NN;
+    const uint32_t off = (uint32_t)(first * 125 + (e < NN ? e : 0));
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      zu[u][f] = on ? ld32(Us + (uint32_t)(f * fsz), off) : 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        zk[u][f][i] = (on && i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
+    }
+  }
+  // (2a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
+  constexpr int G = X::G;
+  constexpr int G3 = G * G * G;
+  for (int gi = threadIdx.x; gi < G3; gi += NT) {
+    const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
+    const int ce = (gz * P + gy + 3) * P + gx + 3;
+    double k[F];
+    // one axis at a time: fewer live registers (same operations, same order)
+    rhs_at<LT, EQ, F, true>(CrossAt<LT, TT>{Y, ce, X::HB + gy * G + gx, gz}, (LT)c.h, (LT)v.sigma, ref, k);
+#pragma unroll
+    for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
+  }
+  __syncthreads();
+  // (2b) zip: every DG node of the tile's (contiguous) octants takes its grid
+  // value; node e of the tile is element first*125 + e of every field array;
+  // the last stage also forms the RK update
+  double bs = sp.b[0];   // b_s without a dynamic index into the kernel arguments
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (i == sp.stage) bs = sp.b[i];
+#pragma unroll
+  for (int u = 0; u < KZ; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e >= NN) continue;
+    const uint32_t off = (uint32_t)(first * 125 + e);
+    if (!PF && last) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        zu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          zk[u][f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
+      }
+    }
+    const int o = e / 125, node = e - 125 * (e / 125);
+    const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
+    const int gi = ((4 * ((o >> 2) & 1) + cc) * G + (4 * ((o >> 1) & 1) + b)) * G + (4 * (o & 1) + a);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double kv = R[f * G3 + gi];
+      if constexpr (KF32) {
+        const float kf = (float)kv;
+        st32(Kw + (uint32_t)(f * fsz), off, kf);
+        kv = (double)kf;
+      } else {
+        st32(Kw + (uint32_t)(f * fsz), off, kv);
+      }
+      if (last) {
+        // compute_step_partial: U_new = U0 + dt (b_0 K_0 + ... + b_s K_s),
+        // s = p - 1, accumulated in stage order, into the other buffer
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          if (i < sp.stage) acc = fma(sp.b[i], zk[u][f][i], acc);
+        acc = fma(bs, kv, acc);
+        st32(Uw1 + (uint32_t)(f * fsz), off, zu[u][f] + c.dt * acc);
+      }
+    }
+  }
 }
 
-template <int TT, int F, bool KF32, bool CPRE>
-__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32, CPRE>& L, const StageParams& sp) {
+template <int TT, int F, bool KF32>
+__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const StageParams& sp) {
   if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
-  if (threadIdx.x < 45) L.lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
 }
 
 // Waves per SIMD that the LDS of one workgroup allows: the register budget the
 // compiler is asked to keep so that registers do not cost occupancy.  Capped at
-// 6 (80 registers), and left free for 6 fields, where a tighter budget spills.
-template <int TT, int F, bool KF32, bool CPRE, int NT>
+// 6 (80 registers; 5 for side-1 tiles, which spill at 80), and left free for 6
+// fields, where a tighter budget spills.
+template <int TT, int F, bool KF32, int NT>
 constexpr int fused_waves_per_eu() {
-  const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32, CPRE>);
+  const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32>);
   const int w = wg * (NT / 64) / 4;
-  return (F > 2 || w < 1) ? 1 : (w > 6 ? 6 : w);
+  const int cap = TT == 1 ? 5 : 6;
+  return (F > 2 || w < 1) ? 1 : (w > cap ? cap : w);
 }
 
 // One mesh: workgroups are dealt to the 8 XCDs round robin; XCD x walks its own
 // contiguous (Morton-ordered, cost-balanced) range of tiles.  Coarser ghosts come
 // prolongated from the ghost-table pre-pass (scr).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, true, NT>())))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT>())))
 void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* __restrict__ slots,
              const double* __restrict__ scr, XcdRanges xr) {
-  __shared__ FusedLds<TT, F, KF32, true> L;
+  __shared__ FusedLds<TT, F, KF32> L;
   fused_init(L, sp);
   const int n4 = (int)(*sp.step & 3);
   const int nslot = gridDim.x >> 3;
@@ -700,7 +653,7 @@ void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* _
   const int sid = blockIdx.x >> 3;
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
   for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot)
-    fused_tile<TT, F, EQ, KF32, NT, KS, true>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots, scr);
+    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots, scr);
 }
 
 // Several independent meshes advanced together (continuous batching): in round r
@@ -711,10 +664,10 @@ void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* _
 // arithmetic of every tile is that of the one-mesh kernel; coarser ghosts come
 // from the batch's ghost pre-pass (scr, simulation s at entry gbase_s).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, true, NT>())))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT>())))
 void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims, const int64_t* __restrict__ round,
                    const double* __restrict__ scr) {
-  __shared__ FusedLds<TT, F, KF32, true> L;
+  __shared__ FusedLds<TT, F, KF32> L;
   __shared__ int cum[kMaxBatch + 1];
   fused_init(L, sp0);
   const int64_t r = *round;
@@ -753,7 +706,7 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
     const int dl = b.lmax - b.lmin;
     const SimView v{b.U, b.U, b.K, b.K, b.N, b.lmin, b.lmax, (int)(rr & ((1 << dl) - 1)), b.sigma};
     const int n4 = (int)((b.n0 + (rr >> dl)) & 3);
-    fused_tile<TT, F, EQ, KF32, NT, KS, true>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
+    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
                                               b.slots[TT - 1], scr + (int64_t)b.gbase * F * 729);
   }
 }
