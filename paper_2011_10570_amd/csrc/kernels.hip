@@ -65,11 +65,10 @@ __device__ __forceinline__ double stage_weight(const StageParams& sp, int e) {
 }
 
 __device__ __forceinline__ int stage_mask(const StageParams& sp, int cs) {
-  int m = sp.kmask[0];
-#pragma unroll
-  for (int k = 1; k < 4; ++k)
-    if (cs == k) m = sp.kmask[k];
-  return m;
+  // the 4 masks packed 4 bits each and shifted out: a select chain over the
+  // array can be turned back into an indexed copy in scratch
+  const int packed = (sp.kmask[0] & 15) | (sp.kmask[1] & 15) << 4 | (sp.kmask[2] & 15) << 8 | (sp.kmask[3] & 15) << 12;
+  return (packed >> (4 * cs)) & 15;
 }
 
 struct TileCtx {
@@ -388,10 +387,11 @@ struct FusedLds {
   using LT = typename std::conditional<KF32, float, double>::type;
   double R[F * G3];               // stencil results
   double wsh[16];                 // stage weights of the 4 time cases
-  double ref[F];
   LT Y[F * Cross<TT>::LS];        // stage values of the used padded points
-  int32_t sl[2 * NS];             // slot records
-  uint8_t axl[3][4 * TT + 7];     // per axis: slot position | node offset << 3
+  // per-tile tables, two buffers: the next tile's are filled while this one runs
+  double ref[2][F];               // FP32 stencils: reference value of each field
+  int32_t sl[2][2 * NS];          // slot records
+  uint8_t axl[2][3][4 * TT + 7];  // per axis: slot position | node offset << 3
 };
 
 // The arrays and schedule position of the simulation a tile belongs to.
@@ -405,67 +405,111 @@ struct SimView {
   double sigma;
 };
 
-// One tile of the fused stage (Sec. 3.4, eqs. fc_1/fc_2, eq. rk_schemes):
-//   (0) the slot records and per-axis location tables (slot position and node
-//       offset of every padded coordinate, from the location rule) go to LDS;
+// A tile and what it needs of its simulation and mesh.
+struct TileRef {
+  SimView v;
+  int n4;                   // coarse-step index mod 4
+  const int32_t* tile;      // its 8-int record
+  const int32_t* slots;     // slot table of its mesh
+  const double* cs;         // ghost table of its mesh
+};
+
+// The tile record is uniform: keep it in scalar registers.
+__device__ __forceinline__ void load_trec(const int32_t* tile, int32_t t[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t[k] = __builtin_amdgcn_readfirstlane(tile[k]);
+}
+
+// One thread's share of a tile's LDS tables: slot record element, location-table
+// element (from the location rule) and, for FP32 stencils, a field's reference
+// value.  Loads are issued here and consumed by tables_store, so that their
+// latency can be covered by other work.
+struct TileTables {
+  int32_t slv;
+  int32_t axv;
+  double refv;
+};
+
+template <int TT, int F, bool KF32, int NT>
+__device__ __forceinline__ TileTables tables_issue(const StageParams& sp, const TileRef& r, const int32_t* t) {
+  constexpr int P = 4 * TT + 7;
+  constexpr int NS2 = 2 * (TT + 2) * (TT + 2) * (TT + 2);
+  static_assert(NT >= NS2 && NT >= 3 * P, "one table element per thread");
+  TileTables tb{0, 0, 0.0};
+  if (threadIdx.x < NS2) tb.slv = r.slots[2 * (int64_t)t[TI_SLOT] + threadIdx.x];
+  if (threadIdx.x < 3 * P) {
+    const int d = threadIdx.x / P, q = threadIdx.x - P * d;
+    const int off = t[TI_OFF];
+    const int o = (off >> (8 * d)) & 255;
+    const int Q = 4 * o + q - 3;
+    const int cell = cell_of(Q, t[TI_M]);
+    tb.axv = (cell - o + 1) | ((Q - 4 * cell) << 3);
+  }
+  if (KF32 && threadIdx.x < F) {
+    // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
+    const TileCtx c = tile_ctx(t, sp.mode, r.v.j, r.v.lmin, r.v.lmax, r.n4);
+    const int64_t fsz = r.v.N * 125;
+    tb.refv = r.v.U[((int64_t)c.par_same * F + threadIdx.x) * fsz + (int64_t)t[TI_FIRST] * 125];
+  }
+  return tb;
+}
+
+template <int TT, int F, bool KF32>
+__device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32>& L, int b, const TileTables& tb) {
+  constexpr int P = 4 * TT + 7;
+  constexpr int NS2 = 2 * (TT + 2) * (TT + 2) * (TT + 2);
+  if (threadIdx.x < NS2) L.sl[b][threadIdx.x] = tb.slv;
+  if (threadIdx.x < 3 * P) L.axl[b][threadIdx.x / P][threadIdx.x % P] = (uint8_t)tb.axv;
+  if (threadIdx.x < F) L.ref[b][threadIdx.x] = KF32 ? tb.refv : 0.0;
+}
+
+// One tile of the fused stage (Sec. 3.4, eqs. fc_1/fc_2, eq. rk_schemes).  Its
+// slot records and per-axis location tables (slot position and node offset of
+// every padded coordinate, from the location rule) are in LDS buffer b.
 //   (1) every used padded point takes its stage value: a same-level leaf (the
 //       tile's own octants included) or 8 finer leaves give Y = U0 + dt sum w_i
 //       K_i, read directly (uniform base pointers, 32-bit offsets, UB points per
 //       thread loaded before use); a coarser leaf gives its prolongated value
-//       from the ghost table cs;
+//       from the ghost table;
 //   (2) the stencils run once per tile grid point; K_s (and the RK update at the
 //       last stage) are written to every DG node of the tile's contiguous octants.
-// sp holds the stage (weights, masks), v the tile's simulation.
+// With a next tile, its record is loaded at the start and its tables during the
+// stencils, into buffer b ^ 1.  Two barriers per tile: after the gather (the
+// previous tile's zip has read the stencil results) and after the stencils.
+// sp holds the stage (weights, masks).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const StageParams& sp, const SimView& v,
-                                           int n4, const int32_t* __restrict__ tile,
-                                           const int32_t* __restrict__ slots, const double* __restrict__ cs) {
+__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const StageParams& sp, const TileRef& cur,
+                                           const int32_t* t, int b, const TileRef& nxt, bool more,
+                                           int32_t (&ntrec)[8]) {
   using X = Cross<TT>;
   constexpr int P = X::P;
   constexpr int LS = X::LS;
   constexpr int W = TT + 2;
-  constexpr int NS = W * W * W;
   constexpr int UB = 2;                      // points per thread loaded together
   using LT = typename std::conditional<KF32, float, double>::type;
   using KT = typename std::conditional<KF32, float, double>::type;
+  const SimView& v = cur.v;
+  const double* __restrict__ cs = cur.cs;
   auto& Y = L.Y;
-  auto& sl = L.sl;
-  auto& axl = L.axl;
+  const int32_t* sl = L.sl[b];
+  const auto& axl = L.axl[b];
   auto& wsh = L.wsh;
-  auto& ref = L.ref;
+  const double* ref = L.ref[b];
   auto& R = L.R;
+  if (more) load_trec(nxt.tile, ntrec);
   const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
   const KT* __restrict__ Kr = (const KT*)v.K;
   KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
   // KS: stages read by same-level sources (the tableau row's non-zero pattern),
   // a compile-time mask so the hot gather has no branches around its loads
-  // the tile record is uniform: keep it in scalar registers
-  int32_t trec[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) trec[k] = __builtin_amdgcn_readfirstlane(tile[k]);
-  const int32_t* t = trec;
-  const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, n4);
+  const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, cur.n4);
   const int first = t[TI_FIRST];
   const double* __restrict__ Us = v.U + (int64_t)c.par_same * F * fsz;
   const double* __restrict__ Uf = v.U + (int64_t)c.par_fine * F * fsz;
   double* __restrict__ Uw1 = v.Uw + (int64_t)(c.par_same ^ 1) * F * fsz;
   const int kmf = stage_mask(sp, c.case_fine);
   const double* wf = wsh + 4 * c.case_fine;
-  __syncthreads();  // previous tile done with LDS
-  for (int e = threadIdx.x; e < 2 * NS; e += NT) sl[e] = slots[2 * (int64_t)t[TI_SLOT] + e];
-  if (threadIdx.x < 3 * P) {
-    const int d = threadIdx.x / P, q = threadIdx.x - P * d;
-    const int o = d == 0 ? c.ox : (d == 1 ? c.oy : c.oz);
-    const int Q = 4 * o + q - 3;
-    const int cell = cell_of(Q, c.m);
-    axl[d][q] = (uint8_t)((cell - o + 1) | ((Q - 4 * cell) << 3));
-  }
-  if (threadIdx.x < F) {
-    // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
-    ref[threadIdx.x] = KF32 ? Us[threadIdx.x * fsz + first * 125] : 0.0;
-  }
-  __syncthreads();
 
   // PF: issue the last stage's RK operands before the stencils.  Off: holding
   // them costs the registers that 3 resident side-2 workgroups per CU leave.
@@ -479,6 +523,9 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       const int pi = p0 + u * NT;
       kind[u] = -1;
       li[u] = 0;
+      leaf[u] = 0;
+      kbv[u] = 0;
+      nuv[u][0] = nuv[u][1] = nuv[u][2] = 0;
       if (pi >= X::NC) continue;
       int qx, qy, qz;
       X::point(pi, qx, qy, qz, li[u]);
@@ -491,25 +538,27 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       kind[u] = kbv[u] & 15;
       leaf[u] = sl[2 * si];
     }
+    // one straight-line batch of loads for every lane: a same-level point reads
+    // U0 and the K's of its node, a coarser one its ghost-table value (and,
+    // like every other lane, K's at a valid dummy element); loads under
+    // per-kind branches would wait for each other's registers
     double uu[UB][F], kk[UB][F][4];
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      if (kind[u] == SRC_SAME) {
-        const uint32_t off = (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]);
+      const bool same = kind[u] == SRC_SAME, coarse = kind[u] == SRC_COARSE;
+      const uint32_t off = same ? (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]) : 0u;
+      // ghost-table entry (in the slot's first int), octant beta of the leaf
+      const int beta = (kbv[u] >> 4) & 7;
+      const int x2 = 4 * (beta & 1) + nuv[u][0], y2 = 4 * ((beta >> 1) & 1) + nuv[u][1],
+                z2 = 4 * ((beta >> 2) & 1) + nuv[u][2];
+      const double* pa = coarse ? cs + ((int64_t)leaf[u] * F * 729 + (z2 * 9 + y2) * 9 + x2) : Us + off;
+      const int fst = coarse ? 729 : fsz;
 #pragma unroll
-        for (int f = 0; f < F; ++f) {
-          uu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
+      for (int f = 0; f < F; ++f) {
+        uu[u][f] = pa[(int64_t)f * fst];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
-        }
-      } else if (kind[u] == SRC_COARSE) {
-        // ghost-table entry (in the slot's first int), octant beta of the leaf
-        const int beta = (kbv[u] >> 4) & 7;
-        const int x2 = 4 * (beta & 1) + nuv[u][0], y2 = 4 * ((beta >> 1) & 1) + nuv[u][1],
-                  z2 = 4 * ((beta >> 2) & 1) + nuv[u][2];
-#pragma unroll
-        for (int f = 0; f < F; ++f) uu[u][f] = cs[((int64_t)leaf[u] * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
+        for (int i = 0; i < 4; ++i)
+          if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
       }
     }
 #pragma unroll
@@ -541,6 +590,8 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       }
     }
   }
+  TileTables tb{0, 0, 0.0};
+  if (more) tb = tables_issue<TT, F, KF32, NT>(sp, nxt, ntrec);
   __syncthreads();
   // last stage: U0 and the earlier stages at this thread's zip nodes, issued
   // before the stencils so that their latency overlaps them
@@ -572,6 +623,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
 #pragma unroll
     for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
   }
+  if (more) tables_store(L, b ^ 1, tb);
   __syncthreads();
   // (2b) zip: every DG node of the tile's (contiguous) octants takes its grid
   // value; node e of the tile is element first*125 + e of every field array;
@@ -638,6 +690,44 @@ constexpr int fused_waves_per_eu() {
   return (F > 2 || w < 1) ? 1 : (w > cap ? cap : w);
 }
 
+// Tile range [lo, hi) of XCD x (uniform): unrolled selects, so that the kernel
+// argument array is not indexed at run time (which would copy it to scratch).
+__device__ __forceinline__ void xcd_range(const XcdRanges& xr, int x, int& lo, int& hi) {
+  lo = xr.b[0];
+  hi = xr.b[1];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (k == x) {
+      lo = xr.b[k];
+      hi = xr.b[k + 1];
+    }
+}
+
+// A workgroup's walk over tiles lo, lo + step, ... < hi; ref_of(i) gives tile i.
+// The first tile's tables are loaded here, every later one's by the tile before.
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, typename RefOf>
+__device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32>& L, const StageParams& sp, int lo, int step, int hi,
+                                           const RefOf& ref_of) {
+  if (lo >= hi) return;
+  TileRef cur = ref_of(lo);
+  int32_t trec[8];
+  load_trec(cur.tile, trec);
+  tables_store(L, 0, tables_issue<TT, F, KF32, NT>(sp, cur, trec));
+  __syncthreads();
+  int b = 0;
+  for (int ti = lo;; ti += step) {
+    const bool more = ti + step < hi;
+    TileRef nxt = more ? ref_of(ti + step) : cur;
+    int32_t ntrec[8];
+    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp, cur, trec, b, nxt, more, ntrec);
+    if (!more) break;
+    cur = nxt;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) trec[k] = ntrec[k];
+    b ^= 1;
+  }
+}
+
 // One mesh: workgroups are dealt to the 8 XCDs round robin; XCD x walks its own
 // contiguous (Morton-ordered, cost-balanced) range of tiles.  Coarser ghosts come
 // prolongated from the ghost-table pre-pass (scr).
@@ -652,8 +742,11 @@ void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* _
   const int xcd = blockIdx.x & 7;
   const int sid = blockIdx.x >> 3;
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
-  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot)
-    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots, scr);
+  int lo, hi;
+  xcd_range(xr, xcd, lo, hi);
+  fused_walk<TT, F, EQ, KF32, NT, KS>(L, sp, lo + sid, nslot, hi, [&](int ti) {
+    return TileRef{v, n4, tiles + 8 * (int64_t)ti, slots, scr};
+  });
 }
 
 // Several independent meshes advanced together (continuous batching): in round r
@@ -693,7 +786,7 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
   const int xcd = blockIdx.x & 7;
   const int sid = blockIdx.x >> 3;
   const int lo = (int)((int64_t)total * xcd / 8), hi = (int)((int64_t)total * (xcd + 1) / 8);
-  for (int ti = lo + sid; ti < hi; ti += nslot) {
+  fused_walk<TT, F, EQ, KF32, NT, KS>(L, sp0, lo + sid, nslot, hi, [&](int ti) {
     int a = 0, z = nsims - 1;   // the simulation s with cum[s] <= ti < cum[s+1]
     while (a < z) {
       const int mid = (a + z + 1) >> 1;
@@ -704,11 +797,10 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
     const BatchSim& b = sims[s];
     const int64_t rr = r - b.r0;
     const int dl = b.lmax - b.lmin;
-    const SimView v{b.U, b.U, b.K, b.K, b.N, b.lmin, b.lmax, (int)(rr & ((1 << dl) - 1)), b.sigma};
-    const int n4 = (int)((b.n0 + (rr >> dl)) & 3);
-    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp0, v, n4, b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]),
-                                              b.slots[TT - 1], scr + (int64_t)b.gbase * F * 729);
-  }
+    return TileRef{SimView{b.U, b.U, b.K, b.K, b.N, b.lmin, b.lmax, (int)(rr & ((1 << dl) - 1)), b.sigma},
+                   (int)((b.n0 + (rr >> dl)) & 3), b.tiles[TT - 1] + 8 * (int64_t)(ti - cum[s]), b.slots[TT - 1],
+                   scr + (int64_t)b.gbase * F * 729};
+  });
 }
 
 // ------------------------------------------------------------------ streamed blocks
@@ -1199,7 +1291,9 @@ __global__ __launch_bounds__(NT) void k_stream(StageParams sp, const int32_t* __
   const int xcd = blockIdx.x & 7;
   const int sid = blockIdx.x >> 3;
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
-  for (int ti = xr.b[xcd] + sid; ti < xr.b[xcd + 1]; ti += nslot)
+  int lo, hi;
+  xcd_range(xr, xcd, lo, hi);
+  for (int ti = lo + sid; ti < hi; ti += nslot)
     stream_tile<F, EQ, KF32, NT, KS, LAST>(L, sp, v, n4, tiles + 8 * (int64_t)ti, slots, scr);
 }
 
