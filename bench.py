@@ -89,11 +89,11 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def stored_traffic():
+def stored_traffic(path=None):
     """Measured HBM bytes per fused stage from the committed counter summary, or
     None when the kernel or launch sources have changed since it was taken."""
     import re
-    path = os.path.join(ROOT, "profiles", "fused_stage_wave_c2_counters.md")
+    path = path or os.path.join(ROOT, "profiles", "fused_stage_wave_c2_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -108,6 +108,28 @@ def stored_traffic():
 # stages the stage state needs, write K_s; the last stage also writes U_new.
 def passes_rk4(stage: int) -> int:
     return {0: 2, 1: 3, 2: 3, 3: 6}[stage]
+
+
+def stage_accounting(info: dict, tiles: np.ndarray, nfields: int = 2) -> dict:
+    """Algorithmic bytes of one LTS coarse step of RK4 (FP64), counted per fused
+    stage: substep j runs the tiles of levels >= its lowest active level (all
+    levels at j = 0, lmax - ctz(j) otherwise; Alg. 2 with the schedule B_j), and
+    each of its 4 stages moves passes_rk4(s) x 8 B per node and field.  Also the
+    launches (ghost pre-pass + one per tile side present) of the step."""
+    nsub = int(info["n_substeps"])
+    lev = tiles[:, 2]
+    nodes_t = 125 * tiles[:, 4].astype(np.int64) ** 3
+    alg = stages = launches = 0
+    for j in range(nsub):
+        lo = info["lmin"] if j == 0 else info["lmax"] - ((j & -j).bit_length() - 1)
+        act = lev >= lo
+        nodes = int(nodes_t[act].sum())
+        sides = len(set(tiles[act, 4].tolist()))
+        for s in range(4):
+            alg += nodes * passes_rk4(s) * 8 * nfields
+            stages += 1
+            launches += 1 + sides
+    return {"alg_bytes": alg, "stages": stages, "launches": launches}
 
 
 def analytic_error(sim_out, leaves, L, pulses, sigma, T):
@@ -286,22 +308,9 @@ def main():
     lts = res.get("lts")
     roof = None
     if lts:
-        nsub = info["n_substeps"]
         tiles = gm.tiles()
-        lev = tiles[:, 2]
-        nodes_t = 125 * tiles[:, 4].astype(np.int64) ** 3
-        alg = 0
-        stages = 0
-        launches = 0
-        for j in range(nsub):
-            lo = info["lmin"] if j == 0 else info["lmax"] - ((j & -j).bit_length() - 1)
-            act = lev >= lo
-            nodes = int(nodes_t[act].sum())
-            sides = len(set(tiles[act, 4].tolist()))
-            for s in range(4):
-                alg += nodes * passes_rk4(s) * 8 * 2
-                stages += 1
-                launches += 1 + sides
+        acc_ = stage_accounting(info, tiles)
+        alg, stages, launches = acc_["alg_bytes"], acc_["stages"], acc_["launches"]
         assert alg == 224 * w_lts
         t_step = lts["event_s"] / args.steps
         achieved = alg / t_step / 1e9

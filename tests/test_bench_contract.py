@@ -1,0 +1,54 @@
+"""CPU tests of bench.py's contract: one GPU only, the roofline's algorithmic
+byte count (224 B per FP64 LTS node-update, counted per fused stage) and the
+reader of the committed counter summary."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+@pytest.mark.parametrize("tile", [1, 2, 4])
+def test_stage_accounting_is_224_bytes_per_node_update(tile):
+    import paper_2011_10570_amd as P
+    from workloads import mesh_spec
+    gm = P.build_mesh(mesh_spec("small"))
+    gm.set_tile(tile)
+    info = gm.info()
+    acc = bench.stage_accounting(info, gm.tiles())
+    assert acc["alg_bytes"] == 224 * info["node_updates_lts"]
+    assert acc["stages"] == 4 * info["n_substeps"]
+    # a ghost pre-pass and at least one tile launch per stage
+    assert 2 * acc["stages"] <= acc["launches"] <= 4 * acc["stages"]
+
+
+def test_rk4_passes_total_14():
+    assert sum(bench.passes_rk4(s) for s in range(4)) == 14
+
+
+def test_stored_traffic_reader(tmp_path):
+    good = tmp_path / "c.md"
+    good.write_text(f"traffic_bytes_per_stage: 2.5e+09\nsources_sha256: {bench.source_digest()}\n")
+    assert bench.stored_traffic(str(good)) == 2.5e9
+    stale = tmp_path / "s.md"
+    stale.write_text("traffic_bytes_per_stage: 2.5e+09\nsources_sha256: " + "0" * 64 + "\n")
+    assert bench.stored_traffic(str(stale)) is None
+    assert bench.stored_traffic(str(tmp_path / "missing.md")) is None
+
+
+def test_committed_counter_summary_parses():
+    txt = open(os.path.join(ROOT, "profiles", "fused_stage_wave_c2_counters.md")).read()
+    assert "traffic_bytes_per_stage:" in txt and "sources_sha256:" in txt
