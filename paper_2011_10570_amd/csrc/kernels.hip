@@ -997,21 +997,27 @@ struct RingAt {
 };
 
 // Raw loads of one padded plane (per thread: KP points), issued one step before
-// they are combined into stage values, so that their latency spans a whole step.
-template <int KP, int F>
+// they are combined into stage values, so that their latency spans a whole step:
+// U (or the prolongated ghost) and the same-level stages K_i, i in the mask KS.
+// Points of finer sources load theirs when they are combined (they are few).
+template <int KP, int F, int KS>
 struct PlaneLoads {
+  static constexpr int NK = (KS & 1) + ((KS >> 1) & 1) + ((KS >> 2) & 1);
   int kind[KP];
   double uu[KP][F];
-  double kk[KP][F][3];   // a stage state reads K_i, i < p - 1 <= 3
+  double kk[KP][F][NK > 0 ? NK : 1];
 };
 
-// Last stage: U0 and the earlier stages at the DG nodes of one output plane
-// (per thread: KN nodes), loaded one step before the RK update uses them.
-template <int KN, int F>
-struct NodeLoads {
-  double u0[KN][F];
-  double kp[KN][F][3];
-};
+// The k-th set bit of the mask KS (compile-time).
+template <int KS>
+constexpr int ks_bit(int k) {
+  for (int i = 0; i < 3; ++i)
+    if ((KS >> i) & 1) {
+      if (k == 0) return i;
+      --k;
+    }
+  return 0;
+}
 
 // Per-block constants of the streaming kernel.
 template <bool KF32>
@@ -1028,85 +1034,99 @@ struct StreamCtx {
   int fsz, first, kmf;
 };
 
-// loads of padded plane pz into Q.  Every path writes every field of Q (values
-// are selected, not the fields), so Q stays in registers across the step.
+// loads of padded plane pz into Q.  Every lane loads (lanes that need no value
+// read a valid dummy element), so the loads form one straight-line batch.  Only
+// points that a stencil reads are loaded: no corner of a plane of the block's z
+// range, and only the block's x-y core in the planes above and below it.
 template <int F, bool KF32, int NT, int KS, int KP>
 __device__ __forceinline__ void stream_issue(const StreamLds<F, KF32>& L, const StreamCtx<KF32>& x, int pz,
-                                             PlaneLoads<KP, F>& Q) {
+                                             PlaneLoads<KP, F, KS>& Q) {
   constexpr int P = StreamLds<F, KF32>::P, PL = StreamLds<F, KF32>::PL;
+  constexpr int NK = PlaneLoads<KP, F, KS>::NK;
   if (pz >= P) return;
   const int Qz = pz - 3;
   const int cz = cell_of(Qz, 4);
   const int nuz = Qz - 4 * cz, szz = cz + 1;
+  const bool zcore = pz >= 3 && pz < P - 3;
 #pragma unroll
   for (int u = 0; u < KP; ++u) {
     const int p = threadIdx.x + u * NT;
-    const bool on = p < PL;
-    const int pp = on ? p : 0;
+    const int pp = p < PL ? p : 0;
     const int qy = pp / P, qx = pp - P * qy;
+    const bool xc = qx >= 3 && qx < P - 3, yc = qy >= 3 && qy < P - 3;
+    const bool on = p < PL && (zcore ? (xc || yc) : (xc && yc));
     const int ax = L.axl[0][qx], ay = L.axl[1][qy];
     const int si = (ax & 7) + 6 * ((ay & 7) + 6 * szz);
     const int kb = L.sl[2 * si + 1];
     const int leaf = L.sl[2 * si];
     const int nux = ax >> 3, nuy = ay >> 3;
-    const int kind = kb & 15;
-    const bool fine = kind == SRC_FINE, coarse = kind == SRC_COARSE;
-    // node of the source leaf (finer: the coincident node of child c)
-    const int cx = fine ? min(nux >> 1, 1) : 0, cy = fine ? min(nuy >> 1, 1) : 0, czz = fine ? min(nuz >> 1, 1) : 0;
-    const int sc = fine ? 2 : 1;
-    const uint32_t off = (uint32_t)((leaf + cx + 2 * cy + 4 * czz) * 125 + sc * (nux - 2 * cx) +
-                                    5 * sc * (nuy - 2 * cy) + 25 * sc * (nuz - 2 * czz));
-    // coarser: the prolongated ghost in scr
-    const int beta = (kb >> 4) & 7;   // coarser: leaf = the ghost-table entry
+    const int kind = on ? (kb & 15) : -1;
+    const bool same = kind == SRC_SAME, coarse = kind == SRC_COARSE;
+    const uint32_t off = same ? (uint32_t)(leaf * 125 + nux + 5 * nuy + 25 * nuz) : 0u;
+    // coarser: the prolongated ghost in scr (leaf = the ghost-table entry)
+    const int beta = (kb >> 4) & 7;
     const int x2 = 4 * (beta & 1) + nux, y2 = 4 * ((beta >> 1) & 1) + nuy, z2 = 4 * ((beta >> 2) & 1) + nuz;
-    const int km = (!on || coarse) ? 0 : (fine ? x.kmf : KS);
-    Q.kind[u] = on ? kind : -1;
+    const double* pa = coarse ? x.cs + ((int64_t)leaf * F * 729 + (z2 * 9 + y2) * 9 + x2) : x.Us + off;
+    const int fst = coarse ? 729 : x.fsz;
+    Q.kind[u] = kind;
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      double uv = 0.0;
-      if (on) {
-        if (coarse) uv = x.cs[((int64_t)leaf * F + f) * 729 + (z2 * 9 + y2) * 9 + x2];
-        else uv = ld32((fine ? x.Uf : x.Us) + (uint32_t)(f * x.fsz), off);
-      }
-      Q.uu[u][f] = uv;
+      Q.uu[u][f] = pa[(int64_t)f * fst];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        Q.kk[u][f][i] = ((km >> i) & 1) ? (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off) : 0.0;
+      for (int k = 0; k < NK; ++k)
+        Q.kk[u][f][k] = (double)ld32(x.Kr + (uint32_t)((ks_bit<KS>(k) * F + f) * x.fsz), off);
     }
   }
 }
 
 // stage values of plane pz (loads in Q) into its ring slot: Y = U + dt sum w K
-// (same-level: case (0,1) weights, finer: case (0,1/2)), coarser ghosts as they are
+// (same-level: case (0,1) weights; finer: case (0,1/2), loaded here), coarser
+// ghosts as they are
 template <int F, bool KF32, int NT, int KS, int KP>
 __device__ __forceinline__ void stream_store(StreamLds<F, KF32>& L, const StreamCtx<KF32>& x, int pz,
-                                             const PlaneLoads<KP, F>& Q) {
+                                             const PlaneLoads<KP, F, KS>& Q) {
   using LS = StreamLds<F, KF32>;
   constexpr int P = LS::P, PL = LS::PL;
+  constexpr int NK = PlaneLoads<KP, F, KS>::NK;
   using LT = typename LS::LT;
   if (pz >= P) return;
   LT* Yp = L.Y + (pz & 7) * PL;
+  const int Qz = pz - 3;
+  const int cz = cell_of(Qz, 4);
+  const int nuz = Qz - 4 * cz, szz = cz + 1;
 #pragma unroll
   for (int u = 0; u < KP; ++u) {
     const int kind = Q.kind[u];
-    if (kind < 0) continue;
     const int p = threadIdx.x + u * NT;
-    const bool fine = kind == SRC_FINE;
-    const int km = fine ? x.kmf : KS;
-    const double* w = fine ? x.wf : L.wsh;
+    if (kind == SRC_FINE) {
+      // the coincident node of child c of the finer source
+      const int qy = p / P, qx = p - P * qy;
+      const int ax = L.axl[0][qx], ay = L.axl[1][qy];
+      const int si = (ax & 7) + 6 * ((ay & 7) + 6 * szz);
+      const int leaf = L.sl[2 * si];
+      const int nux = ax >> 3, nuy = ay >> 3;
+      const int cx = min(nux >> 1, 1), cy = min(nuy >> 1, 1), czz = min(nuz >> 1, 1);
+      const uint32_t off = (uint32_t)((leaf + cx + 2 * cy + 4 * czz) * 125 + 2 * (nux - 2 * cx) +
+                                      10 * (nuy - 2 * cy) + 50 * (nuz - 2 * czz));
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      double y;
-      if (kind == SRC_COARSE) {
-        y = Q.uu[u][f] - L.ref[f];
-      } else {
+      for (int f = 0; f < F; ++f) {
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          if ((km >> i) & 1) acc = fma(w[i], Q.kk[u][f][i], acc);
-        y = Q.uu[u][f] + x.dt * acc - L.ref[f];
+          if ((x.kmf >> i) & 1) acc = fma(x.wf[i], (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off), acc);
+        Yp[f * 8 * PL + p] = (LT)(ld32(x.Uf + (uint32_t)(f * x.fsz), off) + x.dt * acc - L.ref[f]);
       }
-      Yp[f * 8 * PL + p] = (LT)y;
+    } else if (kind == SRC_SAME) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) acc = fma(L.wsh[ks_bit<KS>(k)], Q.kk[u][f][k], acc);
+        Yp[f * 8 * PL + p] = (LT)(Q.uu[u][f] + x.dt * acc - L.ref[f]);
+      }
+    } else if (kind == SRC_COARSE) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) Yp[f * 8 * PL + p] = (LT)(Q.uu[u][f] - L.ref[f]);
     }
   }
 }
@@ -1147,32 +1167,10 @@ __device__ __forceinline__ void plane_node(int first, int gz, int e, uint32_t& o
 
 __device__ __forceinline__ int plane_nodes(int gz) { return ((gz & 3) == 0 && gz > 0 && gz < 16) ? 800 : 400; }
 
-// last stage: the RK-update operands of output plane gz into N
-template <int F, bool KF32, int NT, int KN>
-__device__ __forceinline__ void stream_issue_rk(const StageParams& sp, const StreamCtx<KF32>& x, int gz,
-                                                NodeLoads<KN, F>& N) {
-  if (gz < 0 || gz >= 17) return;
-  const int nn = plane_nodes(gz);
-#pragma unroll
-  for (int u = 0; u < KN; ++u) {
-    const int e = threadIdx.x + u * NT;
-    uint32_t off = 0;
-    int gp = 0;
-    if (e < nn) plane_node(x.first, gz, e, off, gp);
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      N.u0[u][f] = e < nn ? ld32(x.Us + (uint32_t)(f * x.fsz), off) : 0.0;
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        N.kp[u][f][i] = (e < nn && i < sp.stage) ? (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off) : 0.0;
-    }
-  }
-}
-
-// zip (+ RK update at the last stage, operands in N) of output plane gz from R
-template <int F, bool KF32, int NT, bool LAST, int KN>
-__device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCtx<KF32>& x, int gz, const double* R,
-                                           const NodeLoads<KN, F>& N) {
+// zip (+ RK update at the last stage, its operands loaded here) of output
+// plane gz from R
+template <int F, bool KF32, int NT, bool LAST>
+__device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCtx<KF32>& x, int gz, const double* R) {
   constexpr int GL = StreamLds<F, KF32>::GL;
   if (gz < 0 || gz >= 17) return;
   const int nn = plane_nodes(gz);
@@ -1180,14 +1178,21 @@ __device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCt
 #pragma unroll
   for (int i = 1; i < 4; ++i)
     if (i == sp.stage) bs = sp.b[i];
-  constexpr int KZ = (800 + NT - 1) / NT;
-#pragma unroll
-  for (int u = 0; u < KZ; ++u) {
-    const int e = threadIdx.x + u * NT;
-    if (e >= nn) continue;
+#pragma unroll 1
+  for (int e = threadIdx.x; e < nn; e += NT) {
     uint32_t off;
     int gp;
     plane_node(x.first, gz, e, off, gp);
+    double u0[F], kp[F][3];
+    if constexpr (LAST) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        u0[f] = ld32(x.Us + (uint32_t)(f * x.fsz), off);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          kp[f][i] = i < sp.stage ? (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off) : 0.0;
+      }
+    }
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       double kv = R[f * GL + gp];
@@ -1203,9 +1208,9 @@ __device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCt
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          if (i < sp.stage) acc = fma(sp.b[i], N.kp[u][f][i], acc);
+          if (i < sp.stage) acc = fma(sp.b[i], kp[f][i], acc);
         acc = fma(bs, kv, acc);
-        st32(x.Uw1 + (uint32_t)(f * x.fsz), off, N.u0[u][f] + x.dt * acc);
+        st32(x.Uw1 + (uint32_t)(f * x.fsz), off, u0[f] + x.dt * acc);
       }
     }
   }
@@ -1256,25 +1261,19 @@ __device__ __forceinline__ void stream_tile(StreamLds<F, KF32>& L, const StagePa
   if (threadIdx.x < F) L.ref[threadIdx.x] = KF32 ? x.Us[threadIdx.x * x.fsz + x.first * 125] : 0.0;
   __syncthreads();
   // Two sets of plane loads alternate: step `it` issues plane it+1 into one set
-  // while the other, issued in step it-1, is consumed.  At the last stage the
-  // RK operands of output plane it-8 are issued at the start of step it and used
-  // by its zip after the stencils.
-  constexpr int KN = (800 + NT - 1) / NT;
-  PlaneLoads<KP, F> A, B;
-  NodeLoads<LAST ? KN : 1, F> N;
+  // while the other, issued in step it-1, is consumed.
+  PlaneLoads<KP, F, KS> A, B;
   stream_issue<F, KF32, NT, KS>(L, x, 0, A);
   for (int it = 0; it <= P + 1; it += 2) {
-    if constexpr (LAST) stream_issue_rk<F, KF32, NT>(sp, x, it - 8, N);
     stream_issue<F, KF32, NT, KS>(L, x, it + 1, B);
     stream_stencil<F, EQ, KF32, NT>(L, x, it - 7, L.R[it & 1]);
-    stream_zip<F, KF32, NT, LAST>(sp, x, it - 8, L.R[(it + 1) & 1], N);
+    stream_zip<F, KF32, NT, LAST>(sp, x, it - 8, L.R[(it + 1) & 1]);
     stream_store<F, KF32, NT, KS>(L, x, it, A);
     __syncthreads();
     if (it + 1 > P + 1) break;
-    if constexpr (LAST) stream_issue_rk<F, KF32, NT>(sp, x, it - 7, N);
     stream_issue<F, KF32, NT, KS>(L, x, it + 2, A);
     stream_stencil<F, EQ, KF32, NT>(L, x, it - 6, L.R[(it + 1) & 1]);
-    stream_zip<F, KF32, NT, LAST>(sp, x, it - 7, L.R[it & 1], N);
+    stream_zip<F, KF32, NT, LAST>(sp, x, it - 7, L.R[it & 1]);
     stream_store<F, KF32, NT, KS>(L, x, it + 1, B);
     __syncthreads();
   }

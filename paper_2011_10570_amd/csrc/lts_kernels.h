@@ -27,7 +27,7 @@ struct StageParams {
 struct LaunchShape {
   int threads = 512;
   int max_wg = 4096;
-  int stream_threads = 256;
+  int stream_threads = 512;
 };
 
 // Tiles of one launch cut into 8 contiguous ranges, one per XCD: XCD x walks
