@@ -679,14 +679,14 @@ __device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const Stage
 }
 
 // Waves per SIMD that the LDS of one workgroup allows: the register budget the
-// compiler is asked to keep so that registers do not cost occupancy.  Capped at
-// 6 (80 registers; 5 for side-1 tiles, which spill at 80), and left free for 6
-// fields, where a tighter budget spills.
+// compiler is asked to keep so that registers do not cost occupancy.  Capped
+// where a tighter budget spills: 6 (80 registers) for FP64 side-2 tiles, 8 (64)
+// with FP32 stencils, 5 for side-1 tiles; left free for 6 fields.
 template <int TT, int F, bool KF32, int NT>
 constexpr int fused_waves_per_eu() {
   const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32>);
   const int w = wg * (NT / 64) / 4;
-  const int cap = TT == 1 ? 5 : 6;
+  const int cap = TT == 1 ? 5 : (KF32 ? 8 : 6);
   return (F > 2 || w < 1) ? 1 : (w > cap ? cap : w);
 }
 
