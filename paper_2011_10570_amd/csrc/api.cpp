@@ -492,7 +492,7 @@ lts_status lts_rk_stage(lts_mesh* mesh, const lts_stage_view* view, const double
   return LTS_OK;
 }
 
-static LaunchShape g_shape;  // defaults: tile kernels 512 threads, streaming kernel 256, grid cap 4096
+static LaunchShape g_shape;  // defaults: 512 threads (tile and streaming kernels), grid cap 65536
 static int64_t g_shape_gen = 0;  // bumped by every change (captured graphs bake the shape in)
 
 lts_status lts_set_launch(int32_t threads, int32_t max_workgroups, int32_t stream_threads) {

@@ -1546,7 +1546,7 @@ static hipError_t go(const StageParams& sp, const OneArgs& a, int max_wg, hipStr
 }
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
 static hipError_t go(const StageParams& sp, const BatchArgs& a, int max_wg, hipStream_t s) {
-  const int grid = fused_grid((int)std::min<int64_t>(a.total, 1 << 30), max_wg);
+  const int grid = fused_grid((int)std::min<int64_t>(a.total, 1 << 30), std::min(max_wg, kBatchMaxWg));
   hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims,
                      a.round, a.scr);
   return hipGetLastError();
@@ -1626,7 +1626,7 @@ hipError_t launch_ghost_pre_batch(int F, bool kf32, const StageParams& sp0, cons
                                   const int64_t* round, int64_t total, double* scr, int max_wg, hipStream_t s) {
   if (total <= 0 || nsims <= 0) return hipSuccess;
   if (nsims > kMaxBatch) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, max_wg)));
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, std::min(max_wg, kBatchMaxWg))));
   if (F == 2) {
     if (kf32) hipLaunchKernelGGL((k_ghost_pre_batch<true, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
     else hipLaunchKernelGGL((k_ghost_pre_batch<false, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);

@@ -26,7 +26,7 @@ struct StageParams {
 // grid (workgroups, rounded to a multiple of 8 XCDs).
 struct LaunchShape {
   int threads = 512;
-  int max_wg = 4096;
+  int max_wg = 65536;
   int stream_threads = 512;
 };
 
@@ -40,6 +40,9 @@ struct XcdRanges {
 // r0 from coarse step n0 and takes part in `rounds` rounds; round r is its
 // substep (r - r0) mod 2^(lmax-lmin) of coarse step n0 + (r - r0) div 2^(lmax-lmin).
 constexpr int kMaxBatch = 256;
+// Grid cap of batched launches: every workgroup of one first prefix-sums the
+// active counts of all simulations of the batch, so it should walk many tiles.
+constexpr int kBatchMaxWg = 4096;
 struct BatchSim {
   double* U;                     // [2][F][N][125]
   void* K;                       // [p][F][N][125]

@@ -33,7 +33,7 @@ def _candidates(tiles, threads, max_workgroups, stream_threads):
 
 def tune(mesh, U0, equation: str = "wave", precision: int = 0, tableau: str = "rk4", mode: int = MODE_LTS,
          tiles: Iterable[int] = (1, 2, 4), threads: Iterable[int] = (256, 512),
-         max_workgroups: Iterable[int] = (1024, 2048, 4096), stream_threads: Iterable[int] = (512, 256),
+         max_workgroups: Iterable[int] = (4096, 16384, 65536), stream_threads: Iterable[int] = (512, 256),
          n_coarse: int = 1, reps: int = 2, check: bool = True, ko_sigma: float = 0.1, device: str = "cuda",
          use_cache: bool = True) -> dict:
     """Time every (tile, threads, max_workgroups, stream_threads) candidate on
