@@ -511,10 +511,6 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   const int kmf = stage_mask(sp, c.case_fine);
   const double* wf = wsh + 4 * c.case_fine;
 
-  // PF: issue the last stage's RK operands before the stencils.  Off: holding
-  // them costs the registers that 3 resident side-2 workgroups per CU leave.
-  constexpr bool PF = false;
-
   // (1) stage values of the used padded points
   for (int p0 = threadIdx.x; p0 < X::NC; p0 += UB * NT) {
     int li[UB], kind[UB], leaf[UB], kbv[UB], nuv[UB][3];
@@ -593,24 +589,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   TileTables tb{0, 0, 0.0};
   if (more) tb = tables_issue<TT, F, KF32, NT>(sp, nxt, ntrec);
   __syncthreads();
-  // last stage: U0 and the earlier stages at this thread's zip nodes, issued
-  // before the stencils so that their latency overlaps them
+  // the last stage's RK operands are loaded in the zip: holding them across the
+  // stencils would cost the registers that 3 resident side-2 workgroups leave
   constexpr int NN = TT * TT * TT * 125;
   constexpr int KZ = (NN + NT - 1) / NT;
-  double zu[KZ][F], zk[KZ][F][3];
-#pragma unroll
-  for (int u = 0; u < KZ; ++u) {
-    const int e = threadIdx.x + u * NT;
-    const bool on = PF && last && e < NN;
-    const uint32_t off = (uint32_t)(first * 125 + (e < NN ? e : 0));
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      zu[u][f] = on ? ld32(Us + (uint32_t)(f * fsz), off) : 0.0;
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        zk[u][f][i] = (on && i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
-    }
-  }
   // (2a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
   constexpr int G = X::G;
   constexpr int G3 = G * G * G;
@@ -637,13 +619,14 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     const int e = threadIdx.x + u * NT;
     if (e >= NN) continue;
     const uint32_t off = (uint32_t)(first * 125 + e);
-    if (!PF && last) {
+    double zu[F], zk[F][3];
+    if (last) {
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        zu[u][f] = ld32(Us + (uint32_t)(f * fsz), off);
+        zu[f] = ld32(Us + (uint32_t)(f * fsz), off);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          zk[u][f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
+          zk[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
       }
     }
     const int o = e / 125, node = e - 125 * (e / 125);
@@ -665,9 +648,9 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          if (i < sp.stage) acc = fma(sp.b[i], zk[u][f][i], acc);
+          if (i < sp.stage) acc = fma(sp.b[i], zk[f][i], acc);
         acc = fma(bs, kv, acc);
-        st32(Uw1 + (uint32_t)(f * fsz), off, zu[u][f] + c.dt * acc);
+        st32(Uw1 + (uint32_t)(f * fsz), off, zu[f] + c.dt * acc);
       }
     }
   }
@@ -808,8 +791,8 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
 // (23^3 points per field) never sits in LDS at once.  A ring of 8 padded planes
 // holds the 7 planes one output plane of the 17^3 block grid needs plus the plane
 // being loaded, so the loads of padded plane z+7 are in flight while the stencils
-// of output plane z run.  Gathered points per DG node drop from 3.4 (side-2
-// tiles) to 1.5.
+// of output plane z run.  Of each plane only the points a stencil reads are
+// gathered: 1.26 points per DG node, against 2.19 for side-2 tiles.
 
 // Ghost-table pre-pass, before the fused launches of a stage: entry g (a leaf
 // that is a coarser source of receivers one level finer) gets its stage state

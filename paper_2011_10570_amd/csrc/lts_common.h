@@ -74,12 +74,4 @@ LTS_HD Loc locate(int qx, int qy, int qz, int ox, int oy, int oz, int tt, int m)
   return r;
 }
 
-// Nodes of slot position s (0 .. tt+1 along one axis) that the location rule
-// assigns to that slot inside the padded region: nu in [lo, hi].
-LTS_HD void owned_range(int s, int o, int tt, int m, int& lo, int& hi) {
-  const int cell = o + s - 1;
-  lo = (s == 0 || cell >= m) ? 1 : 0;
-  hi = (s >= 1 && s <= tt && cell == m - 1) ? 4 : 3;
-}
-
 }  // namespace lts
