@@ -157,3 +157,20 @@ def test_batch_arguments_checked_before_device_use():
     assert L.lts_batch_run(None, 1, 1, None) == _lib.EINVAL
     assert L.lts_sim_rounds_left(None) == 0
     L.lts_batch_destroy(None)
+
+
+def test_launch_shape_defaults_and_validation():
+    """lts_set_launch / lts_get_launch (host state only): the defaults, a round
+    trip, and rejection of shapes the kernels are not built for."""
+    old = P.get_launch()
+    try:
+        assert old == (512, 65536, 512)
+        P.set_launch(256, 4096, 256)
+        assert P.get_launch() == (256, 4096, 256)
+        for bad in ((128, 4096, 512), (512, 4, 512), (512, 4096, 1024), (768, 4096, 512)):
+            with pytest.raises(P.LTSError):
+                P.set_launch(*bad)
+            assert P.get_launch() == (256, 4096, 256)
+    finally:
+        P.set_launch(*old)
+    assert P.get_launch() == old
