@@ -89,6 +89,43 @@ def test_streamed_blocks_equal_tiles(mode):
     assert np.array_equal(a, b)
 
 
+def _blocky_mesh():
+    """A batch problem with several 4^3 blocks next to coarser and finer leaves."""
+    p = config("batch")["problems"][6]
+    gm = P.build_mesh(p["mesh"])
+    lv = gm.leaves()
+    U0 = wave_gaussian(lv[:, :3], lv[:, 3], gm.info()["L"], [p["mesh"]["criteria"][0]["center"]], sigma=0.1)
+    return gm, U0
+
+
+def test_streamed_blocks_ssprk3():
+    """Streamed blocks with SSP-RK3 (stage masks with two same-level stages)."""
+    gm, U0 = _blocky_mesh()
+    a = _run_gpu(gm, U0, 2, P.MODE_LTS, tile=2, tableau="ssprk3")
+    b = _run_gpu(gm, U0, 2, P.MODE_LTS, tile=4, tableau="ssprk3")
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32_RHS])
+@pytest.mark.parametrize("tile", [1, 2, 4])
+def test_walked_tiles_equal_one_per_workgroup(tile, prec):
+    """Under a small grid cap every workgroup walks many tiles, loading the next
+    tile's tables while the current one runs: results equal one workgroup per
+    tile, bitwise."""
+    gm, U0 = _blocky_mesh()
+    old = P.get_launch()
+    try:
+        P.set_launch(512, 65536, 512)
+        a = _run_gpu(gm, U0, 1, P.MODE_LTS, prec=prec, tile=tile)
+        for shape in ((512, 16, 512), (256, 64, 256)):
+            print(f"[walk] tile {tile} prec {prec} shape {shape}", flush=True)
+            P.set_launch(*shape)
+            b = _run_gpu(gm, U0, 1, P.MODE_LTS, prec=prec, tile=tile)
+            assert np.array_equal(a, b), shape
+    finally:
+        P.set_launch(*old)
+
+
 def test_graph_replays_repeatable(c1):
     """Several graph replays with eager work and syncs between them."""
     om, gm, U0 = c1

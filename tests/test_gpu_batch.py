@@ -72,6 +72,24 @@ def test_batch_equals_alone(meshes, mode, prec):
         assert torch.equal(s.current(), w)
 
 
+def test_batch_walked_tiles(meshes):
+    """A batch under a small grid cap (each workgroup walks many tiles and ghost
+    entries) equals the default launch shape, bitwise."""
+    old = P.get_launch()
+    try:
+        P.set_launch(512, 65536, 512)
+        sims = [_sim(gm, t, U0) for gm, t, U0 in meshes]
+        P.batch_advance(sims, 1, P.MODE_LTS)
+        want = [s.current() for s in sims]
+        P.set_launch(512, 16, 512)
+        sims = [_sim(gm, t, U0) for gm, t, U0 in meshes]
+        P.batch_advance(sims, 1, P.MODE_LTS)
+        for s, w in zip(sims, want):
+            assert torch.equal(s.current(), w)
+    finally:
+        P.set_launch(*old)
+
+
 def test_batch_matches_oracle():
     """The small mesh advanced inside a batch against the oracle's LTS driver."""
     om = oracle_mesh("small")
