@@ -174,3 +174,17 @@ def test_launch_shape_defaults_and_validation():
     finally:
         P.set_launch(*old)
     assert P.get_launch() == old
+
+
+def test_arrays_beyond_32bit_offsets_rejected():
+    """The kernels address field arrays with 32-bit element offsets: a simulation
+    whose stage arrays (p x F x N x 125 elements) reach 2^31 is refused before any
+    device work.  A uniform level-7 mesh (2,097,152 octants) fits the wave
+    equation (4 x 2 fields) but not Maxwell (4 x 6 fields)."""
+    a, l = ot.uniform_leaves(7, 7)
+    gm = P.build_mesh(leaves=np.concatenate([a, l[:, None]], 1), L=7)
+    n = gm.info()["n_oct"]
+    assert n == 2 ** 21
+    assert 4 * 2 * n * 125 < 2 ** 31 <= 4 * 6 * n * 125
+    with pytest.raises(P.LTSError, match="32-bit"):
+        P.Sim(gm, "maxwell", P.FP64, "rk4", device="cpu")
