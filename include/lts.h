@@ -256,8 +256,8 @@ void lts_sim_destroy(lts_sim* sim);
  * equation, precision, tableau and mode together, by rounds.  In round r a sim
  * that joined at round r0 runs its own substep j = (r - r0) mod 2^(lmax-lmin)
  * (Alg. 2 schedule, fig. blk_loop, of its own mesh) of coarse step
- * n0 + (r - r0) div 2^(lmax-lmin); every stage of a round is one persistent launch
- * per tile side over the union of the active tiles of all attached sims (the
+ * n0 + (r - r0) div 2^(lmax-lmin); every stage of a round is one launch per tile
+ * side over the union of the active tiles of all attached sims (the
  * sims' meshes, level ranges and sizes may differ).  Each sim's arithmetic is the
  * one lts_advance performs: its results are bitwise those of running it alone.
  * A batch is used from one host thread and one stream. */

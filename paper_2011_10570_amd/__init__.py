@@ -223,7 +223,7 @@ def norms(mesh: Mesh, a, b=None, nfields: int = 2, stream=None) -> dict:
 
 def set_launch(threads: int, max_workgroups: int, stream_threads: int = 512):
     """Launch shape of every later fused launch: threads of the LDS tile kernels and
-    of the streaming kernel (256 or 512 each), persistent-grid cap."""
+    of the streaming kernel (256 or 512 each), grid cap in workgroups."""
     check(lib().lts_set_launch(int(threads), int(max_workgroups), int(stream_threads)), "lts_set_launch")
 
 

@@ -934,8 +934,8 @@ lts_status lts_copy_probe(const void* src, void* dst, size_t nbytes, void* strea
 // Continuous batching: a table of up to `cap` simulations (one equation,
 // precision, tableau and mode) advanced by rounds.  Round r runs, for every
 // attached simulation, its substep (r - r0) mod 2^(lmax-lmin); each stage of a
-// round is one persistent launch per tile side over the union of the active
-// tiles.  Simulations join and leave at round boundaries.
+// round is a ghost pre-pass and one launch per tile side over the union of the
+// active tiles.  Simulations join and leave at round boundaries.
 struct lts_batch {
   int eq = 0, prec = 0, tab = 0, mode = 0, F = 2, p = 4, cap = 0;
   int device = -1;

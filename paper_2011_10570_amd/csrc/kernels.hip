@@ -6,10 +6,12 @@
 // octant-local nodes and, after the last stage, the RK update (eq. rk_schemes).
 //
 // Two forms:
-//   * k_fused:  one workgroup per tile of tt^3 octants, padded tile of
-//               (4tt+7)^3 points per field resident in LDS; persistent grid with
-//               an XCD-aware tile order (each of the 8 XCDs walks a contiguous,
-//               Morton-ordered range of tiles so neighbour octants hit its L2).
+//   * fused: k_ghost_pre prolongates the coarser ghosts of the stage into a
+//               table; k_fused then runs one workgroup per tile of tt^3 octants
+//               (tt = 1, 2) with the padded points its stencils read resident
+//               in LDS, and k_stream streams whole 4^3-octant blocks along z.
+//               Tiles are dealt to the 8 XCDs in contiguous, Morton-ordered
+//               ranges, so neighbour tiles run on one XCD and share its L2.
 //   * k_unzip / k_rhs / k_zip / k_rk: the same steps as separate launches over
 //               whole blocks through HBM (phase-by-phase path and parity checks).
 // Stencils are not dense contractions: no MFMA; the work is bound by HBM traffic.
@@ -799,8 +801,8 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
 // for those receivers (time case, buffer and dt of the receiver level, eqs.
 // fc_1/fc_2) prolongated to its 9^3 half-node grid, scr[g][f][z2][y2][x2].  The
 // prolongation is separable, x, then y, then z, each a degree-4 Lagrange sum in
-// node order (the in-kernel prolongation of the batched kernel adds the same
-// terms in the same order, so a ghost has one value whichever kernel forms it).
+// node order; the one-mesh and batched pre-passes share it, so a ghost has one
+// value whichever launch forms it.
 template <int F>
 struct GhostLds {
   double wsh[16];
@@ -908,7 +910,8 @@ __global__ __launch_bounds__(256) void k_ghost_pre(StageParams sp, const int32_t
 
 // The same for every simulation of a batch in round *round: the union of their
 // active entries (receivers of levels >= each one's lowest active level), in
-// table order; simulation s writes its entries at gbase_s.  Persistent grid.
+// table order; simulation s writes its entries at gbase_s.  Each workgroup walks
+// several entries (the grid is capped for batches).
 template <bool KF32, int F>
 __global__ __launch_bounds__(256) void k_ghost_pre_batch(StageParams sp0, const BatchSim* __restrict__ sims,
                                                          int nsims, const int64_t* __restrict__ round,

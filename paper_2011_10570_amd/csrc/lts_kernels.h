@@ -22,8 +22,9 @@ struct StageParams {
 };
 
 // Launch shape of the fused kernels: threads per workgroup of the tile kernels
-// and of the streaming kernel (256 or 512 each) and the cap on the persistent
-// grid (workgroups, rounded to a multiple of 8 XCDs).
+// and of the streaming kernel (256 or 512 each) and the cap on the grid
+// (workgroups, rounded to a multiple of 8 XCDs): at or above the tile count one
+// workgroup per tile, below it workgroups walk several tiles.
 struct LaunchShape {
   int threads = 512;
   int max_wg = 65536;

@@ -2,7 +2,7 @@
 
 The shape of a fused launch (tile side t: 1 or 2 for LDS-resident tiles, 4 for
 streamed whole blocks; workgroup sizes of the tile and streaming kernels; cap on
-the persistent grid) changes which workgroup computes which grid point but not
+the grid) changes which workgroup computes which grid point but not
 the FP64 arithmetic: every candidate gives bitwise the same state, which `tune`
 checks (FP32-RHS results depend on the tile side at FP32 rounding, so there the
 check compares candidates of one tile side only).  Each candidate advances a private copy of the initial state by
