@@ -5,9 +5,10 @@ streamed whole blocks; workgroup sizes of the tile and streaming kernels; cap on
 the grid) changes which workgroup computes which grid point but not
 the FP64 arithmetic: every candidate gives bitwise the same state, which `tune`
 checks (FP32-RHS results depend on the tile side at FP32 rounding, so there the
-check compares candidates of one tile side only).  Each candidate advances a private copy of the initial state by
-`n_coarse` coarse steps (graph-captured, as lts_advance runs in production) and
-is timed with device events; the fastest is applied and cached per mesh shape.
+check compares candidates of one tile side only).  Each candidate advances a
+private copy of the initial state by reps + 1 times `n_coarse` coarse steps
+(graph-captured, as lts_advance runs in production; the first pass captures and
+warms up), and the later passes are timed with device events; the fastest is applied and cached per mesh shape.
 """
 from __future__ import annotations
 
@@ -58,9 +59,12 @@ def tune(mesh, U0, equation: str = "wave", precision: int = 0, tableau: str = "r
             mesh.set_tile(t)
             set_launch(nt, wg, st)
             sim = Sim(mesh, equation, precision, tableau, ko_sigma=ko_sigma, device=device)
+            # the state is set once: setting it again rebinds the sim, which drops
+            # the captured graph; every candidate advances (reps + 1) n_coarse
+            # steps from U0, so the final states stay comparable
+            sim.set_state(U0)
             times = []
             for r in range(reps + 1):        # first pass captures the graph and warms up
-                sim.set_state(U0)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
                 sim.advance(n_coarse, mode, graph=True)
