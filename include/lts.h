@@ -235,9 +235,6 @@ lts_status lts_set_launch(int32_t threads, int32_t max_workgroups, int32_t strea
 lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups, int32_t* stream_threads);
 
 /* ---- simulation driver (a7; Alg. 1 / Alg. 2) ---------------------------------- */
-/* A simulation of `equation` on `mesh`.  The kernels address a node inside a
- * field array with a 32-bit byte offset: LTS_EUNSUPPORTED when a field array
- * (N x 125 doubles) reaches 4 GiB, i.e. from 4,294,968 octants on. */
 lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, int32_t tableau,
                           const lts_rhs_params* params, lts_sim** out);
 /* Bind caller-owned device arrays (see lts_stage_view).  U[0] must hold the

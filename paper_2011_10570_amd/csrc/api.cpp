@@ -167,8 +167,8 @@ static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage,
   if (stage < 0 || stage >= p) return fail(LTS_EINVAL, "stage out of range");
   if (pos->mode != LTS_MODE_LTS && pos->mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
   if (pos->substep < 0 || pos->substep >= (1 << (m.lmax - m.lmin))) return fail(LTS_EINVAL, "substep out of range");
-  if (m.n() * 125 * 8 >= (1ll << 32))
-    return fail(LTS_EUNSUPPORTED, "field arrays too large for the kernels' 32-bit offsets");
+  if ((int64_t)p * v->nfields * m.n() * 125 >= (1ll << 31) || m.n() * 125 * 8 >= (1ll << 32))
+    return fail(LTS_EUNSUPPORTED, "arrays too large for the kernels' 32-bit offsets");
   double w[64], a[16], b[4];
   coefficient_tables(v->tableau, w, a, b);
   std::memset(&sp, 0, sizeof(sp));
@@ -648,8 +648,9 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
   if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
   const int p = tableau_stages(tableau);
   if (!p) return fail(LTS_EINVAL, "bad tableau");
-  if (mesh->m.n() * 125 * 8 >= (1ll << 32))
-    return fail(LTS_EUNSUPPORTED, "field arrays too large for the kernels' 32-bit offsets");
+  if ((int64_t)p * (equation == LTS_EQ_WAVE ? 2 : 6) * mesh->m.n() * 125 >= (1ll << 31) ||
+      mesh->m.n() * 125 * 8 >= (1ll << 32))
+    return fail(LTS_EUNSUPPORTED, "arrays too large for the kernels' 32-bit offsets");
   lts_status st = ensure_device(mesh->m);
   if (st != LTS_OK) return st;
   lts_sim* sim = new (std::nothrow) lts_sim();

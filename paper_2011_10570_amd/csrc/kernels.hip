@@ -499,9 +499,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   const double* ref = L.ref[b];
   auto& R = L.R;
   if (more) load_trec(nxt.tile, ntrec);
-  // elements per field (< 2^29: a node's byte offset in a field is 32-bit; the
-  // field and stage bases are 64-bit and uniform)
-  const int fsz = (int)(v.N * 125);
+  const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
   const KT* __restrict__ Kr = (const KT*)v.K;
   KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
@@ -558,7 +556,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         uu[u][f] = pa[(int64_t)f * fst];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (int64_t)(i * F + f) * fsz, off);
+          if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
       }
     }
 #pragma unroll
@@ -572,8 +570,8 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
           double acc = 0.0;
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if ((kmf >> i) & 1) acc = fma(wf[i], (double)ld32(Kr + (int64_t)(i * F + f) * fsz, off), acc);
-          Y[f * LS + li[u]] = (LT)(ld32(Uf + (int64_t)f * fsz, off) + c.dt * acc - ref[f]);
+            if ((kmf >> i) & 1) acc = fma(wf[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
+          Y[f * LS + li[u]] = (LT)(ld32(Uf + (uint32_t)(f * fsz), off) + c.dt * acc - ref[f]);
         }
       } else if (kind[u] == SRC_SAME) {
 #pragma unroll
@@ -627,10 +625,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     if (last) {
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        zu[f] = ld32(Us + (int64_t)f * fsz, off);
+        zu[f] = ld32(Us + (uint32_t)(f * fsz), off);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          zk[f][i] = (i < sp.stage) ? (double)ld32(Kr + (int64_t)(i * F + f) * fsz, off) : 0.0;
+          zk[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
       }
     }
     const int o = e / 125, node = e - 125 * (e / 125);
@@ -641,10 +639,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       double kv = R[f * G3 + gi];
       if constexpr (KF32) {
         const float kf = (float)kv;
-        st32(Kw + (int64_t)f * fsz, off, kf);
+        st32(Kw + (uint32_t)(f * fsz), off, kf);
         kv = (double)kf;
       } else {
-        st32(Kw + (int64_t)f * fsz, off, kv);
+        st32(Kw + (uint32_t)(f * fsz), off, kv);
       }
       if (last) {
         // compute_step_partial: U_new = U0 + dt (b_0 K_0 + ... + b_s K_s),
@@ -654,7 +652,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         for (int i = 0; i < 3; ++i)
           if (i < sp.stage) acc = fma(sp.b[i], zk[f][i], acc);
         acc = fma(bs, kv, acc);
-        st32(Uw1 + (int64_t)f * fsz, off, zu[f] + c.dt * acc);
+        st32(Uw1 + (uint32_t)(f * fsz), off, zu[f] + c.dt * acc);
       }
     }
   }
@@ -836,8 +834,8 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F>& L, const StageParams& s
     double acc = 0.0;
     #pragma unroll
     for (int i = 0; i < 4; ++i)
-      if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (int64_t)(i * F + f) * fsz, off), acc);
-    L.Yc[e] = ld32(Uc + (int64_t)f * fsz, off) + c.dt * acc;
+      if ((kmc >> i) & 1) acc = fma(wc[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
+    L.Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < F * 225; e += blockDim.x) {
@@ -1062,7 +1060,7 @@ __device__ __forceinline__ void stream_issue(const StreamLds<F, KF32>& L, const 
       Q.uu[u][f] = pa[(int64_t)f * fst];
 #pragma unroll
       for (int k = 0; k < NK; ++k)
-        Q.kk[u][f][k] = (double)ld32(x.Kr + (int64_t)(ks_bit<KS>(k) * F + f) * x.fsz, off);
+        Q.kk[u][f][k] = (double)ld32(x.Kr + (uint32_t)((ks_bit<KS>(k) * F + f) * x.fsz), off);
     }
   }
 }
@@ -1101,8 +1099,8 @@ __device__ __forceinline__ void stream_store(StreamLds<F, KF32>& L, const Stream
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          if ((x.kmf >> i) & 1) acc = fma(x.wf[i], (double)ld32(x.Kr + (int64_t)(i * F + f) * x.fsz, off), acc);
-        Yp[f * 8 * PL + p] = (LT)(ld32(x.Uf + (int64_t)f * x.fsz, off) + x.dt * acc - L.ref[f]);
+          if ((x.kmf >> i) & 1) acc = fma(x.wf[i], (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off), acc);
+        Yp[f * 8 * PL + p] = (LT)(ld32(x.Uf + (uint32_t)(f * x.fsz), off) + x.dt * acc - L.ref[f]);
       }
     } else if (kind == SRC_SAME) {
 #pragma unroll
@@ -1175,10 +1173,10 @@ __device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCt
     if constexpr (LAST) {
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        u0[f] = ld32(x.Us + (int64_t)f * x.fsz, off);
+        u0[f] = ld32(x.Us + (uint32_t)(f * x.fsz), off);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-          kp[f][i] = i < sp.stage ? (double)ld32(x.Kr + (int64_t)(i * F + f) * x.fsz, off) : 0.0;
+          kp[f][i] = i < sp.stage ? (double)ld32(x.Kr + (uint32_t)((i * F + f) * x.fsz), off) : 0.0;
       }
     }
 #pragma unroll
@@ -1186,10 +1184,10 @@ __device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCt
       double kv = R[f * GL + gp];
       if constexpr (KF32) {
         const float kf = (float)kv;
-        st32(x.Kw + (int64_t)f * x.fsz, off, kf);
+        st32(x.Kw + (uint32_t)(f * x.fsz), off, kf);
         kv = (double)kf;
       } else {
-        st32(x.Kw + (int64_t)f * x.fsz, off, kv);
+        st32(x.Kw + (uint32_t)(f * x.fsz), off, kv);
       }
       if constexpr (LAST) {
         // U0 + dt (b_0 K_0 + ... + b_s K_s), s = p - 1, accumulated in stage order
@@ -1198,7 +1196,7 @@ __device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCt
         for (int i = 0; i < 3; ++i)
           if (i < sp.stage) acc = fma(sp.b[i], kp[f][i], acc);
         acc = fma(bs, kv, acc);
-        st32(x.Uw1 + (int64_t)f * x.fsz, off, u0[f] + x.dt * acc);
+        st32(x.Uw1 + (uint32_t)(f * x.fsz), off, u0[f] + x.dt * acc);
       }
     }
   }

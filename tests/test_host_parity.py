@@ -176,25 +176,15 @@ def test_launch_shape_defaults_and_validation():
     assert P.get_launch() == old
 
 
-def test_field_arrays_beyond_32bit_offsets_rejected():
-    """The kernels address a node inside a field array with a 32-bit byte offset
-    (field and stage bases are 64-bit): a simulation whose field arrays (N x 125
-    doubles) reach 4 GiB is refused before any device work.  A uniform level-8
-    mesh (16,777,216 octants) is beyond that; a level-7 one (2,097,152) passes the
-    check for Maxwell too, which the 6-field stage arrays (4 x 6 x N x 125
-    elements, more than 2^31) no longer limit."""
+def test_arrays_beyond_32bit_offsets_rejected():
+    """The kernels address field arrays with 32-bit element offsets: a simulation
+    whose stage arrays (p x F x N x 125 elements) reach 2^31 is refused before any
+    device work.  A uniform level-7 mesh (2,097,152 octants) fits the wave
+    equation (4 x 2 fields) but not Maxwell (4 x 6 fields)."""
     a, l = ot.uniform_leaves(7, 7)
     gm = P.build_mesh(leaves=np.concatenate([a, l[:, None]], 1), L=7)
-    assert 4 * 6 * gm.info()["n_oct"] * 125 > 2 ** 31
-    try:
-        P.Sim(gm, "maxwell", P.FP64, "rk4", device="cpu")
-    except P.LTSError as e:     # no GPU here: the device step fails instead
-        assert "32-bit" not in str(e), e
-    except Exception:
-        pass
-    del gm
-    a, l = ot.uniform_leaves(8, 8)
-    gm = P.build_mesh(leaves=np.concatenate([a, l[:, None]], 1), L=8)
-    assert gm.info()["n_oct"] * 125 * 8 >= 2 ** 32
+    n = gm.info()["n_oct"]
+    assert n == 2 ** 21
+    assert 4 * 2 * n * 125 < 2 ** 31 <= 4 * 6 * n * 125
     with pytest.raises(P.LTSError, match="32-bit"):
-        P.Sim(gm, "wave", P.FP64, "rk4", device="cpu")
+        P.Sim(gm, "maxwell", P.FP64, "rk4", device="cpu")
