@@ -132,40 +132,68 @@ def stage_accounting(info: dict, tiles: np.ndarray, nfields: int = 2) -> dict:
     return {"alg_bytes": alg, "stages": stages, "launches": launches}
 
 
-def analytic_error(sim_out, leaves, L, pulses, sigma, T):
-    """L2 (volume weighted) / max error of u against the periodic Gaussian spherical wave."""
+def analytic_fields(leaves, L, pulses, sigma, T, device):
+    """(u, v) [2, N, 125] of the periodic Gaussian spherical wave at time T on every
+    DG node: u = (phi(r+T) + phi(r-T)) / (2r), v = (phi'(r+T) - phi'(r-T)) / (2r),
+    phi(xi) = xi g(xi), summed over the pulses and their 27 nearest images; below
+    r = 1e-4 the limits u = phi'(T) + r^2 phi'''(T) / 6, v = phi''(T)."""
     import torch
-    dev = sim_out.device
-    lv = torch.as_tensor(leaves, dtype=torch.int64, device=dev)
+    lv = torch.as_tensor(np.asarray(leaves), dtype=torch.int64, device=device)
     s = torch.bitwise_left_shift(torch.ones_like(lv[:, 3]), L - lv[:, 3]).to(torch.float64)
-    i = torch.arange(5, dtype=torch.float64, device=dev)
+    i = torch.arange(5, dtype=torch.float64, device=device)
     k_, j_, i_ = torch.meshgrid(i, i, i, indexing="ij")
     loc = torch.stack([i_, j_, k_], -1).reshape(125, 3)
     X = 4.0 * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]
     x = -1.0 + 2.0 * X / float(4 * (1 << L))
-    u = torch.zeros(x.shape[:2], dtype=torch.float64, device=dev)
+    u = torch.zeros(x.shape[:2], dtype=torch.float64, device=device)
+    v = torch.zeros_like(u)
+    s2 = sigma * sigma
+
+    def g(xi):
+        return torch.exp(-xi * xi / (2 * s2))
 
     def phi(xi):
-        return xi * torch.exp(-xi * xi / (2 * sigma * sigma))
+        return xi * g(xi)
 
-    def dphi(xi):
-        return torch.exp(-xi * xi / (2 * sigma * sigma)) * (1 - xi * xi / sigma ** 2)
+    def d1(xi):
+        return g(xi) * (1 - xi * xi / s2)
 
+    def d2(xi):
+        return g(xi) * (xi ** 3 / s2 ** 2 - 3 * xi / s2)
+
+    def d3(xi):
+        return g(xi) * (-xi ** 4 / s2 ** 3 + 6 * xi * xi / s2 ** 2 - 3 / s2)
+
+    Tt = torch.full((), float(T), dtype=torch.float64, device=device)
     for cc in pulses:
-        c = -1.0 + 2.0 * torch.tensor(cc, dtype=torch.float64, device=dev) / float(4 * (1 << L))
+        c = -1.0 + 2.0 * torch.tensor(cc, dtype=torch.float64, device=device) / float(4 * (1 << L))
         for a in (-1, 0, 1):
             for b in (-1, 0, 1):
                 for d in (-1, 0, 1):
-                    dd = x - (c + 2.0 * torch.tensor([a, b, d], dtype=torch.float64, device=dev))
+                    dd = x - (c + 2.0 * torch.tensor([d, b, a], dtype=torch.float64, device=device))
                     r = torch.sqrt((dd * dd).sum(-1))
                     small = r < 1e-4
                     rs = torch.where(small, torch.ones_like(r), r)
-                    val = (phi(rs + T) + phi(rs - T)) / (2 * rs)
-                    u += torch.where(small, dphi(torch.full_like(r, T)), val)
-    e = sim_out[0] - u
+                    u += torch.where(small, d1(Tt) + r * r * d3(Tt) / 6, (phi(rs + T) + phi(rs - T)) / (2 * rs))
+                    v += torch.where(small, d2(Tt).expand_as(r), (d1(rs + T) - d1(rs - T)) / (2 * rs))
+    return torch.stack([u, v])
+
+
+def analytic_error(sim_out, leaves, L, pulses, sigma, T):
+    """Per field (u, v): volume-weighted L2 and max error against the periodic
+    Gaussian spherical wave at T, and the L2 of the exact field itself."""
+    import torch
+    dev = sim_out.device
+    ex = analytic_fields(leaves, L, pulses, sigma, T, dev)
+    lv = torch.as_tensor(np.asarray(leaves), dtype=torch.int64, device=dev)
     w = (2.0 ** (L - lv[:, 3].to(torch.float64))) ** 3
-    l2 = torch.sqrt((w * (e * e).sum(1)).sum() / (125.0 * w.sum())).item()
-    return {"l2": l2, "linf": e.abs().max().item(), "l2_u": torch.sqrt((w * (u * u).sum(1)).sum() / (125.0 * w.sum())).item()}
+    out = {}
+    for f, name in enumerate(("u", "v")):
+        e = sim_out[f] - ex[f]
+        out[f"l2_{name}"] = torch.sqrt((w * (e * e).sum(1)).sum() / (125.0 * w.sum())).item()
+        out[f"linf_{name}"] = e.abs().max().item()
+        out[f"l2_exact_{name}"] = torch.sqrt((w * (ex[f] * ex[f]).sum(1)).sum() / (125.0 * w.sum())).item()
+    return out
 
 
 def time_leg(P, gm, U0, mode, prec, steps, warmup, torch):

@@ -5,8 +5,8 @@
  * arXiv 2011.10570).  A method-of-lines system du/dt = F(u) (eq. evolve_eq) is
  * discretised on a periodic, balanced linear octree over [-1,1]^3 whose leaves
  * carry 5^3 octant-local nodes (Sec. 3.2, fig. dg_to_cg "octant local nodes").
- * The octree is cut into uniformly refined blocks (Sec. 3.3, fig. oct_to_blocks);
- * each RK stage builds ghost-padded blocks (unzip, Sec. 3.4, fig. unzip), applies
+ * The octree is cut into uniformly refined blocks (Sec. 3.2.5, fig. oct_to_blocks);
+ * each RK stage builds ghost-padded blocks (unzip, Sec. 3.3, fig. unzip), applies
  * sixth-order finite differences with Kreiss-Oliger dissipation on the block
  * grid (rhs), scatters the result back to the octants (zip) and, after the last
  * stage, forms the RK update (eq. rk_schemes).  Global timestepping (GTS,
@@ -83,7 +83,7 @@ enum {
   LTS_EXPORT_TILES = 4       /* [T][8] tiles of the fused kernel (see lts_mesh_set_tile)       */
 };
 
-/* Unzip-map source kinds (Sec. 3.4): own octant, same-level neighbour, finer
+/* Unzip-map source kinds (Sec. 3.3): own octant, same-level neighbour, finer
  * neighbour (f->c injection), coarser neighbour (c->f interpolation). */
 enum { LTS_SRC_OWN = 0, LTS_SRC_SAME = 1, LTS_SRC_FINE = 2, LTS_SRC_COARSE = 3 };
 
@@ -164,7 +164,7 @@ typedef struct {
 const char* lts_last_error(void);
 const char* lts_version(void);
 
-/* ---- mesh (host; Sec. 3.2-3.3) ----------------------------------------------- */
+/* ---- mesh (host; Sec. 3.2) ----------------------------------------------- */
 /* Build leaves (refinement + balance), blocks, tiles, unzip source tables and the
  * level schedule on the host.  No device call is made; tables are uploaded on
  * first device use.  Errors: LTS_EINVAL (bad spec / leaves do not tile),
@@ -189,13 +189,13 @@ lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile);
  * (0,2), (1,2); plus a[p][p] and b[p].  out: double[4*p*p + p*p + p] (host). */
 lts_status lts_coefficients(int32_t tableau, double* out, size_t cap);
 
-/* ---- unfused hot path (one call per phase; Sec. 3.4, Alg. 1/2) --------------- */
+/* ---- unfused hot path (one call per phase; Sec. 3.3, Alg. 1/2) --------------- */
 /* `blocks` is a HOST array of nb block indices (NULL = every block of B_j at
  * `pos`, in block order).  All other pointers are device pointers. */
 
 /* a2: padded stage state Y_s = U0 + dt_r sum_i w^_{s,i}(case) K_i of every padded
  * point of the listed blocks, with f->c injection and tensor degree-4 Lagrange
- * c->f interpolation (Sec. 3.4; eqs. fc_1/fc_2).  stage is 0-based. */
+ * c->f interpolation (Sec. 3.3; eqs. fc_1/fc_2).  stage is 0-based. */
 lts_status lts_unzip(lts_mesh* mesh, const lts_stage_view* view, int32_t stage,
                      const lts_position* pos, const int32_t* blocks, int32_t nb,
                      double* padded, void* stream);

@@ -14,7 +14,7 @@ Modules
             fc_1, fc_2).
   octree    linear octree, refinement criteria, ghost-reach balance, octree-to-block
             decomposition, neighbour search, canonical unzip map, LTS schedule and
-            the speedup model (Sec. 3.2, 3.3, 3.6.3, 3.7; eqs. w_nuts, w_uts, invS).
+            the speedup model (Sec. 3.2, 3.2.5, 3.3, 3.6.3, 3.7; eqs. w_nuts, w_uts, invS).
   fd        finite-difference stencils and the degree-4 Lagrange interpolant.
   solver    unzip / rhs / zip / RK update and the LTS (Alg. 2) and GTS (Alg. 1)
             drivers.

@@ -11,6 +11,15 @@ The Gaussian pulse u0 = A exp(-r^2/(2 sigma^2)), v0 = 0 evolves as the spherical
 wave u = (phi(r+t) + phi(r-t)) / (2r), phi(xi) = xi g(xi) (d'Alembert applied to
 r u); on the periodic domain the 27 nearest images are summed.
 
+Vacuum Maxwell (the serving mix's second equation; not in the paper): with Psi
+the Gaussian spherical wave above and Phi the wave solution with Phi(0) = 0,
+Phi_t(0) = g, i.e. Phi = sigma^2 (g(r - t) - g(r + t)) / (2 r) (so Phi_t = Psi and
+Lap Phi = Psi_t),
+    E = curl(z Psi) = (d_y Psi, -d_x Psi, 0),   B = -grad(d_z Phi) + z Psi_t
+solves dE/dt = curl B, dB/dt = -curl E with div E = div B = 0, and starts from
+E = curl(z g), B = 0.  A plane wave E = e sin(k.x - |k| t), B = (k/|k| x e)
+sin(k.x - |k| t), e.k = 0, is the second closed form.
+
 For a Fourier mode on a uniform periodic grid the discrete scheme has a closed
 form: with the symbols lam (sixth-order Laplacian) and kap (Kreiss-Oliger term)
 the semi-discrete system is d/dt (u^, v^) = [[kap, 1], [lam, kap]] (u^, v^), and
@@ -73,6 +82,116 @@ def gaussian_periodic(x: np.ndarray, centres: np.ndarray, t: float, sigma: float
             u += du
             v += dv
     return np.stack([u, v])
+
+
+# ----------------------------------------------------------------------------- Maxwell
+def _gauss_derivs(xi, sigma, amp, nmax):
+    """g^(n)(xi), n = 0..nmax, for g = amp exp(-xi^2 / (2 sigma^2)):
+    g^(n) = (-1/sigma)^n He_n(xi/sigma) g with the probabilists' Hermite
+    polynomials He_0 = 1, He_1 = x, He_(n+1) = x He_n - n He_(n-1)."""
+    x = xi / sigma
+    g = amp * np.exp(-0.5 * x * x)
+    he = [np.ones_like(x), x]
+    for n in range(1, nmax):
+        he.append(x * he[n] - n * he[n - 1])
+    return [(-1.0 / sigma) ** n * he[n] * g for n in range(nmax + 1)]
+
+
+#: radius below which the radial factors are summed as Taylor series (in sigma)
+_SERIES_R = 0.5
+_SERIES_K = 16
+
+
+def _radial_factors(r, t, sigma, amp):
+    """Radial factors of one image at distance r: Psi_r / r, Psi_t, Phi_r / r and
+    (Phi_rr - Phi_r / r) / r^2, for Psi = N / (2r), N = phi(r+t) + phi(r-t),
+    phi = xi g, and Phi = M / (2r), M = sigma^2 (g(r-t) - g(r+t)).
+
+    With N' etc. the r-derivatives: Psi_r / r = (r N' - N) / (2 r^3) and
+    (Phi_rr - Phi_r/r) / r^2 = (r^2 M'' - 3 r M' + 3 M) / (2 r^5).  Near r = 0 these
+    cancel; there the odd series N = sum_k n_k r^(2k+1) gives
+    sum_(k>=1) k n_k r^(2k-2) and sum_(k>=2) 2k(k-1) n_k r^(2k-4)."""
+    r = np.asarray(r, dtype=np.float64)
+    out = [np.zeros_like(r) for _ in range(4)]
+    far = r >= _SERIES_R * sigma
+    if far.any():
+        rf = r[far]
+        gp = _gauss_derivs(rf + t, sigma, amp, 3)
+        gm = _gauss_derivs(rf - t, sigma, amp, 3)
+        # phi^(n) = xi g^(n) + n g^(n-1)
+        def ph(gd, xi, n):
+            return xi * gd[n] + (n * gd[n - 1] if n > 0 else 0.0)
+        N = ph(gp, rf + t, 0) + ph(gm, rf - t, 0)
+        N1 = ph(gp, rf + t, 1) + ph(gm, rf - t, 1)
+        V = ph(gp, rf + t, 1) - ph(gm, rf - t, 1)          # phi'(r+t) - phi'(r-t)
+        s2 = sigma * sigma
+        M = s2 * (gm[0] - gp[0])
+        M1 = s2 * (gm[1] - gp[1])
+        M2 = s2 * (gm[2] - gp[2])
+        out[0][far] = (rf * N1 - N) / (2.0 * rf ** 3)
+        out[1][far] = V / (2.0 * rf)
+        out[2][far] = (rf * M1 - M) / (2.0 * rf ** 3)
+        out[3][far] = (rf * rf * M2 - 3.0 * rf * M1 + 3.0 * M) / (2.0 * rf ** 5)
+    near = ~far
+    if near.any():
+        from math import factorial
+        rn = r[near]
+        K = _SERIES_K
+        tt = np.full_like(rn, float(t))
+        gd = _gauss_derivs(tt, sigma, amp, 2 * K + 5)
+        s2 = sigma * sigma
+
+        def phd(n):                                      # phi^(n)(t) = t g^(n) + n g^(n-1)
+            return tt * gd[n] + n * gd[n - 1]
+
+        def n_(k):                                       # N = sum_k n_k r^(2k+1)
+            return 2.0 * phd(2 * k + 1) / float(factorial(2 * k + 1))
+
+        def m_(k):                                       # M = sum_k m_k r^(2k+1)
+            return -2.0 * s2 * gd[2 * k + 1] / float(factorial(2 * k + 1))
+
+        def v_(k):                                       # Psi_t = sum_k v_k r^(2k)
+            return phd(2 * k + 2) / float(factorial(2 * k + 1))
+
+        coef = [[(j + 1) * n_(j + 1) for j in range(K + 1)],
+                [v_(j) for j in range(K + 1)],
+                [(j + 1) * m_(j + 1) for j in range(K + 1)],
+                [2.0 * (j + 2) * (j + 1) * m_(j + 2) for j in range(K + 1)]]
+        r2 = rn * rn
+        for i in range(4):
+            acc = np.zeros_like(rn)
+            for j in range(K, -1, -1):                   # Horner in r^2
+                acc = acc * r2 + coef[i][j]
+            out[i][near] = acc
+    return out
+
+
+def maxwell_gaussian(x: np.ndarray, centres: np.ndarray, t: float, sigma: float, amp: float = 1.0):
+    """(E, B) = [6, ...] of the Gaussian-potential Maxwell solution at time t, summed
+    over the pulses and their 27 nearest periodic images.  x: [..., 3]."""
+    out = np.zeros((6,) + x.shape[:-1])
+    for c in np.atleast_2d(centres):
+        for im in IMAGES:
+            d = x - (c + im)
+            r = np.sqrt((d * d).sum(axis=-1))
+            p_psi, psi_t, s_phi, q_phi = _radial_factors(r, t, sigma, amp)
+            dx, dy, dz = d[..., 0], d[..., 1], d[..., 2]
+            out[0] += p_psi * dy
+            out[1] -= p_psi * dx
+            out[3] -= q_phi * dx * dz
+            out[4] -= q_phi * dy * dz
+            out[5] += psi_t - (q_phi * dz * dz + s_phi)
+    return out
+
+
+def maxwell_plane(x: np.ndarray, n, e, t: float):
+    """E = e sin(k.x - |k| t), B = (k/|k| x e) sin(k.x - |k| t), k = pi n, e.k = 0."""
+    k = np.pi * np.asarray(n, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    w = np.linalg.norm(k)
+    bvec = np.cross(k / w, e)
+    s = np.sin((x * k).sum(axis=-1) - w * t)
+    return np.stack([e[i] * s for i in range(3)] + [bvec[i] * s for i in range(3)])
 
 
 def plane_wave(x: np.ndarray, n, t: float):

@@ -1,6 +1,6 @@
 """Finite-difference stencils and the c->f interpolant (test infrastructure only).
 
-The paper uses high-order central differences on padded blocks (Sec. 3.4) but
+The paper uses high-order central differences on padded blocks (Sec. 3.3) but
 prints no stencil.  Readings:
   * second derivative: sixth-order central, weights (1/90, -3/20, 3/2, -49/18,
     3/2, -3/20, 1/90) / h^2 per axis;
@@ -9,7 +9,7 @@ prints no stencil.  Readings:
   * Kreiss-Oliger dissipation (not in the paper): + sigma/(64 h) * (1, -6, 15,
     -20, 15, -6, 1) per axis, i.e. sigma h^5 / 64 * D+^3 D-^3, which is
     non-positive in Fourier space (dissipative) and fits three ghost layers;
-  * coarse->fine interpolation (Sec. 3.4 "coarser to finer interpolation"):
+  * coarse->fine interpolation (Sec. 3.3 "coarser to finer interpolation"):
     tensor degree-4 Lagrange on the coarse leaf's own 5 nodes per axis.
 All weights are exact rationals converted by one correctly rounded division.
 """

@@ -9,15 +9,15 @@ Paper passages:
   * Sec. 3.2.3 (2:1 balance) extended to ghost reach: a leaf of level l is split
     when a leaf of level >= l+2 lies within three grid spacings of it.  With 5^3
     nodes per octant and three ghost layers this keeps every ghost source within
-    one level of the receiver, which the paper's time-gap argument (Sec. 3.7.3)
+    one level of the receiver, which the paper's time-gap argument (Sec. 3.6.3)
     assumes.
-  * Sec. 3.3 + fig. oct_to_blocks (octree to block decomposition): a block is a
+  * Sec. 3.2.5 + fig. oct_to_blocks (octree to block decomposition): a block is a
     maximal uniformly refined sub-tree, split into aligned cubes of at most
     ``cap`` octants per side.
-  * Sec. 3.4 + fig. unzip: padded blocks; coarse->fine interpolation and
+  * Sec. 3.3 + fig. unzip: padded blocks; coarse->fine interpolation and
     fine->coarse injection for the padding.
-  * Sec. 3.7.3 + fig. blk_loop: level-frequency schedule.
-  * Sec. 3.8, eqs. w_nuts, w_uts, invS: speedup model.
+  * Sec. 3.6.3 + fig. blk_loop: level-frequency schedule.
+  * Sec. 3.7, eqs. w_nuts, w_uts, invS: speedup model.
 
 Geometry (integer "node units" at the finest level L of the spec):
   domain [-1, 1]^3, periodic; N_u = 4 * 2^L node units per side, x = -1 + 2 X / N_u.
@@ -318,7 +318,7 @@ class Mesh:
 
 
 def build_blocks(anchors: np.ndarray, levels: np.ndarray, L: int, cap: int) -> np.ndarray:
-    """Octree-to-block decomposition (Sec. 3.3, fig. oct_to_blocks).
+    """Octree-to-block decomposition (Sec. 3.2.5, fig. oct_to_blocks).
 
     For every leaf find its largest ancestor whose sub-tree is uniformly refined
     at the leaf's level; that sub-tree, split into aligned cubes of side
@@ -361,7 +361,7 @@ def build_blocks(anchors: np.ndarray, levels: np.ndarray, L: int, cap: int) -> n
 
 
 def build_mesh(spec: MeshSpec) -> Mesh:
-    """Refinement, balance, blocks (Sec. 3.2.2 -> 3.2.3 -> 3.3)."""
+    """Refinement, balance, blocks (Sec. 3.2.2 -> 3.2.3 -> 3.2.5)."""
     a, l = refine(spec)
     a, l = balance(a, l, spec.l_max)
     blk = build_blocks(a, l, spec.l_max, spec.block_cap)
@@ -388,7 +388,7 @@ def block_octants(mesh: Mesh, b: int) -> np.ndarray:
 
 
 def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
-    """Canonical source of every padded point of block b (Sec. 3.4, fig. unzip).
+    """Canonical source of every padded point of block b (Sec. 3.3, fig. unzip).
 
     Returns int64 [S^3, 5] rows (leaf, kind, 2*px, 2*py, 2*pz), S = 4m+7, points in
     lexicographic order of Q in [-3, 4m+3]^3 with x fastest; (px, py, pz) is the
@@ -460,7 +460,7 @@ def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- schedule
 def substeps(mesh: Mesh) -> int:
-    """2^(Delta L) substeps per coarsest step (Sec. 3.7.3)."""
+    """2^(Delta L) substeps per coarsest step (Sec. 3.6.3)."""
     return 1 << (mesh.lmax - mesh.lmin)
 
 
@@ -475,12 +475,12 @@ def active_blocks(mesh: Mesh, j: int, mode: str = "lts") -> np.ndarray:
 
 
 def dt_level(level) -> float:
-    """dt_l = 0.25 h_l with h_l = 2^(-l-1) (CFL 0.25, Sec. 3.7)."""
+    """dt_l = 0.25 h_l with h_l = 2^(-l-1) (CFL 0.25, Sec. 3.6)."""
     return 2.0 ** (-int(level) - 3)
 
 
 def speedup_model(mesh: Mesh) -> dict:
-    """Sec. 3.8, eqs. w_nuts, w_uts, invS with alpha_l = DG nodes at level lmax - l."""
+    """Sec. 3.7, eqs. w_nuts, w_uts, invS with alpha_l = DG nodes at level lmax - l."""
     Lspan = mesh.lmax - mesh.lmin
     alpha = np.zeros(Lspan + 1, dtype=np.int64)
     for lev in range(mesh.lmin, mesh.lmax + 1):

@@ -1,11 +1,11 @@
 """Runge-Kutta tableaus and LTS stage-conversion weights (test infrastructure only).
 
 Paper passages:
-  * eq. rk_schemes (Sec. 3.5): explicit p-stage RK, stages k_i and weights w_i.
-  * eq. rk_crrection (Sec. 3.7.2): linear relation between the stages K and the
+  * eq. rk_schemes (Sec. 3.4): explicit p-stage RK, stages k_i and weights w_i.
+  * eq. rk_crrection (Sec. 3.6.2): linear relation between the stages K and the
     time derivatives d^j U / dt^j through a lower-triangular matrix C and the
     step-size matrix P_dt = diag(1, dt, ..., dt^{p-1}).
-  * eqs. fc_1 / fc_2 (Sec. 3.7.2): stage corrections between a finer and a
+  * eqs. fc_1 / fc_2 (Sec. 3.6.2): stage corrections between a finer and a
     coarser block, M = (P C) B (P C)^{-1} with B an upper-triangular Taylor shift.
 
 Readings (the printed factor order is dimensionally inconsistent):
@@ -163,7 +163,7 @@ def conversion_weights(tab: Tableau, delta: Fr, rho: Fr) -> List[List[Fr]]:
 
 
 #: The four legal time cases of a ghost relation on a ghost-reach-balanced octree
-#: (Sec. 3.7.3: adjacent blocks differ by at most one level and their time gap is
+#: (Sec. 3.6.3: adjacent blocks differ by at most one level and their time gap is
 #: at most the finer step).  Index -> (delta, rho).
 CASES: Tuple[Tuple[Fr, Fr], ...] = (
     (Fr(0), Fr(1)),        # 0: same level

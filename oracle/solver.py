@@ -1,15 +1,15 @@
 """Plain FP64 LTS / GTS solver on padded blocks (test infrastructure only).
 
 Paper passages:
-  * Alg. 1 (GTS, Sec. 3.6): every block takes every stage with the finest step;
+  * Alg. 1 (GTS, Sec. 3.5): every block takes every stage with the finest step;
     stage values of all blocks are synchronised after each stage.
-  * Alg. 2 (LTS, Sec. 3.7.2) with the level-frequency loop of Sec. 3.7.3 and
+  * Alg. 2 (LTS, Sec. 3.6.2) with the level-frequency loop of Sec. 3.6.3 and
     fig. blk_loop: at substep j the blocks B_j of every level lam with
     j mod 2^(lmax-lam) == 0 take one step of size dt_lam.
-  * eqs. fc_1 / fc_2 (Sec. 3.7.2): stage corrections between levels, applied to
-    the values copied into the padding of neighbouring blocks (Sec. 3.7.3, last
+  * eqs. fc_1 / fc_2 (Sec. 3.6.2): stage corrections between levels, applied to
+    the values copied into the padding of neighbouring blocks (Sec. 3.6.3, last
     sentences).
-  * Sec. 3.4, fig. unzip / fig. overview: unzip (padding), block RHS on the
+  * Sec. 3.3, fig. unzip / fig. overview: unzip (padding), block RHS on the
     uniform block grid, zip (back to octant-local DG nodes).
 
 Readings:
@@ -98,7 +98,7 @@ class State:
 
     # ------------------------------------------------------------------ cases
     def case_of(self, recv: int, src: int) -> int:
-        """Time case of a ghost relation from the two blocks' records (Sec. 3.7.2).
+        """Time case of a ghost relation from the two blocks' records (Sec. 3.6.2).
 
         delta = (receiver start - source start) / dt_r, rho = dt_src / dt_r; the
         pair must be one of the four cases a balanced mesh produces."""
@@ -133,7 +133,7 @@ class State:
         return pl
 
     def unzip(self, b: int, s: int) -> np.ndarray:
-        """Padded stage state Y_s of block b: [F][S][S][S] (Sec. 3.4 and eqs. fc_1/fc_2).
+        """Padded stage state Y_s of block b: [F][S][S][S] (Sec. 3.3 and eqs. fc_1/fc_2).
 
         Every padded point takes, from its source leaf's step record, the value
         Y = U0 + dt_r * sum_i w^_{s,i}(case) K_i; a point that is not a node of a
@@ -182,7 +182,7 @@ class State:
 
     # ------------------------------------------------------------------ zip
     def zip_into(self, b: int, grid: np.ndarray, dest: np.ndarray):
-        """Block grid [F][4m+1]^3 -> every DG node of the block's octants (Sec. 3.4)."""
+        """Block grid [F][4m+1]^3 -> every DG node of the block's octants (Sec. 3.3)."""
         m = int(self.mesh.blocks[b, 1])
         octs = self.plan(b)["octs"]
         for ok in range(m):

@@ -1,8 +1,8 @@
 // Exact-rational RK coefficient tables for LTS stage conversion.
 //
-// eq. rk_schemes (Sec. 3.5): p-stage explicit RK, stage argument
+// eq. rk_schemes (Sec. 3.4): p-stage explicit RK, stage argument
 // u + dt sum_q a_sq k_q, update u + dt sum_i b_i k_i.
-// eq. rk_crrection (Sec. 3.7.2), read as K = C P_dt D: for u' = L u,
+// eq. rk_crrection (Sec. 3.6.2), read as K = C P_dt D: for u' = L u,
 // k_i = sum_j C_ij dt^(j-1) L^j u with C_i1 = 1, C_i,j+1 = sum_m a_im C_mj.
 // eqs. fc_1 / fc_2: stages of a record (step dt_n) seen from a receiver step dt_r
 // starting Delta later are k~ = C P_r B_Delta P_n^-1 C^-1 K, B_Delta the Taylor

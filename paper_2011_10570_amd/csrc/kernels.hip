@@ -1,6 +1,6 @@
 // HIP kernels of the LTS hot path for gfx950 (MI355X).
 //
-// One RK stage (Sec. 3.4 + Alg. 1/2): unzip (ghost-padded block state with
+// One RK stage (Sec. 3.3 + Alg. 1/2): unzip (ghost-padded block state with
 // f->c injection, degree-4 c->f interpolation and the LTS stage conversion of
 // eqs. fc_1/fc_2), block RHS (sixth-order FD + Kreiss-Oliger), zip back to the
 // octant-local nodes and, after the last stage, the RK update (eq. rk_schemes).
@@ -97,7 +97,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, int mode, int j, i
     c.dt = ldexp(1.0, -lmax - 3);
   } else {
     // a finer neighbour steps twice per receiver step: its step index is 2 s;
-    // a coarser one once per two: its index is floor(s / 2) (Sec. 3.7.3).
+    // a coarser one once per two: its index is floor(s / 2) (Sec. 3.6.3).
     c.par_fine = 0;
     c.par_coarse = (s >> 1) & 1;
     c.case_fine = 1;                                   // (delta, rho) = (0, 1/2)
@@ -465,7 +465,7 @@ __device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32>& L, int b, co
   if (threadIdx.x < F) L.ref[b][threadIdx.x] = KF32 ? tb.refv : 0.0;
 }
 
-// One tile of the fused stage (Sec. 3.4, eqs. fc_1/fc_2, eq. rk_schemes).  Its
+// One tile of the fused stage (Sec. 3.3, eqs. fc_1/fc_2, eq. rk_schemes).  Its
 // slot records and per-axis location tables (slot position and node offset of
 // every padded coordinate, from the location rule) are in LDS buffer b.
 //   (1) every used padded point takes its stage value: a same-level leaf (the

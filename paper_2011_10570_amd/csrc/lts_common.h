@@ -1,6 +1,6 @@
 // Host/device helpers shared by the mesh builder's exports and the HIP kernels.
 //
-// Point location inside a tile's padded region (Sec. 3.4, fig. unzip).  A tile is
+// Point location inside a tile's padded region (Sec. 3.3, fig. unzip).  A tile is
 // a cube of tt^3 octants at offset o (octants) inside a block of m^3 octants at
 // level l.  Padded tile point q in [0, 4tt+7)^3 has block-relative node
 // coordinate Q = 4 o + q - 3 in [-3, 4m+3].  Per axis the receiver-level cell is

@@ -2,7 +2,7 @@
 // decomposition, tiles with their ghost-source slot tables, exports.
 //
 // Sec. 3.2.2 (refinement), Sec. 3.2.3 (2:1 balance, here extended to the reach
-// of three ghost layers), Sec. 3.2.4 (o2o neighbour search), Sec. 3.3 +
+// of three ghost layers), Sec. 3.2.4 (o2o neighbour search), Sec. 3.2.5 +
 // fig. oct_to_blocks (blocks = uniformly refined sub-trees).
 #include <algorithm>
 #include <cstring>
@@ -420,7 +420,7 @@ void finish_levels(TileSet& ts) {
     ts.n_ge[l] = c;
   }
   // Weighted partition of every launch prefix over the 8 XCDs (the paper's
-  // weighted SFC partitioning, Sec. 3.7.4, applied to the chip's dies): cost of a
+  // weighted SFC partitioning, Sec. 3.6.4, applied to the chip's dies): cost of a
   // tile = direct points + coarser slots + coarser leaves to prolongate.
   std::vector<double> pre(T + 1, 0.0);
   for (int64_t i = 0; i < T; ++i) {

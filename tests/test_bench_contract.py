@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -52,3 +53,28 @@ def test_stored_traffic_reader(tmp_path):
 def test_committed_counter_summary_parses():
     txt = open(os.path.join(ROOT, "profiles", "fused_stage_wave_c2_counters.md")).read()
     assert "traffic_bytes_per_stage:" in txt and "sources_sha256:" in txt
+
+
+def test_analytic_fields_match_oracle():
+    """bench.py's torch evaluation of the Gaussian spherical wave (the accuracy
+    numbers of every bench line) equals the oracle's closed form on every DG node,
+    u and v, including the node at a pulse centre (the r -> 0 limits)."""
+    import torch
+    from oracle import analytic as an
+    from oracle import octree as ot
+    from workloads import centre_physical, mesh_spec, node_units, physical
+    m = ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec("small")))
+    L = m.L
+    pulses = [[16, 12, 20], [5, 30, 11]]
+    leaves = np.concatenate([m.anchors, m.levels[:, None]], axis=1)
+    X = physical(node_units(m.anchors, m.levels, L), L)
+    c = np.stack([centre_physical(p, L) for p in pulses])
+    r0 = np.sqrt(((X - c[0]) ** 2).sum(-1)).min()
+    assert r0 == 0.0          # a node sits on the first centre
+    for T in (0.0, 0.0625, 0.3):
+        got = bench.analytic_fields(leaves, L, pulses, 0.1, T, "cpu").numpy()
+        want = an.gaussian_periodic(X, c, T, 0.1).reshape(2, m.n_oct, 125)
+        for f in range(2):
+            assert np.abs(got[f] - want[f]).max() <= 1e-12 * np.abs(want[f]).max(), (T, f)
+    e = bench.analytic_error(torch.as_tensor(want), leaves, L, pulses, 0.1, 0.3)
+    assert e["l2_u"] < 1e-13 * e["l2_exact_u"] and e["l2_v"] < 1e-13 * e["l2_exact_v"]

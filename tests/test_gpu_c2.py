@@ -82,7 +82,8 @@ def test_c2_coarse_step_properties(c2):
     lv = gm.leaves()
     for name in out:
         e = bench.analytic_error(out[name], lv, info["L"], cfg["pulses"], cfg["sigma"], T)
-        assert e["l2"] < 1e-6 and e["linf"] < 2e-5, (name, e)
+        assert e["l2_u"] < 1e-6 and e["linf_u"] < 2e-5, (name, e)
+        assert e["l2_v"] < 1e-4 and e["linf_v"] < 1e-3, (name, e)
     # LTS and GTS differ by the time discretisation error only: per field, far
     # below the field's scale
     for f in range(2):

@@ -50,6 +50,20 @@ def test_mesh_bit_exact(name):
         assert np.array_equal(got, ot.active_blocks(om, j))
 
 
+def test_ghost_owner_fixture_library():
+    """The library's unzip map gives the owners of tests/golden/ghost_owner.txt."""
+    from test_oracle_mesh import map_row, owner_fixture_mesh, owner_fixture_rows
+    a, l, L = owner_fixture_mesh()
+    gm = P.build_mesh(leaves=np.concatenate([a, l[:, None]], axis=1), L=L)
+    blocks = gm.blocks()
+    S = 4 * blocks[:, 1] + 7
+    off = np.concatenate([[0], np.cumsum(S ** 3)])
+    mp = gm.unzip_map()
+    for r in owner_fixture_rows():
+        b, qx, qy, qz = r[:4]
+        assert map_row(mp[off[b]:off[b + 1]], int(blocks[b, 1]), qx, qy, qz) == r[4:9], r
+
+
 @pytest.mark.parametrize("name", ["small", "wave_c1"])
 def test_unzip_map_bit_exact(name):
     om = _oracle_mesh(name)

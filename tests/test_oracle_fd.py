@@ -1,5 +1,5 @@
 """Pins of the oracle's stencils and interpolant against exactness properties fixed
-by the mathematics (Sec. 3.4: high-order FD on padded blocks, c->f interpolation)."""
+by the mathematics (Sec. 3.3: high-order FD on padded blocks, c->f interpolation)."""
 from fractions import Fraction as Fr
 
 import numpy as np

@@ -46,6 +46,44 @@ def test_oct_to_blocks_fixture():
     assert got == want
 
 
+def owner_fixture_mesh():
+    """The mesh of tests/golden/ghost_owner.txt: L = 2, level-1 octants with the
+    one at the origin refined once (15 leaves, 8 blocks)."""
+    L = 2
+    a, l = ot.uniform_leaves(1, L)
+    al, ll = [], []
+    for an_, lv in zip(a, l):
+        if (an_ == 0).all():
+            al.append(ot._children(an_[None, :], 1, L)); ll.append(np.full(8, 2))
+        else:
+            al.append(an_[None, :]); ll.append(np.array([1]))
+    return np.concatenate(al), np.concatenate(ll), L
+
+
+def owner_fixture_rows():
+    return [[int(v) for v in r[:9]] for r in
+            ([x for x in line.split("#")[0].split()] for line in open(os.path.join(GOLD, "ghost_owner.txt")))
+            if len(r) >= 9]
+
+
+def map_row(mp, m, qx, qy, qz):
+    S = 4 * m + 7
+    return mp[((qz + 3) * S + (qy + 3)) * S + (qx + 3)].tolist()
+
+
+def test_ghost_owner_fixture():
+    """The unzip map's owner of face, edge and corner points equals the hand
+    derivation of tests/golden/ghost_owner.txt (Sec. 3.3, fig. unzip)."""
+    a, l, L = owner_fixture_mesh()
+    m = ot.mesh_from_leaves(a, l, L, cap=4, do_balance=True)
+    assert m.n_oct == 15 and len(m.blocks) == 8
+    rows = owner_fixture_rows()
+    assert len(rows) == 13
+    for r in rows:
+        b, qx, qy, qz = r[:4]
+        assert map_row(ot.unzip_map(m, b), int(m.blocks[b, 1]), qx, qy, qz) == r[4:9], r
+
+
 @pytest.fixture(scope="module")
 def small_mesh():
     return ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec("small")))
