@@ -45,6 +45,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("dev_common.h", "dev_fused.h", "k_fused.hip", "k_fused_batch.hip", "k_ghost.hip", "k_stream.hip",
+                  "k_phase.hip", "api.cpp")
 WORKLOAD = "wave_c2"
 
 
@@ -81,10 +83,10 @@ def copy_probe_gbs(P, torch, mib: int = 2048, reps: int = 5) -> float:
 
 
 def source_digest() -> str:
-    """sha256 over the kernel and launch sources (kernels.hip, then api.cpp)."""
+    """sha256 over the kernel and launch sources (device headers, kernels, api.cpp)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "api.cpp"):
+    for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2011_10570_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 

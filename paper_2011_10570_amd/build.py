@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libltsmi.so")
 ARCH = os.environ.get("LTS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["mesh.cpp", "coeffs.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["mesh.cpp", "coeffs.cpp", "api.cpp", "k_fused.hip", "k_fused_batch.hip", "k_ghost.hip", "k_stream.hip",
+           "k_phase.hip"]
 
 # -ffp-contract=on: a multiply-add is fused only inside one expression, so the
 # rounding of a stencil or combine does not depend on how the compiler lays out
@@ -39,16 +40,22 @@ def _hipcc() -> str:
 def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     with tempfile.TemporaryDirectory(prefix="ltsbuild_") as tmp:
-        objs = []
+        objs, procs = [], []
+        # the sources compile independently: all at once, then one link
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
             cmd = [hipcc, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            if r.returncode != 0:
-                raise RuntimeError(f"compile of {src} failed:\n{r.stdout}\n{r.stderr}")
+            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
             objs.append(obj)
+        errors = []
+        for src, pr in procs:
+            out, err = pr.communicate()
+            if pr.returncode != 0:
+                errors.append(f"compile of {src} failed:\n{out}\n{err}")
+        if errors:
+            raise RuntimeError("\n".join(errors))
         out_tmp = LIB + ".tmp"
         cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)

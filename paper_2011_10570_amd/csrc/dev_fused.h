@@ -1,0 +1,418 @@
+// The fused stage of LDS-resident tiles: layout, one tile, a workgroup's walk
+// over tiles and the dispatch over template arguments.
+#pragma once
+#include "dev_common.h"
+
+namespace lts {
+
+// ------------------------------------------------------------------ fused stage
+// The block RHS reads only along the axes (centred first and second differences
+// and Kreiss-Oliger terms, no mixed derivatives), so of the (4tt+7)^3 padded
+// points of a tile it uses those with at most one coordinate in the 3-point halo.
+// They are kept plane by plane: core plane z = 3 + gz (gz < G) as a P x P square
+// at gz P^2 (its four 3 x 3 corners unused), then the six halo planes (z = h for
+// h < 3, z = G + h for h >= 3) as G x G squares of the core x and y.
+template <int TT>
+struct Cross {
+  static constexpr int P = 4 * TT + 7;     // padded points per axis
+  static constexpr int G = 4 * TT + 1;     // grid points per axis
+  static constexpr int PP = P * P, GG = G * G;
+  static constexpr int HB = G * PP;        // element of the first halo plane
+  static constexpr int LS = HB + 6 * GG;   // elements per field
+  static constexpr int NA = P * GG;        // core planes, y in the core: whole x rows
+  static constexpr int NB = 6 * GG;        // core planes, y in the halo: x in the core
+  static constexpr int NC = NA + NB + 6 * GG;
+  // used point i (x rows, then y-halo rows, then halo planes) -> padded
+  // coordinates and element
+  __device__ static __forceinline__ void point(int i, int& qx, int& qy, int& qz, int& li) {
+    if (i < NA) {
+      qx = i % P;
+      const int r = i / P;
+      qy = 3 + r % G;
+      qz = 3 + r / G;
+    } else if (i < NA + NB) {
+      const int j = i - NA, r = j / G, h = r % 6;
+      qx = 3 + j % G;
+      qy = h < 3 ? h : G + h;
+      qz = 3 + r / 6;
+    } else {
+      const int j = i - NA - NB, r = j / G, h = r / G;
+      qx = 3 + j % G;
+      qy = 3 + r % G;
+      qz = h < 3 ? h : G + h;
+    }
+    li = (qz >= 3 && qz < 3 + G) ? ((qz - 3) * P + qy) * P + qx : HB + ((qz < 3 ? qz : qz - G) * G + qy - 3) * G + qx - 3;
+  }
+};
+
+// Accessor of the plane-wise padded tile at grid point (gx, gy, gz): c is its
+// element in the core planes, hb the element of (gx, gy) in the first halo plane.
+template <typename T, int TT>
+struct CrossAt {
+  const T* Y;
+  int c, hb, gz;
+  __device__ __forceinline__ T operator()(int f, int ax, int k) const {
+    using X = Cross<TT>;
+    int e;
+    if (ax == 0) {
+      e = c + k;
+    } else if (ax == 1) {
+      e = c + k * X::P;
+    } else {
+      const int z = gz + k;
+      e = (z >= 0 && z < X::G) ? c + k * X::PP : hb + (z < 0 ? z + 3 : z - X::G + 3) * X::GG;
+    }
+    return Y[f * X::LS + e];
+  }
+};
+
+// LDS of one workgroup of the fused stage kernels.
+template <int TT, int F, bool KF32>
+struct FusedLds {
+  static constexpr int W = TT + 2;
+  static constexpr int NS = W * W * W;
+  static constexpr int G3 = (4 * TT + 1) * (4 * TT + 1) * (4 * TT + 1);
+  using LT = typename std::conditional<KF32, float, double>::type;
+  double R[F * G3];               // stencil results
+  double wsh[16];                 // stage weights of the 4 time cases
+  LT Y[F * Cross<TT>::LS];        // stage values of the used padded points
+  // per-tile tables, two buffers: the next tile's are filled while this one runs
+  double ref[2][F];               // FP32 stencils: reference value of each field
+  int32_t sl[2][2 * NS];          // slot records
+  uint8_t axl[2][3][4 * TT + 7];  // per axis: slot position | node offset << 3
+};
+
+// A tile and what it needs of its simulation and mesh.
+struct TileRef {
+  SimView v;
+  int n4;                   // coarse-step index mod 4
+  const int32_t* tile;      // its 8-int record
+  const int32_t* slots;     // slot table of its mesh
+  const double* cs;         // ghost table of its mesh
+};
+
+// The tile record is uniform: keep it in scalar registers.
+__device__ __forceinline__ void load_trec(const int32_t* tile, int32_t t[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t[k] = __builtin_amdgcn_readfirstlane(tile[k]);
+}
+
+// One thread's share of a tile's LDS tables: slot record element, location-table
+// element (from the location rule) and, for FP32 stencils, a field's reference
+// value.  Loads are issued here and consumed by tables_store, so that their
+// latency can be covered by other work.
+struct TileTables {
+  int32_t slv;
+  int32_t axv;
+  double refv;
+};
+
+template <int TT, int F, bool KF32, int NT>
+__device__ __forceinline__ TileTables tables_issue(const StageParams& sp, const TileRef& r, const int32_t* t) {
+  constexpr int P = 4 * TT + 7;
+  constexpr int NS2 = 2 * (TT + 2) * (TT + 2) * (TT + 2);
+  static_assert(NT >= NS2 && NT >= 3 * P, "one table element per thread");
+  TileTables tb{0, 0, 0.0};
+  if (threadIdx.x < NS2) tb.slv = r.slots[2 * (int64_t)t[TI_SLOT] + threadIdx.x];
+  if (threadIdx.x < 3 * P) {
+    const int d = threadIdx.x / P, q = threadIdx.x - P * d;
+    const int off = t[TI_OFF];
+    const int o = (off >> (8 * d)) & 255;
+    const int Q = 4 * o + q - 3;
+    const int cell = cell_of(Q, t[TI_M]);
+    tb.axv = (cell - o + 1) | ((Q - 4 * cell) << 3);
+  }
+  if (KF32 && threadIdx.x < F) {
+    // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
+    const TileCtx c = tile_ctx(t, sp.mode, r.v.j, r.v.lmin, r.v.lmax, r.n4);
+    const int64_t fsz = r.v.N * 125;
+    tb.refv = r.v.U[((int64_t)c.par_same * F + threadIdx.x) * fsz + (int64_t)t[TI_FIRST] * 125];
+  }
+  return tb;
+}
+
+template <int TT, int F, bool KF32>
+__device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32>& L, int b, const TileTables& tb) {
+  constexpr int P = 4 * TT + 7;
+  constexpr int NS2 = 2 * (TT + 2) * (TT + 2) * (TT + 2);
+  if (threadIdx.x < NS2) L.sl[b][threadIdx.x] = tb.slv;
+  if (threadIdx.x < 3 * P) L.axl[b][threadIdx.x / P][threadIdx.x % P] = (uint8_t)tb.axv;
+  if (threadIdx.x < F) L.ref[b][threadIdx.x] = KF32 ? tb.refv : 0.0;
+}
+
+// One tile of the fused stage (Sec. 3.3, eqs. fc_1/fc_2, eq. rk_schemes).  Its
+// slot records and per-axis location tables (slot position and node offset of
+// every padded coordinate, from the location rule) are in LDS buffer b.
+//   (1) every used padded point takes its stage value: a same-level leaf (the
+//       tile's own octants included) or 8 finer leaves give Y = U0 + dt sum w_i
+//       K_i, read directly (uniform base pointers, 32-bit offsets, UB points per
+//       thread loaded before use); a coarser leaf gives its prolongated value
+//       from the ghost table;
+//   (2) the stencils run once per tile grid point; K_s (and the RK update at the
+//       last stage) are written to every DG node of the tile's contiguous octants.
+// With a next tile, its record is loaded at the start and its tables during the
+// stencils, into buffer b ^ 1.  Two barriers per tile: after the gather (the
+// previous tile's zip has read the stencil results) and after the stencils.
+// sp holds the stage (weights, masks).
+template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const StageParams& sp, const TileRef& cur,
+                                           const int32_t* t, int b, const TileRef& nxt, bool more,
+                                           int32_t (&ntrec)[8]) {
+  using X = Cross<TT>;
+  constexpr int P = X::P;
+  constexpr int LS = X::LS;
+  constexpr int W = TT + 2;
+  constexpr int UB = 2;                      // points per thread loaded together
+  using LT = typename std::conditional<KF32, float, double>::type;
+  using KT = typename std::conditional<KF32, float, double>::type;
+  const SimView& v = cur.v;
+  const double* __restrict__ cs = cur.cs;
+  auto& Y = L.Y;
+  const int32_t* sl = L.sl[b];
+  const auto& axl = L.axl[b];
+  auto& wsh = L.wsh;
+  const double* ref = L.ref[b];
+  auto& R = L.R;
+  if (more) load_trec(nxt.tile, ntrec);
+  const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
+  const bool last = sp.stage == sp.p - 1;
+  const KT* __restrict__ Kr = (const KT*)v.K;
+  KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
+  // KS: stages read by same-level sources (the tableau row's non-zero pattern),
+  // a compile-time mask so the hot gather has no branches around its loads
+  const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, cur.n4);
+  const int first = t[TI_FIRST];
+  const double* __restrict__ Us = v.U + (int64_t)c.par_same * F * fsz;
+  const double* __restrict__ Uf = v.U + (int64_t)c.par_fine * F * fsz;
+  double* __restrict__ Uw1 = v.Uw + (int64_t)(c.par_same ^ 1) * F * fsz;
+  const int kmf = stage_mask(sp, c.case_fine);
+  const double* wf = wsh + 4 * c.case_fine;
+
+  // (1) stage values of the used padded points
+  for (int p0 = threadIdx.x; p0 < X::NC; p0 += UB * NT) {
+    int li[UB], kind[UB], leaf[UB], kbv[UB], nuv[UB][3];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int pi = p0 + u * NT;
+      kind[u] = -1;
+      li[u] = 0;
+      leaf[u] = 0;
+      kbv[u] = 0;
+      nuv[u][0] = nuv[u][1] = nuv[u][2] = 0;
+      if (pi >= X::NC) continue;
+      int qx, qy, qz;
+      X::point(pi, qx, qy, qz, li[u]);
+      const int ax = axl[0][qx], ay = axl[1][qy], az = axl[2][qz];
+      const int si = (ax & 7) + W * ((ay & 7) + W * (az & 7));
+      nuv[u][0] = ax >> 3;
+      nuv[u][1] = ay >> 3;
+      nuv[u][2] = az >> 3;
+      kbv[u] = sl[2 * si + 1];
+      kind[u] = kbv[u] & 15;
+      leaf[u] = sl[2 * si];
+    }
+    // one straight-line batch of loads for every lane: a same-level point reads
+    // U0 and the K's of its node, a coarser one its ghost-table value (and,
+    // like every other lane, K's at a valid dummy element); loads under
+    // per-kind branches would wait for each other's registers
+    double uu[UB][F], kk[UB][F][4];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const bool same = kind[u] == SRC_SAME, coarse = kind[u] == SRC_COARSE;
+      const uint32_t off = same ? (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]) : 0u;
+      // ghost-table entry (in the slot's first int), octant beta of the leaf
+      const int beta = (kbv[u] >> 4) & 7;
+      const int x2 = 4 * (beta & 1) + nuv[u][0], y2 = 4 * ((beta >> 1) & 1) + nuv[u][1],
+                z2 = 4 * ((beta >> 2) & 1) + nuv[u][2];
+      const double* pa = coarse ? cs + ((int64_t)leaf[u] * F * 729 + (z2 * 9 + y2) * 9 + x2) : Us + off;
+      const int fst = coarse ? 729 : fsz;
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        uu[u][f] = pa[(int64_t)f * fst];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if ((KS >> i) & 1) kk[u][f][i] = (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      if (kind[u] == SRC_FINE) {
+        const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
+        const uint32_t off = (uint32_t)((leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
+                                        10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz));
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if ((kmf >> i) & 1) acc = fma(wf[i], (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off), acc);
+          Y[f * LS + li[u]] = (LT)(ld32(Uf + (uint32_t)(f * fsz), off) + c.dt * acc - ref[f]);
+        }
+      } else if (kind[u] == SRC_SAME) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if ((KS >> i) & 1) acc = fma(wsh[i], kk[u][f][i], acc);
+          Y[f * LS + li[u]] = (LT)(uu[u][f] + c.dt * acc - ref[f]);
+        }
+      } else if (kind[u] == SRC_COARSE) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) Y[f * LS + li[u]] = (LT)(uu[u][f] - ref[f]);
+      }
+    }
+  }
+  TileTables tb{0, 0, 0.0};
+  if (more) tb = tables_issue<TT, F, KF32, NT>(sp, nxt, ntrec);
+  __syncthreads();
+  // the last stage's RK operands are loaded in the zip: holding them across the
+  // stencils would cost the registers that 3 resident side-2 workgroups leave
+  constexpr int NN = TT * TT * TT * 125;
+  constexpr int KZ = (NN + NT - 1) / NT;
+  // (2a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
+  constexpr int G = X::G;
+  constexpr int G3 = G * G * G;
+  for (int gi = threadIdx.x; gi < G3; gi += NT) {
+    const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
+    const int ce = (gz * P + gy + 3) * P + gx + 3;
+    double k[F];
+    // one axis at a time: fewer live registers (same operations, same order)
+    rhs_at<LT, EQ, F, true>(CrossAt<LT, TT>{Y, ce, X::HB + gy * G + gx, gz}, (LT)c.h, (LT)v.sigma, ref, k);
+#pragma unroll
+    for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
+  }
+  if (more) tables_store(L, b ^ 1, tb);
+  __syncthreads();
+  // (2b) zip: every DG node of the tile's (contiguous) octants takes its grid
+  // value; node e of the tile is element first*125 + e of every field array;
+  // the last stage also forms the RK update
+  double bs = sp.b[0];   // b_s without a dynamic index into the kernel arguments
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (i == sp.stage) bs = sp.b[i];
+#pragma unroll
+  for (int u = 0; u < KZ; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (e >= NN) continue;
+    const uint32_t off = (uint32_t)(first * 125 + e);
+    double zu[F], zk[F][3];
+    if (last) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        zu[f] = ld32(Us + (uint32_t)(f * fsz), off);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          zk[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
+      }
+    }
+    const int o = e / 125, node = e - 125 * (e / 125);
+    const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
+    const int gi = ((4 * ((o >> 2) & 1) + cc) * G + (4 * ((o >> 1) & 1) + b)) * G + (4 * (o & 1) + a);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double kv = R[f * G3 + gi];
+      if constexpr (KF32) {
+        const float kf = (float)kv;
+        st32(Kw + (uint32_t)(f * fsz), off, kf);
+        kv = (double)kf;
+      } else {
+        st32(Kw + (uint32_t)(f * fsz), off, kv);
+      }
+      if (last) {
+        // compute_step_partial: U_new = U0 + dt (b_0 K_0 + ... + b_s K_s),
+        // s = p - 1, accumulated in stage order, into the other buffer
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          if (i < sp.stage) acc = fma(sp.b[i], zk[f][i], acc);
+        acc = fma(bs, kv, acc);
+        st32(Uw1 + (uint32_t)(f * fsz), off, zu[f] + c.dt * acc);
+      }
+    }
+  }
+}
+
+template <int TT, int F, bool KF32>
+__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const StageParams& sp) {
+  if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
+}
+
+// Waves per SIMD that the LDS of one workgroup allows: the register budget the
+// compiler is asked to keep so that registers do not cost occupancy.  Capped
+// where a tighter budget spills: 6 (80 registers) for FP64 side-2 tiles, 8 (64)
+// with FP32 stencils, 5 for side-1 tiles; left free for 6 fields.
+template <int TT, int F, bool KF32, int NT>
+constexpr int fused_waves_per_eu() {
+  const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32>);
+  const int w = wg * (NT / 64) / 4;
+  const int cap = TT == 1 ? 5 : (KF32 ? 8 : 6);
+  return (F > 2 || w < 1) ? 1 : (w > cap ? cap : w);
+}
+
+// A workgroup's walk over tiles lo, lo + step, ... < hi; ref_of(i) gives tile i.
+// The first tile's tables are loaded here, every later one's by the tile before.
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, typename RefOf>
+__device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32>& L, const StageParams& sp, int lo, int step, int hi,
+                                           const RefOf& ref_of) {
+  if (lo >= hi) return;
+  TileRef cur = ref_of(lo);
+  int32_t trec[8];
+  load_trec(cur.tile, trec);
+  tables_store(L, 0, tables_issue<TT, F, KF32, NT>(sp, cur, trec));
+  __syncthreads();
+  int b = 0;
+  for (int ti = lo;; ti += step) {
+    const bool more = ti + step < hi;
+    TileRef nxt = more ? ref_of(ti + step) : cur;
+    int32_t ntrec[8];
+    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp, cur, trec, b, nxt, more, ntrec);
+    if (!more) break;
+    cur = nxt;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) trec[k] = ntrec[k];
+    b ^= 1;
+  }
+}
+
+
+// The same-level stage mask and the workgroup size are template arguments: the
+// masks that occur for the built tableaus are RK4: none, {0}, {1}, {2} and
+// SSP-RK3: none, {0}, {0,1}.  A::go<...> launches the kernel of one combination.
+template <int TT, int F, int EQ, bool KF32, int NT, typename A>
+hipError_t dispatch_ks(const StageParams& sp, const A& a, int max_wg, hipStream_t s) {
+  switch (sp.kmask[0]) {
+    case 0: return A::template go<TT, F, EQ, KF32, NT, 0>(sp, a, max_wg, s);
+    case 1: return A::template go<TT, F, EQ, KF32, NT, 1>(sp, a, max_wg, s);
+    case 2: return A::template go<TT, F, EQ, KF32, NT, 2>(sp, a, max_wg, s);
+    case 3: return A::template go<TT, F, EQ, KF32, NT, 3>(sp, a, max_wg, s);
+    case 4: return A::template go<TT, F, EQ, KF32, NT, 4>(sp, a, max_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int TT, int F, int EQ, bool KF32, typename A>
+hipError_t dispatch_nt(const StageParams& sp, const A& a, const LaunchShape& ls, hipStream_t s) {
+  switch (ls.threads) {
+    case 256: return dispatch_ks<TT, F, EQ, KF32, 256>(sp, a, ls.max_wg, s);
+    case 512: return dispatch_ks<TT, F, EQ, KF32, 512>(sp, a, ls.max_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename A>
+hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& sp, const A& a, const LaunchShape& ls,
+                          hipStream_t s) {
+  if (eq == LTS_EQ_WAVE) {
+    if (tt == 1) return kf32 ? dispatch_nt<1, 2, LTS_EQ_WAVE, true>(sp, a, ls, s)
+                             : dispatch_nt<1, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);
+    if (tt == 2) return kf32 ? dispatch_nt<2, 2, LTS_EQ_WAVE, true>(sp, a, ls, s)
+                             : dispatch_nt<2, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);
+    return hipErrorInvalidValue;
+  }
+  if (tt != 1) return hipErrorInvalidValue;  // 6 FP64 fields of a side-2 tile exceed LDS
+  return kf32 ? dispatch_nt<1, 6, LTS_EQ_MAXWELL, true>(sp, a, ls, s)
+              : dispatch_nt<1, 6, LTS_EQ_MAXWELL, false>(sp, a, ls, s);
+}
+
+}  // namespace lts

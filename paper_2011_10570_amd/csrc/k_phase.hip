@@ -1,0 +1,312 @@
+// Phase-by-phase kernels (unzip, rhs, zip, RK update as separate launches over
+// whole blocks through HBM), state gather, counters, norms and the copy probe.
+#include "dev_common.h"
+
+namespace lts {
+
+// ------------------------------------------------------------------ standalone kernels
+template <bool KF32, int F>
+__global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __restrict__ tiles,
+                                               const int32_t* __restrict__ slots, const int32_t* __restrict__ list,
+                                               const int64_t* __restrict__ off, int64_t total, double* out) {
+  __shared__ double wsh[16];
+  if (threadIdx.x < 16) wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
+  __syncthreads();
+  const int bi = blockIdx.y;
+  const int b = list[bi];
+  const int32_t* t = tiles + 8 * (int64_t)b;
+  const int n4 = (int)(*sp.step & 3);
+  const TileCtx c = tile_ctx(t, sp, n4);
+  const int P = 4 * c.m + 7;
+  const int P3 = P * P * P;
+  const int32_t* sl = slots + 2 * (int64_t)t[TI_SLOT];
+  for (int pi = blockIdx.x * blockDim.x + threadIdx.x; pi < P3; pi += gridDim.x * blockDim.x) {
+    const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
+    double v[F];
+    point_values<KF32, F>(sp, c, sl, wsh, qx, qy, qz, v);
+    #pragma unroll
+    for (int f = 0; f < F; ++f) out[f * total + off[bi] + pi] = v[f];
+  }
+}
+
+template <int EQ, int F, bool F32>
+__global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
+                                             const int64_t* __restrict__ poff, int64_t ptotal,
+                                             const int64_t* __restrict__ goff, int64_t gtotal,
+                                             const double* __restrict__ padded, void* kout, double sigma) {
+  const int bi = blockIdx.y;
+  const int32_t* t = tiles + 8 * (int64_t)list[bi];
+  const int m = t[TI_M];
+  const int P = 4 * m + 7, G = 4 * m + 1;
+  const int G3 = G * G * G;
+  const double h = ldexp(1.0, -t[TI_LEVEL] - 1);
+  for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G3; gi += gridDim.x * blockDim.x) {
+    const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
+    const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
+    double k[F];
+    if constexpr (F32) {
+      // float stencils on Y - ref, ref = the block's first grid value
+      double ref[F];
+      const int c0 = (3 * P + 3) * P + 3;
+      #pragma unroll
+      for (int f = 0; f < F; ++f) ref[f] = padded[f * ptotal + poff[bi] + c0];
+      const int st[3] = {1, P, P * P};
+      if constexpr (EQ == LTS_EQ_WAVE) {
+        const double* u = padded + poff[bi];
+        const double* v = padded + ptotal + poff[bi];
+        float lap = 0.f, ku = 0.f, kv = 0.f;
+        for (int ax = 0; ax < 3; ++ax) {
+          const int s = st[ax];
+          float uu[7], vv[7];
+          for (int q = 0; q < 7; ++q) {
+            uu[q] = (float)(u[ci + (q - 3) * s] - ref[0]);
+            vv[q] = (float)(v[ci + (q - 3) * s] - ref[1]);
+          }
+          lap += float(D2C3) * (uu[0] + uu[6]) + float(D2C2) * (uu[1] + uu[5]) + float(D2C1) * (uu[2] + uu[4]) +
+                 float(D2C0) * uu[3];
+          ku += (uu[0] + uu[6]) - 6.f * (uu[1] + uu[5]) + 15.f * (uu[2] + uu[4]) - 20.f * uu[3];
+          kv += (vv[0] + vv[6]) - 6.f * (vv[1] + vv[5]) + 15.f * (vv[2] + vv[4]) - 20.f * vv[3];
+        }
+        const float hf = (float)h;
+        const float kos = (float)sigma / (64.f * hf);
+        k[0] = ((double)(float)(v[ci] - ref[1]) + ref[1]) + (double)(kos * ku);
+        k[1] = (double)(lap / (hf * hf) + kos * kv);
+      } else {
+        float d[F][3], ko[F];
+        for (int f = 0; f < F; ++f) {
+          const double* g = padded + f * ptotal + poff[bi];
+          ko[f] = 0.f;
+          for (int ax = 0; ax < 3; ++ax) {
+            const int s = st[ax];
+            float gg[7];
+            for (int q = 0; q < 7; ++q) gg[q] = (float)(g[ci + (q - 3) * s] - ref[f]);
+            d[f][ax] = (float(D1C1) * (gg[4] - gg[2]) + float(D1C2) * (gg[5] - gg[1]) + float(D1C3) * (gg[6] - gg[0])) /
+                       (float)h;
+            ko[f] += (gg[0] + gg[6]) - 6.f * (gg[1] + gg[5]) + 15.f * (gg[2] + gg[4]) - 20.f * gg[3];
+          }
+        }
+        const float kos = (float)sigma / (64.f * (float)h);
+        k[0] = (double)((d[5][1] - d[4][2]) + kos * ko[0]);
+        k[1] = (double)((d[3][2] - d[5][0]) + kos * ko[1]);
+        k[2] = (double)((d[4][0] - d[3][1]) + kos * ko[2]);
+        k[3] = (double)(-(d[2][1] - d[1][2]) + kos * ko[3]);
+        k[4] = (double)(-(d[0][2] - d[2][0]) + kos * ko[4]);
+        k[5] = (double)(-(d[1][0] - d[0][1]) + kos * ko[5]);
+      }
+    } else {
+      const double zero[F] = {};
+      rhs_point<double, EQ, F>(padded + poff[bi], ptotal, ci, P, P * P, h, sigma, zero, k);
+    }
+    #pragma unroll
+    for (int f = 0; f < F; ++f) {
+      if constexpr (F32) ((float*)kout)[f * gtotal + goff[bi] + gi] = (float)k[f];
+      else ((double*)kout)[f * gtotal + goff[bi] + gi] = k[f];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zip(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
+                                             const int64_t* __restrict__ goff, int64_t gtotal, int F, int64_t N,
+                                             const T* __restrict__ kblock, T* __restrict__ kout) {
+  const int bi = blockIdx.y;
+  const int32_t* t = tiles + 8 * (int64_t)list[bi];
+  const int m = t[TI_M];
+  const int G = 4 * m + 1;
+  const int first = t[TI_FIRST];
+  const int nn = m * m * m * 125;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int o = e / 125, node = e % 125;
+    // octant o of the block in Morton order -> lexicographic octant coordinates
+    int ox = 0, oy = 0, oz = 0;
+    for (int bit = 0; bit < 3; ++bit) {
+      ox |= ((o >> (3 * bit)) & 1) << bit;
+      oy |= ((o >> (3 * bit + 1)) & 1) << bit;
+      oz |= ((o >> (3 * bit + 2)) & 1) << bit;
+    }
+    const int gx = 4 * ox + node % 5, gy = 4 * oy + (node / 5) % 5, gz = 4 * oz + node / 25;
+    const int64_t gi = ((int64_t)gz * G + gy) * G + gx;
+    for (int f = 0; f < F; ++f) kout[(f * N + first + o) * 125 + node] = kblock[f * gtotal + goff[bi] + gi];
+  }
+}
+
+template <bool KF32>
+__global__ __launch_bounds__(256) void k_rk(StageParams sp, const int32_t* __restrict__ tiles,
+                                            const int32_t* __restrict__ list, const double* __restrict__ coef,
+                                            double* out) {
+  const int bi = blockIdx.y;
+  const int32_t* t = tiles + 8 * (int64_t)list[bi];
+  const int n4 = (int)(*sp.step & 3);
+  const TileCtx c = tile_ctx(t, sp, n4);
+  const int first = t[TI_FIRST];
+  const int nn = c.m * c.m * c.m * 125;
+  const int64_t fs = sp.N * 125, ps = fs * sp.F;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)first * 125 + e;
+    for (int f = 0; f < sp.F; ++f) {
+      double acc = 0.0;
+      for (int i = 0; i < sp.p; ++i) acc = fma(coef[i], kload<KF32>(sp.K, i * ps + f * fs + idx), acc);
+      const double v = sp.U[c.par_same * ps + f * fs + idx] + c.dt * acc;
+      if (out) out[f * fs + idx] = v;
+      else sp.Uw[(c.par_same ^ 1) * ps + f * fs + idx] = v;
+    }
+  }
+}
+
+// current state: block b's buffer after a whole number of coarse steps
+__global__ __launch_bounds__(256) void k_current(StageParams sp, const int32_t* __restrict__ tiles, int nblocks,
+                                                 double* out) {
+  const int b = blockIdx.y;
+  if (b >= nblocks) return;
+  const int32_t* t = tiles + 8 * (int64_t)b;
+  const int lev = t[TI_LEVEL];
+  const int m = t[TI_M];
+  const int first = t[TI_FIRST];
+  const int64_t n = *sp.step;
+  // steps taken: LTS n 2^(lev-lmin), GTS n 2^(lmax-lmin)
+  const int64_t steps = sp.mode == LTS_MODE_GTS ? (n << (sp.lmax - sp.lmin)) : (n << (lev - sp.lmin));
+  const int par = (int)(steps & 1);
+  const int64_t fs = sp.N * 125, ps = fs * sp.F;
+  const int nn = m * m * m * 125;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)first * 125 + e;
+    for (int f = 0; f < sp.F; ++f) out[f * fs + idx] = sp.U[par * ps + f * fs + idx];
+  }
+}
+
+__global__ void k_increment(int64_t* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] += 1;
+}
+
+// per-octant partial sums for the norms: [F][N] sum e^2, [F][N] max |e|, nonfinite count
+__global__ __launch_bounds__(128) void k_norm_partials(const double* a, const double* b, int F, int64_t N,
+                                                       double* sq, double* mx, unsigned long long* bad) {
+  const int64_t o = blockIdx.x;
+  const int f = blockIdx.y;
+  __shared__ double s1[128], s2[128];
+  __shared__ int s3[128];
+  double q = 0.0, m = 0.0;
+  int nb = 0;
+  const int node = threadIdx.x;
+  if (node < 125) {
+    const int64_t idx = ((int64_t)f * N + o) * 125 + node;
+    const double x = a[idx];
+    const double e = b ? x - b[idx] : x;
+    if (!isfinite(x)) nb = 1;
+    q = e * e;
+    m = fabs(e);
+  }
+  s1[threadIdx.x] = q;
+  s2[threadIdx.x] = m;
+  s3[threadIdx.x] = nb;
+  __syncthreads();
+  for (int w = 64; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + w]);
+      s3[threadIdx.x] += s3[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sq[(int64_t)f * N + o] = s1[0];
+    mx[(int64_t)f * N + o] = s2[0];
+    if (s3[0]) atomicAdd(bad, (unsigned long long)s3[0]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy(const double4* __restrict__ src, double4* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, ptr, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
+                        const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(8, nb);
+  if (sp.F == 2) {
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 2>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    else hipLaunchKernelGGL((k_unzip<false, 2>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+  } else if (sp.F == 6) {
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 6>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    else hipLaunchKernelGGL((k_unzip<false, 6>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,
+                      int64_t ptotal, const int64_t* goff, int64_t gtotal, int nb, const double* padded, void* kout,
+                      double sigma, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(8, nb);
+  if (eq == LTS_EQ_WAVE) {
+    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
+                                gtotal, padded, kout, sigma);
+    else hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
+                            gtotal, padded, kout, sigma);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
+                                goff, gtotal, padded, kout, sigma);
+    else hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
+                            goff, gtotal, padded, kout, sigma);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zip(bool f32, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal, int nb,
+                      int F, int64_t N, const void* kblock, void* kout, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(8, nb);
+  if (f32) hipLaunchKernelGGL((k_zip<float>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
+                              (const float*)kblock, (float*)kout);
+  else hipLaunchKernelGGL((k_zip<double>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
+                          (const double*)kblock, (double*)kout);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* list, int nb,
+                     const double* coef, double* out, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  dim3 grid(4, nb);
+  if (kf32) hipLaunchKernelGGL((k_rk<true>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+  else hipLaunchKernelGGL((k_rk<false>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_current(const StageParams& sp, const int32_t* tiles, int nblocks, double* out, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_current, dim3(4, nblocks), dim3(256), 0, s, sp, tiles, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_increment(int64_t* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_increment, dim3(1), dim3(64), 0, s, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, double* sq, double* mx,
+                                unsigned long long* bad, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_norm_partials, dim3((unsigned)N, F), dim3(128), 0, s, a, b, F, N, sq, mx, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t nbytes, hipStream_t s) {
+  const int64_t n = (int64_t)(nbytes / sizeof(double4));
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, (const double4*)src, (double4*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace lts

@@ -1,4 +1,4 @@
-// Kernel launch interface between the C ABI layer and kernels.hip.
+// Kernel launch interface between the C ABI layer and the HIP kernels (k_*.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
