@@ -176,6 +176,9 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   if (more) load_trec(nxt.tile, ntrec);
   const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
+  // GTS reads no stored stage of the last one (every ghost relation is the
+  // same-level case, whose first stage reads U0 only): it is not stored
+  const bool storek = !(last && sp.mode == LTS_MODE_GTS);
   const KT* __restrict__ Kr = (const KT*)v.K;
   KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
   // KS: stages read by same-level sources (the tableau row's non-zero pattern),
@@ -314,10 +317,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       double kv = R[f * G3 + gi];
       if constexpr (KF32) {
         const float kf = (float)kv;
-        st32(Kw + (uint32_t)(f * fsz), off, kf);
+        if (storek) st32(Kw + (uint32_t)(f * fsz), off, kf);
         kv = (double)kf;
       } else {
-        st32(Kw + (uint32_t)(f * fsz), off, kv);
+        if (storek) st32(Kw + (uint32_t)(f * fsz), off, kv);
       }
       if (last) {
         // compute_step_partial: U_new = U0 + dt (b_0 K_0 + ... + b_s K_s),

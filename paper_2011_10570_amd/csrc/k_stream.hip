@@ -236,12 +236,14 @@ __device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCt
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       double kv = R[f * GL + gp];
+      // GTS: the last stage's K is read by no ghost relation and not stored
+      const bool storek = !(LAST && sp.mode == LTS_MODE_GTS);
       if constexpr (KF32) {
         const float kf = (float)kv;
-        st32(x.Kw + (uint32_t)(f * x.fsz), off, kf);
+        if (storek) st32(x.Kw + (uint32_t)(f * x.fsz), off, kf);
         kv = (double)kf;
       } else {
-        st32(x.Kw + (uint32_t)(f * x.fsz), off, kv);
+        if (storek) st32(x.Kw + (uint32_t)(f * x.fsz), off, kv);
       }
       if constexpr (LAST) {
         // U0 + dt (b_0 K_0 + ... + b_s K_s), s = p - 1, accumulated in stage order

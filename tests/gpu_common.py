@@ -3,7 +3,7 @@ import numpy as np
 
 from oracle import octree as ot
 from oracle import solver as so
-from workloads import mesh_spec, random_dg
+from workloads import config, mesh_spec, random_dg, wave_gaussian
 
 TOL = 1e-12   # FP64 parity: max |gpu - oracle| / max |oracle| per field
 
@@ -43,3 +43,12 @@ def padded_sizes(blocks, ids):
     S = 4 * blocks[ids, 1] + 7
     G = 4 * blocks[ids, 1] + 1
     return S, G
+
+
+def oracle_c1_at_T(mode):
+    """The oracle's whole C1 run (Gaussian pulse, 8 coarse steps to T) in one mode;
+    a plain function so that a process pool can run the two modes side by side."""
+    om = oracle_mesh("wave_c1")
+    cfg = config("wave_c1")
+    U0 = wave_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=cfg["sigma"])
+    return so.run(om, U0, cfg["n_coarse"], mode, sigma=cfg["ko_sigma"]).reshape(2, om.n_oct, 125)

@@ -9,7 +9,7 @@ from oracle import octree as ot
 from oracle import solver as so
 from workloads import config, mesh_spec, wave_gaussian, wave_plane, maxwell_gaussian, random_dg
 
-from gpu_common import TOL, oracle_mesh, rel_err
+from gpu_common import TOL, oracle_c1_at_T, oracle_mesh, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -38,21 +38,27 @@ def c1():
     return om, gm, U0
 
 
+N_C1 = config("wave_c1")["n_coarse"]
+
+
 @pytest.fixture(scope="module")
 def c1_oracle(c1):
-    om, gm, U0 = c1
-    out = {}
-    for mode in ("lts", "gts"):
-        print(f"[oracle] wave_c1 {mode} 2 coarse steps", flush=True)
-        out[mode] = so.run(om, U0, 2, mode, sigma=0.1).reshape(2, om.n_oct, 125)
-    return out
+    """LTS and GTS of the oracle on the whole C1 configuration, to its final time
+    T = 8 dt_lmin (8 coarse steps), computed in two processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    print(f"[oracle] wave_c1 lts+gts {N_C1} coarse steps", flush=True)
+    with ProcessPoolExecutor(2, mp_context=mp.get_context("spawn")) as ex:
+        res = dict(zip(("lts", "gts"), ex.map(oracle_c1_at_T, ("lts", "gts"))))
+    return res
 
 
 @pytest.mark.parametrize("mode", ["lts", "gts"])
 def test_advance_fused_graph(c1, c1_oracle, mode):
+    """C1 to T: LTS / GTS with the graph-captured fused path vs the oracle."""
     om, gm, U0 = c1
     md = P.MODE_LTS if mode == "lts" else P.MODE_GTS
-    got = _run_gpu(gm, U0, 2, md)
+    got = _run_gpu(gm, U0, N_C1, md)
     assert rel_err(got, c1_oracle[mode]) < TOL
 
 
@@ -60,7 +66,7 @@ def test_advance_fused_graph(c1, c1_oracle, mode):
 def test_advance_unfused(c1, c1_oracle, mode):
     om, gm, U0 = c1
     md = P.MODE_LTS if mode == "lts" else P.MODE_GTS
-    got = _run_gpu(gm, U0, 2, md, unfused=True)
+    got = _run_gpu(gm, U0, N_C1, md, unfused=True)
     assert rel_err(got, c1_oracle[mode]) < TOL
 
 
@@ -170,29 +176,63 @@ def test_ssprk3(c1):
     assert rel_err(got, want) < TOL
 
 
-def test_maxwell_tile1():
+@pytest.fixture(scope="module")
+def maxwell_small():
     om = oracle_mesh("small")
     gm = P.build_mesh(mesh_spec("small"))
     cfg = config("small")
     U0 = maxwell_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=0.1)
-    want = so.run(om, U0, 1, "lts", equation="maxwell", sigma=0.1).reshape(6, om.n_oct, 125)
-    got = _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", tile=1)
+    return om, gm, U0
+
+
+@pytest.mark.parametrize("mode", ["lts", "gts"])
+def test_maxwell_tile1(maxwell_small, mode):
+    om, gm, U0 = maxwell_small
+    md = P.MODE_LTS if mode == "lts" else P.MODE_GTS
+    want = so.run(om, U0, 1, mode, equation="maxwell", sigma=0.1).reshape(6, om.n_oct, 125)
+    got = _run_gpu(gm, U0, 1, md, eq="maxwell", tile=1)
     assert rel_err(got, want) < TOL
     for tile in (2, 4):
         with pytest.raises(P.LTSError):
-            _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", tile=tile)
+            _run_gpu(gm, U0, 1, md, eq="maxwell", tile=tile)
+
+
+def _field_errors(got, want, om):
+    """Per field: volume-weighted l2 and max error, relative to the field's max."""
+    w = (2.0 ** (om.L - om.levels)) ** 3
+    out = []
+    for f in range(want.shape[0]):
+        e = got[f] - want[f]
+        scale = np.abs(want[f]).max()
+        l2 = np.sqrt((w * (e ** 2).sum(1)).sum() / (125 * w.sum()))
+        out.append((l2 / scale, np.abs(e).max() / scale))
+    return out
+
+
+def test_maxwell_fp32_rhs_error_stated(maxwell_small):
+    """Maxwell with FP32 stencils (FP64 state, RK and time interpolation) vs the
+    FP64 oracle, one coarse step: error stated per field."""
+    om, gm, U0 = maxwell_small
+    want = so.run(om, U0, 1, "lts", equation="maxwell", sigma=0.1).reshape(6, om.n_oct, 125)
+    got = _run_gpu(gm, U0, 1, P.MODE_LTS, eq="maxwell", prec=P.FP32_RHS, tile=1)
+    for f, (l2, linf) in enumerate(_field_errors(got, want, om)):
+        print(f"maxwell fp32-rhs field {'EB'[f // 3]}{'xyz'[f % 3]}: rel l2 {l2:.3e}  rel max {linf:.3e}")
+        assert linf < 1e-4
 
 
 def test_fp32_rhs_error_stated(c1, c1_oracle):
-    """FP32 stencils with FP64 state: error vs the FP64 oracle, per field."""
+    """C3: the C1 mesh and data to T with FP32 stencils and FP64 state, RK and
+    time interpolation, against the FP64 oracle at T; per field l2 and max error
+    relative to the field's scale.  The bound follows from the stencil's
+    cancellation error, about eps32 |u| / h^2 relative per RHS evaluation
+    (6e-5 at h = 2^-5), not growing over the 8 coarse steps."""
     om, gm, U0 = c1
     want = c1_oracle["lts"]
     for tile in (2, 4):
-        got = _run_gpu(gm, U0, 2, P.MODE_LTS, prec=P.FP32_RHS, tile=tile)
-        for f in range(2):
-            e = np.abs(got[f] - want[f]).max() / np.abs(want[f]).max()
-            print(f"fp32-rhs tile {tile} field {f}: max rel err {e:.3e}")
-            assert e < 1e-4
+        got = _run_gpu(gm, U0, N_C1, P.MODE_LTS, prec=P.FP32_RHS, tile=tile)
+        for f, (l2, linf) in enumerate(_field_errors(got, want, om)):
+            print(f"C3 fp32-rhs tile {tile} field {'uv'[f]} at T: rel l2 {l2:.3e}  rel max {linf:.3e}")
+            assert linf < 2e-4
 
 
 def test_graph_recaptured_after_table_and_shape_changes(c1):

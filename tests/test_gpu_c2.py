@@ -6,6 +6,12 @@ launch shape, side-2 tiles).
   state is U0 there (stage 1 of Alg. 2, all time cases start together), so the
   oracle computes K_1 of any block on its own.  A seeded sample of blocks of
   every level is compared, element by element, at the FP64 tolerance.
+* Later stages at positions inside a coarse step (seeded random U and K, step
+  records positioned at substep j of coarse step n): every time case of the
+  stage conversion (same level, finer source, coarser source at a common start
+  and one fine step later) occurs; a sample of 8 active blocks per level is
+  compared element by element with the oracle's stage (and RK update at the
+  last stage).
 * One whole coarse step, graph-captured as in the benchmark: properties that
   hold at any size -- LTS and GTS agree to the scheme's error, and both are
   close to the analytic spherical wave (image sums over the periodic box)."""
@@ -22,7 +28,7 @@ from oracle import octree as ot
 from oracle import solver as so
 from workloads import config, mesh_spec, random_dg, wave_gaussian_torch
 
-from gpu_common import TOL, rel_err
+from gpu_common import TOL, positioned_state, rel_err
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 import bench  # noqa: E402
@@ -63,6 +69,45 @@ def test_c2_first_stage_sampled_blocks(c2):
     octs = np.concatenate([np.arange(om.blocks[b, 0], om.blocks[b, 0] + om.blocks[b, 1] ** 3) for b in sample])
     want = st.K[0].reshape(2, om.n_oct, 125)[:, octs]
     assert rel_err(got[:, octs], want) < TOL
+
+
+def _sample_active(om, act, seed, per_level=8):
+    lev = om.blocks[act, 2]
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.choice(act[lev == l], size=min(per_level, int((lev == l).sum())), replace=False)
+                           for l in np.unique(lev)])
+
+
+@pytest.mark.parametrize("mode,n,j,stage", [("lts", 1, 16, 3), ("lts", 3, 1, 1), ("lts", 0, 31, 2),
+                                            ("lts", 2, 2, 3), ("gts", 1, 7, 2), ("gts", 0, 3, 3)])
+def test_c2_positioned_stage_sampled_blocks(c2, mode, n, j, stage):
+    """Fused stage `stage` of substep j of coarse step n on the full C2 mesh vs the
+    oracle's unzip + rhs + zip (+ RK update) of a sample of the active blocks."""
+    cfg, gm, om = c2
+    print(f"[c2] positioned {mode} n={n} j={j} stage={stage}", flush=True)
+    st, act = positioned_state(om, 2, mode, n, j, seed=7000 + 100 * n + j)
+    act = np.asarray(act)
+    U = torch.from_numpy(st.U.reshape(2, 2, om.n_oct, 125)).to(DEV)
+    K = torch.from_numpy(st.K.reshape(4, 2, om.n_oct, 125)).to(DEV)
+    md = P.MODE_GTS if mode == "gts" else P.MODE_LTS
+    P.fused_stage(gm, U, K, P.EQ_WAVE, cfg["ko_sigma"], stage, j, md, n)
+    sample = _sample_active(om, act, 11 * n + j)
+    if mode == "lts":   # every active level is sampled
+        assert len(np.unique(om.blocks[sample, 2])) == len(np.unique(om.blocks[act, 2]))
+    st.stage(sample, stage, fd.rhs_wave, cfg["ko_sigma"])
+    octs = np.concatenate([np.arange(om.blocks[b, 0], om.blocks[b, 0] + om.blocks[b, 1] ** 3) for b in sample])
+    if not (mode == "gts" and stage == 3):   # GTS does not store the last stage
+        got = K[stage][:, torch.from_numpy(octs).to(DEV)].cpu().numpy()
+        want = st.K[stage].reshape(2, om.n_oct, 125)[:, octs]
+        assert rel_err(got, want) < TOL
+    if stage == 3:
+        st.rk_update(sample)
+        par = st.rec_par[sample]
+        for b, pb in zip(sample, par):
+            o = np.arange(om.blocks[b, 0], om.blocks[b, 0] + om.blocks[b, 1] ** 3)
+            got = U[1 - pb][:, torch.from_numpy(o).to(DEV)].cpu().numpy()
+            want = st.U[1 - pb].reshape(2, om.n_oct, 125)[:, o]
+            assert rel_err(got, want) < TOL, b
 
 
 def test_c2_coarse_step_properties(c2):

@@ -120,12 +120,17 @@ def test_fused_stage(meshes, tile, mode, n, j, stage):
     print(f"[fused] tile={tile} {mode} n={n} j={j} s={stage}", flush=True)
     st, act = positioned_state(om, 2, mode, n, j, seed=100 + 10 * j + stage)
     U, K = _dev(st.U), _dev(st.K)
+    k_in = K.clone()
     md = P.MODE_GTS if mode == "gts" else P.MODE_LTS
     P.fused_stage(gm, U, K, P.EQ_WAVE, 0.1, stage, j, md, n)
     st.stage(act, stage, fd.rhs_wave, 0.1)
     if stage == 3:
         st.rk_update(act)
-    assert rel_err(K.cpu().numpy().reshape(4, 2, -1)[stage], st.K[stage].reshape(2, -1)) < TOL
+    if mode == "gts" and stage == 3:
+        # GTS does not store the last stage (no ghost relation reads it)
+        assert torch.equal(K.reshape(4, -1)[stage], k_in.reshape(4, -1)[stage])
+    else:
+        assert rel_err(K.cpu().numpy().reshape(4, 2, -1)[stage], st.K[stage].reshape(2, -1)) < TOL
     assert rel_err(U.cpu().numpy().reshape(2, 2, -1).transpose(1, 0, 2), st.U.reshape(2, 2, -1).transpose(1, 0, 2)) < TOL
     gm.set_tile(2)
 
