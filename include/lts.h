@@ -224,6 +224,27 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
                            const lts_rhs_params* params, int32_t stage,
                            const lts_position* pos, void* stream);
 
+/* The same fused stage for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): it
+ * calls no hipMalloc / hipFree and no allocating library routine.  Its scratch
+ * (the coarse-step counter and the stage's ghost table) is a fixed 64 MiB device
+ * array of the library, one per GPU, held until the process ends; its address is
+ * looked up on the first call on each device.  The caller still owns U and K.
+ * Requirements and errors:
+ *   - the mesh's tables must already be on the current device (any earlier
+ *     device call on the mesh uploads them: lts_sim_create, lts_fused_stage,
+ *     lts_unzip, ...), else LTS_EINVAL;
+ *   - the stage's ghost table (entries with receiver level >= the substep's
+ *     lowest active level, F x 729 doubles each) must fit in 64 MiB - 256 B,
+ *     else LTS_EINVAL before any device work;
+ *   - all calls on one GPU share that GPU's scratch, which keeps the last call's
+ *     contents: calls that overlap on one GPU (different streams or host threads
+ *     without ordering) race.  Calls ordered on one stream are safe.
+ * Results are bitwise those of lts_fused_stage with the same arguments. */
+lts_status lts_fused_stage_noalloc(lts_mesh* mesh, const lts_stage_view* view, int32_t equation,
+                                   const lts_rhs_params* params, int32_t stage, const lts_position* pos,
+                                   void* stream);
+
 /* Launch shape of the fused stage kernels (process-wide; used by every later
  * fused launch and graph capture): threads per workgroup of the LDS tile kernels
  * (256 or 512, default 512) and of the streaming kernel of side-4 tiles (256 or

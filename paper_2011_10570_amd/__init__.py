@@ -18,7 +18,7 @@ from ._lib import (CRIT_ANNULUS, CRIT_BALL, EQ_MAXWELL, EQ_WAVE, FP32_RHS, FP64,
 
 __all__ = ["Mesh", "Sim", "build_mesh", "unzip", "rhs", "zip", "rk_stage", "fused_stage", "coefficients",
            "norms", "copy_probe", "LTSError", "MODE_LTS", "MODE_GTS", "EQ_WAVE", "EQ_MAXWELL", "FP64", "FP32_RHS",
-           "RK4", "SSPRK3", "Batch", "batch_advance", "set_launch", "get_launch"]
+           "RK4", "SSPRK3", "Batch", "batch_advance", "set_launch", "get_launch", "fused_stage_noalloc"]
 
 EQUATIONS = {"wave": EQ_WAVE, "maxwell": EQ_MAXWELL}
 TABLEAUS = {"rk4": RK4, "ssprk3": SSPRK3}
@@ -210,6 +210,17 @@ def fused_stage(mesh: Mesh, U, K, equation: int, ko_sigma: float, stage: int, su
     p = _pos(substep, mode, coarse_step)
     check(lib().lts_fused_stage(mesh.h, C.byref(v), equation, C.byref(prm), stage, C.byref(p), _stream_ptr(stream)),
           "lts_fused_stage")
+
+
+def fused_stage_noalloc(mesh: Mesh, U, K, equation: int, ko_sigma: float, stage: int, substep: int, mode: int,
+                        coarse_step: int, precision: int = FP64, tableau: int = RK4, stream=None):
+    """lts_fused_stage_noalloc: the fused stage with the library's fixed device scratch."""
+    v = _view(U, K, NFIELDS[equation], precision, tableau)
+    prm = _L.RhsParams()
+    prm.ko_sigma = ko_sigma
+    p = _pos(substep, mode, coarse_step)
+    check(lib().lts_fused_stage_noalloc(mesh.h, C.byref(v), equation, C.byref(prm), stage, C.byref(p),
+                                        _stream_ptr(stream)), "lts_fused_stage_noalloc")
 
 
 def norms(mesh: Mesh, a, b=None, nfields: int = 2, stream=None) -> dict:

@@ -81,6 +81,8 @@ PROTOTYPES = {
                                _P, _P]),
     "lts_fused_stage": (C.c_int, [_P, C.POINTER(StageView), C.c_int32, C.POINTER(RhsParams), C.c_int32,
                                   C.POINTER(Position), _P]),
+    "lts_fused_stage_noalloc": (C.c_int, [_P, C.POINTER(StageView), C.c_int32, C.POINTER(RhsParams), C.c_int32,
+                                          C.POINTER(Position), _P]),
     "lts_set_launch": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
     "lts_get_launch": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lts_sim_create": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(RhsParams), C.POINTER(_P)]),

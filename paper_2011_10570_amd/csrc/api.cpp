@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -224,6 +225,15 @@ static lts_status ensure_cscr(const Mesh& m, int F, double** p, size_t* cap) {
   HIP_TRY(hipMalloc(p, need), "hipMalloc ghost scratch");
   *cap = need;
   return LTS_OK;
+}
+
+// Lowest level of the blocks B_j (Alg. 2, fig. blk_loop): all levels at j = 0
+// and in GTS, else lmax - ctz(j).
+static int lowest_active_level(const Mesh& m, int mode, int j) {
+  if (mode == LTS_MODE_GTS || j == 0) return m.lmin;
+  int tz = 0;
+  while (!(j & 1)) { j >>= 1; ++tz; }
+  return m.lmax - tz;
 }
 
 // Every fused launch of one stage for the tiles of levels >= lo: the ghost-table
@@ -533,17 +543,76 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
   StageParams sp;
   if ((st = fill_params(m, view, stage, pos, h->x.d_step, sp)) != LTS_OK) return st;
   sp.sigma = params->ko_sigma;
-  const int lo = pos->mode == LTS_MODE_GTS ? 0 : [&] {
-    int j = pos->substep, tz = 0;
-    if (j == 0) return m.lmin;
-    while (!(j & 1)) { j >>= 1; ++tz; }
-    return m.lmax - tz;
-  }();
+  const int lo = lowest_active_level(m, pos->mode, pos->substep);
   if ((st = ensure_cscr(m, sp.F, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
   return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, h->x.d_cscr, g_shape, s);
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- no-allocation variant
+// Fixed device scratch of lts_fused_stage_noalloc: the coarse-step counter in the
+// first 256 bytes, then the ghost table of the stage.  Every GPU the library runs
+// on holds its own copy (its address is looked up once per device).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr size_t kNoAllocHeader = 256;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved on the first call
+// on that device.
+lts_status scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LTS_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(LTS_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LTS_OK;
+}
+}  // namespace
+
+extern "C" lts_status lts_fused_stage_noalloc(lts_mesh* mesh, const lts_stage_view* view, int32_t equation,
+                                              const lts_rhs_params* params, int32_t stage, const lts_position* pos,
+                                              void* stream) {
+  clear_error();
+  if (!mesh || !params || !pos) return fail(LTS_EINVAL, "NULL argument");
+  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  Mesh& m = mesh->m;
+  if (!m.uploaded) return fail(LTS_EINVAL, "mesh tables are not on the device (make one device call on the mesh first)");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != m.device) return fail(LTS_EINVAL, "mesh tables were uploaded to another device");
+  if (equation == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
+    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
+  if ((equation == LTS_EQ_WAVE) != (view && view->nfields == 2))
+    return fail(LTS_EINVAL, "nfields does not match the equation");
+  void* base = nullptr;
+  lts_status st = scratch_address(&base);
+  if (st != LTS_OK) return st;
+  int64_t* d_step = (int64_t*)base;
+  double* gtab = (double*)((char*)base + kNoAllocHeader);
+  StageParams sp;
+  if ((st = fill_params(m, view, stage, pos, d_step, sp)) != LTS_OK) return st;
+  sp.sigma = params->ko_sigma;
+  const int lo = lowest_active_level(m, pos->mode, pos->substep);
+  const size_t need = (size_t)m.ghost_ge[lo] * sp.F * 729 * sizeof(double);
+  if (need > kNoAllocScratchBytes - kNoAllocHeader)
+    return fail(LTS_EINVAL, "the stage's ghost table (" + std::to_string(need) + " B) exceeds the fixed scratch (" +
+                                std::to_string(kNoAllocScratchBytes - kNoAllocHeader) + " B)");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_set_i64(d_step, pos->coarse_step, s), "set step");
+  return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, gtab, g_shape, s);
+}
 
 // ------------------------------------------------------------------------ sims
 struct lts_sim {
@@ -603,12 +672,6 @@ void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams
   set_kmask(sp);
 }
 
-int lowest_active_level(const Mesh& m, int mode, int j) {
-  if (mode == LTS_MODE_GTS || j == 0) return m.lmin;
-  int tz = 0;
-  while (!(j & 1)) { j >>= 1; ++tz; }
-  return m.lmax - tz;
-}
 
 lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
   Mesh& m = sim->mesh->m;
