@@ -20,12 +20,20 @@ Reported (one JSON line):
   roofline       the fused stage (ghost-table pre-pass + fused tile launches of
                  one RK stage): algorithmic HBM bytes (224 B per FP64 LTS
                  node-update) / event-timed stage duration, against 8 TB/s;
-  cpu_baseline   the FP64 oracle on a bounded sample of the same workload;
+  cpu_baseline   the FP64 oracle on a bounded sample of the same workload
+                 (value), the host's CPU model and core count, and the oracle
+                 run in full on the C1 configuration (LTS and GTS to T, one
+                 process each, beside the GPU legs): wall times, node-updates/s
+                 and the oracle's own LTS-over-GTS speedup;
+  c3             the C1 configuration to T with FP32 stencils on the GPU against
+                 that FP64 oracle result: l2 / max error per field;
+  maxwell        6-field Maxwell on the same mesh (tile side 1), FP64 LTS:
+                 node-updates/s and its roofline fraction (672 B per update);
   batch          64 independent wave problems (1k-50k leaves, levels 2..4-8)
-                 advanced to T together by continuous batching: raw
-                 node-updates/s until all reach T (--no-batch skips it);
-  serve          with --serve: the Poisson-arrival wave/Maxwell serving loop
-                 (throughput, p50/p99 time-to-T).
+                 advanced to T together by continuous batching, FP64 and
+                 FP32-RHS: raw node-updates/s until all reach T (--no-batch);
+  serve          the Poisson-arrival wave/Maxwell serving loop over the stored
+                 requests: throughput, p50/p99 time-to-T (--no-serve skips it).
 
     python bench.py --copy-probe-mib N   only times the device copy probe (the
                                          known-size kernel that scales counters)
@@ -61,7 +69,9 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="autotune tile side and launch shape first")
     ap.add_argument("--only", default="", help="comma list of legs: lts,gts,fp32")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
-    ap.add_argument("--serve", action="store_true", help="also run the serving loop")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=None, help="first N stored requests (default all)")
+    ap.add_argument("--no-maxwell", action="store_true", help="skip the Maxwell leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only time a copy of this many MiB")
     return ap.parse_args()
 
@@ -198,10 +208,10 @@ def analytic_error(sim_out, leaves, L, pulses, sigma, T):
     return out
 
 
-def time_leg(P, gm, U0, mode, prec, steps, warmup, torch):
+def time_leg(P, gm, U0, mode, prec, steps, warmup, torch, equation="wave"):
     """Warmup + timed coarse steps; HIP events on the launch stream bracket the
     timed region, torch.cuda.synchronize() on both sides."""
-    sim = P.Sim(gm, "wave", prec, "rk4", ko_sigma=0.1, device="cuda:0")
+    sim = P.Sim(gm, equation, prec, "rk4", ko_sigma=0.1, device="cuda:0")
     sim.set_state(U0)
     stream = torch.cuda.current_stream()
     sim.advance(warmup, mode, graph=True, stream=stream)
@@ -260,6 +270,64 @@ def cpu_baseline(spec, cfg, target_s=15.0):
                       f"({cpu:.1f} s CPU), single thread"}
 
 
+def host_cpu() -> dict:
+    """CPU model and core count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc_online": os.cpu_count(), "cores_available": avail}
+
+
+def oracle_c1_run(mode: str) -> dict:
+    """The oracle in full on the C1 configuration (one Gaussian pulse, levels 2-4,
+    8 coarse steps to T), single thread: wall time and the state at T."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
+    from oracle import octree as ot
+    from oracle import solver as so
+    from workloads import config, mesh_spec, wave_gaussian
+    cfg = config("wave_c1")
+    om = ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec("wave_c1")))
+    U0 = wave_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=cfg["sigma"])
+    t = time.perf_counter()
+    out = so.run(om, U0, cfg["n_coarse"], mode, sigma=cfg["ko_sigma"])
+    wall = time.perf_counter() - t
+    return {"wall_s": wall, "state": out.reshape(2, om.n_oct, 125)}
+
+
+def start_oracle_c1():
+    """The two C1 oracle runs (LTS, GTS) in background processes (spawned: the
+    parent holds a GPU context)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    ex = ProcessPoolExecutor(2, mp_context=mp.get_context("spawn"))
+    return ex, {m: ex.submit(oracle_c1_run, m) for m in ("lts", "gts")}
+
+
+def field_errors(got, want, levels, L) -> dict:
+    """Per field: volume-weighted l2 and max error relative to the field's max."""
+    w = (2.0 ** (L - np.asarray(levels, dtype=np.float64))) ** 3
+    out = {}
+    for f, name in enumerate(("u", "v")):
+        e = got[f] - want[f]
+        scale = np.abs(want[f]).max()
+        out[f"rel_l2_{name}"] = float(np.sqrt((w * (e ** 2).sum(1)).sum() / (125 * w.sum())) / scale)
+        out[f"rel_linf_{name}"] = float(np.abs(e).max() / scale)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -270,6 +338,8 @@ def main():
     import paper_2011_10570_amd as P
     from workloads import config, mesh_spec, wave_gaussian_torch
 
+    # the oracle's C1 runs start before this process touches the GPU
+    oracle_pool = start_oracle_c1() if not (args.no_cpu or args.copy_probe_mib) else None
     torch.cuda.set_device(0)
     if args.copy_probe_mib:
         print(json.dumps({"copy_probe_mib": args.copy_probe_mib,
@@ -355,24 +425,84 @@ def main():
                 "copy_probe_gbs": round(cp, 1), "frac_of_copy": round(achieved / cp, 4),
                 "sources_sha256": source_digest()}
 
+    # GTS moves 208 B per node-update (its last stage stores no K): the same
+    # fused stage kernels against the same peak
+    gts_roof = None
+    if res.get("gts"):
+        t_step = res["gts"]["event_s"] / args.steps
+        n_stages = 4 * int(info["n_substeps"])
+        a_g = 208 * w_gts / t_step / 1e9
+        gts_roof = {"achieved": round(a_g, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a_g / HBM_PEAK_GBS, 4),
+                    "bytes_per_node_update": 208, "avg_stage_us": round(1e6 * t_step / n_stages, 2)}
+
+    maxwell = None
+    if not args.no_maxwell and "lts" in legs:
+        # 6 fields (E, B) from divergence-free Gaussian data, tile side 1
+        from workloads import maxwell_gaussian_torch
+        gm.set_tile(1)
+        Um = maxwell_gaussian_torch(leaves, info["L"], cfg["pulses"], sigma=cfg["sigma"], device="cuda:0")
+        steps_m = max(1, min(args.steps, 4))
+        wall, ev = time_leg(P, gm, Um, P.MODE_LTS, P.FP64, steps_m, 1, torch, equation="maxwell")
+        del Um
+        gm.set_tile(args.tile or 2)
+        rate = w_lts * steps_m / wall
+        a_m = 672 * w_lts * steps_m / ev / 1e9
+        maxwell = {"rate": rate, "ms_per_step": 1e3 * wall / steps_m, "steps": steps_m, "tile": 1,
+                   "roofline": {"achieved": round(a_m, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(a_m / HBM_PEAK_GBS, 4), "bytes_per_node_update": 672}}
+        print(f"[bench] maxwell: {rate:.4e} node-updates/s, frac {a_m / HBM_PEAK_GBS:.3f}", file=sys.stderr,
+              flush=True)
+
     batch = None
     if not args.no_batch:
         from paper_2011_10570_amd import serve
-        print("[bench] batch: 64 problems to T...", file=sys.stderr, flush=True)
         bc = config("batch")
-        batch = serve.batch_throughput(bc["problems"], bc["n_coarse"])
-        print(f"[bench] batch: {batch['node_updates_per_s']:.4e} node-updates/s", file=sys.stderr, flush=True)
+        batch = {}
+        for name, prec in (("fp64", P.FP64), ("fp32_rhs", P.FP32_RHS)):
+            print(f"[bench] batch {name}: 64 problems to T...", file=sys.stderr, flush=True)
+            batch[name] = serve.batch_throughput(bc["problems"], bc["n_coarse"], precision=prec)
+            print(f"[bench] batch {name}: {batch[name]['node_updates_per_s']:.4e} node-updates/s", file=sys.stderr,
+                  flush=True)
     served = None
-    if args.serve:
+    if not args.no_serve:
         from paper_2011_10570_amd import serve
         print("[bench] serving loop...", file=sys.stderr, flush=True)
-        cap = batch["node_updates_per_s"] if batch else None
-        served = serve.run_config(capacity=cap, verbose=True)
+        cap = batch["fp64"]["node_updates_per_s"] if batch else None
+        served = serve.run_config(capacity=cap, n=args.serve_requests)
+        print(f"[bench] serve: p50 {served['p50_time_to_t_s']:.3f} s, p99 {served['p99_time_to_t_s']:.3f} s",
+              file=sys.stderr, flush=True)
 
     cpu = None
+    c3 = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(spec, cfg)
+        cpu.update(host_cpu())
+        ex, futs = oracle_pool
+        full = {m: f.result() for m, f in futs.items()}
+        ex.shutdown()
+        c1cfg = config("wave_c1")
+        gc1 = P.build_mesh(mesh_spec("wave_c1"))
+        ic1 = gc1.info()
+        c1 = {"config": "wave_c1: levels 2-4, 596 octants, one Gaussian pulse, RK4, 8 coarse steps to T = 0.25",
+              "threads": 1, "processes": 2}
+        for m in ("lts", "gts"):
+            nu = ic1["node_updates_lts" if m == "lts" else "node_updates_gts"] * c1cfg["n_coarse"]
+            c1[m] = {"wall_s": full[m]["wall_s"], "node_updates": nu, "rate": nu / full[m]["wall_s"]}
+        c1["oracle_lts_over_gts_speedup"] = full["gts"]["wall_s"] / full["lts"]["wall_s"]
+        c1["model_speedup_eq_invS"] = ic1["s_est"]
+        cpu["c1_full_run"] = c1
+        # C3: the C1 configuration with FP32 stencils on the GPU vs the FP64 oracle at T
+        lv1 = gc1.leaves()
+        U1 = wave_gaussian_torch(lv1, ic1["L"], c1cfg["pulses"], sigma=c1cfg["sigma"], device="cuda:0")
+        c3 = {"config": "C1 mesh and data to T, FP32 stencils, FP64 state / RK / time interpolation"}
+        for name, prec in (("fp32_rhs", P.FP32_RHS), ("fp64", P.FP64)):
+            sim = P.Sim(gc1, "wave", prec, "rk4", ko_sigma=c1cfg["ko_sigma"], device="cuda:0")
+            sim.set_state(U1)
+            sim.advance(c1cfg["n_coarse"], P.MODE_LTS, graph=True)
+            c3[f"{name}_vs_oracle"] = field_errors(sim.current().cpu().numpy(), full["lts"]["state"], lv1[:, 3],
+                                                   ic1["L"])
+            del sim
 
     value = lts["rate"] if lts else None
     out = {
@@ -407,10 +537,17 @@ def main():
         out["fp32_rhs"] = {"rate": res["fp32"]["rate"], "speedup_over_fp64": lts["wall_s"] / res["fp32"]["wall_s"]}
     if acc:
         out["accuracy"] = acc
+    if gts_roof:
+        out["gts_roofline"] = gts_roof
+    if maxwell:
+        out["maxwell"] = maxwell
+    if c3:
+        out["c3"] = c3
     if batch:
         out["batch"] = batch
     if served:
         out["serve"] = served
+        out["p99_time_to_t_s"] = served["p99_time_to_t_s"]
     if tuned:
         out["tuned"] = {"best": tuned["best"], "ms": tuned["ms"]}
     print(json.dumps(out))

@@ -132,6 +132,8 @@ typedef struct {
   double s_est;              /* speedup model 1/S of eq. invS, inverted             */
   double s_max;              /* |W| / alpha_0                                        */
   int64_t table_bytes;       /* device memory of the mesh's tables (all tile sides) */
+  int64_t ghost_entries;     /* coarser ghost sources of the fused tiles: a sim's   */
+                             /* ghost-table scratch is ghost_entries x F x 729 doubles */
 } lts_mesh_info;
 
 typedef struct lts_mesh lts_mesh;

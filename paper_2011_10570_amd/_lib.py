@@ -40,7 +40,7 @@ class MeshInfo(C.Structure):
                 ("lmin", C.c_int32), ("lmax", C.c_int32), ("n_substeps", C.c_int32), ("tile", C.c_int32),
                 ("level_count", C.c_int64 * MAX_LEVEL), ("unzip_points", C.c_int64), ("grid_points", C.c_int64),
                 ("node_updates_lts", C.c_int64), ("node_updates_gts", C.c_int64), ("s_est", C.c_double),
-                ("s_max", C.c_double), ("table_bytes", C.c_int64)]
+                ("s_max", C.c_double), ("table_bytes", C.c_int64), ("ghost_entries", C.c_int64)]
 
 
 class StageView(C.Structure):

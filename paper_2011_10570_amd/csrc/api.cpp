@@ -330,6 +330,7 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   for (int k : {1, 2, 4}) tb += (int64_t)(m.ts[k].tiles.size() + m.ts[k].slots.size());
   tb += (int64_t)m.ghosts.size();
   info->table_bytes = 4 * tb;
+  info->ghost_entries = (int64_t)(m.ghosts.size() / 2);
   info->node_updates_lts = wl;
   info->node_updates_gts = wg;
   // eq. invS with alpha_l = DG nodes at level lmax - l

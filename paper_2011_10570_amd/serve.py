@@ -7,8 +7,11 @@ C++ builder releases the GIL) when it arrives; it is admitted, first come first
 served, once its footprint fits the device-memory budget:
 
     footprint = N * 125 * F * (2 * 8 + p * sizeof(K)) + device tables
+                + ghost entries * F * 729 * 8
 
-(two U buffers in float64, p stage arrays).  Admitted sims are attached to the
+(two U buffers in float64, p stage arrays, the mesh's tile and slot tables and
+its region of the batch's ghost-table scratch).  A request whose footprint
+exceeds the whole budget is refused (status "rejected"), not queued.  Admitted sims are attached to the
 batch of their equation (wave or Maxwell: one fused kernel each) at the next
 round boundary; each round advances every attached sim by one of its own
 substeps; sims leave when they reach T and their memory returns to the budget.
@@ -23,6 +26,7 @@ import argparse
 import collections
 import concurrent.futures as cf
 import json
+import threading
 import time
 from dataclasses import dataclass, field
 from typing import List, Optional
@@ -41,6 +45,7 @@ class Request:
     n_coarse: int
     arrival: float = 0.0          # seconds after the start
     sigma: float = 0.1
+    cancel_after: Optional[float] = None   # cancel this many seconds after arrival
     # filled by the server
     mesh: Optional[Mesh] = None
     sim: Optional[Sim] = None
@@ -48,6 +53,7 @@ class Request:
     node_updates: int = 0
     admitted: float = float("nan")
     finished: float = float("nan")
+    status: str = "pending"       # pending | done | rejected | cancelled
     state: Optional[object] = None  # final state [F][N][125] when kept
 
     @property
@@ -59,7 +65,8 @@ def footprint_bytes(info: dict, equation: str, precision: int, tableau: str = "r
     F = NFIELDS[EQUATIONS[equation]]
     p = NSTAGES[TABLEAUS[tableau]]
     kb = 4 if precision == FP32_RHS else 8
-    return int(info["n_oct"]) * 125 * F * (2 * 8 + p * kb) + int(info["table_bytes"])
+    return (int(info["n_oct"]) * 125 * F * (2 * 8 + p * kb) + int(info["table_bytes"])
+            + int(info["ghost_entries"]) * F * 729 * 8)
 
 
 def initial_state(mesh: Mesh, equation: str, centre, sigma: float, device):
@@ -70,9 +77,15 @@ def initial_state(mesh: Mesh, equation: str, centre, sigma: float, device):
 
 
 class Server:
+    """Admission by footprint, continuous batching per equation.  The wave and
+    Maxwell batches run on two streams (default priority), so their rounds
+    overlap on the device; a tick enqueues a few rounds of both and then waits
+    for both."""
+
     def __init__(self, budget_bytes: int, precision: int = FP64, tableau: str = "rk4", mode: int = MODE_LTS,
                  capacity: int = 64, tick_rounds: int = 4, keep_state: bool = False, device: str = "cuda",
                  builders: int = 4, ko_sigma: float = 0.1, verbose: bool = False):
+        import torch
         self.verbose = verbose
         self.budget = int(budget_bytes)
         self.prec = precision
@@ -83,8 +96,23 @@ class Server:
         self.device = device
         self.ko_sigma = ko_sigma
         self.batches = {eq: Batch(eq, precision, tableau, mode, capacity) for eq in ("wave", "maxwell")}
+        self.streams = {"wave": torch.cuda.current_stream(), "maxwell": torch.cuda.Stream()}
         self.capacity = capacity
         self.pool = cf.ThreadPoolExecutor(max_workers=builders)
+        self._cancel = set()
+        self._lock = threading.Lock()
+
+    def cancel(self, rid: int):
+        """Cancel request rid (thread-safe): dropped if not yet admitted, else
+        released at its next coarse-step boundary."""
+        with self._lock:
+            self._cancel.add(rid)
+
+    def _cancelled(self, r: Request, now: float) -> bool:
+        if r.cancel_after is not None and now >= r.arrival + r.cancel_after:
+            return True
+        with self._lock:
+            return r.rid in self._cancel
 
     def _prepare(self, req: Request):
         m = Mesh(req.mesh_spec)
@@ -108,6 +136,22 @@ class Server:
         nb_att = {eq: 0 for eq in self.batches}
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
+        main = torch.cuda.current_stream()
+
+        def release(r: Request, status: str, now: float):
+            nonlocal used
+            r.status = status
+            r.finished = now
+            used -= r.footprint
+            nb_att[r.equation] -= 1
+            if self.verbose:
+                print(f"[serve] request {r.rid} ({r.equation}, {r.node_updates} node-updates) {status}: "
+                      f"queued {r.admitted - r.arrival:.3f} s, time-to-T {r.time_to_t:.3f} s", flush=True)
+            if self.keep_state and status == "done":
+                r.state = r.sim.current()
+            r.sim = None
+            r.mesh = None
+
         while pending or building or resident:
             now = clock()
             while pending and pending[0].arrival <= now:
@@ -116,14 +160,24 @@ class Server:
             # first come, first served: the head of the queue blocks later requests
             while building and building[0][1].done():
                 r, fut = building[0]
+                if self._cancelled(r, clock()):
+                    building.popleft()
+                    r.status, r.finished = "cancelled", clock()
+                    continue
                 if r.mesh is None:
                     r.mesh = fut.result()
                     info = r.mesh.info()
                     r.footprint = footprint_bytes(info, r.equation, self.prec, self.tab)
-                    if r.footprint > self.budget:
-                        raise ValueError(f"request {r.rid} needs {r.footprint} B, more than the budget")
                     r.node_updates = int(info["node_updates_lts" if self.mode == MODE_LTS
                                               else "node_updates_gts"]) * r.n_coarse
+                    if r.footprint > self.budget:
+                        # can never fit: refused, not queued
+                        building.popleft()
+                        r.status, r.finished, r.mesh = "rejected", clock(), None
+                        if self.verbose:
+                            print(f"[serve] request {r.rid} rejected: {r.footprint} B > budget {self.budget} B",
+                                  flush=True)
+                        continue
                 if used + r.footprint > self.budget or nb_att[r.equation] >= self.capacity:
                     break
                 building.popleft()
@@ -136,39 +190,55 @@ class Server:
                 wait = (pending[0].arrival - clock()) if pending else 0.0
                 time.sleep(min(max(wait, 0.0), 0.01) if pending else 0.001)
                 continue
-            k = min(self.tick_rounds, min(r.sim.rounds_left for r in resident))
+            # cancelled residents leave at their next coarse-step boundary
+            now = clock()
+            keep = []
+            bound = []
+            for r in resident:
+                if self._cancelled(r, now):
+                    nsub = int(r.mesh.info()["n_substeps"])
+                    to_b = r.sim.rounds_left % nsub
+                    if to_b == 0:
+                        self.batches[r.equation].detach(r.sim, stream=self.streams[r.equation])
+                        self.streams[r.equation].synchronize()
+                        release(r, "cancelled", now)
+                        continue
+                    bound.append(to_b)
+                keep.append(r)
+            resident = keep
+            if not resident:
+                continue
+            k = min([self.tick_rounds, min(r.sim.rounds_left for r in resident)] + bound)
             done = []
             for eq, b in self.batches.items():
                 if nb_att[eq]:
-                    done += b.run(k)
-            torch.cuda.current_stream().synchronize()
+                    st = self.streams[eq]
+                    if st is not main:
+                        st.wait_stream(main)      # initial states were written on the main stream
+                    done += b.run(k, stream=st)
+            for eq, st in self.streams.items():
+                if nb_att[eq]:
+                    st.synchronize()
             now = clock()
             fin = {id(s) for s in done}
             keep = []
             for r in resident:
                 if id(r.sim) in fin:
-                    r.finished = now
-                    if self.verbose:
-                        print(f"[serve] request {r.rid} ({r.equation}, {r.node_updates} node-updates) done: "
-                              f"queued {r.admitted - r.arrival:.3f} s, time-to-T {r.time_to_t:.3f} s", flush=True)
-                    if self.keep_state:
-                        r.state = r.sim.current()
-                    used -= r.footprint
-                    nb_att[r.equation] -= 1
-                    r.sim = None
-                    r.mesh = None
+                    release(r, "done", now)
                 else:
                     keep.append(r)
             resident = keep
         wall = clock()
-        tt = np.array([r.time_to_t for r in reqs])
-        total = sum(r.node_updates for r in reqs)
-        return {"requests": len(reqs), "wall_s": wall, "node_updates": total,
+        ok = [r for r in reqs if r.status == "done"]
+        tt = np.array([r.time_to_t for r in ok]) if ok else np.array([float("nan")])
+        total = sum(r.node_updates for r in ok)
+        return {"requests": len(reqs), "done": len(ok), "rejected": sum(r.status == "rejected" for r in reqs),
+                "cancelled": sum(r.status == "cancelled" for r in reqs), "wall_s": wall, "node_updates": total,
                 "node_updates_per_s": total / wall if wall > 0 else float("nan"),
                 "p50_time_to_t_s": float(np.percentile(tt, 50)), "p99_time_to_t_s": float(np.percentile(tt, 99)),
-                "mean_queue_s": float(np.mean([r.admitted - r.arrival for r in reqs])),
+                "mean_queue_s": float(np.mean([r.admitted - r.arrival for r in ok])) if ok else float("nan"),
                 "peak_resident_bytes": peak, "budget_bytes": self.budget,
-                "wave": sum(r.equation == "wave" for r in reqs), "maxwell": sum(r.equation == "maxwell" for r in reqs)}
+                "wave": sum(r.equation == "wave" for r in ok), "maxwell": sum(r.equation == "maxwell" for r in ok)}
 
     def close(self):
         self.pool.shutdown(wait=True)

@@ -68,6 +68,31 @@ def test_served_with_arrivals():
         assert torch.equal(r.state, _alone(r)), r.rid
 
 
+def test_serve_refuses_oversize_and_cancels():
+    """A request larger than the whole budget is refused with a status (the rest
+    is served); a cancelled request leaves (before admission, or at its next
+    coarse-step boundary) and the others still end bitwise as alone."""
+    reqs = _requests()[:4]
+    fps = [serve.footprint_bytes(P.Mesh(r.mesh_spec).info(), r.equation, P.FP64) for r in reqs]
+    probs = config("batch")["problems"]
+    big = serve.Request(10, "wave", probs[35]["mesh"], probs[35]["mesh"]["criteria"][0]["center"], 1)
+    big_fp = serve.footprint_bytes(P.Mesh(big.mesh_spec).info(), "wave", P.FP64)
+    budget = max(fps) * 2
+    assert big_fp > budget
+    early = serve.Request(11, "wave", mesh_spec("small"), [18, 12, 9], 1, cancel_after=0.0)
+    late = serve.Request(12, "wave", mesh_spec("wave_c1"), [36, 25, 17], 3, cancel_after=0.002)
+    srv = serve.Server(budget, keep_state=True, tick_rounds=1, device=DEV)
+    stats = srv.run(reqs + [big, early, late])
+    srv.close()
+    print("[serve]", stats, flush=True)
+    assert big.status == "rejected" and stats["rejected"] == 1
+    assert early.status == "cancelled" and late.status == "cancelled"
+    assert stats["done"] == len(reqs) and stats["peak_resident_bytes"] <= budget
+    for r in reqs:
+        assert r.status == "done"
+        assert torch.equal(r.state, _alone(r)), r.rid
+
+
 def test_autotuner_applies_fastest_and_keeps_results():
     from workloads import wave_gaussian_torch
     m = P.Mesh(mesh_spec("wave_c1"))

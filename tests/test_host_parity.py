@@ -202,3 +202,14 @@ def test_arrays_beyond_32bit_offsets_rejected():
     assert 4 * 2 * n * 125 < 2 ** 31 <= 4 * 6 * n * 125
     with pytest.raises(P.LTSError, match="32-bit"):
         P.Sim(gm, "maxwell", P.FP64, "rk4", device="cpu")
+
+
+def test_footprint_counts_ghost_scratch():
+    """The serving loop's admission footprint counts the mesh's region of the
+    batch ghost-table scratch (F x 729 doubles per coarser ghost source)."""
+    from paper_2011_10570_amd import serve
+    m = P.Mesh(mesh_spec("wave_c1"))
+    info = m.info()
+    assert info["ghost_entries"] > 0
+    base = info["n_oct"] * 125 * 2 * (16 + 4 * 8) + info["table_bytes"]
+    assert serve.footprint_bytes(info, "wave", P.FP64) == base + info["ghost_entries"] * 2 * 729 * 8
