@@ -70,7 +70,12 @@ enum { LTS_MAX_LEVEL = 16 };
 
 enum { LTS_CRIT_BALL = 0, LTS_CRIT_ANNULUS = 1 };
 enum { LTS_MODE_LTS = 0, LTS_MODE_GTS = 1 };
-enum { LTS_EQ_WAVE = 0, LTS_EQ_MAXWELL = 1 };
+/* Equations: the linear wave system (u, v); vacuum Maxwell (E, B); the
+ * non-linear wave of Sec. 4.2 (eqs. lsm, chi, phi: fields chi, phi, source
+ * -c sin(2 chi) / r^2) with, on a bounded mesh, the radiative outer boundary. */
+enum { LTS_EQ_WAVE = 0, LTS_EQ_MAXWELL = 1, LTS_EQ_NLWAVE = 2 };
+/* Domain: periodic [-1, 1]^3, or [-1, 1]^3 bounded by its outer faces. */
+enum { LTS_BOUNDARY_PERIODIC = 0, LTS_BOUNDARY_OUTER = 1 };
 enum { LTS_FP64 = 0, LTS_FP32_RHS = 1 };
 enum { LTS_RK4 = 0, LTS_SSPRK3 = 1 };
 
@@ -84,8 +89,9 @@ enum {
 };
 
 /* Unzip-map source kinds (Sec. 3.3): own octant, same-level neighbour, finer
- * neighbour (f->c injection), coarser neighbour (c->f interpolation). */
-enum { LTS_SRC_OWN = 0, LTS_SRC_SAME = 1, LTS_SRC_FINE = 2, LTS_SRC_COARSE = 3 };
+ * neighbour (f->c injection), coarser neighbour (c->f interpolation), and on a
+ * bounded mesh a point beyond the outer faces (no source, leaf -1). */
+enum { LTS_SRC_OWN = 0, LTS_SRC_SAME = 1, LTS_SRC_FINE = 2, LTS_SRC_COARSE = 3, LTS_SRC_NONE = 4 };
 
 /* Refinement criterion around an integer centre (node units at level l_max:
  * 4 * 2^l_max per side, x = -1 + 2 X / (4 * 2^l_max)).  A level-l leaf is split
@@ -116,6 +122,9 @@ typedef struct {
   const lts_criterion* criteria;   /* host */
   int64_t n_leaves;          /* > 0: use the explicit leaf list                    */
   const int32_t* leaves;     /* host */
+  int32_t boundary;          /* LTS_BOUNDARY_PERIODIC (0) or LTS_BOUNDARY_OUTER: on a */
+                             /* bounded mesh distances, balance and neighbours stop */
+                             /* at the outer faces                                   */
 } lts_mesh_spec;
 
 typedef struct {
@@ -134,6 +143,7 @@ typedef struct {
   int64_t table_bytes;       /* device memory of the mesh's tables (all tile sides) */
   int64_t ghost_entries;     /* coarser ghost sources of the fused tiles: a sim's   */
                              /* ghost-table scratch is ghost_entries x F x 729 doubles */
+  int32_t boundary;          /* the spec's boundary                                  */
 } lts_mesh_info;
 
 typedef struct lts_mesh lts_mesh;
@@ -160,6 +170,8 @@ typedef struct {
 
 typedef struct {
   double ko_sigma;           /* Kreiss-Oliger strength (0.1 default)                */
+  double nl_coeff;           /* LTS_EQ_NLWAVE: coefficient c of the source (1 in   */
+                             /* the paper's runs, 0 gives the linear wave)          */
 } lts_rhs_params;
 
 /* ---- errors ---------------------------------------------------------------- */
@@ -263,14 +275,29 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
 /* Bind caller-owned device arrays (see lts_stage_view).  U[0] must hold the
  * initial state; the sim's coarse-step counter is reset to 0. */
 lts_status lts_sim_bind(lts_sim* sim, void* U, void* K);
-/* Advance n coarse steps (T += n dt_lmin) with the fused kernels.  use_graph != 0
- * captures one coarse step in a hipGraph on first use and replays it. */
-lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t use_graph,
+/* Flags of lts_advance. */
+enum {
+  LTS_ADVANCE_GRAPH = 1,         /* capture one coarse step in a hipGraph on first use, replay it */
+  LTS_ADVANCE_CHECK_FINITE = 2   /* count non-finite values written by the RK updates of these
+                                    steps (inside the last stage's kernels), synchronise the
+                                    stream at the end and return LTS_ENONFINITE if any */
+};
+/* Advance n coarse steps (T += n dt_lmin) with the fused kernels (Alg. 1 / Alg. 2).
+ * flags: LTS_ADVANCE_* (1 alone = graph, the former use_graph != 0).  Without
+ * LTS_ADVANCE_CHECK_FINITE the call is asynchronous. */
+lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t flags,
                        void* stream);
 /* Same with the unfused phase kernels (unzip, rhs, zip, rk_stage). */
 lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, void* stream);
 /* Gather the current state of every octant into out ([F][N][125] doubles). */
 lts_status lts_sim_current(lts_sim* sim, double* out, void* stream);
+/* Restart from a checkpoint taken at a coarse-step boundary: `state` (device,
+ * [F][N][125] doubles, as lts_sim_current returns it) becomes the state of every
+ * octant after `coarse_step` coarse steps in `mode`; the sim's counter is set to
+ * it.  Continuing from here gives bitwise the results of the uninterrupted run
+ * (nothing of an earlier coarse step is read after its end: every level starts
+ * a step at substep 0).  LTS_EINVAL for a sim attached to a batch. */
+lts_status lts_sim_restore(lts_sim* sim, const double* state, int64_t coarse_step, int32_t mode, void* stream);
 int64_t lts_sim_coarse_step(const lts_sim* sim);
 void lts_sim_destroy(lts_sim* sim);
 
@@ -320,6 +347,32 @@ void lts_batch_destroy(lts_batch* batch);
  * (create, attach, run graph-captured rounds until drained, destroy). */
 lts_status lts_batch_advance(lts_sim* const* sims, int32_t n, int64_t n_coarse_steps,
                              int32_t mode, void* stream);
+
+/* ---- remeshing at a coarse-step boundary (Sec. 3.2.2, Sec. 5) -------------------------
+ * The octree follows the wavelet criterion: the wavelet indicator of an octant
+ * is the largest |v - I2 v| over fields and over its nodes off the every-second-
+ * node grid, I2 the tensor degree-2 Lagrange interpolant of its 27 nodes at
+ * positions 0, 2, 4 (the failure to be interpolated from one level coarser).
+ * `state` is a device array [F][N][125] (lts_sim_current's layout). */
+/* Host arrays of N doubles: the indicator of every leaf, and at the first leaf of
+ * every complete family of 8 same-level siblings the indicator of their parent
+ * (whose nodes are nodes of the children), -1 at the other leaves.  Synchronises. */
+lts_status lts_remesh_indicators(lts_mesh* mesh, int32_t nfields, const double* state, double* leaf_ind,
+                                 double* family_ind, void* stream);
+/* The new octree: a leaf of level < l_max splits where its indicator exceeds eps,
+ * a family of level > l_min none of whose leaves splits merges where its parent's
+ * indicator is below eps / 4; then the ghost-reach balance.  Same coordinates (L),
+ * domain and block cap as `mesh`; free *out with lts_mesh_destroy.  Synchronises. */
+lts_status lts_remesh(lts_mesh* mesh, int32_t nfields, const double* state, double eps, int32_t l_min,
+                      int32_t l_max, lts_mesh** out, void* stream);
+/* Intergrid transfer of a state between meshes of one domain whose leaves nest:
+ * a leaf of `to` inside a leaf of `from` takes the tensor degree-4 Lagrange
+ * interpolant of that leaf at its nodes (a copy at equal levels); a leaf of `to`
+ * that is the union of 8 leaves of `from` one level finer takes their coincident
+ * nodes.  state_to: device [F][N_to][125].  LTS_EINVAL if the meshes do not nest
+ * that way.  Synchronises. */
+lts_status lts_transfer(lts_mesh* from, lts_mesh* to, int32_t nfields, const double* state_from, double* state_to,
+                        void* stream);
 
 /* ---- reductions ----------------------------------------------------------------- */
 /* Per field volume-weighted l2 and max norm of (a - b) over all DG nodes (b may

@@ -249,3 +249,38 @@ def norms(err: np.ndarray, levels: np.ndarray, L: int):
     l2 = np.sqrt((e2 * w[None, :]).sum(axis=1) / (125.0 * w.sum()))
     linf = np.abs(err).reshape(err.shape[0], -1).max(axis=1)
     return l2, linf
+
+
+def nlwave_radial(profile, T: float, r_max: float = 2.0, n: int = 2000, c_nl: float = 1.0):
+    """Spherically symmetric solution of the non-linear wave (Sec. 4.2, eqs. lsm,
+    chi, phi) from chi(r, 0) = profile(r), chi_t(r, 0) = 0, by a method independent
+    of the octree solver: with u = r chi the radial equation reads
+        u_tt = u_rr - c sin(2 u / r) / r,   u odd in r (u(0) = 0),
+    discretised with sixth-order centred differences on r_i = i dr (odd reflection
+    at r = 0, zero beyond r_max, which the data must not reach by T) and classic RK4
+    with dt = dr / 4.  Returns (r, chi(r, T)) on the grid r_i, i >= 1."""
+    dr = r_max / n
+    r = dr * np.arange(n + 1)
+    u = r * profile(r)
+    u[0] = 0.0
+    w = np.zeros_like(u)
+    c2 = np.array([1 / 90, -3 / 20, 3 / 2, -49 / 18, 3 / 2, -3 / 20, 1 / 90])
+
+    def acc(u):
+        ext = np.concatenate([-u[3:0:-1], u, np.zeros(3)])        # odd at r = 0
+        urr = sum(c2[k] * ext[k:k + n + 1] for k in range(7)) / (dr * dr)
+        src = np.zeros_like(u)
+        src[1:] = np.sin(2.0 * u[1:] / r[1:]) / r[1:]
+        return urr - c_nl * src
+
+    dt = dr / 4.0
+    steps = int(round(T / dt))
+    assert abs(steps * dt - T) < 1e-12 * max(T, 1.0)
+    for _ in range(steps):
+        k1u, k1w = w, acc(u)
+        k2u, k2w = w + 0.5 * dt * k1w, acc(u + 0.5 * dt * k1u)
+        k3u, k3w = w + 0.5 * dt * k2w, acc(u + 0.5 * dt * k2u)
+        k4u, k4w = w + dt * k3w, acc(u + dt * k3u)
+        u = u + dt / 6.0 * (k1u + 2 * k2u + 2 * k3u + k4u)
+        w = w + dt / 6.0 * (k1w + 2 * k2w + 2 * k3w + k4w)
+    return r[1:], u[1:] / r[1:]

@@ -20,7 +20,9 @@ Paper passages:
   * Sec. 3.7, eqs. w_nuts, w_uts, invS: speedup model.
 
 Geometry (integer "node units" at the finest level L of the spec):
-  domain [-1, 1]^3, periodic; N_u = 4 * 2^L node units per side, x = -1 + 2 X / N_u.
+  domain [-1, 1]^3, periodic (default) or bounded by the outer faces (boundary
+  "outer", the radiative boundary of Sec. 4.2); N_u = 4 * 2^L node units per
+  side, x = -1 + 2 X / N_u.
   A leaf has an anchor a (in level-L octant units, a multiple of s = 2^(L-l)) and a
   level l; its 5 nodes per axis sit at 4 a + i s, i = 0..4; spacing h_l = 2^(-l-1).
 """
@@ -35,7 +37,7 @@ from scipy.ndimage import maximum_filter1d
 NODES = 5          # nodes per octant side
 GHOST = 3          # ghost layers of the sixth-order stencils
 
-KIND_OWN, KIND_SAME, KIND_FINE, KIND_COARSE = 0, 1, 2, 3
+KIND_OWN, KIND_SAME, KIND_FINE, KIND_COARSE, KIND_NONE = 0, 1, 2, 3, 4   # NONE: outside the domain
 
 
 # ----------------------------------------------------------------------------- Morton
@@ -76,6 +78,11 @@ class MeshSpec:
     l_max: int
     criteria: List[Criterion] = field(default_factory=list)
     block_cap: int = 4
+    boundary: str = "periodic"      # "periodic" or "outer"
+
+    @property
+    def periodic(self) -> bool:
+        return self.boundary == "periodic"
 
     @staticmethod
     def from_dict(d: dict) -> "MeshSpec":
@@ -84,7 +91,10 @@ class MeshSpec:
             crit.append(Criterion(kind=c["kind"], center=tuple(int(v) for v in c["center"]),
                                   r2=tuple(c.get("r2", ())), rlo2=tuple(c.get("rlo2", ())),
                                   rhi2=tuple(c.get("rhi2", ()))))
-        return MeshSpec(int(d["l_min"]), int(d["l_max"]), crit, int(d.get("block_cap", 4)))
+        b = d.get("boundary", "periodic")
+        if b not in ("periodic", "outer"):
+            raise ValueError(f"unknown boundary {b}")
+        return MeshSpec(int(d["l_min"]), int(d["l_max"]), crit, int(d.get("block_cap", 4)), b)
 
 
 def _periodic_min_dist(lo, hi, c, n):
@@ -117,8 +127,9 @@ def _periodic_max_dist(lo, hi, c, n):
     return np.where(inside, n // 2, ends)
 
 
-def criterion_holds(crit: Criterion, anchors: np.ndarray, level: int, L: int) -> np.ndarray:
-    """Evaluate a criterion for leaves of one level (Sec. 3.2.2, reading in module doc)."""
+def criterion_holds(crit: Criterion, anchors: np.ndarray, level: int, L: int, periodic: bool = True) -> np.ndarray:
+    """Evaluate a criterion for leaves of one level (Sec. 3.2.2, reading in module doc).
+    Distances are periodic (nearest image) or, for a bounded domain, plain."""
     if len(anchors) == 0:
         return np.zeros(0, dtype=bool)
     n = 4 * (1 << L)
@@ -126,7 +137,10 @@ def criterion_holds(crit: Criterion, anchors: np.ndarray, level: int, L: int) ->
     lo = 4 * anchors.astype(np.int64)
     hi = lo + 4 * s
     c = np.asarray(crit.center, dtype=np.int64)[None, :]
-    dmin2 = (_periodic_min_dist(lo, hi, c, n) ** 2).sum(axis=1)
+    if periodic:
+        dmin2 = (_periodic_min_dist(lo, hi, c, n) ** 2).sum(axis=1)
+    else:
+        dmin2 = (np.maximum(0, np.maximum(lo - c, c - hi)) ** 2).sum(axis=1)
     if crit.kind == "ball":
         r2 = crit.r2[level] if level < len(crit.r2) else -1
         if r2 < 0:
@@ -137,7 +151,10 @@ def criterion_holds(crit: Criterion, anchors: np.ndarray, level: int, L: int) ->
         rhi2 = crit.rhi2[level] if level < len(crit.rhi2) else -1
         if rhi2 < 0:
             return np.zeros(len(anchors), dtype=bool)
-        dmax2 = (_periodic_max_dist(lo, hi, c, n) ** 2).sum(axis=1)
+        if periodic:
+            dmax2 = (_periodic_max_dist(lo, hi, c, n) ** 2).sum(axis=1)
+        else:
+            dmax2 = (np.maximum(np.abs(lo - c), np.abs(hi - c)) ** 2).sum(axis=1)
         return (rlo2 < dmax2) & (dmin2 < rhi2)
     raise ValueError(f"unknown criterion kind {crit.kind}")
 
@@ -179,7 +196,7 @@ def refine(spec: MeshSpec) -> Tuple[np.ndarray, np.ndarray]:
             break
         split = np.zeros(len(cur), dtype=bool)
         for crit in spec.criteria:
-            split |= criterion_holds(crit, cur, lev, L)
+            split |= criterion_holds(crit, cur, lev, L, spec.periodic)
         keep_a.append(cur[~split]); keep_l.append(np.full(int((~split).sum()), lev, np.int64))
         cur = _children(cur[split], lev, L)
         if len(cur) == 0:
@@ -201,18 +218,21 @@ def level_grid(anchors: np.ndarray, levels: np.ndarray, L: int) -> np.ndarray:
     return g
 
 
-def _window_max(grid: np.ndarray, s: int) -> np.ndarray:
+def _window_max(grid: np.ndarray, s: int, periodic: bool = True) -> np.ndarray:
     """max over cells [a-1-f, a+s+f]^3 around every anchor a, f = floor(3 s / 4).
 
     These are exactly the level-L cells whose closed box meets the closed box of a
     level-l leaf (width 4 s node units) grown by 3 h_l = 3 s node units.  A centred
-    window of even size s + 2f + 2 read at a + s/2 covers that range.
+    window of even size s + 2f + 2 read at a + s/2 covers that range.  A bounded
+    domain has no cells beyond its faces (padding -1 is below every level).
     """
     f = (3 * s) // 4
     size = s + 2 * f + 2
     out = grid
     for ax in range(3):
-        if size >= out.shape[ax]:
+        if not periodic:
+            out = maximum_filter1d(out, size=size, axis=ax, mode="constant", cval=-1)
+        elif size >= out.shape[ax]:
             # the window covers the whole period: the axis-wise maximum
             out = np.broadcast_to(out.max(axis=ax, keepdims=True), out.shape).copy()
         else:
@@ -220,7 +240,7 @@ def _window_max(grid: np.ndarray, s: int) -> np.ndarray:
     return out
 
 
-def balance(anchors: np.ndarray, levels: np.ndarray, L: int) -> Tuple[np.ndarray, np.ndarray]:
+def balance(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = True) -> Tuple[np.ndarray, np.ndarray]:
     """Ghost-reach balance (Sec. 3.2.3 extended): split any leaf a of level l for
     which some leaf of level >= l+2 has periodic Chebyshev box distance <= 3 h_l.
 
@@ -240,7 +260,7 @@ def balance(anchors: np.ndarray, levels: np.ndarray, L: int) -> Tuple[np.ndarray
             if len(sel) == 0:
                 continue
             s = 1 << (L - lev)
-            wm = _window_max(grid, s)
+            wm = _window_max(grid, s, periodic)
             pos = (anchors[sel] + s // 2) % n
             mx = wm[pos[:, 0], pos[:, 1], pos[:, 2]]
             split_mask[sel[mx >= lev + 2]] = True
@@ -257,7 +277,7 @@ def balance(anchors: np.ndarray, levels: np.ndarray, L: int) -> Tuple[np.ndarray
             return anchors, levels
 
 
-def is_balanced_bruteforce(anchors: np.ndarray, levels: np.ndarray, L: int) -> bool:
+def is_balanced_bruteforce(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = True) -> bool:
     """O(N^2) check of the balance predicate (for small meshes in tests)."""
     n = 4 * (1 << L)
     lo = 4 * anchors.astype(np.int64)
@@ -269,7 +289,7 @@ def is_balanced_bruteforce(anchors: np.ndarray, levels: np.ndarray, L: int) -> b
         if not cand.any():
             continue
         gap = np.zeros((int(cand.sum()), 3), dtype=np.int64) + 10 ** 9
-        for k in (-1, 0, 1):
+        for k in ((-1, 0, 1) if periodic else (0,)):
             g = np.maximum(0, np.maximum(lo[cand] + k * n - hi[a], lo[a] - (hi[cand] + k * n)))
             gap = np.minimum(gap, g)
         if (gap.max(axis=1) <= 3 * h).any():
@@ -285,6 +305,7 @@ class Mesh:
     levels: np.ndarray          # [N]
     blocks: np.ndarray          # [B, 6] first_leaf, m, level, ax, ay, az (level-L units)
     cap: int
+    periodic: bool = True       # False: bounded by the outer faces of [-1, 1]^3
 
     @property
     def n_oct(self) -> int:
@@ -310,9 +331,11 @@ class Mesh:
 
     def find(self, level: int, cell) -> int:
         """Leaf index of the octant at `level` with level-`level` coordinates `cell`
-        (wrapped periodically), or -1."""
+        (wrapped periodically; outside a bounded domain: -1), or -1."""
         n = 1 << level
         s = 1 << (self.L - level)
+        if not self.periodic and any(int(v) < 0 or int(v) >= n for v in cell):
+            return -1
         key = (level, (int(cell[0]) % n) * s, (int(cell[1]) % n) * s, (int(cell[2]) % n) * s)
         return self._lookup.get(key, -1)
 
@@ -363,19 +386,19 @@ def build_blocks(anchors: np.ndarray, levels: np.ndarray, L: int, cap: int) -> n
 def build_mesh(spec: MeshSpec) -> Mesh:
     """Refinement, balance, blocks (Sec. 3.2.2 -> 3.2.3 -> 3.2.5)."""
     a, l = refine(spec)
-    a, l = balance(a, l, spec.l_max)
+    a, l = balance(a, l, spec.l_max, spec.periodic)
     blk = build_blocks(a, l, spec.l_max, spec.block_cap)
-    return Mesh(spec.l_max, a, l, blk, spec.block_cap)
+    return Mesh(spec.l_max, a, l, blk, spec.block_cap, spec.periodic)
 
 
-def mesh_from_leaves(anchors, levels, L: int, cap: int = 4, do_balance: bool = True) -> Mesh:
+def mesh_from_leaves(anchors, levels, L: int, cap: int = 4, do_balance: bool = True, periodic: bool = True) -> Mesh:
     a = np.asarray(anchors, dtype=np.int64).reshape(-1, 3)
     l = np.asarray(levels, dtype=np.int64).reshape(-1)
     a, l = _sort(a, l)
     level_grid(a, l, L)  # validates the tiling
     if do_balance:
-        a, l = balance(a, l, L)
-    return Mesh(L, a, l, build_blocks(a, l, L, cap), cap)
+        a, l = balance(a, l, L, periodic)
+    return Mesh(L, a, l, build_blocks(a, l, L, cap), cap, periodic)
 
 
 # ----------------------------------------------------------------------------- unzip map
@@ -406,7 +429,9 @@ def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
       * 8 leaves one level finer (FINE): child c = min(nu >> 1, 1) per axis, fine
         node 2 (nu - 2c)  (injection of the coincident fine node);
       * one octant (child bits beta) of a leaf one level coarser (COARSE): position
-        (4 beta + nu) / 2 in its node units (interpolated when odd).
+        (4 beta + nu) / 2 in its node units (interpolated when odd);
+      * on a bounded domain, a cell beyond the outer faces (NONE, leaf -1): the
+        block's stencils there switch to the boundary closure and read no value.
     """
     first, m, lev = int(mesh.blocks[b, 0]), int(mesh.blocks[b, 1]), int(mesh.blocks[b, 2])
     s = 1 << (mesh.L - lev)
@@ -419,11 +444,21 @@ def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
     nu = Q - 4 * cell
     out = np.zeros((S ** 3, 5), dtype=np.int64)
     inside = ((cell >= 0) & (cell <= m - 1)).all(axis=1)
+    if not mesh.periodic:
+        # a bounded domain: points beyond its outer faces have no source
+        n = 1 << lev
+        gc = base[None, :] + cell
+        outside = ((gc < 0) | (gc >= n)).any(axis=1)
+        out[outside, 0] = -1
+        out[outside, 1] = KIND_NONE
+        out[outside, 2:5] = 2 * nu[outside]
+    else:
+        outside = np.zeros(len(Q), dtype=bool)
     oc = cell[inside]
     out[inside, 0] = first + morton_key(oc[:, 0], oc[:, 1], oc[:, 2])
     out[inside, 1] = KIND_OWN
     out[inside, 2:5] = 2 * nu[inside]
-    gi = np.nonzero(~inside)[0]
+    gi = np.nonzero(~inside & ~outside)[0]
     cells = base[None, :] + cell[gi]
     nug = nu[gi]
     uniq, inv = np.unique(cells, axis=0, return_inverse=True)

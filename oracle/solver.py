@@ -35,7 +35,7 @@ from typing import Dict, List, Optional
 import numpy as np
 
 from . import fd
-from .octree import (GHOST, KIND_COARSE, KIND_OWN, NODES, Mesh, active_blocks, block_octants,
+from .octree import (GHOST, KIND_COARSE, KIND_NONE, KIND_OWN, NODES, Mesh, active_blocks, block_octants,
                      dt_level, substeps, unzip_map)
 from .rk import CASES, TABLEAUS, a_f64, b_f64, weight_table_f64
 
@@ -119,14 +119,17 @@ class State:
         mesh = self.mesh
         mp = self.map(b)
         leaf, kind, pos2 = mp[:, 0], mp[:, 1], mp[:, 2:5]
-        srcb = mesh.block_of_leaf[leaf]
+        # points beyond a bounded domain's faces have no source (the block itself
+        # stands in for the bookkeeping; their value is never read)
+        srcb = np.where(kind == KIND_NONE, b, mesh.block_of_leaf[np.maximum(leaf, 0)])
         ub, inv = np.unique(srcb, return_inverse=True)
-        direct = np.nonzero(kind != KIND_COARSE)[0]
+        direct = np.nonzero((kind != KIND_COARSE) & (kind != KIND_NONE))[0]
         n = pos2[direct] // 2
         flat = leaf[direct] * 125 + n[:, 2] * 25 + n[:, 1] * 5 + n[:, 0]
         coarse = np.nonzero(kind == KIND_COARSE)[0]
         pl = dict(m=int(mesh.blocks[b, 1]), leaf=leaf, kind=kind, pos2=pos2, srcb=srcb, ub=ub,
                   inv=inv.reshape(-1), direct=direct, flat=flat, coarse=coarse,
+                  none=np.nonzero(kind == KIND_NONE)[0],
                   lag=[LAGRANGE[pos2[coarse, d]] for d in range(3)],
                   octs=block_octants(mesh, b))
         self._plans[b] = pl
@@ -150,6 +153,7 @@ class State:
         dt = self.dt_phys(b)
         w = self.W[cases, s]                               # [P, p]
         out = np.empty((self.F, S ** 3))
+        out[:, pl["none"]] = 0.0
         d = pl["direct"]
         if len(d):
             Uf = self.U.reshape(2, self.F, -1)
@@ -205,12 +209,21 @@ class State:
             self.cur_par[b] = 1 - self.rec_par[b]
             self.cur_t[b] = self.rec_t0[b] + self.dt_ticks[b]
 
+    def geometry(self, b: int) -> dict:
+        """Block grid of b in node units: origin X0 (x, y, z), step w, domain side
+        Nu, and whether the domain is periodic (for equations that need positions
+        or the outer boundary)."""
+        mesh = self.mesh
+        lev = int(mesh.blocks[b, 2])
+        return {"X0": 4 * mesh.blocks[b, 3:6].astype(np.int64), "w": 1 << (mesh.L - lev),
+                "Nu": 4 << mesh.L, "periodic": mesh.periodic}
+
     def stage(self, act, s: int, rhs, sigma: float):
         """Stage s of every block of B_j: unzip, block RHS, zip into K_s."""
         for b in act:
             pad = self.unzip(b, s)
             h = 2.0 ** (-int(self.mesh.blocks[b, 2]) - 1)     # block grid spacing h_lam
-            grid = rhs(pad, h, sigma)
+            grid = rhs(pad, h, sigma, self.geometry(b))
             self.zip_into(b, grid, self.K[s])
 
     def rk_update(self, act):
@@ -233,13 +246,17 @@ class State:
         self.close_records(act)
 
 
-EQ = {"wave": (2, fd.rhs_wave), "maxwell": (6, fd.rhs_maxwell)}
+EQ = {"wave": (2, fd.rhs_wave), "maxwell": (6, fd.rhs_maxwell), "nlwave": (2, fd.rhs_nlwave)}
 
 
 def run(mesh: Mesh, U0: np.ndarray, n_coarse: int, mode: str = "lts", equation: str = "wave",
-        tableau: str = "rk4", sigma: float = 0.1, return_state: bool = False):
-    """Advance U0 ([F][N][5][5][5]) by n_coarse coarsest steps (T = n_coarse dt_lmin)."""
+        tableau: str = "rk4", sigma: float = 0.1, return_state: bool = False, nl_coeff: float = 1.0):
+    """Advance U0 ([F][N][5][5][5]) by n_coarse coarsest steps (T = n_coarse dt_lmin).
+    nl_coeff: the coefficient c of the non-linear source (equation "nlwave")."""
     F, rhs = EQ[equation]
+    if equation == "nlwave":
+        def rhs(pad, h, sg, geo, _c=nl_coeff):
+            return fd.rhs_nlwave(pad, h, sg, geo, _c)
     st = State(mesh, F, tableau, mode)
     st.set_initial(U0)
     nsub = substeps(mesh)

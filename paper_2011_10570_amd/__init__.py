@@ -13,16 +13,20 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib as _L
-from ._lib import (CRIT_ANNULUS, CRIT_BALL, EQ_MAXWELL, EQ_WAVE, FP32_RHS, FP64, MODE_GTS, MODE_LTS, RK4,
+from ._lib import (BOUNDARY_OUTER, BOUNDARY_PERIODIC, CRIT_ANNULUS, CRIT_BALL, EQ_MAXWELL, EQ_NLWAVE, EQ_WAVE,
+                   FP32_RHS, FP64, MODE_GTS, MODE_LTS, RK4,
                    SSPRK3, LTSError, check, lib)
 
 __all__ = ["Mesh", "Sim", "build_mesh", "unzip", "rhs", "zip", "rk_stage", "fused_stage", "coefficients",
-           "norms", "copy_probe", "LTSError", "MODE_LTS", "MODE_GTS", "EQ_WAVE", "EQ_MAXWELL", "FP64", "FP32_RHS",
-           "RK4", "SSPRK3", "Batch", "batch_advance", "set_launch", "get_launch", "fused_stage_noalloc"]
+           "norms", "copy_probe", "LTSError", "MODE_LTS", "MODE_GTS", "EQ_WAVE", "EQ_MAXWELL", "EQ_NLWAVE",
+           "BOUNDARY_PERIODIC", "BOUNDARY_OUTER", "FP64", "FP32_RHS",
+           "RK4", "SSPRK3", "Batch", "batch_advance", "set_launch", "get_launch", "fused_stage_noalloc",
+           "remesh_indicators", "remesh", "transfer"]
 
-EQUATIONS = {"wave": EQ_WAVE, "maxwell": EQ_MAXWELL}
+EQUATIONS = {"wave": EQ_WAVE, "maxwell": EQ_MAXWELL, "nlwave": EQ_NLWAVE}
+BOUNDARIES = {"periodic": BOUNDARY_PERIODIC, "outer": BOUNDARY_OUTER}
 TABLEAUS = {"rk4": RK4, "ssprk3": SSPRK3}
-NFIELDS = {EQ_WAVE: 2, EQ_MAXWELL: 6}
+NFIELDS = {EQ_WAVE: 2, EQ_MAXWELL: 6, EQ_NLWAVE: 2}
 NSTAGES = {RK4: 4, SSPRK3: 3}
 
 
@@ -48,9 +52,11 @@ def _ptr(t) -> Optional[int]:
 class Mesh:
     """Octree mesh (leaves, blocks, tiles, ghost tables) built by the library's host code."""
 
-    def __init__(self, spec: Optional[dict] = None, leaves=None, L: Optional[int] = None, block_cap: int = 4):
+    def __init__(self, spec: Optional[dict] = None, leaves=None, L: Optional[int] = None, block_cap: int = 4,
+                 boundary: str = "periodic"):
         cs = _L.MeshSpecC()
         keep = []
+        cs.boundary = BOUNDARIES[spec.get("boundary", "periodic") if spec is not None else boundary]
         if leaves is not None:
             arr = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
             keep.append(arr)
@@ -79,6 +85,13 @@ class Mesh:
         h = C.c_void_p()
         check(lib().lts_build_mesh(C.byref(cs), C.byref(h)), "lts_build_mesh")
         self.h = h
+
+    @classmethod
+    def _wrap(cls, h) -> "Mesh":
+        """A Mesh owning a handle the library built (lts_remesh)."""
+        obj = cls.__new__(cls)
+        obj.h = h
+        return obj
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -178,10 +191,17 @@ def unzip(mesh: Mesh, U, K, stage: int, substep: int, mode: int, coarse_step: in
           "lts_unzip")
 
 
-def rhs(mesh: Mesh, equation: int, ko_sigma: float, padded, precision: int, blocks, k_block, stream=None):
-    b, nb, keep = _blocks_arg(blocks)
+def _params(ko_sigma: float, nl_coeff: float = 1.0):
     prm = _L.RhsParams()
     prm.ko_sigma = ko_sigma
+    prm.nl_coeff = nl_coeff
+    return prm
+
+
+def rhs(mesh: Mesh, equation: int, ko_sigma: float, padded, precision: int, blocks, k_block, stream=None,
+        nl_coeff: float = 1.0):
+    b, nb, keep = _blocks_arg(blocks)
+    prm = _params(ko_sigma, nl_coeff)
     check(lib().lts_rhs(mesh.h, equation, C.byref(prm), _ptr(padded), precision, b, nb, _ptr(k_block),
                         _stream_ptr(stream)), "lts_rhs")
 
@@ -203,24 +223,51 @@ def rk_stage(mesh: Mesh, U, K, coef: Sequence[float], substep: int, mode: int, c
 
 
 def fused_stage(mesh: Mesh, U, K, equation: int, ko_sigma: float, stage: int, substep: int, mode: int,
-                coarse_step: int, precision: int = FP64, tableau: int = RK4, stream=None):
+                coarse_step: int, precision: int = FP64, tableau: int = RK4, stream=None, nl_coeff: float = 1.0):
     v = _view(U, K, NFIELDS[equation], precision, tableau)
-    prm = _L.RhsParams()
-    prm.ko_sigma = ko_sigma
+    prm = _params(ko_sigma, nl_coeff)
     p = _pos(substep, mode, coarse_step)
     check(lib().lts_fused_stage(mesh.h, C.byref(v), equation, C.byref(prm), stage, C.byref(p), _stream_ptr(stream)),
           "lts_fused_stage")
 
 
 def fused_stage_noalloc(mesh: Mesh, U, K, equation: int, ko_sigma: float, stage: int, substep: int, mode: int,
-                        coarse_step: int, precision: int = FP64, tableau: int = RK4, stream=None):
+                        coarse_step: int, precision: int = FP64, tableau: int = RK4, stream=None,
+                        nl_coeff: float = 1.0):
     """lts_fused_stage_noalloc: the fused stage with the library's fixed device scratch."""
     v = _view(U, K, NFIELDS[equation], precision, tableau)
-    prm = _L.RhsParams()
-    prm.ko_sigma = ko_sigma
+    prm = _params(ko_sigma, nl_coeff)
     p = _pos(substep, mode, coarse_step)
     check(lib().lts_fused_stage_noalloc(mesh.h, C.byref(v), equation, C.byref(prm), stage, C.byref(p),
                                         _stream_ptr(stream)), "lts_fused_stage_noalloc")
+
+
+def remesh_indicators(mesh: Mesh, state, nfields: int = 2, stream=None):
+    """lts_remesh_indicators: (leaf indicator [N], family indicator [N], -1 where a
+    leaf does not start a complete sibling family) of a device state [F][N][125]."""
+    N = mesh.info()["n_oct"]
+    lw = np.zeros(N)
+    fw = np.zeros(N)
+    check(lib().lts_remesh_indicators(mesh.h, nfields, _ptr(state), lw.ctypes.data_as(C.POINTER(C.c_double)),
+                                      fw.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)),
+          "lts_remesh_indicators")
+    return lw, fw
+
+
+def remesh(mesh: Mesh, state, eps: float, l_min: int, l_max: int, nfields: int = 2, stream=None) -> Mesh:
+    """lts_remesh: the new octree of a state at a coarse-step boundary."""
+    h = C.c_void_p()
+    check(lib().lts_remesh(mesh.h, nfields, _ptr(state), float(eps), int(l_min), int(l_max), C.byref(h),
+                           _stream_ptr(stream)), "lts_remesh")
+    return Mesh._wrap(h)
+
+
+def transfer(src: Mesh, dst: Mesh, state, nfields: int = 2, stream=None):
+    """lts_transfer: the state [F][N_src][125] (device) carried to dst's leaves."""
+    import torch
+    out = torch.empty((nfields, dst.info()["n_oct"], 125), dtype=torch.float64, device=state.device)
+    check(lib().lts_transfer(src.h, dst.h, nfields, _ptr(state), _ptr(out), _stream_ptr(stream)), "lts_transfer")
+    return out
 
 
 def norms(mesh: Mesh, a, b=None, nfields: int = 2, stream=None) -> dict:
@@ -253,7 +300,8 @@ class Sim:
     """One simulation: device state U [2][F][N][125] (float64) and stages K
     [p][F][N][125] (float64, or float32 in FP32-RHS mode) as torch tensors."""
 
-    def __init__(self, mesh: Mesh, equation="wave", precision=FP64, tableau="rk4", ko_sigma=0.1, device="cuda"):
+    def __init__(self, mesh: Mesh, equation="wave", precision=FP64, tableau="rk4", ko_sigma=0.1, device="cuda",
+                 nl_coeff: float = 1.0):
         import torch
         self.mesh = mesh
         self.eq = EQUATIONS[equation] if isinstance(equation, str) else int(equation)
@@ -261,8 +309,7 @@ class Sim:
         self.prec = int(precision)
         self.F = NFIELDS[self.eq]
         self.p = NSTAGES[self.tab]
-        prm = _L.RhsParams()
-        prm.ko_sigma = ko_sigma
+        prm = _params(ko_sigma, nl_coeff)
         self.ko_sigma = ko_sigma
         h = C.c_void_p()
         check(lib().lts_sim_create(mesh.h, self.eq, self.prec, self.tab, C.byref(prm), C.byref(h)), "lts_sim_create")
@@ -273,6 +320,7 @@ class Sim:
         kdt = torch.float32 if self.prec == FP32_RHS else torch.float64
         self.K = torch.zeros((self.p, self.F, N, 125), dtype=kdt, device=device)
         check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
+        self._mode = MODE_LTS
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -292,12 +340,46 @@ class Sim:
         self.U[0].copy_(t.reshape(self.F, self.N, 125).to(self.U.device))
         check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
 
-    def advance(self, n_coarse: int, mode: int = MODE_LTS, graph: bool = True, stream=None):
-        check(lib().lts_advance(self.h, int(n_coarse), int(mode), 1 if graph else 0, _stream_ptr(stream)),
-              "lts_advance")
+    def advance(self, n_coarse: int, mode: int = MODE_LTS, graph: bool = True, stream=None, check_finite=False):
+        """n coarse steps; with check_finite the call synchronises and raises
+        LTSError (status LTS_ENONFINITE) if an RK update wrote a NaN or Inf."""
+        flags = (_L.ADVANCE_GRAPH if graph else 0) | (_L.ADVANCE_CHECK_FINITE if check_finite else 0)
+        check(lib().lts_advance(self.h, int(n_coarse), int(mode), flags, _stream_ptr(stream)), "lts_advance")
+        self._mode = int(mode)
+
+    def checkpoint(self, stream=None) -> dict:
+        """State at the current coarse-step boundary (host arrays, no pickling)."""
+        return {"state": self.current(stream).cpu().numpy(), "coarse_step": self.coarse_step,
+                "mode": int(self._mode), "equation": int(self.eq), "tableau": int(self.tab),
+                "precision": int(self.prec)}
+
+    def restore(self, ckpt: dict, stream=None):
+        """Continue from a checkpoint (bitwise the uninterrupted run)."""
+        import torch
+        for k in ("equation", "tableau", "precision"):
+            if int(ckpt[k]) != int(getattr(self, {"equation": "eq", "tableau": "tab", "precision": "prec"}[k])):
+                raise ValueError(f"checkpoint {k} differs from the sim's")
+        st = torch.as_tensor(np.asarray(ckpt["state"]), dtype=torch.float64).to(self.U.device).contiguous()
+        self.U.zero_()
+        self.K.zero_()
+        check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
+        check(lib().lts_sim_restore(self.h, _ptr(st), int(ckpt["coarse_step"]), int(ckpt["mode"]),
+                                    _stream_ptr(stream)), "lts_sim_restore")
+        self._mode = int(ckpt["mode"])
+        self._keep = st      # the restore kernel reads it asynchronously
+
+    @staticmethod
+    def save_checkpoint(ckpt: dict, path: str):
+        np.savez(path, **{k: np.asarray(v) for k, v in ckpt.items()})
+
+    @staticmethod
+    def load_checkpoint(path: str) -> dict:
+        with np.load(path, allow_pickle=False) as z:
+            return {k: (z[k] if k == "state" else int(z[k])) for k in z.files}
 
     def advance_unfused(self, n_coarse: int, mode: int = MODE_LTS, stream=None):
         check(lib().lts_advance_unfused(self.h, int(n_coarse), int(mode), _stream_ptr(stream)), "lts_advance_unfused")
+        self._mode = int(mode)
 
     def current(self, stream=None):
         import torch

@@ -16,7 +16,9 @@ MAX_LEVEL = 16
 OK, EINVAL, ENOMEM, EDEVICE, EUNBALANCED, ENONFINITE, EUNSUPPORTED = range(7)
 CRIT_BALL, CRIT_ANNULUS = 0, 1
 MODE_LTS, MODE_GTS = 0, 1
-EQ_WAVE, EQ_MAXWELL = 0, 1
+EQ_WAVE, EQ_MAXWELL, EQ_NLWAVE = 0, 1, 2
+BOUNDARY_PERIODIC, BOUNDARY_OUTER = 0, 1
+ADVANCE_GRAPH, ADVANCE_CHECK_FINITE = 1, 2
 FP64, FP32_RHS = 0, 1
 RK4, SSPRK3 = 0, 1
 EXPORT_LEAVES, EXPORT_BLOCKS, EXPORT_UNZIP_MAP, EXPORT_SCHEDULE, EXPORT_TILES = range(5)
@@ -32,7 +34,8 @@ class Criterion(C.Structure):
 
 class MeshSpecC(C.Structure):
     _fields_ = [("l_min", C.c_int32), ("l_max", C.c_int32), ("block_cap", C.c_int32), ("n_criteria", C.c_int32),
-                ("criteria", C.POINTER(Criterion)), ("n_leaves", C.c_int64), ("leaves", C.POINTER(C.c_int32))]
+                ("criteria", C.POINTER(Criterion)), ("n_leaves", C.c_int64), ("leaves", C.POINTER(C.c_int32)),
+                ("boundary", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -40,7 +43,8 @@ class MeshInfo(C.Structure):
                 ("lmin", C.c_int32), ("lmax", C.c_int32), ("n_substeps", C.c_int32), ("tile", C.c_int32),
                 ("level_count", C.c_int64 * MAX_LEVEL), ("unzip_points", C.c_int64), ("grid_points", C.c_int64),
                 ("node_updates_lts", C.c_int64), ("node_updates_gts", C.c_int64), ("s_est", C.c_double),
-                ("s_max", C.c_double), ("table_bytes", C.c_int64), ("ghost_entries", C.c_int64)]
+                ("s_max", C.c_double), ("table_bytes", C.c_int64), ("ghost_entries", C.c_int64),
+                ("boundary", C.c_int32)]
 
 
 class StageView(C.Structure):
@@ -53,7 +57,7 @@ class Position(C.Structure):
 
 
 class RhsParams(C.Structure):
-    _fields_ = [("ko_sigma", C.c_double)]
+    _fields_ = [("ko_sigma", C.c_double), ("nl_coeff", C.c_double)]
 
 
 class BatchInfo(C.Structure):
@@ -90,6 +94,7 @@ PROTOTYPES = {
     "lts_advance": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P]),
     "lts_advance_unfused": (C.c_int, [_P, C.c_int64, C.c_int32, _P]),
     "lts_sim_current": (C.c_int, [_P, _P, _P]),
+    "lts_sim_restore": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P]),
     "lts_sim_coarse_step": (C.c_int64, [_P]),
     "lts_sim_destroy": (None, [_P]),
     "lts_batch_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]),
@@ -100,6 +105,9 @@ PROTOTYPES = {
     "lts_sim_rounds_left": (C.c_int64, [_P]),
     "lts_batch_destroy": (None, [_P]),
     "lts_batch_advance": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int64, C.c_int32, _P]),
+    "lts_remesh_indicators": (C.c_int, [_P, C.c_int32, _P, _DP, _DP, _P]),
+    "lts_remesh": (C.c_int, [_P, C.c_int32, _P, C.c_double, C.c_int32, C.c_int32, C.POINTER(_P), _P]),
+    "lts_transfer": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
     "lts_norms": (C.c_int, [_P, C.c_int32, _P, _P, _DP, _P]),
     "lts_copy_probe": (C.c_int, [_P, _P, C.c_size_t, _P]),
 }

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libltsmi.so")
 ARCH = os.environ.get("LTS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["mesh.cpp", "coeffs.cpp", "api.cpp", "k_fused.hip", "k_fused_batch.hip", "k_ghost.hip", "k_stream.hip",
+SOURCES = ["mesh.cpp", "coeffs.cpp", "remesh.cpp", "api.cpp", "k_fused.hip", "k_fused_batch.hip", "k_ghost.hip", "k_stream.hip",
            "k_phase.hip"]
 
 # -ffp-contract=on: a multiply-add is fused only inside one expression, so the

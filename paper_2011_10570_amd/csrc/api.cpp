@@ -76,6 +76,11 @@ static lts_status ensure_device(Mesh& m) {
   lts_status st;
   if ((st = upload_set(m.bt)) != LTS_OK) return st;
   if ((st = upload_fused_sets(m)) != LTS_OK) return st;
+  std::vector<int32_t> xyz(4 * (size_t)m.n());
+  for (int64_t i = 0; i < m.n(); ++i) {
+    xyz[4 * i] = m.ax[i]; xyz[4 * i + 1] = m.ay[i]; xyz[4 * i + 2] = m.az[i]; xyz[4 * i + 3] = m.lev[i];
+  }
+  if ((st = upload_vec(xyz, &m.d_leafxyz, "upload leaf anchors")) != LTS_OK) return st;
   m.uploaded = true;
   return LTS_OK;
 }
@@ -190,6 +195,29 @@ static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage,
     for (int i = 0; i < p; ++i) sp.w[c][i] = w[(c * p + stage) * p + i];
   for (int i = 0; i < p; ++i) sp.b[i] = b[i];
   set_kmask(sp);
+  sp.leafxyz = m.d_leafxyz;
+  sp.L = m.L;
+  sp.periodic = m.periodic ? 1 : 0;
+  sp.nl_coeff = 1.0;
+  return LTS_OK;
+}
+
+// Fields of an equation (0: unknown).
+static int equation_fields(int eq) {
+  return eq == LTS_EQ_WAVE || eq == LTS_EQ_NLWAVE ? 2 : (eq == LTS_EQ_MAXWELL ? 6 : 0);
+}
+
+// Equation / mesh / precision / tile combinations the fused kernels are built for.
+static lts_status check_combination(const Mesh& m, int eq, int prec, bool batch) {
+  if (!m.periodic && eq != LTS_EQ_NLWAVE)
+    return fail(LTS_EUNSUPPORTED, "a bounded mesh needs the non-linear wave equation (radiative boundary)");
+  if (eq == LTS_EQ_NLWAVE) {
+    if (prec != LTS_FP64) return fail(LTS_EUNSUPPORTED, "the non-linear wave runs in FP64");
+    if (m.ts[4].count() > 0) return fail(LTS_EUNSUPPORTED, "the non-linear wave needs tile side 1 or 2");
+    if (batch) return fail(LTS_EUNSUPPORTED, "the non-linear wave is not built for batched launches");
+  }
+  if (eq == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
+    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
   return LTS_OK;
 }
 
@@ -291,6 +319,7 @@ void lts_mesh_destroy(lts_mesh* mesh) {
   free_set(h->m.bt);
   for (int k : {1, 2, 4}) free_set(h->m.ts[k]);
   if (h->m.d_ghosts) (void)hipFree(h->m.d_ghosts);
+  if (h->m.d_leafxyz) (void)hipFree(h->m.d_leafxyz);
   if (h->x.d_cscr) (void)hipFree(h->x.d_cscr);
   if (h->m.d_off) (void)hipFree(h->m.d_off);
   if (h->x.d_step) (void)hipFree(h->x.d_step);
@@ -331,6 +360,7 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   tb += (int64_t)m.ghosts.size();
   info->table_bytes = 4 * tb;
   info->ghost_entries = (int64_t)(m.ghosts.size() / 2);
+  info->boundary = m.periodic ? LTS_BOUNDARY_PERIODIC : LTS_BOUNDARY_OUTER;
   info->node_updates_lts = wl;
   info->node_updates_gts = wg;
   // eq. invS with alpha_l = DG nodes at level lmax - l
@@ -448,17 +478,27 @@ lts_status lts_rhs(lts_mesh* mesh, int32_t equation, const lts_rhs_params* param
                    int32_t precision, const int32_t* blocks, int32_t nb, void* k_block, void* stream) {
   clear_error();
   if (!mesh || !padded || !k_block || !params) return fail(LTS_EINVAL, "NULL argument");
-  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (!equation_fields(equation)) return fail(LTS_EINVAL, "bad equation");
   if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
   if (!blocks) return fail(LTS_EINVAL, "lts_rhs needs an explicit block list");
   Mesh& m = mesh->m;
+  if (!m.periodic && equation != LTS_EQ_NLWAVE)
+    return fail(LTS_EUNSUPPORTED, "a bounded mesh needs the non-linear wave equation (radiative boundary)");
+  if (equation == LTS_EQ_NLWAVE && precision != LTS_FP64)
+    return fail(LTS_EUNSUPPORTED, "the non-linear wave runs in FP64");
   hipStream_t s = (hipStream_t)stream;
   lts_status st = ensure_device(m);
   if (st != LTS_OK) return st;
   ListDev L;
   if ((st = stage_list(m, blocks, nb, nullptr, s, L)) != LTS_OK) return st;
+  StageParams geo;
+  std::memset(&geo, 0, sizeof(geo));
+  geo.leafxyz = m.d_leafxyz;
+  geo.L = m.L;
+  geo.periodic = m.periodic ? 1 : 0;
+  geo.nl_coeff = params->nl_coeff;
   HIP_TRY(launch_rhs(equation, precision == LTS_FP32_RHS, m.bt.d_tiles, L.list, L.poff, L.ptotal, L.goff, L.gtotal,
-                     L.nb, padded, k_block, params->ko_sigma, s),
+                     L.nb, padded, k_block, params->ko_sigma, geo, s),
           "rhs launch");
   return LTS_OK;
 }
@@ -530,20 +570,19 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
                            const lts_rhs_params* params, int32_t stage, const lts_position* pos, void* stream) {
   clear_error();
   if (!mesh || !params) return fail(LTS_EINVAL, "NULL argument");
-  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (!equation_fields(equation)) return fail(LTS_EINVAL, "bad equation");
   lts_mesh_full* h = static_cast<lts_mesh_full*>(mesh);
   Mesh& m = mesh->m;
   hipStream_t s = (hipStream_t)stream;
   lts_status st = ensure_device(m);
   if (st != LTS_OK) return st;
-  if (equation == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
-    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
-  if ((equation == LTS_EQ_WAVE) != (view && view->nfields == 2))
-    return fail(LTS_EINVAL, "nfields does not match the equation");
+  if (!view || view->nfields != equation_fields(equation)) return fail(LTS_EINVAL, "nfields does not match the equation");
+  if ((st = check_combination(m, equation, view->precision, false)) != LTS_OK) return st;
   if ((st = set_step(&h->x.d_step, pos ? pos->coarse_step : 0, s)) != LTS_OK) return st;
   StageParams sp;
   if ((st = fill_params(m, view, stage, pos, h->x.d_step, sp)) != LTS_OK) return st;
   sp.sigma = params->ko_sigma;
+  sp.nl_coeff = params->nl_coeff;
   const int lo = lowest_active_level(m, pos->mode, pos->substep);
   if ((st = ensure_cscr(m, sp.F, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
   return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, h->x.d_cscr, g_shape, s);
@@ -587,24 +626,23 @@ extern "C" lts_status lts_fused_stage_noalloc(lts_mesh* mesh, const lts_stage_vi
                                               void* stream) {
   clear_error();
   if (!mesh || !params || !pos) return fail(LTS_EINVAL, "NULL argument");
-  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (!equation_fields(equation)) return fail(LTS_EINVAL, "bad equation");
   Mesh& m = mesh->m;
   if (!m.uploaded) return fail(LTS_EINVAL, "mesh tables are not on the device (make one device call on the mesh first)");
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
   if (dev != m.device) return fail(LTS_EINVAL, "mesh tables were uploaded to another device");
-  if (equation == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
-    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
-  if ((equation == LTS_EQ_WAVE) != (view && view->nfields == 2))
-    return fail(LTS_EINVAL, "nfields does not match the equation");
-  void* base = nullptr;
-  lts_status st = scratch_address(&base);
+  if (!view || view->nfields != equation_fields(equation)) return fail(LTS_EINVAL, "nfields does not match the equation");
+  lts_status st = check_combination(m, equation, view->precision, false);
   if (st != LTS_OK) return st;
+  void* base = nullptr;
+  if ((st = scratch_address(&base)) != LTS_OK) return st;
   int64_t* d_step = (int64_t*)base;
   double* gtab = (double*)((char*)base + kNoAllocHeader);
   StageParams sp;
   if ((st = fill_params(m, view, stage, pos, d_step, sp)) != LTS_OK) return st;
   sp.sigma = params->ko_sigma;
+  sp.nl_coeff = params->nl_coeff;
   const int lo = lowest_active_level(m, pos->mode, pos->substep);
   const size_t need = (size_t)m.ghost_ge[lo] * sp.F * 729 * sizeof(double);
   if (need > kNoAllocScratchBytes - kNoAllocHeader)
@@ -625,6 +663,7 @@ struct lts_sim {
   int64_t n = 0;
   int mode = -1;
   int64_t* d_step = nullptr;
+  unsigned int* d_nonfinite = nullptr;   // non-finite values written by RK updates
   double w[64], a[16], b[4];
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};
@@ -670,6 +709,11 @@ void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams
     for (int i = 0; i < p; ++i) sp.w[c][i] = sim->w[(c * p + stage) * p + i];
   for (int i = 0; i < p; ++i) sp.b[i] = sim->b[i];
   sp.sigma = sim->prm.ko_sigma;
+  sp.leafxyz = m.d_leafxyz;
+  sp.L = m.L;
+  sp.periodic = m.periodic ? 1 : 0;
+  sp.nl_coeff = sim->prm.nl_coeff;
+  sp.nonfinite = sim->d_nonfinite;
   set_kmask(sp);
 }
 
@@ -708,11 +752,15 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
   clear_error();
   if (!mesh || !out || !params) return fail(LTS_EINVAL, "NULL argument");
   *out = nullptr;
-  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (!equation_fields(equation)) return fail(LTS_EINVAL, "bad equation");
   if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
   const int p = tableau_stages(tableau);
   if (!p) return fail(LTS_EINVAL, "bad tableau");
-  if ((int64_t)p * (equation == LTS_EQ_WAVE ? 2 : 6) * mesh->m.n() * 125 >= (1ll << 31) ||
+  if (!mesh->m.periodic && equation != LTS_EQ_NLWAVE)
+    return fail(LTS_EUNSUPPORTED, "a bounded mesh needs the non-linear wave equation (radiative boundary)");
+  if (equation == LTS_EQ_NLWAVE && precision != LTS_FP64)
+    return fail(LTS_EUNSUPPORTED, "the non-linear wave runs in FP64");
+  if ((int64_t)p * equation_fields(equation) * mesh->m.n() * 125 >= (1ll << 31) ||
       mesh->m.n() * 125 * 8 >= (1ll << 32))
     return fail(LTS_EUNSUPPORTED, "arrays too large for the kernels' 32-bit offsets");
   lts_status st = ensure_device(mesh->m);
@@ -723,12 +771,14 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
   sim->eq = equation;
   sim->prec = precision;
   sim->tab = tableau;
-  sim->F = equation == LTS_EQ_WAVE ? 2 : 6;
+  sim->F = equation_fields(equation);
   sim->p = p;
   sim->prm = *params;
   coefficient_tables(tableau, sim->w, sim->a, sim->b);
   hipError_t e = hipMalloc(&sim->d_step, sizeof(int64_t));
   if (e == hipSuccess) e = hipMemset(sim->d_step, 0, sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&sim->d_nonfinite, sizeof(unsigned int));
+  if (e == hipSuccess) e = hipMemset(sim->d_nonfinite, 0, sizeof(unsigned int));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&sim->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     lts_sim_destroy(sim);
@@ -751,8 +801,25 @@ lts_status lts_sim_bind(lts_sim* sim, void* U, void* K) {
   return LTS_OK;
 }
 
-lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t use_graph, void* stream) {
+static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, bool use_graph, hipStream_t s);
+
+lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t flags, void* stream) {
   clear_error();
+  if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
+  if (flags & ~(LTS_ADVANCE_GRAPH | LTS_ADVANCE_CHECK_FINITE)) return fail(LTS_EINVAL, "unknown advance flags");
+  hipStream_t s = (hipStream_t)stream;
+  const bool check = (flags & LTS_ADVANCE_CHECK_FINITE) != 0;
+  if (check) HIP_TRY(launch_set_u32(sim->d_nonfinite, 0u, s), "reset finiteness counter");
+  lts_status st = advance_steps(sim, n_coarse_steps, mode, (flags & LTS_ADVANCE_GRAPH) != 0, s);
+  if (st != LTS_OK || !check) return st;
+  unsigned int bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, sim->d_nonfinite, sizeof(bad), hipMemcpyDeviceToHost, s), "read finiteness counter");
+  HIP_TRY(hipStreamSynchronize(s), "finiteness sync");
+  if (bad) return fail(LTS_ENONFINITE, std::to_string(bad) + " non-finite values written by the RK updates");
+  return LTS_OK;
+}
+
+static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, bool use_graph, hipStream_t s) {
   if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
   if (sim->batch) return fail(LTS_EINVAL, "sim is attached to a batch");
   if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
@@ -760,9 +827,8 @@ lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32
   if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
     return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
   Mesh& m = sim->mesh->m;
-  if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
-    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
-  hipStream_t s = (hipStream_t)stream;
+  lts_status cc = check_combination(m, sim->eq, sim->prec, false);
+  if (cc != LTS_OK) return cc;
   lts_status sc = ensure_cscr(m, sim->F, &sim->d_cscr, &sim->cscr_cap);
   if (sc != LTS_OK) return sc;
   sim->mode = mode;
@@ -870,7 +936,7 @@ lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mod
         HIP_TRY(launch_unzip(kf32, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb, L.ptotal, sim->d_pad, s),
                 "unzip launch");
         HIP_TRY(launch_rhs(sim->eq, kf32, m.bt.d_tiles, L.list, L.poff, L.ptotal, L.goff, L.gtotal, L.nb, sim->d_pad,
-                           sim->d_kb, sim->prm.ko_sigma, s),
+                           sim->d_kb, sim->prm.ko_sigma, sp, s),
                 "rhs launch");
         char* kslice = (char*)sim->K + (size_t)st * sim->F * m.n() * 125 * kbytes;
         HIP_TRY(launch_zip(kf32, m.bt.d_tiles, L.list, L.goff, L.gtotal, L.nb, sim->F, m.n(), sim->d_kb, kslice, s),
@@ -896,6 +962,23 @@ lts_status lts_sim_current(lts_sim* sim, double* out, void* stream) {
   return LTS_OK;
 }
 
+lts_status lts_sim_restore(lts_sim* sim, const double* state, int64_t coarse_step, int32_t mode, void* stream) {
+  clear_error();
+  if (!sim || !state || !sim->U) return fail(LTS_EINVAL, "NULL argument or sim not bound");
+  if (sim->batch) return fail(LTS_EINVAL, "sim is attached to a batch");
+  if (coarse_step < 0) return fail(LTS_EINVAL, "coarse_step < 0");
+  if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
+  Mesh& m = sim->mesh->m;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_set_i64(sim->d_step, coarse_step, s), "set step");
+  StageParams sp;
+  fill_sim_params(sim, 0, mode, 0, sp);
+  HIP_TRY(launch_restore(sp, m.bt.d_tiles, (int)m.blocks.size(), state, s), "restore launch");
+  sim->n = coarse_step;
+  sim->mode = mode;
+  return LTS_OK;
+}
+
 int64_t lts_sim_coarse_step(const lts_sim* sim) { return sim ? sim->n : -1; }
 
 void lts_sim_destroy(lts_sim* sim) {
@@ -904,6 +987,7 @@ void lts_sim_destroy(lts_sim* sim) {
   drop_graphs(sim);
   if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
   if (sim->d_step) (void)hipFree(sim->d_step);
+  if (sim->d_nonfinite) (void)hipFree(sim->d_nonfinite);
   for (void* p : sim->ualloc) (void)hipFree(p);
   if (sim->d_pad) (void)hipFree(sim->d_pad);
   if (sim->d_kb) (void)hipFree(sim->d_kb);
@@ -982,6 +1066,94 @@ lts_status lts_norms(lts_mesh* mesh, int32_t nfields, const double* a, const dou
   std::memcpy(&nb, &hs[2 * nfields * N], 8);
   out[2 * nfields] = (double)nb;
   return nb ? fail(LTS_ENONFINITE, "non-finite values in the state") : LTS_OK;
+}
+
+// ---- remeshing (Sec. 3.2.2; at coarse-step boundaries) ------------------------------
+namespace {
+// wavelet indicators of a state on the device: per leaf, and per family (first leaf)
+lts_status wavelet_indicators(Mesh& m, int F, const double* state, std::vector<double>& leaf_w,
+                              std::vector<int64_t>& fam, std::vector<double>& fam_w, hipStream_t s) {
+  fam = families(m);
+  const int64_t N = m.n(), nf = (int64_t)fam.size();
+  leaf_w.assign(N, 0.0);
+  fam_w.assign(nf, 0.0);
+  char* d = nullptr;
+  const size_t bytes = (size_t)(N + 2 * nf + 1) * 8;
+  HIP_TRY(hipMalloc(&d, bytes), "hipMalloc indicators");
+  double* d_leaf = (double*)d;
+  int64_t* d_fam = (int64_t*)(d + (size_t)N * 8);
+  double* d_famw = (double*)(d + (size_t)(N + nf) * 8);
+  hipError_t e = hipSuccess;
+  if (nf) e = hipMemcpyAsync(d_fam, fam.data(), nf * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_wavelet(state, F, N, d_fam, nf, d_leaf, d_famw, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(leaf_w.data(), d_leaf, N * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && nf) e = hipMemcpyAsync(fam_w.data(), d_famw, nf * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "wavelet indicators");
+  return LTS_OK;
+}
+}  // namespace
+
+lts_status lts_remesh_indicators(lts_mesh* mesh, int32_t nfields, const double* state, double* leaf_ind,
+                                 double* family_ind, void* stream) {
+  clear_error();
+  if (!mesh || !state || !leaf_ind || !family_ind) return fail(LTS_EINVAL, "NULL argument");
+  if (nfields < 1 || nfields > 6) return fail(LTS_EINVAL, "bad nfields");
+  Mesh& m = mesh->m;
+  std::vector<double> lw, fw;
+  std::vector<int64_t> fam;
+  lts_status st = wavelet_indicators(m, nfields, state, lw, fam, fw, (hipStream_t)stream);
+  if (st != LTS_OK) return st;
+  std::copy(lw.begin(), lw.end(), leaf_ind);
+  std::fill(family_ind, family_ind + m.n(), -1.0);
+  for (size_t q = 0; q < fam.size(); ++q) family_ind[fam[q]] = fw[q];
+  return LTS_OK;
+}
+
+lts_status lts_remesh(lts_mesh* mesh, int32_t nfields, const double* state, double eps, int32_t l_min, int32_t l_max,
+                      lts_mesh** out, void* stream) {
+  clear_error();
+  if (!mesh || !state || !out) return fail(LTS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (nfields < 1 || nfields > 6) return fail(LTS_EINVAL, "bad nfields");
+  Mesh& m = mesh->m;
+  if (!(eps > 0.0) || l_min < 0 || l_min > l_max || l_max > m.L) return fail(LTS_EINVAL, "need eps > 0, 0 <= l_min <= l_max <= L");
+  std::vector<double> lw, fw;
+  std::vector<int64_t> fam;
+  lts_status st = wavelet_indicators(m, nfields, state, lw, fam, fw, (hipStream_t)stream);
+  if (st != LTS_OK) return st;
+  std::vector<int32_t> leaves;
+  remesh_leaves(m, lw, fam, fw, eps, l_min, l_max, leaves);
+  lts_mesh_spec spec;
+  std::memset(&spec, 0, sizeof(spec));
+  spec.l_max = m.L;
+  spec.l_min = 99;
+  for (size_t i = 3; i < leaves.size(); i += 4) spec.l_min = std::min(spec.l_min, leaves[i]);
+  spec.block_cap = m.cap;
+  spec.n_leaves = (int64_t)leaves.size() / 4;
+  spec.leaves = leaves.data();
+  spec.boundary = m.periodic ? LTS_BOUNDARY_PERIODIC : LTS_BOUNDARY_OUTER;
+  return lts_build_mesh(&spec, out);
+}
+
+lts_status lts_transfer(lts_mesh* from, lts_mesh* to, int32_t nfields, const double* state_from, double* state_to,
+                        void* stream) {
+  clear_error();
+  if (!from || !to || !state_from || !state_to) return fail(LTS_EINVAL, "NULL argument");
+  if (nfields < 1 || nfields > 6) return fail(LTS_EINVAL, "bad nfields");
+  std::vector<int32_t> rec;
+  lts_status st = transfer_records(from->m, to->m, rec);
+  if (st != LTS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* d = nullptr;
+  HIP_TRY(hipMalloc(&d, rec.size() * 4 + 4), "hipMalloc transfer records");
+  hipError_t e = hipMemcpyAsync(d, rec.data(), rec.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_transfer(state_from, from->m.n(), state_to, to->m.n(), nfields, d, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "transfer");
+  return LTS_OK;
 }
 
 lts_status lts_copy_probe(const void* src, void* dst, size_t nbytes, void* stream) {
@@ -1156,7 +1328,8 @@ lts_status lts_batch_create(int32_t equation, int32_t precision, int32_t tableau
   clear_error();
   if (!out) return fail(LTS_EINVAL, "out is NULL");
   *out = nullptr;
-  if (equation != LTS_EQ_WAVE && equation != LTS_EQ_MAXWELL) return fail(LTS_EINVAL, "bad equation");
+  if (!equation_fields(equation)) return fail(LTS_EINVAL, "bad equation");
+  if (equation == LTS_EQ_NLWAVE) return fail(LTS_EUNSUPPORTED, "the non-linear wave is not built for batched launches");
   if (precision != LTS_FP64 && precision != LTS_FP32_RHS) return fail(LTS_EINVAL, "bad precision");
   if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
   const int p = tableau_stages(tableau);
@@ -1168,7 +1341,7 @@ lts_status lts_batch_create(int32_t equation, int32_t precision, int32_t tableau
   b->prec = precision;
   b->tab = tableau;
   b->mode = mode;
-  b->F = equation == LTS_EQ_WAVE ? 2 : 6;
+  b->F = equation_fields(equation);
   b->p = p;
   b->cap = capacity;
   coefficient_tables(tableau, b->w, b->a, b->b);

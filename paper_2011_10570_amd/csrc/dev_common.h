@@ -186,6 +186,11 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
   const int kb = slots[2 * L.slot + 1];
   const int kind = kb & 15;
   const int64_t fs = sp.N * 125;
+  if (kind == SRC_NONE) {   // beyond the outer faces: no source
+#pragma unroll
+    for (int f = 0; f < F; ++f) out[f] = 0.0;
+    return;
+  }
   if (kind != SRC_COARSE) {
     int node, lf, par, km;
     const double* w;
@@ -300,6 +305,117 @@ __device__ __forceinline__ void rhs_at(const At& at, T h, T sigma, const double 
     out[4] = (double)(-(d[0][2] - d[2][0]) + kos * ko[4]);
     out[5] = (double)(-(d[1][0] - d[0][1]) + kos * ko[5]);
   }
+}
+
+// ------------------------------------------------------------------ non-linear wave
+// The non-linear wave of Sec. 4.2 (eqs. lsm, chi, phi), fields (chi, phi):
+//   dchi/dt = phi + KO(chi),  dphi/dt = Lap chi - c sin(2 chi) / r^2 + KO(phi),
+// r = |x|; with c != 0 the node r = 0 holds the source's regularity condition
+// chi = 0 (a regular solution behaves like chi ~ a(t) r there): its state does
+// not change.  On a bounded domain a grid
+// point d grid steps from the nearest face along an axis uses the widest centred
+// stencil that fits there (sixth order for d >= 3, fourth for d = 2, second for
+// d = 1) and Kreiss-Oliger only along axes with d >= 3; a point on a face takes
+// the radiative condition of Sec. 4.2, df/dt = -(x . grad f) / r - k f / r
+// (k = 1 for chi, 2 for phi, asymptotic value 0), with one-sided fourth-order
+// first differences along the axes where it sits on a face.
+#define D2C4_1 (4.0 / 3.0)
+#define D2C4_2 (-1.0 / 12.0)
+#define D2C4_0 (-5.0 / 2.0)
+#define D1C4_1 (2.0 / 3.0)
+#define D1C4_2 (-1.0 / 12.0)
+
+// Per axis: grid steps to the nearest face (large on a periodic domain) and the
+// face a point on it lies on (+1 low, -1 high, 0 none).
+__device__ __forceinline__ void face_distance(const Geom& g, const int X[3], int d[3], int side[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (g.periodic) {
+      d[a] = 1 << 20;
+      side[a] = 0;
+    } else {
+      d[a] = min(X[a], g.Nu - X[a]) / g.w;
+      side[a] = X[a] == 0 ? 1 : (X[a] == g.Nu ? -1 : 0);
+    }
+  }
+}
+
+// First difference (times h) along axis ax at distance d from the nearest face
+// (side: which face when d = 0).
+template <typename At>
+__device__ __forceinline__ double d1_bounded(const At& at, int f, int ax, int d, int side) {
+  if (d == 0) {
+    // one-sided, fourth order: (-25/12, 4, -3, 4/3, -1/4) into the domain
+    const double s = (double)side;
+    return s * ((-25.0 / 12.0) * at(f, ax, 0) + 4.0 * at(f, ax, side) + (-3.0) * at(f, ax, 2 * side) +
+                (4.0 / 3.0) * at(f, ax, 3 * side) + (-0.25) * at(f, ax, 4 * side));
+  }
+  if (d == 1) return 0.5 * (at(f, ax, 1) - at(f, ax, -1));
+  if (d == 2) return D1C4_1 * (at(f, ax, 1) - at(f, ax, -1)) + D1C4_2 * (at(f, ax, 2) - at(f, ax, -2));
+  return D1C1 * (at(f, ax, 1) - at(f, ax, -1)) + D1C2 * (at(f, ax, 2) - at(f, ax, -2)) +
+         D1C3 * (at(f, ax, 3) - at(f, ax, -3));
+}
+
+// The non-linear wave's RHS at a block grid point with node-unit coordinates X.
+template <typename At>
+__device__ __forceinline__ void rhs_nl_at(const At& at, double h, double sigma, const Geom& g, const int X[3],
+                                          double out[2]) {
+  int d[3], side[3];
+  face_distance(g, X, d, side);
+  double x[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] = -1.0 + 2.0 * (double)X[a] / (double)g.Nu;
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  if (d[0] == 0 || d[1] == 0 || d[2] == 0) {
+    // on a face: the radiative condition
+    const double r = sqrt(r2);
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      double xg = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xg += x[a] * (d1_bounded(at, f, a, d[a], side[a]) / h);
+      out[f] = -xg / r - (f == 0 ? 1.0 : 2.0) * at(f, 0, 0) / r;
+    }
+    return;
+  }
+  double lap = 0.0, kc = 0.0, kp = 0.0;
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    const double c0 = at(0, a, 0);
+    if (d[a] >= 3) {
+      const double s1 = at(0, a, -1) + at(0, a, 1), s2 = at(0, a, -2) + at(0, a, 2), s3 = at(0, a, -3) + at(0, a, 3);
+      lap += D2C3 * s3 + D2C2 * s2 + D2C1 * s1 + D2C0 * c0;
+      kc += s3 - 6.0 * s2 + 15.0 * s1 - 20.0 * c0;
+      const double q1 = at(1, a, -1) + at(1, a, 1), q2 = at(1, a, -2) + at(1, a, 2), q3 = at(1, a, -3) + at(1, a, 3);
+      kp += q3 - 6.0 * q2 + 15.0 * q1 - 20.0 * at(1, a, 0);
+    } else if (d[a] == 2) {
+      lap += D2C4_2 * (at(0, a, -2) + at(0, a, 2)) + D2C4_1 * (at(0, a, -1) + at(0, a, 1)) + D2C4_0 * c0;
+    } else {
+      lap += (at(0, a, -1) + at(0, a, 1)) - 2.0 * c0;
+    }
+  }
+  const double chi = at(0, 0, 0);
+  const double lapn = lap / (h * h);
+  const double src = r2 > 0.0 ? sin(2.0 * chi) / r2 : 0.0;
+  const double kos = sigma / (64.0 * h);
+  out[0] = at(1, 0, 0) + kos * kc;
+  out[1] = lapn - g.c_nl * src + kos * kp;
+  if (g.c_nl != 0.0 && r2 == 0.0) {   // the regularity condition chi = 0 at r = 0
+    out[0] = 0.0;
+    out[1] = 0.0;
+  }
+}
+
+// Geometry of the block (or tile) whose grid starts at leaf `first`.
+__device__ __forceinline__ Geom geom_of(const StageParams& sp, int first, int level) {
+  Geom g;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) g.X0[a] = 4 * sp.leafxyz[4 * first + a];
+  g.w = 1 << (sp.L - level);
+  g.Nu = 4 << sp.L;
+  g.periodic = sp.periodic;
+  g.c_nl = sp.nl_coeff;
+  return g;
 }
 
 // Accessor of a padded array with point strides (1, sy, sz) and field stride fs.

@@ -263,6 +263,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       } else if (kind[u] == SRC_COARSE) {
 #pragma unroll
         for (int f = 0; f < F; ++f) Y[f * LS + li[u]] = (LT)(uu[u][f] - ref[f]);
+      } else if (kind[u] == SRC_NONE) {
+        // beyond the outer faces: never read by the bounded-domain stencils
+#pragma unroll
+        for (int f = 0; f < F; ++f) Y[f * LS + li[u]] = (LT)0;
       }
     }
   }
@@ -276,12 +280,19 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   // (2a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
   constexpr int G = X::G;
   constexpr int G3 = G * G * G;
+  Geom geo{};
+  if constexpr (EQ == LTS_EQ_NLWAVE) geo = geom_of(sp, first, c.lev);
   for (int gi = threadIdx.x; gi < G3; gi += NT) {
     const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
     const int ce = (gz * P + gy + 3) * P + gx + 3;
     double k[F];
-    // one axis at a time: fewer live registers (same operations, same order)
-    rhs_at<LT, EQ, F, true>(CrossAt<LT, TT>{Y, ce, X::HB + gy * G + gx, gz}, (LT)c.h, (LT)v.sigma, ref, k);
+    if constexpr (EQ == LTS_EQ_NLWAVE) {
+      const int Xp[3] = {geo.X0[0] + geo.w * gx, geo.X0[1] + geo.w * gy, geo.X0[2] + geo.w * gz};
+      rhs_nl_at(CrossAt<LT, TT>{Y, ce, X::HB + gy * G + gx, gz}, c.h, v.sigma, geo, Xp, k);
+    } else {
+      // one axis at a time: fewer live registers (same operations, same order)
+      rhs_at<LT, EQ, F, true>(CrossAt<LT, TT>{Y, ce, X::HB + gy * G + gx, gz}, (LT)c.h, (LT)v.sigma, ref, k);
+    }
 #pragma unroll
     for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
   }
@@ -330,7 +341,9 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
         for (int i = 0; i < 3; ++i)
           if (i < sp.stage) acc = fma(sp.b[i], zk[f][i], acc);
         acc = fma(bs, kv, acc);
-        st32(Uw1 + (uint32_t)(f * fsz), off, zu[f] + c.dt * acc);
+        const double un = zu[f] + c.dt * acc;
+        st32(Uw1 + (uint32_t)(f * fsz), off, un);
+        if (sp.nonfinite && !isfinite(un)) atomicAdd(sp.nonfinite, 1u);
       }
     }
   }
@@ -344,12 +357,14 @@ __device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const Stage
 // Waves per SIMD that the LDS of one workgroup allows: the register budget the
 // compiler is asked to keep so that registers do not cost occupancy.  Capped
 // where a tighter budget spills: 6 (80 registers) for FP64 side-2 tiles, 8 (64)
-// with FP32 stencils, 5 for side-1 tiles; left free for 6 fields.
-template <int TT, int F, bool KF32, int NT>
+// with FP32 stencils, 5 for side-1 tiles, 4 for the non-linear wave; left free
+// for 6 fields.
+template <int TT, int F, bool KF32, int NT, int EQ = LTS_EQ_WAVE>
 constexpr int fused_waves_per_eu() {
   const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32>);
   const int w = wg * (NT / 64) / 4;
-  const int cap = TT == 1 ? 5 : (KF32 ? 8 : 6);
+  // the non-linear wave's boundary-aware stencils need more registers
+  const int cap = EQ == LTS_EQ_NLWAVE ? 4 : (TT == 1 ? 5 : (KF32 ? 8 : 6));
   return (F > 2 || w < 1) ? 1 : (w > cap ? cap : w);
 }
 
@@ -406,6 +421,14 @@ hipError_t dispatch_nt(const StageParams& sp, const A& a, const LaunchShape& ls,
 template <typename A>
 hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& sp, const A& a, const LaunchShape& ls,
                           hipStream_t s) {
+  if (eq == LTS_EQ_NLWAVE) {   // FP64, tile sides 1 and 2, launches that allow it
+    if constexpr (A::kNonLinear) {
+      if (kf32) return hipErrorInvalidValue;
+      if (tt == 1) return dispatch_nt<1, 2, LTS_EQ_NLWAVE, false>(sp, a, ls, s);
+      if (tt == 2) return dispatch_nt<2, 2, LTS_EQ_NLWAVE, false>(sp, a, ls, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (eq == LTS_EQ_WAVE) {
     if (tt == 1) return kf32 ? dispatch_nt<1, 2, LTS_EQ_WAVE, true>(sp, a, ls, s)
                              : dispatch_nt<1, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);

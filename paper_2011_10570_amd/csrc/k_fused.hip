@@ -9,7 +9,7 @@ namespace lts {
 // contiguous (Morton-ordered, cost-balanced) range of tiles.  Coarser ghosts come
 // prolongated from the ghost-table pre-pass (scr).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT>())))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT, EQ>())))
 void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* __restrict__ slots,
              const double* __restrict__ scr, XcdRanges xr) {
   __shared__ FusedLds<TT, F, KF32> L;
@@ -28,6 +28,7 @@ void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* _
 
 namespace {
 struct OneArgs {
+  static constexpr bool kNonLinear = true;   // whether the non-linear wave kernels are built for these launches
   const int32_t* tiles;
   const int32_t* slots;
   const double* scr;

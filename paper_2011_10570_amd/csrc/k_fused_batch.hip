@@ -12,7 +12,7 @@ namespace lts {
 // arithmetic of every tile is that of the one-mesh kernel; coarser ghosts come
 // from the batch's ghost pre-pass (scr, simulation s at entry gbase_s).
 template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT>())))
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT, EQ>())))
 void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims, const int64_t* __restrict__ round,
                    const double* __restrict__ scr) {
   __shared__ FusedLds<TT, F, KF32> L;
@@ -61,6 +61,7 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
 
 namespace {
 struct BatchArgs {
+  static constexpr bool kNonLinear = false;   // whether the non-linear wave kernels are built for these launches
   const BatchSim* sims;
   int nsims;
   const int64_t* round;

@@ -33,7 +33,8 @@ template <int EQ, int F, bool F32>
 __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
                                              const int64_t* __restrict__ poff, int64_t ptotal,
                                              const int64_t* __restrict__ goff, int64_t gtotal,
-                                             const double* __restrict__ padded, void* kout, double sigma) {
+                                             const double* __restrict__ padded, void* kout, double sigma,
+                                             StageParams geo) {
   const int bi = blockIdx.y;
   const int32_t* t = tiles + 8 * (int64_t)list[bi];
   const int m = t[TI_M];
@@ -93,6 +94,10 @@ __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, 
         k[4] = (double)(-(d[0][2] - d[2][0]) + kos * ko[4]);
         k[5] = (double)(-(d[1][0] - d[0][1]) + kos * ko[5]);
       }
+    } else if constexpr (EQ == LTS_EQ_NLWAVE) {
+      const Geom g = geom_of(geo, t[TI_FIRST], t[TI_LEVEL]);
+      const int Xp[3] = {g.X0[0] + g.w * gx, g.X0[1] + g.w * gy, g.X0[2] + g.w * gz};
+      rhs_nl_at(StridedAt<double>{padded + poff[bi], ptotal, ci, P, P * P}, h, sigma, g, Xp, k);
     } else {
       const double zero[F] = {};
       rhs_point<double, EQ, F>(padded + poff[bi], ptotal, ci, P, P * P, h, sigma, zero, k);
@@ -149,6 +154,7 @@ __global__ __launch_bounds__(256) void k_rk(StageParams sp, const int32_t* __res
       const double v = sp.U[c.par_same * ps + f * fs + idx] + c.dt * acc;
       if (out) out[f * fs + idx] = v;
       else sp.Uw[(c.par_same ^ 1) * ps + f * fs + idx] = v;
+      if (!out && sp.nonfinite && !isfinite(v)) atomicAdd(sp.nonfinite, 1u);
     }
   }
 }
@@ -172,6 +178,136 @@ __global__ __launch_bounds__(256) void k_current(StageParams sp, const int32_t* 
     const int64_t idx = (int64_t)first * 125 + e;
     for (int f = 0; f < sp.F; ++f) out[f * fs + idx] = sp.U[par * ps + f * fs + idx];
   }
+}
+
+// restore: the state of every octant into the buffer block b reads after a whole
+// number of coarse steps (inverse of k_current)
+__global__ __launch_bounds__(256) void k_restore(StageParams sp, const int32_t* __restrict__ tiles, int nblocks,
+                                                 const double* __restrict__ in) {
+  const int b = blockIdx.y;
+  if (b >= nblocks) return;
+  const int32_t* t = tiles + 8 * (int64_t)b;
+  const int lev = t[TI_LEVEL];
+  const int m = t[TI_M];
+  const int first = t[TI_FIRST];
+  const int64_t n = *sp.step;
+  const int64_t steps = sp.mode == LTS_MODE_GTS ? (n << (sp.lmax - sp.lmin)) : (n << (lev - sp.lmin));
+  const int par = (int)(steps & 1);
+  const int64_t fs = sp.N * 125, ps = fs * sp.F;
+  const int nn = m * m * m * 125;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)first * 125 + e;
+    for (int f = 0; f < sp.F; ++f) sp.Uw[par * ps + f * fs + idx] = in[f * fs + idx];
+  }
+}
+
+// ------------------------------------------------------------------ remeshing
+// Wavelet indicator of one octant's node values v[f][125] (Sec. 3.2.2: the
+// failure to be interpolated from the coarser level): max over fields and the
+// nodes off the every-second-node grid of |v - I2 v|, I2 the tensor degree-2
+// Lagrange interpolant of the 27 nodes at positions 0, 2, 4.
+__device__ __forceinline__ double i2_weight(int pos, int e) {
+  // degree-2 weights from nodes 0, 2, 4 at positions 0..4 (exact binary fractions)
+  constexpr double w[5][3] = {{1, 0, 0}, {0.375, 0.75, -0.125}, {0, 1, 0}, {-0.125, 0.75, 0.375}, {0, 0, 1}};
+  return w[pos][e];
+}
+
+template <typename Get>
+__device__ __forceinline__ double wavelet_of(const Get& get, int F) {
+  double mx = 0.0;
+  for (int f = 0; f < F; ++f)
+    for (int n = 0; n < 125; ++n) {
+      const int i = n % 5, j = (n / 5) % 5, k = n / 25;
+      if (!((i | j | k) & 1)) continue;
+      double t = 0.0;
+      for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+          for (int a = 0; a < 3; ++a)
+            t += i2_weight(k, c) * i2_weight(j, b) * i2_weight(i, a) * get(f, 2 * a + 10 * b + 50 * c);
+      mx = fmax(mx, fabs(get(f, n) - t));
+    }
+  return mx;
+}
+
+__global__ __launch_bounds__(256) void k_wavelet_leaf(const double* __restrict__ st, int F, int64_t N,
+                                                      double* __restrict__ out) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= N) return;
+  out[o] = wavelet_of([&](int f, int n) { return st[((int64_t)f * N + o) * 125 + n]; }, F);
+}
+
+// the same at the parent of the family whose 8 leaves start at fam[q]: node i of
+// the parent is node 2 (i - 2c) of child c = min(i >> 1, 1) per axis
+__global__ __launch_bounds__(256) void k_wavelet_family(const double* __restrict__ st, int F, int64_t N,
+                                                        const int64_t* __restrict__ fam, int64_t nfam,
+                                                        double* __restrict__ out) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nfam) return;
+  const int64_t first = fam[q];
+  out[q] = wavelet_of(
+      [&](int f, int n) {
+        const int i = n % 5, j = (n / 5) % 5, k = n / 25;
+        const int cx = min(i >> 1, 1), cy = min(j >> 1, 1), cz = min(k >> 1, 1);
+        const int64_t leaf = first + cx + 2 * cy + 4 * cz;
+        const int node = 2 * (i - 2 * cx) + 10 * (j - 2 * cy) + 50 * (k - 2 * cz);
+        return st[((int64_t)f * N + leaf) * 125 + node];
+      },
+      F);
+}
+
+// Intergrid transfer (remeshing): new leaf q takes, per record rec[q] = {old leaf,
+// kind, offset x, y, z, shift}: kind 0 -- the old leaf's tensor degree-4 Lagrange
+// interpolant at position (offset + i 2^-shift... ) given in old node units as
+// (off_d + i) / 2^shift; kind 1 -- the coincident node of child c of the 8 old
+// leaves starting at the old leaf (injection).
+__global__ __launch_bounds__(128) void k_transfer(const double* __restrict__ st_old, int64_t N_old,
+                                                  double* __restrict__ st_new, int64_t N_new, int F,
+                                                  const int32_t* __restrict__ rec) {
+  const int64_t q = blockIdx.x;
+  const int n = threadIdx.x;
+  if (q >= N_new || n >= 125) return;
+  const int32_t* r = rec + 6 * q;
+  const int64_t o = r[0];
+  const int i = n % 5, j = (n / 5) % 5, k = n / 25;
+  if (r[1] == 1) {
+    const int cx = min(i >> 1, 1), cy = min(j >> 1, 1), cz = min(k >> 1, 1);
+    const int64_t leaf = o + cx + 2 * cy + 4 * cz;
+    const int node = 2 * (i - 2 * cx) + 10 * (j - 2 * cy) + 50 * (k - 2 * cz);
+    for (int f = 0; f < F; ++f) st_new[((int64_t)f * N_new + q) * 125 + n] = st_old[((int64_t)f * N_old + leaf) * 125 + node];
+    return;
+  }
+  // position of this node in the old leaf's node units, per axis
+  const double sc = ldexp(1.0, -r[5]);
+  const double xi[3] = {(r[2] + i) * sc, (r[3] + j) * sc, (r[4] + k) * sc};
+  double w[3][5];
+  for (int d = 0; d < 3; ++d)
+    for (int a = 0; a < 5; ++a) {
+      double num = 1.0, den = 1.0;
+      for (int m = 0; m < 5; ++m)
+        if (m != a) {
+          num *= xi[d] - m;
+          den *= (double)(a - m);
+        }
+      w[d][a] = num / den;
+    }
+  for (int f = 0; f < F; ++f) {
+    const double* v = st_old + ((int64_t)f * N_old + o) * 125;
+    double t = 0.0;
+    for (int c = 0; c < 5; ++c) {
+      double ty = 0.0;
+      for (int b = 0; b < 5; ++b) {
+        double tx = 0.0;
+        for (int a = 0; a < 5; ++a) tx = fma(w[0][a], v[a + 5 * b + 25 * c], tx);
+        ty = fma(w[1][b], tx, ty);
+      }
+      t = fma(w[2][c], ty, t);
+    }
+    st_new[((int64_t)f * N_new + q) * 125 + n] = t;
+  }
+}
+
+__global__ void k_set_u32(unsigned int* p, unsigned int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 __global__ void k_increment(int64_t* ctr) {
@@ -247,19 +383,25 @@ hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, 
 
 hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,
                       int64_t ptotal, const int64_t* goff, int64_t gtotal, int nb, const double* padded, void* kout,
-                      double sigma, hipStream_t s) {
+                      double sigma, const StageParams& geo, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   dim3 grid(8, nb);
+  if (eq == LTS_EQ_NLWAVE) {
+    if (f32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_rhs<LTS_EQ_NLWAVE, 2, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
+                       gtotal, padded, kout, sigma, geo);
+    return hipGetLastError();
+  }
   if (eq == LTS_EQ_WAVE) {
     if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
-                                gtotal, padded, kout, sigma);
+                                gtotal, padded, kout, sigma, geo);
     else hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
-                            gtotal, padded, kout, sigma);
+                            gtotal, padded, kout, sigma, geo);
   } else {
     if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
-                                goff, gtotal, padded, kout, sigma);
+                                goff, gtotal, padded, kout, sigma, geo);
     else hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
-                            goff, gtotal, padded, kout, sigma);
+                            goff, gtotal, padded, kout, sigma, geo);
   }
   return hipGetLastError();
 }
@@ -287,6 +429,33 @@ hipError_t launch_rk(bool kf32, const StageParams& sp, const int32_t* tiles, con
 hipError_t launch_current(const StageParams& sp, const int32_t* tiles, int nblocks, double* out, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_current, dim3(4, nblocks), dim3(256), 0, s, sp, tiles, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_restore(const StageParams& sp, const int32_t* tiles, int nblocks, const double* in, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restore, dim3(4, nblocks), dim3(256), 0, s, sp, tiles, nblocks, in);
+  return hipGetLastError();
+}
+
+hipError_t launch_wavelet(const double* st, int F, int64_t N, const int64_t* fam, int64_t nfam, double* leaf_out,
+                          double* fam_out, hipStream_t s) {
+  if (N > 0) hipLaunchKernelGGL(k_wavelet_leaf, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, st, F, N, leaf_out);
+  if (nfam > 0)
+    hipLaunchKernelGGL(k_wavelet_family, dim3((unsigned)((nfam + 255) / 256)), dim3(256), 0, s, st, F, N, fam, nfam,
+                       fam_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(const double* st_old, int64_t N_old, double* st_new, int64_t N_new, int F,
+                           const int32_t* rec, hipStream_t s) {
+  if (N_new <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transfer, dim3((unsigned)N_new), dim3(128), 0, s, st_old, N_old, st_new, N_new, F, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u32(unsigned int* ptr, unsigned int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, ptr, value);
   return hipGetLastError();
 }
 

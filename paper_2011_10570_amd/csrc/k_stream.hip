@@ -252,7 +252,9 @@ __device__ __forceinline__ void stream_zip(const StageParams& sp, const StreamCt
         for (int i = 0; i < 3; ++i)
           if (i < sp.stage) acc = fma(sp.b[i], kp[f][i], acc);
         acc = fma(bs, kv, acc);
-        st32(x.Uw1 + (uint32_t)(f * x.fsz), off, u0[f] + x.dt * acc);
+        const double un = u0[f] + x.dt * acc;
+        st32(x.Uw1 + (uint32_t)(f * x.fsz), off, un);
+        if (sp.nonfinite && !isfinite(un)) atomicAdd(sp.nonfinite, 1u);
       }
     }
   }

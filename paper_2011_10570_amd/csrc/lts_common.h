@@ -24,7 +24,7 @@
 
 namespace lts {
 
-enum { SRC_OWN = 0, SRC_SAME = 1, SRC_FINE = 2, SRC_COARSE = 3 };
+enum { SRC_OWN = 0, SRC_SAME = 1, SRC_FINE = 2, SRC_COARSE = 3, SRC_NONE = 4 };
 
 // tile record: int32[8]; TI_COUNTS packs the lengths of the tile's work lists:
 // same-level slots | finer slots << 8 | coarser slots << 16 | coarser leaves << 24

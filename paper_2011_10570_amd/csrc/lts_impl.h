@@ -35,6 +35,7 @@ struct TileSet {
 
 struct Mesh {
   int L = 0, lmin = 0, lmax = 0, cap = 4;
+  bool periodic = true;               // false: bounded by the outer faces
   std::vector<int32_t> ax, ay, az;
   std::vector<int8_t> lev;
   std::vector<uint64_t> key;          // Morton key of the anchor (sorted)
@@ -50,6 +51,7 @@ struct Mesh {
   std::vector<int32_t> ghosts;        // [E][2] = leaf, receiver level
   std::vector<int64_t> ghost_ge;
   int32_t* d_ghosts = nullptr;
+  int32_t* d_leafxyz = nullptr;      // [N][4] leaf anchors and levels (positions of the non-linear wave)
   TileSet bt;                         // one tile per block (standalone kernels)
   bool uploaded = false;
   int device = -1;
@@ -68,6 +70,14 @@ lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m);
 lts_status build_tiles(Mesh& m, int t);
 lts_status build_block_tiles(Mesh& m);
 void unzip_map_block(const Mesh& m, int b, int32_t* out);  // [(4m+7)^3][5]
+
+// Remeshing (remesh.cpp): complete same-level sibling families (first leaf), the
+// new leaf list [n][4] from the wavelet indicators, and the intergrid transfer
+// records [N_to][6] (see launch_transfer).
+std::vector<int64_t> families(const Mesh& m);
+void remesh_leaves(const Mesh& m, const std::vector<double>& leaf_w, const std::vector<int64_t>& fam,
+                   const std::vector<double>& fam_w, double eps, int l_min, int l_max, std::vector<int32_t>& out);
+lts_status transfer_records(const Mesh& from, const Mesh& to, std::vector<int32_t>& rec);
 
 // Exact-rational coefficient tables: w[case][s][i] (4 x p x p), a[p][p], b[p].
 int tableau_stages(int tableau);

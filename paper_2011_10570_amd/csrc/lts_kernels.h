@@ -19,6 +19,22 @@ struct StageParams {
   double b[4];
   double sigma;
   int kmask[4];         // per case: bit i set if w[case][i] != 0 (uniform branches)
+  // non-linear wave (positions and the outer boundary): leaf anchors [N][4]
+  // (x, y, z in level-L octant units, level), L, periodic flag, source coefficient
+  const int32_t* leafxyz;
+  int L, periodic;
+  double nl_coeff;
+  // counter of non-finite values written by the RK update (nullptr: not counted)
+  unsigned int* nonfinite;
+};
+
+// Geometry the non-linear wave's stencils need at one block: its grid origin in
+// node units, the grid step, and the domain (side Nu node units; periodic or
+// bounded by the outer faces).
+struct Geom {
+  int X0[3];
+  int w, Nu, periodic;
+  double c_nl;
 };
 
 // Launch shape of the fused kernels: threads per workgroup of the tile kernels
@@ -87,12 +103,23 @@ hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, 
                         const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);
 hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,
                       int64_t ptotal, const int64_t* goff, int64_t gtotal, int nb, const double* padded, void* kout,
-                      double sigma, hipStream_t s);
+                      double sigma, const StageParams& geo, hipStream_t s);
 hipError_t launch_zip(bool f32, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal, int nb,
                       int F, int64_t N, const void* kblock, void* kout, hipStream_t s);
 hipError_t launch_rk(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* list, int nb,
                      const double* coef, double* out, hipStream_t s);
 hipError_t launch_current(const StageParams& sp, const int32_t* tiles, int nblocks, double* out, hipStream_t s);
+// Inverse of launch_current: the state of every octant into the U buffer each
+// block reads at the coarse step *sp.step.
+hipError_t launch_restore(const StageParams& sp, const int32_t* tiles, int nblocks, const double* in, hipStream_t s);
+hipError_t launch_set_u32(unsigned int* ptr, unsigned int value, hipStream_t s);
+// Remeshing: wavelet indicators of every leaf and of the parents of the families
+// fam[0..nfam) (first leaf of 8 siblings); intergrid transfer by records
+// rec[N_new][6] = {old leaf, kind (0 interpolate, 1 inject), offset x, y, z, shift}.
+hipError_t launch_wavelet(const double* st, int F, int64_t N, const int64_t* fam, int64_t nfam, double* leaf_out,
+                          double* fam_out, hipStream_t s);
+hipError_t launch_transfer(const double* st_old, int64_t N_old, double* st_new, int64_t N_new, int F,
+                           const int32_t* rec, hipStream_t s);
 hipError_t launch_increment(int64_t* ctr, hipStream_t s);
 hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, double* sq, double* mx,
                                 unsigned long long* bad, hipStream_t s);

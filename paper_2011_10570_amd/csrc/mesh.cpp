@@ -59,7 +59,11 @@ int64_t dmax_axis(int64_t lo, int64_t hi, int64_t c, int64_t n) {
   return std::max(point_dist(lo, c, n), point_dist(hi, c, n));
 }
 
-bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L) {
+// The same distances on a bounded domain (no images).
+int64_t dmin_axis_bounded(int64_t lo, int64_t hi, int64_t c) { return std::max<int64_t>(0, std::max(lo - c, c - hi)); }
+int64_t dmax_axis_bounded(int64_t lo, int64_t hi, int64_t c) { return std::max(std::abs(lo - c), std::abs(hi - c)); }
+
+bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L, bool periodic) {
   const int64_t n = 4ll << L;
   const int64_t s = 1ll << (L - f.l);
   const int64_t lo[3] = {4ll * f.x, 4ll * f.y, 4ll * f.z};
@@ -67,7 +71,8 @@ bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L) {
     const lts_criterion& c = spec->criteria[ci];
     int64_t dmin2 = 0, dmax2 = 0;
     for (int d = 0; d < 3; ++d) {
-      int64_t a = dmin_axis(lo[d], lo[d] + 4 * s, c.center[d], n);
+      int64_t a = periodic ? dmin_axis(lo[d], lo[d] + 4 * s, c.center[d], n)
+                           : dmin_axis_bounded(lo[d], lo[d] + 4 * s, c.center[d]);
       dmin2 += a * a;
     }
     if (c.kind == LTS_CRIT_BALL) {
@@ -75,7 +80,8 @@ bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L) {
     } else {
       if (c.rhi2[f.l] < 0) continue;
       for (int d = 0; d < 3; ++d) {
-        int64_t a = dmax_axis(lo[d], lo[d] + 4 * s, c.center[d], n);
+        int64_t a = periodic ? dmax_axis(lo[d], lo[d] + 4 * s, c.center[d], n)
+                             : dmax_axis_bounded(lo[d], lo[d] + 4 * s, c.center[d]);
         dmax2 += a * a;
       }
       if (c.rlo2[f.l] < dmax2 && dmin2 < c.rhi2[f.l]) return true;
@@ -100,6 +106,7 @@ void sort_leaves(std::vector<Leaf>& v) {
 // closed integer box [lo, hi] per axis (may wrap or exceed the period).
 struct Prefix {
   int64_t n = 0;
+  bool periodic = true;   // false: cells beyond [0, n) do not exist
   std::vector<int32_t> P;  // (n+1)^3
   int64_t at(int64_t x, int64_t y, int64_t z) const { return P[(size_t)((z * (n + 1) + y) * (n + 1) + x)]; }
   int64_t box(int64_t x0, int64_t x1, int64_t y0, int64_t y1, int64_t z0, int64_t z1) const {
@@ -108,6 +115,12 @@ struct Prefix {
   }
   // split [lo, hi] into at most two half-open ranges inside [0, n)
   int ranges(int64_t lo, int64_t hi, int64_t r[2][2]) const {
+    if (!periodic) {
+      r[0][0] = std::max<int64_t>(lo, 0);
+      r[0][1] = std::min<int64_t>(hi + 1, n);
+      if (r[0][1] <= r[0][0]) { r[0][0] = 0; r[0][1] = 0; }
+      return 1;
+    }
     if (hi - lo + 1 >= n) {
       r[0][0] = 0; r[0][1] = n;
       return 1;
@@ -133,10 +146,10 @@ struct Prefix {
 };
 
 // Ghost-reach balance: split a level-l leaf while a leaf of level >= l+2 has
-// periodic Chebyshev box distance <= 3 h_l from it.  For each l the test runs on
+// Chebyshev box distance <= 3 h_l from it (periodic images on a periodic domain).  For each l the test runs on
 // the level-(l+2) cell grid: the leaf spans cells [A, A+4) per axis and the cells
 // whose closed box meets its box grown by 3 h_l (= 3 cells) are [A-4, A+7].
-lts_status balance(std::vector<Leaf>& leaves, int L) {
+lts_status balance(std::vector<Leaf>& leaves, int L, bool periodic) {
   for (int pass = 0; pass < 64; ++pass) {
     int lo_lev = 99, hi_lev = -1;
     for (const Leaf& f : leaves) { lo_lev = std::min(lo_lev, f.l); hi_lev = std::max(hi_lev, f.l); }
@@ -147,6 +160,7 @@ lts_status balance(std::vector<Leaf>& leaves, int L) {
       const int64_t n = 1ll << g;
       Prefix pf;
       pf.n = n;
+      pf.periodic = periodic;
       std::vector<uint8_t> ind((size_t)(n * n * n), 0);
       for (const Leaf& f : leaves) {
         if (f.l < g) continue;
@@ -191,6 +205,7 @@ lts_status balance(std::vector<Leaf>& leaves, int L) {
 int Mesh::find(int level, int64_t cx, int64_t cy, int64_t cz) const {
   if (level < 0 || level > L) return -1;
   const int64_t n = 1ll << level;
+  if (!periodic && (cx < 0 || cy < 0 || cz < 0 || cx >= n || cy >= n || cz >= n)) return -1;
   const int64_t s = 1ll << (L - level);
   const uint64_t k = key_of(pmod(cx, n) * s, pmod(cy, n) * s, pmod(cz, n) * s);
   auto it = std::lower_bound(key.begin(), key.end(), k);
@@ -206,6 +221,9 @@ lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m) {
     return fail(LTS_EINVAL, "need 0 <= l_min <= l_max <= 10");
   if (spec->block_cap != 1 && spec->block_cap != 2 && spec->block_cap != 4)
     return fail(LTS_EINVAL, "block_cap must be 1, 2 or 4");
+  if (spec->boundary != LTS_BOUNDARY_PERIODIC && spec->boundary != LTS_BOUNDARY_OUTER)
+    return fail(LTS_EINVAL, "boundary must be LTS_BOUNDARY_PERIODIC or LTS_BOUNDARY_OUTER");
+  const bool periodic = spec->boundary == LTS_BOUNDARY_PERIODIC;
   std::vector<Leaf> leaves;
   if (spec->n_leaves > 0) {
     if (!spec->leaves) return fail(LTS_EINVAL, "leaves is NULL");
@@ -248,18 +266,19 @@ lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m) {
     for (int l = spec->l_min; l < L && !cur.empty(); ++l) {
       std::vector<Leaf> next;
       for (const Leaf& f : cur) {
-        if (refine_leaf(spec, f, L)) push_children(next, f, L);
+        if (refine_leaf(spec, f, L, periodic)) push_children(next, f, L);
         else leaves.push_back(f);
       }
       cur.swap(next);
     }
     leaves.insert(leaves.end(), cur.begin(), cur.end());
   }
-  lts_status st = balance(leaves, L);
+  lts_status st = balance(leaves, L, periodic);
   if (st != LTS_OK) return st;
   sort_leaves(leaves);
 
   m.L = L;
+  m.periodic = periodic;
   m.cap = spec->block_cap;
   const size_t N = leaves.size();
   m.ax.resize(N); m.ay.resize(N); m.az.resize(N); m.lev.resize(N); m.key.resize(N);
@@ -323,6 +342,14 @@ lts_status slot_entry(const Mesh& m, const Block& B, int cx, int cy, int cz, int
   const int l = B.level;
   const int64_t s = 1ll << (m.L - l);
   const int64_t gx = B.ax / s + cx, gy = B.ay / s + cy, gz = B.az / s + cz;
+  if (!m.periodic) {
+    const int64_t n = 1ll << l;
+    if (gx < 0 || gy < 0 || gz < 0 || gx >= n || gy >= n || gz >= n) {
+      out[0] = -1;   // beyond the outer faces: no source
+      out[1] = SRC_NONE;
+      return LTS_OK;
+    }
+  }
   int leaf = m.find(l, gx, gy, gz);
   if (leaf >= 0) {
     out[0] = leaf;
@@ -381,7 +408,7 @@ lts_status add_tile(const Mesh& m, int b, int tt, int ox, int oy, int oz, TileSe
           coarse.push_back(si);
         } else if (kind == SRC_FINE) {
           fine.push_back(si);
-        } else {
+        } else if (kind == SRC_SAME) {
           same.push_back(si);
         }
         tab[2 * si] = e[0];
@@ -562,6 +589,9 @@ void unzip_map_block(const Mesh& m, int b, int32_t* out) {
           for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
         } else if (kind == SRC_SAME) {
           o[0] = leaf; o[1] = SRC_SAME;
+          for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
+        } else if (kind == SRC_NONE) {
+          o[0] = -1; o[1] = SRC_NONE;
           for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
         } else if (kind == SRC_FINE) {
           int c[3];

@@ -255,3 +255,39 @@ def test_graph_recaptured_after_table_and_shape_changes(c1):
         P.set_launch(*old)
     want = _run_gpu(gm, U0, 3, P.MODE_LTS, graph=False)
     assert np.array_equal(sim.current().cpu().numpy(), want)
+
+
+def test_finiteness_flag_reports_nan(c1):
+    """A NaN forced into the initial state from the host: lts_advance with the
+    finiteness check returns LTS_ENONFINITE; clean data passes the check."""
+    om, gm, U0 = c1
+    sim = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=0.1, device=DEV)
+    sim.set_state(U0)
+    sim.advance(1, P.MODE_LTS, check_finite=True)
+    bad = np.array(U0, copy=True).reshape(2, om.n_oct, 125)
+    bad[0, 17, 62] = np.nan
+    sim.set_state(bad)
+    with pytest.raises(P.LTSError) as e:
+        sim.advance(1, P.MODE_LTS, check_finite=True)
+    assert e.value.status == 5
+
+
+@pytest.mark.parametrize("mode", [P.MODE_LTS, P.MODE_GTS])
+def test_checkpoint_resume_bitwise(c1, tmp_path, mode):
+    """Checkpoint after 2 coarse steps, save and load it (npz, no pickling),
+    resume in a new sim for 2 more: bitwise the uninterrupted 4-step run."""
+    om, gm, U0 = c1
+    ref = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=0.1, device=DEV)
+    ref.set_state(U0)
+    ref.advance(2, mode)
+    ck = ref.checkpoint()
+    path = str(tmp_path / "ck.npz")
+    P.Sim.save_checkpoint(ck, path)
+    ref.advance(2, mode)
+    a = ref.current().cpu().numpy()
+    sim = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=0.1, device=DEV)
+    sim.restore(P.Sim.load_checkpoint(path))
+    assert sim.coarse_step == 2
+    sim.advance(2, mode)
+    assert sim.coarse_step == 4
+    assert np.array_equal(sim.current().cpu().numpy(), a)

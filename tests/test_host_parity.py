@@ -37,7 +37,7 @@ def _oracle_mesh(name):
     return ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec(name)))
 
 
-@pytest.mark.parametrize("name", ["small", "wave_c1"])
+@pytest.mark.parametrize("name", ["small", "wave_c1", "nl_small", "nl_c1"])
 def test_mesh_bit_exact(name):
     om = _oracle_mesh(name)
     gm = P.build_mesh(mesh_spec(name))
@@ -64,7 +64,7 @@ def test_ghost_owner_fixture_library():
         assert map_row(mp[off[b]:off[b + 1]], int(blocks[b, 1]), qx, qy, qz) == r[4:9], r
 
 
-@pytest.mark.parametrize("name", ["small", "wave_c1"])
+@pytest.mark.parametrize("name", ["small", "wave_c1", "nl_small", "nl_c1"])
 def test_unzip_map_bit_exact(name):
     om = _oracle_mesh(name)
     gm = P.build_mesh(mesh_spec(name))
@@ -213,3 +213,13 @@ def test_footprint_counts_ghost_scratch():
     assert info["ghost_entries"] > 0
     base = info["n_oct"] * 125 * 2 * (16 + 4 * 8) + info["table_bytes"]
     assert serve.footprint_bytes(info, "wave", P.FP64) == base + info["ghost_entries"] * 2 * 729 * 8
+
+
+def test_bounded_mesh_info():
+    """A bounded mesh reports its boundary; an unknown boundary is refused."""
+    assert P.build_mesh(mesh_spec("nl_small")).info()["boundary"] == P.BOUNDARY_OUTER
+    assert P.build_mesh(mesh_spec("small")).info()["boundary"] == P.BOUNDARY_PERIODIC
+    spec = P._L.MeshSpecC()
+    spec.l_min, spec.l_max, spec.block_cap, spec.boundary = 2, 3, 4, 7
+    h = ctypes.c_void_p()
+    assert P.lib().lts_build_mesh(ctypes.byref(spec), ctypes.byref(h)) == _lib.EINVAL

@@ -7,7 +7,8 @@ time-stepping or mesh logic).  It provides
     this file and then stored here),
   * seeded pulse centres,
   * initial data evaluated at octant-local node coordinates of a given leaf list
-    (Gaussian pulse, plane wave, divergence-free Maxwell data),
+    (Gaussian pulse, plane wave, divergence-free Maxwell data, the non-linear
+    wave's shell),
   * seeded random DG arrays for kernel unit tests.
 
 Coordinates: level-L node units, N_u = 4 * 2^L per side, x = -1 + 2 X / N_u; a
@@ -95,6 +96,22 @@ def maxwell_gaussian(anchors, levels, L, centres_nu, sigma=0.1, amp=1.0) -> np.n
             ey += d[..., 0] / (sigma * sigma) * g
     z = np.zeros_like(ex)
     return np.stack([ex, ey, z, z, z.copy(), z.copy()])
+
+
+def nlwave_shell(anchors, levels, L, radius=0.5, sigma=0.1, amp=1.0) -> np.ndarray:
+    """Non-linear wave data (chi, phi) = (amp (r/R)^2 exp(-(r - R)^2 / (2 sigma^2)), 0),
+    r = |x|: a spherical shell around the origin (no images), even in r and
+    vanishing at r = 0 like r^2, as a regular solution does: [2, N, 5, 5, 5]."""
+    x = physical(node_units(anchors, levels, L), L)
+    r2 = (x * x).sum(axis=-1)
+    chi = shell_profile(np.sqrt(r2), radius, sigma, amp)
+    return np.stack([chi, np.zeros_like(chi)])
+
+
+def shell_profile(r, radius=0.5, sigma=0.1, amp=1.0):
+    """The radial profile of nlwave_shell."""
+    r = np.asarray(r, dtype=np.float64)
+    return amp * (r / radius) ** 2 * np.exp(-(r - radius) ** 2 / (2.0 * sigma * sigma))
 
 
 def random_dg(shape, seed: int, scale: float = 1.0) -> np.ndarray:

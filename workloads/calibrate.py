@@ -18,8 +18,13 @@ the paper's Gaussian-pulse workloads, Sec. 4.2 and 4.5):
             [2k, 200k], wave or Maxwell with probability 1/2, nested balls;
             unit-rate exponential inter-arrival gaps and a load factor
             rho ~ U(0.5, 0.9) (the loop scales gaps by the measured capacity).
+  nl_*      the non-linear wave of Sec. 4.2 on [-1, 1]^3 bounded by its outer
+            faces (radiative boundary): a Gaussian shell pulse around the origin
+            (radius R, width sigma), refined on a shell of annuli around R.
+            nl_small levels 2-3; nl_c1 levels 3-5; nl_c2 levels 3-6 (the
+            LTS-GTS difference over time, the analogue of Table accu_nl).
 
-Usage: ``python -m workloads.calibrate [--base] [--batch] [--serve]`` recomputes
+Usage: ``python -m workloads.calibrate [--base] [--batch] [--serve] [--nl]`` recomputes
 the named groups (all of them when the file does not exist yet) and keeps the
 others as stored.
 """
@@ -181,6 +186,34 @@ def batch_specs(n_prob=64, seed=1234):
     return out
 
 
+def shell_spec(l_min, L, R, half, grow):
+    """Annuli around the domain centre (the origin): a level-l leaf is split where it
+    meets radii R -/+ half (1 + grow (L - 1 - l)); bounded domain."""
+    n_u = 4 * (1 << L)
+    c = n_u // 2
+    rlo, rhi = [-1] * L, [-1] * L
+    for lev in range(l_min, L):
+        w = half * (1.0 + grow * (L - 1 - lev))
+        rlo[lev] = int(round(max(R - w, 0.0) * n_u / 2)) ** 2
+        rhi[lev] = int(round((R + w) * n_u / 2)) ** 2
+    return {"l_min": l_min, "l_max": L, "block_cap": 4, "boundary": "outer",
+            "criteria": [{"kind": "annulus", "center": [c, c, c], "rlo2": rlo, "rhi2": rhi}]}
+
+
+def nl_specs():
+    out = {}
+    for name, (lm, L, R, half, grow, shell_r, shell_s, nco) in {
+            "nl_small": (2, 3, 0.4, 0.05, 0.0, 0.4, 0.1, 2),
+            "nl_c1": (2, 5, 0.2, 0.02, 0.5, 0.2, 0.05, 8),
+            "nl_c2": (3, 6, 0.5, 0.02, 0.5, 0.5, 0.1, 64)}.items():
+        spec = shell_spec(lm, L, R, half, grow)
+        n = count(spec)
+        out[name] = {"mesh": spec, "equation": "nlwave", "shell_radius": shell_r, "sigma": shell_s, "amp": 1.0,
+                     "nl_coeff": 1.0, "ko_sigma": 0.1, "tableau": "rk4", "n_coarse": nco, "leaves": n}
+        print(f"  {name}: leaves={n}", flush=True)
+    return out
+
+
 def main():
     path = os.path.join(HERE, "specs.json")
     specs = json.load(open(path)) if os.path.exists(path) else {}
@@ -203,6 +236,8 @@ def main():
                           "tableau": "rk4", "n_coarse": 8}
     if "--serve" in sys.argv or "serve" not in specs:
         specs["serve"] = serve_specs()
+    if "--nl" in sys.argv or "nl_c1" not in specs:
+        specs.update(nl_specs())
     with open(path, "w") as f:
         json.dump(specs, f, indent=1)
 
