@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=None, help="first N stored requests (default all)")
     ap.add_argument("--no-maxwell", action="store_true", help="skip the Maxwell leg")
+    ap.add_argument("--no-nl", action="store_true", help="skip the non-linear wave leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only time a copy of this many MiB")
     return ap.parse_args()
 
@@ -227,6 +228,50 @@ def time_leg(P, gm, U0, mode, prec, steps, warmup, torch, equation="wave"):
     ev = e0.elapsed_time(e1) / 1e3
     del sim
     return wall, ev
+
+
+def nl_leg(P, torch, steps, warmup) -> dict:
+    """The non-linear wave with the radiative outer boundary (Sec. 4.2) on the
+    bounded shell mesh nl_c2: LTS and GTS throughput, the fused stage against
+    the same 224 / 208 B per node-update as the linear wave (the boundary
+    geometry comes from one leaf coordinate per tile)."""
+    from workloads import config, mesh_spec, nlwave_shell
+    cfg = config("nl_c2")
+    gm = P.build_mesh(mesh_spec("nl_c2"))
+    gm.set_tile(2)
+    info = gm.info()
+    lv = gm.leaves()
+    U0 = torch.as_tensor(nlwave_shell(lv[:, :3], lv[:, 3], info["L"], cfg["shell_radius"], cfg["sigma"],
+                                      cfg["amp"]).reshape(2, -1, 125), device="cuda:0")
+    out = {"config": f"nl_c2: chi_tt = lap chi + chi^2 (Sec. 4.2) on [-1,1]^3 with the radiative outer "
+                     f"boundary, levels {info['lmin']}-{info['lmax']} around the shell r = {cfg['shell_radius']}, "
+                     f"{info['n_oct']} octants, RK4, tile side 2",
+           "n_octants": info["n_oct"], "steps": steps}
+    for leg in ("lts", "gts"):
+        mode = P.MODE_GTS if leg == "gts" else P.MODE_LTS
+        sim = P.Sim(gm, "nlwave", P.FP64, "rk4", ko_sigma=cfg["ko_sigma"], device="cuda:0",
+                    nl_coeff=cfg["nl_coeff"])
+        sim.set_state(U0)
+        stream = torch.cuda.current_stream()
+        sim.advance(warmup, mode, graph=True, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        sim.advance(steps, mode, graph=True, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev = e0.elapsed_time(e1) / 1e3
+        nu = info["node_updates_gts" if leg == "gts" else "node_updates_lts"] * steps
+        out[leg] = {"rate": nu / wall, "ms_per_step": 1e3 * wall / steps, "event_s": ev}
+        del sim
+    a = 224 * info["node_updates_lts"] * steps / out["lts"]["event_s"] / 1e9
+    out["roofline"] = {"achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4),
+                       "bytes_per_node_update": 224}
+    out["measured_speedup"] = out["gts"]["ms_per_step"] / out["lts"]["ms_per_step"]
+    out["model_speedup_eq_invS"] = info["s_est"]
+    return out
 
 
 def cpu_baseline(spec, cfg, target_s=15.0):
@@ -453,6 +498,12 @@ def main():
         print(f"[bench] maxwell: {rate:.4e} node-updates/s, frac {a_m / HBM_PEAK_GBS:.3f}", file=sys.stderr,
               flush=True)
 
+    nl = None
+    if not args.no_nl and "lts" in legs:
+        nl = nl_leg(P, torch, max(1, min(args.steps, 8)), args.warmup)
+        print(f"[bench] nlwave: lts {nl['lts']['rate']:.4e}, gts {nl['gts']['rate']:.4e} node-updates/s, "
+              f"frac {nl['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
+
     batch = None
     if not args.no_batch:
         from paper_2011_10570_amd import serve
@@ -541,6 +592,8 @@ def main():
         out["gts_roofline"] = gts_roof
     if maxwell:
         out["maxwell"] = maxwell
+    if nl:
+        out["nlwave"] = nl
     if c3:
         out["c3"] = c3
     if batch:

@@ -268,6 +268,12 @@ lts_status lts_fused_stage_noalloc(lts_mesh* mesh, const lts_stage_view* view, i
  * depend on it.  LTS_EINVAL for other values. */
 lts_status lts_set_launch(int32_t threads, int32_t max_workgroups, int32_t stream_threads);
 lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups, int32_t* stream_threads);
+/* Launch shape of batched launches (lts_batch_*): threads per workgroup of their
+ * tile kernels (256 or 512, default 512) and the cap on their grids (default
+ * 4096; workgroups walk several tiles of the union).  Results do not depend on
+ * it; a captured round is redone when it changes. */
+lts_status lts_set_batch_launch(int32_t threads, int32_t max_workgroups);
+lts_status lts_get_batch_launch(int32_t* threads, int32_t* max_workgroups);
 
 /* ---- simulation driver (a7; Alg. 1 / Alg. 2) ---------------------------------- */
 lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, int32_t tableau,

@@ -21,7 +21,7 @@ __all__ = ["Mesh", "Sim", "build_mesh", "unzip", "rhs", "zip", "rk_stage", "fuse
            "norms", "copy_probe", "LTSError", "MODE_LTS", "MODE_GTS", "EQ_WAVE", "EQ_MAXWELL", "EQ_NLWAVE",
            "BOUNDARY_PERIODIC", "BOUNDARY_OUTER", "FP64", "FP32_RHS",
            "RK4", "SSPRK3", "Batch", "batch_advance", "set_launch", "get_launch", "fused_stage_noalloc",
-           "remesh_indicators", "remesh", "transfer"]
+           "remesh_indicators", "remesh", "transfer", "set_batch_launch", "get_batch_launch"]
 
 EQUATIONS = {"wave": EQ_WAVE, "maxwell": EQ_MAXWELL, "nlwave": EQ_NLWAVE}
 BOUNDARIES = {"periodic": BOUNDARY_PERIODIC, "outer": BOUNDARY_OUTER}
@@ -283,6 +283,16 @@ def set_launch(threads: int, max_workgroups: int, stream_threads: int = 512):
     """Launch shape of every later fused launch: threads of the LDS tile kernels and
     of the streaming kernel (256 or 512 each), grid cap in workgroups."""
     check(lib().lts_set_launch(int(threads), int(max_workgroups), int(stream_threads)), "lts_set_launch")
+
+
+def set_batch_launch(threads: int, max_workgroups: int):
+    check(lib().lts_set_batch_launch(int(threads), int(max_workgroups)), "lts_set_batch_launch")
+
+
+def get_batch_launch() -> tuple:
+    a, b = C.c_int32(), C.c_int32()
+    check(lib().lts_get_batch_launch(C.byref(a), C.byref(b)), "lts_get_batch_launch")
+    return a.value, b.value
 
 
 def get_launch() -> tuple:

@@ -89,6 +89,8 @@ PROTOTYPES = {
                                           C.POINTER(Position), _P]),
     "lts_set_launch": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
     "lts_get_launch": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lts_set_batch_launch": (C.c_int, [C.c_int32, C.c_int32]),
+    "lts_get_batch_launch": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lts_sim_create": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(RhsParams), C.POINTER(_P)]),
     "lts_sim_bind": (C.c_int, [_P, _P, _P]),
     "lts_advance": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P]),
@@ -127,6 +129,13 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2011_10570_amd.build`")
+        # torch bundles a HIP runtime with the same soname as the system one this
+        # library links: load torch's first, so that the process holds one HIP
+        # runtime (loaded the other way round, this library saw no device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in PROTOTYPES.items():
             fn = getattr(L, name)

@@ -559,6 +559,22 @@ lts_status lts_set_launch(int32_t threads, int32_t max_workgroups, int32_t strea
   return LTS_OK;
 }
 
+lts_status lts_set_batch_launch(int32_t threads, int32_t max_workgroups) {
+  clear_error();
+  if (threads != 256 && threads != 512) return fail(LTS_EINVAL, "threads must be 256 or 512");
+  if (max_workgroups < 8) return fail(LTS_EINVAL, "max_workgroups must be >= 8");
+  if (g_shape.batch_threads != threads || g_shape.batch_max_wg != max_workgroups) ++g_shape_gen;
+  g_shape.batch_threads = threads;
+  g_shape.batch_max_wg = max_workgroups;
+  return LTS_OK;
+}
+
+lts_status lts_get_batch_launch(int32_t* threads, int32_t* max_workgroups) {
+  if (threads) *threads = g_shape.batch_threads;
+  if (max_workgroups) *max_workgroups = g_shape.batch_max_wg;
+  return LTS_OK;
+}
+
 lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups, int32_t* stream_threads) {
   if (threads) *threads = g_shape.threads;
   if (max_workgroups) *max_workgroups = g_shape.max_wg;
@@ -1187,6 +1203,7 @@ struct lts_batch {
   int nused = 0;                // table entries [0, nused) are passed to the kernels
   int64_t round = 0;            // next round to run
   int64_t* d_round = nullptr;   // device copy of `round`, read by the kernels
+  int32_t* d_tab = nullptr;     // the round table [3][kMaxBatch + 1] (launch_batch_table)
   // one round captured as a graph (valid while the table and the shape stay)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -1304,15 +1321,20 @@ void round_totals(const lts_batch* b, int64_t r, bool any_round, int64_t total[3
 // sides, then the round counter.
 lts_status enqueue_round(lts_batch* b, const int64_t total[3], hipStream_t s) {
   const bool kf32 = b->prec == LTS_FP32_RHS;
+  // the round's table of cumulative active counts, once for all its launches
+  HIP_TRY(launch_batch_table(b->d_desc, b->nused, b->mode, b->d_round, b->d_tab, s), "batch round table");
+  LaunchShape bs = g_shape;
+  bs.threads = g_shape.batch_threads;
+  bs.max_wg = g_shape.batch_max_wg;
   for (int stg = 0; stg < b->p; ++stg) {
     StageParams sp;
     fill_batch_params(b, stg, sp);
-    HIP_TRY(launch_ghost_pre_batch(b->F, kf32, sp, b->d_desc, b->nused, b->d_round, total[2], b->d_gscr,
-                                   g_shape.max_wg, s),
+    HIP_TRY(launch_ghost_pre_batch(b->F, kf32, sp, b->d_desc, b->nused, b->d_round, total[2], b->d_gscr, b->d_tab,
+                                   bs.max_wg, s),
             "batch ghost pre-pass");
     for (int tt = 1; tt <= 2; ++tt)
       HIP_TRY(launch_fused_batch(tt, b->eq, kf32, sp, b->d_desc, b->nused, b->d_round, total[tt - 1], b->d_gscr,
-                                 g_shape, s),
+                                 b->d_tab, bs, s),
               "batch launch");
   }
   HIP_TRY(launch_increment(b->d_round, s), "round increment");
@@ -1353,6 +1375,7 @@ lts_status lts_batch_create(int32_t equation, int32_t precision, int32_t tableau
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc(&b->d_round, sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&b->d_tab, 3 * (kMaxBatch + 1) * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(b->d_round, 0, sizeof(int64_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -1498,6 +1521,7 @@ void lts_batch_destroy(lts_batch* b) {
   if (b->d_gscr) (void)hipFree(b->d_gscr);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_round) (void)hipFree(b->d_round);
+  if (b->d_tab) (void)hipFree(b->d_tab);
   if (b->staged) (void)hipEventDestroy(b->staged);
   if (b->done) (void)hipEventDestroy(b->done);
   if (b->d_desc) (void)hipFree(b->d_desc);

@@ -122,27 +122,13 @@ __global__ __launch_bounds__(256) void k_ghost_pre(StageParams sp, const int32_t
 template <bool KF32, int F>
 __global__ __launch_bounds__(256) void k_ghost_pre_batch(StageParams sp0, const BatchSim* __restrict__ sims,
                                                          int nsims, const int64_t* __restrict__ round,
-                                                         double* __restrict__ scr) {
+                                                         double* __restrict__ scr, const int32_t* __restrict__ cum_tab) {
   __shared__ GhostLds<F> L;
   __shared__ int cum[kMaxBatch + 1];
   ghost_init(L, sp0);
   const int64_t r = *round;
-  for (int s = threadIdx.x; s < nsims; s += blockDim.x) {
-    const BatchSim& b = sims[s];
-    const int64_t rr = r - b.r0;
-    int cnt = 0;
-    if (rr >= 0 && rr < b.rounds) {
-      const int j = (int)(rr & ((1 << (b.lmax - b.lmin)) - 1));
-      const int lo = (sp0.mode == LTS_MODE_GTS || j == 0) ? b.lmin : b.lmax - __builtin_ctz(j);
-      cnt = b.ghost_ge[lo];
-    }
-    cum[s + 1] = cnt;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    cum[0] = 0;
-    for (int s = 0; s < nsims; ++s) cum[s + 1] += cum[s];
-  }
+  // cumulative active ghost entries of this round (the round table)
+  for (int s = threadIdx.x; s <= nsims; s += blockDim.x) cum[s] = cum_tab[2 * (kMaxBatch + 1) + s];
   __syncthreads();
   const int total = cum[nsims];
   for (int q = blockIdx.x; q < total; q += gridDim.x) {
@@ -182,16 +168,17 @@ hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32
 }
 
 hipError_t launch_ghost_pre_batch(int F, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
-                                  const int64_t* round, int64_t total, double* scr, int max_wg, hipStream_t s) {
+                                  const int64_t* round, int64_t total, double* scr, const int32_t* cum_tab,
+                                  int max_wg, hipStream_t s) {
   if (total <= 0 || nsims <= 0) return hipSuccess;
   if (nsims > kMaxBatch) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, std::min(max_wg, kBatchMaxWg))));
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, max_wg)));
   if (F == 2) {
-    if (kf32) hipLaunchKernelGGL((k_ghost_pre_batch<true, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
-    else hipLaunchKernelGGL((k_ghost_pre_batch<false, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre_batch<true, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr, cum_tab);
+    else hipLaunchKernelGGL((k_ghost_pre_batch<false, 2>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr, cum_tab);
   } else if (F == 6) {
-    if (kf32) hipLaunchKernelGGL((k_ghost_pre_batch<true, 6>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
-    else hipLaunchKernelGGL((k_ghost_pre_batch<false, 6>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr);
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre_batch<true, 6>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr, cum_tab);
+    else hipLaunchKernelGGL((k_ghost_pre_batch<false, 6>), grid, dim3(256), 0, s, sp0, sims, nsims, round, scr, cum_tab);
   } else {
     return hipErrorInvalidValue;
   }

@@ -45,6 +45,9 @@ struct LaunchShape {
   int threads = 512;
   int max_wg = 65536;
   int stream_threads = 512;
+  // batched launches (lts_batch_*): threads of the tile kernels and grid cap
+  int batch_threads = 512;
+  int batch_max_wg = 4096;
 };
 
 // Tiles of one launch cut into 8 contiguous ranges, one per XCD: XCD x walks
@@ -57,8 +60,7 @@ struct XcdRanges {
 // r0 from coarse step n0 and takes part in `rounds` rounds; round r is its
 // substep (r - r0) mod 2^(lmax-lmin) of coarse step n0 + (r - r0) div 2^(lmax-lmin).
 constexpr int kMaxBatch = 256;
-// Grid cap of batched launches: every workgroup of one first prefix-sums the
-// active counts of all simulations of the batch, so it should walk many tiles.
+// Default grid cap of batched launches (lts_set_batch_launch changes it).
 constexpr int kBatchMaxWg = 4096;
 struct BatchSim {
   double* U;                     // [2][F][N][125]
@@ -88,12 +90,18 @@ hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32
 // sims[0..nsims) (device table); `total` bounds the union of their active side-tt
 // tiles and sizes the grid (host-computed; any larger value is correct too).
 hipError_t launch_fused_batch(int tt, int eq, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
-                              const int64_t* round, int64_t total, const double* scr, const LaunchShape& ls,
+                              const int64_t* round, int64_t total, const double* scr, const int32_t* cum_tab,
+                              const LaunchShape& ls, hipStream_t s);
+// The round table of a batch: the exclusive prefix sums of the active side-1
+// tiles, side-2 tiles and ghost entries of every simulation in round *round, into
+// tab[3][kMaxBatch + 1] (read by the round's batched launches).
+hipError_t launch_batch_table(const BatchSim* sims, int nsims, int mode, const int64_t* round, int32_t* tab,
                               hipStream_t s);
 // The batch's ghost pre-pass of one stage: the union (at most `total` entries)
 // of the active ghost entries of every simulation, into scr at each gbase.
 hipError_t launch_ghost_pre_batch(int F, bool kf32, const StageParams& sp0, const BatchSim* sims, int nsims,
-                                  const int64_t* round, int64_t total, double* scr, int max_wg, hipStream_t s);
+                                  const int64_t* round, int64_t total, double* scr, const int32_t* cum_tab,
+                                  int max_wg, hipStream_t s);
 // Streamed whole 4^3 blocks (side-4 tiles, wave equation) over the launch's
 // tiles (XCD ranges as for launch_fused), ghosts from the ghost table scr.
 hipError_t launch_stream(int eq, bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,

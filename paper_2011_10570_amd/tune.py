@@ -1,4 +1,4 @@
-"""Launch-shape autotuner of the fused stage kernels.
+"""Launch-shape autotuner of the fused stage kernels (one mesh, and batches).
 
 The shape of a fused launch (tile side t: 1 or 2 for LDS-resident tiles, 4 for
 streamed whole blocks; workgroup sizes of the tile and streaming kernels; cap on
@@ -15,7 +15,7 @@ from __future__ import annotations
 import itertools
 from typing import Dict, Iterable, Optional, Tuple
 
-from . import MODE_LTS, Sim, get_launch, set_launch
+from . import MODE_LTS, Batch, Sim, get_batch_launch, get_launch, set_batch_launch, set_launch
 
 _CACHE: Dict[tuple, tuple] = {}
 
@@ -88,6 +88,77 @@ def tune(mesh, U0, equation: str = "wave", precision: int = 0, tableau: str = "r
     best, ms = min(table, key=lambda r: r[1])
     mesh.set_tile(best[0])
     set_launch(best[1], best[2], best[3])
+    _CACHE[key] = (best, ms)
+    return {"best": best, "ms": ms, "table": table}
+
+
+def tune_batch(meshes, states, equation: str = "wave", precision: int = 0, tableau: str = "rk4",
+               mode: int = MODE_LTS, tiles: Iterable[int] = (1, 2), threads: Iterable[int] = (256, 512),
+               max_workgroups: Iterable[int] = (1024, 2048, 4096, 8192, 16384), n_coarse: int = 1,
+               reps: int = 1, check: bool = True, ko_sigma: float = 0.1, device: str = "cuda",
+               use_cache: bool = True) -> dict:
+    """Batched launches: time every (tile side of all meshes, threads, grid cap)
+    candidate on the batch of (meshes[i], states[i]) advanced n_coarse coarse steps
+    together (graph-captured rounds, after one untimed warm-up drain), check that
+    every candidate gives bitwise the same states, and apply the fastest
+    (mesh.set_tile on every mesh + set_batch_launch).  Cached per batch
+    composition.  Returns {"best", "ms", "table"}."""
+    import torch
+    key = ("batch",) + tuple(_key(m, equation, precision, tableau, mode) for m in meshes)
+    if use_cache and key in _CACHE:
+        best, ms = _CACHE[key]
+        for m in meshes:
+            m.set_tile(best[0])
+        set_batch_launch(best[1], best[2])
+        return {"best": best, "ms": ms, "table": None}
+    if equation == "maxwell":
+        tiles = [t for t in tiles if t == 1]
+    old_tiles = [m.info()["tile"] for m in meshes]
+    old_shape = get_batch_launch()
+    table = []
+    ref = {}
+    try:
+        for t, nt, wg in itertools.product(list(tiles), list(threads), list(max_workgroups)):
+            for m in meshes:
+                m.set_tile(t)
+            set_batch_launch(nt, wg)
+            times = []
+            outs = None
+            for r in range(reps + 1):       # the first pass captures the round graph and warms up
+                sims = []
+                for m, st in zip(meshes, states):
+                    sim = Sim(m, equation, precision, tableau, ko_sigma=ko_sigma, device=device)
+                    sim.set_state(st)
+                    sims.append(sim)
+                b = Batch(equation, precision, tableau, mode, capacity=max(1, len(sims)))
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for sim in sims:
+                    b.attach(sim, n_coarse)
+                b.drain()
+                e1.record()
+                e1.synchronize()
+                if r > 0:
+                    times.append(e0.elapsed_time(e1))
+                outs = [sim.current() for sim in sims]
+                del b, sims
+            if check:
+                k = t if precision != 0 else 0
+                if k not in ref:
+                    ref[k] = outs
+                elif not all(torch.equal(a, c) for a, c in zip(outs, ref[k])):
+                    raise RuntimeError(f"batch launch shape {(t, nt, wg)} changed the result")
+            table.append(((t, nt, wg), min(times)))
+    except Exception:
+        for m, t in zip(meshes, old_tiles):
+            m.set_tile(t)
+        set_batch_launch(*old_shape)
+        raise
+    best, ms = min(table, key=lambda r: r[1])
+    for m in meshes:
+        m.set_tile(best[0])
+    set_batch_launch(best[1], best[2])
     _CACHE[key] = (best, ms)
     return {"best": best, "ms": ms, "table": table}
 

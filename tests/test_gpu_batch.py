@@ -72,22 +72,50 @@ def test_batch_equals_alone(meshes, mode, prec):
         assert torch.equal(s.current(), w)
 
 
-def test_batch_walked_tiles(meshes):
-    """A batch under a small grid cap (each workgroup walks many tiles and ghost
-    entries) equals the default launch shape, bitwise."""
-    old = P.get_launch()
+@pytest.mark.parametrize("threads,cap", [(512, 16), (256, 16), (256, 4096), (512, 100000)])
+def test_batch_walked_tiles(meshes, threads, cap):
+    """A batch under another batch launch shape (a small grid cap: each workgroup
+    walks many tiles and ghost entries; 256-thread workgroups) equals the
+    default shape, bitwise; the one-mesh launch shape does not affect batches."""
+    old, old_one = P.get_batch_launch(), P.get_launch()
     try:
-        P.set_launch(512, 65536, 512)
+        assert old == (512, 4096)
         sims = [_sim(gm, t, U0) for gm, t, U0 in meshes]
         P.batch_advance(sims, 1, P.MODE_LTS)
         want = [s.current() for s in sims]
-        P.set_launch(512, 16, 512)
+        P.set_batch_launch(threads, cap)
+        P.set_launch(256, 16, 256)
         sims = [_sim(gm, t, U0) for gm, t, U0 in meshes]
         P.batch_advance(sims, 1, P.MODE_LTS)
         for s, w in zip(sims, want):
             assert torch.equal(s.current(), w)
     finally:
-        P.set_launch(*old)
+        P.set_batch_launch(*old)
+        P.set_launch(*old_one)
+
+
+def test_tune_batch_bitwise(meshes):
+    """The batch autotuner times every candidate, checks each gives bitwise the
+    same states (it raises otherwise), applies the fastest, and caches it."""
+    from paper_2011_10570_amd import tune
+    old = P.get_batch_launch()
+    tiles_before = [gm.info()["tile"] for gm, _, _ in meshes]
+    try:
+        ms = [gm for gm, _, _ in meshes[:4]]
+        st = [U0 for _, _, U0 in meshes[:4]]
+        tune.clear_cache()
+        r = tune.tune_batch(ms, st, threads=(256, 512), max_workgroups=(512, 4096))
+        assert len(r["table"]) == 2 * 2 * 2
+        best = r["best"]
+        assert P.get_batch_launch() == (best[1], best[2])
+        assert all(m.info()["tile"] == best[0] for m in ms)
+        r2 = tune.tune_batch(ms, st)
+        assert r2["table"] is None and r2["best"] == best
+    finally:
+        tune.clear_cache()
+        P.set_batch_launch(*old)
+        for (gm, _, _), t in zip(meshes, tiles_before):
+            gm.set_tile(t)
 
 
 def test_batch_matches_oracle():

@@ -190,6 +190,23 @@ def test_launch_shape_defaults_and_validation():
     assert P.get_launch() == old
 
 
+def test_batch_launch_shape_defaults_and_validation():
+    """lts_set_batch_launch / lts_get_batch_launch: the defaults, a round trip,
+    independence from the one-mesh shape, and rejection of unsupported shapes."""
+    old, old_one = P.get_batch_launch(), P.get_launch()
+    try:
+        assert old == (512, 4096)
+        P.set_batch_launch(256, 1024)
+        assert P.get_batch_launch() == (256, 1024) and P.get_launch() == old_one
+        for bad in ((128, 1024), (384, 1024), (1024, 1024), (512, 4), (512, 0)):
+            with pytest.raises(P.LTSError):
+                P.set_batch_launch(*bad)
+            assert P.get_batch_launch() == (256, 1024)
+    finally:
+        P.set_batch_launch(*old)
+    assert P.get_batch_launch() == old
+
+
 def test_arrays_beyond_32bit_offsets_rejected():
     """The kernels address field arrays with 32-bit element offsets: a simulation
     whose stage arrays (p x F x N x 125 elements) reach 2^31 is refused before any
