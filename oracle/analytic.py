@@ -5,7 +5,7 @@ Paper passages:
     (eqs. chi, phi); its 1D solution chi = (f(x - t) + f(x + t)) / 2.
   * Sec. 4.3: accuracy is measured as the discrete l2 error against the analytic
     solution.  Reading: the l2 norm is volume weighted over the DG nodes,
-    sqrt(sum_o W_o^3 sum_n e^2 / (125 sum_o W_o^3)), W_o the octant width.
+    sqrt(sum_o W_o^3 sum_n e^2 / (n^3 sum_o W_o^3)), W_o the octant width, n^3 nodes per octant.
 
 The Gaussian pulse u0 = A exp(-r^2/(2 sigma^2)), v0 = 0 evolves as the spherical
 wave u = (phi(r+t) + phi(r-t)) / (2r), phi(xi) = xi g(xi) (d'Alembert applied to
@@ -243,10 +243,11 @@ def fourier_mode_solution(order: int, n, h: float, dt: float, nsteps: int, sigma
 
 # ----------------------------------------------------------------------------- norms
 def norms(err: np.ndarray, levels: np.ndarray, L: int):
-    """Per field volume-weighted l2 and max norms of err [F][N][5][5][5]."""
+    """Per field volume-weighted l2 and max norms of err [F][N][n][n][n]."""
     w = (2.0 ** (L - np.asarray(levels, dtype=np.float64))) ** 3
     e2 = (err.reshape(err.shape[0], err.shape[1], -1) ** 2).sum(axis=2)      # [F, N]
-    l2 = np.sqrt((e2 * w[None, :]).sum(axis=1) / (125.0 * w.sum()))
+    nn = err.reshape(err.shape[0], err.shape[1], -1).shape[2]                 # nodes per octant
+    l2 = np.sqrt((e2 * w[None, :]).sum(axis=1) / (nn * w.sum()))
     linf = np.abs(err).reshape(err.shape[0], -1).max(axis=1)
     return l2, linf
 

@@ -10,7 +10,8 @@ prints no stencil.  Readings:
     -20, 15, -6, 1) per axis, i.e. sigma h^5 / 64 * D+^3 D-^3, which is
     non-positive in Fourier space (dissipative) and fits three ghost layers;
   * coarse->fine interpolation (Sec. 3.3 "coarser to finer interpolation"):
-    tensor degree-4 Lagrange on the coarse leaf's own 5 nodes per axis;
+    tensor degree n-1 Lagrange on the coarse leaf's own n nodes per axis (n = 5
+    or 7 nodes per octant side);
   * on a bounded domain (the non-linear wave with radiative boundary of
     Sec. 4.2): centred stencils of reduced order next to the faces and one-sided
     fourth-order first differences on them (the paper gives the radiative
@@ -47,9 +48,10 @@ def lagrange_weights_fr(xi: Fr, n: int = 5) -> List[Fr]:
     return w
 
 
-def lagrange_weights(xi2: int) -> np.ndarray:
-    """float64 weights for the position xi = xi2 / 2 (xi2 integer in [0, 8])."""
-    return np.array([float(x) for x in lagrange_weights_fr(Fr(int(xi2), 2))])
+def lagrange_weights(xi2: int, n: int = 5) -> np.ndarray:
+    """float64 weights on nodes 0..n-1 for the position xi = xi2 / 2 (xi2 integer
+    in [0, 2n-2])."""
+    return np.array([float(x) for x in lagrange_weights_fr(Fr(int(xi2), 2), n)])
 
 
 def _axis_stencil(f: np.ndarray, w: np.ndarray, axis: int, m4: int) -> np.ndarray:

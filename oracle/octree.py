@@ -6,11 +6,14 @@ Paper passages:
   * Sec. 3.2.2 (construction/refinement): refine while a criterion holds.  The
     paper's wavelet criterion is replaced by integer geometric criteria so that
     meshes are bit-exact (ball / annulus around a point).
-  * Sec. 3.2.3 (2:1 balance) extended to ghost reach: a leaf of level l is split
-    when a leaf of level >= l+2 lies within three grid spacings of it.  With 5^3
-    nodes per octant and three ghost layers this keeps every ghost source within
-    one level of the receiver, which the paper's time-gap argument (Sec. 3.6.3)
-    assumes.
+  * Sec. 3.2.3 (2:1 balance).  Octants carry n^3 nodes, n = 5 or 7 (the paper's
+    runs use 7^3, Sec. 4.5 / fig. of the mesh generation).  The three ghost layers
+    of the sixth-order stencils reach 3/(n-1) of a neighbouring octant: half of it
+    for n = 7, where the paper's 2:1 balance (face, edge and corner) keeps every
+    ghost source within one level of the receiver, as the time-gap argument of
+    Sec. 3.6.3 assumes.  For n = 5 the reach is 3/4 of an octant, so the balance
+    is extended to ghost reach: a leaf of level l is split when a leaf of level
+    >= l+2 lies within three grid spacings of it.
   * Sec. 3.2.5 + fig. oct_to_blocks (octree to block decomposition): a block is a
     maximal uniformly refined sub-tree, split into aligned cubes of at most
     ``cap`` octants per side.
@@ -19,12 +22,14 @@ Paper passages:
   * Sec. 3.6.3 + fig. blk_loop: level-frequency schedule.
   * Sec. 3.7, eqs. w_nuts, w_uts, invS: speedup model.
 
-Geometry (integer "node units" at the finest level L of the spec):
+Geometry (integer "node units" at the finest level L of the spec), with
+n nodes per octant side and ni = n - 1 intervals:
   domain [-1, 1]^3, periodic (default) or bounded by the outer faces (boundary
-  "outer", the radiative boundary of Sec. 4.2); N_u = 4 * 2^L node units per
+  "outer", the radiative boundary of Sec. 4.2); N_u = ni * 2^L node units per
   side, x = -1 + 2 X / N_u.
   A leaf has an anchor a (in level-L octant units, a multiple of s = 2^(L-l)) and a
-  level l; its 5 nodes per axis sit at 4 a + i s, i = 0..4; spacing h_l = 2^(-l-1).
+  level l; its n nodes per axis sit at ni a + i s, i = 0..ni; spacing
+  h_l = 2^(1-l) / ni (2^(-l-1) for n = 5).
 """
 from __future__ import annotations
 
@@ -34,7 +39,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 from scipy.ndimage import maximum_filter1d
 
-NODES = 5          # nodes per octant side
+NODES = 5          # default nodes per octant side (5 or 7)
 GHOST = 3          # ghost layers of the sixth-order stencils
 
 KIND_OWN, KIND_SAME, KIND_FINE, KIND_COARSE, KIND_NONE = 0, 1, 2, 3, 4   # NONE: outside the domain
@@ -79,6 +84,7 @@ class MeshSpec:
     criteria: List[Criterion] = field(default_factory=list)
     block_cap: int = 4
     boundary: str = "periodic"      # "periodic" or "outer"
+    nodes: int = NODES              # nodes per octant side: 5 or 7
 
     @property
     def periodic(self) -> bool:
@@ -94,7 +100,10 @@ class MeshSpec:
         b = d.get("boundary", "periodic")
         if b not in ("periodic", "outer"):
             raise ValueError(f"unknown boundary {b}")
-        return MeshSpec(int(d["l_min"]), int(d["l_max"]), crit, int(d.get("block_cap", 4)), b)
+        n = int(d.get("nodes", NODES))
+        if n not in (5, 7):
+            raise ValueError(f"nodes per octant side must be 5 or 7, not {n}")
+        return MeshSpec(int(d["l_min"]), int(d["l_max"]), crit, int(d.get("block_cap", 4)), b, n)
 
 
 def _periodic_min_dist(lo, hi, c, n):
@@ -127,15 +136,18 @@ def _periodic_max_dist(lo, hi, c, n):
     return np.where(inside, n // 2, ends)
 
 
-def criterion_holds(crit: Criterion, anchors: np.ndarray, level: int, L: int, periodic: bool = True) -> np.ndarray:
+def criterion_holds(crit: Criterion, anchors: np.ndarray, level: int, L: int, periodic: bool = True,
+                    nodes: int = NODES) -> np.ndarray:
     """Evaluate a criterion for leaves of one level (Sec. 3.2.2, reading in module doc).
-    Distances are periodic (nearest image) or, for a bounded domain, plain."""
+    Distances are periodic (nearest image) or, for a bounded domain, plain, in the
+    node units of a mesh of `nodes` nodes per octant side."""
     if len(anchors) == 0:
         return np.zeros(0, dtype=bool)
-    n = 4 * (1 << L)
+    ni = nodes - 1
+    n = ni * (1 << L)
     s = 1 << (L - level)
-    lo = 4 * anchors.astype(np.int64)
-    hi = lo + 4 * s
+    lo = ni * anchors.astype(np.int64)
+    hi = lo + ni * s
     c = np.asarray(crit.center, dtype=np.int64)[None, :]
     if periodic:
         dmin2 = (_periodic_min_dist(lo, hi, c, n) ** 2).sum(axis=1)
@@ -196,7 +208,7 @@ def refine(spec: MeshSpec) -> Tuple[np.ndarray, np.ndarray]:
             break
         split = np.zeros(len(cur), dtype=bool)
         for crit in spec.criteria:
-            split |= criterion_holds(crit, cur, lev, L, spec.periodic)
+            split |= criterion_holds(crit, cur, lev, L, spec.periodic, spec.nodes)
         keep_a.append(cur[~split]); keep_l.append(np.full(int((~split).sum()), lev, np.int64))
         cur = _children(cur[split], lev, L)
         if len(cur) == 0:
@@ -218,15 +230,17 @@ def level_grid(anchors: np.ndarray, levels: np.ndarray, L: int) -> np.ndarray:
     return g
 
 
-def _window_max(grid: np.ndarray, s: int, periodic: bool = True) -> np.ndarray:
-    """max over cells [a-1-f, a+s+f]^3 around every anchor a, f = floor(3 s / 4).
+def _window_max(grid: np.ndarray, s: int, periodic: bool = True, reach: bool = True) -> np.ndarray:
+    """max over cells [a-1-f, a+s+f]^3 around every anchor a.
 
-    These are exactly the level-L cells whose closed box meets the closed box of a
-    level-l leaf (width 4 s node units) grown by 3 h_l = 3 s node units.  A centred
+    reach (5 nodes per side): f = floor(3 s / 4); these are exactly the level-L
+    cells whose closed box meets the closed box of a level-l leaf (width 4 s node
+    units) grown by 3 h_l = 3 s node units.  Without reach (2:1 balance, 7 nodes
+    per side): f = 0, the cells whose closed box meets the leaf's.  A centred
     window of even size s + 2f + 2 read at a + s/2 covers that range.  A bounded
     domain has no cells beyond its faces (padding -1 is below every level).
     """
-    f = (3 * s) // 4
+    f = (3 * s) // 4 if reach else 0
     size = s + 2 * f + 2
     out = grid
     for ax in range(3):
@@ -240,9 +254,12 @@ def _window_max(grid: np.ndarray, s: int, periodic: bool = True) -> np.ndarray:
     return out
 
 
-def balance(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = True) -> Tuple[np.ndarray, np.ndarray]:
-    """Ghost-reach balance (Sec. 3.2.3 extended): split any leaf a of level l for
-    which some leaf of level >= l+2 has periodic Chebyshev box distance <= 3 h_l.
+def balance(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = True,
+            nodes: int = NODES) -> Tuple[np.ndarray, np.ndarray]:
+    """Balance (Sec. 3.2.3).  5 nodes per side: ghost-reach balance, split any leaf
+    a of level l for which some leaf of level >= l+2 has periodic Chebyshev box
+    distance <= 3 h_l.  7 nodes per side: 2:1 balance, the same with distance 0
+    (a leaf of level >= l+2 touching a at a face, edge or corner).
 
     Iterated to the fixpoint.  Every split is forced in any balanced refinement of
     the current tree, so the result is the unique minimal balanced refinement.
@@ -260,7 +277,7 @@ def balance(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = Tr
             if len(sel) == 0:
                 continue
             s = 1 << (L - lev)
-            wm = _window_max(grid, s, periodic)
+            wm = _window_max(grid, s, periodic, nodes == 5)
             pos = (anchors[sel] + s // 2) % n
             mx = wm[pos[:, 0], pos[:, 1], pos[:, 2]]
             split_mask[sel[mx >= lev + 2]] = True
@@ -277,11 +294,13 @@ def balance(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = Tr
             return anchors, levels
 
 
-def is_balanced_bruteforce(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = True) -> bool:
+def is_balanced_bruteforce(anchors: np.ndarray, levels: np.ndarray, L: int, periodic: bool = True,
+                           nodes: int = NODES) -> bool:
     """O(N^2) check of the balance predicate (for small meshes in tests)."""
-    n = 4 * (1 << L)
-    lo = 4 * anchors.astype(np.int64)
-    w = 4 * (1 << (L - levels.astype(np.int64)))
+    ni = nodes - 1
+    n = ni * (1 << L)
+    lo = ni * anchors.astype(np.int64)
+    w = ni * (1 << (L - levels.astype(np.int64)))
     hi = lo + w[:, None]
     for a in range(len(levels)):
         h = 1 << (L - int(levels[a]))
@@ -292,7 +311,7 @@ def is_balanced_bruteforce(anchors: np.ndarray, levels: np.ndarray, L: int, peri
         for k in ((-1, 0, 1) if periodic else (0,)):
             g = np.maximum(0, np.maximum(lo[cand] + k * n - hi[a], lo[a] - (hi[cand] + k * n)))
             gap = np.minimum(gap, g)
-        if (gap.max(axis=1) <= 3 * h).any():
+        if (gap.max(axis=1) <= (3 * h if nodes == 5 else 0)).any():
             return False
     return True
 
@@ -306,6 +325,12 @@ class Mesh:
     blocks: np.ndarray          # [B, 6] first_leaf, m, level, ax, ay, az (level-L units)
     cap: int
     periodic: bool = True       # False: bounded by the outer faces of [-1, 1]^3
+    nodes: int = NODES          # nodes per octant side (5 or 7)
+
+    @property
+    def ni(self) -> int:
+        """Node intervals per octant side."""
+        return self.nodes - 1
 
     @property
     def n_oct(self) -> int:
@@ -386,19 +411,20 @@ def build_blocks(anchors: np.ndarray, levels: np.ndarray, L: int, cap: int) -> n
 def build_mesh(spec: MeshSpec) -> Mesh:
     """Refinement, balance, blocks (Sec. 3.2.2 -> 3.2.3 -> 3.2.5)."""
     a, l = refine(spec)
-    a, l = balance(a, l, spec.l_max, spec.periodic)
+    a, l = balance(a, l, spec.l_max, spec.periodic, spec.nodes)
     blk = build_blocks(a, l, spec.l_max, spec.block_cap)
-    return Mesh(spec.l_max, a, l, blk, spec.block_cap, spec.periodic)
+    return Mesh(spec.l_max, a, l, blk, spec.block_cap, spec.periodic, spec.nodes)
 
 
-def mesh_from_leaves(anchors, levels, L: int, cap: int = 4, do_balance: bool = True, periodic: bool = True) -> Mesh:
+def mesh_from_leaves(anchors, levels, L: int, cap: int = 4, do_balance: bool = True, periodic: bool = True,
+                     nodes: int = NODES) -> Mesh:
     a = np.asarray(anchors, dtype=np.int64).reshape(-1, 3)
     l = np.asarray(levels, dtype=np.int64).reshape(-1)
     a, l = _sort(a, l)
     level_grid(a, l, L)  # validates the tiling
     if do_balance:
-        a, l = balance(a, l, L, periodic)
-    return Mesh(L, a, l, build_blocks(a, l, L, cap), cap, periodic)
+        a, l = balance(a, l, L, periodic, nodes)
+    return Mesh(L, a, l, build_blocks(a, l, L, cap), cap, periodic, nodes)
 
 
 # ----------------------------------------------------------------------------- unzip map
@@ -413,35 +439,41 @@ def block_octants(mesh: Mesh, b: int) -> np.ndarray:
 def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
     """Canonical source of every padded point of block b (Sec. 3.3, fig. unzip).
 
-    Returns int64 [S^3, 5] rows (leaf, kind, 2*px, 2*py, 2*pz), S = 4m+7, points in
-    lexicographic order of Q in [-3, 4m+3]^3 with x fastest; (px, py, pz) is the
-    position in the source leaf's node units (half-integers only for kind COARSE).
+    Returns int64 [S^3, 5] rows (leaf, kind, 2*px, 2*py, 2*pz), S = ni m + 7
+    (ni = nodes - 1 intervals per octant side), points in lexicographic order of
+    Q in [-3, ni m + 3]^3 with x fastest; (px, py, pz) is the position in the
+    source leaf's node units (half-integers only for kind COARSE).
 
     Ownership rule (the paper is silent on points shared by several leaves), per
-    axis on the receiver-level grid (node spacing h_lam, 4 per octant):
-      cell = -1 if Q < 0;  min(Q >> 2, m-1) if 0 <= Q <= 4m;  m if Q > 4m,
-      nu = Q - 4 cell in [0, 4],
+    axis on the receiver-level grid (node spacing h_lam, ni per octant):
+      cell = -1 if Q < 0;  min(Q // ni, m-1) if 0 <= Q <= ni m;  m if Q > ni m,
+      nu = Q - ni cell in [0, ni],
     i.e. the block's closed box is cut along its own octant grid (its upper faces
     belong to its last octants) and outside it the cells are half-open.  The
     receiver-level cell (cx, cy, cz) is then
       * one of the block's octants (OWN): node nu;
       * one same-level leaf (SAME): node nu;
-      * 8 leaves one level finer (FINE): child c = min(nu >> 1, 1) per axis, fine
-        node 2 (nu - 2c)  (injection of the coincident fine node);
+      * leaves one level finer (FINE): per axis a child c and the fine node
+        2 (nu - c ni/2) (injection of the coincident fine node).  5 nodes:
+        c = min(nu >> 1, 1), and all 8 children are leaves.  7 nodes: c = 1 if
+        nu > 3, 0 if nu < 3, and on the mid-plane nu = 3 the child next to the
+        block (c = 1 below it, 0 above): the children next to the block are the
+        ones that 2:1 balance keeps leaves (the others may be refined further);
       * one octant (child bits beta) of a leaf one level coarser (COARSE): position
-        (4 beta + nu) / 2 in its node units (interpolated when odd);
+        (ni beta + nu) / 2 in its node units (interpolated when odd);
       * on a bounded domain, a cell beyond the outer faces (NONE, leaf -1): the
         block's stencils there switch to the boundary closure and read no value.
     """
     first, m, lev = int(mesh.blocks[b, 0]), int(mesh.blocks[b, 1]), int(mesh.blocks[b, 2])
+    ni = mesh.ni
     s = 1 << (mesh.L - lev)
     base = mesh.blocks[b, 3:6] // s          # block anchor in level-lev units
-    S = 4 * m + 7
-    q = np.arange(-3, 4 * m + 4, dtype=np.int64)
+    S = ni * m + 7
+    q = np.arange(-3, ni * m + 4, dtype=np.int64)
     Qz, Qy, Qx = np.meshgrid(q, q, q, indexing="ij")
     Q = np.stack([Qx.ravel(), Qy.ravel(), Qz.ravel()], axis=1)  # [S^3, 3]
-    cell = np.where(Q < 0, -1, np.where(Q <= 4 * m, np.minimum(Q >> 2, m - 1), m))
-    nu = Q - 4 * cell
+    cell = np.where(Q < 0, -1, np.where(Q <= ni * m, np.minimum(Q // ni, m - 1), m))
+    nu = Q - ni * cell
     out = np.zeros((S ** 3, 5), dtype=np.int64)
     inside = ((cell >= 0) & (cell <= m - 1)).all(axis=1)
     if not mesh.periodic:
@@ -461,11 +493,13 @@ def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
     gi = np.nonzero(~inside & ~outside)[0]
     cells = base[None, :] + cell[gi]
     nug = nu[gi]
+    below = cell[gi] < 0                      # per axis: the cell lies below the block
     uniq, inv = np.unique(cells, axis=0, return_inverse=True)
     inv = inv.reshape(-1)
     for u_i, c in enumerate(uniq):
         rows = gi[inv == u_i]
         nur = nug[inv == u_i]
+        blw = below[inv == u_i]
         same = mesh.find(lev, c)
         if same >= 0:
             out[rows, 0] = same
@@ -477,19 +511,30 @@ def unzip_map(mesh: Mesh, b: int) -> np.ndarray:
             beta = np.asarray(c) & 1
             out[rows, 0] = coarse
             out[rows, 1] = KIND_COARSE
-            out[rows, 2:5] = 4 * beta[None, :] + nur
+            out[rows, 2:5] = ni * beta[None, :] + nur
             continue
-        ch0 = mesh.find(lev + 1, 2 * c)
-        if ch0 < 0:
-            raise ValueError(f"unbalanced mesh: no ghost source for block {b} cell {c}")
-        for k in range(8):
-            cc = 2 * c + np.array([k & 1, (k >> 1) & 1, (k >> 2) & 1])
-            if mesh.find(lev + 1, cc) != ch0 + k:
-                raise ValueError(f"unbalanced mesh: cell {c} of block {b} is not 8 finer leaves")
-        cb = np.minimum(nur >> 1, 1)
-        out[rows, 0] = ch0 + cb[:, 0] + 2 * cb[:, 1] + 4 * cb[:, 2]
+        if ni == 4:
+            # the padding reaches 3/4 into the cell: all 8 children are leaves
+            ch0 = mesh.find(lev + 1, 2 * c)
+            if ch0 < 0:
+                raise ValueError(f"unbalanced mesh: no ghost source for block {b} cell {c}")
+            for k in range(8):
+                cc = 2 * c + np.array([k & 1, (k >> 1) & 1, (k >> 2) & 1])
+                if mesh.find(lev + 1, cc) != ch0 + k:
+                    raise ValueError(f"unbalanced mesh: cell {c} of block {b} is not 8 finer leaves")
+            cb = np.minimum(nur >> 1, 1)
+            out[rows, 0] = ch0 + cb[:, 0] + 2 * cb[:, 1] + 4 * cb[:, 2]
+        else:
+            # the padding reaches half-way into the cell: only the children next to
+            # the block are read, and 2:1 balance keeps exactly those leaves
+            cb = np.where(2 * nur > ni, 1, np.where(2 * nur < ni, 0, blw.astype(np.int64)))
+            for r, cbr in zip(rows, cb):
+                lf = mesh.find(lev + 1, 2 * c + cbr)
+                if lf < 0:
+                    raise ValueError(f"unbalanced mesh: no ghost source for block {b} cell {c}")
+                out[r, 0] = lf
         out[rows, 1] = KIND_FINE
-        out[rows, 2:5] = 2 * (2 * (nur - 2 * cb))
+        out[rows, 2:5] = 2 * (2 * nur - ni * cb)
     return out
 
 
@@ -509,9 +554,14 @@ def active_blocks(mesh: Mesh, j: int, mode: str = "lts") -> np.ndarray:
     return np.nonzero(j % r == 0)[0]
 
 
-def dt_level(level) -> float:
-    """dt_l = 0.25 h_l with h_l = 2^(-l-1) (CFL 0.25, Sec. 3.6)."""
-    return 2.0 ** (-int(level) - 3)
+def h_level(level, nodes: int = NODES) -> float:
+    """Node spacing h_l = 2^(1-l) / (nodes - 1) of a level-l octant of [-1, 1]^3."""
+    return 2.0 ** (1 - int(level)) / (nodes - 1)
+
+
+def dt_level(level, nodes: int = NODES) -> float:
+    """dt_l = 0.25 h_l (CFL 0.25, Sec. 3.6): 2^(-l-3) for 5 nodes per side."""
+    return 0.25 * h_level(level, nodes)
 
 
 def speedup_model(mesh: Mesh) -> dict:
@@ -519,7 +569,7 @@ def speedup_model(mesh: Mesh) -> dict:
     Lspan = mesh.lmax - mesh.lmin
     alpha = np.zeros(Lspan + 1, dtype=np.int64)
     for lev in range(mesh.lmin, mesh.lmax + 1):
-        alpha[mesh.lmax - lev] = NODES ** 3 * int((mesh.levels == lev).sum())
+        alpha[mesh.lmax - lev] = mesh.nodes ** 3 * int((mesh.levels == lev).sum())
     w_lts = int(sum((1 << (Lspan - l)) * int(alpha[l]) for l in range(Lspan + 1)))
     w_gts = int((1 << Lspan) * int(alpha.sum()))
     inv_s = sum(float(alpha[l]) / 2 ** l for l in range(Lspan + 1)) / float(alpha.sum())

@@ -24,8 +24,9 @@ Readings:
     record (U0, K_1..K_p, start time, step) stays readable by neighbours until the
     block starts its next step.
 
-Layouts (identical to the library's so that arrays compare directly):
-  U[2][F][N][5][5][5] and K[p][F][N][5][5][5], node index [k][j][i], i fastest.
+Layouts (identical to the library's so that arrays compare directly), n = 5 or
+7 nodes per octant side:
+  U[2][F][N][n][n][n] and K[p][F][N][n][n][n], node index [k][j][i], i fastest.
 """
 from __future__ import annotations
 
@@ -35,13 +36,13 @@ from typing import Dict, List, Optional
 import numpy as np
 
 from . import fd
-from .octree import (GHOST, KIND_COARSE, KIND_NONE, KIND_OWN, NODES, Mesh, active_blocks, block_octants,
-                     dt_level, substeps, unzip_map)
+from .octree import (GHOST, KIND_COARSE, KIND_NONE, KIND_OWN, Mesh, active_blocks, block_octants, dt_level,
+                     h_level, substeps, unzip_map)
 from .rk import CASES, TABLEAUS, a_f64, b_f64, weight_table_f64
 
 
-#: Lagrange weights for the positions xi = 0, 1/2, ..., 4 (index 2 xi).
-LAGRANGE = np.stack([fd.lagrange_weights(v) for v in range(9)])
+#: Lagrange weights on n = 5 or 7 nodes for the positions xi = 0, 1/2, ..., n-1 (index 2 xi).
+LAGRANGE = {n: np.stack([fd.lagrange_weights(v, n) for v in range(2 * n - 1)]) for n in (5, 7)}
 
 
 class State:
@@ -54,8 +55,9 @@ class State:
         self.p = self.tab.p
         self.mode = mode
         N = mesh.n_oct
-        self.U = np.zeros((2, nfields, N, NODES, NODES, NODES))
-        self.K = np.zeros((self.p, nfields, N, NODES, NODES, NODES))
+        n = self.n = mesh.nodes
+        self.U = np.zeros((2, nfields, N, n, n, n))
+        self.K = np.zeros((self.p, nfields, N, n, n, n))
         B = len(mesh.blocks)
         lev = mesh.blocks[:, 2]
         # time in ticks of the finest present step; a level-lam step is 2^(lmax-lam) ticks
@@ -77,10 +79,10 @@ class State:
 
     def dt_phys(self, b: int) -> float:
         lev = self.mesh.lmax if self.mode == "gts" else int(self.mesh.blocks[b, 2])
-        return dt_level(lev)
+        return dt_level(lev, self.n)
 
     def current(self) -> np.ndarray:
-        """Current state of every octant, [F][N][5][5][5]."""
+        """Current state of every octant, [F][N][n][n][n]."""
         out = np.empty_like(self.U[0])
         for b in range(len(self.mesh.blocks)):
             octs = block_octants(self.mesh, b).ravel()
@@ -88,7 +90,7 @@ class State:
         return out
 
     def set_initial(self, U0: np.ndarray):
-        """U0: [F][N][5][5][5]; all blocks at t = 0, state in buffer 0."""
+        """U0: [F][N][n][n][n]; all blocks at t = 0, state in buffer 0."""
         self.U[:] = 0.0
         self.U[0] = U0
         self.cur_par[:] = 0
@@ -124,13 +126,14 @@ class State:
         srcb = np.where(kind == KIND_NONE, b, mesh.block_of_leaf[np.maximum(leaf, 0)])
         ub, inv = np.unique(srcb, return_inverse=True)
         direct = np.nonzero((kind != KIND_COARSE) & (kind != KIND_NONE))[0]
-        n = pos2[direct] // 2
-        flat = leaf[direct] * 125 + n[:, 2] * 25 + n[:, 1] * 5 + n[:, 0]
+        nd = pos2[direct] // 2
+        n = self.n
+        flat = leaf[direct] * n ** 3 + nd[:, 2] * n * n + nd[:, 1] * n + nd[:, 0]
         coarse = np.nonzero(kind == KIND_COARSE)[0]
         pl = dict(m=int(mesh.blocks[b, 1]), leaf=leaf, kind=kind, pos2=pos2, srcb=srcb, ub=ub,
                   inv=inv.reshape(-1), direct=direct, flat=flat, coarse=coarse,
                   none=np.nonzero(kind == KIND_NONE)[0],
-                  lag=[LAGRANGE[pos2[coarse, d]] for d in range(3)],
+                  lag=[LAGRANGE[self.n][pos2[coarse, d]] for d in range(3)],
                   octs=block_octants(mesh, b))
         self._plans[b] = pl
         return pl
@@ -140,12 +143,13 @@ class State:
 
         Every padded point takes, from its source leaf's step record, the value
         Y = U0 + dt_r * sum_i w^_{s,i}(case) K_i; a point that is not a node of a
-        coarser source leaf is interpolated from that leaf's 5^3 Y values with the
-        tensor degree-4 Lagrange interpolant."""
+        coarser source leaf is interpolated from that leaf's n^3 Y values with the
+        tensor degree n-1 Lagrange interpolant."""
         mesh = self.mesh
         pl = self.plan(b)
         m = pl["m"]
-        S = 4 * m + 7
+        n = self.n
+        S = (n - 1) * m + 7
         leaf, kind = pl["leaf"], pl["kind"]
         cases = np.array([self.case_of(b, int(x)) for x in pl["ub"]], dtype=np.int64)[pl["inv"]]
         cases[kind == KIND_OWN] = 0
@@ -166,17 +170,17 @@ class State:
             out[:, d] = u0 + dt * acc
         ci = pl["coarse"]
         if len(ci):
-            # Y of every distinct (source leaf, case) over the leaf's 5^3 nodes
+            # Y of every distinct (source leaf, case) over the leaf's n^3 nodes
             pairs, pinv = np.unique(np.stack([leaf[ci], cases[ci]], axis=1), axis=0, return_inverse=True)
             pinv = pinv.reshape(-1)
             li, pc = pairs[:, 0], pairs[:, 1]
             pp = self.rec_par[mesh.block_of_leaf[li]]
             wu = self.W[pc, s]                                                # [U, p]
-            acc = np.zeros((len(li), self.F, NODES, NODES, NODES))
+            acc = np.zeros((len(li), self.F, n, n, n))
             for i in range(self.p):
                 acc += wu[:, i][:, None, None, None, None] * self.K[i][:, li].transpose(1, 0, 2, 3, 4)
-            ysrc = self.U[pp, :, li] + dt * acc                               # [U, F, 5,5,5]
-            yp = ysrc[pinv]                                                   # [P, F, 5,5,5]
+            ysrc = self.U[pp, :, li] + dt * acc                               # [U, F, n,n,n]
+            yp = ysrc[pinv]                                                   # [P, F, n,n,n]
             wx, wy, wz = pl["lag"]
             t = (yp * wx[:, None, None, None, :]).sum(axis=4)                 # x
             t = (t * wy[:, None, None, :]).sum(axis=3)                        # y
@@ -186,13 +190,15 @@ class State:
 
     # ------------------------------------------------------------------ zip
     def zip_into(self, b: int, grid: np.ndarray, dest: np.ndarray):
-        """Block grid [F][4m+1]^3 -> every DG node of the block's octants (Sec. 3.3)."""
+        """Block grid [F][ni m+1]^3 -> every DG node of the block's octants (Sec. 3.3)."""
         m = int(self.mesh.blocks[b, 1])
         octs = self.plan(b)["octs"]
+        n = self.n
+        ni = n - 1
         for ok in range(m):
             for oj in range(m):
                 for oi in range(m):
-                    dest[:, octs[ok, oj, oi]] = grid[:, 4 * ok:4 * ok + 5, 4 * oj:4 * oj + 5, 4 * oi:4 * oi + 5]
+                    dest[:, octs[ok, oj, oi]] = grid[:, ni * ok:ni * ok + n, ni * oj:ni * oj + n, ni * oi:ni * oi + n]
 
     # ------------------------------------------------------------------ one substep
     def open_records(self, j: int) -> np.ndarray:
@@ -215,14 +221,14 @@ class State:
         or the outer boundary)."""
         mesh = self.mesh
         lev = int(mesh.blocks[b, 2])
-        return {"X0": 4 * mesh.blocks[b, 3:6].astype(np.int64), "w": 1 << (mesh.L - lev),
-                "Nu": 4 << mesh.L, "periodic": mesh.periodic}
+        return {"X0": mesh.ni * mesh.blocks[b, 3:6].astype(np.int64), "w": 1 << (mesh.L - lev),
+                "Nu": mesh.ni << mesh.L, "periodic": mesh.periodic}
 
     def stage(self, act, s: int, rhs, sigma: float):
         """Stage s of every block of B_j: unzip, block RHS, zip into K_s."""
         for b in act:
             pad = self.unzip(b, s)
-            h = 2.0 ** (-int(self.mesh.blocks[b, 2]) - 1)     # block grid spacing h_lam
+            h = h_level(int(self.mesh.blocks[b, 2]), self.n)     # block grid spacing h_lam
             grid = rhs(pad, h, sigma, self.geometry(b))
             self.zip_into(b, grid, self.K[s])
 
@@ -251,7 +257,7 @@ EQ = {"wave": (2, fd.rhs_wave), "maxwell": (6, fd.rhs_maxwell), "nlwave": (2, fd
 
 def run(mesh: Mesh, U0: np.ndarray, n_coarse: int, mode: str = "lts", equation: str = "wave",
         tableau: str = "rk4", sigma: float = 0.1, return_state: bool = False, nl_coeff: float = 1.0):
-    """Advance U0 ([F][N][5][5][5]) by n_coarse coarsest steps (T = n_coarse dt_lmin).
+    """Advance U0 ([F][N][n][n][n]) by n_coarse coarsest steps (T = n_coarse dt_lmin).
     nl_coeff: the coefficient c of the non-linear source (equation "nlwave")."""
     F, rhs = EQ[equation]
     if equation == "nlwave":

@@ -11,8 +11,9 @@ time-stepping or mesh logic).  It provides
     wave's shell),
   * seeded random DG arrays for kernel unit tests.
 
-Coordinates: level-L node units, N_u = 4 * 2^L per side, x = -1 + 2 X / N_u; a
-leaf (anchor a in level-L octant units, level l) has nodes 4 a + i 2^(L-l).
+Coordinates: level-L node units, N_u = ni * 2^L per side, x = -1 + 2 X / N_u,
+with n = 5 (default) or 7 nodes per octant side and ni = n - 1; a leaf (anchor a
+in level-L octant units, level l) has nodes ni a + i 2^(L-l), i = 0..ni.
 """
 from __future__ import annotations
 
@@ -26,30 +27,30 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 # ----------------------------------------------------------------------------- coordinates
-def node_units(anchors: np.ndarray, levels: np.ndarray, L: int) -> np.ndarray:
-    """Integer node coordinates [N, 5, 5, 5, 3] (x, y, z), node index [k][j][i]."""
+def node_units(anchors: np.ndarray, levels: np.ndarray, L: int, nodes: int = 5) -> np.ndarray:
+    """Integer node coordinates [N, n, n, n, 3] (x, y, z), node index [k][j][i]."""
     anchors = np.asarray(anchors, dtype=np.int64)
     s = (1 << (L - np.asarray(levels, dtype=np.int64)))
-    i = np.arange(5, dtype=np.int64)
+    i = np.arange(nodes, dtype=np.int64)
     k_, j_, i_ = np.meshgrid(i, i, i, indexing="ij")
-    loc = np.stack([i_, j_, k_], axis=-1)[None]                   # [1,5,5,5,3]
-    return 4 * anchors[:, None, None, None, :] + loc * s[:, None, None, None, None]
+    loc = np.stack([i_, j_, k_], axis=-1)[None]                   # [1,n,n,n,3]
+    return (nodes - 1) * anchors[:, None, None, None, :] + loc * s[:, None, None, None, None]
 
 
-def physical(X: np.ndarray, L: int) -> np.ndarray:
-    return -1.0 + 2.0 * X.astype(np.float64) / float(4 * (1 << L))
+def physical(X: np.ndarray, L: int, nodes: int = 5) -> np.ndarray:
+    return -1.0 + 2.0 * X.astype(np.float64) / float((nodes - 1) * (1 << L))
 
 
-def centre_from_seed(seed: int, L: int, lo: float = -0.5, hi: float = 0.5) -> List[int]:
+def centre_from_seed(seed: int, L: int, lo: float = -0.5, hi: float = 0.5, nodes: int = 5) -> List[int]:
     """Pulse centre ~ U([lo, hi]^3) from numpy's default_rng(seed), snapped to node units."""
     rng = np.random.default_rng(seed)
     x = rng.uniform(lo, hi, size=3)
-    n = 4 * (1 << L)
+    n = (nodes - 1) * (1 << L)
     return [int(round((v + 1.0) * 0.5 * n)) % n for v in x]
 
 
-def centre_physical(c: Sequence[int], L: int) -> np.ndarray:
-    return -1.0 + 2.0 * np.asarray(c, dtype=np.float64) / float(4 * (1 << L))
+def centre_physical(c: Sequence[int], L: int, nodes: int = 5) -> np.ndarray:
+    return -1.0 + 2.0 * np.asarray(c, dtype=np.float64) / float((nodes - 1) * (1 << L))
 
 
 IMAGES = np.array([(a, b, c) for c in (-1, 0, 1) for b in (-1, 0, 1) for a in (-1, 0, 1)], dtype=np.float64) * 2.0
@@ -66,17 +67,17 @@ def gaussian(x: np.ndarray, centres: np.ndarray, sigma: float, amp: float = 1.0)
     return out
 
 
-def wave_gaussian(anchors, levels, L, centres_nu, sigma=0.1, amp=1.0) -> np.ndarray:
-    """Wave-equation data (u, v) = (Gaussian, 0): [2, N, 5, 5, 5]."""
-    x = physical(node_units(anchors, levels, L), L)
-    c = np.stack([centre_physical(cc, L) for cc in centres_nu])
+def wave_gaussian(anchors, levels, L, centres_nu, sigma=0.1, amp=1.0, nodes: int = 5) -> np.ndarray:
+    """Wave-equation data (u, v) = (Gaussian, 0): [2, N, n, n, n]."""
+    x = physical(node_units(anchors, levels, L, nodes), L, nodes)
+    c = np.stack([centre_physical(cc, L, nodes) for cc in centres_nu])
     u = gaussian(x, c, sigma, amp)
     return np.stack([u, np.zeros_like(u)])
 
 
-def wave_plane(anchors, levels, L, n=(1, 0, 0)) -> np.ndarray:
+def wave_plane(anchors, levels, L, n=(1, 0, 0), nodes: int = 5) -> np.ndarray:
     """(u, v) = (sin(k.x), -|k| cos(k.x)), k = pi n: a periodic travelling wave."""
-    x = physical(node_units(anchors, levels, L), L)
+    x = physical(node_units(anchors, levels, L, nodes), L, nodes)
     k = np.pi * np.asarray(n, dtype=np.float64)
     ph = (x * k).sum(axis=-1)
     return np.stack([np.sin(ph), -np.linalg.norm(k) * np.cos(ph)])
@@ -118,11 +119,11 @@ def random_dg(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(shape) * scale
 
 
-def consistent_random_dg(anchors, levels, L, nfields: int, seed: int) -> np.ndarray:
+def consistent_random_dg(anchors, levels, L, nfields: int, seed: int, nodes: int = 5) -> np.ndarray:
     """Random smooth-free data whose duplicated DG nodes agree: a random value per
     distinct node coordinate (hash of the integer coordinate)."""
-    X = node_units(anchors, levels, L)
-    n = 4 * (1 << L)
+    X = node_units(anchors, levels, L, nodes)
+    n = (nodes - 1) * (1 << L)
     key = (X[..., 0] % n) + n * ((X[..., 1] % n) + n * (X[..., 2] % n))
     out = []
     for f in range(nfields):
@@ -152,27 +153,27 @@ def config_names() -> List[str]:
     return list(_load_specs().keys())
 
 
-def _nodes_torch(leaves: np.ndarray, L: int, device):
-    """Physical coordinates [N, 125, 3] of every DG node (torch, float64)."""
+def _nodes_torch(leaves: np.ndarray, L: int, device, nodes: int = 5):
+    """Physical coordinates [N, n^3, 3] of every DG node (torch, float64)."""
     import torch
     lv = torch.as_tensor(np.asarray(leaves), dtype=torch.int64, device=device)
     s = torch.bitwise_left_shift(torch.ones_like(lv[:, 3]), L - lv[:, 3]).to(torch.float64)
-    i = torch.arange(5, dtype=torch.float64, device=device)
+    i = torch.arange(nodes, dtype=torch.float64, device=device)
     k_, j_, i_ = torch.meshgrid(i, i, i, indexing="ij")
-    loc = torch.stack([i_, j_, k_], -1).reshape(125, 3)
-    X = 4.0 * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]       # [N,125,3]
-    return -1.0 + 2.0 * X / float(4 * (1 << L))
+    loc = torch.stack([i_, j_, k_], -1).reshape(nodes ** 3, 3)
+    X = float(nodes - 1) * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]       # [N,n^3,3]
+    return -1.0 + 2.0 * X / float((nodes - 1) * (1 << L))
 
 
-def wave_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1.0, device="cuda"):
+def wave_gaussian_torch(leaves: np.ndarray, L: int, centres_nu, sigma=0.1, amp=1.0, device="cuda", nodes: int = 5):
     """Same data as wave_gaussian, evaluated with torch on `device` (large meshes).
-    leaves: int [N, 4] (anchor x, y, z, level).  Returns [2, N, 125] float64."""
+    leaves: int [N, 4] (anchor x, y, z, level).  Returns [2, N, n^3] float64."""
     import torch
-    x = _nodes_torch(leaves, L, device)
+    x = _nodes_torch(leaves, L, device, nodes)
     u = torch.zeros(x.shape[:2], dtype=torch.float64, device=device)
     ims = torch.as_tensor(IMAGES, device=device)
     for cc in centres_nu:
-        c = torch.as_tensor(centre_physical(cc, L), device=device)
+        c = torch.as_tensor(centre_physical(cc, L, nodes), device=device)
         for im in ims:
             d = x - (c + im)
             u += amp * torch.exp(-(d * d).sum(-1) / (2.0 * sigma * sigma))
