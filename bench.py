@@ -243,7 +243,8 @@ def nl_leg(P, torch, steps, warmup) -> dict:
     lv = gm.leaves()
     U0 = torch.as_tensor(nlwave_shell(lv[:, :3], lv[:, 3], info["L"], cfg["shell_radius"], cfg["sigma"],
                                       cfg["amp"]).reshape(2, -1, 125), device="cuda:0")
-    out = {"config": f"nl_c2: chi_tt = lap chi + chi^2 (Sec. 4.2) on [-1,1]^3 with the radiative outer "
+    out = {"config": f"nl_c2: chi_tt = lap chi - sin(2 chi) / r^2 (Sec. 4.2, c = {cfg['nl_coeff']}) on [-1,1]^3 "
+                     f"with the radiative outer "
                      f"boundary, levels {info['lmin']}-{info['lmax']} around the shell r = {cfg['shell_radius']}, "
                      f"{info['n_oct']} octants, RK4, tile side 2",
            "n_octants": info["n_oct"], "steps": steps}
