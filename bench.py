@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=None, help="first N stored requests (default all)")
     ap.add_argument("--no-maxwell", action="store_true", help="skip the Maxwell leg")
     ap.add_argument("--no-nl", action="store_true", help="skip the non-linear wave leg")
+    ap.add_argument("--no-n7", action="store_true", help="skip the 7^3-node leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only time a copy of this many MiB")
     return ap.parse_args()
 
@@ -145,19 +146,20 @@ def stage_accounting(info: dict, tiles: np.ndarray, nfields: int = 2) -> dict:
     return {"alg_bytes": alg, "stages": stages, "launches": launches}
 
 
-def analytic_fields(leaves, L, pulses, sigma, T, device):
-    """(u, v) [2, N, 125] of the periodic Gaussian spherical wave at time T on every
+def analytic_fields(leaves, L, pulses, sigma, T, device, nodes: int = 5):
+    """(u, v) [2, N, n^3] of the periodic Gaussian spherical wave at time T on every
     DG node: u = (phi(r+T) + phi(r-T)) / (2r), v = (phi'(r+T) - phi'(r-T)) / (2r),
     phi(xi) = xi g(xi), summed over the pulses and their 27 nearest images; below
     r = 1e-4 the limits u = phi'(T) + r^2 phi'''(T) / 6, v = phi''(T)."""
     import torch
+    ni = nodes - 1
     lv = torch.as_tensor(np.asarray(leaves), dtype=torch.int64, device=device)
     s = torch.bitwise_left_shift(torch.ones_like(lv[:, 3]), L - lv[:, 3]).to(torch.float64)
-    i = torch.arange(5, dtype=torch.float64, device=device)
+    i = torch.arange(nodes, dtype=torch.float64, device=device)
     k_, j_, i_ = torch.meshgrid(i, i, i, indexing="ij")
-    loc = torch.stack([i_, j_, k_], -1).reshape(125, 3)
-    X = 4.0 * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]
-    x = -1.0 + 2.0 * X / float(4 * (1 << L))
+    loc = torch.stack([i_, j_, k_], -1).reshape(nodes ** 3, 3)
+    X = float(ni) * lv[:, None, :3].to(torch.float64) + loc[None] * s[:, None, None]
+    x = -1.0 + 2.0 * X / float(ni * (1 << L))
     u = torch.zeros(x.shape[:2], dtype=torch.float64, device=device)
     v = torch.zeros_like(u)
     s2 = sigma * sigma
@@ -179,7 +181,7 @@ def analytic_fields(leaves, L, pulses, sigma, T, device):
 
     Tt = torch.full((), float(T), dtype=torch.float64, device=device)
     for cc in pulses:
-        c = -1.0 + 2.0 * torch.tensor(cc, dtype=torch.float64, device=device) / float(4 * (1 << L))
+        c = -1.0 + 2.0 * torch.tensor(cc, dtype=torch.float64, device=device) / float(ni * (1 << L))
         for a in (-1, 0, 1):
             for b in (-1, 0, 1):
                 for d in (-1, 0, 1):
@@ -192,20 +194,21 @@ def analytic_fields(leaves, L, pulses, sigma, T, device):
     return torch.stack([u, v])
 
 
-def analytic_error(sim_out, leaves, L, pulses, sigma, T):
+def analytic_error(sim_out, leaves, L, pulses, sigma, T, nodes: int = 5):
     """Per field (u, v): volume-weighted L2 and max error against the periodic
     Gaussian spherical wave at T, and the L2 of the exact field itself."""
     import torch
     dev = sim_out.device
-    ex = analytic_fields(leaves, L, pulses, sigma, T, dev)
+    ex = analytic_fields(leaves, L, pulses, sigma, T, dev, nodes)
+    nn = float(nodes ** 3)
     lv = torch.as_tensor(np.asarray(leaves), dtype=torch.int64, device=dev)
     w = (2.0 ** (L - lv[:, 3].to(torch.float64))) ** 3
     out = {}
     for f, name in enumerate(("u", "v")):
         e = sim_out[f] - ex[f]
-        out[f"l2_{name}"] = torch.sqrt((w * (e * e).sum(1)).sum() / (125.0 * w.sum())).item()
+        out[f"l2_{name}"] = torch.sqrt((w * (e * e).sum(1)).sum() / (nn * w.sum())).item()
         out[f"linf_{name}"] = e.abs().max().item()
-        out[f"l2_exact_{name}"] = torch.sqrt((w * (ex[f] * ex[f]).sum(1)).sum() / (125.0 * w.sum())).item()
+        out[f"l2_exact_{name}"] = torch.sqrt((w * (ex[f] * ex[f]).sum(1)).sum() / (nn * w.sum())).item()
     return out
 
 
@@ -270,6 +273,51 @@ def nl_leg(P, torch, steps, warmup) -> dict:
     a = 224 * info["node_updates_lts"] * steps / out["lts"]["event_s"] / 1e9
     out["roofline"] = {"achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4),
                        "bytes_per_node_update": 224}
+    out["measured_speedup"] = out["gts"]["ms_per_step"] / out["lts"]["ms_per_step"]
+    out["model_speedup_eq_invS"] = info["s_est"]
+    return out
+
+
+def nodes7_leg(P, torch, steps, warmup) -> dict:
+    """7^3 nodes per octant with 2:1 balance and SSP-RK3 (the paper's
+    discretisation) on wave7_c2, through the phase kernels: LTS and GTS
+    throughput, the error against the analytic solution after the timed steps,
+    and the rate against the algorithmic minimum of SSP-RK3 (stage s reads U and
+    the K's its stage value needs and writes K_s; the last stage also writes the
+    new U): (2 + 3 + 5) x 16 B = 160 B per node-update in LTS."""
+    from workloads import config, mesh_spec, wave_gaussian_torch
+    cfg = config("wave7_c2")
+    gm = P.build_mesh(mesh_spec("wave7_c2"))
+    info = gm.info()
+    lv = gm.leaves()
+    U0 = wave_gaussian_torch(lv, info["L"], cfg["pulses"], sigma=cfg["sigma"], device="cuda:0", nodes=7)
+    out = {"config": f"wave7_c2: 3D scalar wave, periodic [-1,1]^3, 7^3 nodes per octant, 2:1 balance, levels "
+                     f"{info['lmin']}-{info['lmax']}, 4 Gaussian pulses, {info['n_oct']} octants x 343 nodes, "
+                     f"SSP-RK3, phase kernels (unzip, rhs, zip, RK update)",
+           "n_octants": info["n_oct"], "nodes": 343 * info["n_oct"], "steps": steps}
+    for leg in ("lts", "gts"):
+        mode = P.MODE_GTS if leg == "gts" else P.MODE_LTS
+        sim = P.Sim(gm, "wave", P.FP64, cfg["tableau"], ko_sigma=cfg["ko_sigma"], device="cuda:0")
+        sim.set_state(U0)
+        stream = torch.cuda.current_stream()
+        sim.advance(warmup, mode, graph=True, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        sim.advance(steps, mode, graph=True, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        nu = info["node_updates_gts" if leg == "gts" else "node_updates_lts"] * steps
+        out[leg] = {"rate": nu / wall, "ms_per_step": 1e3 * wall / steps, "event_s": e0.elapsed_time(e1) / 1e3}
+        T = (warmup + steps) * 0.25 * (2.0 ** (1 - info["lmin"]) / 6.0)
+        out[leg]["accuracy"] = analytic_error(sim.current(), lv, info["L"], cfg["pulses"], cfg["sigma"], T, nodes=7)
+        out[leg]["accuracy"]["T"] = T
+        del sim
+    a = 160 * info["node_updates_lts"] * steps / out["lts"]["event_s"] / 1e9
+    out["roofline"] = {"achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4),
+                       "bytes_per_node_update": 160}
     out["measured_speedup"] = out["gts"]["ms_per_step"] / out["lts"]["ms_per_step"]
     out["model_speedup_eq_invS"] = info["s_est"]
     return out
@@ -505,6 +553,12 @@ def main():
         print(f"[bench] nlwave: lts {nl['lts']['rate']:.4e}, gts {nl['gts']['rate']:.4e} node-updates/s, "
               f"frac {nl['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
 
+    n7 = None
+    if not args.no_n7 and "lts" in legs:
+        n7 = nodes7_leg(P, torch, max(1, min(args.steps, 4)), 1)
+        print(f"[bench] nodes7: lts {n7['lts']['rate']:.4e}, gts {n7['gts']['rate']:.4e} node-updates/s, "
+              f"frac {n7['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
+
     batch = None
     if not args.no_batch:
         from paper_2011_10570_amd import serve
@@ -595,6 +649,8 @@ def main():
         out["maxwell"] = maxwell
     if nl:
         out["nlwave"] = nl
+    if n7:
+        out["nodes7"] = n7
     if c3:
         out["c3"] = c3
     if batch:

@@ -27,18 +27,19 @@
  *               (passed as void*, NULL = default stream); only calls that return
  *               host results synchronise that stream.  A kernel fault surfaces as
  *               LTS_EDEVICE from the next call that synchronises.
- *   Layouts.    All device arrays are contiguous.
- *               U  : double [2][F][N][125]       two state buffers ("parities")
- *               K  : double|float [p][F][N][125] RK stages (float in FP32-RHS mode)
- *               node index within an octant: i + 5 j + 25 k (i fastest, along x);
+ *   Layouts.    All device arrays are contiguous.  n = nodes per octant side
+ *               (5 by default, or 7; lts_mesh_spec.nodes), ni = n - 1.
+ *               U  : double [2][F][N][n^3]       two state buffers ("parities")
+ *               K  : double|float [p][F][N][n^3] RK stages (float in FP32-RHS mode)
+ *               node index within an octant: i + n j + n^2 k (i fastest, along x);
  *               octants in Morton order (child index x + 2y + 4z), the order of
  *               lts_mesh_export(LTS_EXPORT_LEAVES).
  *               Padded blocks (lts_unzip output / lts_rhs input): per field, the
  *               blocks of the call in call order, block b holding S^3 doubles,
- *               S = 4 m_b + 7, point (i,j,k) in [-3, 4m+3]^3 at
+ *               S = ni m_b + 7, point (i,j,k) in [-3, ni m + 3]^3 at
  *               ((k+3) S + (j+3)) S + (i+3).
  *               Block grids (lts_rhs output / lts_zip input): per field, blocks
- *               in call order, (4 m_b + 1)^3 values each, (k (4m+1) + j)(4m+1) + i.
+ *               in call order, G^3 values each, G = ni m_b + 1, (k G + j) G + i.
  *   Buffers.    A block's step writes its new state into the U buffer its step
  *               record does not read.  Which buffer a block reads follows from the
  *               step counters: a level-l block's step index at substep j of
@@ -94,7 +95,8 @@ enum {
 enum { LTS_SRC_OWN = 0, LTS_SRC_SAME = 1, LTS_SRC_FINE = 2, LTS_SRC_COARSE = 3, LTS_SRC_NONE = 4 };
 
 /* Refinement criterion around an integer centre (node units at level l_max:
- * 4 * 2^l_max per side, x = -1 + 2 X / (4 * 2^l_max)).  A level-l leaf is split
+ * ni * 2^l_max per side, x = -1 + 2 X / (ni * 2^l_max), ni = nodes - 1 the
+ * node intervals per octant side).  A level-l leaf is split
  * if, with dmin / dmax the smallest / largest periodic distance from the centre
  * to the leaf's closed box,
  *   LTS_CRIT_BALL:    dmin^2 < r2[l]
@@ -111,10 +113,14 @@ typedef struct {
 
 /* Mesh specification.  Either criteria (refine from the uniform level l_min) or an
  * explicit leaf list (int32 [n_leaves][4] = anchor x, y, z in level-l_max octant
- * units, level; must tile the domain) is used.  The result is always closed under
- * the ghost-reach balance: a level-l leaf is split while a leaf of level >= l+2
- * lies within 3 h_l of it (2:1 balance of Sec. 3.2.3 extended so that the three
- * ghost layers of a block only reach leaves one level apart). */
+ * units, level; must tile the domain) is used.  Octants carry nodes^3 DG nodes.
+ * The result is always closed under the balance the three ghost layers of a block
+ * need to reach only leaves one level apart:
+ *   nodes = 5: ghost-reach balance, a level-l leaf is split while a leaf of level
+ *              >= l+2 lies within 3 h_l of it (2:1 balance of Sec. 3.2.3
+ *              extended: the layers reach 3/4 into a neighbouring octant);
+ *   nodes = 7: the paper's 2:1 balance (face, edge and corner contact; the
+ *              layers reach half-way into a neighbouring octant). */
 typedef struct {
   int32_t l_min, l_max;      /* 0 <= l_min <= l_max < LTS_MAX_LEVEL, l_max <= 10 */
   int32_t block_cap;         /* max octants per block side: 1, 2 or 4              */
@@ -125,6 +131,8 @@ typedef struct {
   int32_t boundary;          /* LTS_BOUNDARY_PERIODIC (0) or LTS_BOUNDARY_OUTER: on a */
                              /* bounded mesh distances, balance and neighbours stop */
                              /* at the outer faces                                   */
+  int32_t nodes;             /* nodes per octant side: 5 (0 means 5) or 7 (the      */
+                             /* paper's 7^3 points per octant, Sec. 4.5)            */
 } lts_mesh_spec;
 
 typedef struct {
@@ -134,8 +142,8 @@ typedef struct {
   int32_t n_substeps;        /* 2^(lmax - lmin)                                     */
   int32_t tile;              /* current fused-kernel tile side (1, 2 or 4)          */
   int64_t level_count[LTS_MAX_LEVEL];   /* leaves per level                          */
-  int64_t unzip_points;      /* sum over blocks of (4m+7)^3                         */
-  int64_t grid_points;       /* sum over blocks of (4m+1)^3                         */
+  int64_t unzip_points;      /* sum over blocks of (ni m + 7)^3, ni = nodes - 1      */
+  int64_t grid_points;       /* sum over blocks of (ni m + 1)^3                     */
   int64_t node_updates_lts;  /* DG node-updates per coarse step, LTS (eq. w_nuts)   */
   int64_t node_updates_gts;  /* same for GTS (eq. w_uts)                             */
   double s_est;              /* speedup model 1/S of eq. invS, inverted             */
@@ -144,6 +152,7 @@ typedef struct {
   int64_t ghost_entries;     /* coarser ghost sources of the fused tiles: a sim's   */
                              /* ghost-table scratch is ghost_entries x F x 729 doubles */
   int32_t boundary;          /* the spec's boundary                                  */
+  int32_t nodes;             /* nodes per octant side (5 or 7)                       */
 } lts_mesh_info;
 
 typedef struct lts_mesh lts_mesh;
@@ -152,8 +161,8 @@ typedef struct lts_batch lts_batch;
 
 /* Device arrays of one state (see Layouts).  nfields: 2 (wave) or 6 (Maxwell). */
 typedef struct {
-  void* U;                   /* double [2][F][N][125]                               */
-  void* K;                   /* [p][F][N][125], double (LTS_FP64) / float (FP32_RHS) */
+  void* U;                   /* double [2][F][N][n^3], n = nodes per octant side    */
+  void* K;                   /* [p][F][N][n^3], double (LTS_FP64) / float (FP32_RHS) */
   int32_t nfields;
   int32_t precision;         /* LTS_FP64 / LTS_FP32_RHS                             */
   int32_t tableau;           /* LTS_RK4 / LTS_SSPRK3                                */
@@ -213,7 +222,7 @@ lts_status lts_coefficients(int32_t tableau, double* out, size_t cap);
 lts_status lts_unzip(lts_mesh* mesh, const lts_stage_view* view, int32_t stage,
                      const lts_position* pos, const int32_t* blocks, int32_t nb,
                      double* padded, void* stream);
-/* a3: block RHS on the (4m+1)^3 block grid: wave du = v + KO(u), dv = Lap6 u +
+/* a3: block RHS on the (ni m+1)^3 block grid: wave du = v + KO(u), dv = Lap6 u +
  * KO(v); Maxwell dE = curl6 B + KO(E), dB = -curl6 E + KO(B); KO(f) =
  * sigma/(64h) sum_axes (1,-6,15,-20,15,-6,1) f.  precision LTS_FP32_RHS evaluates
  * the stencils in float (output float), else double. */
@@ -221,7 +230,7 @@ lts_status lts_rhs(lts_mesh* mesh, int32_t equation, const lts_rhs_params* param
                    const double* padded, int32_t precision, const int32_t* blocks,
                    int32_t nb, void* k_block, void* stream);
 /* a5: block grid -> every DG node of the blocks' octants (intra-block duplicates
- * get the block grid value).  k_octant: [F][N][125] (a K_s slice), element type
+ * get the block grid value).  k_octant: [F][N][n^3] (a K_s slice), element type
  * from precision. */
 lts_status lts_zip(lts_mesh* mesh, int32_t nfields, int32_t precision, const void* k_block,
                    const int32_t* blocks, int32_t nb, void* k_octant, void* stream);
@@ -288,17 +297,19 @@ enum {
                                     steps (inside the last stage's kernels), synchronise the
                                     stream at the end and return LTS_ENONFINITE if any */
 };
-/* Advance n coarse steps (T += n dt_lmin) with the fused kernels (Alg. 1 / Alg. 2).
+/* Advance n coarse steps (T += n dt_lmin) with the fused kernels (Alg. 1 / Alg. 2);
+ * a mesh of 7-node octants runs the same schedule on the phase kernels (unzip,
+ * rhs, zip, RK update; its first call allocates their block lists and scratch).
  * flags: LTS_ADVANCE_* (1 alone = graph, the former use_graph != 0).  Without
  * LTS_ADVANCE_CHECK_FINITE the call is asynchronous. */
 lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t flags,
                        void* stream);
 /* Same with the unfused phase kernels (unzip, rhs, zip, rk_stage). */
 lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, void* stream);
-/* Gather the current state of every octant into out ([F][N][125] doubles). */
+/* Gather the current state of every octant into out ([F][N][n^3] doubles). */
 lts_status lts_sim_current(lts_sim* sim, double* out, void* stream);
 /* Restart from a checkpoint taken at a coarse-step boundary: `state` (device,
- * [F][N][125] doubles, as lts_sim_current returns it) becomes the state of every
+ * [F][N][n^3] doubles, as lts_sim_current returns it) becomes the state of every
  * octant after `coarse_step` coarse steps in `mode`; the sim's counter is set to
  * it.  Continuing from here gives bitwise the results of the uninterrupted run
  * (nothing of an earlier coarse step is read after its end: every level starts

@@ -53,10 +53,14 @@ class Mesh:
     """Octree mesh (leaves, blocks, tiles, ghost tables) built by the library's host code."""
 
     def __init__(self, spec: Optional[dict] = None, leaves=None, L: Optional[int] = None, block_cap: int = 4,
-                 boundary: str = "periodic"):
+                 boundary: str = "periodic", nodes: int = 5):
+        """spec: a mesh specification dict (l_min, l_max, block_cap, criteria,
+        boundary, nodes), or leaves [n][4] with L.  nodes: DG nodes per octant
+        side, 5 or 7."""
         cs = _L.MeshSpecC()
         keep = []
         cs.boundary = BOUNDARIES[spec.get("boundary", "periodic") if spec is not None else boundary]
+        cs.nodes = int(spec.get("nodes", 5) if spec is not None else nodes)
         if leaves is not None:
             arr = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
             keep.append(arr)
@@ -307,8 +311,9 @@ def copy_probe(src, dst, nbytes: int, stream=None):
 
 
 class Sim:
-    """One simulation: device state U [2][F][N][125] (float64) and stages K
-    [p][F][N][125] (float64, or float32 in FP32-RHS mode) as torch tensors."""
+    """One simulation: device state U [2][F][N][n^3] (float64) and stages K
+    [p][F][N][n^3] (float64, or float32 in FP32-RHS mode) as torch tensors, n the
+    mesh's nodes per octant side (5 or 7)."""
 
     def __init__(self, mesh: Mesh, equation="wave", precision=FP64, tableau="rk4", ko_sigma=0.1, device="cuda",
                  nl_coeff: float = 1.0):
@@ -324,11 +329,13 @@ class Sim:
         h = C.c_void_p()
         check(lib().lts_sim_create(mesh.h, self.eq, self.prec, self.tab, C.byref(prm), C.byref(h)), "lts_sim_create")
         self.h = h
-        N = mesh.info()["n_oct"]
+        inf = mesh.info()
+        N = inf["n_oct"]
         self.N = N
-        self.U = torch.zeros((2, self.F, N, 125), dtype=torch.float64, device=device)
+        self.nn = inf["nodes"] ** 3
+        self.U = torch.zeros((2, self.F, N, self.nn), dtype=torch.float64, device=device)
         kdt = torch.float32 if self.prec == FP32_RHS else torch.float64
-        self.K = torch.zeros((self.p, self.F, N, 125), dtype=kdt, device=device)
+        self.K = torch.zeros((self.p, self.F, N, self.nn), dtype=kdt, device=device)
         check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
         self._mode = MODE_LTS
 
@@ -342,12 +349,12 @@ class Sim:
             self.h = None
 
     def set_state(self, U0):
-        """U0: [F][N][5][5][5] or [F][N][125] (numpy or torch); resets the step counter."""
+        """U0: [F][N][n][n][n] or [F][N][n^3] (numpy or torch); resets the step counter."""
         import torch
         t = torch.as_tensor(np.asarray(U0) if not hasattr(U0, "device") else U0, dtype=torch.float64)
         self.U.zero_()
         self.K.zero_()
-        self.U[0].copy_(t.reshape(self.F, self.N, 125).to(self.U.device))
+        self.U[0].copy_(t.reshape(self.F, self.N, self.nn).to(self.U.device))
         check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
 
     def advance(self, n_coarse: int, mode: int = MODE_LTS, graph: bool = True, stream=None, check_finite=False):
@@ -393,7 +400,7 @@ class Sim:
 
     def current(self, stream=None):
         import torch
-        out = torch.empty((self.F, self.N, 125), dtype=torch.float64, device=self.U.device)
+        out = torch.empty((self.F, self.N, self.nn), dtype=torch.float64, device=self.U.device)
         check(lib().lts_sim_current(self.h, _ptr(out), _stream_ptr(stream)), "lts_sim_current")
         return out
 

@@ -35,7 +35,7 @@ class Criterion(C.Structure):
 class MeshSpecC(C.Structure):
     _fields_ = [("l_min", C.c_int32), ("l_max", C.c_int32), ("block_cap", C.c_int32), ("n_criteria", C.c_int32),
                 ("criteria", C.POINTER(Criterion)), ("n_leaves", C.c_int64), ("leaves", C.POINTER(C.c_int32)),
-                ("boundary", C.c_int32)]
+                ("boundary", C.c_int32), ("nodes", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -44,7 +44,7 @@ class MeshInfo(C.Structure):
                 ("level_count", C.c_int64 * MAX_LEVEL), ("unzip_points", C.c_int64), ("grid_points", C.c_int64),
                 ("node_updates_lts", C.c_int64), ("node_updates_gts", C.c_int64), ("s_est", C.c_double),
                 ("s_max", C.c_double), ("table_bytes", C.c_int64), ("ghost_entries", C.c_int64),
-                ("boundary", C.c_int32)]
+                ("boundary", C.c_int32), ("nodes", C.c_int32)]
 
 
 class StageView(C.Structure):

@@ -81,6 +81,7 @@ static lts_status ensure_device(Mesh& m) {
     xyz[4 * i] = m.ax[i]; xyz[4 * i + 1] = m.ay[i]; xyz[4 * i + 2] = m.az[i]; xyz[4 * i + 3] = m.lev[i];
   }
   if ((st = upload_vec(xyz, &m.d_leafxyz, "upload leaf anchors")) != LTS_OK) return st;
+  if ((st = upload_vec(m.fine8, &m.d_fine8, "upload fine table")) != LTS_OK) return st;
   m.uploaded = true;
   return LTS_OK;
 }
@@ -115,12 +116,13 @@ static lts_status stage_list(Mesh& m, const int32_t* blocks, int nb, const lts_p
   const size_t n = lst.size();
   std::vector<int64_t> pack(3 * n + 1, 0);
   int64_t p = 0, g = 0;
+  const int ni = m.ni();
   for (size_t i = 0; i < n; ++i) {
     const int mm = m.blocks[lst[i]].m;
     pack[n + i] = p;
     pack[2 * n + i] = g;
-    p += (int64_t)(4 * mm + 7) * (4 * mm + 7) * (4 * mm + 7);
-    g += (int64_t)(4 * mm + 1) * (4 * mm + 1) * (4 * mm + 1);
+    p += (int64_t)(ni * mm + 7) * (ni * mm + 7) * (ni * mm + 7);
+    g += (int64_t)(ni * mm + 1) * (ni * mm + 1) * (ni * mm + 1);
   }
   for (size_t i = 0; i < n; ++i) pack[i] = lst[i];
   out.ptotal = p;
@@ -173,7 +175,7 @@ static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage,
   if (stage < 0 || stage >= p) return fail(LTS_EINVAL, "stage out of range");
   if (pos->mode != LTS_MODE_LTS && pos->mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
   if (pos->substep < 0 || pos->substep >= (1 << (m.lmax - m.lmin))) return fail(LTS_EINVAL, "substep out of range");
-  if ((int64_t)p * v->nfields * m.n() * 125 >= (1ll << 31) || m.n() * 125 * 8 >= (1ll << 32))
+  if ((int64_t)p * v->nfields * m.n() * m.nn() >= (1ll << 31) || m.n() * m.nn() * 8 >= (1ll << 32))
     return fail(LTS_EUNSUPPORTED, "arrays too large for the kernels' 32-bit offsets");
   double w[64], a[16], b[4];
   coefficient_tables(v->tableau, w, a, b);
@@ -196,6 +198,8 @@ static lts_status fill_params(const Mesh& m, const lts_stage_view* v, int stage,
   for (int i = 0; i < p; ++i) sp.b[i] = b[i];
   set_kmask(sp);
   sp.leafxyz = m.d_leafxyz;
+  sp.fine8 = m.d_fine8;
+  sp.ni = m.ni();
   sp.L = m.L;
   sp.periodic = m.periodic ? 1 : 0;
   sp.nl_coeff = 1.0;
@@ -209,6 +213,11 @@ static int equation_fields(int eq) {
 
 // Equation / mesh / precision / tile combinations the fused kernels are built for.
 static lts_status check_combination(const Mesh& m, int eq, int prec, bool batch) {
+  if (m.nodes != 5) {
+    if (batch) return fail(LTS_EUNSUPPORTED, "7-node octants are not built for batched launches");
+    return fail(LTS_EUNSUPPORTED, "the fused stage kernels are built for 5-node octants (7-node octants run on "
+                                  "the phase kernels: lts_advance, lts_advance_unfused, lts_unzip/rhs/zip/rk_stage)");
+  }
   if (!m.periodic && eq != LTS_EQ_NLWAVE)
     return fail(LTS_EUNSUPPORTED, "a bounded mesh needs the non-linear wave equation (radiative boundary)");
   if (eq == LTS_EQ_NLWAVE) {
@@ -320,6 +329,7 @@ void lts_mesh_destroy(lts_mesh* mesh) {
   for (int k : {1, 2, 4}) free_set(h->m.ts[k]);
   if (h->m.d_ghosts) (void)hipFree(h->m.d_ghosts);
   if (h->m.d_leafxyz) (void)hipFree(h->m.d_leafxyz);
+  if (h->m.d_fine8) (void)hipFree(h->m.d_fine8);
   if (h->x.d_cscr) (void)hipFree(h->x.d_cscr);
   if (h->m.d_off) (void)hipFree(h->m.d_off);
   if (h->x.d_step) (void)hipFree(h->x.d_step);
@@ -344,10 +354,11 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   for (int8_t l : m.lev) info->level_count[l] += 1;
   int64_t up = 0, gp = 0, wl = 0, wg = 0;
   const int64_t nsub = 1ll << (m.lmax - m.lmin);
+  const int ni = m.ni();
   for (const Block& b : m.blocks) {
-    up += (int64_t)(4 * b.m + 7) * (4 * b.m + 7) * (4 * b.m + 7);
-    gp += (int64_t)(4 * b.m + 1) * (4 * b.m + 1) * (4 * b.m + 1);
-    const int64_t nodes = 125ll * b.m * b.m * b.m;
+    up += (int64_t)(ni * b.m + 7) * (ni * b.m + 7) * (ni * b.m + 7);
+    gp += (int64_t)(ni * b.m + 1) * (ni * b.m + 1) * (ni * b.m + 1);
+    const int64_t nodes = m.nn() * b.m * b.m * b.m;
     wl += nodes * (1ll << (b.level - m.lmin));
     wg += nodes * nsub;
   }
@@ -357,16 +368,17 @@ lts_status lts_mesh_query(const lts_mesh* mesh, lts_mesh_info* info) {
   // kernels) and of the fused tiles
   int64_t tb = (int64_t)(m.bt.tiles.size() + m.bt.slots.size());
   for (int k : {1, 2, 4}) tb += (int64_t)(m.ts[k].tiles.size() + m.ts[k].slots.size());
-  tb += (int64_t)m.ghosts.size();
+  tb += (int64_t)m.ghosts.size() + (int64_t)m.fine8.size();
   info->table_bytes = 4 * tb;
   info->ghost_entries = (int64_t)(m.ghosts.size() / 2);
   info->boundary = m.periodic ? LTS_BOUNDARY_PERIODIC : LTS_BOUNDARY_OUTER;
+  info->nodes = m.nodes;
   info->node_updates_lts = wl;
   info->node_updates_gts = wg;
   // eq. invS with alpha_l = DG nodes at level lmax - l
   double inv = 0.0, tot = 0.0, a0 = 0.0;
   for (int l = m.lmin; l <= m.lmax; ++l) {
-    const double al = 125.0 * (double)info->level_count[l];
+    const double al = (double)m.nn() * (double)info->level_count[l];
     inv += al / std::ldexp(1.0, m.lmax - l);
     tot += al;
     if (l == m.lmax) a0 = al;
@@ -396,11 +408,12 @@ lts_status lts_mesh_export(const lts_mesh* mesh, int32_t kind, void* buf, size_t
       break;
     case LTS_EXPORT_UNZIP_MAP: {
       size_t tot = 0;
-      for (const Block& b : m.blocks) tot += (size_t)(4 * b.m + 7) * (4 * b.m + 7) * (4 * b.m + 7);
+      const int ni = m.ni();
+      for (const Block& b : m.blocks) tot += (size_t)(ni * b.m + 7) * (ni * b.m + 7) * (ni * b.m + 7);
       out.resize(5 * tot);
       size_t o = 0;
       for (size_t b = 0; b < m.blocks.size(); ++b) {
-        const int S = 4 * m.blocks[b].m + 7;
+        const int S = ni * m.blocks[b].m + 7;
         unzip_map_block(m, (int)b, out.data() + 5 * o);
         o += (size_t)S * S * S;
       }
@@ -486,6 +499,8 @@ lts_status lts_rhs(lts_mesh* mesh, int32_t equation, const lts_rhs_params* param
     return fail(LTS_EUNSUPPORTED, "a bounded mesh needs the non-linear wave equation (radiative boundary)");
   if (equation == LTS_EQ_NLWAVE && precision != LTS_FP64)
     return fail(LTS_EUNSUPPORTED, "the non-linear wave runs in FP64");
+  if (equation == LTS_EQ_NLWAVE && m.nodes != 5)
+    return fail(LTS_EUNSUPPORTED, "the non-linear wave is built for 5-node octants");
   hipStream_t s = (hipStream_t)stream;
   lts_status st = ensure_device(m);
   if (st != LTS_OK) return st;
@@ -494,6 +509,7 @@ lts_status lts_rhs(lts_mesh* mesh, int32_t equation, const lts_rhs_params* param
   StageParams geo;
   std::memset(&geo, 0, sizeof(geo));
   geo.leafxyz = m.d_leafxyz;
+  geo.ni = m.ni();
   geo.L = m.L;
   geo.periodic = m.periodic ? 1 : 0;
   geo.nl_coeff = params->nl_coeff;
@@ -515,7 +531,7 @@ lts_status lts_zip(lts_mesh* mesh, int32_t nfields, int32_t precision, const voi
   if (st != LTS_OK) return st;
   ListDev L;
   if ((st = stage_list(m, blocks, nb, nullptr, s, L)) != LTS_OK) return st;
-  HIP_TRY(launch_zip(precision == LTS_FP32_RHS, m.bt.d_tiles, L.list, L.goff, L.gtotal, L.nb, nfields, m.n(), k_block,
+  HIP_TRY(launch_zip(precision == LTS_FP32_RHS, m.ni(), m.bt.d_tiles, L.list, L.goff, L.gtotal, L.nb, nfields, m.n(), k_block,
                      k_octant, s),
           "zip launch");
   return LTS_OK;
@@ -726,6 +742,8 @@ void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams
   for (int i = 0; i < p; ++i) sp.b[i] = sim->b[i];
   sp.sigma = sim->prm.ko_sigma;
   sp.leafxyz = m.d_leafxyz;
+  sp.fine8 = m.d_fine8;
+  sp.ni = m.ni();
   sp.L = m.L;
   sp.periodic = m.periodic ? 1 : 0;
   sp.nl_coeff = sim->prm.nl_coeff;
@@ -776,8 +794,10 @@ lts_status lts_sim_create(lts_mesh* mesh, int32_t equation, int32_t precision, i
     return fail(LTS_EUNSUPPORTED, "a bounded mesh needs the non-linear wave equation (radiative boundary)");
   if (equation == LTS_EQ_NLWAVE && precision != LTS_FP64)
     return fail(LTS_EUNSUPPORTED, "the non-linear wave runs in FP64");
-  if ((int64_t)p * equation_fields(equation) * mesh->m.n() * 125 >= (1ll << 31) ||
-      mesh->m.n() * 125 * 8 >= (1ll << 32))
+  if (equation == LTS_EQ_NLWAVE && mesh->m.nodes != 5)
+    return fail(LTS_EUNSUPPORTED, "the non-linear wave is built for 5-node octants");
+  if ((int64_t)p * equation_fields(equation) * mesh->m.n() * mesh->m.nn() >= (1ll << 31) ||
+      mesh->m.n() * mesh->m.nn() * 8 >= (1ll << 32))
     return fail(LTS_EUNSUPPORTED, "arrays too large for the kernels' 32-bit offsets");
   lts_status st = ensure_device(mesh->m);
   if (st != LTS_OK) return st;
@@ -818,6 +838,8 @@ lts_status lts_sim_bind(lts_sim* sim, void* U, void* K) {
 }
 
 static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, bool use_graph, hipStream_t s);
+static lts_status prepare_unfused(lts_sim* sim);
+static lts_status enqueue_unfused_step(lts_sim* sim, int32_t mode, hipStream_t s);
 
 lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t flags, void* stream) {
   clear_error();
@@ -843,14 +865,24 @@ static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mo
   if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
     return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
   Mesh& m = sim->mesh->m;
-  lts_status cc = check_combination(m, sim->eq, sim->prec, false);
-  if (cc != LTS_OK) return cc;
-  lts_status sc = ensure_cscr(m, sim->F, &sim->d_cscr, &sim->cscr_cap);
-  if (sc != LTS_OK) return sc;
+  // 7-node octants run on the phase kernels; 5-node octants on the fused stage
+  const bool phase = m.nodes != 5;
+  if (phase) {
+    lts_status st = prepare_unfused(sim);
+    if (st != LTS_OK) return st;
+  } else {
+    lts_status cc = check_combination(m, sim->eq, sim->prec, false);
+    if (cc != LTS_OK) return cc;
+    lts_status sc = ensure_cscr(m, sim->F, &sim->d_cscr, &sim->cscr_cap);
+    if (sc != LTS_OK) return sc;
+  }
+  auto one_step = [&](hipStream_t st) {
+    return phase ? enqueue_unfused_step(sim, mode, st) : enqueue_coarse_step(sim, mode, st);
+  };
   sim->mode = mode;
   if (!use_graph) {
     for (int64_t c = 0; c < n_coarse_steps; ++c) {
-      lts_status st = enqueue_coarse_step(sim, mode, s);
+      lts_status st = one_step(s);
       if (st != LTS_OK) return st;
       sim->n += 1;
     }
@@ -861,7 +893,7 @@ static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mo
   }
   if (!sim->exec[mode]) {
     HIP_TRY(hipStreamBeginCapture(sim->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    lts_status st = enqueue_coarse_step(sim, mode, sim->cap_stream);
+    lts_status st = one_step(sim->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(sim->cap_stream, &g);
     if (st != LTS_OK) {
@@ -881,18 +913,10 @@ static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mo
   return LTS_OK;
 }
 
-lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, void* stream) {
-  clear_error();
-  if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
-  if (sim->batch) return fail(LTS_EINVAL, "sim is attached to a batch");
-  if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
-  if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
-    return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
+// Device block lists of every substep class and the padded / block-grid scratch
+// of the phase kernels, allocated once (outside any graph capture).
+static lts_status prepare_unfused(lts_sim* sim) {
   Mesh& m = sim->mesh->m;
-  hipStream_t s = (hipStream_t)stream;
-  sim->mode = mode;
-  const int nsub = 1 << (m.lmax - m.lmin);
-  // device block lists of every substep class, built once
   if (sim->ulists.empty()) {
     int64_t pmax = 0, gmax = 0;
     for (int cls = 0; cls <= m.lmax - m.lmin + 1; ++cls) {
@@ -908,8 +932,9 @@ lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mod
         const int mm = m.blocks[lst[i]].m;
         off[i] = p;
         off[n + i] = g;
-        p += (int64_t)(4 * mm + 7) * (4 * mm + 7) * (4 * mm + 7);
-        g += (int64_t)(4 * mm + 1) * (4 * mm + 1) * (4 * mm + 1);
+        const int ni = m.ni();
+        p += (int64_t)(ni * mm + 7) * (ni * mm + 7) * (ni * mm + 7);
+        g += (int64_t)(ni * mm + 1) * (ni * mm + 1) * (ni * mm + 1);
       }
       pmax = std::max(pmax, p);
       gmax = std::max(gmax, g);
@@ -938,31 +963,54 @@ lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mod
     HIP_TRY(hipMalloc(&sim->d_coef, 4 * sizeof(double)), "hipMalloc coef");
     HIP_TRY(hipMemcpy(sim->d_coef, sim->b, sim->p * sizeof(double), hipMemcpyHostToDevice), "upload b");
   }
+  return LTS_OK;
+}
+
+// One coarse step through the phase kernels (unzip, rhs, zip per stage, then the
+// RK update) and the step counter increment.
+static lts_status enqueue_unfused_step(lts_sim* sim, int32_t mode, hipStream_t s) {
+  Mesh& m = sim->mesh->m;
+  const int nsub = 1 << (m.lmax - m.lmin);
   const bool kf32 = sim->prec == LTS_FP32_RHS;
   const size_t kbytes = kf32 ? 4 : 8;
-  for (int64_t c = 0; c < n_coarse_steps; ++c) {
-    for (int j = 0; j < nsub; ++j) {
-      int cls;
-      if (mode == LTS_MODE_GTS) cls = m.lmax - m.lmin + 1;
-      else cls = m.lmax - lowest_active_level(m, mode, j);
-      const ListDev& L = sim->ulists[cls];
-      for (int st = 0; st < sim->p; ++st) {
-        StageParams sp;
-        fill_sim_params(sim, st, mode, j, sp);
-        HIP_TRY(launch_unzip(kf32, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb, L.ptotal, sim->d_pad, s),
-                "unzip launch");
-        HIP_TRY(launch_rhs(sim->eq, kf32, m.bt.d_tiles, L.list, L.poff, L.ptotal, L.goff, L.gtotal, L.nb, sim->d_pad,
-                           sim->d_kb, sim->prm.ko_sigma, sp, s),
-                "rhs launch");
-        char* kslice = (char*)sim->K + (size_t)st * sim->F * m.n() * 125 * kbytes;
-        HIP_TRY(launch_zip(kf32, m.bt.d_tiles, L.list, L.goff, L.gtotal, L.nb, sim->F, m.n(), sim->d_kb, kslice, s),
-                "zip launch");
-      }
+  for (int j = 0; j < nsub; ++j) {
+    int cls;
+    if (mode == LTS_MODE_GTS) cls = m.lmax - m.lmin + 1;
+    else cls = m.lmax - lowest_active_level(m, mode, j);
+    const ListDev& L = sim->ulists[cls];
+    for (int st = 0; st < sim->p; ++st) {
       StageParams sp;
-      fill_sim_params(sim, 0, mode, j, sp);
-      HIP_TRY(launch_rk(kf32, sp, m.bt.d_tiles, L.list, L.nb, sim->d_coef, nullptr, s), "rk launch");
+      fill_sim_params(sim, st, mode, j, sp);
+      HIP_TRY(launch_unzip(kf32, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb, L.ptotal, sim->d_pad, s),
+              "unzip launch");
+      HIP_TRY(launch_rhs(sim->eq, kf32, m.bt.d_tiles, L.list, L.poff, L.ptotal, L.goff, L.gtotal, L.nb, sim->d_pad,
+                         sim->d_kb, sim->prm.ko_sigma, sp, s),
+              "rhs launch");
+      char* kslice = (char*)sim->K + (size_t)st * sim->F * m.n() * m.nn() * kbytes;
+      HIP_TRY(launch_zip(kf32, m.ni(), m.bt.d_tiles, L.list, L.goff, L.gtotal, L.nb, sim->F, m.n(), sim->d_kb, kslice, s),
+              "zip launch");
     }
-    HIP_TRY(launch_increment(sim->d_step, s), "step increment");
+    StageParams sp;
+    fill_sim_params(sim, 0, mode, j, sp);
+    HIP_TRY(launch_rk(kf32, sp, m.bt.d_tiles, L.list, L.nb, sim->d_coef, nullptr, s), "rk launch");
+  }
+  HIP_TRY(launch_increment(sim->d_step, s), "step increment");
+  return LTS_OK;
+}
+
+lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, void* stream) {
+  clear_error();
+  if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
+  if (sim->batch) return fail(LTS_EINVAL, "sim is attached to a batch");
+  if (mode != LTS_MODE_LTS && mode != LTS_MODE_GTS) return fail(LTS_EINVAL, "bad mode");
+  if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
+    return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
+  hipStream_t s = (hipStream_t)stream;
+  lts_status st = prepare_unfused(sim);
+  if (st != LTS_OK) return st;
+  sim->mode = mode;
+  for (int64_t c = 0; c < n_coarse_steps; ++c) {
+    if ((st = enqueue_unfused_step(sim, mode, s)) != LTS_OK) return st;
     sim->n += 1;
   }
   return LTS_OK;
@@ -1059,7 +1107,7 @@ lts_status lts_norms(lts_mesh* mesh, int32_t nfields, const double* a, const dou
   double* mx = sq + nfields * N;
   unsigned long long* bad = (unsigned long long*)(mx + nfields * N);
   HIP_TRY(hipMemsetAsync(bad, 0, 8, s), "memset");
-  HIP_TRY(launch_norm_partials(a, b, nfields, N, sq, mx, bad, s), "norm launch");
+  HIP_TRY(launch_norm_partials(a, b, nfields, N, (int)m.nn(), sq, mx, bad, s), "norm launch");
   std::vector<double> hs(2 * nfields * N + 1);
   HIP_TRY(hipMemcpyAsync(hs.data(), sq, need, hipMemcpyDeviceToHost, s), "norm copy");
   HIP_TRY(hipStreamSynchronize(s), "norm sync");
@@ -1075,7 +1123,7 @@ lts_status lts_norms(lts_mesh* mesh, int32_t nfields, const double* a, const dou
       acc += w[o] * hs[f * N + o];
       mxv = std::max(mxv, hs[nfields * N + f * N + o]);
     }
-    out[f] = std::sqrt(acc / (125.0 * wsum));
+    out[f] = std::sqrt(acc / ((double)m.nn() * wsum));
     out[nfields + f] = mxv;
   }
   unsigned long long nb;
@@ -1117,6 +1165,7 @@ lts_status lts_remesh_indicators(lts_mesh* mesh, int32_t nfields, const double* 
   if (!mesh || !state || !leaf_ind || !family_ind) return fail(LTS_EINVAL, "NULL argument");
   if (nfields < 1 || nfields > 6) return fail(LTS_EINVAL, "bad nfields");
   Mesh& m = mesh->m;
+  if (m.nodes != 5) return fail(LTS_EUNSUPPORTED, "remeshing is built for 5-node octants");
   std::vector<double> lw, fw;
   std::vector<int64_t> fam;
   lts_status st = wavelet_indicators(m, nfields, state, lw, fam, fw, (hipStream_t)stream);
@@ -1134,6 +1183,7 @@ lts_status lts_remesh(lts_mesh* mesh, int32_t nfields, const double* state, doub
   *out = nullptr;
   if (nfields < 1 || nfields > 6) return fail(LTS_EINVAL, "bad nfields");
   Mesh& m = mesh->m;
+  if (m.nodes != 5) return fail(LTS_EUNSUPPORTED, "remeshing is built for 5-node octants");
   if (!(eps > 0.0) || l_min < 0 || l_min > l_max || l_max > m.L) return fail(LTS_EINVAL, "need eps > 0, 0 <= l_min <= l_max <= L");
   std::vector<double> lw, fw;
   std::vector<int64_t> fam;
@@ -1158,6 +1208,7 @@ lts_status lts_transfer(lts_mesh* from, lts_mesh* to, int32_t nfields, const dou
   clear_error();
   if (!from || !to || !state_from || !state_to) return fail(LTS_EINVAL, "NULL argument");
   if (nfields < 1 || nfields > 6) return fail(LTS_EINVAL, "bad nfields");
+  if (from->m.nodes != 5 || to->m.nodes != 5) return fail(LTS_EUNSUPPORTED, "remeshing is built for 5-node octants");
   std::vector<int32_t> rec;
   lts_status st = transfer_records(from->m, to->m, rec);
   if (st != LTS_OK) return st;
@@ -1397,6 +1448,7 @@ lts_status lts_batch_attach(lts_batch* b, lts_sim* sim, int64_t n_coarse_steps) 
   if (sim->mode >= 0 && sim->mode != b->mode && sim->n > 0)
     return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
   Mesh& m = sim->mesh->m;
+  if (m.nodes != 5) return fail(LTS_EUNSUPPORTED, "7-node octants are not built for batched launches");
   if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
     return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
   if (m.ts[4].count() > 0)

@@ -39,6 +39,31 @@ static __constant__ double c_lag[9][5] = {
     {-5.0 / 128, 28.0 / 128, -70.0 / 128, 140.0 / 128, 35.0 / 128},
     {0, 0, 0, 0, 1}};
 
+// The same for degree 6 on nodes 0..6 at xi = x2/2 (x2 = 0..12), 7-node octants.
+// Exact binary fractions (denominator 1024).
+static __constant__ double c_lag7[13][7] = {
+    {1, 0, 0, 0, 0, 0, 0},
+    {231.0 / 1024, 693.0 / 512, -1155.0 / 1024, 231.0 / 256, -495.0 / 1024, 77.0 / 512, -21.0 / 1024},
+    {0, 1, 0, 0, 0, 0, 0},
+    {-21.0 / 1024, 189.0 / 512, 945.0 / 1024, -105.0 / 256, 189.0 / 1024, -27.0 / 512, 7.0 / 1024},
+    {0, 0, 1, 0, 0, 0, 0},
+    {7.0 / 1024, -35.0 / 512, 525.0 / 1024, 175.0 / 256, -175.0 / 1024, 21.0 / 512, -5.0 / 1024},
+    {0, 0, 0, 1, 0, 0, 0},
+    {-5.0 / 1024, 21.0 / 512, -175.0 / 1024, 175.0 / 256, 525.0 / 1024, -35.0 / 512, 7.0 / 1024},
+    {0, 0, 0, 0, 1, 0, 0},
+    {7.0 / 1024, -27.0 / 512, 189.0 / 1024, -105.0 / 256, 945.0 / 1024, 189.0 / 512, -21.0 / 1024},
+    {0, 0, 0, 0, 0, 1, 0},
+    {-21.0 / 1024, 77.0 / 512, -495.0 / 1024, 231.0 / 256, -1155.0 / 1024, 693.0 / 512, 231.0 / 1024},
+    {0, 0, 0, 0, 0, 0, 1}};
+
+// Node spacing of a level-lev octant of [-1, 1]^3 with NI node intervals per
+// side, h = 2^(1-lev) / NI (a power of two for NI = 4), and the step dt = h / 4.
+template <int NI>
+__device__ __forceinline__ double h_level(int lev) {
+  if constexpr (NI == 4) return ldexp(1.0, -lev - 1);
+  else return ldexp(1.0, 1 - lev) / (double)NI;
+}
+
 // sixth-order central second derivative, first derivative, KO sixth difference
 #define D2C0 (-49.0 / 18.0)
 #define D2C1 (3.0 / 2.0)
@@ -81,6 +106,7 @@ struct TileCtx {
   double dt, h;
 };
 
+template <int NI = 4>
 __device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, int mode, int j, int lmin, int lmax, int n4) {
   TileCtx c;
   c.lev = t[TI_LEVEL];
@@ -95,7 +121,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, int mode, int j, i
   if (mode == LTS_MODE_GTS) {
     c.par_fine = c.par_coarse = s & 1;
     c.case_fine = c.case_coarse = 0;
-    c.dt = ldexp(1.0, -lmax - 3);
+    c.dt = 0.25 * h_level<NI>(lmax);
   } else {
     // a finer neighbour steps twice per receiver step: its step index is 2 s;
     // a coarser one once per two: its index is floor(s / 2) (Sec. 3.6.3).
@@ -103,14 +129,15 @@ __device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, int mode, int j, i
     c.par_coarse = (s >> 1) & 1;
     c.case_fine = 1;                                   // (delta, rho) = (0, 1/2)
     c.case_coarse = 2 + ((j >> (lmax - c.lev)) & 1);  // (0, 2) or (1, 2)
-    c.dt = ldexp(1.0, -c.lev - 3);
+    c.dt = 0.25 * h_level<NI>(c.lev);
   }
-  c.h = ldexp(1.0, -c.lev - 1);
+  c.h = h_level<NI>(c.lev);
   return c;
 }
 
+template <int NI = 4>
 __device__ __forceinline__ TileCtx tile_ctx(const int32_t* t, const StageParams& sp, int n4) {
-  return tile_ctx(t, sp.mode, sp.j, sp.lmin, sp.lmax, n4);
+  return tile_ctx<NI>(t, sp.mode, sp.j, sp.lmin, sp.lmax, n4);
 }
 
 // ------------------------------------------------------------------ gather
@@ -132,12 +159,13 @@ __device__ __forceinline__ double kload(const void* K, int64_t idx) {
   else return ((const double*)K)[idx];
 }
 
-// Y = U0 + dt sum_i w_i K_i at one DG node (field stride fs = N*125); only the
-// stages with a non-zero weight (bit mask km, uniform per case) are read.
-template <bool KF32>
+// Y = U0 + dt sum_i w_i K_i at one DG node (field stride fs = N*NN, NN nodes
+// per octant); only the stages with a non-zero weight (bit mask km, uniform per
+// case) are read.
+template <bool KF32, int NN = 125>
 __device__ __forceinline__ double yval(const StageParams& sp, const double* w, int km, int par, int64_t idx,
                                        double dt) {
-  const int64_t fs = sp.N * 125;
+  const int64_t fs = sp.N * NN;
   const int64_t ps = fs * sp.F;
   double acc = 0.0;
   #pragma unroll
@@ -177,15 +205,17 @@ __device__ __forceinline__ double ycombine(const YLoad<KF32, F>& r, int f, const
 }
 
 // Value of every field at padded tile point (qx, qy, qz).  slots: the tile's
-// slot table; wsh: stage-s weights per case [4][4].
-template <bool KF32, int F>
+// slot table; wsh: stage-s weights per case [4][4].  NI: node intervals per
+// octant side (4, or 6 for 7-node octants).
+template <bool KF32, int F, int NI = 4>
 __device__ __forceinline__ void point_values(const StageParams& sp, const TileCtx& c, const int32_t* slots,
                                              const double* wsh, int qx, int qy, int qz, double out[F]) {
-  const Loc L = locate(qx, qy, qz, c.ox, c.oy, c.oz, c.tt, c.m);
+  constexpr int NP = NI + 1, NN = NP * NP * NP;
+  const Loc L = locate(qx, qy, qz, c.ox, c.oy, c.oz, c.tt, c.m, NI);
   const int leaf = slots[2 * L.slot];
   const int kb = slots[2 * L.slot + 1];
   const int kind = kb & 15;
-  const int64_t fs = sp.N * 125;
+  const int64_t fs = sp.N * NN;
   if (kind == SRC_NONE) {   // beyond the outer faces: no source
 #pragma unroll
     for (int f = 0; f < F; ++f) out[f] = 0.0;
@@ -195,34 +225,43 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
     int node, lf, par, km;
     const double* w;
     if (kind == SRC_FINE) {
-      const int cx = min(L.nu[0] >> 1, 1), cy = min(L.nu[1] >> 1, 1), cz = min(L.nu[2] >> 1, 1);
-      lf = leaf + cx + 2 * cy + 4 * cz;
-      node = 2 * (L.nu[0] - 2 * cx) + 5 * 2 * (L.nu[1] - 2 * cy) + 25 * 2 * (L.nu[2] - 2 * cz);
+      if constexpr (NI == 4) {
+        const int cx = min(L.nu[0] >> 1, 1), cy = min(L.nu[1] >> 1, 1), cz = min(L.nu[2] >> 1, 1);
+        lf = leaf + cx + 2 * cy + 4 * cz;
+        node = 2 * (L.nu[0] - 2 * cx) + 5 * 2 * (L.nu[1] - 2 * cy) + 25 * 2 * (L.nu[2] - 2 * cz);
+      } else {
+        // 2:1 balance: the slot names a row of the fine table (children next to
+        // the block are leaves)
+        const int cx = fine_child6(L.nu[0], L.below & 1), cy = fine_child6(L.nu[1], (L.below >> 1) & 1),
+                  cz = fine_child6(L.nu[2], (L.below >> 2) & 1);
+        lf = sp.fine8[8 * leaf + cx + 2 * cy + 4 * cz];
+        node = (2 * L.nu[0] - NI * cx) + NP * (2 * L.nu[1] - NI * cy) + NP * NP * (2 * L.nu[2] - NI * cz);
+      }
       par = c.par_fine;
       w = wsh + 4 * c.case_fine;
       km = stage_mask(sp, c.case_fine);
     } else {
       lf = leaf;
-      node = L.nu[0] + 5 * L.nu[1] + 25 * L.nu[2];
+      node = L.nu[0] + NP * L.nu[1] + NP * NP * L.nu[2];
       par = c.par_same;
       w = wsh;
       km = sp.kmask[0];
     }
-    const int64_t base = (int64_t)lf * 125 + node;
+    const int64_t base = (int64_t)lf * NN + node;
     #pragma unroll
-    for (int f = 0; f < F; ++f) out[f] = yval<KF32>(sp, w, km, par, f * fs + base, c.dt);
+    for (int f = 0; f < F; ++f) out[f] = yval<KF32, NN>(sp, w, km, par, f * fs + base, c.dt);
     return;
   }
-  // coarser source: tensor degree-4 Lagrange interpolation of its Y values
+  // coarser source: tensor degree-NI Lagrange interpolation of its Y values
   const int beta = (kb >> 4) & 7;
   int x2[3];
-  for (int d = 0; d < 3; ++d) x2[d] = 4 * ((beta >> d) & 1) + L.nu[d];
+  for (int d = 0; d < 3; ++d) x2[d] = NI * ((beta >> d) & 1) + L.nu[d];
   const double* w = wsh + 4 * c.case_coarse;
   const int km = stage_mask(sp, c.case_coarse);
   const int par = c.par_coarse;
   int lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
-    if (x2[d] & 1) { lo[d] = 0; hi[d] = 4; }
+    if (x2[d] & 1) { lo[d] = 0; hi[d] = NI; }
     else { lo[d] = hi[d] = x2[d] >> 1; }
   }
   #pragma unroll
@@ -236,16 +275,16 @@ __device__ __forceinline__ void point_values(const StageParams& sp, const TileCt
       #pragma unroll
       for (int f = 0; f < F; ++f) tx[f] = 0.0;
       for (int kx = lo[0]; kx <= hi[0]; ++kx) {
-        const double wx = c_lag[x2[0]][kx];
-        const int64_t base = (int64_t)leaf * 125 + kx + 5 * ky + 25 * kz;
+        const double wx = NI == 4 ? c_lag[x2[0]][kx] : c_lag7[x2[0]][kx];
+        const int64_t base = (int64_t)leaf * NN + kx + NP * ky + NP * NP * kz;
         #pragma unroll
-        for (int f = 0; f < F; ++f) tx[f] = fma(wx, yval<KF32>(sp, w, km, par, f * fs + base, c.dt), tx[f]);
+        for (int f = 0; f < F; ++f) tx[f] = fma(wx, yval<KF32, NN>(sp, w, km, par, f * fs + base, c.dt), tx[f]);
       }
-      const double wy = c_lag[x2[1]][ky];
+      const double wy = NI == 4 ? c_lag[x2[1]][ky] : c_lag7[x2[1]][ky];
       #pragma unroll
       for (int f = 0; f < F; ++f) ty[f] = fma(wy, tx[f], ty[f]);
     }
-    const double wz = c_lag[x2[2]][kz];
+    const double wz = NI == 4 ? c_lag[x2[2]][kz] : c_lag7[x2[2]][kz];
     #pragma unroll
     for (int f = 0; f < F; ++f) out[f] = fma(wz, ty[f], out[f]);
   }

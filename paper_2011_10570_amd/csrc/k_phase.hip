@@ -1,11 +1,13 @@
 // Phase-by-phase kernels (unzip, rhs, zip, RK update as separate launches over
 // whole blocks through HBM), state gather, counters, norms and the copy probe.
+// The phase kernels take NI, the node intervals per octant side (4 for 5^3
+// nodes, 6 for 7^3 nodes), as a template argument.
 #include "dev_common.h"
 
 namespace lts {
 
 // ------------------------------------------------------------------ standalone kernels
-template <bool KF32, int F>
+template <bool KF32, int F, int NI>
 __global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __restrict__ tiles,
                                                const int32_t* __restrict__ slots, const int32_t* __restrict__ list,
                                                const int64_t* __restrict__ off, int64_t total, double* out) {
@@ -16,20 +18,20 @@ __global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __
   const int b = list[bi];
   const int32_t* t = tiles + 8 * (int64_t)b;
   const int n4 = (int)(*sp.step & 3);
-  const TileCtx c = tile_ctx(t, sp, n4);
-  const int P = 4 * c.m + 7;
+  const TileCtx c = tile_ctx<NI>(t, sp, n4);
+  const int P = NI * c.m + 7;
   const int P3 = P * P * P;
   const int32_t* sl = slots + 2 * (int64_t)t[TI_SLOT];
   for (int pi = blockIdx.x * blockDim.x + threadIdx.x; pi < P3; pi += gridDim.x * blockDim.x) {
     const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
     double v[F];
-    point_values<KF32, F>(sp, c, sl, wsh, qx, qy, qz, v);
+    point_values<KF32, F, NI>(sp, c, sl, wsh, qx, qy, qz, v);
     #pragma unroll
     for (int f = 0; f < F; ++f) out[f * total + off[bi] + pi] = v[f];
   }
 }
 
-template <int EQ, int F, bool F32>
+template <int EQ, int F, bool F32, int NI>
 __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
                                              const int64_t* __restrict__ poff, int64_t ptotal,
                                              const int64_t* __restrict__ goff, int64_t gtotal,
@@ -38,9 +40,9 @@ __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, 
   const int bi = blockIdx.y;
   const int32_t* t = tiles + 8 * (int64_t)list[bi];
   const int m = t[TI_M];
-  const int P = 4 * m + 7, G = 4 * m + 1;
+  const int P = NI * m + 7, G = NI * m + 1;
   const int G3 = G * G * G;
-  const double h = ldexp(1.0, -t[TI_LEVEL] - 1);
+  const double h = h_level<NI>(t[TI_LEVEL]);
   for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G3; gi += gridDim.x * blockDim.x) {
     const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
     const int ci = ((gz + 3) * P + (gy + 3)) * P + (gx + 3);
@@ -110,18 +112,19 @@ __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ tiles, 
   }
 }
 
-template <typename T>
+template <typename T, int NI>
 __global__ __launch_bounds__(256) void k_zip(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
                                              const int64_t* __restrict__ goff, int64_t gtotal, int F, int64_t N,
                                              const T* __restrict__ kblock, T* __restrict__ kout) {
+  constexpr int NP = NI + 1, NN = NP * NP * NP;
   const int bi = blockIdx.y;
   const int32_t* t = tiles + 8 * (int64_t)list[bi];
   const int m = t[TI_M];
-  const int G = 4 * m + 1;
+  const int G = NI * m + 1;
   const int first = t[TI_FIRST];
-  const int nn = m * m * m * 125;
+  const int nn = m * m * m * NN;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
-    const int o = e / 125, node = e % 125;
+    const int o = e / NN, node = e % NN;
     // octant o of the block in Morton order -> lexicographic octant coordinates
     int ox = 0, oy = 0, oz = 0;
     for (int bit = 0; bit < 3; ++bit) {
@@ -129,25 +132,26 @@ __global__ __launch_bounds__(256) void k_zip(const int32_t* __restrict__ tiles, 
       oy |= ((o >> (3 * bit + 1)) & 1) << bit;
       oz |= ((o >> (3 * bit + 2)) & 1) << bit;
     }
-    const int gx = 4 * ox + node % 5, gy = 4 * oy + (node / 5) % 5, gz = 4 * oz + node / 25;
+    const int gx = NI * ox + node % NP, gy = NI * oy + (node / NP) % NP, gz = NI * oz + node / (NP * NP);
     const int64_t gi = ((int64_t)gz * G + gy) * G + gx;
-    for (int f = 0; f < F; ++f) kout[(f * N + first + o) * 125 + node] = kblock[f * gtotal + goff[bi] + gi];
+    for (int f = 0; f < F; ++f) kout[(f * N + first + o) * NN + node] = kblock[f * gtotal + goff[bi] + gi];
   }
 }
 
-template <bool KF32>
+template <bool KF32, int NI>
 __global__ __launch_bounds__(256) void k_rk(StageParams sp, const int32_t* __restrict__ tiles,
                                             const int32_t* __restrict__ list, const double* __restrict__ coef,
                                             double* out) {
+  constexpr int NN = (NI + 1) * (NI + 1) * (NI + 1);
   const int bi = blockIdx.y;
   const int32_t* t = tiles + 8 * (int64_t)list[bi];
   const int n4 = (int)(*sp.step & 3);
-  const TileCtx c = tile_ctx(t, sp, n4);
+  const TileCtx c = tile_ctx<NI>(t, sp, n4);
   const int first = t[TI_FIRST];
-  const int nn = c.m * c.m * c.m * 125;
-  const int64_t fs = sp.N * 125, ps = fs * sp.F;
+  const int nn = c.m * c.m * c.m * NN;
+  const int64_t fs = sp.N * NN, ps = fs * sp.F;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
-    const int64_t idx = (int64_t)first * 125 + e;
+    const int64_t idx = (int64_t)first * NN + e;
     for (int f = 0; f < sp.F; ++f) {
       double acc = 0.0;
       for (int i = 0; i < sp.p; ++i) acc = fma(coef[i], kload<KF32>(sp.K, i * ps + f * fs + idx), acc);
@@ -172,10 +176,11 @@ __global__ __launch_bounds__(256) void k_current(StageParams sp, const int32_t* 
   // steps taken: LTS n 2^(lev-lmin), GTS n 2^(lmax-lmin)
   const int64_t steps = sp.mode == LTS_MODE_GTS ? (n << (sp.lmax - sp.lmin)) : (n << (lev - sp.lmin));
   const int par = (int)(steps & 1);
-  const int64_t fs = sp.N * 125, ps = fs * sp.F;
-  const int nn = m * m * m * 125;
+  const int NN = (sp.ni + 1) * (sp.ni + 1) * (sp.ni + 1);
+  const int64_t fs = sp.N * NN, ps = fs * sp.F;
+  const int nn = m * m * m * NN;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
-    const int64_t idx = (int64_t)first * 125 + e;
+    const int64_t idx = (int64_t)first * NN + e;
     for (int f = 0; f < sp.F; ++f) out[f * fs + idx] = sp.U[par * ps + f * fs + idx];
   }
 }
@@ -193,10 +198,11 @@ __global__ __launch_bounds__(256) void k_restore(StageParams sp, const int32_t* 
   const int64_t n = *sp.step;
   const int64_t steps = sp.mode == LTS_MODE_GTS ? (n << (sp.lmax - sp.lmin)) : (n << (lev - sp.lmin));
   const int par = (int)(steps & 1);
-  const int64_t fs = sp.N * 125, ps = fs * sp.F;
-  const int nn = m * m * m * 125;
+  const int NN = (sp.ni + 1) * (sp.ni + 1) * (sp.ni + 1);
+  const int64_t fs = sp.N * NN, ps = fs * sp.F;
+  const int nn = m * m * m * NN;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) {
-    const int64_t idx = (int64_t)first * 125 + e;
+    const int64_t idx = (int64_t)first * NN + e;
     for (int f = 0; f < sp.F; ++f) sp.Uw[par * ps + f * fs + idx] = in[f * fs + idx];
   }
 }
@@ -315,7 +321,7 @@ __global__ void k_increment(int64_t* ctr) {
 }
 
 // per-octant partial sums for the norms: [F][N] sum e^2, [F][N] max |e|, nonfinite count
-__global__ __launch_bounds__(128) void k_norm_partials(const double* a, const double* b, int F, int64_t N,
+__global__ __launch_bounds__(128) void k_norm_partials(const double* a, const double* b, int F, int64_t N, int nn,
                                                        double* sq, double* mx, unsigned long long* bad) {
   const int64_t o = blockIdx.x;
   const int f = blockIdx.y;
@@ -323,14 +329,13 @@ __global__ __launch_bounds__(128) void k_norm_partials(const double* a, const do
   __shared__ int s3[128];
   double q = 0.0, m = 0.0;
   int nb = 0;
-  const int node = threadIdx.x;
-  if (node < 125) {
-    const int64_t idx = ((int64_t)f * N + o) * 125 + node;
+  for (int node = threadIdx.x; node < nn; node += 128) {
+    const int64_t idx = ((int64_t)f * N + o) * nn + node;
     const double x = a[idx];
     const double e = b ? x - b[idx] : x;
-    if (!isfinite(x)) nb = 1;
-    q = e * e;
-    m = fabs(e);
+    if (!isfinite(x)) nb += 1;
+    q += e * e;
+    m = fmax(m, fabs(e));
   }
   s1[threadIdx.x] = q;
   s2[threadIdx.x] = m;
@@ -365,18 +370,46 @@ hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NI>
+static void unzip_ni(bool kf32, const StageParams& sp, dim3 grid, const int32_t* tiles, const int32_t* slots,
+                     const int32_t* list, const int64_t* off, int64_t total, double* out, hipStream_t s) {
+  if (sp.F == 2) {
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 2, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    else hipLaunchKernelGGL((k_unzip<false, 2, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+  } else {
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 6, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    else hipLaunchKernelGGL((k_unzip<false, 6, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+  }
+}
+
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
                         const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
+  if ((sp.F != 2 && sp.F != 6) || (sp.ni != 4 && sp.ni != 6)) return hipErrorInvalidValue;
   dim3 grid(8, nb);
-  if (sp.F == 2) {
-    if (kf32) hipLaunchKernelGGL((k_unzip<true, 2>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
-    else hipLaunchKernelGGL((k_unzip<false, 2>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
-  } else if (sp.F == 6) {
-    if (kf32) hipLaunchKernelGGL((k_unzip<true, 6>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
-    else hipLaunchKernelGGL((k_unzip<false, 6>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+  if (sp.ni == 4) unzip_ni<4>(kf32, sp, grid, tiles, slots, list, off, total, out, s);
+  else unzip_ni<6>(kf32, sp, grid, tiles, slots, list, off, total, out, s);
+  return hipGetLastError();
+}
+
+template <int NI>
+static hipError_t rhs_ni(int eq, bool f32, dim3 grid, const int32_t* tiles, const int32_t* list, const int64_t* poff,
+                         int64_t ptotal, const int64_t* goff, int64_t gtotal, const double* padded, void* kout,
+                         double sigma, const StageParams& geo, hipStream_t s) {
+  if (eq == LTS_EQ_NLWAVE) {
+    if (f32 || NI != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_rhs<LTS_EQ_NLWAVE, 2, false, NI>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
+                       gtotal, padded, kout, sigma, geo);
+  } else if (eq == LTS_EQ_WAVE) {
+    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, true, NI>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
+                                goff, gtotal, padded, kout, sigma, geo);
+    else hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, false, NI>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
+                            goff, gtotal, padded, kout, sigma, geo);
   } else {
-    return hipErrorInvalidValue;
+    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, true, NI>), grid, dim3(256), 0, s, tiles, list, poff,
+                                ptotal, goff, gtotal, padded, kout, sigma, geo);
+    else hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, false, NI>), grid, dim3(256), 0, s, tiles, list, poff,
+                            ptotal, goff, gtotal, padded, kout, sigma, geo);
   }
   return hipGetLastError();
 }
@@ -386,34 +419,27 @@ hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* lis
                       double sigma, const StageParams& geo, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   dim3 grid(8, nb);
-  if (eq == LTS_EQ_NLWAVE) {
-    if (f32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_rhs<LTS_EQ_NLWAVE, 2, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
-                       gtotal, padded, kout, sigma, geo);
-    return hipGetLastError();
-  }
-  if (eq == LTS_EQ_WAVE) {
-    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
-                                gtotal, padded, kout, sigma, geo);
-    else hipLaunchKernelGGL((k_rhs<LTS_EQ_WAVE, 2, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal, goff,
-                            gtotal, padded, kout, sigma, geo);
-  } else {
-    if (f32) hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, true>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
-                                goff, gtotal, padded, kout, sigma, geo);
-    else hipLaunchKernelGGL((k_rhs<LTS_EQ_MAXWELL, 6, false>), grid, dim3(256), 0, s, tiles, list, poff, ptotal,
-                            goff, gtotal, padded, kout, sigma, geo);
-  }
-  return hipGetLastError();
+  if (geo.ni == 4) return rhs_ni<4>(eq, f32, grid, tiles, list, poff, ptotal, goff, gtotal, padded, kout, sigma, geo, s);
+  if (geo.ni == 6) return rhs_ni<6>(eq, f32, grid, tiles, list, poff, ptotal, goff, gtotal, padded, kout, sigma, geo, s);
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_zip(bool f32, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal, int nb,
-                      int F, int64_t N, const void* kblock, void* kout, hipStream_t s) {
+template <int NI>
+static void zip_ni(bool f32, dim3 grid, const int32_t* tiles, const int32_t* list, const int64_t* goff,
+                   int64_t gtotal, int F, int64_t N, const void* kblock, void* kout, hipStream_t s) {
+  if (f32) hipLaunchKernelGGL((k_zip<float, NI>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
+                              (const float*)kblock, (float*)kout);
+  else hipLaunchKernelGGL((k_zip<double, NI>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
+                          (const double*)kblock, (double*)kout);
+}
+
+hipError_t launch_zip(bool f32, int ni, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal,
+                      int nb, int F, int64_t N, const void* kblock, void* kout, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   dim3 grid(8, nb);
-  if (f32) hipLaunchKernelGGL((k_zip<float>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
-                              (const float*)kblock, (float*)kout);
-  else hipLaunchKernelGGL((k_zip<double>), grid, dim3(256), 0, s, tiles, list, goff, gtotal, F, N,
-                          (const double*)kblock, (double*)kout);
+  if (ni == 4) zip_ni<4>(f32, grid, tiles, list, goff, gtotal, F, N, kblock, kout, s);
+  else if (ni == 6) zip_ni<6>(f32, grid, tiles, list, goff, gtotal, F, N, kblock, kout, s);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -421,8 +447,15 @@ hipError_t launch_rk(bool kf32, const StageParams& sp, const int32_t* tiles, con
                      const double* coef, double* out, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   dim3 grid(4, nb);
-  if (kf32) hipLaunchKernelGGL((k_rk<true>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
-  else hipLaunchKernelGGL((k_rk<false>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+  if (sp.ni == 4) {
+    if (kf32) hipLaunchKernelGGL((k_rk<true, 4>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+    else hipLaunchKernelGGL((k_rk<false, 4>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+  } else if (sp.ni == 6) {
+    if (kf32) hipLaunchKernelGGL((k_rk<true, 6>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+    else hipLaunchKernelGGL((k_rk<false, 6>), grid, dim3(256), 0, s, sp, tiles, list, coef, out);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -464,10 +497,10 @@ hipError_t launch_increment(int64_t* ctr, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, double* sq, double* mx,
+hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, int nn, double* sq, double* mx,
                                 unsigned long long* bad, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_norm_partials, dim3((unsigned)N, F), dim3(128), 0, s, a, b, F, N, sq, mx, bad);
+  hipLaunchKernelGGL(k_norm_partials, dim3((unsigned)N, F), dim3(128), 0, s, a, b, F, N, nn, sq, mx, bad);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/lts.h"
@@ -36,6 +37,12 @@ struct TileSet {
 struct Mesh {
   int L = 0, lmin = 0, lmax = 0, cap = 4;
   bool periodic = true;               // false: bounded by the outer faces
+  int nodes = 5;                      // nodes per octant side (5 or 7)
+  // 7-node meshes: a finer slot names a row of 8 child leaves (-1: refined
+  // further), one row per distinct finer ghost cell (key: level, cell)
+  std::vector<int32_t> fine8;
+  std::unordered_map<uint64_t, int32_t> fine_row;
+  int32_t* d_fine8 = nullptr;
   std::vector<int32_t> ax, ay, az;
   std::vector<int8_t> lev;
   std::vector<uint64_t> key;          // Morton key of the anchor (sorted)
@@ -63,13 +70,15 @@ struct Mesh {
   size_t list_cap = 0;
 
   int64_t n() const { return (int64_t)lev.size(); }
+  int ni() const { return nodes - 1; }
+  int64_t nn() const { return (int64_t)nodes * nodes * nodes; }   // nodes per octant
   int find(int level, int64_t cx, int64_t cy, int64_t cz) const;
 };
 
 lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m);
 lts_status build_tiles(Mesh& m, int t);
 lts_status build_block_tiles(Mesh& m);
-void unzip_map_block(const Mesh& m, int b, int32_t* out);  // [(4m+7)^3][5]
+void unzip_map_block(const Mesh& m, int b, int32_t* out);  // [(ni m+7)^3][5]
 
 // Remeshing (remesh.cpp): complete same-level sibling families (first leaf), the
 // new leaf list [n][4] from the wavelet indicators, and the intergrid transfer

@@ -8,9 +8,9 @@ namespace lts {
 // Arguments of one stage launch.  w holds the stage's conversion weights per
 // time case (w[case][i], eqs. fc_1/fc_2); b the RK weights.
 struct StageParams {
-  const double* U;      // [2][F][N][125]
+  const double* U;      // [2][F][N][n^3], n = ni + 1 nodes per octant side
   double* Uw;           // same array, written by the last stage
-  const void* K;        // [p][F][N][125] double or float
+  const void* K;        // [p][F][N][n^3] double or float
   void* Kw;             // same array, K_stage written
   int64_t N;
   int F, p, stage, mode, j, lmin, lmax;
@@ -26,6 +26,10 @@ struct StageParams {
   double nl_coeff;
   // counter of non-finite values written by the RK update (nullptr: not counted)
   unsigned int* nonfinite;
+  // node intervals per octant side (4 or 6) and, for ni = 6, the mesh's table
+  // of 8 finer leaves per finer ghost cell
+  int ni;
+  const int32_t* fine8;
 };
 
 // Geometry the non-linear wave's stencils need at one block: its grid origin in
@@ -112,8 +116,8 @@ hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, 
 hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,
                       int64_t ptotal, const int64_t* goff, int64_t gtotal, int nb, const double* padded, void* kout,
                       double sigma, const StageParams& geo, hipStream_t s);
-hipError_t launch_zip(bool f32, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal, int nb,
-                      int F, int64_t N, const void* kblock, void* kout, hipStream_t s);
+hipError_t launch_zip(bool f32, int ni, const int32_t* tiles, const int32_t* list, const int64_t* goff, int64_t gtotal,
+                      int nb, int F, int64_t N, const void* kblock, void* kout, hipStream_t s);
 hipError_t launch_rk(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* list, int nb,
                      const double* coef, double* out, hipStream_t s);
 hipError_t launch_current(const StageParams& sp, const int32_t* tiles, int nblocks, double* out, hipStream_t s);
@@ -129,7 +133,7 @@ hipError_t launch_wavelet(const double* st, int F, int64_t N, const int64_t* fam
 hipError_t launch_transfer(const double* st_old, int64_t N_old, double* st_new, int64_t N_new, int F,
                            const int32_t* rec, hipStream_t s);
 hipError_t launch_increment(int64_t* ctr, hipStream_t s);
-hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, double* sq, double* mx,
+hipError_t launch_norm_partials(const double* a, const double* b, int F, int64_t N, int nn, double* sq, double* mx,
                                 unsigned long long* bad, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t nbytes, hipStream_t s);
 

@@ -1,9 +1,9 @@
-// Host mesh builder: refinement, ghost-reach balance, octree-to-block
-// decomposition, tiles with their ghost-source slot tables, exports.
+// Host mesh builder: refinement, balance, octree-to-block decomposition, tiles
+// with their ghost-source slot tables, exports.
 //
-// Sec. 3.2.2 (refinement), Sec. 3.2.3 (2:1 balance, here extended to the reach
-// of three ghost layers), Sec. 3.2.4 (o2o neighbour search), Sec. 3.2.5 +
-// fig. oct_to_blocks (blocks = uniformly refined sub-trees).
+// Sec. 3.2.2 (refinement), Sec. 3.2.3 (2:1 balance; for 5-node octants extended
+// to the reach of three ghost layers), Sec. 3.2.4 (o2o neighbour search),
+// Sec. 3.2.5 + fig. oct_to_blocks (blocks = uniformly refined sub-trees).
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -63,16 +63,16 @@ int64_t dmax_axis(int64_t lo, int64_t hi, int64_t c, int64_t n) {
 int64_t dmin_axis_bounded(int64_t lo, int64_t hi, int64_t c) { return std::max<int64_t>(0, std::max(lo - c, c - hi)); }
 int64_t dmax_axis_bounded(int64_t lo, int64_t hi, int64_t c) { return std::max(std::abs(lo - c), std::abs(hi - c)); }
 
-bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L, bool periodic) {
-  const int64_t n = 4ll << L;
+bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L, bool periodic, int ni) {
+  const int64_t n = (int64_t)ni << L;
   const int64_t s = 1ll << (L - f.l);
-  const int64_t lo[3] = {4ll * f.x, 4ll * f.y, 4ll * f.z};
+  const int64_t lo[3] = {(int64_t)ni * f.x, (int64_t)ni * f.y, (int64_t)ni * f.z};
   for (int ci = 0; ci < spec->n_criteria; ++ci) {
     const lts_criterion& c = spec->criteria[ci];
     int64_t dmin2 = 0, dmax2 = 0;
     for (int d = 0; d < 3; ++d) {
-      int64_t a = periodic ? dmin_axis(lo[d], lo[d] + 4 * s, c.center[d], n)
-                           : dmin_axis_bounded(lo[d], lo[d] + 4 * s, c.center[d]);
+      int64_t a = periodic ? dmin_axis(lo[d], lo[d] + ni * s, c.center[d], n)
+                           : dmin_axis_bounded(lo[d], lo[d] + ni * s, c.center[d]);
       dmin2 += a * a;
     }
     if (c.kind == LTS_CRIT_BALL) {
@@ -80,8 +80,8 @@ bool refine_leaf(const lts_mesh_spec* spec, const Leaf& f, int L, bool periodic)
     } else {
       if (c.rhi2[f.l] < 0) continue;
       for (int d = 0; d < 3; ++d) {
-        int64_t a = periodic ? dmax_axis(lo[d], lo[d] + 4 * s, c.center[d], n)
-                             : dmax_axis_bounded(lo[d], lo[d] + 4 * s, c.center[d]);
+        int64_t a = periodic ? dmax_axis(lo[d], lo[d] + ni * s, c.center[d], n)
+                             : dmax_axis_bounded(lo[d], lo[d] + ni * s, c.center[d]);
         dmax2 += a * a;
       }
       if (c.rlo2[f.l] < dmax2 && dmin2 < c.rhi2[f.l]) return true;
@@ -145,11 +145,13 @@ struct Prefix {
   }
 };
 
-// Ghost-reach balance: split a level-l leaf while a leaf of level >= l+2 has
-// Chebyshev box distance <= 3 h_l from it (periodic images on a periodic domain).  For each l the test runs on
-// the level-(l+2) cell grid: the leaf spans cells [A, A+4) per axis and the cells
-// whose closed box meets its box grown by 3 h_l (= 3 cells) are [A-4, A+7].
-lts_status balance(std::vector<Leaf>& leaves, int L, bool periodic) {
+// Balance: split a level-l leaf while a leaf of level >= l+2 has Chebyshev box
+// distance <= 3 h_l from it (reach: 5-node octants) or touches it (2:1 balance:
+// 7-node octants), with periodic images on a periodic domain.  For each l the
+// test runs on the level-(l+2) cell grid: the leaf spans cells [A, A+4) per axis;
+// the cells whose closed box meets its box grown by 3 h_l (= 3 cells) are
+// [A-4, A+7], those whose closed box meets its own box [A-1, A+4].
+lts_status balance(std::vector<Leaf>& leaves, int L, bool periodic, bool reach) {
   for (int pass = 0; pass < 64; ++pass) {
     int lo_lev = 99, hi_lev = -1;
     for (const Leaf& f : leaves) { lo_lev = std::min(lo_lev, f.l); hi_lev = std::max(hi_lev, f.l); }
@@ -184,7 +186,10 @@ lts_status balance(std::vector<Leaf>& leaves, int L, bool periodic) {
         if (f.l != l) continue;
         const int64_t A[3] = {f.x >> sh, f.y >> sh, f.z >> sh};
         int64_t lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) { lo[d] = A[d] - 4; hi[d] = A[d] + 7; }
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = A[d] - (reach ? 4 : 1);
+          hi[d] = A[d] + (reach ? 7 : 4);
+        }
         if (pf.count(lo, hi) > 0) { split[i] = 1; any = true; }
       }
     }
@@ -224,6 +229,8 @@ lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m) {
   if (spec->boundary != LTS_BOUNDARY_PERIODIC && spec->boundary != LTS_BOUNDARY_OUTER)
     return fail(LTS_EINVAL, "boundary must be LTS_BOUNDARY_PERIODIC or LTS_BOUNDARY_OUTER");
   const bool periodic = spec->boundary == LTS_BOUNDARY_PERIODIC;
+  const int nodes = spec->nodes == 0 ? 5 : spec->nodes;
+  if (nodes != 5 && nodes != 7) return fail(LTS_EINVAL, "nodes per octant side must be 5 or 7");
   std::vector<Leaf> leaves;
   if (spec->n_leaves > 0) {
     if (!spec->leaves) return fail(LTS_EINVAL, "leaves is NULL");
@@ -266,19 +273,22 @@ lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m) {
     for (int l = spec->l_min; l < L && !cur.empty(); ++l) {
       std::vector<Leaf> next;
       for (const Leaf& f : cur) {
-        if (refine_leaf(spec, f, L, periodic)) push_children(next, f, L);
+        if (refine_leaf(spec, f, L, periodic, nodes - 1)) push_children(next, f, L);
         else leaves.push_back(f);
       }
       cur.swap(next);
     }
     leaves.insert(leaves.end(), cur.begin(), cur.end());
   }
-  lts_status st = balance(leaves, L, periodic);
+  lts_status st = balance(leaves, L, periodic, nodes == 5);
   if (st != LTS_OK) return st;
   sort_leaves(leaves);
 
   m.L = L;
   m.periodic = periodic;
+  m.nodes = nodes;
+  m.fine8.clear();
+  m.fine_row.clear();
   m.cap = spec->block_cap;
   const size_t N = leaves.size();
   m.ax.resize(N); m.ay.resize(N); m.az.resize(N); m.lev.resize(N); m.key.resize(N);
@@ -333,7 +343,7 @@ namespace {
 
 // Slot table entry of the level-l cell c (block-relative octant coordinates,
 // may lie outside the block).
-lts_status slot_entry(const Mesh& m, const Block& B, int cx, int cy, int cz, int32_t out[2]) {
+lts_status slot_entry(Mesh& m, const Block& B, int cx, int cy, int cz, int32_t out[2]) {
   if (cx >= 0 && cy >= 0 && cz >= 0 && cx < B.m && cy < B.m && cz < B.m) {
     out[0] = B.first + (int32_t)morton3(cx, cy, cz);
     out[1] = SRC_SAME;
@@ -367,6 +377,34 @@ lts_status slot_entry(const Mesh& m, const Block& B, int cx, int cy, int cz, int
       return LTS_OK;
     }
   }
+  if (m.nodes == 7) {
+    // the children next to the block must be leaves: per axis c = 1 below the
+    // block, 0 above it, both where the cell is level with the block
+    int32_t row[8];
+    const int cc[3] = {cx, cy, cz};
+    for (int c = 0; c < 8; ++c) {
+      row[c] = m.find(l + 1, 2 * wx + (c & 1), 2 * wy + ((c >> 1) & 1), 2 * wz + ((c >> 2) & 1));
+      bool needed = true;
+      for (int d = 0; d < 3; ++d) {
+        const int cd = (c >> d) & 1;
+        if ((cc[d] < 0 && cd == 0) || (cc[d] >= B.m && cd == 1)) needed = false;
+      }
+      if (needed && row[c] < 0) return fail(LTS_EUNBALANCED, "ghost cell is neither same, coarser nor finer");
+    }
+    const uint64_t key = ((uint64_t)(l + 1) << 60) | key_of(wx, wy, wz);
+    auto it = m.fine_row.find(key);
+    int32_t r;
+    if (it != m.fine_row.end()) {
+      r = it->second;
+    } else {
+      r = (int32_t)(m.fine8.size() / 8);
+      m.fine8.insert(m.fine8.end(), row, row + 8);
+      m.fine_row.emplace(key, r);
+    }
+    out[0] = r;
+    out[1] = SRC_FINE;
+    return LTS_OK;
+  }
   leaf = m.find(l + 1, 2 * wx, 2 * wy, 2 * wz);
   if (leaf < 0) return fail(LTS_EUNBALANCED, "ghost cell is neither same, coarser nor finer");
   for (int c = 1; c < 8; ++c) {
@@ -382,8 +420,8 @@ lts_status slot_entry(const Mesh& m, const Block& B, int cx, int cy, int cz, int
 // order, followed by work lists (one int pair each): the same-level slots, the
 // finer slots, the coarser slots, then the distinct coarser source leaves (cidx
 // numbers them in order of first appearance).
-lts_status add_tile(const Mesh& m, int b, int tt, int ox, int oy, int oz, TileSet& ts) {
-  const Block& B = m.blocks[b];
+lts_status add_tile(Mesh& m, int b, int tt, int ox, int oy, int oz, TileSet& ts) {
+  const Block B = m.blocks[b];
   const int w = tt + 2;
   const int ns = w * w * w;
   std::vector<int32_t> tab(2 * ns);
@@ -572,13 +610,14 @@ void unzip_map_block(const Mesh& m, int b, int32_t* out) {
   const TileSet& ts = m.bt;
   const int32_t* t = &ts.tiles[8 * b];
   const int mm = t[TI_M];
-  const int P = 4 * mm + 7;
+  const int ni = m.ni();
+  const int P = ni * mm + 7;
   const int32_t* slots = &ts.slots[2 * (size_t)t[TI_SLOT]];
   size_t r = 0;
   for (int qz = 0; qz < P; ++qz)
     for (int qy = 0; qy < P; ++qy)
       for (int qx = 0; qx < P; ++qx, ++r) {
-        Loc L = locate(qx, qy, qz, 0, 0, 0, mm, mm);
+        Loc L = locate(qx, qy, qz, 0, 0, 0, mm, mm, ni);
         const int32_t leaf = slots[2 * L.slot], kb = slots[2 * L.slot + 1];
         const int kind = kb & 15, beta = (kb >> 4) & 7;
         const int sx = L.slot % (mm + 2), sy = (L.slot / (mm + 2)) % (mm + 2), sz = L.slot / ((mm + 2) * (mm + 2));
@@ -595,12 +634,18 @@ void unzip_map_block(const Mesh& m, int b, int32_t* out) {
           for (int d = 0; d < 3; ++d) o[2 + d] = 2 * L.nu[d];
         } else if (kind == SRC_FINE) {
           int c[3];
-          for (int d = 0; d < 3; ++d) c[d] = L.nu[d] >> 1 < 1 ? L.nu[d] >> 1 : 1;
-          o[0] = leaf + c[0] + 2 * c[1] + 4 * c[2]; o[1] = SRC_FINE;
-          for (int d = 0; d < 3; ++d) o[2 + d] = 4 * (L.nu[d] - 2 * c[d]);
+          if (ni == 4) {
+            for (int d = 0; d < 3; ++d) c[d] = L.nu[d] >> 1 < 1 ? L.nu[d] >> 1 : 1;
+            o[0] = leaf + c[0] + 2 * c[1] + 4 * c[2];
+          } else {
+            for (int d = 0; d < 3; ++d) c[d] = fine_child6(L.nu[d], (L.below >> d) & 1);
+            o[0] = m.fine8[8 * (size_t)leaf + c[0] + 2 * c[1] + 4 * c[2]];
+          }
+          o[1] = SRC_FINE;
+          for (int d = 0; d < 3; ++d) o[2 + d] = 2 * (2 * L.nu[d] - ni * c[d]);
         } else {
           o[0] = leaf; o[1] = SRC_COARSE;
-          for (int d = 0; d < 3; ++d) o[2 + d] = 4 * ((beta >> d) & 1) + L.nu[d];
+          for (int d = 0; d < 3; ++d) o[2 + d] = ni * ((beta >> d) & 1) + L.nu[d];
         }
       }
 }

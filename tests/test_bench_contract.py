@@ -78,3 +78,21 @@ def test_analytic_fields_match_oracle():
             assert np.abs(got[f] - want[f]).max() <= 1e-12 * np.abs(want[f]).max(), (T, f)
     e = bench.analytic_error(torch.as_tensor(want), leaves, L, pulses, 0.1, 0.3)
     assert e["l2_u"] < 1e-13 * e["l2_exact_u"] and e["l2_v"] < 1e-13 * e["l2_exact_v"]
+
+
+def test_analytic_fields_nodes7_match_oracle():
+    """The same on a 7-node mesh (wave7_small): every node of its 7^3 octants."""
+    from oracle import analytic as an
+    from oracle import octree as ot
+    from workloads import centre_physical, mesh_spec, node_units, physical
+    m = ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec("wave7_small")))
+    L = m.L
+    pulses = [[55, 37, 26]]
+    leaves = np.concatenate([m.anchors, m.levels[:, None]], axis=1)
+    X = physical(node_units(m.anchors, m.levels, L, nodes=7), L, nodes=7)
+    c = np.stack([centre_physical(p, L, nodes=7) for p in pulses])
+    for T in (0.0, 0.05):
+        got = bench.analytic_fields(leaves, L, pulses, 0.1, T, "cpu", nodes=7).numpy()
+        want = an.gaussian_periodic(X, c, T, 0.1).reshape(2, m.n_oct, 343)
+        for f in range(2):
+            assert np.abs(got[f] - want[f]).max() <= 1e-12 * max(np.abs(want[f]).max(), 1e-300), (T, f)

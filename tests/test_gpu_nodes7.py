@@ -1,0 +1,206 @@
+"""GPU parity of the 7^3-node path (the paper's octants, 2:1 balance; phase kernels
+templated on the node count) with the oracle, through the C ABI: unzip at
+positioned LTS/GTS states, block RHS, zip, RK update, whole runs with classic RK4
+and SSP-RK3, the graph-captured lts_advance against the eager phase calls,
+FP32 stencils, norms, checkpoint/restore, and the refusals."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2011_10570_amd as P
+from oracle import fd
+from oracle import octree as ot
+from oracle import solver as so
+from workloads import config, mesh_spec, random_dg, wave_gaussian
+
+from gpu_common import TOL, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+NAME = "wave7_small"
+N7 = 7
+
+
+@pytest.fixture(scope="module")
+def mesh7():
+    om = ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec(NAME)))
+    gm = P.build_mesh(mesh_spec(NAME))
+    assert gm.info()["nodes"] == 7 and om.nodes == 7
+    return om, gm
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _positioned(om, nfields, mode, n, j, seed, tableau="rk4"):
+    st = so.State(om, nfields, tableau, mode)
+    nsub = ot.substeps(om)
+    for _ in range(n):
+        for jj in range(nsub):
+            st.close_records(st.open_records(jj))
+    for jj in range(j):
+        st.close_records(st.open_records(jj))
+    act = st.open_records(j)
+    st.U[:] = random_dg(st.U.shape, seed)
+    st.K[:] = random_dg(st.K.shape, seed + 1, 0.5)
+    return st, act
+
+
+CASES = [("lts", 0, 0), ("lts", 0, 1), ("lts", 1, 2), ("lts", 1, 3), ("gts", 1, 2)]
+
+
+@pytest.mark.parametrize("mode,n,j", CASES)
+@pytest.mark.parametrize("stage", [0, 1, 2, 3])
+def test_unzip7(mesh7, mode, n, j, stage):
+    om, gm = mesh7
+    print(f"[unzip7] {mode} n={n} j={j} s={stage}", flush=True)
+    st, act = _positioned(om, 2, mode, n, j, seed=10 * n + j + stage)
+    S = 6 * om.blocks[act, 1] + 7
+    out = torch.full((2, int((S ** 3).sum())), np.nan, dtype=torch.float64, device=DEV)
+    md = P.MODE_GTS if mode == "gts" else P.MODE_LTS
+    P.unzip(gm, _dev(st.U), _dev(st.K), stage, j, md, n, None, out)
+    want = np.concatenate([st.unzip(int(b), stage).reshape(2, -1) for b in act], axis=1)
+    assert rel_err(out.cpu().numpy(), want) < TOL
+
+
+@pytest.mark.parametrize("eq,prec", [("wave", P.FP64), ("maxwell", P.FP64), ("wave", P.FP32_RHS)])
+def test_rhs7(mesh7, eq, prec):
+    om, gm = mesh7
+    F = 2 if eq == "wave" else 6
+    ids = np.arange(len(om.blocks))
+    S = 6 * om.blocks[ids, 1] + 7
+    G = 6 * om.blocks[ids, 1] + 1
+    pad = random_dg((F, int((S ** 3).sum())), 5)
+    kdt = torch.float32 if prec == P.FP32_RHS else torch.float64
+    out = torch.zeros((F, int((G ** 3).sum())), dtype=kdt, device=DEV)
+    P.rhs(gm, P.EQ_WAVE if eq == "wave" else P.EQ_MAXWELL, 0.1, _dev(pad), prec, ids, out)
+    rfun = fd.rhs_wave if eq == "wave" else fd.rhs_maxwell
+    po, want = 0, []
+    for b, s in zip(ids, S):
+        h = ot.h_level(int(om.blocks[b, 2]), N7)
+        want.append(rfun(pad[:, po:po + s ** 3].reshape(F, s, s, s), h, 0.1).reshape(F, -1))
+        po += s ** 3
+    tol = 2e-5 if prec == P.FP32_RHS else TOL
+    assert rel_err(out.double().cpu().numpy(), np.concatenate(want, axis=1)) < tol
+
+
+def test_zip7(mesh7):
+    om, gm = mesh7
+    ids = np.arange(0, len(om.blocks), 2)
+    G = 6 * om.blocks[ids, 1] + 1
+    kb = random_dg((2, int((G ** 3).sum())), 8)
+    N = om.n_oct
+    out = torch.full((2, N, 343), 7.0, dtype=torch.float64, device=DEV)
+    P.zip(gm, 2, P.FP64, _dev(kb), ids, out)
+    st, _ = _positioned(om, 2, "lts", 0, 0, seed=1)
+    want = np.full((2, N, 7, 7, 7), 7.0)
+    go = 0
+    for b, g in zip(ids, G):
+        st.zip_into(int(b), kb[:, go:go + g ** 3].reshape(2, g, g, g), want)
+        go += g ** 3
+    assert np.array_equal(out.cpu().numpy(), want.reshape(2, N, 343))
+
+
+@pytest.mark.parametrize("mode,n,j", [("lts", 0, 0), ("lts", 1, 3), ("gts", 0, 2)])
+def test_rk_update7(mesh7, mode, n, j):
+    om, gm = mesh7
+    st, act = _positioned(om, 2, mode, n, j, seed=21, tableau="ssprk3")
+    U, K = _dev(st.U), _dev(st.K)
+    md = P.MODE_GTS if mode == "gts" else P.MODE_LTS
+    P.rk_stage(gm, U, K, list(st.b), j, md, n, None, None, tableau=P.SSPRK3)
+    st.rk_update(act)
+    assert rel_err(U.cpu().numpy().reshape(2, 2, -1), st.U.reshape(2, 2, -1)) < TOL
+
+
+@pytest.fixture(scope="module")
+def initial7(mesh7):
+    om, _ = mesh7
+    cfg = config(NAME)
+    return wave_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=cfg["sigma"], nodes=N7)
+
+
+@pytest.mark.parametrize("mode,tableau", [("lts", "ssprk3"), ("gts", "ssprk3"), ("lts", "rk4")])
+def test_run_matches_oracle7(mesh7, initial7, mode, tableau):
+    """Two coarse steps (levels 2-4: 4 substeps each) of the configuration, graph-
+    captured lts_advance against the oracle; the eager phase calls give the same
+    state bitwise (the same kernels)."""
+    om, gm = mesh7
+    cfg = config(NAME)
+    n = cfg["n_coarse"]
+    print(f"[run7] {mode} {tableau} oracle...", flush=True)
+    want = so.run(om, initial7, n, mode, sigma=cfg["ko_sigma"], tableau=tableau).reshape(2, om.n_oct, -1)
+    md = P.MODE_GTS if mode == "gts" else P.MODE_LTS
+    s = P.Sim(gm, "wave", P.FP64, tableau, ko_sigma=cfg["ko_sigma"], device=DEV)
+    s.set_state(initial7)
+    s.advance(n, md, graph=True, check_finite=True)
+    got = s.current()
+    assert s.coarse_step == n
+    assert rel_err(got.cpu().numpy(), want) < TOL
+    e = P.Sim(gm, "wave", P.FP64, tableau, ko_sigma=cfg["ko_sigma"], device=DEV)
+    e.set_state(initial7)
+    e.advance_unfused(n, md)
+    assert torch.equal(e.current(), got)
+
+
+def test_fp32_rhs_run7(mesh7, initial7):
+    """FP32 stencils (FP64 state, RK and time interpolation) stay within FP32
+    rounding of the FP64 run."""
+    _, gm = mesh7
+    outs = {}
+    for prec in (P.FP64, P.FP32_RHS):
+        s = P.Sim(gm, "wave", prec, "ssprk3", ko_sigma=0.1, device=DEV)
+        s.set_state(initial7)
+        s.advance(2, P.MODE_LTS)
+        outs[prec] = s.current().cpu().numpy()
+    assert rel_err(outs[P.FP32_RHS], outs[P.FP64]) < 1e-4
+
+
+def test_checkpoint_restore7(mesh7, initial7):
+    _, gm = mesh7
+    a = P.Sim(gm, "wave", P.FP64, "ssprk3", device=DEV)
+    a.set_state(initial7)
+    a.advance(1, P.MODE_LTS)
+    ck = a.checkpoint()
+    a.advance(1, P.MODE_LTS)
+    b = P.Sim(gm, "wave", P.FP64, "ssprk3", device=DEV)
+    b.restore(ck)
+    b.advance(1, P.MODE_LTS)
+    assert torch.equal(a.current(), b.current())
+
+
+def test_norms7(mesh7):
+    om, gm = mesh7
+    a = random_dg((2, om.n_oct, 343), 3)
+    b = random_dg((2, om.n_oct, 343), 4)
+    r = P.norms(gm, _dev(a), _dev(b), 2)
+    w = (2.0 ** (om.L - om.levels)) ** 3
+    for f in range(2):
+        e = a[f] - b[f]
+        l2 = np.sqrt((w * (e ** 2).sum(1)).sum() / (343 * w.sum()))
+        assert abs(r["l2"][f] - l2) < 1e-12 * l2
+        assert r["linf"][f] == np.abs(e).max()
+
+
+def test_refusals7(mesh7):
+    """The fused stage, batches, the non-linear wave and remeshing refuse 7-node
+    meshes with LTS_EUNSUPPORTED."""
+    om, gm = mesh7
+    U = torch.zeros((2, 2, om.n_oct, 343), dtype=torch.float64, device=DEV)
+    K = torch.zeros((4, 2, om.n_oct, 343), dtype=torch.float64, device=DEV)
+    with pytest.raises(P.LTSError) as e:
+        P.fused_stage(gm, U, K, P.EQ_WAVE, 0.1, 0, 0, P.MODE_LTS, 0)
+    assert e.value.status == P._L.EUNSUPPORTED
+    s = P.Sim(gm, "wave", P.FP64, "rk4", device=DEV)
+    s.set_state(np.zeros((2, om.n_oct, 343)))
+    b = P.Batch("wave", P.FP64, "rk4", P.MODE_LTS, capacity=2)
+    with pytest.raises(P.LTSError) as e:
+        b.attach(s, 1)
+    assert e.value.status == P._L.EUNSUPPORTED
+    with pytest.raises(P.LTSError) as e:
+        P.Sim(gm, "nlwave", P.FP64, "rk4", device=DEV)
+    assert e.value.status == P._L.EUNSUPPORTED
+    with pytest.raises(P.LTSError) as e:
+        P.remesh_indicators(gm, s.current())
+    assert e.value.status == P._L.EUNSUPPORTED

@@ -37,7 +37,7 @@ def _oracle_mesh(name):
     return ot.build_mesh(ot.MeshSpec.from_dict(mesh_spec(name)))
 
 
-@pytest.mark.parametrize("name", ["small", "wave_c1", "nl_small", "nl_c1"])
+@pytest.mark.parametrize("name", ["small", "wave_c1", "nl_small", "nl_c1", "wave7_small"])
 def test_mesh_bit_exact(name):
     om = _oracle_mesh(name)
     gm = P.build_mesh(mesh_spec(name))
@@ -64,7 +64,7 @@ def test_ghost_owner_fixture_library():
         assert map_row(mp[off[b]:off[b + 1]], int(blocks[b, 1]), qx, qy, qz) == r[4:9], r
 
 
-@pytest.mark.parametrize("name", ["small", "wave_c1", "nl_small", "nl_c1"])
+@pytest.mark.parametrize("name", ["small", "wave_c1", "nl_small", "nl_c1", "wave7_small"])
 def test_unzip_map_bit_exact(name):
     om = _oracle_mesh(name)
     gm = P.build_mesh(mesh_spec(name))
@@ -84,10 +84,12 @@ def test_mesh_info_matches_model():
 
 
 @pytest.mark.slow
-def test_c2_mesh_bit_exact():
-    """The 200k-leaf benchmark mesh: leaves and blocks identical to the oracle's."""
-    om = _oracle_mesh("wave_c2")
-    gm = P.build_mesh(mesh_spec("wave_c2"))
+@pytest.mark.parametrize("name", ["wave_c2", "wave7_c2"])
+def test_c2_mesh_bit_exact(name):
+    """The benchmark meshes (200k leaves of 5^3 nodes; 75k leaves of 7^3 nodes):
+    leaves and blocks identical to the oracle's."""
+    om = _oracle_mesh(name)
+    gm = P.build_mesh(mesh_spec(name))
     lv = gm.leaves()
     assert np.array_equal(lv[:, :3], om.anchors) and np.array_equal(lv[:, 3], om.levels)
     assert np.array_equal(gm.blocks(), om.blocks)
@@ -240,3 +242,22 @@ def test_bounded_mesh_info():
     spec.l_min, spec.l_max, spec.block_cap, spec.boundary = 2, 3, 4, 7
     h = ctypes.c_void_p()
     assert P.lib().lts_build_mesh(ctypes.byref(spec), ctypes.byref(h)) == _lib.EINVAL
+
+
+def test_nodes7_mesh_info_and_refusals():
+    """A 7-node mesh reports its nodes and the speedup model with 343 nodes per
+    octant; the fused stage, batches and remeshing refuse it before device work;
+    an unknown node count is refused."""
+    om = _oracle_mesh("wave7_small")
+    gm = P.build_mesh(mesh_spec("wave7_small"))
+    info = gm.info()
+    sm = ot.speedup_model(om)
+    assert info["nodes"] == 7 and om.nodes == 7
+    assert info["node_updates_lts"] == sm["w_lts"] and info["node_updates_gts"] == sm["w_gts"]
+    ni = 6
+    assert info["unzip_points"] == sum((ni * int(m) + 7) ** 3 for m in om.blocks[:, 1])
+    assert P.build_mesh(mesh_spec("small")).info()["nodes"] == 5
+    spec = dict(mesh_spec("small"))
+    spec["nodes"] = 6
+    with pytest.raises(P.LTSError):
+        P.build_mesh(spec)

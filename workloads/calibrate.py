@@ -23,8 +23,13 @@ the paper's Gaussian-pulse workloads, Sec. 4.2 and 4.5):
             (radius R, width sigma), refined on a shell of annuli around R.
             nl_small levels 2-3; nl_c1 levels 3-5; nl_c2 levels 3-6 (the
             LTS-GTS difference over time, the analogue of Table accu_nl).
+  wave7_*   7^3 nodes per octant with 2:1 balance and SSP-RK3 (the paper's
+            discretisation, Sec. 4.3 and 4.5): wave7_small levels 2-4 around one
+            pulse (oracle-sized); wave7_c2 levels 3-8, the four wave_c2 pulses
+            and the same gradient criterion in 7-node units, about as many DG
+            nodes as wave_c2 (75k leaves x 343 nodes).
 
-Usage: ``python -m workloads.calibrate [--base] [--batch] [--serve] [--nl]`` recomputes
+Usage: ``python -m workloads.calibrate [--base] [--batch] [--serve] [--nl] [--n7]`` recomputes
 the named groups (all of them when the file does not exist yet) and keeps the
 others as stored.
 """
@@ -45,12 +50,15 @@ from workloads import centre_from_seed  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def ball_spec(l_min, L, centre, radii_nu):
+def ball_spec(l_min, L, centre, radii_nu, nodes=5):
     r2 = [-1] * L
     for lev in range(l_min, L):
         r2[lev] = int(radii_nu[lev - l_min]) ** 2
-    return {"l_min": l_min, "l_max": L, "block_cap": 4,
+    spec = {"l_min": l_min, "l_max": L, "block_cap": 4,
             "criteria": [{"kind": "ball", "center": centre, "r2": r2}]}
+    if nodes != 5:
+        spec["nodes"] = nodes
+    return spec
 
 
 def count(spec, levels=None):
@@ -94,25 +102,28 @@ def annulus(sigma, eps, level, n_u):
     return int(math.floor((r_lo * s) ** 2)), int(math.ceil((r_hi * s) ** 2))
 
 
-def c2_spec(eps, L=8, l_min=3, sigma=0.1):
-    n_u = 4 * (1 << L)
+def c2_spec(eps, L=8, l_min=3, sigma=0.1, nodes=5):
+    n_u = (nodes - 1) * (1 << L)
     crit = []
     for seed in range(4):
-        c = centre_from_seed(seed, L, -0.6, 0.6)
+        c = centre_from_seed(seed, L, -0.6, 0.6, nodes)
         rlo2, rhi2 = [-1] * L, [-1] * L
         for lev in range(l_min, L):
             a, b = annulus(sigma, eps, lev, n_u)
             rlo2[lev], rhi2[lev] = a, b
         crit.append({"kind": "annulus", "center": c, "rlo2": rlo2, "rhi2": rhi2})
-    return {"l_min": l_min, "l_max": L, "block_cap": 4, "criteria": crit}
+    spec = {"l_min": l_min, "l_max": L, "block_cap": 4, "criteria": crit}
+    if nodes != 5:
+        spec["nodes"] = nodes
+    return spec
 
 
-def calib_c2(target=200_000):
+def calib_c2(target=200_000, nodes=5):
     lo, hi = 0.002, 0.2        # larger eps -> fewer leaves
     best = None
     for _ in range(22):
         mid = math.sqrt(lo * hi)
-        spec = c2_spec(mid)
+        spec = c2_spec(mid, nodes=nodes)
         n = count(spec)
         print(f"  c2 eps={mid:.6g} leaves={n}", flush=True)
         if best is None or abs(n - target) < abs(best[0] - target):
@@ -214,6 +225,24 @@ def nl_specs():
     return out
 
 
+def n7_specs():
+    out = {}
+    L = 4
+    c = centre_from_seed(0, L, nodes=7)
+    small = ball_spec(2, L, c, [24, 10], nodes=7)
+    m = build_mesh(MeshSpec.from_dict(small))
+    assert (m.lmin, m.lmax) == (2, 4), (m.lmin, m.lmax)
+    out["wave7_small"] = {"mesh": small, "equation": "wave", "sigma": 0.1, "pulses": [c], "ko_sigma": 0.1,
+                          "tableau": "ssprk3", "n_coarse": 2, "leaves": m.n_oct}
+    print(f"  wave7_small: leaves={m.n_oct}", flush=True)
+    n2, spec2, eps = calib_c2(target=75_000, nodes=7)
+    out["wave7_c2"] = {"mesh": spec2, "equation": "wave", "sigma": 0.1,
+                       "pulses": [cc["center"] for cc in spec2["criteria"]], "eps": eps, "ko_sigma": 0.1,
+                       "tableau": "ssprk3", "n_coarse": 8, "leaves": n2}
+    print(f"  wave7_c2: leaves={n2} eps={eps}", flush=True)
+    return out
+
+
 def main():
     path = os.path.join(HERE, "specs.json")
     specs = json.load(open(path)) if os.path.exists(path) else {}
@@ -238,6 +267,8 @@ def main():
         specs["serve"] = serve_specs()
     if "--nl" in sys.argv or "nl_c1" not in specs:
         specs.update(nl_specs())
+    if "--n7" in sys.argv or "wave7_c2" not in specs:
+        specs.update(n7_specs())
     with open(path, "w") as f:
         json.dump(specs, f, indent=1)
 
