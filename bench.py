@@ -280,7 +280,7 @@ def nl_leg(P, torch, steps, warmup) -> dict:
 
 def nodes7_leg(P, torch, steps, warmup) -> dict:
     """7^3 nodes per octant with 2:1 balance and SSP-RK3 (the paper's
-    discretisation) on wave7_c2, through the phase kernels: LTS and GTS
+    discretisation) on wave7_c2, fused side-1 tiles: LTS and GTS
     throughput, the error against the analytic solution after the timed steps,
     and the rate against the algorithmic minimum of SSP-RK3 (stage s reads U and
     the K's its stage value needs and writes K_s; the last stage also writes the
@@ -293,7 +293,7 @@ def nodes7_leg(P, torch, steps, warmup) -> dict:
     U0 = wave_gaussian_torch(lv, info["L"], cfg["pulses"], sigma=cfg["sigma"], device="cuda:0", nodes=7)
     out = {"config": f"wave7_c2: 3D scalar wave, periodic [-1,1]^3, 7^3 nodes per octant, 2:1 balance, levels "
                      f"{info['lmin']}-{info['lmax']}, 4 Gaussian pulses, {info['n_oct']} octants x 343 nodes, "
-                     f"SSP-RK3, phase kernels (unzip, rhs, zip, RK update)",
+                     f"SSP-RK3, fused side-1 tiles with a 13^3-point ghost table",
            "n_octants": info["n_oct"], "nodes": 343 * info["n_oct"], "steps": steps}
     for leg in ("lts", "gts"):
         mode = P.MODE_GTS if leg == "gts" else P.MODE_LTS
@@ -563,10 +563,24 @@ def main():
     if not args.no_batch:
         from paper_2011_10570_amd import serve
         bc = config("batch")
-        batch = {}
+        # the batch launch shape, tuned on one coarse step of the same problems
+        # (every candidate's states bitwise equal); then every problem to T
+        from paper_2011_10570_amd import tune
+        from workloads import wave_gaussian_torch
+        tms, tst = [], []
+        for p in bc["problems"]:
+            m = P.Mesh(p["mesh"])
+            tms.append(m)
+            tst.append(wave_gaussian_torch(m.leaves(), m.info()["L"], [p["mesh"]["criteria"][0]["center"]],
+                                           sigma=0.1, device="cuda:0"))
+        tb = tune.tune_batch(tms, tst, tiles=(2,), threads=(256, 512), max_workgroups=(2048, 4096, 16384))
+        batch = {"tuned_shape": {"tile": tb["best"][0], "threads": tb["best"][1], "max_workgroups": tb["best"][2],
+                                 "candidates_ms": {str(k): round(v, 3) for k, v in tb["table"]}}}
+        del tms, tst
         for name, prec in (("fp64", P.FP64), ("fp32_rhs", P.FP32_RHS)):
             print(f"[bench] batch {name}: 64 problems to T...", file=sys.stderr, flush=True)
-            batch[name] = serve.batch_throughput(bc["problems"], bc["n_coarse"], precision=prec)
+            batch[name] = serve.batch_throughput(bc["problems"], bc["n_coarse"], precision=prec,
+                                                 alone=(prec == P.FP64))
             print(f"[bench] batch {name}: {batch[name]['node_updates_per_s']:.4e} node-updates/s", file=sys.stderr,
                   flush=True)
     served = None

@@ -215,8 +215,11 @@ static int equation_fields(int eq) {
 static lts_status check_combination(const Mesh& m, int eq, int prec, bool batch) {
   if (m.nodes != 5) {
     if (batch) return fail(LTS_EUNSUPPORTED, "7-node octants are not built for batched launches");
-    return fail(LTS_EUNSUPPORTED, "the fused stage kernels are built for 5-node octants (7-node octants run on "
-                                  "the phase kernels: lts_advance, lts_advance_unfused, lts_unzip/rhs/zip/rk_stage)");
+    if (eq != LTS_EQ_WAVE)
+      return fail(LTS_EUNSUPPORTED, "the fused stage for 7-node octants is built for the wave equation (other "
+                                    "equations run on the phase kernels: lts_advance, lts_advance_unfused)");
+    if (m.ts[2].count() + m.ts[4].count() > 0)
+      return fail(LTS_EUNSUPPORTED, "the fused stage for 7-node octants needs tile side 1 (lts_mesh_set_tile)");
   }
   if (!m.periodic && eq != LTS_EQ_NLWAVE)
     return fail(LTS_EUNSUPPORTED, "a bounded mesh needs the non-linear wave equation (radiative boundary)");
@@ -235,6 +238,13 @@ static lts_status check_combination(const Mesh& m, int eq, int prec, bool batch)
 using namespace lts;
 
 
+// Whether a simulation's coarse steps run on the fused stage kernels (else on the
+// phase kernels): every 5-node mesh; 7-node meshes for the wave equation on
+// side-1 tiles.
+static bool fused_path(const Mesh& m, int eq) {
+  return m.nodes == 5 || (eq == LTS_EQ_WAVE && m.ts[2].count() + m.ts[4].count() == 0);
+}
+
 static lts_status set_step(int64_t** slot, int64_t value, hipStream_t s) {
   if (!*slot) HIP_TRY(hipMalloc(slot, sizeof(int64_t)), "hipMalloc step");
   // a kernel-argument write keeps the value with the enqueued work (no sync)
@@ -251,10 +261,17 @@ struct MeshExtra {
   size_t cscr_cap = 0;
 };
 
-// Ghost-table scratch: F x 729 doubles per entry.  Grown outside graph capture
+// Half-node points of one ghost-table entry per field, GW^3 with GW = 2 ni + 1.
+static size_t ghost_points(const Mesh& m) {
+  const size_t gw = (size_t)(2 * m.ni() + 1);
+  return gw * gw * gw;
+}
+
+// Ghost-table scratch: F x GW^3 doubles per entry (GW = 2 ni + 1: 729 doubles for
+// 5-node octants, 2197 for 7-node octants).  Grown outside graph capture
 // only.
 static lts_status ensure_cscr(const Mesh& m, int F, double** p, size_t* cap) {
-  const size_t need = (m.ghosts.size() / 2) * (size_t)F * 729 * sizeof(double);
+  const size_t need = (m.ghosts.size() / 2) * (size_t)F * ghost_points(m) * sizeof(double);
   if (need <= *cap) return LTS_OK;
   if (*p) (void)hipFree(*p);
   *p = nullptr;
@@ -676,7 +693,7 @@ extern "C" lts_status lts_fused_stage_noalloc(lts_mesh* mesh, const lts_stage_vi
   sp.sigma = params->ko_sigma;
   sp.nl_coeff = params->nl_coeff;
   const int lo = lowest_active_level(m, pos->mode, pos->substep);
-  const size_t need = (size_t)m.ghost_ge[lo] * sp.F * 729 * sizeof(double);
+  const size_t need = (size_t)m.ghost_ge[lo] * sp.F * ghost_points(m) * sizeof(double);
   if (need > kNoAllocScratchBytes - kNoAllocHeader)
     return fail(LTS_EINVAL, "the stage's ghost table (" + std::to_string(need) + " B) exceeds the fixed scratch (" +
                                 std::to_string(kNoAllocScratchBytes - kNoAllocHeader) + " B)");
@@ -865,8 +882,8 @@ static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mo
   if (sim->mode >= 0 && sim->mode != mode && sim->n > 0)
     return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
   Mesh& m = sim->mesh->m;
-  // 7-node octants run on the phase kernels; 5-node octants on the fused stage
-  const bool phase = m.nodes != 5;
+  // the fused stage where it is built for the mesh and equation, else the phase kernels
+  const bool phase = !fused_path(m, sim->eq);
   if (phase) {
     lts_status st = prepare_unfused(sim);
     if (st != LTS_OK) return st;
@@ -1292,6 +1309,7 @@ int64_t rounds_left(const lts_batch* b, const lts_sim* sim) { return sim->r0 + s
 // stage parameters shared by the batch (arrays and position come from the table)
 void fill_batch_params(const lts_batch* b, int stage, StageParams& sp) {
   std::memset(&sp, 0, sizeof(sp));
+  sp.ni = 4;   // batches hold 5-node meshes only
   sp.F = b->F;
   sp.p = b->p;
   sp.stage = stage;

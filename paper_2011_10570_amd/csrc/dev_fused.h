@@ -7,15 +7,16 @@ namespace lts {
 
 // ------------------------------------------------------------------ fused stage
 // The block RHS reads only along the axes (centred first and second differences
-// and Kreiss-Oliger terms, no mixed derivatives), so of the (4tt+7)^3 padded
-// points of a tile it uses those with at most one coordinate in the 3-point halo.
+// and Kreiss-Oliger terms, no mixed derivatives), so of the (NI tt+7)^3 padded
+// points of a tile (NI node intervals per octant side: 4, or 6 for 7-node
+// octants) it uses those with at most one coordinate in the 3-point halo.
 // They are kept plane by plane: core plane z = 3 + gz (gz < G) as a P x P square
 // at gz P^2 (its four 3 x 3 corners unused), then the six halo planes (z = h for
 // h < 3, z = G + h for h >= 3) as G x G squares of the core x and y.
-template <int TT>
+template <int TT, int NI = 4>
 struct Cross {
-  static constexpr int P = 4 * TT + 7;     // padded points per axis
-  static constexpr int G = 4 * TT + 1;     // grid points per axis
+  static constexpr int P = NI * TT + 7;    // padded points per axis
+  static constexpr int G = NI * TT + 1;    // grid points per axis
   static constexpr int PP = P * P, GG = G * G;
   static constexpr int HB = G * PP;        // element of the first halo plane
   static constexpr int LS = HB + 6 * GG;   // elements per field
@@ -47,12 +48,12 @@ struct Cross {
 
 // Accessor of the plane-wise padded tile at grid point (gx, gy, gz): c is its
 // element in the core planes, hb the element of (gx, gy) in the first halo plane.
-template <typename T, int TT>
+template <typename T, int TT, int NI = 4>
 struct CrossAt {
   const T* Y;
   int c, hb, gz;
   __device__ __forceinline__ T operator()(int f, int ax, int k) const {
-    using X = Cross<TT>;
+    using X = Cross<TT, NI>;
     int e;
     if (ax == 0) {
       e = c + k;
@@ -67,19 +68,19 @@ struct CrossAt {
 };
 
 // LDS of one workgroup of the fused stage kernels.
-template <int TT, int F, bool KF32>
+template <int TT, int F, bool KF32, int NI = 4>
 struct FusedLds {
   static constexpr int W = TT + 2;
   static constexpr int NS = W * W * W;
-  static constexpr int G3 = (4 * TT + 1) * (4 * TT + 1) * (4 * TT + 1);
+  static constexpr int G3 = (NI * TT + 1) * (NI * TT + 1) * (NI * TT + 1);
   using LT = typename std::conditional<KF32, float, double>::type;
   double R[F * G3];               // stencil results
   double wsh[16];                 // stage weights of the 4 time cases
-  LT Y[F * Cross<TT>::LS];        // stage values of the used padded points
+  LT Y[F * Cross<TT, NI>::LS];    // stage values of the used padded points
   // per-tile tables, two buffers: the next tile's are filled while this one runs
   double ref[2][F];               // FP32 stencils: reference value of each field
   int32_t sl[2][2 * NS];          // slot records
-  uint8_t axl[2][3][4 * TT + 7];  // per axis: slot position | node offset << 3
+  uint8_t axl[2][3][NI * TT + 7]; // per axis: slot position | node offset << 3
 };
 
 // A tile and what it needs of its simulation and mesh.
@@ -107,9 +108,10 @@ struct TileTables {
   double refv;
 };
 
-template <int TT, int F, bool KF32, int NT>
+template <int TT, int F, bool KF32, int NT, int NI = 4>
 __device__ __forceinline__ TileTables tables_issue(const StageParams& sp, const TileRef& r, const int32_t* t) {
-  constexpr int P = 4 * TT + 7;
+  constexpr int P = NI * TT + 7;
+  constexpr int NN = (NI + 1) * (NI + 1) * (NI + 1);
   constexpr int NS2 = 2 * (TT + 2) * (TT + 2) * (TT + 2);
   static_assert(NT >= NS2 && NT >= 3 * P, "one table element per thread");
   TileTables tb{0, 0, 0.0};
@@ -118,22 +120,22 @@ __device__ __forceinline__ TileTables tables_issue(const StageParams& sp, const 
     const int d = threadIdx.x / P, q = threadIdx.x - P * d;
     const int off = t[TI_OFF];
     const int o = (off >> (8 * d)) & 255;
-    const int Q = 4 * o + q - 3;
-    const int cell = cell_of(Q, t[TI_M]);
-    tb.axv = (cell - o + 1) | ((Q - 4 * cell) << 3);
+    const int Q = NI * o + q - 3;
+    const int cell = cell_of(Q, t[TI_M], NI);
+    tb.axv = (cell - o + 1) | ((Q - NI * cell) << 3);
   }
   if (KF32 && threadIdx.x < F) {
     // FP32 stencils work on Y - ref (the Laplacian and KO ignore constants)
-    const TileCtx c = tile_ctx(t, sp.mode, r.v.j, r.v.lmin, r.v.lmax, r.n4);
-    const int64_t fsz = r.v.N * 125;
-    tb.refv = r.v.U[((int64_t)c.par_same * F + threadIdx.x) * fsz + (int64_t)t[TI_FIRST] * 125];
+    const TileCtx c = tile_ctx<NI>(t, sp.mode, r.v.j, r.v.lmin, r.v.lmax, r.n4);
+    const int64_t fsz = r.v.N * NN;
+    tb.refv = r.v.U[((int64_t)c.par_same * F + threadIdx.x) * fsz + (int64_t)t[TI_FIRST] * NN];
   }
   return tb;
 }
 
-template <int TT, int F, bool KF32>
-__device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32>& L, int b, const TileTables& tb) {
-  constexpr int P = 4 * TT + 7;
+template <int TT, int F, bool KF32, int NI>
+__device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32, NI>& L, int b, const TileTables& tb) {
+  constexpr int P = NI * TT + 7;
   constexpr int NS2 = 2 * (TT + 2) * (TT + 2) * (TT + 2);
   if (threadIdx.x < NS2) L.sl[b][threadIdx.x] = tb.slv;
   if (threadIdx.x < 3 * P) L.axl[b][threadIdx.x / P][threadIdx.x % P] = (uint8_t)tb.axv;
@@ -154,11 +156,13 @@ __device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32>& L, int b, co
 // stencils, into buffer b ^ 1.  Two barriers per tile: after the gather (the
 // previous tile's zip has read the stencil results) and after the stencils.
 // sp holds the stage (weights, masks).
-template <int TT, int F, int EQ, bool KF32, int NT, int KS>
-__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const StageParams& sp, const TileRef& cur,
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI = 4>
+__device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const StageParams& sp, const TileRef& cur,
                                            const int32_t* t, int b, const TileRef& nxt, bool more,
                                            int32_t (&ntrec)[8]) {
-  using X = Cross<TT>;
+  using X = Cross<TT, NI>;
+  constexpr int NP = NI + 1, NN = NP * NP * NP;   // nodes per octant side, per octant
+  constexpr int GW = 2 * NI + 1, GE = GW * GW * GW;  // ghost-table half-node grid of an entry
   constexpr int P = X::P;
   constexpr int LS = X::LS;
   constexpr int W = TT + 2;
@@ -174,7 +178,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   const double* ref = L.ref[b];
   auto& R = L.R;
   if (more) load_trec(nxt.tile, ntrec);
-  const int fsz = (int)(v.N * 125);          // elements per field (< 2^31)
+  const int fsz = (int)(v.N * NN);           // elements per field (< 2^31)
   const bool last = sp.stage == sp.p - 1;
   // GTS reads no stored stage of the last one (every ghost relation is the
   // same-level case, whose first stage reads U0 only): it is not stored
@@ -183,7 +187,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
   // KS: stages read by same-level sources (the tableau row's non-zero pattern),
   // a compile-time mask so the hot gather has no branches around its loads
-  const TileCtx c = tile_ctx(t, sp.mode, v.j, v.lmin, v.lmax, cur.n4);
+  const TileCtx c = tile_ctx<NI>(t, sp.mode, v.j, v.lmin, v.lmax, cur.n4);
   const int first = t[TI_FIRST];
   const double* __restrict__ Us = v.U + (int64_t)c.par_same * F * fsz;
   const double* __restrict__ Uf = v.U + (int64_t)c.par_fine * F * fsz;
@@ -193,7 +197,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
 
   // (1) stage values of the used padded points
   for (int p0 = threadIdx.x; p0 < X::NC; p0 += UB * NT) {
-    int li[UB], kind[UB], leaf[UB], kbv[UB], nuv[UB][3];
+    int li[UB], kind[UB], leaf[UB], kbv[UB], nuv[UB][3], below[UB];
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       const int pi = p0 + u * NT;
@@ -201,6 +205,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       li[u] = 0;
       leaf[u] = 0;
       kbv[u] = 0;
+      below[u] = 0;
       nuv[u][0] = nuv[u][1] = nuv[u][2] = 0;
       if (pi >= X::NC) continue;
       int qx, qy, qz;
@@ -210,6 +215,8 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
       nuv[u][0] = ax >> 3;
       nuv[u][1] = ay >> 3;
       nuv[u][2] = az >> 3;
+      // a finer slot at slot position 0 along an axis lies below the block there
+      if constexpr (NI == 6) below[u] = ((ax & 7) == 0 ? 1 : 0) | ((ay & 7) == 0 ? 2 : 0) | ((az & 7) == 0 ? 4 : 0);
       kbv[u] = sl[2 * si + 1];
       kind[u] = kbv[u] & 15;
       leaf[u] = sl[2 * si];
@@ -222,13 +229,13 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       const bool same = kind[u] == SRC_SAME, coarse = kind[u] == SRC_COARSE;
-      const uint32_t off = same ? (uint32_t)(leaf[u] * 125 + nuv[u][0] + 5 * nuv[u][1] + 25 * nuv[u][2]) : 0u;
+      const uint32_t off = same ? (uint32_t)(leaf[u] * NN + nuv[u][0] + NP * nuv[u][1] + NP * NP * nuv[u][2]) : 0u;
       // ghost-table entry (in the slot's first int), octant beta of the leaf
       const int beta = (kbv[u] >> 4) & 7;
-      const int x2 = 4 * (beta & 1) + nuv[u][0], y2 = 4 * ((beta >> 1) & 1) + nuv[u][1],
-                z2 = 4 * ((beta >> 2) & 1) + nuv[u][2];
-      const double* pa = coarse ? cs + ((int64_t)leaf[u] * F * 729 + (z2 * 9 + y2) * 9 + x2) : Us + off;
-      const int fst = coarse ? 729 : fsz;
+      const int x2 = NI * (beta & 1) + nuv[u][0], y2 = NI * ((beta >> 1) & 1) + nuv[u][1],
+                z2 = NI * ((beta >> 2) & 1) + nuv[u][2];
+      const double* pa = coarse ? cs + ((int64_t)leaf[u] * F * GE + (z2 * GW + y2) * GW + x2) : Us + off;
+      const int fst = coarse ? GE : fsz;
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         uu[u][f] = pa[(int64_t)f * fst];
@@ -240,9 +247,19 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       if (kind[u] == SRC_FINE) {
-        const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
-        const uint32_t off = (uint32_t)((leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
-                                        10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz));
+        uint32_t off;
+        if constexpr (NI == 4) {
+          const int cx = min(nuv[u][0] >> 1, 1), cy = min(nuv[u][1] >> 1, 1), cz = min(nuv[u][2] >> 1, 1);
+          off = (uint32_t)((leaf[u] + cx + 2 * cy + 4 * cz) * 125 + 2 * (nuv[u][0] - 2 * cx) +
+                           10 * (nuv[u][1] - 2 * cy) + 50 * (nuv[u][2] - 2 * cz));
+        } else {
+          // 2:1 balance: the slot names a row of the fine table
+          const int cx = fine_child6(nuv[u][0], below[u] & 1), cy = fine_child6(nuv[u][1], (below[u] >> 1) & 1),
+                    cz = fine_child6(nuv[u][2], (below[u] >> 2) & 1);
+          const int lf = sp.fine8[8 * leaf[u] + cx + 2 * cy + 4 * cz];
+          off = (uint32_t)(lf * NN + (2 * nuv[u][0] - NI * cx) + NP * (2 * nuv[u][1] - NI * cy) +
+                           NP * NP * (2 * nuv[u][2] - NI * cz));
+        }
 #pragma unroll
         for (int f = 0; f < F; ++f) {
           double acc = 0.0;
@@ -271,13 +288,13 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     }
   }
   TileTables tb{0, 0, 0.0};
-  if (more) tb = tables_issue<TT, F, KF32, NT>(sp, nxt, ntrec);
+  if (more) tb = tables_issue<TT, F, KF32, NT, NI>(sp, nxt, ntrec);
   __syncthreads();
   // the last stage's RK operands are loaded in the zip: holding them across the
   // stencils would cost the registers that 3 resident side-2 workgroups leave
-  constexpr int NN = TT * TT * TT * 125;
-  constexpr int KZ = (NN + NT - 1) / NT;
-  // (2a) stencils once per tile grid point (4tt+1)^3; results staged in LDS
+  constexpr int NT3 = TT * TT * TT * NN;     // DG nodes of the tile
+  constexpr int KZ = (NT3 + NT - 1) / NT;
+  // (2a) stencils once per tile grid point (NI tt+1)^3; results staged in LDS
   constexpr int G = X::G;
   constexpr int G3 = G * G * G;
   Geom geo{};
@@ -288,10 +305,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
     double k[F];
     if constexpr (EQ == LTS_EQ_NLWAVE) {
       const int Xp[3] = {geo.X0[0] + geo.w * gx, geo.X0[1] + geo.w * gy, geo.X0[2] + geo.w * gz};
-      rhs_nl_at(CrossAt<LT, TT>{Y, ce, X::HB + gy * G + gx, gz}, c.h, v.sigma, geo, Xp, k);
+      rhs_nl_at(CrossAt<LT, TT, NI>{Y, ce, X::HB + gy * G + gx, gz}, c.h, v.sigma, geo, Xp, k);
     } else {
       // one axis at a time: fewer live registers (same operations, same order)
-      rhs_at<LT, EQ, F, true>(CrossAt<LT, TT>{Y, ce, X::HB + gy * G + gx, gz}, (LT)c.h, (LT)v.sigma, ref, k);
+      rhs_at<LT, EQ, F, true>(CrossAt<LT, TT, NI>{Y, ce, X::HB + gy * G + gx, gz}, (LT)c.h, (LT)v.sigma, ref, k);
     }
 #pragma unroll
     for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
@@ -299,7 +316,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   if (more) tables_store(L, b ^ 1, tb);
   __syncthreads();
   // (2b) zip: every DG node of the tile's (contiguous) octants takes its grid
-  // value; node e of the tile is element first*125 + e of every field array;
+  // value; node e of the tile is element first*NN + e of every field array;
   // the last stage also forms the RK update
   double bs = sp.b[0];   // b_s without a dynamic index into the kernel arguments
 #pragma unroll
@@ -308,8 +325,8 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
 #pragma unroll
   for (int u = 0; u < KZ; ++u) {
     const int e = threadIdx.x + u * NT;
-    if (e >= NN) continue;
-    const uint32_t off = (uint32_t)(first * 125 + e);
+    if (e >= NT3) continue;
+    const uint32_t off = (uint32_t)(first * NN + e);
     double zu[F], zk[F][3];
     if (last) {
 #pragma unroll
@@ -320,9 +337,9 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
           zk[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
       }
     }
-    const int o = e / 125, node = e - 125 * (e / 125);
-    const int a = node % 5, b = (node / 5) % 5, cc = node / 25;
-    const int gi = ((4 * ((o >> 2) & 1) + cc) * G + (4 * ((o >> 1) & 1) + b)) * G + (4 * (o & 1) + a);
+    const int o = e / NN, node = e - NN * (e / NN);
+    const int a = node % NP, b = (node / NP) % NP, cc = node / (NP * NP);
+    const int gi = ((NI * ((o >> 2) & 1) + cc) * G + (NI * ((o >> 1) & 1) + b)) * G + (NI * (o & 1) + a);
 #pragma unroll
     for (int f = 0; f < F; ++f) {
       double kv = R[f * G3 + gi];
@@ -349,8 +366,8 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32>& L, const Stage
   }
 }
 
-template <int TT, int F, bool KF32>
-__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const StageParams& sp) {
+template <int TT, int F, bool KF32, int NI>
+__device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32, NI>& L, const StageParams& sp) {
   if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
 }
 
@@ -359,9 +376,9 @@ __device__ __forceinline__ void fused_init(FusedLds<TT, F, KF32>& L, const Stage
 // where a tighter budget spills: 6 (80 registers) for FP64 side-2 tiles, 8 (64)
 // with FP32 stencils, 5 for side-1 tiles, 4 for the non-linear wave; left free
 // for 6 fields.
-template <int TT, int F, bool KF32, int NT, int EQ = LTS_EQ_WAVE>
+template <int TT, int F, bool KF32, int NT, int EQ = LTS_EQ_WAVE, int NI = 4>
 constexpr int fused_waves_per_eu() {
-  const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32>);
+  const int wg = (160 * 1024) / (int)sizeof(FusedLds<TT, F, KF32, NI>);
   const int w = wg * (NT / 64) / 4;
   // the non-linear wave's boundary-aware stencils need more registers
   const int cap = EQ == LTS_EQ_NLWAVE ? 4 : (TT == 1 ? 5 : (KF32 ? 8 : 6));
@@ -370,21 +387,21 @@ constexpr int fused_waves_per_eu() {
 
 // A workgroup's walk over tiles lo, lo + step, ... < hi; ref_of(i) gives tile i.
 // The first tile's tables are loaded here, every later one's by the tile before.
-template <int TT, int F, int EQ, bool KF32, int NT, int KS, typename RefOf>
-__device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32>& L, const StageParams& sp, int lo, int step, int hi,
-                                           const RefOf& ref_of) {
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI, typename RefOf>
+__device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32, NI>& L, const StageParams& sp, int lo, int step,
+                                           int hi, const RefOf& ref_of) {
   if (lo >= hi) return;
   TileRef cur = ref_of(lo);
   int32_t trec[8];
   load_trec(cur.tile, trec);
-  tables_store(L, 0, tables_issue<TT, F, KF32, NT>(sp, cur, trec));
+  tables_store(L, 0, tables_issue<TT, F, KF32, NT, NI>(sp, cur, trec));
   __syncthreads();
   int b = 0;
   for (int ti = lo;; ti += step) {
     const bool more = ti + step < hi;
     TileRef nxt = more ? ref_of(ti + step) : cur;
     int32_t ntrec[8];
-    fused_tile<TT, F, EQ, KF32, NT, KS>(L, sp, cur, trec, b, nxt, more, ntrec);
+    fused_tile<TT, F, EQ, KF32, NT, KS, NI>(L, sp, cur, trec, b, nxt, more, ntrec);
     if (!more) break;
     cur = nxt;
 #pragma unroll
@@ -397,23 +414,23 @@ __device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32>& L, const Stage
 // The same-level stage mask and the workgroup size are template arguments: the
 // masks that occur for the built tableaus are RK4: none, {0}, {1}, {2} and
 // SSP-RK3: none, {0}, {0,1}.  A::go<...> launches the kernel of one combination.
-template <int TT, int F, int EQ, bool KF32, int NT, typename A>
+template <int TT, int F, int EQ, bool KF32, int NT, int NI, typename A>
 hipError_t dispatch_ks(const StageParams& sp, const A& a, int max_wg, hipStream_t s) {
   switch (sp.kmask[0]) {
-    case 0: return A::template go<TT, F, EQ, KF32, NT, 0>(sp, a, max_wg, s);
-    case 1: return A::template go<TT, F, EQ, KF32, NT, 1>(sp, a, max_wg, s);
-    case 2: return A::template go<TT, F, EQ, KF32, NT, 2>(sp, a, max_wg, s);
-    case 3: return A::template go<TT, F, EQ, KF32, NT, 3>(sp, a, max_wg, s);
-    case 4: return A::template go<TT, F, EQ, KF32, NT, 4>(sp, a, max_wg, s);
+    case 0: return A::template go<TT, F, EQ, KF32, NT, 0, NI>(sp, a, max_wg, s);
+    case 1: return A::template go<TT, F, EQ, KF32, NT, 1, NI>(sp, a, max_wg, s);
+    case 2: return A::template go<TT, F, EQ, KF32, NT, 2, NI>(sp, a, max_wg, s);
+    case 3: return A::template go<TT, F, EQ, KF32, NT, 3, NI>(sp, a, max_wg, s);
+    case 4: return A::template go<TT, F, EQ, KF32, NT, 4, NI>(sp, a, max_wg, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int TT, int F, int EQ, bool KF32, typename A>
+template <int TT, int F, int EQ, bool KF32, typename A, int NI = 4>
 hipError_t dispatch_nt(const StageParams& sp, const A& a, const LaunchShape& ls, hipStream_t s) {
   switch (ls.threads) {
-    case 256: return dispatch_ks<TT, F, EQ, KF32, 256>(sp, a, ls.max_wg, s);
-    case 512: return dispatch_ks<TT, F, EQ, KF32, 512>(sp, a, ls.max_wg, s);
+    case 256: return dispatch_ks<TT, F, EQ, KF32, 256, NI>(sp, a, ls.max_wg, s);
+    case 512: return dispatch_ks<TT, F, EQ, KF32, 512, NI>(sp, a, ls.max_wg, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -421,6 +438,15 @@ hipError_t dispatch_nt(const StageParams& sp, const A& a, const LaunchShape& ls,
 template <typename A>
 hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& sp, const A& a, const LaunchShape& ls,
                           hipStream_t s) {
+  if (sp.ni == 6) {   // 7-node octants: the wave equation on side-1 tiles, launches that allow it
+    if constexpr (A::kNodes7) {
+      if (eq == LTS_EQ_WAVE && tt == 1)
+        return kf32 ? dispatch_nt<1, 2, LTS_EQ_WAVE, true, A, 6>(sp, a, ls, s)
+                    : dispatch_nt<1, 2, LTS_EQ_WAVE, false, A, 6>(sp, a, ls, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (sp.ni != 4) return hipErrorInvalidValue;
   if (eq == LTS_EQ_NLWAVE) {   // FP64, tile sides 1 and 2, launches that allow it
     if constexpr (A::kNonLinear) {
       if (kf32) return hipErrorInvalidValue;

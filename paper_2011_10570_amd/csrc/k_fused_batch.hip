@@ -48,14 +48,16 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
 namespace {
 struct BatchArgs {
   static constexpr bool kNonLinear = false;   // whether the non-linear wave kernels are built for these launches
+  static constexpr bool kNodes7 = false;      // whether the 7-node-octant kernels are built for these launches
   const BatchSim* sims;
   int nsims;
   const int64_t* round;
   int64_t total;
   const double* scr;
   const int32_t* cum_tab;
-  template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+  template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI>
   static hipError_t go(const StageParams& sp, const BatchArgs& a, int max_wg, hipStream_t s) {
+    static_assert(NI == 4, "batched launches are built for 5-node octants");
     const int grid = fused_grid((int)std::min<int64_t>(a.total, 1 << 30), max_wg);
     hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims,
                        a.round, a.scr, a.cum_tab);

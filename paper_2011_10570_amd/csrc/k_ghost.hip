@@ -6,38 +6,41 @@ namespace lts {
 // Ghost-table pre-pass, before the fused launches of a stage: entry g (a leaf
 // that is a coarser source of receivers one level finer) gets its stage state
 // for those receivers (time case, buffer and dt of the receiver level, eqs.
-// fc_1/fc_2) prolongated to its 9^3 half-node grid, scr[g][f][z2][y2][x2].  The
-// prolongation is separable, x, then y, then z, each a degree-4 Lagrange sum in
+// fc_1/fc_2) prolongated to its GW^3 half-node grid (GW = 2 NI + 1: 9 for
+// 5-node octants, 13 for 7-node octants), scr[g][f][z2][y2][x2].  The
+// prolongation is separable, x, then y, then z, each a degree-NI Lagrange sum in
 // node order; the one-mesh and batched pre-passes share it, so a ghost has one
 // value whichever launch forms it.
-template <int F>
+template <int F, int NI = 4>
 struct GhostLds {
+  static constexpr int NP = NI + 1, GW = 2 * NI + 1;
   double wsh[16];
-  double lag[45];
-  double Yc[F * 125];
-  double T1[F * 225];
-  double T2[F * 405];
+  double lag[GW * NP];
+  double Yc[F * NP * NP * NP];
+  double T1[F * GW * NP * NP];
+  double T2[F * GW * GW * NP];
 };
 
 // One ghost-table entry of simulation v: leaf (coarser source), receivers of
-// level rlev; the 9^3 grid of each field to out[f][729].
-template <bool KF32, int F>
-__device__ __forceinline__ void ghost_entry(GhostLds<F>& L, const StageParams& sp, const SimView& v, int n4,
+// level rlev; the GW^3 grid of each field to out[f][GW^3].
+template <bool KF32, int F, int NI = 4>
+__device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParams& sp, const SimView& v, int n4,
                                             int leaf, int rlev, double* __restrict__ out) {
   using KT = typename std::conditional<KF32, float, double>::type;
+  constexpr int NP = NI + 1, NN = NP * NP * NP, GW = 2 * NI + 1;
   // a receiver tile of the entry's receiver level (only its level matters here)
   int32_t trec[8] = {0, 0, 0, 1, 1, 0, 0, 0};
   trec[TI_LEVEL] = rlev;
-  const TileCtx c = tile_ctx(trec, sp.mode, v.j, v.lmin, v.lmax, n4);
-  const int fsz = (int)(v.N * 125);
+  const TileCtx c = tile_ctx<NI>(trec, sp.mode, v.j, v.lmin, v.lmax, n4);
+  const int fsz = (int)(v.N * NN);
   const double* __restrict__ Uc = v.U + (int64_t)c.par_coarse * F * fsz;
   const KT* __restrict__ Kr = (const KT*)v.K;
   const int kmc = stage_mask(sp, c.case_coarse);
   const double* wc = L.wsh + 4 * c.case_coarse;
   __syncthreads();   // weights loaded; previous entry done with Yc / T1 / T2
-  for (int e = threadIdx.x; e < F * 125; e += blockDim.x) {
-    const int f = e / 125, n = e - 125 * f;
-    const uint32_t off = (uint32_t)(leaf * 125 + n);
+  for (int e = threadIdx.x; e < F * NN; e += blockDim.x) {
+    const int f = e / NN, n = e - NN * f;
+    const uint32_t off = (uint32_t)(leaf * NN + n);
     double acc = 0.0;
     #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -45,46 +48,50 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F>& L, const StageParams& s
     L.Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < F * 225; e += blockDim.x) {
-    const int kf = e / 225, r = e - 225 * kf;
-    const int x2 = r / 25, yz = r - 25 * x2;
-    const double* yc = L.Yc + kf * 125 + 5 * yz;
+  // x: T1[f][x2][z][y]
+  for (int e = threadIdx.x; e < F * GW * NP * NP; e += blockDim.x) {
+    const int kf = e / (GW * NP * NP), r = e - (GW * NP * NP) * kf;
+    const int x2 = r / (NP * NP), yz = r - (NP * NP) * x2;
+    const double* yc = L.Yc + kf * NN + NP * yz;
     double tx;
     if (x2 & 1) {
       tx = 0.0;
       #pragma unroll
-      for (int kx = 0; kx < 5; ++kx) tx = fma(L.lag[5 * x2 + kx], yc[kx], tx);
+      for (int kx = 0; kx < NP; ++kx) tx = fma(L.lag[NP * x2 + kx], yc[kx], tx);
     } else {
       tx = fma(1.0, yc[x2 >> 1], 0.0);
     }
     L.T1[e] = tx;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < F * 405; e += blockDim.x) {
-    const int kf = e / 405, r = e - 405 * kf;
-    const int x2 = r / 45, r2 = r - 45 * x2;
-    const int y2 = r2 / 5, kz = r2 - 5 * y2;
-    const double* t1 = L.T1 + kf * 225 + 25 * x2 + 5 * kz;
+  // y: T2[f][x2][y2][z]
+  for (int e = threadIdx.x; e < F * GW * GW * NP; e += blockDim.x) {
+    const int kf = e / (GW * GW * NP), r = e - (GW * GW * NP) * kf;
+    const int x2 = r / (GW * NP), r2 = r - (GW * NP) * x2;
+    const int y2 = r2 / NP, kz = r2 - NP * y2;
+    const double* t1 = L.T1 + kf * (GW * NP * NP) + (NP * NP) * x2 + NP * kz;
     double ty;
     if (y2 & 1) {
       ty = 0.0;
       #pragma unroll
-      for (int ky = 0; ky < 5; ++ky) ty = fma(L.lag[5 * y2 + ky], t1[ky], ty);
+      for (int ky = 0; ky < NP; ++ky) ty = fma(L.lag[NP * y2 + ky], t1[ky], ty);
     } else {
       ty = fma(1.0, t1[y2 >> 1], 0.0);
     }
     L.T2[e] = ty;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < F * 729; e += blockDim.x) {
-    const int f = e / 729, r = e - 729 * f;
-    const int z2 = r / 81, y2 = (r / 9) % 9, x2 = r % 9;
-    const double* t2 = L.T2 + f * 405 + 45 * x2 + 5 * y2;
+  // z: out[f][z2][y2][x2]
+  constexpr int GE = GW * GW * GW;
+  for (int e = threadIdx.x; e < F * GE; e += blockDim.x) {
+    const int f = e / GE, r = e - GE * f;
+    const int z2 = r / (GW * GW), y2 = (r / GW) % GW, x2 = r % GW;
+    const double* t2 = L.T2 + f * (GW * GW * NP) + (GW * NP) * x2 + NP * y2;
     double v2;
     if (z2 & 1) {
       v2 = 0.0;
       #pragma unroll
-      for (int kz = 0; kz < 5; ++kz) v2 = fma(L.lag[5 * z2 + kz], t2[kz], v2);
+      for (int kz = 0; kz < NP; ++kz) v2 = fma(L.lag[NP * z2 + kz], t2[kz], v2);
     } else {
       v2 = fma(1.0, t2[z2 >> 1], 0.0);
     }
@@ -92,10 +99,12 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F>& L, const StageParams& s
   }
 }
 
-template <int F>
-__device__ __forceinline__ void ghost_init(GhostLds<F>& L, const StageParams& sp) {
+template <int F, int NI = 4>
+__device__ __forceinline__ void ghost_init(GhostLds<F, NI>& L, const StageParams& sp) {
+  constexpr int NP = NI + 1, GW = 2 * NI + 1;
   if (threadIdx.x < 16) L.wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
-  if (threadIdx.x < 45) L.lag[threadIdx.x] = c_lag[threadIdx.x / 5][threadIdx.x % 5];
+  for (int i = threadIdx.x; i < GW * NP; i += blockDim.x)
+    L.lag[i] = NI == 4 ? c_lag[i / NP][i % NP] : c_lag7[i / NP][i % NP];
 }
 
 // Ghost-table pre-pass, before the fused launches of a stage: entry g (a leaf
@@ -104,15 +113,17 @@ __device__ __forceinline__ void ghost_init(GhostLds<F>& L, const StageParams& sp
 // fc_1/fc_2) prolongated to its 9^3 half-node grid, scr[g][f][z2][y2][x2].  The
 // prolongation is separable, x, then y, then z, each a degree-4 Lagrange sum in
 // node order.
-template <bool KF32, int F>
+template <bool KF32, int F, int NI>
 __global__ __launch_bounds__(256) void k_ghost_pre(StageParams sp, const int32_t* __restrict__ ghosts,
                                                    double* __restrict__ scr) {
-  __shared__ GhostLds<F> L;
+  constexpr int GW = 2 * NI + 1;
+  __shared__ GhostLds<F, NI> L;
   ghost_init(L, sp);
   const int g = blockIdx.x;
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
-  ghost_entry<KF32, F>(L, sp, v, (int)(*sp.step & 3), __builtin_amdgcn_readfirstlane(ghosts[2 * g]),
-                       __builtin_amdgcn_readfirstlane(ghosts[2 * g + 1]), scr + (int64_t)g * F * 729);
+  ghost_entry<KF32, F, NI>(L, sp, v, (int)(*sp.step & 3), __builtin_amdgcn_readfirstlane(ghosts[2 * g]),
+                           __builtin_amdgcn_readfirstlane(ghosts[2 * g + 1]),
+                           scr + (int64_t)g * F * (GW * GW * GW));
 }
 
 // The same for every simulation of a batch in round *round: the union of their
@@ -155,12 +166,19 @@ hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32
                             hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const dim3 grid((unsigned)n);
+  if (sp.ni == 6) {   // 7-node octants: the wave equation
+    if (F != 2) return hipErrorInvalidValue;
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 2, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    else hipLaunchKernelGGL((k_ghost_pre<false, 2, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    return hipGetLastError();
+  }
+  if (sp.ni != 4) return hipErrorInvalidValue;
   if (F == 2) {
-    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 2>), grid, dim3(256), 0, s, sp, ghosts, scr);
-    else hipLaunchKernelGGL((k_ghost_pre<false, 2>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 2, 4>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    else hipLaunchKernelGGL((k_ghost_pre<false, 2, 4>), grid, dim3(256), 0, s, sp, ghosts, scr);
   } else if (F == 6) {
-    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
-    else hipLaunchKernelGGL((k_ghost_pre<false, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 6, 4>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    else hipLaunchKernelGGL((k_ghost_pre<false, 6, 4>), grid, dim3(256), 0, s, sp, ghosts, scr);
   } else {
     return hipErrorInvalidValue;
   }

@@ -336,7 +336,7 @@ lts_status build_mesh(const lts_mesh_spec* spec, Mesh& m) {
   }
   st = build_block_tiles(m);
   if (st != LTS_OK) return st;
-  return build_tiles(m, 2);
+  return build_tiles(m, m.nodes == 5 ? 2 : 1);   // 7-node octants: side-1 tiles
 }
 
 namespace {

@@ -259,20 +259,26 @@ def requests_from_config(n: Optional[int] = None, rate: Optional[float] = None) 
 
 
 def batch_throughput(problems: list, n_coarse: int = 1, precision: int = FP64, device: str = "cuda",
-                     mode: int = MODE_LTS) -> dict:
+                     mode: int = MODE_LTS, alone: bool = False) -> dict:
     """Wave problems advanced together in one batch from a Gaussian pulse: raw
-    node-updates per second over the wall time until all reach T (setup excluded)."""
+    node-updates per second over the wall time until all reach T (setup excluded).
+    With alone, the same problems are also advanced one after another, each with
+    its own graph-captured lts_advance (one untimed coarse step captures the
+    graph; the timed n_coarse steps follow it), and the two rates are compared."""
     import torch
     from workloads import wave_gaussian_torch
-    sims = []
+    meshes, states, sims = [], [], []
     work = 0
     for p in problems:
         m = Mesh(p["mesh"])
-        s = Sim(m, "wave", precision, "rk4", ko_sigma=0.1, device=device)
         c = p["mesh"]["criteria"][0]["center"]
-        s.set_state(wave_gaussian_torch(m.leaves(), m.info()["L"], [c], sigma=0.1, device=device))
+        U0 = wave_gaussian_torch(m.leaves(), m.info()["L"], [c], sigma=0.1, device=device)
+        s = Sim(m, "wave", precision, "rk4", ko_sigma=0.1, device=device)
+        s.set_state(U0)
         info = m.info()
         work += info["node_updates_lts" if mode == MODE_LTS else "node_updates_gts"] * n_coarse
+        meshes.append(m)
+        states.append(U0)
         sims.append(s)
     b = Batch("wave", precision, "rk4", mode, capacity=max(1, len(sims)))
     torch.cuda.synchronize()
@@ -282,7 +288,25 @@ def batch_throughput(problems: list, n_coarse: int = 1, precision: int = FP64, d
     b.drain()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
-    return {"problems": len(sims), "node_updates": work, "wall_s": wall, "node_updates_per_s": work / wall}
+    out = {"problems": len(sims), "node_updates": work, "wall_s": wall, "node_updates_per_s": work / wall}
+    del b, sims
+    if alone:
+        solo = []
+        for m, U0 in zip(meshes, states):
+            s = Sim(m, "wave", precision, "rk4", ko_sigma=0.1, device=device)
+            s.set_state(U0)
+            s.advance(1, mode, graph=True)       # captures the coarse-step graph (untimed);
+            solo.append(s)                       # every coarse step does the same work
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s in solo:
+            s.advance(n_coarse, mode, graph=True)
+        torch.cuda.synchronize()
+        wall1 = time.perf_counter() - t
+        out["alone_wall_s"] = wall1
+        out["alone_node_updates_per_s"] = work / wall1
+        out["batch_over_alone"] = wall1 / wall
+    return out
 
 
 def run_config(capacity: Optional[float] = None, n: Optional[int] = None, budget: Optional[int] = None,

@@ -1,8 +1,9 @@
-"""GPU parity of the 7^3-node path (the paper's octants, 2:1 balance; phase kernels
-templated on the node count) with the oracle, through the C ABI: unzip at
-positioned LTS/GTS states, block RHS, zip, RK update, whole runs with classic RK4
-and SSP-RK3, the graph-captured lts_advance against the eager phase calls,
-FP32 stencils, norms, checkpoint/restore, and the refusals."""
+"""GPU parity of the 7^3-node path (the paper's octants, 2:1 balance; phase and
+fused kernels templated on the node count) with the oracle, through the C ABI:
+unzip at positioned LTS/GTS states, block RHS, zip, RK update, the fused stage
+(side-1 tiles, ghost table of 13^3 points), whole runs with classic RK4 and
+SSP-RK3, the graph-captured fused lts_advance against the eager phase calls
+(bitwise), FP32 stencils, norms, checkpoint/restore, and the refusals."""
 import numpy as np
 import pytest
 import torch
@@ -114,6 +115,50 @@ def test_rk_update7(mesh7, mode, n, j):
     assert rel_err(U.cpu().numpy().reshape(2, 2, -1), st.U.reshape(2, 2, -1)) < TOL
 
 
+@pytest.mark.parametrize("mode,n,j", [("lts", 0, 0), ("lts", 0, 1), ("lts", 1, 2), ("lts", 1, 3), ("gts", 1, 1)])
+@pytest.mark.parametrize("stage", [0, 1, 2, 3])
+def test_fused_stage7(mesh7, mode, n, j, stage):
+    """One fused launch (ghost pre-pass + side-1 tiles) == oracle unzip + rhs +
+    zip (+ the RK update at the last stage)."""
+    om, gm = mesh7
+    assert gm.info()["tile"] == 1
+    print(f"[fused7] {mode} n={n} j={j} s={stage}", flush=True)
+    st, act = _positioned(om, 2, mode, n, j, seed=100 + 10 * j + stage)
+    U, K = _dev(st.U), _dev(st.K)
+    k_in = K.clone()
+    md = P.MODE_GTS if mode == "gts" else P.MODE_LTS
+    P.fused_stage(gm, U, K, P.EQ_WAVE, 0.1, stage, j, md, n)
+    st.stage(act, stage, fd.rhs_wave, 0.1)
+    if stage == 3:
+        st.rk_update(act)
+    if mode == "gts" and stage == 3:
+        assert torch.equal(K.reshape(4, -1)[stage], k_in.reshape(4, -1)[stage])
+    else:
+        assert rel_err(K.cpu().numpy().reshape(4, 2, -1)[stage], st.K[stage].reshape(2, -1)) < TOL
+    assert rel_err(U.cpu().numpy().reshape(2, 2, -1).transpose(1, 0, 2),
+                   st.U.reshape(2, 2, -1).transpose(1, 0, 2)) < TOL
+
+
+@pytest.mark.parametrize("threads,cap", [(256, 16), (512, 65536)])
+def test_fused_walk7(mesh7, threads, cap):
+    """Workgroups walking many tiles (small grid cap) equal one workgroup per
+    tile, bitwise, for the 7-node tiles."""
+    om, gm = mesh7
+    old = P.get_launch()
+    try:
+        outs = []
+        for shape in ((512, 65536, 512), (threads, cap, 512)):
+            P.set_launch(*shape)
+            st, act = _positioned(om, 2, "lts", 1, 0, seed=5)
+            U, K = _dev(st.U), _dev(st.K)
+            for stage in range(4):
+                P.fused_stage(gm, U, K, P.EQ_WAVE, 0.1, stage, 0, P.MODE_LTS, 1)
+            outs.append((U, K))
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    finally:
+        P.set_launch(*old)
+
+
 @pytest.fixture(scope="module")
 def initial7(mesh7):
     om, _ = mesh7
@@ -124,8 +169,8 @@ def initial7(mesh7):
 @pytest.mark.parametrize("mode,tableau", [("lts", "ssprk3"), ("gts", "ssprk3"), ("lts", "rk4")])
 def test_run_matches_oracle7(mesh7, initial7, mode, tableau):
     """Two coarse steps (levels 2-4: 4 substeps each) of the configuration, graph-
-    captured lts_advance against the oracle; the eager phase calls give the same
-    state bitwise (the same kernels)."""
+    captured lts_advance (fused side-1 tiles) against the oracle; the eager phase
+    calls give the same state bitwise (same values, same operation order)."""
     om, gm = mesh7
     cfg = config(NAME)
     n = cfg["n_coarse"]
@@ -184,14 +229,23 @@ def test_norms7(mesh7):
 
 
 def test_refusals7(mesh7):
-    """The fused stage, batches, the non-linear wave and remeshing refuse 7-node
-    meshes with LTS_EUNSUPPORTED."""
+    """The fused stage for Maxwell or on side-2 tiles, batches, the non-linear
+    wave and remeshing refuse 7-node meshes with LTS_EUNSUPPORTED."""
     om, gm = mesh7
     U = torch.zeros((2, 2, om.n_oct, 343), dtype=torch.float64, device=DEV)
     K = torch.zeros((4, 2, om.n_oct, 343), dtype=torch.float64, device=DEV)
+    Um = torch.zeros((2, 6, om.n_oct, 343), dtype=torch.float64, device=DEV)
+    Km = torch.zeros((4, 6, om.n_oct, 343), dtype=torch.float64, device=DEV)
     with pytest.raises(P.LTSError) as e:
-        P.fused_stage(gm, U, K, P.EQ_WAVE, 0.1, 0, 0, P.MODE_LTS, 0)
+        P.fused_stage(gm, Um, Km, P.EQ_MAXWELL, 0.1, 0, 0, P.MODE_LTS, 0)
     assert e.value.status == P._L.EUNSUPPORTED
+    gm.set_tile(2)
+    try:
+        with pytest.raises(P.LTSError) as e:
+            P.fused_stage(gm, U, K, P.EQ_WAVE, 0.1, 0, 0, P.MODE_LTS, 0)
+        assert e.value.status == P._L.EUNSUPPORTED
+    finally:
+        gm.set_tile(1)
     s = P.Sim(gm, "wave", P.FP64, "rk4", device=DEV)
     s.set_state(np.zeros((2, om.n_oct, 343)))
     b = P.Batch("wave", P.FP64, "rk4", P.MODE_LTS, capacity=2)
