@@ -155,8 +155,16 @@ __device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32, NI>& L, int b
 // With a next tile, its record is loaded at the start and its tables during the
 // stencils, into buffer b ^ 1.  Two barriers per tile: after the gather (the
 // previous tile's zip has read the stencil results) and after the stencils.
-// sp holds the stage (weights, masks).
-template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI = 4>
+// sp holds the stage (weights, masks).  ZM, the zip mode, is fixed per launch:
+// bit 0 = the last stage (RK update), bit 1 = store K_s (all but the last stage
+// of GTS), bit 2 = count non-finite updates; as template bits the zip carries no
+// run-time branch for them.
+template <int ZM>
+struct ZipMode {
+  static constexpr bool last = (ZM & 1) != 0, storek = (ZM & 2) != 0, check = (ZM & 4) != 0;
+};
+
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI = 4, int ZM = 2>
 __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const StageParams& sp, const TileRef& cur,
                                            const int32_t* t, int b, const TileRef& nxt, bool more,
                                            int32_t (&ntrec)[8]) {
@@ -179,10 +187,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
   auto& R = L.R;
   if (more) load_trec(nxt.tile, ntrec);
   const int fsz = (int)(v.N * NN);           // elements per field (< 2^31)
-  const bool last = sp.stage == sp.p - 1;
+  constexpr bool last = ZipMode<ZM>::last;
   // GTS reads no stored stage of the last one (every ghost relation is the
   // same-level case, whose first stage reads U0 only): it is not stored
-  const bool storek = !(last && sp.mode == LTS_MODE_GTS);
+  constexpr bool storek = ZipMode<ZM>::storek;
   const KT* __restrict__ Kr = (const KT*)v.K;
   KT* __restrict__ Kw = (KT*)v.Kw + (int64_t)sp.stage * F * fsz;
   // KS: stages read by same-level sources (the tableau row's non-zero pattern),
@@ -280,7 +288,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
       } else if (kind[u] == SRC_COARSE) {
 #pragma unroll
         for (int f = 0; f < F; ++f) Y[f * LS + li[u]] = (LT)(uu[u][f] - ref[f]);
-      } else if (kind[u] == SRC_NONE) {
+      } else if (EQ == LTS_EQ_NLWAVE && kind[u] == SRC_NONE) {   // only bounded meshes have them
         // beyond the outer faces: never read by the bounded-domain stencils
 #pragma unroll
         for (int f = 0; f < F; ++f) Y[f * LS + li[u]] = (LT)0;
@@ -328,7 +336,7 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
     if (e >= NT3) continue;
     const uint32_t off = (uint32_t)(first * NN + e);
     double zu[F], zk[F][3];
-    if (last) {
+    if constexpr (last) {
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         zu[f] = ld32(Us + (uint32_t)(f * fsz), off);
@@ -345,12 +353,12 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
       double kv = R[f * G3 + gi];
       if constexpr (KF32) {
         const float kf = (float)kv;
-        if (storek) st32(Kw + (uint32_t)(f * fsz), off, kf);
+        if constexpr (storek) st32(Kw + (uint32_t)(f * fsz), off, kf);
         kv = (double)kf;
       } else {
-        if (storek) st32(Kw + (uint32_t)(f * fsz), off, kv);
+        if constexpr (storek) st32(Kw + (uint32_t)(f * fsz), off, kv);
       }
-      if (last) {
+      if constexpr (last) {
         // compute_step_partial: U_new = U0 + dt (b_0 K_0 + ... + b_s K_s),
         // s = p - 1, accumulated in stage order, into the other buffer
         double acc = 0.0;
@@ -360,7 +368,9 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
         acc = fma(bs, kv, acc);
         const double un = zu[f] + c.dt * acc;
         st32(Uw1 + (uint32_t)(f * fsz), off, un);
-        if (sp.nonfinite && !isfinite(un)) atomicAdd(sp.nonfinite, 1u);
+        if constexpr (ZipMode<ZM>::check) {
+          if (!isfinite(un)) atomicAdd(sp.nonfinite, 1u);
+        }
       }
     }
   }
@@ -387,7 +397,7 @@ constexpr int fused_waves_per_eu() {
 
 // A workgroup's walk over tiles lo, lo + step, ... < hi; ref_of(i) gives tile i.
 // The first tile's tables are loaded here, every later one's by the tile before.
-template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI, typename RefOf>
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI, int ZM, typename RefOf>
 __device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32, NI>& L, const StageParams& sp, int lo, int step,
                                            int hi, const RefOf& ref_of) {
   if (lo >= hi) return;
@@ -401,7 +411,7 @@ __device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32, NI>& L, const S
     const bool more = ti + step < hi;
     TileRef nxt = more ? ref_of(ti + step) : cur;
     int32_t ntrec[8];
-    fused_tile<TT, F, EQ, KF32, NT, KS, NI>(L, sp, cur, trec, b, nxt, more, ntrec);
+    fused_tile<TT, F, EQ, KF32, NT, KS, NI, ZM>(L, sp, cur, trec, b, nxt, more, ntrec);
     if (!more) break;
     cur = nxt;
 #pragma unroll
@@ -411,17 +421,35 @@ __device__ __forceinline__ void fused_walk(FusedLds<TT, F, KF32, NI>& L, const S
 }
 
 
-// The same-level stage mask and the workgroup size are template arguments: the
-// masks that occur for the built tableaus are RK4: none, {0}, {1}, {2} and
-// SSP-RK3: none, {0}, {0,1}.  A::go<...> launches the kernel of one combination.
+// The same-level stage mask, the zip mode and the workgroup size are template
+// arguments: the masks that occur for the built tableaus are RK4: none, {0},
+// {1} for the first three stages and {2} for the last, SSP-RK3: none, {0} and
+// {0,1} for the last; only the last stages (masks {2} and {0,1}) take the RK
+// update, and only they have zip modes other than "store K".  A::go<...>
+// launches the kernel of one combination.
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI, typename A>
+hipError_t dispatch_zm(int zm, const StageParams& sp, const A& a, int max_wg, hipStream_t s) {
+  switch (zm) {
+    case 1: return A::template go<TT, F, EQ, KF32, NT, KS, NI, 1>(sp, a, max_wg, s);
+    case 3: return A::template go<TT, F, EQ, KF32, NT, KS, NI, 3>(sp, a, max_wg, s);
+    case 5: return A::template go<TT, F, EQ, KF32, NT, KS, NI, 5>(sp, a, max_wg, s);
+    case 7: return A::template go<TT, F, EQ, KF32, NT, KS, NI, 7>(sp, a, max_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int TT, int F, int EQ, bool KF32, int NT, int NI, typename A>
 hipError_t dispatch_ks(const StageParams& sp, const A& a, int max_wg, hipStream_t s) {
-  switch (sp.kmask[0]) {
-    case 0: return A::template go<TT, F, EQ, KF32, NT, 0, NI>(sp, a, max_wg, s);
-    case 1: return A::template go<TT, F, EQ, KF32, NT, 1, NI>(sp, a, max_wg, s);
-    case 2: return A::template go<TT, F, EQ, KF32, NT, 2, NI>(sp, a, max_wg, s);
-    case 3: return A::template go<TT, F, EQ, KF32, NT, 3, NI>(sp, a, max_wg, s);
-    case 4: return A::template go<TT, F, EQ, KF32, NT, 4, NI>(sp, a, max_wg, s);
+  const bool last = sp.stage == sp.p - 1;
+  const int zm = last ? (1 | (sp.mode == LTS_MODE_GTS ? 0 : 2) | (sp.nonfinite ? 4 : 0)) : 2;
+  const int ks = sp.kmask[0];
+  if (last != (ks == 3 || ks == 4)) return hipErrorInvalidValue;
+  switch (ks) {
+    case 0: return A::template go<TT, F, EQ, KF32, NT, 0, NI, 2>(sp, a, max_wg, s);
+    case 1: return A::template go<TT, F, EQ, KF32, NT, 1, NI, 2>(sp, a, max_wg, s);
+    case 2: return A::template go<TT, F, EQ, KF32, NT, 2, NI, 2>(sp, a, max_wg, s);
+    case 3: return dispatch_zm<TT, F, EQ, KF32, NT, 3, NI>(zm, sp, a, max_wg, s);
+    case 4: return dispatch_zm<TT, F, EQ, KF32, NT, 4, NI>(zm, sp, a, max_wg, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -9,7 +9,7 @@ namespace lts {
 // contiguous (Morton-ordered, cost-balanced) range of tiles.  Coarser ghosts come
 // prolongated from the ghost-table pre-pass (scr).  NI: node intervals per octant
 // side (4, or 6 for 7-node octants).
-template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI>
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI, int ZM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT, EQ, NI>())))
 void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* __restrict__ slots,
              const double* __restrict__ scr, XcdRanges xr) {
@@ -22,7 +22,7 @@ void k_fused(StageParams sp, const int32_t* __restrict__ tiles, const int32_t* _
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
   int lo, hi;
   xcd_range(xr, xcd, lo, hi);
-  fused_walk<TT, F, EQ, KF32, NT, KS, NI>(L, sp, lo + sid, nslot, hi, [&](int ti) {
+  fused_walk<TT, F, EQ, KF32, NT, KS, NI, ZM>(L, sp, lo + sid, nslot, hi, [&](int ti) {
     return TileRef{v, n4, tiles + 8 * (int64_t)ti, slots, scr};
   });
 }
@@ -35,9 +35,9 @@ struct OneArgs {
   const int32_t* slots;
   const double* scr;
   XcdRanges xr;
-  template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI>
+  template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI, int ZM>
   static hipError_t go(const StageParams& sp, const OneArgs& a, int max_wg, hipStream_t s) {
-    hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32, NT, KS, NI>), dim3(fused_grid(a.xr.b[8], max_wg)), dim3(NT), 0, s, sp,
+    hipLaunchKernelGGL((k_fused<TT, F, EQ, KF32, NT, KS, NI, ZM>), dim3(fused_grid(a.xr.b[8], max_wg)), dim3(NT), 0, s, sp,
                        a.tiles, a.slots, a.scr, a.xr);
     return hipGetLastError();
   }

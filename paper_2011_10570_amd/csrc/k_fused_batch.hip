@@ -11,7 +11,7 @@ namespace lts {
 // holds it; the union is cut into 8 contiguous ranges, one per XCD.  The
 // arithmetic of every tile is that of the one-mesh kernel; coarser ghosts come
 // from the batch's ghost pre-pass (scr, simulation s at entry gbase_s).
-template <int TT, int F, int EQ, bool KF32, int NT, int KS>
+template <int TT, int F, int EQ, bool KF32, int NT, int KS, int ZM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<TT, F, KF32, NT, EQ>())))
 void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims, const int64_t* __restrict__ round,
                    const double* __restrict__ scr, const int32_t* __restrict__ cum_tab) {
@@ -27,7 +27,7 @@ void k_fused_batch(StageParams sp0, const BatchSim* __restrict__ sims, int nsims
   const int xcd = blockIdx.x & 7;
   const int sid = blockIdx.x >> 3;
   const int lo = (int)((int64_t)total * xcd / 8), hi = (int)((int64_t)total * (xcd + 1) / 8);
-  fused_walk<TT, F, EQ, KF32, NT, KS>(L, sp0, lo + sid, nslot, hi, [&](int ti) {
+  fused_walk<TT, F, EQ, KF32, NT, KS, 4, ZM>(L, sp0, lo + sid, nslot, hi, [&](int ti) {
     int a = 0, z = nsims - 1;   // the simulation s with cum[s] <= ti < cum[s+1]
     while (a < z) {
       const int mid = (a + z + 1) >> 1;
@@ -55,11 +55,11 @@ struct BatchArgs {
   int64_t total;
   const double* scr;
   const int32_t* cum_tab;
-  template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI>
+  template <int TT, int F, int EQ, bool KF32, int NT, int KS, int NI, int ZM>
   static hipError_t go(const StageParams& sp, const BatchArgs& a, int max_wg, hipStream_t s) {
     static_assert(NI == 4, "batched launches are built for 5-node octants");
     const int grid = fused_grid((int)std::min<int64_t>(a.total, 1 << 30), max_wg);
-    hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims,
+    hipLaunchKernelGGL((k_fused_batch<TT, F, EQ, KF32, NT, KS, ZM>), dim3(grid), dim3(NT), 0, s, sp, a.sims, a.nsims,
                        a.round, a.scr, a.cum_tab);
     return hipGetLastError();
   }
