@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--no-maxwell", action="store_true", help="skip the Maxwell leg")
     ap.add_argument("--no-nl", action="store_true", help="skip the non-linear wave leg")
     ap.add_argument("--no-n7", action="store_true", help="skip the 7^3-node leg")
+    ap.add_argument("--unfused", action="store_true", help="also time one coarse step of the phase-by-phase path")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only time a copy of this many MiB")
     return ap.parse_args()
 
@@ -231,6 +232,27 @@ def time_leg(P, gm, U0, mode, prec, steps, warmup, torch, equation="wave"):
     ev = e0.elapsed_time(e1) / 1e3
     del sim
     return wall, ev
+
+
+def unfused_leg(P, torch, gm, U0) -> dict:
+    """One LTS coarse step of the phase-by-phase path (unzip, rhs and zip per
+    stage through HBM, then the RK update; the structure of the paper's
+    per-phase bars), event-timed after one warm-up step, beside the fused
+    stage's step.  The split between the phases is in the kernel trace of the
+    same path (profiles/)."""
+    sim = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=0.1, device="cuda:0")
+    sim.set_state(U0)
+    stream = torch.cuda.current_stream()
+    sim.advance_unfused(1, P.MODE_LTS, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.advance_unfused(1, P.MODE_LTS, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del sim
+    return {"ms_per_step": ms, "rate": gm.info()["node_updates_lts"] / (ms / 1e3)}
 
 
 def nl_leg(P, torch, steps, warmup) -> dict:
@@ -547,6 +569,11 @@ def main():
         print(f"[bench] maxwell: {rate:.4e} node-updates/s, frac {a_m / HBM_PEAK_GBS:.3f}", file=sys.stderr,
               flush=True)
 
+    unf = None
+    if args.unfused and "lts" in legs:
+        unf = unfused_leg(P, torch, gm, U0)
+        print(f"[bench] unfused: {unf['ms_per_step']:.1f} ms per coarse step", file=sys.stderr, flush=True)
+
     nl = None
     if not args.no_nl and "lts" in legs:
         nl = nl_leg(P, torch, max(1, min(args.steps, 8)), args.warmup)
@@ -661,6 +688,8 @@ def main():
         out["gts_roofline"] = gts_roof
     if maxwell:
         out["maxwell"] = maxwell
+    if unf:
+        out["unfused"] = unf
     if nl:
         out["nlwave"] = nl
     if n7:
