@@ -62,6 +62,9 @@ static lts_status upload_fused_sets(Mesh& m) {
     if ((st = upload_set(m.ts[k])) != LTS_OK) return st;
   if (m.d_ghosts) (void)hipFree(m.d_ghosts);
   m.d_ghosts = nullptr;
+  if (m.d_ghost_of_leaf) (void)hipFree(m.d_ghost_of_leaf);
+  m.d_ghost_of_leaf = nullptr;
+  if ((st = upload_vec(m.ghost_of_leaf, &m.d_ghost_of_leaf, "upload ghost entries of leaves")) != LTS_OK) return st;
   return upload_vec(m.ghosts, &m.d_ghosts, "upload ghost table");
 }
 
@@ -345,6 +348,7 @@ void lts_mesh_destroy(lts_mesh* mesh) {
   free_set(h->m.bt);
   for (int k : {1, 2, 4}) free_set(h->m.ts[k]);
   if (h->m.d_ghosts) (void)hipFree(h->m.d_ghosts);
+  if (h->m.d_ghost_of_leaf) (void)hipFree(h->m.d_ghost_of_leaf);
   if (h->m.d_leafxyz) (void)hipFree(h->m.d_leafxyz);
   if (h->m.d_fine8) (void)hipFree(h->m.d_fine8);
   if (h->x.d_cscr) (void)hipFree(h->x.d_cscr);
@@ -498,8 +502,17 @@ lts_status lts_unzip(lts_mesh* mesh, const lts_stage_view* view, int32_t stage, 
   if ((st = fill_params(m, view, stage, pos, h->x.d_step, sp)) != LTS_OK) return st;
   ListDev L;
   if ((st = stage_list(m, blocks, nb, pos, s, L)) != LTS_OK) return st;
+  // coarser ghosts come prolongated from the ghost table: the entries of every
+  // receiver level the call can touch (the lowest level of its blocks up)
+  int lo = m.lmax;
+  if (blocks) {
+    for (int i = 0; i < nb; ++i) lo = std::min(lo, (int)m.blocks[blocks[i]].level);
+  } else {
+    lo = lowest_active_level(m, pos->mode, pos->substep);
+  }
+  if ((st = ensure_cscr(m, sp.F, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
   HIP_TRY(launch_unzip(view->precision == LTS_FP32_RHS, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb,
-                       L.ptotal, padded, s),
+                       L.ptotal, padded, m.d_ghosts, m.ghost_ge[lo], h->x.d_cscr, m.d_ghost_of_leaf, s),
           "unzip launch");
   return LTS_OK;
 }
@@ -980,7 +993,8 @@ static lts_status prepare_unfused(lts_sim* sim) {
     HIP_TRY(hipMalloc(&sim->d_coef, 4 * sizeof(double)), "hipMalloc coef");
     HIP_TRY(hipMemcpy(sim->d_coef, sim->b, sim->p * sizeof(double), hipMemcpyHostToDevice), "upload b");
   }
-  return LTS_OK;
+  // the ghost table the unzip reads its coarser ghosts from
+  return ensure_cscr(m, sim->F, &sim->d_cscr, &sim->cscr_cap);
 }
 
 // One coarse step through the phase kernels (unzip, rhs, zip per stage, then the
@@ -994,11 +1008,13 @@ static lts_status enqueue_unfused_step(lts_sim* sim, int32_t mode, hipStream_t s
     int cls;
     if (mode == LTS_MODE_GTS) cls = m.lmax - m.lmin + 1;
     else cls = m.lmax - lowest_active_level(m, mode, j);
+    const int lo = lowest_active_level(m, mode, j);
     const ListDev& L = sim->ulists[cls];
     for (int st = 0; st < sim->p; ++st) {
       StageParams sp;
       fill_sim_params(sim, st, mode, j, sp);
-      HIP_TRY(launch_unzip(kf32, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb, L.ptotal, sim->d_pad, s),
+      HIP_TRY(launch_unzip(kf32, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb, L.ptotal, sim->d_pad,
+                           m.d_ghosts, m.ghost_ge[lo], sim->d_cscr, m.d_ghost_of_leaf, s),
               "unzip launch");
       HIP_TRY(launch_rhs(sim->eq, kf32, m.bt.d_tiles, L.list, L.poff, L.ptotal, L.goff, L.gtotal, L.nb, sim->d_pad,
                          sim->d_kb, sim->prm.ko_sigma, sp, s),

@@ -7,10 +7,15 @@
 namespace lts {
 
 // ------------------------------------------------------------------ standalone kernels
-template <bool KF32, int F, int NI>
+// TAB: coarser ghosts read from the ghost table scr (entry of a leaf: gid[leaf],
+// filled by the ghost pre-pass of the same stage) instead of interpolated here
+// from the coarser leaf's stage values; both give bitwise the same value.
+template <bool KF32, int F, int NI, bool TAB>
 __global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __restrict__ tiles,
                                                const int32_t* __restrict__ slots, const int32_t* __restrict__ list,
-                                               const int64_t* __restrict__ off, int64_t total, double* out) {
+                                               const int64_t* __restrict__ off, int64_t total, double* out,
+                                               const double* __restrict__ scr, const int32_t* __restrict__ gid) {
+  constexpr int GW = 2 * NI + 1, GE = GW * GW * GW;
   __shared__ double wsh[16];
   if (threadIdx.x < 16) wsh[threadIdx.x] = stage_weight(sp, threadIdx.x);
   __syncthreads();
@@ -25,7 +30,21 @@ __global__ __launch_bounds__(256) void k_unzip(StageParams sp, const int32_t* __
   for (int pi = blockIdx.x * blockDim.x + threadIdx.x; pi < P3; pi += gridDim.x * blockDim.x) {
     const int qx = pi % P, qy = (pi / P) % P, qz = pi / (P * P);
     double v[F];
-    point_values<KF32, F, NI>(sp, c, sl, wsh, qx, qy, qz, v);
+    bool done = false;
+    if constexpr (TAB) {
+      const Loc Lc = locate(qx, qy, qz, c.ox, c.oy, c.oz, c.tt, c.m, NI);
+      const int kb = sl[2 * Lc.slot + 1];
+      if ((kb & 15) == SRC_COARSE) {
+        const int beta = (kb >> 4) & 7;
+        const int g = gid[sl[2 * Lc.slot]];
+        const int x2 = NI * (beta & 1) + Lc.nu[0], y2 = NI * ((beta >> 1) & 1) + Lc.nu[1],
+                  z2 = NI * ((beta >> 2) & 1) + Lc.nu[2];
+        #pragma unroll
+        for (int f = 0; f < F; ++f) v[f] = scr[((int64_t)g * F + f) * GE + (z2 * GW + y2) * GW + x2];
+        done = true;
+      }
+    }
+    if (!done) point_values<KF32, F, NI>(sp, c, sl, wsh, qx, qy, qz, v);
     #pragma unroll
     for (int f = 0; f < F; ++f) out[f * total + off[bi] + pi] = v[f];
   }
@@ -370,25 +389,40 @@ hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NI>
+template <int NI, bool TAB>
 static void unzip_ni(bool kf32, const StageParams& sp, dim3 grid, const int32_t* tiles, const int32_t* slots,
-                     const int32_t* list, const int64_t* off, int64_t total, double* out, hipStream_t s) {
+                     const int32_t* list, const int64_t* off, int64_t total, double* out, const double* scr,
+                     const int32_t* gid, hipStream_t s) {
   if (sp.F == 2) {
-    if (kf32) hipLaunchKernelGGL((k_unzip<true, 2, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
-    else hipLaunchKernelGGL((k_unzip<false, 2, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 2, NI, TAB>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total,
+                                 out, scr, gid);
+    else hipLaunchKernelGGL((k_unzip<false, 2, NI, TAB>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total,
+                            out, scr, gid);
   } else {
-    if (kf32) hipLaunchKernelGGL((k_unzip<true, 6, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
-    else hipLaunchKernelGGL((k_unzip<false, 6, NI>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total, out);
+    if (kf32) hipLaunchKernelGGL((k_unzip<true, 6, NI, TAB>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total,
+                                 out, scr, gid);
+    else hipLaunchKernelGGL((k_unzip<false, 6, NI, TAB>), grid, dim3(256), 0, s, sp, tiles, slots, list, off, total,
+                            out, scr, gid);
   }
 }
 
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
-                        const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s) {
+                        const int32_t* list, const int64_t* off, int nb, int64_t total, double* out,
+                        const int32_t* ghosts, int64_t nghost, double* scr, const int32_t* gid, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   if ((sp.F != 2 && sp.F != 6) || (sp.ni != 4 && sp.ni != 6)) return hipErrorInvalidValue;
+  // the ghost table is built for every 5-node case and for two fields of 7-node
+  // octants (six fields of 13^3 points would exceed a workgroup's LDS)
+  const bool tab = sp.ni == 4 || sp.F == 2;
+  if (tab && nghost > 0) {
+    if (!scr || !gid || !ghosts) return hipErrorInvalidValue;
+    hipError_t e = launch_ghost_pre(sp.F, kf32, sp, ghosts, nghost, scr, s);
+    if (e != hipSuccess) return e;
+  }
   dim3 grid(8, nb);
-  if (sp.ni == 4) unzip_ni<4>(kf32, sp, grid, tiles, slots, list, off, total, out, s);
-  else unzip_ni<6>(kf32, sp, grid, tiles, slots, list, off, total, out, s);
+  if (sp.ni == 4) unzip_ni<4, true>(kf32, sp, grid, tiles, slots, list, off, total, out, scr, gid, s);
+  else if (tab) unzip_ni<6, true>(kf32, sp, grid, tiles, slots, list, off, total, out, scr, gid, s);
+  else unzip_ni<6, false>(kf32, sp, grid, tiles, slots, list, off, total, out, scr, gid, s);
   return hipGetLastError();
 }
 

@@ -57,7 +57,9 @@ struct Mesh {
   // to scratch g; a tile's list of distinct coarser leaves holds (leaf, g).
   std::vector<int32_t> ghosts;        // [E][2] = leaf, receiver level
   std::vector<int64_t> ghost_ge;
+  std::vector<int32_t> ghost_of_leaf; // [N]: the leaf's ghost-table entry, -1 if none
   int32_t* d_ghosts = nullptr;
+  int32_t* d_ghost_of_leaf = nullptr;
   int32_t* d_leafxyz = nullptr;      // [N][4] leaf anchors and levels (positions of the non-linear wave)
   TileSet bt;                         // one tile per block (standalone kernels)
   bool uploaded = false;

@@ -111,8 +111,11 @@ hipError_t launch_ghost_pre_batch(int F, bool kf32, const StageParams& sp0, cons
 hipError_t launch_stream(int eq, bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
                          const double* scr, const XcdRanges& xr, const LaunchShape& ls, hipStream_t s);
 hipError_t launch_set_i64(int64_t* ptr, int64_t value, hipStream_t s);
+// The phase unzip; coarser ghosts come from the ghost table that the launch
+// first fills (ghosts[0..nghost) into scr, entry of a leaf: gid[leaf]).
 hipError_t launch_unzip(bool kf32, const StageParams& sp, const int32_t* tiles, const int32_t* slots,
-                        const int32_t* list, const int64_t* off, int nb, int64_t total, double* out, hipStream_t s);
+                        const int32_t* list, const int64_t* off, int nb, int64_t total, double* out,
+                        const int32_t* ghosts, int64_t nghost, double* scr, const int32_t* gid, hipStream_t s);
 hipError_t launch_rhs(int eq, bool f32, const int32_t* tiles, const int32_t* list, const int64_t* poff,
                       int64_t ptotal, const int64_t* goff, int64_t gtotal, int nb, const double* padded, void* kout,
                       double sigma, const StageParams& geo, hipStream_t s);

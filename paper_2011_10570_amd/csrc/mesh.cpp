@@ -541,6 +541,7 @@ static void build_ghosts(Mesh& m) {
     m.ghosts.push_back(leaves[g]);
     m.ghosts.push_back(m.lev[leaves[g]] + 1);
   }
+  m.ghost_of_leaf = gid;
   m.ghost_ge.assign(LTS_MAX_LEVEL + 1, 0);
   for (int l = 0; l <= LTS_MAX_LEVEL; ++l) {
     int64_t c = 0;
