@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--no-nl", action="store_true", help="skip the non-linear wave leg")
     ap.add_argument("--no-n7", action="store_true", help="skip the 7^3-node leg")
     ap.add_argument("--unfused", action="store_true", help="also time one coarse step of the phase-by-phase path")
+    ap.add_argument("--jsonl", default="", help="also append the result line to this JSONL file")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="only time a copy of this many MiB")
     return ap.parse_args()
 
@@ -670,6 +671,7 @@ def main():
                                f"{info['n_oct']} octants x 125 nodes, RK4, 6th-order FD + KO, LTS, "
                                f"dt_l = 0.25 h_l; step = one coarsest step ({info['n_substeps']} substeps)",
                    "n_octants": info["n_oct"], "nodes": 125 * info["n_oct"],
+                   "level_count": {str(l): int(c) for l, c in enumerate(info["level_count"]) if c},
                    "node_updates_per_step_lts": w_lts, "node_updates_per_step_gts": w_gts,
                    "tile": info["tile"]},
         "roofline": roof,
@@ -703,7 +705,11 @@ def main():
         out["p99_time_to_t_s"] = served["p99_time_to_t_s"]
     if tuned:
         out["tuned"] = {"best": tuned["best"], "ms": tuned["ms"]}
-    print(json.dumps(out))
+    line = json.dumps(out)
+    print(line)
+    if args.jsonl:
+        with open(args.jsonl, "a") as f:
+            f.write(line + "\n")
 
 
 if __name__ == "__main__":

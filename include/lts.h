@@ -293,9 +293,15 @@ lts_status lts_sim_bind(lts_sim* sim, void* U, void* K);
 /* Flags of lts_advance. */
 enum {
   LTS_ADVANCE_GRAPH = 1,         /* capture one coarse step in a hipGraph on first use, replay it */
-  LTS_ADVANCE_CHECK_FINITE = 2   /* count non-finite values written by the RK updates of these
+  LTS_ADVANCE_CHECK_FINITE = 2,  /* count non-finite values written by the RK updates of these
                                     steps (inside the last stage's kernels), synchronise the
                                     stream at the end and return LTS_ENONFINITE if any */
+  LTS_ADVANCE_POISON = 4         /* race check (debug): before every stage, set the stage's K
+                                    entries of the stage's active octants to NaN.  A stage that
+                                    read its own K before writing it (or any K that no stage of
+                                    the step has written yet) would carry NaN into the state,
+                                    which LTS_ADVANCE_CHECK_FINITE reports.  Results are
+                                    otherwise unchanged; GTS leaves the unstored last K NaN */
 };
 /* Advance n coarse steps (T += n dt_lmin) with the fused kernels (Alg. 1 / Alg. 2);
  * a mesh of 7-node octants runs the same schedule on the phase kernels (unzip,

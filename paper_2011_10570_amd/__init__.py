@@ -357,10 +357,14 @@ class Sim:
         self.U[0].copy_(t.reshape(self.F, self.N, self.nn).to(self.U.device))
         check(lib().lts_sim_bind(self.h, _ptr(self.U), _ptr(self.K)), "lts_sim_bind")
 
-    def advance(self, n_coarse: int, mode: int = MODE_LTS, graph: bool = True, stream=None, check_finite=False):
+    def advance(self, n_coarse: int, mode: int = MODE_LTS, graph: bool = True, stream=None, check_finite=False,
+                poison: bool = False):
         """n coarse steps; with check_finite the call synchronises and raises
-        LTSError (status LTS_ENONFINITE) if an RK update wrote a NaN or Inf."""
-        flags = (_L.ADVANCE_GRAPH if graph else 0) | (_L.ADVANCE_CHECK_FINITE if check_finite else 0)
+        LTSError (status LTS_ENONFINITE) if an RK update wrote a NaN or Inf.
+        poison (race check, debug): every stage's K entries of its active octants
+        are set to NaN before the stage runs."""
+        flags = ((_L.ADVANCE_GRAPH if graph else 0) | (_L.ADVANCE_CHECK_FINITE if check_finite else 0) |
+                 (_L.ADVANCE_POISON if poison else 0))
         check(lib().lts_advance(self.h, int(n_coarse), int(mode), flags, _stream_ptr(stream)), "lts_advance")
         self._mode = int(mode)
 

@@ -18,7 +18,7 @@ CRIT_BALL, CRIT_ANNULUS = 0, 1
 MODE_LTS, MODE_GTS = 0, 1
 EQ_WAVE, EQ_MAXWELL, EQ_NLWAVE = 0, 1, 2
 BOUNDARY_PERIODIC, BOUNDARY_OUTER = 0, 1
-ADVANCE_GRAPH, ADVANCE_CHECK_FINITE = 1, 2
+ADVANCE_GRAPH, ADVANCE_CHECK_FINITE, ADVANCE_POISON = 1, 2, 4
 FP64, FP32_RHS = 0, 1
 RK4, SSPRK3 = 0, 1
 EXPORT_LEAVES, EXPORT_BLOCKS, EXPORT_UNZIP_MAP, EXPORT_SCHEDULE, EXPORT_TILES = range(5)

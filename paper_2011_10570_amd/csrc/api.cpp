@@ -732,6 +732,8 @@ struct lts_sim {
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   int64_t graph_tables[2] = {0, 0};  // mesh table generation of each captured graph
   int64_t graph_gen[2] = {0, 0};   // launch-shape generation of each captured graph
+  bool poison = false;             // LTS_ADVANCE_POISON: K_s set to NaN before each stage
+  bool graph_poison[2] = {false, false};
   // unfused path: device block lists per substep class
   std::vector<ListDev> ulists;
   std::vector<void*> ualloc;
@@ -782,6 +784,13 @@ void fill_sim_params(const lts_sim* sim, int stage, int mode, int j, StageParams
 }
 
 
+// The stage-s slice of the sim's K array ([F][N][n^3] of doubles or floats).
+static void* stage_slice(const lts_sim* sim, int s) {
+  const Mesh& m = sim->mesh->m;
+  const size_t kb = sim->prec == LTS_FP32_RHS ? 4 : 8;
+  return (char*)sim->K + (size_t)s * sim->F * m.n() * m.nn() * kb;
+}
+
 lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
   Mesh& m = sim->mesh->m;
   const int nsub = 1 << (m.lmax - m.lmin);
@@ -790,6 +799,15 @@ lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
     for (int st = 0; st < sim->p; ++st) {
       StageParams sp;
       fill_sim_params(sim, st, mode, j, sp);
+      if (sim->poison) {
+        for (int k : {1, 2, 4}) {
+          const TileSet& ts = m.ts[k];
+          if (ts.count() == 0 || ts.n_ge[lo] == 0) continue;
+          HIP_TRY(launch_poison(ts.d_tiles, nullptr, (int)ts.n_ge[lo], stage_slice(sim, st), sim->prec == LTS_FP32_RHS,
+                                sim->F, m.n(), (int)m.nn(), s),
+                  "poison launch");
+        }
+      }
       lts_status r = launch_stage(m, sim->eq, sim->prec == LTS_FP32_RHS, sp, lo, sim->d_cscr, g_shape, s);
       if (r != LTS_OK) return r;
     }
@@ -874,7 +892,9 @@ static lts_status enqueue_unfused_step(lts_sim* sim, int32_t mode, hipStream_t s
 lts_status lts_advance(lts_sim* sim, int64_t n_coarse_steps, int32_t mode, int32_t flags, void* stream) {
   clear_error();
   if (!sim || !sim->U) return fail(LTS_EINVAL, "sim not bound");
-  if (flags & ~(LTS_ADVANCE_GRAPH | LTS_ADVANCE_CHECK_FINITE)) return fail(LTS_EINVAL, "unknown advance flags");
+  if (flags & ~(LTS_ADVANCE_GRAPH | LTS_ADVANCE_CHECK_FINITE | LTS_ADVANCE_POISON))
+    return fail(LTS_EINVAL, "unknown advance flags");
+  sim->poison = (flags & LTS_ADVANCE_POISON) != 0;
   hipStream_t s = (hipStream_t)stream;
   const bool check = (flags & LTS_ADVANCE_CHECK_FINITE) != 0;
   if (check) HIP_TRY(launch_set_u32(sim->d_nonfinite, 0u, s), "reset finiteness counter");
@@ -918,7 +938,8 @@ static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mo
     }
     return LTS_OK;
   }
-  if (sim->exec[mode] && (sim->graph_tables[mode] != m.tables_gen || sim->graph_gen[mode] != g_shape_gen)) {
+  if (sim->exec[mode] && (sim->graph_tables[mode] != m.tables_gen || sim->graph_gen[mode] != g_shape_gen ||
+                          sim->graph_poison[mode] != sim->poison)) {
     drop_graphs(sim);
   }
   if (!sim->exec[mode]) {
@@ -935,6 +956,7 @@ static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mo
     HIP_TRY(hipGraphInstantiate(&sim->exec[mode], g, nullptr, nullptr, 0), "graph instantiate");
     sim->graph_tables[mode] = m.tables_gen;
     sim->graph_gen[mode] = g_shape_gen;
+    sim->graph_poison[mode] = sim->poison;
   }
   for (int64_t c = 0; c < n_coarse_steps; ++c) {
     HIP_TRY(hipGraphLaunch(sim->exec[mode], s), "graph launch");
@@ -1013,6 +1035,9 @@ static lts_status enqueue_unfused_step(lts_sim* sim, int32_t mode, hipStream_t s
     for (int st = 0; st < sim->p; ++st) {
       StageParams sp;
       fill_sim_params(sim, st, mode, j, sp);
+      if (sim->poison)
+        HIP_TRY(launch_poison(m.bt.d_tiles, L.list, L.nb, stage_slice(sim, st), kf32, sim->F, m.n(), (int)m.nn(), s),
+                "poison launch");
       HIP_TRY(launch_unzip(kf32, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb, L.ptotal, sim->d_pad,
                            m.d_ghosts, m.ghost_ge[lo], sim->d_cscr, m.d_ghost_of_leaf, s),
               "unzip launch");
@@ -1042,6 +1067,7 @@ lts_status lts_advance_unfused(lts_sim* sim, int64_t n_coarse_steps, int32_t mod
   lts_status st = prepare_unfused(sim);
   if (st != LTS_OK) return st;
   sim->mode = mode;
+  sim->poison = false;
   for (int64_t c = 0; c < n_coarse_steps; ++c) {
     if ((st = enqueue_unfused_step(sim, mode, s)) != LTS_OK) return st;
     sim->n += 1;

@@ -331,6 +331,26 @@ __global__ __launch_bounds__(128) void k_transfer(const double* __restrict__ st_
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_poison(const int32_t* __restrict__ tiles, const int32_t* __restrict__ list,
+                                                T* Ks, int F, int64_t N, int nn) {
+  const int i = blockIdx.x;
+  const int32_t* t = tiles + 8 * (int64_t)(list ? list[i] : i);
+  const int first = t[TI_FIRST], tt = t[TI_TT];
+  const int cnt = tt * tt * tt * nn;
+  const T nan = (T)__builtin_nan("");
+  for (int f = 0; f < F; ++f)
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) Ks[((int64_t)f * N + first) * nn + e] = nan;
+}
+
+hipError_t launch_poison(const int32_t* tiles, const int32_t* list, int n, void* Ks, bool kf32, int F, int64_t N,
+                         int nn, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (kf32) hipLaunchKernelGGL((k_poison<float>), dim3(n), dim3(256), 0, s, tiles, list, (float*)Ks, F, N, nn);
+  else hipLaunchKernelGGL((k_poison<double>), dim3(n), dim3(256), 0, s, tiles, list, (double*)Ks, F, N, nn);
+  return hipGetLastError();
+}
+
 __global__ void k_set_u32(unsigned int* p, unsigned int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }

@@ -127,6 +127,10 @@ hipError_t launch_current(const StageParams& sp, const int32_t* tiles, int nbloc
 // Inverse of launch_current: the state of every octant into the U buffer each
 // block reads at the coarse step *sp.step.
 hipError_t launch_restore(const StageParams& sp, const int32_t* tiles, int nblocks, const double* in, hipStream_t s);
+// Race check (debug): NaN into the K slice Ks ([F][N][nn]) over the octants of
+// tiles list[0..n) (or tiles 0..n-1 when list is null).
+hipError_t launch_poison(const int32_t* tiles, const int32_t* list, int n, void* Ks, bool kf32, int F, int64_t N,
+                         int nn, hipStream_t s);
 hipError_t launch_set_u32(unsigned int* ptr, unsigned int value, hipStream_t s);
 // Remeshing: wavelet indicators of every leaf and of the parents of the families
 // fam[0..nfam) (first leaf of 8 siblings); intergrid transfer by records

@@ -7,7 +7,8 @@ import torch
 import paper_2011_10570_amd as P
 from oracle import octree as ot
 from oracle import solver as so
-from workloads import config, mesh_spec, wave_gaussian, wave_plane, maxwell_gaussian, random_dg
+from workloads import (config, consistent_random_dg, mesh_spec, wave_gaussian, wave_plane, maxwell_gaussian,
+                       random_dg)
 
 from gpu_common import TOL, oracle_c1_at_T, oracle_mesh, rel_err
 
@@ -291,3 +292,29 @@ def test_checkpoint_resume_bitwise(c1, tmp_path, mode):
     sim.advance(2, mode)
     assert sim.coarse_step == 4
     assert np.array_equal(sim.current().cpu().numpy(), a)
+
+
+@pytest.mark.parametrize("name,mode,eq", [("wave_c1", P.MODE_LTS, "wave"), ("wave_c1", P.MODE_GTS, "wave"),
+                                          ("wave7_small", P.MODE_LTS, "wave"), ("wave7_small", P.MODE_GTS, "maxwell")])
+def test_poison_race_check(name, mode, eq):
+    """Race check: with every stage's K entries of its active octants set to NaN
+    before the stage, two coarse steps report no non-finite update and give
+    bitwise the state of the plain run, so no stage reads a K it has not yet
+    written (fused tiles; Maxwell on 7-node octants takes the phase kernels).
+    In GTS on the fused tiles the unstored last K stays NaN: the poison covered
+    every octant and nothing read it."""
+    gm = P.build_mesh(mesh_spec(name))
+    info = gm.info()
+    lv = gm.leaves()
+    n = info["nodes"]
+    F = 2 if eq == "wave" else 6
+    U0 = consistent_random_dg(lv[:, :3], lv[:, 3], info["L"], F, seed=3, nodes=n)
+    outs = []
+    for poison in (False, True):
+        s = P.Sim(gm, eq, P.FP64, "rk4", ko_sigma=0.1, device=DEV)
+        s.set_state(U0)
+        s.advance(2, mode, graph=True, check_finite=True, poison=poison)
+        outs.append((s.current(), s.K.clone()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    if mode == P.MODE_GTS and eq == "wave":
+        assert torch.isnan(outs[1][1][3]).all() and not torch.isnan(outs[1][1][:3]).any()
