@@ -86,7 +86,11 @@ enum {
   LTS_EXPORT_BLOCKS = 1,     /* [B][6]  first leaf, m, level, anchor x, y, z                  */
   LTS_EXPORT_UNZIP_MAP = 2,  /* [sum_b S_b^3][5] source leaf, kind, 2*px, 2*py, 2*pz            */
   LTS_EXPORT_SCHEDULE = 3,   /* for j = 0..2^dL-1: count, then that many block indices         */
-  LTS_EXPORT_TILES = 4       /* [T][8] tiles of the fused kernel (see lts_mesh_set_tile)       */
+  LTS_EXPORT_TILES = 4,      /* [T][8] tiles of the fused kernel (see lts_mesh_set_tile)       */
+  LTS_EXPORT_GHOSTS = 5      /* [E][2] ghost table: coarser source leaf, then its receivers'
+                              * level (bits 0-4) | the half-node box they read, 4 bits per
+                              * bound from bit 5: x lo, x hi, y lo, y hi, z lo, z hi
+                              * (0..2(n-1) for n nodes per side); finest receivers first   */
 };
 
 /* Unzip-map source kinds (Sec. 3.3): own octant, same-level neighbour, finer

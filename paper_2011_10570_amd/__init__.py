@@ -145,6 +145,17 @@ class Mesh:
     def tiles(self) -> np.ndarray:
         return self.export(_L.EXPORT_TILES).reshape(-1, 8)
 
+    def ghosts(self) -> np.ndarray:
+        """Ghost table [E][8]: coarser source leaf, receiver level, read box
+        (x lo, x hi, y lo, y hi, z lo, z hi on the source's half-node grid)."""
+        raw = self.export(_L.EXPORT_GHOSTS).reshape(-1, 2)
+        out = np.empty((len(raw), 8), np.int64)
+        out[:, 0] = raw[:, 0]
+        out[:, 1] = raw[:, 1] & 31
+        for k in range(6):
+            out[:, 2 + k] = (raw[:, 1] >> (5 + 4 * k)) & 15
+        return out
+
     def set_tile(self, t: int):
         check(lib().lts_mesh_set_tile(self.h, int(t)), "lts_mesh_set_tile")
 

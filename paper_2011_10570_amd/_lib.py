@@ -21,7 +21,7 @@ BOUNDARY_PERIODIC, BOUNDARY_OUTER = 0, 1
 ADVANCE_GRAPH, ADVANCE_CHECK_FINITE, ADVANCE_POISON = 1, 2, 4
 FP64, FP32_RHS = 0, 1
 RK4, SSPRK3 = 0, 1
-EXPORT_LEAVES, EXPORT_BLOCKS, EXPORT_UNZIP_MAP, EXPORT_SCHEDULE, EXPORT_TILES = range(5)
+EXPORT_LEAVES, EXPORT_BLOCKS, EXPORT_UNZIP_MAP, EXPORT_SCHEDULE, EXPORT_TILES, EXPORT_GHOSTS = range(6)
 
 STATUS_NAMES = {0: "LTS_OK", 1: "LTS_EINVAL", 2: "LTS_ENOMEM", 3: "LTS_EDEVICE", 4: "LTS_EUNBALANCED",
                 5: "LTS_ENONFINITE", 6: "LTS_EUNSUPPORTED"}

@@ -454,6 +454,9 @@ lts_status lts_mesh_export(const lts_mesh* mesh, int32_t kind, void* buf, size_t
     case LTS_EXPORT_TILES:
       for (int k : {1, 2, 4}) out.insert(out.end(), m.ts[k].tiles.begin(), m.ts[k].tiles.end());
       break;
+    case LTS_EXPORT_GHOSTS:
+      out = m.ghosts;
+      break;
     default:
       return fail(LTS_EINVAL, "unknown export kind");
   }

@@ -21,13 +21,28 @@ struct GhostLds {
   double T2[F * GW * GW * NP];
 };
 
-// One ghost-table entry of simulation v: leaf (coarser source), receivers of
-// level rlev; the GW^3 grid of each field to out[f][GW^3].
+// e / d for 0 <= e < 2^20 and d >= 1, from a float estimate (off by at most one
+// at these sizes) and one correction each way; r = 1 / d.
+__device__ __forceinline__ int small_div(int e, int d, float r) {
+  int q = (int)((float)e * r);
+  q += (q + 1) * d <= e ? 1 : 0;
+  q -= q * d > e ? 1 : 0;
+  return q;
+}
+
+// One ghost-table entry of simulation v: leaf (coarser source), rec = receiver
+// level (bits 0-4) and the half-node box that the receivers read (4 bits per
+// bound from bit 5: x lo, x hi, y lo, y hi, z lo, z hi); the box of the GW^3
+// grid of each field to out[f][GW^3].  Points outside the box are not written
+// (no tile reads them); inside it every value is the full prolongation's.
 template <bool KF32, int F, int NI = 4>
 __device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParams& sp, const SimView& v, int n4,
-                                            int leaf, int rlev, double* __restrict__ out) {
+                                            int leaf, int rec, double* __restrict__ out) {
   using KT = typename std::conditional<KF32, float, double>::type;
   constexpr int NP = NI + 1, NN = NP * NP * NP, GW = 2 * NI + 1;
+  const int rlev = rec & 31;
+  const int xlo = (rec >> 5) & 15, ylo = (rec >> 13) & 15, zlo = (rec >> 21) & 15;
+  const int bx = ((rec >> 9) & 15) - xlo + 1, by = ((rec >> 17) & 15) - ylo + 1, bz = ((rec >> 25) & 15) - zlo + 1;
   // a receiver tile of the entry's receiver level (only its level matters here)
   int32_t trec[8] = {0, 0, 0, 1, 1, 0, 0, 0};
   trec[TI_LEVEL] = rlev;
@@ -48,10 +63,12 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParam
     L.Yc[e] = ld32(Uc + (uint32_t)(f * fsz), off) + c.dt * acc;
   }
   __syncthreads();
-  // x: T1[f][x2][z][y]
-  for (int e = threadIdx.x; e < F * GW * NP * NP; e += blockDim.x) {
-    const int kf = e / (GW * NP * NP), r = e - (GW * NP * NP) * kf;
-    const int x2 = r / (NP * NP), yz = r - (NP * NP) * x2;
+  // x: T1[f][x2][z][y], x2 in the box
+  const int n1 = bx * NP * NP;
+  const float r1 = 1.0f / (float)n1;
+  for (int e = threadIdx.x; e < F * n1; e += blockDim.x) {
+    const int kf = small_div(e, n1, r1), r = e - n1 * kf;
+    const int x2 = xlo + r / (NP * NP), yz = r % (NP * NP);
     const double* yc = L.Yc + kf * NN + NP * yz;
     double tx;
     if (x2 & 1) {
@@ -61,14 +78,16 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParam
     } else {
       tx = fma(1.0, yc[x2 >> 1], 0.0);
     }
-    L.T1[e] = tx;
+    L.T1[kf * (GW * NP * NP) + (NP * NP) * x2 + yz] = tx;
   }
   __syncthreads();
-  // y: T2[f][x2][y2][z]
-  for (int e = threadIdx.x; e < F * GW * GW * NP; e += blockDim.x) {
-    const int kf = e / (GW * GW * NP), r = e - (GW * GW * NP) * kf;
-    const int x2 = r / (GW * NP), r2 = r - (GW * NP) * x2;
-    const int y2 = r2 / NP, kz = r2 - NP * y2;
+  // y: T2[f][x2][y2][z], (x2, y2) in the box
+  const int n2 = by * NP, n2f = bx * n2;
+  const float r2 = 1.0f / (float)n2, r2f = 1.0f / (float)n2f;
+  for (int e = threadIdx.x; e < F * n2f; e += blockDim.x) {
+    const int kf = small_div(e, n2f, r2f), ra = e - n2f * kf;
+    const int xi = small_div(ra, n2, r2), rb = ra - n2 * xi;
+    const int x2 = xlo + xi, y2 = ylo + rb / NP, kz = rb % NP;
     const double* t1 = L.T1 + kf * (GW * NP * NP) + (NP * NP) * x2 + NP * kz;
     double ty;
     if (y2 & 1) {
@@ -78,14 +97,18 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParam
     } else {
       ty = fma(1.0, t1[y2 >> 1], 0.0);
     }
-    L.T2[e] = ty;
+    L.T2[kf * (GW * GW * NP) + (GW * NP) * x2 + NP * y2 + kz] = ty;
   }
   __syncthreads();
-  // z: out[f][z2][y2][x2]
+  // z: out[f][z2][y2][x2], the box
   constexpr int GE = GW * GW * GW;
-  for (int e = threadIdx.x; e < F * GE; e += blockDim.x) {
-    const int f = e / GE, r = e - GE * f;
-    const int z2 = r / (GW * GW), y2 = (r / GW) % GW, x2 = r % GW;
+  const int nxy = bx * by, n3 = nxy * bz;
+  const float rx = 1.0f / (float)bx, rxy = 1.0f / (float)nxy, r3 = 1.0f / (float)n3;
+  for (int e = threadIdx.x; e < F * n3; e += blockDim.x) {
+    const int f = small_div(e, n3, r3), ra = e - n3 * f;
+    const int zi = small_div(ra, nxy, rxy), rb = ra - nxy * zi;
+    const int yi = small_div(rb, bx, rx), xi = rb - bx * yi;
+    const int x2 = xlo + xi, y2 = ylo + yi, z2 = zlo + zi;
     const double* t2 = L.T2 + f * (GW * GW * NP) + (GW * NP) * x2 + NP * y2;
     double v2;
     if (z2 & 1) {
@@ -95,7 +118,7 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParam
     } else {
       v2 = fma(1.0, t2[z2 >> 1], 0.0);
     }
-    out[e] = v2;
+    out[f * GE + (z2 * GW + y2) * GW + x2] = v2;
   }
 }
 
@@ -107,14 +130,9 @@ __device__ __forceinline__ void ghost_init(GhostLds<F, NI>& L, const StageParams
     L.lag[i] = NI == 4 ? c_lag[i / NP][i % NP] : c_lag7[i / NP][i % NP];
 }
 
-// Ghost-table pre-pass, before the fused launches of a stage: entry g (a leaf
-// that is a coarser source of receivers one level finer) gets its stage state
-// for those receivers (time case, buffer and dt of the receiver level, eqs.
-// fc_1/fc_2) prolongated to its 9^3 half-node grid, scr[g][f][z2][y2][x2].  The
-// prolongation is separable, x, then y, then z, each a degree-4 Lagrange sum in
-// node order.
+// One workgroup per ghost-table entry (see ghost_entry).
 template <bool KF32, int F, int NI>
-__global__ __launch_bounds__(256) void k_ghost_pre(StageParams sp, const int32_t* __restrict__ ghosts,
+__global__ __launch_bounds__(NI == 6 ? 512 : 256) void k_ghost_pre(StageParams sp, const int32_t* __restrict__ ghosts,
                                                    double* __restrict__ scr) {
   constexpr int GW = 2 * NI + 1;
   __shared__ GhostLds<F, NI> L;
@@ -168,8 +186,10 @@ hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32
   const dim3 grid((unsigned)n);
   if (sp.ni == 6) {   // 7-node octants: the wave equation
     if (F != 2) return hipErrorInvalidValue;
-    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 2, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
-    else hipLaunchKernelGGL((k_ghost_pre<false, 2, 6>), grid, dim3(256), 0, s, sp, ghosts, scr);
+    // 512 threads for the 13^3-point entries (measured 4.5 % faster on the
+    // 7-node step than 256)
+    if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 2, 6>), grid, dim3(512), 0, s, sp, ghosts, scr);
+    else hipLaunchKernelGGL((k_ghost_pre<false, 2, 6>), grid, dim3(512), 0, s, sp, ghosts, scr);
     return hipGetLastError();
   }
   if (sp.ni != 4) return hipErrorInvalidValue;

@@ -55,7 +55,7 @@ struct Mesh {
   // (finest first); ghost_ge[l] = entries with receiver level >= l.  The
   // prolongation pre-pass writes entry g's stage state on its 9^3 half-node grid
   // to scratch g; a tile's list of distinct coarser leaves holds (leaf, g).
-  std::vector<int32_t> ghosts;        // [E][2] = leaf, receiver level
+  std::vector<int32_t> ghosts;        // [E][2] = leaf, receiver level | read box << 5
   std::vector<int64_t> ghost_ge;
   std::vector<int32_t> ghost_of_leaf; // [N]: the leaf's ghost-table entry, -1 if none
   int32_t* d_ghosts = nullptr;

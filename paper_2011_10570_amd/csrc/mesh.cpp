@@ -535,17 +535,65 @@ static void build_ghosts(Mesh& m) {
   }
   // receiver level = coarser leaf level + 1; finest receivers first, then leaf order
   std::stable_sort(leaves.begin(), leaves.end(), [&](int32_t a, int32_t b) { return m.lev[a] > m.lev[b]; });
+  for (size_t g = 0; g < leaves.size(); ++g) gid[leaves[g]] = (int32_t)g;
+  // Half-node box of every entry that its receivers read: the union, over the
+  // coarser cells of every block's padding, of (ni beta + nu) per axis with nu
+  // over the padded points in the cell (every tiling's coarser reads lie in its
+  // block's padding).  The pre-pass prolongates only inside the box.
+  const int ni = m.ni(), gw = 2 * ni + 1;
+  std::vector<int32_t> box(6 * leaves.size());
+  for (size_t g = 0; g < leaves.size(); ++g)
+    for (int d = 0; d < 3; ++d) {
+      box[6 * g + 2 * d] = gw;
+      box[6 * g + 2 * d + 1] = -1;
+    }
+  for (size_t b = 0; b < m.blocks.size(); ++b) {
+    const int32_t* t = &m.bt.tiles[8 * b];
+    const int mm = t[TI_M], w = mm + 2;
+    // per receiver cell c (block-relative, -1..m) the range of nu of its padded points
+    std::vector<int> nlo(w, 1 << 20), nhi(w, -1);
+    for (int Q = -3; Q <= ni * mm + 3; ++Q) {
+      const int c = cell_of(Q, mm, ni);
+      nlo[c + 1] = std::min(nlo[c + 1], Q - ni * c);
+      nhi[c + 1] = std::max(nhi[c + 1], Q - ni * c);
+    }
+    const int32_t* sl = &m.bt.slots[2 * (size_t)t[TI_SLOT]];
+    for (int sz = 0; sz < w; ++sz)
+      for (int sy = 0; sy < w; ++sy)
+        for (int sx = 0; sx < w; ++sx) {
+          const int si = sx + w * (sy + w * sz);
+          const int kb = sl[2 * si + 1];
+          if ((kb & 15) != SRC_COARSE) continue;
+          const int g = gid[sl[2 * si]];
+          const int beta = (kb >> 4) & 7;
+          const int s3[3] = {sx, sy, sz};
+          for (int d = 0; d < 3; ++d) {
+            const int o = ni * ((beta >> d) & 1);
+            box[6 * g + 2 * d] = std::min(box[6 * g + 2 * d], o + nlo[s3[d]]);
+            box[6 * g + 2 * d + 1] = std::max(box[6 * g + 2 * d + 1], o + nhi[s3[d]]);
+          }
+        }
+  }
   m.ghosts.clear();
   for (size_t g = 0; g < leaves.size(); ++g) {
-    gid[leaves[g]] = (int32_t)g;
     m.ghosts.push_back(leaves[g]);
-    m.ghosts.push_back(m.lev[leaves[g]] + 1);
+    // receiver level (5 bits) | box (4 bits per bound: x lo, x hi, y lo, y hi, z lo, z hi)
+    int32_t rec = m.lev[leaves[g]] + 1;
+    for (int d = 0; d < 3; ++d) {
+      int lo = box[6 * g + 2 * d], hi = box[6 * g + 2 * d + 1];
+      if (hi < lo) {   // no block reads the entry (not expected): the whole grid
+        lo = 0;
+        hi = gw - 1;
+      }
+      rec |= (lo << (5 + 8 * d)) | (hi << (9 + 8 * d));
+    }
+    m.ghosts.push_back(rec);
   }
   m.ghost_of_leaf = gid;
   m.ghost_ge.assign(LTS_MAX_LEVEL + 1, 0);
   for (int l = 0; l <= LTS_MAX_LEVEL; ++l) {
     int64_t c = 0;
-    for (size_t g = 0; g < leaves.size(); ++g) c += m.ghosts[2 * g + 1] >= l ? 1 : 0;
+    for (size_t g = 0; g < leaves.size(); ++g) c += (m.ghosts[2 * g + 1] & 31) >= l ? 1 : 0;
     m.ghost_ge[l] = c;
   }
   for (int k : {1, 2, 4}) {

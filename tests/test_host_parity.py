@@ -74,6 +74,30 @@ def test_unzip_map_bit_exact(name):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("name", ["small", "nl_small", "wave7_small"])
+def test_ghost_table_read_boxes(name):
+    """The ghost table holds exactly the coarser sources of the oracle's unzip
+    map, receiver level = source level + 1 (finest receivers first), and each
+    entry's box is the tight bounding box of the half-node points read from it."""
+    om = _oracle_mesh(name)
+    gm = P.build_mesh(mesh_spec(name))
+    want = np.concatenate([ot.unzip_map(om, b) for b in range(len(om.blocks))])
+    co = want[want[:, 1] == ot.KIND_COARSE]
+    g = gm.ghosts()
+    assert len(g) > 0
+    assert np.array_equal(np.sort(g[:, 0]), np.unique(co[:, 0]))
+    assert np.array_equal(g[:, 1], om.levels[g[:, 0]] + 1)
+    assert np.all(np.diff(g[:, 1]) <= 0)
+    order = np.argsort(co[:, 0], kind="stable")
+    co = co[order]
+    starts = np.searchsorted(co[:, 0], g[:, 0])
+    ends = np.searchsorted(co[:, 0], g[:, 0], side="right")
+    for row, a, e in zip(g, starts, ends):
+        pts = co[a:e, 2:5]
+        assert np.array_equal(pts.min(0), row[[2, 4, 6]]), row
+        assert np.array_equal(pts.max(0), row[[3, 5, 7]]), row
+
+
 def test_mesh_info_matches_model():
     om = _oracle_mesh("wave_c1")
     info = P.build_mesh(mesh_spec("wave_c1")).info()
