@@ -273,16 +273,18 @@ lts_status lts_fused_stage_noalloc(lts_mesh* mesh, const lts_stage_view* view, i
                                    void* stream);
 
 /* Launch shape of the fused stage kernels (process-wide; used by every later
- * fused launch and graph capture): threads per workgroup of the LDS tile kernels
- * (256 or 512, default 512) and of the streaming kernel of side-4 tiles (256 or
- * 512, default 512), and the cap on the grid in workgroups (default 65536: one
+ * fused launch and graph capture): threads per workgroup of the side-2 LDS tile
+ * kernels (256 or 512, default 512; side-1 tiles always run 256) and of the
+ * streaming kernel of side-4 tiles (256 or 512, default 512), and the cap on the
+ * grid in workgroups (default 65536: one
  * workgroup per tile up to that many tiles; below the tile count, workgroups
  * walk several tiles each; batched launches use at most 4096).  Results do not
  * depend on it.  LTS_EINVAL for other values. */
 lts_status lts_set_launch(int32_t threads, int32_t max_workgroups, int32_t stream_threads);
 lts_status lts_get_launch(int32_t* threads, int32_t* max_workgroups, int32_t* stream_threads);
 /* Launch shape of batched launches (lts_batch_*): threads per workgroup of their
- * tile kernels (256 or 512, default 512) and the cap on their grids (default
+ * side-2 tile kernels (256 or 512, default 512; side-1 tiles always run 256)
+ * and the cap on their grids (default
  * 4096; workgroups walk several tiles of the union).  Results do not depend on
  * it; a captured round is redone when it changes. */
 lts_status lts_set_batch_launch(int32_t threads, int32_t max_workgroups);

@@ -72,15 +72,20 @@ template <int TT, int F, bool KF32, int NI = 4>
 struct FusedLds {
   static constexpr int W = TT + 2;
   static constexpr int NS = W * W * W;
-  static constexpr int G3 = (NI * TT + 1) * (NI * TT + 1) * (NI * TT + 1);
   using LT = typename std::conditional<KF32, float, double>::type;
-  double R[F * G3];               // stencil results
+  // side-2 tiles run their stencils once per grid point and stage the results
+  // for the zip (octants of a tile share face nodes); side-1 tiles of two
+  // fields need no stage (six fields do, for registers: see fused_tile)
+  static constexpr bool kStaged = TT > 1 || F > 2;
+  static constexpr int G3 = (NI * TT + 1) * (NI * TT + 1) * (NI * TT + 1);
+  double R[kStaged ? F * G3 : 1]; // stencil results (staged tiles)
   double wsh[16];                 // stage weights of the 4 time cases
+  double ref[2][F];               // FP32 stencils: reference value of each field (this and the next tile)
   LT Y[F * Cross<TT, NI>::LS];    // stage values of the used padded points
-  // per-tile tables, two buffers: the next tile's are filled while this one runs
-  double ref[2][F];               // FP32 stencils: reference value of each field
-  int32_t sl[2][2 * NS];          // slot records
-  uint8_t axl[2][3][NI * TT + 7]; // per axis: slot position | node offset << 3
+  // per-tile tables, read only by the gather: the next tile's are stored once
+  // this one's gather is done
+  int32_t sl[2 * NS];             // slot records
+  uint8_t axl[3][NI * TT + 7];    // per axis: slot position | node offset << 3
 };
 
 // A tile and what it needs of its simulation and mesh.
@@ -137,24 +142,31 @@ template <int TT, int F, bool KF32, int NI>
 __device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32, NI>& L, int b, const TileTables& tb) {
   constexpr int P = NI * TT + 7;
   constexpr int NS2 = 2 * (TT + 2) * (TT + 2) * (TT + 2);
-  if (threadIdx.x < NS2) L.sl[b][threadIdx.x] = tb.slv;
-  if (threadIdx.x < 3 * P) L.axl[b][threadIdx.x / P][threadIdx.x % P] = (uint8_t)tb.axv;
+  if (threadIdx.x < NS2) L.sl[threadIdx.x] = tb.slv;
+  if (threadIdx.x < 3 * P) L.axl[threadIdx.x / P][threadIdx.x % P] = (uint8_t)tb.axv;
   if (threadIdx.x < F) L.ref[b][threadIdx.x] = KF32 ? tb.refv : 0.0;
 }
 
 // One tile of the fused stage (Sec. 3.3, eqs. fc_1/fc_2, eq. rk_schemes).  Its
 // slot records and per-axis location tables (slot position and node offset of
-// every padded coordinate, from the location rule) are in LDS buffer b.
+// every padded coordinate, from the location rule) are in LDS, its FP32
+// reference values in buffer b.
 //   (1) every used padded point takes its stage value: a same-level leaf (the
 //       tile's own octants included) or 8 finer leaves give Y = U0 + dt sum w_i
 //       K_i, read directly (uniform base pointers, 32-bit offsets, UB points per
 //       thread loaded before use); a coarser leaf gives its prolongated value
 //       from the ghost table;
-//   (2) the stencils run once per tile grid point; K_s (and the RK update at the
-//       last stage) are written to every DG node of the tile's contiguous octants.
-// With a next tile, its record is loaded at the start and its tables during the
-// stencils, into buffer b ^ 1.  Two barriers per tile: after the gather (the
-// previous tile's zip has read the stencil results) and after the stencils.
+//   (2) the stencils run once per tile grid point; K_s (and the RK update at
+//       the last stage) are written to every DG node of the tile's contiguous
+//       octants.  Side-2 tiles stage the results in LDS (octants share face
+//       nodes); a side-1 tile's nodes are its grid points, each written
+//       directly for two fields.  Six fields (Maxwell) stage them as well: six
+//       stencil results held while the last stage's 24 RK operands arrive
+//       would exceed the register file.
+// With a next tile, its record is loaded at the start and its tables are
+// stored once the gather is done (reference values into buffer b ^ 1).  Two
+// barriers per tile: after the gather, and after the stencils (side 2) or the
+// zip (side 1).
 // sp holds the stage (weights, masks).  ZM, the zip mode, is fixed per launch:
 // bit 0 = the last stage (RK update), bit 1 = store K_s (all but the last stage
 // of GTS), bit 2 = count non-finite updates; as template bits the zip carries no
@@ -180,11 +192,10 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
   const SimView& v = cur.v;
   const double* __restrict__ cs = cur.cs;
   auto& Y = L.Y;
-  const int32_t* sl = L.sl[b];
-  const auto& axl = L.axl[b];
+  const int32_t* sl = L.sl;
+  const auto& axl = L.axl;
   auto& wsh = L.wsh;
   const double* ref = L.ref[b];
-  auto& R = L.R;
   if (more) load_trec(nxt.tile, ntrec);
   const int fsz = (int)(v.N * NN);           // elements per field (< 2^31)
   constexpr bool last = ZipMode<ZM>::last;
@@ -298,19 +309,16 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
   TileTables tb{0, 0, 0.0};
   if (more) tb = tables_issue<TT, F, KF32, NT, NI>(sp, nxt, ntrec);
   __syncthreads();
-  // the last stage's RK operands are loaded in the zip: holding them across the
-  // stencils would cost the registers that 3 resident side-2 workgroups leave
+  // from here on the gather is done with this tile's tables: the next tile's
+  // replace them before the second barrier (their loads have had the stencils'
+  // time to arrive)
   constexpr int NT3 = TT * TT * TT * NN;     // DG nodes of the tile
-  constexpr int KZ = (NT3 + NT - 1) / NT;
-  // (2a) stencils once per tile grid point (NI tt+1)^3; results staged in LDS
   constexpr int G = X::G;
-  constexpr int G3 = G * G * G;
   Geom geo{};
   if constexpr (EQ == LTS_EQ_NLWAVE) geo = geom_of(sp, first, c.lev);
-  for (int gi = threadIdx.x; gi < G3; gi += NT) {
-    const int gx = gi % G, gy = (gi / G) % G, gz = gi / (G * G);
+  // the stencils at grid point (gx, gy, gz) of the tile
+  auto stencil = [&](int gx, int gy, int gz, double (&k)[F]) {
     const int ce = (gz * P + gy + 3) * P + gx + 3;
-    double k[F];
     if constexpr (EQ == LTS_EQ_NLWAVE) {
       const int Xp[3] = {geo.X0[0] + geo.w * gx, geo.X0[1] + geo.w * gy, geo.X0[2] + geo.w * gz};
       rhs_nl_at(CrossAt<LT, TT, NI>{Y, ce, X::HB + gy * G + gx, gz}, c.h, v.sigma, geo, Xp, k);
@@ -318,39 +326,26 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
       // one axis at a time: fewer live registers (same operations, same order)
       rhs_at<LT, EQ, F, true>(CrossAt<LT, TT, NI>{Y, ce, X::HB + gy * G + gx, gz}, (LT)c.h, (LT)v.sigma, ref, k);
     }
-#pragma unroll
-    for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
-  }
-  if (more) tables_store(L, b ^ 1, tb);
-  __syncthreads();
-  // (2b) zip: every DG node of the tile's (contiguous) octants takes its grid
-  // value; node e of the tile is element first*NN + e of every field array;
-  // the last stage also forms the RK update
+  };
   double bs = sp.b[0];   // b_s without a dynamic index into the kernel arguments
 #pragma unroll
   for (int i = 1; i < 4; ++i)
     if (i == sp.stage) bs = sp.b[i];
-#pragma unroll
-  for (int u = 0; u < KZ; ++u) {
-    const int e = threadIdx.x + u * NT;
-    if (e >= NT3) continue;
-    const uint32_t off = (uint32_t)(first * NN + e);
-    double zu[F], zk[F][3];
-    if constexpr (last) {
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        zu[f] = ld32(Us + (uint32_t)(f * fsz), off);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-          zk[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
-      }
-    }
-    const int o = e / NN, node = e - NN * (e / NN);
-    const int a = node % NP, b = (node / NP) % NP, cc = node / (NP * NP);
-    const int gi = ((NI * ((o >> 2) & 1) + cc) * G + (NI * ((o >> 1) & 1) + b)) * G + (NI * (o & 1) + a);
+  // the last stage's RK operands of node element off
+  auto rk_operands = [&](uint32_t off, double (&zu)[F], double (&zk)[F][3]) {
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      double kv = R[f * G3 + gi];
+      zu[f] = ld32(Us + (uint32_t)(f * fsz), off);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        zk[f][i] = (i < sp.stage) ? (double)ld32(Kr + (uint32_t)((i * F + f) * fsz), off) : 0.0;
+    }
+  };
+  // K_s of node element off (and at the last stage the RK update)
+  auto emit = [&](uint32_t off, const double (&k)[F], const double (&zu)[F], const double (&zk)[F][3]) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double kv = k[f];
       if constexpr (KF32) {
         const float kf = (float)kv;
         if constexpr (storek) st32(Kw + (uint32_t)(f * fsz), off, kf);
@@ -373,6 +368,55 @@ __device__ __forceinline__ void fused_tile(FusedLds<TT, F, KF32, NI>& L, const S
         }
       }
     }
+  };
+  if constexpr (FusedLds<TT, F, KF32, NI>::kStaged) {
+    // (2a) stencils once per tile grid point (NI tt+1)^3, results staged in LDS
+    constexpr int G3 = G * G * G;
+    auto& R = L.R;
+    for (int gi = threadIdx.x; gi < G3; gi += NT) {
+      double k[F];
+      stencil(gi % G, (gi / G) % G, gi / (G * G), k);
+#pragma unroll
+      for (int f = 0; f < F; ++f) R[f * G3 + gi] = k[f];
+    }
+    if (more) tables_store(L, b ^ 1, tb);
+    __syncthreads();
+    // (2b) zip: node e of the tile is element first*NN + e of every field array
+    // and takes its grid point's results; its RK operands are issued first
+    constexpr int KZ = (NT3 + NT - 1) / NT;
+#pragma unroll
+    for (int u = 0; u < KZ; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (e >= NT3) continue;
+      const uint32_t off = (uint32_t)(first * NN + e);
+      double zu[F], zk[F][3];
+      if constexpr (last) rk_operands(off, zu, zk);
+      const int o = e / NN, node = e - NN * o;
+      const int gi = ((NI * ((o >> 2) & 1) + node / (NP * NP)) * G + (NI * ((o >> 1) & 1) + (node / NP) % NP)) * G +
+                     (NI * (o & 1) + node % NP);
+      double k[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) k[f] = R[f * G3 + gi];
+      emit(off, k, zu, zk);
+    }
+    // the next tile's gather writes Y only, its stencils R after its first barrier
+  } else {
+    // (2) side-1 tiles of two fields: the octant's nodes are the tile's grid
+    // points; each runs its stencils and writes its results directly
+    static_assert(TT == 1 && F == 2, "unstaged stencils are for side-1 tiles of two fields");
+    for (int e = threadIdx.x; e < NT3; e += NT) {
+      const uint32_t off = (uint32_t)(first * NN + e);
+      double k[F];
+      stencil(e % NP, (e / NP) % NP, e / (NP * NP), k);
+      // RK operands after the stencils: held across them they would cost
+      // registers beyond the budget
+      double zu[F], zk[F][3];
+      if constexpr (last) rk_operands(off, zu, zk);
+      emit(off, k, zu, zk);
+    }
+    if (more) tables_store(L, b ^ 1, tb);
+    // the next tile's gather overwrites Y and reads the tables stored above
+    __syncthreads();
   }
 }
 
@@ -466,9 +510,10 @@ hipError_t dispatch_nt(const StageParams& sp, const A& a, const LaunchShape& ls,
 template <typename A>
 hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& sp, const A& a, const LaunchShape& ls,
                           hipStream_t s) {
+  // side-1 tiles run 256-thread workgroups whatever the launch shape's thread
+  // count (more workgroups in flight per CU): 7-node wave 7 %, 5-node wave 28 %,
+  // Maxwell 10-20 % faster than 512
   if (sp.ni == 6) {   // 7-node octants: the wave equation on side-1 tiles, launches that allow it
-    // 256-thread workgroups whatever the launch shape's thread count: 7 % faster
-    // than 512 on the 7-node step (more workgroups in flight per CU)
     if constexpr (A::kNodes7) {
       if (eq == LTS_EQ_WAVE && tt == 1)
         return kf32 ? dispatch_ks<1, 2, LTS_EQ_WAVE, true, 256, 6>(sp, a, ls.max_wg, s)
@@ -480,21 +525,21 @@ hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& sp, cons
   if (eq == LTS_EQ_NLWAVE) {   // FP64, tile sides 1 and 2, launches that allow it
     if constexpr (A::kNonLinear) {
       if (kf32) return hipErrorInvalidValue;
-      if (tt == 1) return dispatch_nt<1, 2, LTS_EQ_NLWAVE, false>(sp, a, ls, s);
+      if (tt == 1) return dispatch_ks<1, 2, LTS_EQ_NLWAVE, false, 256, 4>(sp, a, ls.max_wg, s);
       if (tt == 2) return dispatch_nt<2, 2, LTS_EQ_NLWAVE, false>(sp, a, ls, s);
     }
     return hipErrorInvalidValue;
   }
   if (eq == LTS_EQ_WAVE) {
-    if (tt == 1) return kf32 ? dispatch_nt<1, 2, LTS_EQ_WAVE, true>(sp, a, ls, s)
-                             : dispatch_nt<1, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);
+    if (tt == 1) return kf32 ? dispatch_ks<1, 2, LTS_EQ_WAVE, true, 256, 4>(sp, a, ls.max_wg, s)
+                             : dispatch_ks<1, 2, LTS_EQ_WAVE, false, 256, 4>(sp, a, ls.max_wg, s);
     if (tt == 2) return kf32 ? dispatch_nt<2, 2, LTS_EQ_WAVE, true>(sp, a, ls, s)
                              : dispatch_nt<2, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);
     return hipErrorInvalidValue;
   }
   if (tt != 1) return hipErrorInvalidValue;  // 6 FP64 fields of a side-2 tile exceed LDS
-  return kf32 ? dispatch_nt<1, 6, LTS_EQ_MAXWELL, true>(sp, a, ls, s)
-              : dispatch_nt<1, 6, LTS_EQ_MAXWELL, false>(sp, a, ls, s);
+  return kf32 ? dispatch_ks<1, 6, LTS_EQ_MAXWELL, true, 256, 4>(sp, a, ls.max_wg, s)
+              : dispatch_ks<1, 6, LTS_EQ_MAXWELL, false, 256, 4>(sp, a, ls.max_wg, s);
 }
 
 }  // namespace lts

@@ -26,8 +26,9 @@ def _key(mesh, equation, precision, tableau, mode):
 
 
 def _candidates(tiles, threads, max_workgroups, stream_threads):
+    # side-1 tiles run 256-thread workgroups whatever the thread count asked for
     for t in tiles:
-        for nt, wg in itertools.product(threads, max_workgroups):
+        for nt, wg in itertools.product(threads if t != 1 else threads[:1], max_workgroups):
             for st in (stream_threads if t == 4 else stream_threads[:1]):
                 yield (t, nt, wg, st)
 
@@ -118,7 +119,9 @@ def tune_batch(meshes, states, equation: str = "wave", precision: int = 0, table
     table = []
     ref = {}
     try:
-        for t, nt, wg in itertools.product(list(tiles), list(threads), list(max_workgroups)):
+        threads, wgs = list(threads), list(max_workgroups)
+        cands = [(t, nt, wg) for t in tiles for nt in (threads if t != 1 else threads[:1]) for wg in wgs]
+        for t, nt, wg in cands:
             for m in meshes:
                 m.set_tile(t)
             set_batch_launch(nt, wg)
