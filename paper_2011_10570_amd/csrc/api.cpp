@@ -260,7 +260,7 @@ struct MeshExtra {
   double* d_norm = nullptr;
   size_t norm_cap = 0;
   double* d_coef = nullptr;
-  double* d_cscr = nullptr;   // coarser-ghost scratch of lts_fused_stage (side-4 tiles)
+  double* d_cscr = nullptr;   // ghost table of the single-stage calls (lts_fused_stage, lts_unzip)
   size_t cscr_cap = 0;
 };
 
@@ -270,11 +270,14 @@ static size_t ghost_points(const Mesh& m) {
   return gw * gw * gw;
 }
 
-// Ghost-table scratch: F x GW^3 doubles per entry (GW = 2 ni + 1: 729 doubles for
-// 5-node octants, 2197 for 7-node octants).  Grown outside graph capture
-// only.
-static lts_status ensure_cscr(const Mesh& m, int F, double** p, size_t* cap) {
-  const size_t need = (m.ghosts.size() / 2) * (size_t)F * ghost_points(m) * sizeof(double);
+// Doubles of one stage's ghost table: F x GW^3 per entry (GW = 2 ni + 1: 729
+// doubles for 5-node octants, 2197 for 7-node octants).
+static size_t cscr_slot(const Mesh& m, int F) { return (m.ghosts.size() / 2) * (size_t)F * ghost_points(m); }
+
+// Ghost-table scratch of `slots` stages (lts_advance keeps one per stage of a
+// substep, the single-stage calls one).  Grown outside graph capture only.
+static lts_status ensure_cscr(const Mesh& m, int F, int slots, double** p, size_t* cap) {
+  const size_t need = (size_t)slots * cscr_slot(m, F) * sizeof(double);
   if (need <= *cap) return LTS_OK;
   if (*p) (void)hipFree(*p);
   *p = nullptr;
@@ -294,11 +297,12 @@ static int lowest_active_level(const Mesh& m, int mode, int j) {
 }
 
 // Every fused launch of one stage for the tiles of levels >= lo: the ghost-table
-// pre-pass for receivers of levels >= lo, then streamed side-4 tiles, side-2 and
-// side-1 tiles, in stream order.
-static lts_status launch_stage(const Mesh& m, int eq, bool kf32, const StageParams& sp, int lo, double* cscr,
-                               const LaunchShape& ls, hipStream_t s) {
-  HIP_TRY(launch_ghost_pre(sp.F, kf32, sp, m.d_ghosts, m.ghost_ge[lo], cscr, s), "ghost pre-pass");
+// pre-pass of entries [0, nghost) (receivers of levels >= lo, or the part of them
+// that the multi-stage pre-pass has not filled), then streamed side-4 tiles,
+// side-2 and side-1 tiles, in stream order.
+static lts_status launch_stage(const Mesh& m, int eq, bool kf32, const StageParams& sp, int lo, int64_t nghost,
+                               double* cscr, const LaunchShape& ls, hipStream_t s) {
+  HIP_TRY(launch_ghost_pre(sp.F, kf32, sp, m.d_ghosts, nghost, cscr, s), "ghost pre-pass");
   for (int tt : {4, 2, 1}) {
     const TileSet& ts = m.ts[tt];
     if (ts.count() == 0 || ts.n_ge[lo] == 0) continue;
@@ -513,7 +517,7 @@ lts_status lts_unzip(lts_mesh* mesh, const lts_stage_view* view, int32_t stage, 
   } else {
     lo = lowest_active_level(m, pos->mode, pos->substep);
   }
-  if ((st = ensure_cscr(m, sp.F, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
+  if ((st = ensure_cscr(m, sp.F, 1, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
   HIP_TRY(launch_unzip(view->precision == LTS_FP32_RHS, sp, m.bt.d_tiles, m.bt.d_slots, L.list, L.poff, L.nb,
                        L.ptotal, padded, m.d_ghosts, m.ghost_ge[lo], h->x.d_cscr, m.d_ghost_of_leaf, s),
           "unzip launch");
@@ -649,8 +653,8 @@ lts_status lts_fused_stage(lts_mesh* mesh, const lts_stage_view* view, int32_t e
   sp.sigma = params->ko_sigma;
   sp.nl_coeff = params->nl_coeff;
   const int lo = lowest_active_level(m, pos->mode, pos->substep);
-  if ((st = ensure_cscr(m, sp.F, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
-  return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, h->x.d_cscr, g_shape, s);
+  if ((st = ensure_cscr(m, sp.F, 1, &h->x.d_cscr, &h->x.cscr_cap)) != LTS_OK) return st;
+  return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, m.ghost_ge[lo], h->x.d_cscr, g_shape, s);
 }
 
 }  // extern "C"
@@ -715,7 +719,7 @@ extern "C" lts_status lts_fused_stage_noalloc(lts_mesh* mesh, const lts_stage_vi
                                 std::to_string(kNoAllocScratchBytes - kNoAllocHeader) + " B)");
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_set_i64(d_step, pos->coarse_step, s), "set step");
-  return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, gtab, g_shape, s);
+  return launch_stage(m, equation, view->precision == LTS_FP32_RHS, sp, lo, m.ghost_ge[lo], gtab, g_shape, s);
 }
 
 // ------------------------------------------------------------------------ sims
@@ -743,7 +747,7 @@ struct lts_sim {
   double* d_pad = nullptr;
   void* d_kb = nullptr;
   double* d_coef = nullptr;
-  double* d_cscr = nullptr;     // coarser-ghost scratch (side-4 tiles)
+  double* d_cscr = nullptr;     // ghost tables: one per stage of a substep (lts_advance), the first for the phase path
   size_t cscr_cap = 0;
   // continuous batching: the batch the sim is attached to, its round range
   lts_batch* batch = nullptr;
@@ -797,11 +801,31 @@ static void* stage_slice(const lts_sim* sim, int s) {
 lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
   Mesh& m = sim->mesh->m;
   const int nsub = 1 << (m.lmax - m.lmin);
+  const size_t slot = cscr_slot(m, sim->F);   // stage s reads ghost table s
   for (int j = 0; j < nsub; ++j) {
     const int lo = lowest_active_level(m, mode, j);
+    // entries whose receivers lie above lo have an active coarser source: one
+    // pre-pass per stage; those with receivers at lo (coarser sources idle during
+    // the substep) get all stages at the first
+    const int64_t e_hi = lo < LTS_MAX_LEVEL ? m.ghost_ge[lo + 1] : 0, e_lo = m.ghost_ge[lo];
     for (int st = 0; st < sim->p; ++st) {
       StageParams sp;
       fill_sim_params(sim, st, mode, j, sp);
+      if (st == 0 && e_lo > e_hi) {
+        GhostStages gs{};
+        gs.p = sim->p;
+        for (int k = 0; k < sim->p; ++k) {
+          StageParams sk;
+          fill_sim_params(sim, k, mode, j, sk);
+          for (int c = 0; c < 4; ++c) {
+            for (int i = 0; i < 4; ++i) gs.w[k][c][i] = sk.w[c][i];
+            gs.kmask[k] |= (sk.kmask[c] & 15) << (4 * c);
+          }
+        }
+        HIP_TRY(launch_ghost_multi(sim->F, sim->prec == LTS_FP32_RHS, sp, gs, m.d_ghosts, e_hi, e_lo - e_hi,
+                                   sim->d_cscr, (int64_t)slot, s),
+                "multi-stage ghost pre-pass");
+      }
       if (sim->poison) {
         for (int k : {1, 2, 4}) {
           const TileSet& ts = m.ts[k];
@@ -811,7 +835,8 @@ lts_status enqueue_coarse_step(lts_sim* sim, int mode, hipStream_t s) {
                   "poison launch");
         }
       }
-      lts_status r = launch_stage(m, sim->eq, sim->prec == LTS_FP32_RHS, sp, lo, sim->d_cscr, g_shape, s);
+      lts_status r = launch_stage(m, sim->eq, sim->prec == LTS_FP32_RHS, sp, lo, e_hi, sim->d_cscr + st * slot,
+                                  g_shape, s);
       if (r != LTS_OK) return r;
     }
   }
@@ -926,7 +951,7 @@ static lts_status advance_steps(lts_sim* sim, int64_t n_coarse_steps, int32_t mo
   } else {
     lts_status cc = check_combination(m, sim->eq, sim->prec, false);
     if (cc != LTS_OK) return cc;
-    lts_status sc = ensure_cscr(m, sim->F, &sim->d_cscr, &sim->cscr_cap);
+    lts_status sc = ensure_cscr(m, sim->F, sim->p, &sim->d_cscr, &sim->cscr_cap);
     if (sc != LTS_OK) return sc;
   }
   auto one_step = [&](hipStream_t st) {
@@ -1019,7 +1044,7 @@ static lts_status prepare_unfused(lts_sim* sim) {
     HIP_TRY(hipMemcpy(sim->d_coef, sim->b, sim->p * sizeof(double), hipMemcpyHostToDevice), "upload b");
   }
   // the ghost table the unzip reads its coarser ghosts from
-  return ensure_cscr(m, sim->F, &sim->d_cscr, &sim->cscr_cap);
+  return ensure_cscr(m, sim->F, 1, &sim->d_cscr, &sim->cscr_cap);
 }
 
 // One coarse step through the phase kernels (unzip, rhs, zip per stage, then the

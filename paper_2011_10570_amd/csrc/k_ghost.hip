@@ -30,14 +30,20 @@ __device__ __forceinline__ int small_div(int e, int d, float r) {
   return q;
 }
 
+// The 4 time cases' stage masks of sp, 4 bits each.
+__device__ __forceinline__ int packed_masks(const StageParams& sp) {
+  return (sp.kmask[0] & 15) | (sp.kmask[1] & 15) << 4 | (sp.kmask[2] & 15) << 8 | (sp.kmask[3] & 15) << 12;
+}
+
 // One ghost-table entry of simulation v: leaf (coarser source), rec = receiver
 // level (bits 0-4) and the half-node box that the receivers read (4 bits per
 // bound from bit 5: x lo, x hi, y lo, y hi, z lo, z hi); the box of the GW^3
 // grid of each field to out[f][GW^3].  Points outside the box are not written
-// (no tile reads them); inside it every value is the full prolongation's.
+// (no tile reads them); inside it every value is the full prolongation's.  The
+// stage: weights wsh[case][i] (LDS) and masks km (packed_masks).
 template <bool KF32, int F, int NI = 4>
 __device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParams& sp, const SimView& v, int n4,
-                                            int leaf, int rec, double* __restrict__ out) {
+                                            int leaf, int rec, double* __restrict__ out, const double* wsh, int km) {
   using KT = typename std::conditional<KF32, float, double>::type;
   constexpr int NP = NI + 1, NN = NP * NP * NP, GW = 2 * NI + 1;
   const int rlev = rec & 31;
@@ -50,8 +56,8 @@ __device__ __forceinline__ void ghost_entry(GhostLds<F, NI>& L, const StageParam
   const int fsz = (int)(v.N * NN);
   const double* __restrict__ Uc = v.U + (int64_t)c.par_coarse * F * fsz;
   const KT* __restrict__ Kr = (const KT*)v.K;
-  const int kmc = stage_mask(sp, c.case_coarse);
-  const double* wc = L.wsh + 4 * c.case_coarse;
+  const int kmc = (km >> (4 * c.case_coarse)) & 15;
+  const double* wc = wsh + 4 * c.case_coarse;
   __syncthreads();   // weights loaded; previous entry done with Yc / T1 / T2
   for (int e = threadIdx.x; e < F * NN; e += blockDim.x) {
     const int f = e / NN, n = e - NN * f;
@@ -141,7 +147,32 @@ __global__ __launch_bounds__(NI == 6 ? 512 : 256) void k_ghost_pre(StageParams s
   const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
   ghost_entry<KF32, F, NI>(L, sp, v, (int)(*sp.step & 3), __builtin_amdgcn_readfirstlane(ghosts[2 * g]),
                            __builtin_amdgcn_readfirstlane(ghosts[2 * g + 1]),
-                           scr + (int64_t)g * F * (GW * GW * GW));
+                           scr + (int64_t)g * F * (GW * GW * GW), L.wsh, packed_masks(sp));
+}
+
+// All p stages of a substep for entry g0 + blockIdx.x, whose coarser source is
+// idle during the substep: the stage values differ only in their weights, and
+// the source's U and K's, read from HBM for the first stage, come from L2 for
+// the others.
+template <bool KF32, int F, int NI>
+__global__ __launch_bounds__(NI == 6 ? 512 : 256) void k_ghost_multi(StageParams sp, GhostStages gs,
+                                                     const int32_t* __restrict__ ghosts, int64_t g0,
+                                                     double* __restrict__ scr, int64_t slot) {
+  constexpr int GW = 2 * NI + 1;
+  __shared__ GhostLds<F, NI> L;
+  __shared__ double wall[4][16];
+  ghost_init(L, sp);
+  if (threadIdx.x < 64) wall[threadIdx.x >> 4][threadIdx.x & 15] = gs.w[threadIdx.x >> 4][(threadIdx.x >> 2) & 3][threadIdx.x & 3];
+  const int64_t g = g0 + blockIdx.x;
+  const SimView v{sp.U, sp.Uw, sp.K, sp.Kw, sp.N, sp.lmin, sp.lmax, sp.j, sp.sigma};
+  const int n4 = (int)(*sp.step & 3);
+  const int leaf = __builtin_amdgcn_readfirstlane(ghosts[2 * g]);
+  const int rec = __builtin_amdgcn_readfirstlane(ghosts[2 * g + 1]);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if (s < gs.p)
+      ghost_entry<KF32, F, NI>(L, sp, v, n4, leaf, rec, scr + s * slot + g * F * (GW * GW * GW), wall[s],
+                               gs.kmask[s]);
 }
 
 // The same for every simulation of a batch in round *round: the union of their
@@ -176,7 +207,7 @@ __global__ __launch_bounds__(256) void k_ghost_pre_batch(StageParams sp0, const 
     const int g = q - cum[s];
     ghost_entry<KF32, F>(L, sp0, v, n4, __builtin_amdgcn_readfirstlane(b.ghosts[2 * g]),
                          __builtin_amdgcn_readfirstlane(b.ghosts[2 * g + 1]),
-                         scr + ((int64_t)b.gbase + g) * F * 729);
+                         scr + ((int64_t)b.gbase + g) * F * 729, L.wsh, packed_masks(sp0));
   }
 }
 
@@ -199,6 +230,30 @@ hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32
   } else if (F == 6) {
     if (kf32) hipLaunchKernelGGL((k_ghost_pre<true, 6, 4>), grid, dim3(256), 0, s, sp, ghosts, scr);
     else hipLaunchKernelGGL((k_ghost_pre<false, 6, 4>), grid, dim3(256), 0, s, sp, ghosts, scr);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_multi(int F, bool kf32, const StageParams& sp, const GhostStages& gs, const int32_t* ghosts,
+                              int64_t g0, int64_t n, double* scr, int64_t slot, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (gs.p < 1 || gs.p > 4) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)n);
+  if (sp.ni == 6) {
+    if (F != 2) return hipErrorInvalidValue;
+    if (kf32) hipLaunchKernelGGL((k_ghost_multi<true, 2, 6>), grid, dim3(512), 0, s, sp, gs, ghosts, g0, scr, slot);
+    else hipLaunchKernelGGL((k_ghost_multi<false, 2, 6>), grid, dim3(512), 0, s, sp, gs, ghosts, g0, scr, slot);
+    return hipGetLastError();
+  }
+  if (sp.ni != 4) return hipErrorInvalidValue;
+  if (F == 2) {
+    if (kf32) hipLaunchKernelGGL((k_ghost_multi<true, 2, 4>), grid, dim3(256), 0, s, sp, gs, ghosts, g0, scr, slot);
+    else hipLaunchKernelGGL((k_ghost_multi<false, 2, 4>), grid, dim3(256), 0, s, sp, gs, ghosts, g0, scr, slot);
+  } else if (F == 6) {
+    if (kf32) hipLaunchKernelGGL((k_ghost_multi<true, 6, 4>), grid, dim3(256), 0, s, sp, gs, ghosts, g0, scr, slot);
+    else hipLaunchKernelGGL((k_ghost_multi<false, 6, 4>), grid, dim3(256), 0, s, sp, gs, ghosts, g0, scr, slot);
   } else {
     return hipErrorInvalidValue;
   }

@@ -87,9 +87,22 @@ hipError_t launch_fused(int tt, int eq, bool kf32, const StageParams& sp, const 
                         const int32_t* slots, const double* scr, const XcdRanges& xr, const LaunchShape& ls,
                         hipStream_t s);
 // Ghost-table pre-pass of one stage: entries [0, n) (leaf, receiver level) of
-// ghosts, prolongated to scr[g][F][729].
+// ghosts, prolongated to scr[g][F][GW^3].
 hipError_t launch_ghost_pre(int F, bool kf32, const StageParams& sp, const int32_t* ghosts, int64_t n, double* scr,
                             hipStream_t s);
+// Weights and stage masks of every stage of a substep (the multi-stage pre-pass).
+struct GhostStages {
+  double w[4][4][4];   // [stage][time case][i]
+  int kmask[4];        // [stage]: the 4 time cases' masks, 4 bits each
+  int p;
+};
+// Ghost-table pre-pass of all p stages of a substep at once, for entries
+// [g0, g0 + n) whose coarser sources do not advance during the substep (their
+// level is below the lowest active one): entry g's stage-s values to
+// scr + s * slot + g * F * GW^3.  Each stage's values are those launch_ghost_pre
+// gives for that stage (the same operations, in the same order).
+hipError_t launch_ghost_multi(int F, bool kf32, const StageParams& sp, const GhostStages& gs, const int32_t* ghosts,
+                              int64_t g0, int64_t n, double* scr, int64_t slot, hipStream_t s);
 // One stage of the round *round (device counter) for the simulations
 // sims[0..nsims) (device table); `total` bounds the union of their active side-tt
 // tiles and sizes the grid (host-computed; any larger value is correct too).
