@@ -32,8 +32,8 @@ def test_stage_accounting_is_224_bytes_per_node_update(tile):
     acc = bench.stage_accounting(info, gm.tiles())
     assert acc["alg_bytes"] == 224 * info["node_updates_lts"]
     assert acc["stages"] == 4 * info["n_substeps"]
-    # a ghost pre-pass and at least one tile launch per stage
-    assert 2 * acc["stages"] <= acc["launches"] <= 4 * acc["stages"]
+    # at least one tile launch per stage, at most 3 tile sides and 2 pre-passes
+    assert acc["stages"] <= acc["launches"] <= 5 * acc["stages"]
 
 
 def test_rk4_passes_total_14():
