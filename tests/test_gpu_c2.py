@@ -14,7 +14,9 @@ launch shape, side-2 tiles).
   last stage).
 * One whole coarse step, graph-captured as in the benchmark: properties that
   hold at any size -- LTS and GTS agree to the scheme's error, and both are
-  close to the analytic spherical wave (image sums over the periodic box)."""
+  close to the analytic spherical wave (image sums over the periodic box).
+* One whole LTS coarse step against the oracle's own full run of it (a stored
+  fixture: 4096 seeded nodes, the whole state's maximum and sum of squares)."""
 import os
 import sys
 
@@ -26,7 +28,7 @@ import paper_2011_10570_amd as P
 from oracle import fd
 from oracle import octree as ot
 from oracle import solver as so
-from workloads import config, mesh_spec, random_dg, wave_gaussian_torch
+from workloads import config, mesh_spec, random_dg, wave_gaussian, wave_gaussian_torch
 
 from gpu_common import TOL, positioned_state, rel_err
 
@@ -135,3 +137,44 @@ def test_c2_coarse_step_properties(c2):
         d = (out["lts"][f] - out["gts"][f]).abs().max().item()
         scale = out["gts"][f].abs().max().item()
         assert d < 1e-6 * scale, (f, d, scale)
+
+
+def _golden_c2_step():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_lts_step.txt")
+    stats, rows = {}, []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        p = line.split()
+        if p[0] in ("max_abs", "sum_sq"):
+            stats[(p[0], int(p[1]))] = float(p[2])
+        else:
+            rows.append((int(p[0]), int(p[1]), float(p[2]), float(p[3])))
+    return stats, np.array(rows)
+
+
+def test_c2_lts_coarse_step_vs_oracle(c2):
+    """One whole LTS coarse step of the benchmark workload (graph-captured, the
+    launch configuration bench.py times) against the oracle's full C2 run
+    (tests/golden/c2_lts_step.txt, written by make_c2_lts_step.py from oracle/
+    only): element by element at 4096 seeded nodes, and the whole state's
+    per-field maximum and sum of squares."""
+    cfg, gm, om = c2
+    stats, rows = _golden_c2_step()
+    assert len(rows) == 4096
+    lv = gm.leaves()
+    U0 = wave_gaussian(lv[:, :3], lv[:, 3], gm.info()["L"], cfg["pulses"], sigma=cfg["sigma"])
+    print("[c2] one LTS coarse step vs the oracle's full run", flush=True)
+    sim = P.Sim(gm, "wave", P.FP64, "rk4", ko_sigma=cfg["ko_sigma"], device=DEV)
+    sim.set_state(U0)
+    sim.advance(1, P.MODE_LTS, graph=True)
+    out = sim.current().reshape(2, om.n_oct, 125)
+    o = torch.from_numpy(rows[:, 0].astype(np.int64)).to(DEV)
+    n = torch.from_numpy(rows[:, 1].astype(np.int64)).to(DEV)
+    for f in range(2):
+        got = out[f][o, n].cpu().numpy()
+        scale = stats[("max_abs", f)]
+        assert np.abs(got - rows[:, 2 + f]).max() <= TOL * scale, f
+        assert abs(out[f].abs().max().item() - scale) <= TOL * scale, f
+        ss = (out[f] * out[f]).sum().item()
+        assert abs(ss - stats[("sum_sq", f)]) <= 1e-11 * stats[("sum_sq", f)], f
