@@ -164,9 +164,9 @@ __device__ __forceinline__ void tables_store(FusedLds<TT, F, KF32, NI>& L, int b
 //       stencil results held while the last stage's 24 RK operands arrive
 //       would exceed the register file.
 // With a next tile, its record is loaded at the start and its tables are
-// stored once the gather is done (reference values into buffer b ^ 1).  Two
-// barriers per tile: after the gather, and after the stencils (side 2) or the
-// zip (side 1).
+// stored, once this tile's gather is done, just before the second barrier
+// (reference values into buffer b ^ 1).  Two barriers per tile: after the
+// gather, and after the stencils (staged) or the zip (side 1, two fields).
 // sp holds the stage (weights, masks).  ZM, the zip mode, is fixed per launch:
 // bit 0 = the last stage (RK update), bit 1 = store K_s (all but the last stage
 // of GTS), bit 2 = count non-finite updates; as template bits the zip carries no

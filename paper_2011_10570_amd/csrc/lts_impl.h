@@ -53,8 +53,9 @@ struct Mesh {
   // Ghost table: every leaf that is a coarser source of some fused tile, with the
   // level of its receivers (its own level + 1), ordered by receiver level
   // (finest first); ghost_ge[l] = entries with receiver level >= l.  The
-  // prolongation pre-pass writes entry g's stage state on its 9^3 half-node grid
-  // to scratch g; a tile's list of distinct coarser leaves holds (leaf, g).
+  // prolongation pre-pass writes entry g's stage state on its (2 ni + 1)^3
+  // half-node grid (inside the box its receivers read) to scratch g; a tile's
+  // list of distinct coarser leaves holds (leaf, g).
   std::vector<int32_t> ghosts;        // [E][2] = leaf, receiver level | read box << 5
   std::vector<int64_t> ghost_ge;
   std::vector<int32_t> ghost_of_leaf; // [N]: the leaf's ghost-table entry, -1 if none

@@ -1,7 +1,9 @@
 """Writes tests/golden/c2_lts_step.txt: the oracle's wave_c2 state (201,216
 octants, levels 3-8, 4 Gaussian pulses, RK4, FP64) after one LTS coarse step
 (Alg. 2: 32 substeps), at a seeded sample of nodes, with the per-field maximum
-and sum of squares of the whole state and the run's wall time and cores.
+and sum of squares of the whole state and the run's wall time and cores; with
+--config wave7_c2 the same for the 7^3-node workload (75,230 octants, SSP-RK3)
+into tests/golden/wave7_c2_lts_step.txt.
 
 Test infrastructure: it calls oracle/ (and the input generator of workloads/)
 only.  The blocks of one stage are independent (each reads the step records and
@@ -11,7 +13,9 @@ b = w mod P, run them over state arrays in shared memory; the parent opens and
 closes the step records and orders the stages.  Every block's arithmetic is the
 oracle's own (State.unzip, fd.rhs_wave, State.zip_into, the RK update).
 
-usage: python tests/golden/make_c2_lts_step.py [--procs 8] [--samples 4096]
+usage: python tests/golden/make_c2_lts_step.py [--config wave_c2|wave7_c2] [--procs 8] [--samples 4096]
+       python tests/golden/make_c2_lts_step.py --config wave_c1 --check   (the parallel driver
+       against oracle.solver.run, bitwise; no file written)
 """
 import argparse
 import os
@@ -29,7 +33,8 @@ from oracle import octree as ot  # noqa: E402
 from oracle import solver as so  # noqa: E402
 from workloads import config, mesh_spec, wave_gaussian  # noqa: E402
 
-OUT = os.path.join(ROOT, "tests", "golden", "c2_lts_step.txt")
+OUT = {"wave_c2": os.path.join(ROOT, "tests", "golden", "c2_lts_step.txt"),
+       "wave7_c2": os.path.join(ROOT, "tests", "golden", "wave7_c2_lts_step.txt")}
 SEED = 2011
 
 
@@ -66,14 +71,17 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--procs", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--samples", type=int, default=4096)
-    ap.add_argument("--config", default="wave_c2",
-                    help="another configuration checks the parallel driver against oracle.solver.run (no file written)")
+    ap.add_argument("--config", default="wave_c2")
+    ap.add_argument("--check", action="store_true",
+                    help="compare with oracle.solver.run bitwise instead of writing a fixture")
     a = ap.parse_args()
     cfg, spec = config(a.config), mesh_spec(a.config)
+    tableau = cfg.get("tableau", "rk4")
     t0 = time.time()
     om = ot.build_mesh(ot.MeshSpec.from_dict(spec))
-    U0 = wave_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=cfg["sigma"])
-    st = so.State(om, 2, "rk4", "lts")
+    nn = om.nodes ** 3
+    U0 = wave_gaussian(om.anchors, om.levels, om.L, cfg["pulses"], sigma=cfg["sigma"], nodes=om.nodes)
+    st = so.State(om, 2, tableau, "lts")
     st.set_initial(U0)
     shms = []
     for name in ("U", "K", "cur_par", "cur_t", "rec_par", "rec_t0"):
@@ -116,19 +124,20 @@ def main():
     for shm in shms:
         shm.close()
         shm.unlink()
-    if a.config != "wave_c2":
-        want = so.run(om, U0, 1, "lts", "wave", "rk4", cfg["ko_sigma"]).reshape(2, om.n_oct, -1)
+    if a.check:
+        want = so.run(om, U0, 1, "lts", "wave", tableau, cfg["ko_sigma"]).reshape(2, om.n_oct, -1)
         assert np.array_equal(out, want), np.abs(out - want).max()
         print(f"[c2-oracle] {a.config}: the parallel driver equals oracle.solver.run bitwise", flush=True)
         return
     nu = sum(len(ot.active_blocks(om, j, "lts")) for j in range(ot.substeps(om)))
-    node_updates = int(sum(125 * int(om.blocks[b, 1]) ** 3 for j in range(ot.substeps(om))
+    node_updates = int(sum(nn * int(om.blocks[b, 1]) ** 3 for j in range(ot.substeps(om))
                            for b in ot.active_blocks(om, j, "lts")))
     rng = np.random.default_rng(SEED)
     octs = rng.integers(0, om.n_oct, a.samples)
-    nodes = rng.integers(0, 125, a.samples)
-    with open(OUT, "w") as f:
-        f.write("# wave_c2, one LTS coarse step (32 substeps), RK4, FP64, KO sigma "
+    nodes = rng.integers(0, nn, a.samples)
+    out_path = OUT[a.config]
+    with open(out_path, "w") as f:
+        f.write(f"# {a.config}, one LTS coarse step ({ot.substeps(om)} substeps), {tableau.upper()}, FP64, KO sigma "
                 f"{cfg['ko_sigma']}: oracle state at seeded nodes (seed {SEED})\n")
         f.write("# written by tests/golden/make_c2_lts_step.py (calls oracle/ only)\n")
         f.write(f"# wall_s {wall:.1f} procs {a.procs} block_steps {nu} node_updates {node_updates}\n")
@@ -137,7 +146,7 @@ def main():
             f.write(f"sum_sq {k} {float(np.sum(out[k] * out[k]))!r}\n")
         for o, n in zip(octs, nodes):
             f.write(f"{int(o)} {int(n)} {float(out[0, o, n])!r} {float(out[1, o, n])!r}\n")
-    print(f"[c2-oracle] wrote {OUT}: {wall:.0f} s on {a.procs} processes, "
+    print(f"[c2-oracle] wrote {out_path}: {wall:.0f} s on {a.procs} processes, "
           f"{node_updates / wall:.3e} node-updates/s", flush=True)
 
 

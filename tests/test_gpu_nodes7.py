@@ -3,7 +3,9 @@ fused kernels templated on the node count) with the oracle, through the C ABI:
 unzip at positioned LTS/GTS states, block RHS, zip, RK update, the fused stage
 (side-1 tiles, ghost table of 13^3 points), whole runs with classic RK4 and
 SSP-RK3, the graph-captured fused lts_advance against the eager phase calls
-(bitwise), FP32 stencils, norms, checkpoint/restore, and the refusals."""
+(bitwise), FP32 stencils, norms, checkpoint/restore, the refusals, and one
+whole coarse step of the full-size wave7_c2 workload against the oracle's own
+run of it (a stored fixture)."""
 import numpy as np
 import pytest
 import torch
@@ -258,3 +260,42 @@ def test_refusals7(mesh7):
     with pytest.raises(P.LTSError) as e:
         P.remesh_indicators(gm, s.current())
     assert e.value.status == P._L.EUNSUPPORTED
+
+
+def test_wave7_c2_lts_coarse_step_vs_oracle():
+    """One whole graph-captured LTS coarse step of the 7^3-node benchmark workload
+    (wave7_c2: 75,230 octants, levels 3-8, SSP-RK3, the launch bench.py times)
+    against the oracle's full run of it (tests/golden/wave7_c2_lts_step.txt,
+    written by make_c2_lts_step.py from oracle/ only): element by element at 4096
+    seeded nodes, and the whole state's per-field maximum and sum of squares."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wave7_c2_lts_step.txt")
+    stats, rows = {}, []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        p = line.split()
+        if p[0] in ("max_abs", "sum_sq"):
+            stats[(p[0], int(p[1]))] = float(p[2])
+        else:
+            rows.append((int(p[0]), int(p[1]), float(p[2]), float(p[3])))
+    rows = np.array(rows)
+    assert len(rows) == 4096
+    cfg = config("wave7_c2")
+    gm = P.build_mesh(mesh_spec("wave7_c2"))
+    lv = gm.leaves()
+    U0 = wave_gaussian(lv[:, :3], lv[:, 3], gm.info()["L"], cfg["pulses"], sigma=cfg["sigma"], nodes=N7)
+    print("[n7] one LTS coarse step of wave7_c2 vs the oracle's full run", flush=True)
+    sim = P.Sim(gm, "wave", P.FP64, cfg["tableau"], ko_sigma=cfg["ko_sigma"], device=DEV)
+    sim.set_state(U0)
+    sim.advance(1, P.MODE_LTS, graph=True)
+    out = sim.current().reshape(2, len(lv), N7 ** 3)
+    o = torch.from_numpy(rows[:, 0].astype(np.int64)).to(DEV)
+    n = torch.from_numpy(rows[:, 1].astype(np.int64)).to(DEV)
+    for f in range(2):
+        got = out[f][o, n].cpu().numpy()
+        scale = stats[("max_abs", f)]
+        assert np.abs(got - rows[:, 2 + f]).max() <= TOL * scale, f
+        assert abs(out[f].abs().max().item() - scale) <= TOL * scale, f
+        ss = (out[f] * out[f]).sum().item()
+        assert abs(ss - stats[("sum_sq", f)]) <= 1e-11 * stats[("sum_sq", f)], f
