@@ -27,7 +27,7 @@ Reported (one JSON line):
                  and the oracle's own LTS-over-GTS speedup;
   c3             the C1 configuration to T with FP32 stencils on the GPU against
                  that FP64 oracle result: l2 / max error per field;
-  maxwell        6-field Maxwell on the same mesh (tile side 1), FP64 LTS:
+  maxwell        6-field Maxwell on the same mesh (tile side 2), FP64 LTS:
                  node-updates/s and its roofline fraction (672 B per update);
   batch          64 independent wave problems (1k-50k leaves, levels 2..4-8)
                  advanced to T together by continuous batching, FP64 and
@@ -557,9 +557,10 @@ def main():
 
     maxwell = None
     if not args.no_maxwell and "lts" in legs:
-        # 6 fields (E, B) from divergence-free Gaussian data, tile side 1
+        # 6 fields (E, B) from divergence-free Gaussian data, side-2 tiles (one
+        # workgroup per CU; 1.4x the side-1 tiles' rate)
         from workloads import maxwell_gaussian_torch
-        gm.set_tile(1)
+        gm.set_tile(2)
         Um = maxwell_gaussian_torch(leaves, info["L"], cfg["pulses"], sigma=cfg["sigma"], device="cuda:0")
         steps_m = max(1, min(args.steps, 4))
         wall, ev = time_leg(P, gm, Um, P.MODE_LTS, P.FP64, steps_m, 1, torch, equation="maxwell")
@@ -567,7 +568,7 @@ def main():
         gm.set_tile(args.tile or 2)
         rate = w_lts * steps_m / wall
         a_m = 672 * w_lts * steps_m / ev / 1e9
-        maxwell = {"rate": rate, "ms_per_step": 1e3 * wall / steps_m, "steps": steps_m, "tile": 1,
+        maxwell = {"rate": rate, "ms_per_step": 1e3 * wall / steps_m, "steps": steps_m, "tile": 2,
                    "roofline": {"achieved": round(a_m, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(a_m / HBM_PEAK_GBS, 4), "bytes_per_node_update": 672}}
         print(f"[bench] maxwell: {rate:.4e} node-updates/s, frac {a_m / HBM_PEAK_GBS:.3f}", file=sys.stderr,

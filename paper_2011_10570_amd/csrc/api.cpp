@@ -231,8 +231,9 @@ static lts_status check_combination(const Mesh& m, int eq, int prec, bool batch)
     if (m.ts[4].count() > 0) return fail(LTS_EUNSUPPORTED, "the non-linear wave needs tile side 1 or 2");
     if (batch) return fail(LTS_EUNSUPPORTED, "the non-linear wave is not built for batched launches");
   }
-  if (eq == LTS_EQ_MAXWELL && m.ts[2].count() + m.ts[4].count() > 0)
-    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
+  if (eq == LTS_EQ_MAXWELL && (m.ts[4].count() > 0 || (batch && m.ts[2].count() > 0)))
+    return fail(LTS_EUNSUPPORTED, batch ? "batched Maxwell needs tile side 1 (lts_mesh_set_tile)"
+                                        : "Maxwell fused stage needs tile side 1 or 2 (lts_mesh_set_tile)");
   return LTS_OK;
 }
 

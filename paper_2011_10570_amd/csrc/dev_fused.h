@@ -537,7 +537,13 @@ hipError_t dispatch_fused(int tt, int eq, bool kf32, const StageParams& sp, cons
                              : dispatch_nt<2, 2, LTS_EQ_WAVE, false>(sp, a, ls, s);
     return hipErrorInvalidValue;
   }
-  if (tt != 1) return hipErrorInvalidValue;  // 6 FP64 fields of a side-2 tile exceed LDS
+  if (tt == 2) {   // one workgroup per CU (153 KB of LDS for six FP64 fields), one-mesh launches
+    if constexpr (A::kMaxwell2)
+      return kf32 ? dispatch_nt<2, 6, LTS_EQ_MAXWELL, true, A>(sp, a, ls, s)
+                  : dispatch_nt<2, 6, LTS_EQ_MAXWELL, false, A>(sp, a, ls, s);
+    return hipErrorInvalidValue;
+  }
+  if (tt != 1) return hipErrorInvalidValue;
   return kf32 ? dispatch_ks<1, 6, LTS_EQ_MAXWELL, true, 256, 4>(sp, a, ls.max_wg, s)
               : dispatch_ks<1, 6, LTS_EQ_MAXWELL, false, 256, 4>(sp, a, ls.max_wg, s);
 }

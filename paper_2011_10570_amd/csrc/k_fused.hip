@@ -31,6 +31,7 @@ namespace {
 struct OneArgs {
   static constexpr bool kNonLinear = true;   // whether the non-linear wave kernels are built for these launches
   static constexpr bool kNodes7 = true;      // whether the 7-node-octant kernels are built for these launches
+  static constexpr bool kMaxwell2 = true;    // whether side-2 Maxwell tiles are built for these launches
   const int32_t* tiles;
   const int32_t* slots;
   const double* scr;

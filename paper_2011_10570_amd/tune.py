@@ -48,8 +48,8 @@ def tune(mesh, U0, equation: str = "wave", precision: int = 0, tableau: str = "r
         mesh.set_tile(best[0])
         set_launch(best[1], best[2], best[3])
         return {"best": best, "ms": ms, "table": None}
-    if equation == "maxwell":
-        tiles = [t for t in tiles if t == 1]
+    if equation == "maxwell":   # side-1 and side-2 tiles (no streamed side-4 blocks)
+        tiles = [t for t in tiles if t in (1, 2)]
     stream_threads = list(stream_threads)
     old_tile = mesh.info()["tile"]
     old_shape = get_launch()
@@ -112,7 +112,7 @@ def tune_batch(meshes, states, equation: str = "wave", precision: int = 0, table
             m.set_tile(best[0])
         set_batch_launch(best[1], best[2])
         return {"best": best, "ms": ms, "table": None}
-    if equation == "maxwell":
+    if equation == "maxwell":   # batched Maxwell runs on side-1 tiles
         tiles = [t for t in tiles if t == 1]
     old_tiles = [m.info()["tile"] for m in meshes]
     old_shape = get_batch_launch()

@@ -187,15 +187,25 @@ def maxwell_small():
 
 
 @pytest.mark.parametrize("mode", ["lts", "gts"])
-def test_maxwell_tile1(maxwell_small, mode):
+def test_maxwell_tiles(maxwell_small, mode):
+    """Maxwell on side-1 and side-2 tiles against the oracle; the two tile sides
+    agree bitwise (FP64); a mesh with streamed side-4 blocks is refused (the
+    small mesh has none: its tile side 4 is side-1 and side-2 tiles)."""
     om, gm, U0 = maxwell_small
     md = P.MODE_LTS if mode == "lts" else P.MODE_GTS
     want = so.run(om, U0, 1, mode, equation="maxwell", sigma=0.1).reshape(6, om.n_oct, 125)
     got = _run_gpu(gm, U0, 1, md, eq="maxwell", tile=1)
     assert rel_err(got, want) < TOL
-    for tile in (2, 4):
-        with pytest.raises(P.LTSError):
-            _run_gpu(gm, U0, 1, md, eq="maxwell", tile=tile)
+    got2 = _run_gpu(gm, U0, 1, md, eq="maxwell", tile=2)
+    assert np.array_equal(got2, got)
+    assert 4 not in set(gm.blocks()[:, 1].tolist())
+    assert np.array_equal(_run_gpu(gm, U0, 1, md, eq="maxwell", tile=4), got)
+    g4 = P.build_mesh(mesh_spec("wave_c1"))
+    assert 4 in set(g4.blocks()[:, 1].tolist())
+    lv = g4.leaves()
+    U4 = maxwell_gaussian(lv[:, :3], lv[:, 3], g4.info()["L"], config("wave_c1")["pulses"], sigma=0.1)
+    with pytest.raises(P.LTSError):
+        _run_gpu(g4, U4, 1, md, eq="maxwell", tile=4)
 
 
 def _field_errors(got, want, om):
