@@ -209,8 +209,7 @@ lts_status lts_mesh_export(const lts_mesh* mesh, int32_t kind, void* buf, size_t
  * t (bitwise); in FP32-RHS mode the FP32 stencils run on Y minus one FP64
  * reference value per tile, so results differ between tile sides at FP32
  * rounding.  Maxwell needs t = 1 or 2 (side-2 Maxwell tiles hold 153 KB of LDS:
- * one workgroup per CU); batches (lts_batch_*) need t = 1 or 2, and t = 1 for
- * Maxwell.
+ * one workgroup per CU); batches (lts_batch_*) need t = 1 or 2.
  * LTS_EINVAL for other t or while a sim of the mesh is attached to a batch. */
 lts_status lts_mesh_set_tile(lts_mesh* mesh, int32_t tile);
 /* Exact-rational stage conversion weights w^[case][stage][i] as float64 (eqs.

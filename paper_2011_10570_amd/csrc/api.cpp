@@ -231,9 +231,8 @@ static lts_status check_combination(const Mesh& m, int eq, int prec, bool batch)
     if (m.ts[4].count() > 0) return fail(LTS_EUNSUPPORTED, "the non-linear wave needs tile side 1 or 2");
     if (batch) return fail(LTS_EUNSUPPORTED, "the non-linear wave is not built for batched launches");
   }
-  if (eq == LTS_EQ_MAXWELL && (m.ts[4].count() > 0 || (batch && m.ts[2].count() > 0)))
-    return fail(LTS_EUNSUPPORTED, batch ? "batched Maxwell needs tile side 1 (lts_mesh_set_tile)"
-                                        : "Maxwell fused stage needs tile side 1 or 2 (lts_mesh_set_tile)");
+  if (eq == LTS_EQ_MAXWELL && m.ts[4].count() > 0)
+    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 or 2 (lts_mesh_set_tile)");
   return LTS_OK;
 }
 
@@ -1538,8 +1537,6 @@ lts_status lts_batch_attach(lts_batch* b, lts_sim* sim, int64_t n_coarse_steps) 
     return fail(LTS_EINVAL, "mode differs from the bound state's history; rebind first");
   Mesh& m = sim->mesh->m;
   if (m.nodes != 5) return fail(LTS_EUNSUPPORTED, "7-node octants are not built for batched launches");
-  if (sim->eq == LTS_EQ_MAXWELL && m.ts[2].count() > 0)
-    return fail(LTS_EUNSUPPORTED, "Maxwell fused stage needs tile side 1 (lts_mesh_set_tile)");
   if (m.ts[4].count() > 0)
     return fail(LTS_EUNSUPPORTED, "batched launches use tile sides 1 and 2 (lts_mesh_set_tile)");
   if (m.device != b->device) return fail(LTS_EINVAL, "sim and batch are on different devices");

@@ -49,7 +49,7 @@ namespace {
 struct BatchArgs {
   static constexpr bool kNonLinear = false;   // whether the non-linear wave kernels are built for these launches
   static constexpr bool kNodes7 = false;      // whether the 7-node-octant kernels are built for these launches
-  static constexpr bool kMaxwell2 = false;    // whether side-2 Maxwell tiles are built for these launches
+  static constexpr bool kMaxwell2 = true;     // whether side-2 Maxwell tiles are built for these launches
   const BatchSim* sims;
   int nsims;
   const int64_t* round;

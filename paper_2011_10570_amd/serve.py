@@ -116,7 +116,7 @@ class Server:
 
     def _prepare(self, req: Request):
         m = Mesh(req.mesh_spec)
-        m.set_tile(2 if req.equation == "wave" else 1)
+        m.set_tile(2)
         return m
 
     def _admit(self, req: Request, now: float):

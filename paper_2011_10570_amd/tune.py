@@ -112,8 +112,6 @@ def tune_batch(meshes, states, equation: str = "wave", precision: int = 0, table
             m.set_tile(best[0])
         set_batch_launch(best[1], best[2])
         return {"best": best, "ms": ms, "table": None}
-    if equation == "maxwell":   # batched Maxwell runs on side-1 tiles
-        tiles = [t for t in tiles if t == 1]
     old_tiles = [m.info()["tile"] for m in meshes]
     old_shape = get_batch_launch()
     table = []

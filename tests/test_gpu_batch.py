@@ -179,7 +179,10 @@ def test_join_and_leave(meshes, graph):
     assert torch.equal(a.current(), _alone(ga, ta, Ua, 4, P.MODE_LTS))
 
 
-def test_batch_maxwell():
+@pytest.mark.parametrize("tile", [1, 2])
+def test_batch_maxwell(tile):
+    """Batched Maxwell (side-1 or side-2 tiles) equals the sims advanced alone
+    on side-1 tiles, bitwise."""
     out = []
     for name in ("small", "wave_c1"):
         gm = P.build_mesh(mesh_spec(name))
@@ -187,7 +190,7 @@ def test_batch_maxwell():
         centre = cfg["pulses"][0] if "pulses" in cfg else cfg["mesh"]["criteria"][0]["center"]
         out.append((gm, _state(gm, "maxwell", centre)))
     want = [_alone(gm, 1, U0, 1, P.MODE_LTS, eq="maxwell") for gm, U0 in out]
-    sims = [_sim(gm, 1, U0, eq="maxwell") for gm, U0 in out]
+    sims = [_sim(gm, tile, U0, eq="maxwell") for gm, U0 in out]
     P.batch_advance(sims, 1, P.MODE_LTS)
     for s, w in zip(sims, want):
         assert torch.equal(s.current(), w)
