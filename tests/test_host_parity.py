@@ -285,3 +285,15 @@ def test_nodes7_mesh_info_and_refusals():
     spec["nodes"] = 6
     with pytest.raises(P.LTSError):
         P.build_mesh(spec)
+
+
+def test_tuner_candidates():
+    """Side-1 tiles run 256-thread workgroups whatever the launch shape says, so
+    the tuner times one thread count for them; side-4 candidates also vary the
+    streaming kernel's threads."""
+    from paper_2011_10570_amd import tune
+    c = list(tune._candidates([1, 2, 4], [256, 512], [4096, 65536], [512, 256]))
+    assert len([x for x in c if x[0] == 1]) == 2
+    assert len([x for x in c if x[0] == 2]) == 4
+    assert len([x for x in c if x[0] == 4]) == 8
+    assert all(x[1] == 256 for x in c if x[0] == 1)
