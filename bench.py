@@ -54,7 +54,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("dev_common.h", "dev_fused.h", "k_fused.hip", "k_fused_batch.hip", "k_ghost.hip", "k_stream.hip",
-                  "k_phase.hip", "api.cpp")
+                  "k_phase.hip", "api.cpp", "mesh.cpp")   # mesh.cpp: tile order and XCD ranges
 WORKLOAD = "wave_c2"
 
 
@@ -97,7 +97,8 @@ def copy_probe_gbs(P, torch, mib: int = 2048, reps: int = 5) -> float:
 
 
 def source_digest() -> str:
-    """sha256 over the kernel and launch sources (device headers, kernels, api.cpp)."""
+    """sha256 over the kernel and launch sources (device headers, kernels, api.cpp, and mesh.cpp for
+    the tile order and XCD ranges)."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
